@@ -1,0 +1,213 @@
+"""EGKB, RSVD, Rayleigh-Ritz refinement and Kronecker terms (oracle).
+
+TEST INFRASTRUCTURE ONLY (see ``oracle/__init__``).
+
+``apply_R(X)`` / ``apply_Rt(X)`` are callables giving B X and B^T X for the
+matrix B = R(A) (any of the products in ``oracle.operator``). Everything here
+runs in float64 unless ``dtype`` asks otherwise.
+
+Readings of passages the paper leaves open (each is also listed in the design
+notes):
+
+* nu: the algorithm's index with the text's square root,
+  nu_{j+1} = sqrt(zeta_j zeta_{j-1}) (Algorithm 1 vs eq. "stopnu").
+* initialisation: zeta_1 = alpha_1 t_1 and nu_2 = +inf (scale-invariant);
+  ``literal_init=True`` restores the printed zeta_1 = 1, nu_2 = 100.
+* the garbled loop condition: iterate j = 2 .. k_p + 1 with the current k_p;
+  the auto-k test fires at most once, only while j > k_min and j - 1 != k_p,
+  and sets k = min(j, k_input), k_p = k + p.
+* svds(C, k_p) = full thin SVD of the (k_p+1) x k_p bidiagonal C.
+* output: U_k = S_{(k_p+1)} U[:, :k], V_k = Q_{k_p} V[:, :k] (all k_p+1 Lanczos
+  vectors enter the left factor).
+* breakdown (t_j or alpha_j <= ``bd_rel`` * max of all alphas and ts so far):
+  the coefficient is stored as 0 and the vector is replaced by a Philox normal
+  vector (stream 2j for s_j, 2j+1 for q_j), orthogonalized twice (classical
+  Gram-Schmidt) against the basis built so far, and normalized.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import philox
+
+
+def _norm(x):
+    return float(np.sqrt(np.dot(x, x)))
+
+
+def mgs(v, basis):
+    """One pass of modified Gram-Schmidt of v against the columns in ``basis``
+    (step "one-sided reorthogonalization" of Algorithm 1)."""
+    for b in basis:
+        v = v - np.dot(v, b) * b
+    return v
+
+
+def cgs2(v, basis):
+    """Classical Gram-Schmidt applied twice (used only for restart vectors)."""
+    if len(basis) == 0:
+        return v
+    Bm = np.stack(basis, axis=1)
+    for _ in range(2):
+        v = v - Bm @ (Bm.T @ v)
+    return v
+
+
+def egkb(apply_R, apply_Rt, y, k, p, *, reorth="full", auto_k=False, k_min=0,
+         tau=0.0, literal_init=False, bd_rel=None, seed=0, dtype=np.float64,
+         force_breakdown=None):
+    """Enlarged Golub-Kahan bidiagonalization (Algorithm 1, section 2.2).
+
+    reorth: "one_sided" = step 6 only (q_j against Q, the paper's DP run);
+            "full" = also s_j against S (the paper's SP runs, section 4.4).
+    force_breakdown: optional set of ("s"|"q", j) forcing the breakdown branch
+            at exactly those steps (and nowhere else), so the oracle can follow
+            a run whose breakdown decisions were taken in another precision.
+    Returns a dict with sigma (k), U (M x k), V (N x k), S, Q, C, alpha, t, nu,
+    k, kp, breakdowns.
+    """
+    eps = np.finfo(dtype).eps / 2
+    if bd_rel is None:
+        bd_rel = 1e3 * eps
+    k_in = k
+    kp = k + p
+    y = np.asarray(y, dtype=dtype)
+
+    def is_bd(side, j, val, scale):
+        if force_breakdown is not None:
+            return (side, j) in force_breakdown
+        return val <= bd_rel * scale
+
+    def restart(side, j, basis, size):
+        g = philox.normals(size, seed, 2 * j + (0 if side == "s" else 1)).astype(dtype)
+        g = cgs2(g, basis)
+        return g / _norm(g)
+
+    breakdowns = []
+    t = [_norm(y)]
+    S = [y / t[0]]
+    q = apply_Rt(S[0])
+    alpha = [_norm(q)]
+    if is_bd("q", 1, alpha[0], max(alpha[0], t[0])):
+        breakdowns.append(("q", 1))
+        alpha[0] = 0.0
+        Q = [restart("q", 1, [], q.shape[0])]
+    else:
+        Q = [q / alpha[0]]
+    zeta = {1: 1.0 if literal_init else alpha[0] * t[0]}
+    nu = {2: 100.0 if literal_init else np.inf}
+    scale = max(alpha[0], t[0])
+    fired = False
+    j = 2
+    while j <= kp + 1:
+        s = apply_R(Q[-1]) - alpha[-1] * S[-1]
+        if reorth == "full":
+            s = mgs(s, S)
+        tj = _norm(s)
+        if is_bd("s", j, tj, scale):
+            breakdowns.append(("s", j))
+            tj = 0.0
+            s = restart("s", j, S, s.shape[0])
+        else:
+            s = s / tj
+        S.append(s)
+        t.append(tj)
+        scale = max(scale, tj)
+        if j <= kp:
+            q = apply_Rt(s) - tj * Q[-1]
+            q = mgs(q, Q)
+            aj = _norm(q)
+            if is_bd("q", j, aj, scale):
+                breakdowns.append(("q", j))
+                aj = 0.0
+                q = restart("q", j, Q, q.shape[0])
+            else:
+                q = q / aj
+            Q.append(q)
+            alpha.append(aj)
+            scale = max(scale, aj)
+            zeta[j] = aj * tj
+            nu[j + 1] = float(np.sqrt(zeta[j] * zeta[j - 1]))
+            if auto_k and not fired and j > k_min and (j - 1) != kp:
+                if nu[j + 1] > nu[j] or nu[j] < tau:
+                    fired = True
+                    k = min(j, k_in)
+                    kp = k + p
+        j += 1
+    # S has kp+1 columns, Q has kp columns (the loop ran to the final kp+1).
+    Sm = np.stack(S[:kp + 1], axis=1)
+    Qm = np.stack(Q[:kp], axis=1)
+    C = np.zeros((kp + 1, kp), dtype=np.float64)
+    for i in range(kp):
+        C[i, i] = alpha[i]
+        C[i + 1, i] = t[i + 1]
+    Uc, sc, Vct = np.linalg.svd(C, full_matrices=False)
+    U = Sm @ Uc[:, :k]
+    V = Qm @ Vct[:k].T
+    return dict(sigma=sc[:k].copy(), sigma_all=sc, U=U, V=V, S=Sm, Q=Qm, C=C,
+                alpha=np.array(alpha[:kp]), t=np.array(t[:kp + 1]), nu=nu,
+                k=k, kp=kp, breakdowns=breakdowns, Uc=Uc, Vc=Vct.T)
+
+
+def orth(X):
+    """Orthonormal basis of range(X) (Householder QR, reduced)."""
+    Qm, _ = np.linalg.qr(X)
+    return Qm
+
+
+def rsvd(apply_R, apply_Rt, F, k, q=1):
+    """Randomized SVD (Algorithm 2, section 2.3) with orthonormalization after
+    every application of B or B^T (the paper's practical remark).
+
+    F is the N x k_p Gaussian sketch. Returns dict(sigma, U, V, Y, H).
+    """
+    Y = orth(apply_R(F))
+    for _ in range(q):
+        Z = orth(apply_Rt(Y))
+        Y = orth(apply_R(Z))
+    Ht = apply_Rt(Y)                       # (Q^T B)^T
+    Uh, s, Vt = np.linalg.svd(Ht.T, full_matrices=False)
+    return dict(sigma=s[:k].copy(), sigma_all=s, U=Y @ Uh[:, :k], V=Vt[:k].T,
+                Y=Y, Ht=Ht)
+
+
+def refine(apply_R, V):
+    """One-sided Rayleigh-Ritz refinement of a right factor V (N x k).
+
+    V is re-orthonormalized, W = B V is formed and its thin SVD
+    W = U~ S~ Z^T gives the refined triplets (U~, S~, V Z): the best rank-k
+    approximation of B restricted to range(V).
+    """
+    Vo = orth(V)
+    W = apply_R(Vo)
+    Uw, s, Zt = np.linalg.svd(W, full_matrices=False)
+    return dict(sigma=s, U=Uw, V=Vo @ Zt.T)
+
+
+def sign_fix(U, V):
+    """Flip each pair (u_i, v_i) so that the largest-magnitude entry of v_i is
+    positive (ties to the lowest index). Returns new arrays."""
+    U = U.copy()
+    V = V.copy()
+    for i in range(V.shape[1]):
+        m = int(np.argmax(np.abs(V[:, i])))
+        if V[m, i] < 0:
+            U[:, i] = -U[:, i]
+            V[:, i] = -V[:, i]
+    return U, V
+
+
+def kp_terms(sigma, U, V, n):
+    """Kronecker factors (eq. "KP approx"): A_x,i = sigma_i array(u_i, n, n),
+    A_y,i = array(v_i, n, n), array column-major. Returns (Ax, Ay) with shape
+    (k, n, n)."""
+    U, V = sign_fix(U, V)
+    k = len(sigma)
+    Ax = np.stack([sigma[i] * U[:, i].reshape(n, n, order="F") for i in range(k)])
+    Ay = np.stack([V[:, i].reshape(n, n, order="F") for i in range(k)])
+    return Ax, Ay
+
+
+def kp_approx_matrix(Ax, Ay):
+    """Explicit A_k = sum_i A_x,i (x) A_y,i (small n only)."""
+    return sum(np.kron(Ax[i], Ay[i]) for i in range(Ax.shape[0]))

@@ -1,0 +1,179 @@
+"""Pins for the oracle's EGKB (Algorithm 1), RSVD (Algorithm 2), Rayleigh-Ritz
+refinement and Kronecker terms (eq. "KP approx").
+
+Pins: the Lanczos relation B Q = S C, orthogonality, exactness once the
+Krylov/sketch space contains the range (rank(R) <= k_p), interlacing, the
+Eckart-Young optimum, a hand-computed firing index of the nu rule, and the
+Kronecker-product theorem for the assembled terms.
+"""
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle import kpsvd, operator as op
+from oracle.metrics import kp_rel_error
+
+
+def _ops(P, cu, cv, n):
+    return (lambda X: op.rmat_struct_apply(P, cu, cv, n, X),
+            lambda X: op.rmat_struct_apply(P, cu, cv, n, X, transpose=True))
+
+
+@pytest.mark.parametrize("reorth", ["full", "one_sided"])
+def test_egkb_lanczos_relation_and_orthogonality(reorth):
+    n = 24
+    P, cu, cv = wl.speckle_psf(n, seed=1001)
+    R, Rt = _ops(P, cu, cv, n)
+    y = wl.gaussian_block(n * n, 1, seed=4001)[:, 0]
+    out = kpsvd.egkb(R, Rt, y, k=8, p=8, reorth=reorth)
+    S, Q, C = out["S"], out["Q"], out["C"]
+    s1 = op.exact_kpsvd(P, cu, cv, n, 1)[0][0]
+    assert S.shape == (n * n, 17) and Q.shape == (n * n, 16) and C.shape == (17, 16)
+    assert np.linalg.norm(R(Q) - S @ C) <= 1e-12 * s1
+    assert np.abs(Q.T @ Q - np.eye(16)).max() <= 1e-12
+    if reorth == "full":
+        assert np.abs(S.T @ S - np.eye(17)).max() <= 1e-12
+    # C is lower bidiagonal with non-negative entries
+    assert np.all(np.triu(C, 1) == 0) and np.all(np.tril(C, -2) == 0)
+    assert np.all(np.diag(C) >= 0) and np.all(np.diag(C, -1) >= 0)
+    # first right Lanczos vector is the normalized R^T y
+    q1 = Rt(y)
+    assert np.allclose(Q[:, 0], q1 / np.linalg.norm(q1), atol=1e-14)
+
+
+def test_egkb_ritz_values_interlace_and_converge():
+    n = 24
+    P, cu, cv = wl.speckle_psf(n, seed=1002)
+    R, Rt = _ops(P, cu, cv, n)
+    y = wl.gaussian_block(n * n, 1, seed=4002)[:, 0]
+    s_ex = op.exact_kpsvd(P, cu, cv, n)[0]
+    out = kpsvd.egkb(R, Rt, y, k=5, p=15)
+    sig = out["sigma_all"]
+    assert np.all(sig <= s_ex[:len(sig)] * (1 + 1e-12) + 1e-14)
+    assert np.allclose(out["sigma"], s_ex[:5], rtol=1e-8)
+    # one-sided and full reorthogonalization agree in float64
+    out1 = kpsvd.egkb(R, Rt, y, k=5, p=15, reorth="one_sided")
+    assert np.allclose(out1["sigma"], out["sigma"], rtol=1e-10)
+
+
+def test_egkb_exact_when_krylov_space_contains_range_with_breakdown():
+    # The r=8 disk has Kronecker rank 6: with k_p = 8 > 6 the process breaks
+    # down; the restart keeps the relation and the 6 nonzero sigmas are exact.
+    n = 20
+    P, cu, cv = wl.disk_psf(n)
+    R, Rt = _ops(P, cu, cv, n)
+    y = wl.gaussian_block(n * n, 1, seed=4003)[:, 0]
+    out = kpsvd.egkb(R, Rt, y, k=6, p=2, seed=7)
+    s_ex = op.exact_kpsvd(P, cu, cv, n)[0]
+    assert out["breakdowns"], "expected a breakdown beyond the Kronecker rank"
+    assert np.allclose(out["sigma"], s_ex[:6], rtol=1e-12)
+    assert np.linalg.norm(R(out["Q"]) - out["S"] @ out["C"]) <= 1e-12 * s_ex[0]
+    assert np.abs(out["Q"].T @ out["Q"] - np.eye(out["Q"].shape[1])).max() <= 1e-12
+    err = kp_rel_error(P, cu, cv, n, out["sigma"], out["U"], out["V"])
+    assert err <= 1e-7
+
+
+def test_egkb_forced_breakdown_follows_requested_steps():
+    n = 16
+    P, cu, cv = wl.speckle_psf(n, seed=1003)
+    R, Rt = _ops(P, cu, cv, n)
+    y = wl.gaussian_block(n * n, 1, seed=4004)[:, 0]
+    out = kpsvd.egkb(R, Rt, y, k=4, p=4, force_breakdown={("s", 3)}, seed=3)
+    assert out["breakdowns"] == [("s", 3)]
+    assert out["t"][2] == 0.0
+    assert np.abs(out["S"].T @ out["S"] - np.eye(9)).max() <= 1e-12
+
+
+def _bidiag(alpha, t):
+    """Lower bidiagonal B ((m+1) x m) whose GKB from e_1 reproduces alpha, t."""
+    m = len(alpha)
+    B = np.zeros((m + 1, m))
+    for i in range(m):
+        B[i, i] = alpha[i]
+        B[i + 1, i] = t[i + 1]
+    return B
+
+
+def test_nu_rule_fires_at_hand_computed_index():
+    # t_j = 1, alpha_j = zeta_j. nu_{j+1} = sqrt(zeta_j zeta_{j-1}):
+    # nu3 = .707, nu4 = .387, nu5 = .245, nu6 = .224, nu7 = sqrt(.4*.25) = .316
+    # -> first rise at j = 6, so k = 6 and k_p = 6 + p.
+    zeta = [1.0, 0.5, 0.3, 0.2, 0.25, 0.4, 0.1, 0.05, 0.04, 0.03, 0.02, 0.01, 0.01, 0.01]
+    B = _bidiag(zeta, [1.0] * (len(zeta) + 1))
+    y = np.zeros(B.shape[0])
+    y[0] = 1.0
+    R = lambda X: B @ X
+    Rt = lambda X: B.T @ X
+    out = kpsvd.egkb(R, Rt, y, k=10, p=2, auto_k=True)
+    assert np.allclose(out["alpha"][:6], zeta[:6], atol=1e-15)
+    assert out["k"] == 6 and out["kp"] == 8
+    # k_min guard postpones the test until j > k_min
+    out2 = kpsvd.egkb(R, Rt, y, k=10, p=2, auto_k=True, k_min=6)
+    # after j = 6: nu8 = sqrt(.1*.4) = .2 < nu7 (.316); nu9 = sqrt(.05*.1) = .0707;
+    # nu10 = sqrt(.04*.05) = .0447; nu11 = .0346; nu12 = .0245; nu13 = .0141;
+    # nu14 = sqrt(.01*.01) = .01 < .0141; never rises -> k stays 10
+    assert out2["k"] == 10 and out2["kp"] == 12
+    # threshold clause: nu_j < tau fires at the first j > k_min with nu_j < tau
+    out3 = kpsvd.egkb(R, Rt, y, k=10, p=2, auto_k=True, k_min=6, tau=0.05)
+    # j = 7: nu7 = .316; j = 8: nu8 = .2; j = 9: nu9 = .0707; j = 10: nu10 = .0447 < .05
+    assert out3["k"] == 10
+    out4 = kpsvd.egkb(R, Rt, y, k=12, p=2, auto_k=True, k_min=6, tau=0.05)
+    assert out4["k"] == 10 and out4["kp"] == 12
+    # the printed initialisation (zeta_1 = 1, nu_2 = 100) gives the same index here
+    out5 = kpsvd.egkb(R, Rt, y, k=10, p=2, auto_k=True, literal_init=True)
+    assert out5["k"] == 6
+
+
+def test_rsvd_exact_for_low_rank_and_bounds():
+    n = 20
+    P, cu, cv = wl.disk_psf(n)
+    R, Rt = _ops(P, cu, cv, n)
+    F = wl.gaussian_block(n * n, 8, seed=4005)
+    out = kpsvd.rsvd(R, Rt, F, k=6, q=1)
+    s_ex = op.exact_kpsvd(P, cu, cv, n)[0]
+    assert np.allclose(out["sigma"], s_ex[:6], rtol=1e-12)
+    # general case: sigma_bar_i <= sigma_i and error >= Eckart-Young optimum
+    P, cu, cv = wl.speckle_psf(n, seed=1004)
+    R, Rt = _ops(P, cu, cv, n)
+    s_ex = op.exact_kpsvd(P, cu, cv, n)[0]
+    for q in (0, 1, 2):
+        out = kpsvd.rsvd(R, Rt, wl.gaussian_block(n * n, 12, seed=4006), k=8, q=q)
+        assert np.all(out["sigma"] <= s_ex[:8] * (1 + 1e-12))
+        err = kp_rel_error(P, cu, cv, n, out["sigma"], out["U"], out["V"])
+        opt = np.sqrt(np.sum(s_ex[8:] ** 2) / np.sum(s_ex ** 2))
+        assert err >= opt * (1 - 1e-9)
+        if q == 2:
+            assert err <= 1.01 * opt
+    # orthonormal factors
+    assert np.abs(out["U"].T @ out["U"] - np.eye(8)).max() < 1e-12
+    assert np.abs(out["V"].T @ out["V"] - np.eye(8)).max() < 1e-12
+    # R V = U S on the converged leading triplet
+    assert np.linalg.norm(R(out["V"][:, :1]) - out["U"][:, :1] * out["sigma"][0]) < 1e-6 * s_ex[0]
+
+
+def test_refine_recovers_exact_triplets_and_improves_perturbed_subspace():
+    n = 20
+    P, cu, cv = wl.speckle_psf(n, seed=1005)
+    R, Rt = _ops(P, cu, cv, n)
+    s_ex, U_ex, V_ex = op.exact_kpsvd(P, cu, cv, n, 10)
+    out = kpsvd.refine(R, V_ex)
+    assert np.allclose(out["sigma"], s_ex, rtol=1e-12)
+    # columns perturbed by ~1e-3 in norm: the Ritz values err at second order
+    pert = V_ex + 1e-3 / n * np.random.default_rng(0).standard_normal(V_ex.shape)
+    out = kpsvd.refine(R, pert)
+    e_ref = np.abs(out["sigma"] - s_ex).max() / s_ex[0]
+    assert e_ref < 1e-5
+    assert np.all(out["sigma"] <= s_ex * (1 + 1e-12))
+
+
+def test_kp_terms_reconstruct_A_with_full_rank():
+    n = 6
+    P, cu, cv = wl.random_psf(4, 5, 21)
+    A = op.blur_matrix(P, cu, cv, n)
+    s, U, V = op.exact_kpsvd(P, cu, cv, n)
+    Ax, Ay = kpsvd.kp_terms(s, U, V, n)
+    assert np.abs(kpsvd.kp_approx_matrix(Ax, Ay) - A).max() <= 1e-13
+    # sign convention: the largest-magnitude entry of every A_y is positive
+    for t in range(Ay.shape[0]):
+        flat = Ay[t].flatten(order="F")
+        assert flat[np.argmax(np.abs(flat))] > 0
