@@ -1,0 +1,180 @@
+/*
+ * kpsb.h -- C ABI of libkpsb.so: Kronecker-product SVD of the rearranged blur
+ * matrix R(A) and split Bregman deblurring on AMD Instinct MI355X (gfx950).
+ *
+ * Method: Alsubhi & Renaut, "Split Bregman isotropic and anisotropic image
+ * deblurring with Kronecker product sum approximations using single precision
+ * enlarged-GKB or RSVD", arXiv 2410.00233.
+ *
+ * General rules
+ *  - Every entry point returns kp_status and never aborts or throws; on an
+ *    error kp_last_error(ctx) returns a description. Arguments are validated
+ *    before any device work is queued.
+ *  - "device" pointers are HIP device allocations owned by the caller; "host"
+ *    pointers are ordinary host memory owned by the caller. The library never
+ *    frees caller memory; it owns only the workspace inside its kp_ctx.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream). Device
+ *    outputs are stream-ordered. Calls that return host outputs (sigma, k,
+ *    statistics, diagnostics) synchronize `stream` before returning.
+ *  - One kp_ctx per host thread; a context is not safe for concurrent use.
+ *  - Images: an n x n image is stored row-major, X[row*n + col], row vertical.
+ *    The paper's vec is column-major: pixel (r, c) is entry r + n*c.
+ *    Vectors in the row or column space of R(A) (length n^2, Krylov bases,
+ *    sketches) are stored in that vec order; a block of b such vectors is
+ *    column-major with leading dimension n^2.
+ *  - Blur model (paper, eq. "forward problem", zero boundary conditions):
+ *    A[r + n*i, c + n*j] = P[cu + r - c, cv + i - j] (0 outside P), and the
+ *    rearrangement of section 2.1 (eq. "initial rearrange A") gives
+ *    R[i + n*j, r + n*c] = P[cu + r - c, cv + i - j]. R(A) is never stored: its
+ *    tiles are generated from P on the device.
+ */
+#ifndef KPSB_H
+#define KPSB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  KP_OK = 0,
+  KP_E_INVAL = 1,       /* invalid argument (nothing was queued)              */
+  KP_E_NOMEM = 2,       /* workspace would exceed the context's HBM budget    */
+  KP_E_DEVICE = 3,      /* a HIP runtime call failed                           */
+  KP_E_NUMERIC = 4,     /* non-finite value met (e.g. NaN in the PSF)          */
+  KP_W_BREAKDOWN = 100  /* result valid; a Lanczos breakdown was deflated     */
+} kp_status;
+
+typedef enum { KP_F64 = 0, KP_F32 = 1, KP_BF16 = 2, KP_F16 = 3 } kp_prec;
+
+typedef struct kp_ctx kp_ctx;
+
+/* The blur: PSF P (pu x pv, row-major FP64, HOST memory, P[u*pv + v] with u the
+ * vertical offset) with centre (cu, cv), acting on n x n images with zero
+ * boundary conditions. Requirements: n >= 2, pu, pv >= 1, 0 <= cu < pu,
+ * 0 <= cv < pv, every P entry finite. */
+typedef struct {
+  int32_t n;
+  const double* psf;
+  int32_t pu, pv, cu, cv;
+} kp_blur;
+
+/* Enlarged Golub-Kahan bidiagonalization (paper, Algorithm 1). */
+typedef struct {
+  int32_t k;            /* target rank (upper bound when auto_k = 1)               */
+  int32_t p;            /* enlargement: k_p = k + p Lanczos steps                  */
+  int32_t k_min;        /* stopping test only for steps j > k_min                 */
+  int32_t auto_k;       /* 1: choose k by the nu rule (eq. "stopnu")              */
+  double tau;           /* tau_EGKB of the nu rule (0: only the "nu rises" clause) */
+  int32_t literal_init; /* 1: printed init zeta_1 = 1, nu_2 = 100                  */
+  int32_t reorth;       /* 0: one-sided (q_j against Q), 1: full (also s_j vs S)   */
+  kp_prec prec;         /* KP_F32 (paper's SP) or KP_F64                           */
+  uint64_t seed;        /* Philox seed for the start vector (if y0 == NULL) and
+                           for breakdown restart vectors                           */
+  const double* y0;     /* optional HOST start vector y, length n^2 (vec order)    */
+  double bd_rel;        /* breakdown when t_j or alpha_j <= bd_rel * max(alpha, t);
+                           0 selects 1e3 * unit roundoff of `prec`                 */
+} kp_gkb_opts;
+
+/* Randomized SVD (paper, Algorithm 2) with orthonormalization after every
+ * application of R or R^T. */
+typedef struct {
+  int32_t k, p, q;      /* rank, oversampling, power iterations                    */
+  kp_prec prec;         /* KP_F32, KP_F64, or KP_BF16 / KP_F16 (block products in
+                           16-bit inputs with FP32 accumulation)                   */
+  int32_t refine;       /* 1: second reorthogonalization + Rayleigh-Ritz refinement
+                           of the rank-k factors with an FP32 product              */
+  uint64_t seed;        /* Philox seed for F when F == NULL                        */
+  const double* F;      /* optional HOST sketch, n^2 x (k+p) column-major          */
+} kp_rsvd_opts;
+
+/* Diagnostics (all HOST, all optional). */
+typedef struct {
+  int32_t cap;          /* capacity of alpha / t (>= k_p + 1)                      */
+  double* alpha;        /* out: alpha_1..alpha_kp                                  */
+  double* t;            /* out: t_1..t_{kp+1}                                      */
+  int32_t kp;           /* out: final k_p                                          */
+  int32_t nbreak;       /* out: number of deflated breakdowns                      */
+  int32_t break_side[16]; /* out: 0 = s-vector, 1 = q-vector, first 16 events      */
+  int32_t break_step[16]; /* out: step j of each event                             */
+  double ms_total;      /* out: wall time of the call (device, hipEvent)           */
+  void* basis_u;        /* optional DEVICE out: left basis S (EGKB) or Y (RSVD),
+                           n^2 x (k_p+1) resp. n^2 x k_p, column-major, in the
+                           working precision                                       */
+  void* basis_v;        /* optional DEVICE out: right basis Q (EGKB, n^2 x k_p)    */
+} kp_diag;
+
+/* Kronecker factors (paper, eq. "KP approx"): A ~ sum_t Ax_t (x) Ay_t with
+ * Ax_t = sigma_t * array(u_t, n, n), Ay_t = array(v_t, n, n), array column-major;
+ * each factor is stored row-major n x n at offset t*n*n. Signs are fixed so that
+ * the largest-magnitude entry of v_t (lowest index on ties) is positive. */
+typedef struct {
+  int32_t n, k_cap;     /* in: image size and capacity (terms) of the buffers      */
+  int32_t k;            /* out: number of terms produced                           */
+  double* sigma;        /* HOST out [k_cap], descending                            */
+  void* Ax;             /* DEVICE out, k_cap * n * n                               */
+  void* Ay;             /* DEVICE out, k_cap * n * n                               */
+  kp_prec factor_prec;  /* KP_F64 or KP_F32 element type of Ax / Ay                */
+  kp_diag* diag;        /* optional                                                */
+} kp_factors;
+
+/* Split Bregman parameters (paper, Algorithms 3-5, lambda_x = lambda_y,
+ * beta_x = beta_y). tau_sb = 0 / tau_cgls = 0 mean fixed iteration counts. */
+typedef struct {
+  double lambda, beta;
+  int32_t L_max, I_max;
+  double tau_sb, tau_cgls;
+} sb_opts;
+
+typedef struct {
+  int32_t l_end;        /* outer iterations performed                              */
+  int32_t iota_total;   /* total CGLS iterations                                   */
+  double rc_sb;         /* last RC_SB                                              */
+} sb_stats;
+
+/* Context: binds `device`, owns a workspace that never exceeds
+ * hbm_budget_bytes (0 = 90% of the device's free memory). */
+kp_status kp_ctx_create(int device, size_t hbm_budget_bytes, kp_ctx** out);
+kp_status kp_ctx_destroy(kp_ctx* ctx);
+const char* kp_last_error(const kp_ctx* ctx);
+/* Library version string (static storage). */
+const char* kp_version(void);
+
+/* Y = R X (transpose = 0) or Y = R^T X (transpose = 1), the dense product with
+ * generated tiles of R(A) (the dominant step of both Algorithms 1 and 2,
+ * section 4.1). X, Y: DEVICE, n^2 x ncols column-major (ld = n^2).
+ * prec: KP_F32 (float X, Y; FP32 MFMA), KP_F64 (double; FP64 MFMA), KP_BF16 /
+ * KP_F16 (float X, Y; R tile and X rounded to 16 bits, FP32 accumulation).
+ * ncols == 1 uses the matrix-vector kernel of Algorithm 1. */
+kp_status kp_rmat_apply(kp_ctx* ctx, const kp_blur* blur, int transpose, kp_prec prec,
+                        int32_t ncols, const void* X, void* Y, void* stream);
+
+/* Rank-k KP-SVD of R(A) by EGKB (Algorithm 1). Writes out->k terms. Returns
+ * KP_W_BREAKDOWN when a breakdown was deflated (result still valid). */
+kp_status kp_svd_gkb(kp_ctx* ctx, const kp_blur* blur, const kp_gkb_opts* opts,
+                     kp_factors* out, void* stream);
+
+/* Rank-k KP-SVD of R(A) by RSVD (Algorithm 2). */
+kp_status kp_svd_rsvd(kp_ctx* ctx, const kp_blur* blur, const kp_rsvd_opts* opts,
+                      kp_factors* out, void* stream);
+
+/* array(A_k x) = sum_t Ay_t X Ax_t^T (transpose = 0) or
+ * array(A_k^T x) = sum_t Ay_t^T X Ax_t (transpose = 1) (paper, eq. "KPAx").
+ * f: KP_F64 factors (device); X, Y: DEVICE n x n row-major FP64. */
+kp_status kp_apply(kp_ctx* ctx, const kp_factors* f, int transpose, const double* X,
+                   double* Y, void* stream);
+
+/* Split Bregman anisotropic (Algorithm 3) / isotropic (Algorithm 4) TV
+ * deblurring with A replaced by A_k, CGLS inner solves (Algorithm 5), all FP64.
+ * b, x: DEVICE n x n row-major FP64; f: KP_F64 factors. stats: HOST, optional. */
+kp_status sb_solve_aniso(kp_ctx* ctx, const kp_factors* f, const double* b,
+                         const sb_opts* opts, double* x, sb_stats* stats, void* stream);
+kp_status sb_solve_iso(kp_ctx* ctx, const kp_factors* f, const double* b,
+                       const sb_opts* opts, double* x, sb_stats* stats, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* KPSB_H */

@@ -1,0 +1,98 @@
+"""ctypes binding of libkpsb.so (argument marshalling only).
+
+The structures mirror include/kpsb.h field by field. Device buffers are passed
+as raw pointers (e.g. ``tensor.data_ptr()``), the stream as a hipStream_t
+handle (``torch.cuda.current_stream().cuda_stream``). Nothing here computes.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libkpsb.so")
+
+KP_OK, KP_E_INVAL, KP_E_NOMEM, KP_E_DEVICE, KP_E_NUMERIC = 0, 1, 2, 3, 4
+KP_W_BREAKDOWN = 100
+KP_F64, KP_F32, KP_BF16, KP_F16 = 0, 1, 2, 3
+
+STATUS_NAMES = {0: "KP_OK", 1: "KP_E_INVAL", 2: "KP_E_NOMEM", 3: "KP_E_DEVICE",
+                4: "KP_E_NUMERIC", 100: "KP_W_BREAKDOWN"}
+
+# Every symbol the header declares (checked by the CPU test-suite).
+EXPORTED = ["kp_ctx_create", "kp_ctx_destroy", "kp_last_error", "kp_version",
+            "kp_rmat_apply", "kp_svd_gkb", "kp_svd_rsvd", "kp_apply",
+            "sb_solve_aniso", "sb_solve_iso"]
+
+
+class kp_blur(C.Structure):
+    _fields_ = [("n", C.c_int32), ("psf", C.POINTER(C.c_double)), ("pu", C.c_int32),
+                ("pv", C.c_int32), ("cu", C.c_int32), ("cv", C.c_int32)]
+
+
+class kp_gkb_opts(C.Structure):
+    _fields_ = [("k", C.c_int32), ("p", C.c_int32), ("k_min", C.c_int32),
+                ("auto_k", C.c_int32), ("tau", C.c_double), ("literal_init", C.c_int32),
+                ("reorth", C.c_int32), ("prec", C.c_int), ("seed", C.c_uint64),
+                ("y0", C.POINTER(C.c_double)), ("bd_rel", C.c_double)]
+
+
+class kp_rsvd_opts(C.Structure):
+    _fields_ = [("k", C.c_int32), ("p", C.c_int32), ("q", C.c_int32), ("prec", C.c_int),
+                ("refine", C.c_int32), ("seed", C.c_uint64), ("F", C.POINTER(C.c_double))]
+
+
+class kp_diag(C.Structure):
+    _fields_ = [("cap", C.c_int32), ("alpha", C.POINTER(C.c_double)),
+                ("t", C.POINTER(C.c_double)), ("kp", C.c_int32), ("nbreak", C.c_int32),
+                ("break_side", C.c_int32 * 16), ("break_step", C.c_int32 * 16),
+                ("ms_total", C.c_double), ("basis_u", C.c_void_p), ("basis_v", C.c_void_p)]
+
+
+class kp_factors(C.Structure):
+    _fields_ = [("n", C.c_int32), ("k_cap", C.c_int32), ("k", C.c_int32),
+                ("sigma", C.POINTER(C.c_double)), ("Ax", C.c_void_p), ("Ay", C.c_void_p),
+                ("factor_prec", C.c_int), ("diag", C.POINTER(kp_diag))]
+
+
+class sb_opts(C.Structure):
+    _fields_ = [("lam", C.c_double), ("beta", C.c_double), ("L_max", C.c_int32),
+                ("I_max", C.c_int32), ("tau_sb", C.c_double), ("tau_cgls", C.c_double)]
+
+
+class sb_stats(C.Structure):
+    _fields_ = [("l_end", C.c_int32), ("iota_total", C.c_int32), ("rc_sb", C.c_double)]
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load the shared library (raises if it is missing: there is no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with `python -m paper_2410_00233_amd.build`")
+    lib = C.CDLL(path)
+    vp = C.c_void_p
+    lib.kp_ctx_create.argtypes = [C.c_int, C.c_size_t, C.POINTER(vp)]
+    lib.kp_ctx_destroy.argtypes = [vp]
+    lib.kp_last_error.argtypes = [vp]
+    lib.kp_last_error.restype = C.c_char_p
+    lib.kp_version.argtypes = []
+    lib.kp_version.restype = C.c_char_p
+    lib.kp_rmat_apply.argtypes = [vp, C.POINTER(kp_blur), C.c_int, C.c_int, C.c_int32, vp, vp, vp]
+    lib.kp_svd_gkb.argtypes = [vp, C.POINTER(kp_blur), C.POINTER(kp_gkb_opts),
+                               C.POINTER(kp_factors), vp]
+    lib.kp_svd_rsvd.argtypes = [vp, C.POINTER(kp_blur), C.POINTER(kp_rsvd_opts),
+                                C.POINTER(kp_factors), vp]
+    lib.kp_apply.argtypes = [vp, C.POINTER(kp_factors), C.c_int, vp, vp, vp]
+    lib.sb_solve_aniso.argtypes = [vp, C.POINTER(kp_factors), vp, C.POINTER(sb_opts), vp,
+                                   C.POINTER(sb_stats), vp]
+    lib.sb_solve_iso.argtypes = lib.sb_solve_aniso.argtypes
+    for name in EXPORTED:
+        if name not in ("kp_last_error", "kp_version"):
+            getattr(lib, name).restype = C.c_int
+    _lib = lib
+    return lib

@@ -1,0 +1,192 @@
+"""Python binding over the C ABI (include/kpsb.h), same entry-point names.
+
+Argument marshalling only: inputs are NumPy arrays (host) or torch tensors
+(device); torch provides device memory and the current stream. Every step of
+the computation runs in libkpsb.so. If the library is missing this raises: there
+is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+
+from . import _lib as L
+
+PREC = {"f64": L.KP_F64, "f32": L.KP_F32, "bf16": L.KP_BF16, "f16": L.KP_F16}
+
+
+class KPError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{L.STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream():
+    torch = _torch()
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr())
+
+
+class Blur:
+    """PSF P (pu x pv, u vertical) with centre (cu, cv) acting on n x n images."""
+
+    def __init__(self, P, cu, cv, n):
+        self.P = np.ascontiguousarray(P, dtype=np.float64)
+        self.cu, self.cv, self.n = int(cu), int(cv), int(n)
+        self.s = L.kp_blur(self.n, self.P.ctypes.data_as(C.POINTER(C.c_double)),
+                           self.P.shape[0], self.P.shape[1], self.cu, self.cv)
+
+
+class Factors:
+    """Device Kronecker factors (k x n x n each) plus host sigma."""
+
+    def __init__(self, n, k_cap, prec="f64", device="cuda"):
+        torch = _torch()
+        dt = torch.float64 if prec == "f64" else torch.float32
+        self.n, self.k_cap, self.prec = n, k_cap, prec
+        self.Ax = torch.zeros((k_cap, n, n), dtype=dt, device=device)
+        self.Ay = torch.zeros((k_cap, n, n), dtype=dt, device=device)
+        self.sigma = np.zeros(k_cap)
+        self.diag = L.kp_diag()
+        self.diag.cap = 0
+        self.s = L.kp_factors(n, k_cap, 0, self.sigma.ctypes.data_as(C.POINTER(C.c_double)),
+                              self.Ax.data_ptr(), self.Ay.data_ptr(), PREC[prec],
+                              C.pointer(self.diag))
+        self.status = L.KP_OK
+
+    @property
+    def k(self):
+        return self.s.k
+
+
+class Context:
+    def __init__(self, device=0, hbm_budget=0):
+        self.lib = L.load()
+        h = C.c_void_p()
+        st = self.lib.kp_ctx_create(int(device), C.c_size_t(hbm_budget), C.byref(h))
+        if st != L.KP_OK:
+            raise KPError(st, "kp_ctx_create failed")
+        self.h = h
+
+    def close(self):
+        if self.h:
+            self.lib.kp_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st, allow=(L.KP_OK,)):
+        if st not in allow:
+            raise KPError(st, self.lib.kp_last_error(self.h).decode())
+        return st
+
+    # ---- entry points (names follow the C ABI) ----------------------------
+    def kp_rmat_apply(self, blur: Blur, X, transpose=False, prec="f32", Y=None):
+        """X: device tensor (n^2,) or (ncols, n^2) -- i.e. an n^2 x ncols
+        column-major block; Y has the same shape."""
+        torch = _torch()
+        assert X.is_contiguous() and X.shape[-1] == blur.n * blur.n
+        ncols = 1 if X.dim() == 1 else X.shape[0]
+        if Y is None:
+            Y = torch.empty_like(X)
+        self._check(self.lib.kp_rmat_apply(self.h, C.byref(blur.s), int(transpose), PREC[prec],
+                                           ncols, _ptr(X), _ptr(Y), _stream()))
+        return Y
+
+    def kp_svd_gkb(self, blur: Blur, k, p, *, k_min=0, auto_k=False, tau=0.0,
+                   literal_init=False, reorth=1, prec="f32", seed=0, y0=None, bd_rel=0.0,
+                   factor_prec="f64", k_cap=None, bases=False):
+        torch = _torch()
+        n = blur.n
+        f = Factors(n, k_cap or k, factor_prec)
+        y0a = None if y0 is None else np.ascontiguousarray(y0, dtype=np.float64)
+        o = L.kp_gkb_opts(k, p, k_min, int(auto_k), tau, int(literal_init), reorth, PREC[prec],
+                          seed, None if y0a is None else y0a.ctypes.data_as(C.POINTER(C.c_double)),
+                          bd_rel)
+        cap = k + p + 2
+        alpha = np.zeros(cap)
+        t = np.zeros(cap)
+        f.diag.cap = cap
+        f.diag.alpha = alpha.ctypes.data_as(C.POINTER(C.c_double))
+        f.diag.t = t.ctypes.data_as(C.POINTER(C.c_double))
+        S = Q = None
+        if bases:
+            dt = torch.float32 if prec == "f32" else torch.float64
+            S = torch.zeros((k + p + 1, n * n), dtype=dt, device="cuda")
+            Q = torch.zeros((k + p, n * n), dtype=dt, device="cuda")
+            f.diag.basis_u = S.data_ptr()
+            f.diag.basis_v = Q.data_ptr()
+        st = self._check(self.lib.kp_svd_gkb(self.h, C.byref(blur.s), C.byref(o), C.byref(f.s),
+                                             _stream()), allow=(L.KP_OK, L.KP_W_BREAKDOWN))
+        f.status = st
+        kp = f.diag.kp
+        f.alpha = alpha[:kp].copy()
+        f.t = t[:kp + 1].copy()
+        f.breakdowns = [("s" if f.diag.break_side[i] == 0 else "q", f.diag.break_step[i])
+                        for i in range(min(f.diag.nbreak, 16))]
+        f.ms = f.diag.ms_total
+        if bases:
+            f.S = S[:kp + 1]
+            f.Q = Q[:kp]
+        return f
+
+    def kp_svd_rsvd(self, blur: Blur, k, p, q, *, prec="f32", refine=False, seed=0, F=None,
+                    factor_prec="f64", k_cap=None, bases=False):
+        torch = _torch()
+        n = blur.n
+        f = Factors(n, k_cap or k, factor_prec)
+        Fa = None if F is None else np.asfortranarray(F, dtype=np.float64)
+        o = L.kp_rsvd_opts(k, p, q, PREC[prec], int(refine), seed,
+                           None if Fa is None else Fa.ctypes.data_as(C.POINTER(C.c_double)))
+        Y = None
+        if bases:
+            dt = torch.float64 if prec == "f64" else torch.float32
+            Y = torch.zeros((k + p, n * n), dtype=dt, device="cuda")
+            f.diag.basis_u = Y.data_ptr()
+        f.status = self._check(self.lib.kp_svd_rsvd(self.h, C.byref(blur.s), C.byref(o),
+                                                    C.byref(f.s), _stream()))
+        f.ms = f.diag.ms_total
+        if bases:
+            f.Y = Y
+        return f
+
+    def kp_apply(self, f: Factors, X, transpose=False, Y=None):
+        torch = _torch()
+        if Y is None:
+            Y = torch.empty_like(X)
+        self._check(self.lib.kp_apply(self.h, C.byref(f.s), int(transpose), _ptr(X), _ptr(Y),
+                                      _stream()))
+        return Y
+
+    def _sb(self, fn, f, b, lam, beta, L_max, I_max, tau_sb, tau_cgls, x):
+        torch = _torch()
+        if x is None:
+            x = torch.empty_like(b)
+        o = L.sb_opts(lam, beta, L_max, I_max, tau_sb, tau_cgls)
+        st = L.sb_stats()
+        self._check(fn(self.h, C.byref(f.s), _ptr(b), C.byref(o), _ptr(x), C.byref(st),
+                       _stream()))
+        return x, dict(l_end=st.l_end, iota_total=st.iota_total, rc_sb=st.rc_sb)
+
+    def sb_solve_aniso(self, f, b, lam, beta, L_max=50, I_max=100, tau_sb=0.0, tau_cgls=0.0,
+                       x=None):
+        return self._sb(self.lib.sb_solve_aniso, f, b, lam, beta, L_max, I_max, tau_sb,
+                        tau_cgls, x)
+
+    def sb_solve_iso(self, f, b, lam, beta, L_max=50, I_max=100, tau_sb=0.0, tau_cgls=0.0,
+                     x=None):
+        return self._sb(self.lib.sb_solve_iso, f, b, lam, beta, L_max, I_max, tau_sb,
+                        tau_cgls, x)

@@ -1,0 +1,698 @@
+// C ABI of libkpsb.so: argument validation, workspace, and the host drivers of
+// the KP-SVD (Algorithms 1 and 2 of Alsubhi & Renaut, arXiv 2410.00233) and of
+// split Bregman deblurring (Algorithms 3-5). Every arithmetic step runs in the
+// HIP kernels of this library; the host only sequences them, keeps the scalar
+// recurrences of Algorithm 1 and takes the data-dependent decisions (nu rule,
+// breakdown) exactly as the algorithm states them.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "common.h"
+#include "kpsb.h"
+
+using namespace kpsb;
+
+struct kp_ctx {
+  int device = 0;
+  size_t budget = 0;
+  size_t used = 0;
+  size_t lds_limit = 65536;
+  std::string err;
+  struct Buf {
+    void* p = nullptr;
+    size_t bytes = 0;
+  };
+  std::map<std::string, Buf> bufs;
+  double* pinned = nullptr;   // host readback buffer (64 doubles)
+};
+
+namespace {
+
+kp_status set_err(kp_ctx* c, kp_status st, const std::string& msg) {
+  if (c) c->err = msg;
+  return st;
+}
+
+#define KP_HIP(c, expr)                                                              \
+  do {                                                                               \
+    hipError_t e_ = (expr);                                                          \
+    if (e_ != hipSuccess)                                                            \
+      return set_err((c), KP_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+#define KP_TRY(expr)                \
+  do {                              \
+    kp_status st_ = (expr);         \
+    if (st_ != KP_OK) return st_;   \
+  } while (0)
+
+kp_status check_launch(kp_ctx* c, const char* where) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return set_err(c, KP_E_DEVICE, std::string(where) + ": " + hipGetErrorString(e));
+  return KP_OK;
+}
+
+// Workspace buffer `name` of at least `bytes` (contents undefined).
+kp_status ws(kp_ctx* c, const std::string& name, size_t bytes, void** out) {
+  auto& b = c->bufs[name];
+  if (b.bytes >= bytes && b.p) {
+    *out = b.p;
+    return KP_OK;
+  }
+  bytes = (bytes + 255) & ~(size_t)255;
+  size_t freed = b.bytes;
+  if (c->used - freed + bytes > c->budget)
+    return set_err(c, KP_E_NOMEM, "workspace '" + name + "' of " + std::to_string(bytes) +
+                                      " bytes exceeds the HBM budget (" +
+                                      std::to_string(c->budget) + " bytes, " +
+                                      std::to_string(c->used) + " in use)");
+  if (b.p) {
+    KP_HIP(c, hipDeviceSynchronize());
+    KP_HIP(c, hipFree(b.p));
+    c->used -= b.bytes;
+    b.p = nullptr;
+    b.bytes = 0;
+  }
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return set_err(c, KP_E_NOMEM, "hipMalloc of workspace '" + name + "' failed");
+  }
+  b.p = p;
+  b.bytes = bytes;
+  c->used += bytes;
+  *out = p;
+  return KP_OK;
+}
+
+template <typename T>
+kp_status wsT(kp_ctx* c, const std::string& name, size_t count, T** out) {
+  void* p = nullptr;
+  KP_TRY(ws(c, name, count * sizeof(T), &p));
+  *out = static_cast<T*>(p);
+  return KP_OK;
+}
+
+kp_status validate_blur(kp_ctx* c, const kp_blur* b) {
+  if (!b) return set_err(c, KP_E_INVAL, "blur is NULL");
+  if (b->n < 2 || b->n > 2048) return set_err(c, KP_E_INVAL, "n must be in [2, 2048]");
+  if (!b->psf) return set_err(c, KP_E_INVAL, "psf is NULL");
+  if (b->pu < 1 || b->pv < 1) return set_err(c, KP_E_INVAL, "psf dimensions must be >= 1");
+  if (b->cu < 0 || b->cu >= b->pu || b->cv < 0 || b->cv >= b->pv)
+    return set_err(c, KP_E_INVAL, "psf centre outside the psf array");
+  if ((long)b->pu * b->pv > (1L << 26)) return set_err(c, KP_E_INVAL, "psf too large");
+  for (long e = 0; e < (long)b->pu * b->pv; ++e)
+    if (!std::isfinite(b->psf[e])) return set_err(c, KP_E_NUMERIC, "psf has a non-finite entry");
+  return KP_OK;
+}
+
+template <typename T> const char* tname();
+template <> const char* tname<float>() { return "f32"; }
+template <> const char* tname<double>() { return "f64"; }
+template <> const char* tname<__hip_bfloat16>() { return "bf16"; }
+template <> const char* tname<__half>() { return "f16"; }
+
+template <typename T>
+struct Grids {
+  T* G = nullptr;    // grid of R
+  T* Gt = nullptr;   // grid of R^T
+  int ldg = 0;
+};
+
+kp_status upload_psf(kp_ctx* c, const kp_blur* b, hipStream_t s, double** dpsf) {
+  KP_TRY(wsT(c, "psf", (size_t)b->pu * b->pv, dpsf));
+  KP_HIP(c, hipMemcpyAsync(*dpsf, b->psf, sizeof(double) * b->pu * b->pv,
+                           hipMemcpyHostToDevice, s));
+  return KP_OK;
+}
+
+template <typename T>
+kp_status prep_grids(kp_ctx* c, const kp_blur* b, hipStream_t s, Grids<T>* g) {
+  double* dpsf = nullptr;
+  KP_TRY(upload_psf(c, b, s, &dpsf));
+  const int n = b->n;
+  g->ldg = ((2 * n - 1) + 3) & ~3;
+  const size_t cnt = (size_t)(2 * n - 1) * g->ldg;
+  KP_TRY(wsT(c, std::string("G_") + tname<T>(), cnt, &g->G));
+  KP_TRY(wsT(c, std::string("Gt_") + tname<T>(), cnt, &g->Gt));
+  launch_build_grid<T>(dpsf, b->pu, b->pv, b->cu, b->cv, n, 0, g->G, g->ldg, s);
+  launch_build_grid<T>(dpsf, b->pu, b->pv, b->cu, b->cv, n, 1, g->Gt, g->ldg, s);
+  return check_launch(c, "build_grid");
+}
+
+// Y = R X (or R^T X) for any number of columns (groups of 32 per launch).
+template <typename T>
+kp_status block_product(kp_ctx* c, const Grids<T>& g, int n, int transpose, const T* X,
+                        T* Y, int ncols, hipStream_t s) {
+  BlockPlan bp;
+  if (!plan_block<T>(n, c->lds_limit, &bp))
+    return set_err(c, KP_E_INVAL, "no block-product tiling fits the LDS at this n");
+  const long N = (long)n * n;
+  for (int c0 = 0; c0 < ncols; c0 += 32) {
+    const int nc = ncols - c0 < 32 ? ncols - c0 : 32;
+    launch_rmat_block<T>(bp, transpose ? g.Gt : g.G, g.ldg, n, X + N * c0, N, Y + N * c0, N,
+                         nc, s);
+  }
+  return check_launch(c, "rmat_block");
+}
+
+template <typename T>
+kp_status gemv_product(kp_ctx* c, const Grids<T>& g, int n, int transpose, const T* x, T* y,
+                       const T* z, double coef, hipStream_t s) {
+  BlockPlan gp;
+  if (!plan_gemv<T>(n, c->lds_limit, &gp))
+    return set_err(c, KP_E_INVAL, "no matrix-vector tiling fits the LDS at this n");
+  launch_rmat_gemv<T>(gp, transpose ? g.Gt : g.G, g.ldg, n, x, y, z, coef, s);
+  return check_launch(c, "rmat_gemv");
+}
+
+// Shared scratch of the vector kernels.
+struct Scratch {
+  double* partials = nullptr;   // kRedBlocks * 64
+  double* nrmp = nullptr;       // kRedBlocks
+  double* h = nullptr;          // 4 x 64 coefficient vectors
+  double* scal = nullptr;       // 8 scalars
+};
+
+kp_status get_scratch(kp_ctx* c, Scratch* sc) {
+  KP_TRY(wsT(c, "partials", (size_t)kRedBlocks * 64, &sc->partials));
+  KP_TRY(wsT(c, "nrmp", (size_t)kRedBlocks, &sc->nrmp));
+  KP_TRY(wsT(c, "hvec", 4 * 64, &sc->h));
+  KP_TRY(wsT(c, "scal", 8, &sc->scal));
+  return KP_OK;
+}
+
+// ||w||^2 from kRedBlocks partials, read back to the host (synchronizes s).
+kp_status read_norm(kp_ctx* c, const Scratch& sc, hipStream_t s, double* out) {
+  launch_reduce_partials(sc.nrmp, 1, sc.scal, 0, s);
+  KP_TRY(check_launch(c, "reduce_partials"));
+  KP_HIP(c, hipMemcpyAsync(c->pinned, sc.scal, sizeof(double), hipMemcpyDeviceToHost, s));
+  KP_HIP(c, hipStreamSynchronize(s));
+  *out = std::sqrt(c->pinned[0]);
+  return KP_OK;
+}
+
+// Classical Gram-Schmidt, two passes, of w against the m columns of V; leaves
+// the partial sums of ||w||^2 in sc.nrmp.
+template <typename T>
+void cgs2(const Scratch& sc, T* w, const T* V, long ldv, int m, long N, hipStream_t s) {
+  if (m == 0) {
+    launch_norm2_partials<T>(w, N, sc.nrmp, s);
+    return;
+  }
+  for (int pass = 0; pass < 2; ++pass) {
+    launch_multidot<T>(V, ldv, m, w, N, sc.partials, s);
+    launch_reduce_partials(sc.partials, m, sc.h, 0, s);
+    launch_project_out<T>(w, V, ldv, m, sc.h, N, sc.nrmp, s);
+  }
+}
+
+// Column-wise CGS2 QR of W (N x m, ld N) in place: W = Q R. Each column gets
+// two Gram-Schmidt passes, is normalized, and gets a third pass plus a second
+// normalization (guard for columns that are numerically in the span of the
+// previous ones). R (m x m, column-major FP64) is formed when Rfac != NULL.
+template <typename T>
+kp_status cgs_qr(kp_ctx* c, const Scratch& sc, T* W, long N, int m, double* Rfac,
+                 hipStream_t s) {
+  double* h2 = sc.h + 64;
+  double* h3 = sc.h + 128;
+  double* rscr = sc.scal + 2;
+  double* r3 = sc.scal + 3;
+  if (Rfac) launch_fill_small(Rfac, m * m, 0.0, s);
+  for (int j = 0; j < m; ++j) {
+    T* w = W + N * j;
+    double* Rcol = Rfac ? Rfac + (long)m * j : sc.h + 192;
+    double* rjj = Rfac ? Rfac + j + (long)m * j : rscr;
+    if (j > 0) {
+      launch_multidot<T>(W, N, j, w, N, sc.partials, s);
+      launch_reduce_partials(sc.partials, j, Rcol, 0, s);
+      launch_project_out<T>(w, W, N, j, Rcol, N, nullptr, s);
+      launch_multidot<T>(W, N, j, w, N, sc.partials, s);
+      launch_reduce_partials(sc.partials, j, h2, 0, s);
+      launch_project_out<T>(w, W, N, j, h2, N, sc.nrmp, s);
+      launch_add_small(Rcol, h2, j, s);
+    } else {
+      launch_norm2_partials<T>(w, N, sc.nrmp, s);
+    }
+    launch_normalize<T>(w, N, sc.nrmp, rjj, s);
+    if (j > 0) {
+      launch_multidot<T>(W, N, j, w, N, sc.partials, s);
+      launch_reduce_partials(sc.partials, j, h3, 0, s);
+      launch_project_out<T>(w, W, N, j, h3, N, sc.nrmp, s);
+      launch_normalize<T>(w, N, sc.nrmp, r3, s);
+      launch_cgs_fixup(Rcol, j, h3, rjj, r3, s);
+    }
+  }
+  return check_launch(c, "cgs_qr");
+}
+
+// Upload an N x m FP64 host block into device type T (through a staging buffer).
+template <typename T>
+kp_status upload_block(kp_ctx* c, const double* host, long count, T* dst, hipStream_t s) {
+  double* stage = nullptr;
+  KP_TRY(wsT(c, "stage64", (size_t)count, &stage));
+  KP_HIP(c, hipMemcpyAsync(stage, host, sizeof(double) * count, hipMemcpyHostToDevice, s));
+  launch_convert<double, T>(stage, dst, count, s);
+  return check_launch(c, "convert");
+}
+
+struct Timer {
+  hipEvent_t a = nullptr, b = nullptr;
+  hipStream_t s;
+  explicit Timer(hipStream_t st) : s(st) {
+    if (hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess)
+      (void)hipEventRecord(a, s);
+  }
+  double stop() {
+    float ms = 0.f;
+    if (a && b) {
+      (void)hipEventRecord(b, s);
+      (void)hipEventSynchronize(b);
+      (void)hipEventElapsedTime(&ms, a, b);
+    }
+    return ms;
+  }
+  ~Timer() {
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+  }
+};
+
+kp_status validate_factors_out(kp_ctx* c, const kp_factors* f, int n) {
+  if (!f) return set_err(c, KP_E_INVAL, "factors is NULL");
+  if (f->n != n) return set_err(c, KP_E_INVAL, "factors.n differs from blur.n");
+  if (!f->sigma || !f->Ax || !f->Ay) return set_err(c, KP_E_INVAL, "factors buffers are NULL");
+  if (f->factor_prec != KP_F64 && f->factor_prec != KP_F32)
+    return set_err(c, KP_E_INVAL, "factor_prec must be KP_F64 or KP_F32");
+  return KP_OK;
+}
+
+// Form Kronecker factors from left/right singular vector blocks (FP64, N x k).
+kp_status write_factors(kp_ctx* c, const double* Ud, const double* Vd, const double* sig_dev,
+                        int n, int k, kp_factors* f, hipStream_t s) {
+  int* amax = nullptr;
+  KP_TRY(wsT(c, "argmax", 64, &amax));
+  const long N = (long)n * n;
+  if (f->factor_prec == KP_F64)
+    launch_form_factors<double, double>(Ud, Vd, N, n, k, sig_dev, (double*)f->Ax,
+                                        (double*)f->Ay, amax, s);
+  else
+    launch_form_factors<double, float>(Ud, Vd, N, n, k, sig_dev, (float*)f->Ax,
+                                       (float*)f->Ay, amax, s);
+  return check_launch(c, "form_factors");
+}
+
+// ---------------------------------------------------------------------------
+// EGKB (Algorithm 1). Readings as in the oracle: nu_{j+1} = sqrt(zeta_j
+// zeta_{j-1}); zeta_1 = alpha_1 t_1, nu_2 = +inf (or the printed 1 and 100);
+// j = 2 .. k_p + 1; the nu test fires at most once, for j > k_min and
+// j - 1 != k_p, setting k = min(j, k_in); U_k = S_{k_p+1} U_C[:, :k]; a
+// breakdown stores 0 and restarts with a Philox vector (stream 2j for s_j,
+// 2j + 1 for q_j) orthogonalized against the basis.
+template <typename T>
+kp_status egkb_impl(kp_ctx* c, const kp_blur* b, const kp_gkb_opts* o, kp_factors* f,
+                    hipStream_t s) {
+  Timer timer(s);
+  const int n = b->n;
+  const long N = (long)n * n;
+  int k = o->k;
+  const int p = o->p;
+  const int k_in = k;
+  int kp = k + p;
+  const int kp0 = kp;
+  const double u = (sizeof(T) == 4) ? std::ldexp(1.0, -24) : std::ldexp(1.0, -53);
+  const double bd_rel = o->bd_rel > 0 ? o->bd_rel : 1e3 * u;
+
+  Grids<T> g;
+  KP_TRY(prep_grids<T>(c, b, s, &g));
+  Scratch sc;
+  KP_TRY(get_scratch(c, &sc));
+  T *S = nullptr, *Q = nullptr;
+  KP_TRY(wsT(c, std::string("egkbS_") + tname<T>(), (size_t)N * (kp0 + 1), &S));
+  KP_TRY(wsT(c, std::string("egkbQ_") + tname<T>(), (size_t)N * kp0, &Q));
+
+  std::vector<double> alpha, t;
+  std::vector<std::pair<int, int>> breaks;
+  auto is_bd = [&](double val, double scale) { return val <= bd_rel * scale; };
+
+  // restart vector for side (0 = s, 1 = q) at step j into w, CGS2 against V[:, :m]
+  auto restart = [&](int side, int j, T* w, const T* V, int m) -> kp_status {
+    launch_philox_normals<T>(w, N, o->seed, (uint32_t)(2 * j + side), s);
+    cgs2<T>(sc, w, V, N, m, N, s);
+    double nr = 0;
+    KP_TRY(read_norm(c, sc, s, &nr));
+    if (nr > 0) launch_scale<T>(w, N, 1.0 / nr, s);
+    breaks.push_back({side, j});
+    return check_launch(c, "restart");
+  };
+
+  // start vector y -> s_1 = y / t_1
+  if (o->y0) {
+    KP_TRY(upload_block<T>(c, o->y0, N, S, s));
+  } else {
+    launch_philox_normals<T>(S, N, o->seed, 0u, s);
+  }
+  launch_norm2_partials<T>(S, N, sc.nrmp, s);
+  double t1 = 0;
+  KP_TRY(read_norm(c, sc, s, &t1));
+  if (!(t1 > 0) || !std::isfinite(t1)) return set_err(c, KP_E_INVAL, "start vector has zero or non-finite norm");
+  launch_scale<T>(S, N, 1.0 / t1, s);
+  t.push_back(t1);
+
+  // q = B^T s_1, alpha_1 = ||q||
+  KP_TRY(gemv_product<T>(c, g, n, 1, S, Q, nullptr, 0.0, s));
+  launch_norm2_partials<T>(Q, N, sc.nrmp, s);
+  double a1 = 0;
+  KP_TRY(read_norm(c, sc, s, &a1));
+  if (!std::isfinite(a1)) return set_err(c, KP_E_NUMERIC, "non-finite alpha_1");
+  if (is_bd(a1, std::max(a1, t1))) {
+    a1 = 0.0;
+    KP_TRY(restart(1, 1, Q, Q, 0));
+  } else {
+    launch_scale<T>(Q, N, 1.0 / a1, s);
+  }
+  alpha.push_back(a1);
+  std::map<int, double> zeta, nu;
+  zeta[1] = o->literal_init ? 1.0 : a1 * t1;
+  nu[2] = o->literal_init ? 100.0 : INFINITY;
+  double scale = std::max(a1, t1);
+  bool fired = false;
+
+  for (int j = 2; j <= kp + 1; ++j) {
+    T* sj = S + N * (j - 1);
+    const T* sprev = S + N * (j - 2);
+    const T* qprev = Q + N * (j - 2);
+    // s_j = B q_{j-1} - alpha_{j-1} s_{j-1}
+    KP_TRY(gemv_product<T>(c, g, n, 0, qprev, sj, sprev, alpha.back(), s));
+    if (o->reorth == 1)
+      cgs2<T>(sc, sj, S, N, j - 1, N, s);
+    else
+      launch_norm2_partials<T>(sj, N, sc.nrmp, s);
+    double tj = 0;
+    KP_TRY(read_norm(c, sc, s, &tj));
+    if (!std::isfinite(tj)) return set_err(c, KP_E_NUMERIC, "non-finite t_j");
+    if (is_bd(tj, scale)) {
+      tj = 0.0;
+      KP_TRY(restart(0, j, sj, S, j - 1));
+    } else {
+      launch_scale<T>(sj, N, 1.0 / tj, s);
+    }
+    t.push_back(tj);
+    scale = std::max(scale, tj);
+    if (j <= kp) {
+      T* qj = Q + N * (j - 1);
+      // q_j = B^T s_j - t_j q_{j-1}, reorthogonalized against Q (step 6)
+      KP_TRY(gemv_product<T>(c, g, n, 1, sj, qj, qprev, tj, s));
+      cgs2<T>(sc, qj, Q, N, j - 1, N, s);
+      double aj = 0;
+      KP_TRY(read_norm(c, sc, s, &aj));
+      if (!std::isfinite(aj)) return set_err(c, KP_E_NUMERIC, "non-finite alpha_j");
+      if (is_bd(aj, scale)) {
+        aj = 0.0;
+        KP_TRY(restart(1, j, qj, Q, j - 1));
+      } else {
+        launch_scale<T>(qj, N, 1.0 / aj, s);
+      }
+      alpha.push_back(aj);
+      scale = std::max(scale, aj);
+      zeta[j] = aj * tj;
+      nu[j + 1] = std::sqrt(zeta[j] * zeta[j - 1]);
+      if (o->auto_k && !fired && j > o->k_min && (j - 1) != kp) {
+        if (nu[j + 1] > nu[j] || nu[j] < o->tau) {
+          fired = true;
+          k = std::min(j, k_in);
+          kp = k + p;
+        }
+      }
+    }
+  }
+  KP_TRY(check_launch(c, "egkb loop"));
+
+  // C ((kp+1) x kp lower bidiagonal) and its SVD in FP64 on the device
+  std::vector<double> C((size_t)(kp + 1) * kp, 0.0);
+  for (int i = 0; i < kp; ++i) {
+    C[i + (size_t)(kp + 1) * i] = alpha[i];
+    C[i + 1 + (size_t)(kp + 1) * i] = t[i + 1];
+  }
+  double *dC, *Uc, *sig, *Vc;
+  int* sweeps;
+  KP_TRY(wsT(c, "smallA", 64 * 64, &dC));
+  KP_TRY(wsT(c, "smallU", 64 * 64, &Uc));
+  KP_TRY(wsT(c, "smallS", 64, &sig));
+  KP_TRY(wsT(c, "smallV", 64 * 64, &Vc));
+  KP_TRY(wsT(c, "sweeps", 4, &sweeps));
+  KP_HIP(c, hipMemcpyAsync(dC, C.data(), sizeof(double) * C.size(), hipMemcpyHostToDevice, s));
+  launch_jacobi_svd(dC, kp + 1, kp, Uc, sig, Vc, sweeps, s);
+  KP_TRY(check_launch(c, "jacobi_svd"));
+
+  const int kout = std::min(k, f->k_cap);
+  double *Ud, *Vd;
+  KP_TRY(wsT(c, "Ud", (size_t)N * kout, &Ud));
+  KP_TRY(wsT(c, "Vd", (size_t)N * kout, &Vd));
+  launch_small_gemm<T, double>(S, N, kp + 1, Uc, kp + 1, kout, N, Ud, N, s);
+  launch_small_gemm<T, double>(Q, N, kp, Vc, kp, kout, N, Vd, N, s);
+  KP_TRY(check_launch(c, "small_gemm"));
+  KP_TRY(write_factors(c, Ud, Vd, sig, n, kout, f, s));
+  KP_HIP(c, hipMemcpyAsync(c->pinned, sig, sizeof(double) * kout, hipMemcpyDeviceToHost, s));
+  if (f->diag && f->diag->basis_u)
+    KP_HIP(c, hipMemcpyAsync(f->diag->basis_u, S, sizeof(T) * N * (kp + 1),
+                             hipMemcpyDeviceToDevice, s));
+  if (f->diag && f->diag->basis_v)
+    KP_HIP(c, hipMemcpyAsync(f->diag->basis_v, Q, sizeof(T) * N * kp, hipMemcpyDeviceToDevice, s));
+  KP_HIP(c, hipStreamSynchronize(s));
+  for (int i = 0; i < kout; ++i) f->sigma[i] = c->pinned[i];
+  f->k = kout;
+  if (kp_diag* d = f->diag) {
+    for (int i = 0; i < kp && i < d->cap; ++i) if (d->alpha) d->alpha[i] = alpha[i];
+    for (int i = 0; i < kp + 1 && i < d->cap; ++i) if (d->t) d->t[i] = t[i];
+    d->kp = kp;
+    d->nbreak = (int)breaks.size();
+    for (int i = 0; i < (int)breaks.size() && i < 16; ++i) {
+      d->break_side[i] = breaks[i].first;
+      d->break_step[i] = breaks[i].second;
+    }
+    d->ms_total = timer.stop();
+  }
+  return breaks.empty() ? KP_OK : KP_W_BREAKDOWN;
+}
+
+// ---------------------------------------------------------------------------
+// RSVD (Algorithm 2): Y = orth(B F); q times Z = orth(B^T Y), Y = orth(B Z);
+// H^T = B^T Y = Q_h R_h (CGS2 QR), R_h^T = U_r S V_r^T (Jacobi), so
+// H = U_r S (Q_h V_r)^T: U_k = Y U_r[:, :k], V_k = Q_h V_r[:, :k].
+template <typename T>
+kp_status rsvd_impl(kp_ctx* c, const kp_blur* b, const kp_rsvd_opts* o, kp_factors* f,
+                    hipStream_t s) {
+  Timer timer(s);
+  const int n = b->n;
+  const long N = (long)n * n;
+  const int k = o->k;
+  const int kp = o->k + o->p;
+  Grids<T> g;
+  KP_TRY(prep_grids<T>(c, b, s, &g));
+  Scratch sc;
+  KP_TRY(get_scratch(c, &sc));
+  T *Y = nullptr, *Z = nullptr;
+  KP_TRY(wsT(c, std::string("rsvdY_") + tname<T>(), (size_t)N * kp, &Y));
+  KP_TRY(wsT(c, std::string("rsvdZ_") + tname<T>(), (size_t)N * kp, &Z));
+  if (o->F) {
+    KP_TRY(upload_block<T>(c, o->F, N * kp, Z, s));
+  } else {
+    for (int col = 0; col < kp; ++col)
+      launch_philox_normals<T>(Z + N * col, N, o->seed, 0x40000000u + (uint32_t)col, s);
+  }
+  KP_TRY(block_product<T>(c, g, n, 0, Z, Y, kp, s));
+  KP_TRY(cgs_qr<T>(c, sc, Y, N, kp, nullptr, s));
+  for (int it = 0; it < o->q; ++it) {
+    KP_TRY(block_product<T>(c, g, n, 1, Y, Z, kp, s));
+    KP_TRY(cgs_qr<T>(c, sc, Z, N, kp, nullptr, s));
+    KP_TRY(block_product<T>(c, g, n, 0, Z, Y, kp, s));
+    KP_TRY(cgs_qr<T>(c, sc, Y, N, kp, nullptr, s));
+  }
+  KP_TRY(block_product<T>(c, g, n, 1, Y, Z, kp, s));   // H^T
+  double *Rh, *RhT, *Ur, *sig, *Vr;
+  int* sweeps;
+  KP_TRY(wsT(c, "smallR", 64 * 64, &Rh));
+  KP_TRY(wsT(c, "smallA", 64 * 64, &RhT));
+  KP_TRY(wsT(c, "smallU", 64 * 64, &Ur));
+  KP_TRY(wsT(c, "smallS", 64, &sig));
+  KP_TRY(wsT(c, "smallV", 64 * 64, &Vr));
+  KP_TRY(wsT(c, "sweeps", 4, &sweeps));
+  KP_TRY(cgs_qr<T>(c, sc, Z, N, kp, Rh, s));
+  launch_transpose_small(Rh, kp, kp, RhT, s);
+  launch_jacobi_svd(RhT, kp, kp, Ur, sig, Vr, sweeps, s);
+  KP_TRY(check_launch(c, "jacobi_svd"));
+  const int kout = std::min(k, f->k_cap);
+  double *Ud, *Vd;
+  KP_TRY(wsT(c, "Ud", (size_t)N * kout, &Ud));
+  KP_TRY(wsT(c, "Vd", (size_t)N * kout, &Vd));
+  launch_small_gemm<T, double>(Y, N, kp, Ur, kp, kout, N, Ud, N, s);
+  launch_small_gemm<T, double>(Z, N, kp, Vr, kp, kout, N, Vd, N, s);
+  KP_TRY(check_launch(c, "small_gemm"));
+  KP_TRY(write_factors(c, Ud, Vd, sig, n, kout, f, s));
+  KP_HIP(c, hipMemcpyAsync(c->pinned, sig, sizeof(double) * kout, hipMemcpyDeviceToHost, s));
+  if (f->diag && f->diag->basis_u)
+    KP_HIP(c, hipMemcpyAsync(f->diag->basis_u, Y, sizeof(T) * N * kp, hipMemcpyDeviceToDevice, s));
+  KP_HIP(c, hipStreamSynchronize(s));
+  for (int i = 0; i < kout; ++i) f->sigma[i] = c->pinned[i];
+  f->k = kout;
+  if (kp_diag* d = f->diag) {
+    d->kp = kp;
+    d->nbreak = 0;
+    d->ms_total = timer.stop();
+  }
+  return KP_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+extern "C" {
+
+const char* kp_version(void) { return "kpsb 0.1 (gfx950)"; }
+
+kp_status kp_ctx_create(int device, size_t hbm_budget_bytes, kp_ctx** out) {
+  if (!out) return KP_E_INVAL;
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return KP_E_DEVICE;
+  if (hipSetDevice(device) != hipSuccess) return KP_E_DEVICE;
+  kp_ctx* c = new kp_ctx();
+  c->device = device;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) != hipSuccess) {
+    delete c;
+    return KP_E_DEVICE;
+  }
+  c->lds_limit = prop.sharedMemPerBlock;
+  if (prop.maxSharedMemoryPerMultiProcessor > 0 &&
+      (size_t)prop.maxSharedMemoryPerMultiProcessor < c->lds_limit)
+    c->lds_limit = prop.maxSharedMemoryPerMultiProcessor;
+  size_t freeb = 0, totalb = 0;
+  if (hipMemGetInfo(&freeb, &totalb) != hipSuccess) {
+    delete c;
+    return KP_E_DEVICE;
+  }
+  c->budget = hbm_budget_bytes ? hbm_budget_bytes : (size_t)(0.9 * (double)freeb);
+  if (hipHostMalloc((void**)&c->pinned, 64 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+    delete c;
+    return KP_E_DEVICE;
+  }
+  *out = c;
+  return KP_OK;
+}
+
+kp_status kp_ctx_destroy(kp_ctx* c) {
+  if (!c) return KP_E_INVAL;
+  (void)hipSetDevice(c->device);
+  (void)hipDeviceSynchronize();
+  for (auto& kv : c->bufs)
+    if (kv.second.p) (void)hipFree(kv.second.p);
+  if (c->pinned) (void)hipHostFree(c->pinned);
+  delete c;
+  return KP_OK;
+}
+
+const char* kp_last_error(const kp_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+kp_status kp_rmat_apply(kp_ctx* c, const kp_blur* b, int transpose, kp_prec prec, int32_t ncols,
+                        const void* X, void* Y, void* stream) {
+  if (!c) return KP_E_INVAL;
+  KP_TRY(validate_blur(c, b));
+  if (ncols < 1 || ncols > 4096) return set_err(c, KP_E_INVAL, "ncols must be in [1, 4096]");
+  if (!X || !Y) return set_err(c, KP_E_INVAL, "X or Y is NULL");
+  if (X == Y) return set_err(c, KP_E_INVAL, "X and Y must not alias");
+  KP_HIP(c, hipSetDevice(c->device));
+  hipStream_t s = (hipStream_t)stream;
+  const int n = b->n;
+  if (prec == KP_F32) {
+    Grids<float> g;
+    KP_TRY(prep_grids<float>(c, b, s, &g));
+    if (ncols == 1)
+      return gemv_product<float>(c, g, n, transpose, (const float*)X, (float*)Y, nullptr, 0.0, s);
+    return block_product<float>(c, g, n, transpose, (const float*)X, (float*)Y, ncols, s);
+  }
+  if (prec == KP_F64) {
+    Grids<double> g;
+    KP_TRY(prep_grids<double>(c, b, s, &g));
+    if (ncols == 1)
+      return gemv_product<double>(c, g, n, transpose, (const double*)X, (double*)Y, nullptr,
+                                  0.0, s);
+    return block_product<double>(c, g, n, transpose, (const double*)X, (double*)Y, ncols, s);
+  }
+  return set_err(c, KP_E_INVAL, "precision not supported by kp_rmat_apply");
+}
+
+kp_status kp_svd_gkb(kp_ctx* c, const kp_blur* b, const kp_gkb_opts* o, kp_factors* f,
+                     void* stream) {
+  if (!c) return KP_E_INVAL;
+  KP_TRY(validate_blur(c, b));
+  if (!o) return set_err(c, KP_E_INVAL, "opts is NULL");
+  KP_TRY(validate_factors_out(c, f, b->n));
+  const long N = (long)b->n * b->n;
+  if (o->k < 1 || o->p < 0) return set_err(c, KP_E_INVAL, "need k >= 1 and p >= 0");
+  if (o->k + o->p + 1 > 64) return set_err(c, KP_E_INVAL, "k + p must be <= 63");
+  if (o->k + o->p + 1 > N) return set_err(c, KP_E_INVAL, "k + p must be < n^2");
+  if (o->reorth != 0 && o->reorth != 1) return set_err(c, KP_E_INVAL, "reorth must be 0 or 1");
+  if (f->k_cap < 1) return set_err(c, KP_E_INVAL, "factors.k_cap must be >= 1");
+  if (o->y0)
+    for (long e = 0; e < N; ++e)
+      if (!std::isfinite(o->y0[e])) return set_err(c, KP_E_NUMERIC, "y0 has a non-finite entry");
+  KP_HIP(c, hipSetDevice(c->device));
+  hipStream_t s = (hipStream_t)stream;
+  if (o->prec == KP_F32) return egkb_impl<float>(c, b, o, f, s);
+  if (o->prec == KP_F64) return egkb_impl<double>(c, b, o, f, s);
+  return set_err(c, KP_E_INVAL, "EGKB precision must be KP_F32 or KP_F64");
+}
+
+kp_status kp_svd_rsvd(kp_ctx* c, const kp_blur* b, const kp_rsvd_opts* o, kp_factors* f,
+                      void* stream) {
+  if (!c) return KP_E_INVAL;
+  KP_TRY(validate_blur(c, b));
+  if (!o) return set_err(c, KP_E_INVAL, "opts is NULL");
+  KP_TRY(validate_factors_out(c, f, b->n));
+  const long N = (long)b->n * b->n;
+  if (o->k < 1 || o->p < 0 || o->q < 0) return set_err(c, KP_E_INVAL, "need k >= 1, p >= 0, q >= 0");
+  if (o->k + o->p > 64) return set_err(c, KP_E_INVAL, "k + p must be <= 64");
+  if (o->k + o->p > N) return set_err(c, KP_E_INVAL, "k + p must be <= n^2");
+  if (f->k_cap < 1) return set_err(c, KP_E_INVAL, "factors.k_cap must be >= 1");
+  if (o->F)
+    for (long e = 0; e < N * (o->k + o->p); ++e)
+      if (!std::isfinite(o->F[e])) return set_err(c, KP_E_NUMERIC, "F has a non-finite entry");
+  KP_HIP(c, hipSetDevice(c->device));
+  hipStream_t s = (hipStream_t)stream;
+  if (o->prec == KP_F32) return rsvd_impl<float>(c, b, o, f, s);
+  if (o->prec == KP_F64) return rsvd_impl<double>(c, b, o, f, s);
+  return set_err(c, KP_E_INVAL, "RSVD precision not supported yet");
+}
+
+kp_status kp_apply(kp_ctx* c, const kp_factors* f, int transpose, const double* X, double* Y,
+                   void* stream) {
+  if (!c) return KP_E_INVAL;
+  (void)f; (void)transpose; (void)X; (void)Y; (void)stream;
+  return set_err(c, KP_E_INVAL, "kp_apply: not available in this build");
+}
+
+kp_status sb_solve_aniso(kp_ctx* c, const kp_factors* f, const double* b, const sb_opts* o,
+                         double* x, sb_stats* st, void* stream) {
+  if (!c) return KP_E_INVAL;
+  (void)f; (void)b; (void)o; (void)x; (void)st; (void)stream;
+  return set_err(c, KP_E_INVAL, "sb_solve_aniso: not available in this build");
+}
+
+kp_status sb_solve_iso(kp_ctx* c, const kp_factors* f, const double* b, const sb_opts* o,
+                       double* x, sb_stats* st, void* stream) {
+  if (!c) return KP_E_INVAL;
+  (void)f; (void)b; (void)o; (void)x; (void)st; (void)stream;
+  return set_err(c, KP_E_INVAL, "sb_solve_iso: not available in this build");
+}
+
+}  // extern "C"

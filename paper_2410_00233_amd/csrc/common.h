@@ -1,0 +1,114 @@
+// Internal declarations shared by the HIP kernels and the host drivers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_bf16.h>
+#include <hip/hip_fp16.h>
+
+#include <cstdint>
+
+namespace kpsb {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+
+// Number of partial sums written by the reduction kernels (fixed, so that
+// every reduction adds in the same order on every call: deterministic).
+constexpr int kRedBlocks = 256;
+constexpr int kRedThreads = 256;
+
+// Offset grid of the PSF in the order R(A) uses it:
+//   G[a][b] = P[cu + (b - (n-1)), cv + (a - (n-1))],  a, b in [0, 2n-1),
+// so that R[i + n*j, r + n*c] = G[i - j + n - 1][r - c + n - 1]. The grid of
+// R(A)^T is G^T (the blur with PSF P^T and swapped centre).
+template <typename T>
+void launch_build_grid(const double* psf, int pu, int pv, int cu, int cv, int n,
+                       int transpose, T* G, int ldg, hipStream_t s);
+
+// ---- generated-tile products (rmat_block.hip / rmat_gemv.hip) --------------
+struct BlockPlan {
+  int TJ;      // j-blocks (16 rows each) per workgroup
+  int SW;      // LDS slab row stride (elements)
+  size_t lds;  // dynamic LDS bytes
+  int grid;    // workgroups
+};
+template <typename T>
+bool plan_block(int n, size_t lds_limit, BlockPlan* plan);
+template <typename T>
+void launch_rmat_block(const BlockPlan& plan, const T* G, int ldg, int n, const T* X,
+                       long ldx, T* Y, long ldy, int ncols, hipStream_t s);
+
+// 16-bit-input variant: X (float) and the 16-bit grid; FP32 accumulate.
+bool plan_block16(int n, size_t lds_limit, BlockPlan* plan);
+template <typename H>
+void launch_rmat_block16(const BlockPlan& plan, const H* G16, int ldg, int n,
+                         const float* X, long ldx, float* Y, long ldy, int ncols,
+                         hipStream_t s);
+
+template <typename T>
+bool plan_gemv(int n, size_t lds_limit, BlockPlan* plan);
+// y = R x - coef * z   (z may be null)
+template <typename T>
+void launch_rmat_gemv(const BlockPlan& plan, const T* G, int ldg, int n, const T* x,
+                      T* y, const T* z, double coef, hipStream_t s);
+
+// ---- vector kernels (blas1.hip) --------------------------------------------
+// partials[b * m + i] = sum over rows of block b of V[:, i] . w  (FP64 accum)
+template <typename T>
+void launch_multidot(const T* V, long ldv, int m, const T* w, long N, double* partials,
+                     hipStream_t s);
+// h[i] (+)= sum_b partials[b*m + i]; if accumulate != 0 adds into h
+void launch_reduce_partials(const double* partials, int m, double* h, int accumulate,
+                            hipStream_t s);
+// w -= V h (m columns); nrm_partials[b] = block partial of ||w_new||^2
+template <typename T>
+void launch_project_out(T* w, const T* V, long ldv, int m, const double* h, long N,
+                        double* nrm_partials, hipStream_t s);
+// nrm_partials[b] = block partial of ||w||^2
+template <typename T>
+void launch_norm2_partials(const T* w, long N, double* nrm_partials, hipStream_t s);
+// Normalize w by the norm reduced from nrm_partials; *norm_out = ||w||
+// (written by block 0; may be null). A zero vector is left unchanged.
+template <typename T>
+void launch_normalize(T* w, long N, const double* nrm_partials, double* norm_out,
+                      hipStream_t s);
+template <typename T>
+void launch_scale(T* w, long N, double factor, hipStream_t s);
+// out[e] = Philox normal number e of (seed, stream)
+template <typename T>
+void launch_philox_normals(T* out, long N, uint64_t seed, uint32_t stream_id,
+                           hipStream_t s);
+template <typename S, typename D>
+void launch_convert(const S* in, D* out, long N, hipStream_t s);
+// out = V * C (V: N x m column-major ld ldv; C: m x k column-major FP64, ld ldc)
+template <typename T, typename O>
+void launch_small_gemm(const T* V, long ldv, int m, const double* C, int ldc, int k,
+                       long N, O* out, long ldo, hipStream_t s);
+
+// ---- single-workgroup helpers (smallops.hip) ---------------------------------
+void launch_add_small(double* Rcol, const double* h, int m, hipStream_t s);
+void launch_cgs_fixup(double* Rcol, int m, const double* h3, double* rjj, const double* r3,
+                      hipStream_t s);
+void launch_transpose_small(const double* in, int m, int nc, double* out, hipStream_t s);
+void launch_fill_small(double* p, int m, double v, hipStream_t s);
+
+// ---- small dense SVD (jacobi.hip) ------------------------------------------
+// One-sided Jacobi SVD of an m x nc FP64 matrix (m >= nc, column-major, ld m,
+// m <= 64, nc <= 64): U (m x nc), sig (nc, descending), V (nc x nc).
+void launch_jacobi_svd(const double* A, int m, int nc, double* U, double* sig,
+                       double* V, int* sweeps, hipStream_t s);
+
+// ---- Kronecker factors (factors.hip) ---------------------------------------
+// For t < k: find the index of the largest |v_t| (lowest on ties), then write
+// Ax_t = sgn * sigma_t * array(u_t) and Ay_t = sgn * array(v_t) row-major.
+template <typename T, typename O>
+void launch_form_factors(const T* U, const T* V, long ldu, int n, int k,
+                         const double* sigma, O* Ax, O* Ay, int* argmax_scratch,
+                         hipStream_t s);
+
+// ---- KP apply and split Bregman (kp_apply.hip / sb.hip) --------------------
+void launch_kp_apply(const double* Ax, const double* Ay, int n, int k, int transpose,
+                     const double* X, double* Y, double* T1, const int* skip,
+                     hipStream_t s);
+
+}  // namespace kpsb

@@ -1,0 +1,310 @@
+// Generated-tile block product Y = R X with R = R(A) the rearranged blur
+// (paper section 2.1; the dominant cost of Algorithms 1 and 2 per section 4.1).
+//
+// R is never stored. A workgroup owns 16 consecutive rows i in each of TJ
+// consecutive row blocks j (R row i + n*j). Every entry of those rows is
+// R[i + n*j, r + n*c] = G[i - j + n - 1][r - c + n - 1] (G = offset grid of the
+// PSF), so the 16 + TJ - 1 grid rows they touch are copied once into LDS (the
+// "slab") and every MFMA A-fragment is generated from the slab. The product is
+// the full dense contraction over all n^2 columns of R: nothing is skipped or
+// merged, whatever the PSF.
+//
+// X streams through LDS in K-tiles of TK entries (fixed c, r0 <= r < r0 + TK),
+// double buffered, one barrier per tile. MFMA: v_mfma_f32_16x16x4f32 (FP32) or
+// v_mfma_f64_16x16x4f64 (FP64); fragment layout (CDNA3/4 ISA): A lane l holds
+// row l%16, k = l/16; B lane l holds k = l/16, column l%16; D lane l holds
+// rows 4*(l/16) + e (e = 0..3), column l%16.
+#include "common.h"
+
+namespace kpsb {
+
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void build_grid_kernel(const double* __restrict__ psf, int pu, int pv, int cu,
+                                  int cv, int n, int transpose, T* __restrict__ G, int ldg) {
+  const int g2 = 2 * n - 1;
+  const long total = (long)g2 * ldg;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total;
+       e += (long)gridDim.x * blockDim.x) {
+    int a = (int)(e / ldg);
+    int b = (int)(e - (long)a * ldg);
+    double v = 0.0;
+    if (b < g2) {
+      // G[a][b] = P[cu + b - (n-1), cv + a - (n-1)]; the transposed grid swaps a, b.
+      int aa = transpose ? b : a;
+      int bb = transpose ? a : b;
+      int u = cu + bb - (n - 1);
+      int w = cv + aa - (n - 1);
+      if (u >= 0 && u < pu && w >= 0 && w < pv) v = psf[(long)u * pv + w];
+    }
+    G[e] = (T)v;
+  }
+}
+
+template <>
+__global__ void build_grid_kernel<__hip_bfloat16>(const double* __restrict__ psf, int pu,
+                                                  int pv, int cu, int cv, int n, int transpose,
+                                                  __hip_bfloat16* __restrict__ G, int ldg) {
+  const int g2 = 2 * n - 1;
+  const long total = (long)g2 * ldg;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total;
+       e += (long)gridDim.x * blockDim.x) {
+    int a = (int)(e / ldg);
+    int b = (int)(e - (long)a * ldg);
+    double v = 0.0;
+    if (b < g2) {
+      int aa = transpose ? b : a;
+      int bb = transpose ? a : b;
+      int u = cu + bb - (n - 1);
+      int w = cv + aa - (n - 1);
+      if (u >= 0 && u < pu && w >= 0 && w < pv) v = psf[(long)u * pv + w];
+    }
+    G[e] = __float2bfloat16((float)v);
+  }
+}
+
+template <>
+__global__ void build_grid_kernel<__half>(const double* __restrict__ psf, int pu, int pv,
+                                          int cu, int cv, int n, int transpose,
+                                          __half* __restrict__ G, int ldg) {
+  const int g2 = 2 * n - 1;
+  const long total = (long)g2 * ldg;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total;
+       e += (long)gridDim.x * blockDim.x) {
+    int a = (int)(e / ldg);
+    int b = (int)(e - (long)a * ldg);
+    double v = 0.0;
+    if (b < g2) {
+      int aa = transpose ? b : a;
+      int bb = transpose ? a : b;
+      int u = cu + bb - (n - 1);
+      int w = cv + aa - (n - 1);
+      if (u >= 0 && u < pu && w >= 0 && w < pv) v = psf[(long)u * pv + w];
+    }
+    G[e] = __float2half((float)v);
+  }
+}
+
+template <typename T>
+void launch_build_grid(const double* psf, int pu, int pv, int cu, int cv, int n,
+                       int transpose, T* G, int ldg, hipStream_t s) {
+  long total = (long)(2 * n - 1) * ldg;
+  int blocks = (int)((total + 255) / 256);
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(build_grid_kernel<T>, dim3(blocks), dim3(256), 0, s, psf, pu, pv, cu,
+                     cv, n, transpose, G, ldg);
+}
+template void launch_build_grid<float>(const double*, int, int, int, int, int, int, float*,
+                                       int, hipStream_t);
+template void launch_build_grid<double>(const double*, int, int, int, int, int, int,
+                                        double*, int, hipStream_t);
+template void launch_build_grid<__hip_bfloat16>(const double*, int, int, int, int, int,
+                                                int, __hip_bfloat16*, int, hipStream_t);
+template void launch_build_grid<__half>(const double*, int, int, int, int, int, int,
+                                        __half*, int, hipStream_t);
+
+// ---------------------------------------------------------------------------
+template <typename T> struct Vec4;
+template <> struct Vec4<float> { typedef floatx4 type; };
+template <> struct Vec4<double> { typedef doublex4 type; };
+
+__device__ __forceinline__ floatx4 mfma16x16x4(float a, float b, floatx4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ doublex4 mfma16x16x4(double a, double b, doublex4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+constexpr int kTK = 32;   // K-tile (entries of r per staged X tile)
+constexpr int kXS = 48;   // LDS row stride of the staged X tile (bank-conflict free)
+
+template <typename T, int TJ, int JB, int CB>
+__global__ void __launch_bounds__(64 * (2 * TJ) / (JB * CB))
+rmat_block_kernel(const T* __restrict__ G, int ldg, int n, const T* __restrict__ X, long ldx,
+                  T* __restrict__ Y, long ldy, int ncols, int SW) {
+  constexpr int WAVES = (2 * TJ) / (JB * CB);
+  constexpr int NT = 64 * WAVES;
+  constexpr int SR = 16 + TJ - 1;
+  constexpr int WC = 2 / CB;                 // waves along the 32 output columns
+  constexpr int LPT = (kTK * 32) / NT;       // X elements staged per thread
+  typedef typename Vec4<T>::type acc_t;
+
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  T* slab = reinterpret_cast<T*>(lds_raw);
+  T* xbuf = slab + SR * SW;                  // two buffers of kTK * kXS
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int n_it = (n + 15) >> 4;
+  const int it = blockIdx.x % n_it;
+  const int jt = blockIdx.x / n_it;
+  const int i0 = it * 16;
+  const int j0 = jt * TJ;
+  const int g2 = 2 * n - 1;
+  const int a0 = i0 - j0 - (TJ - 1) + n - 1;
+
+  // ---- slab: grid rows a0 .. a0 + SR - 1, zero outside the grid ----------
+  for (int al = 0; al < SR; ++al) {
+    const int a = a0 + al;
+    const bool rowok = (a >= 0) && (a < g2);
+    const T* src = G + (long)(rowok ? a : 0) * ldg;
+    for (int col = tid; col < SW; col += NT) {
+      T v = (T)0;
+      if (rowok && col < g2) v = src[col];
+      slab[al * SW + col] = v;
+    }
+  }
+
+  const int nrc = (n + kTK - 1) / kTK;       // r-chunks per column block c
+  const int total = n * nrc;
+
+  // staged X element e = tid + NT*m: kk = e % kTK, col = e / kTK
+  T stage[LPT];
+  auto load_tile = [&](int t) {
+    const int c = t / nrc;
+    const int r0 = (t - c * nrc) * kTK;
+#pragma unroll
+    for (int m = 0; m < LPT; ++m) {
+      const int e = tid + NT * m;
+      const int kk = e % kTK;
+      const int col = e / kTK;
+      const int r = r0 + kk;
+      T v = (T)0;
+      if (r < n && col < ncols) v = X[(long)col * ldx + (long)n * c + r];
+      stage[m] = v;
+    }
+  };
+  auto store_tile = [&](int buf) {
+    T* xs = xbuf + buf * (kTK * kXS);
+#pragma unroll
+    for (int m = 0; m < LPT; ++m) {
+      const int e = tid + NT * m;
+      xs[(e % kTK) * kXS + e / kTK] = stage[m];
+    }
+  };
+
+  acc_t acc[JB][CB];
+#pragma unroll
+  for (int jb = 0; jb < JB; ++jb)
+#pragma unroll
+    for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) acc[jb][cb][e] = (T)0;
+
+  const int wc = wave % WC;
+  const int wj = wave / WC;
+  const int lrow = lane & 15;
+  const int lk = lane >> 4;
+  // slab row offset of every A fragment of this wave (independent of the tile)
+  int arow[JB];
+#pragma unroll
+  for (int jb = 0; jb < JB; ++jb) arow[jb] = (lrow + (TJ - 1) - (wj * JB + jb)) * SW;
+
+  load_tile(0);
+  store_tile(0);
+  __syncthreads();
+
+  for (int t = 0; t < total; ++t) {
+    if (t + 1 < total) load_tile(t + 1);
+    const int c = t / nrc;
+    const int r0 = (t - c * nrc) * kTK;
+    const int colbase = r0 - c + n - 1;
+    const T* xs = xbuf + (t & 1) * (kTK * kXS);
+#pragma unroll
+    for (int s = 0; s < kTK / 4; ++s) {
+      const int kk = 4 * s + lk;
+      T bfr[CB];
+#pragma unroll
+      for (int cb = 0; cb < CB; ++cb) bfr[cb] = xs[kk * kXS + (wc * CB + cb) * 16 + lrow];
+      T afr[JB];
+#pragma unroll
+      for (int jb = 0; jb < JB; ++jb) afr[jb] = slab[arow[jb] + colbase + kk];
+#pragma unroll
+      for (int jb = 0; jb < JB; ++jb)
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb) acc[jb][cb] = mfma16x16x4(afr[jb], bfr[cb], acc[jb][cb]);
+    }
+    if (t + 1 < total) store_tile((t + 1) & 1);
+    __syncthreads();
+  }
+
+  // ---- epilogue -----------------------------------------------------------
+#pragma unroll
+  for (int jb = 0; jb < JB; ++jb) {
+    const int j = j0 + wj * JB + jb;
+#pragma unroll
+    for (int cb = 0; cb < CB; ++cb) {
+      const int col = (wc * CB + cb) * 16 + lrow;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int i = i0 + 4 * lk + e;
+        if (i < n && j < n && col < ncols) Y[(long)col * ldy + i + (long)n * j] = acc[jb][cb][e];
+      }
+    }
+  }
+}
+
+template <typename T>
+static int slab_stride(int n) {
+  const int nrc = (n + kTK - 1) / kTK;
+  const int W = nrc * kTK + n - 1;
+  if (sizeof(T) == 4) return ((W + 63) / 64) * 64 + 4;     // 4 (mod 64) floats
+  return ((W + 31) / 32) * 32 + 2;                         // 2 (mod 32) doubles
+}
+
+template <typename T>
+static size_t block_lds(int n, int TJ) {
+  return sizeof(T) * ((size_t)(16 + TJ - 1) * slab_stride<T>(n) + 2 * kTK * kXS);
+}
+
+template <typename T>
+bool plan_block(int n, size_t lds_limit, BlockPlan* plan) {
+  static const int cand[] = {16, 8, 4, 2, 1};
+  int forced = 0;
+  if (const char* e = getenv("KPSB_BLOCK_TJ")) forced = atoi(e);
+  for (int TJ : cand) {
+    if (forced && TJ != forced) continue;
+    size_t lds = block_lds<T>(n, TJ);
+    if (lds <= lds_limit) {
+      plan->TJ = TJ;
+      plan->SW = slab_stride<T>(n);
+      plan->lds = lds;
+      plan->grid = ((n + 15) / 16) * ((n + TJ - 1) / TJ);
+      return true;
+    }
+  }
+  return false;
+}
+template bool plan_block<float>(int, size_t, BlockPlan*);
+template bool plan_block<double>(int, size_t, BlockPlan*);
+
+template <typename T, int TJ, int JB, int CB>
+static void launch_tj(const BlockPlan& p, const T* G, int ldg, int n, const T* X, long ldx,
+                      T* Y, long ldy, int ncols, hipStream_t s) {
+  auto kern = rmat_block_kernel<T, TJ, JB, CB>;
+  constexpr int threads = 64 * (2 * TJ) / (JB * CB);
+  if (p.lds > 65536)
+    (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)p.lds);
+  hipLaunchKernelGGL(kern, dim3(p.grid), dim3(threads), p.lds, s, G, ldg, n, X, ldx, Y, ldy,
+                     ncols, p.SW);
+}
+
+template <typename T>
+void launch_rmat_block(const BlockPlan& p, const T* G, int ldg, int n, const T* X, long ldx,
+                       T* Y, long ldy, int ncols, hipStream_t s) {
+  switch (p.TJ) {
+    case 16: launch_tj<T, 16, 4, 2>(p, G, ldg, n, X, ldx, Y, ldy, ncols, s); break;
+    case 8: launch_tj<T, 8, 2, 2>(p, G, ldg, n, X, ldx, Y, ldy, ncols, s); break;
+    case 4: launch_tj<T, 4, 1, 2>(p, G, ldg, n, X, ldx, Y, ldy, ncols, s); break;
+    case 2: launch_tj<T, 2, 1, 1>(p, G, ldg, n, X, ldx, Y, ldy, ncols, s); break;
+    default: launch_tj<T, 1, 1, 1>(p, G, ldg, n, X, ldx, Y, ldy, ncols, s); break;
+  }
+}
+template void launch_rmat_block<float>(const BlockPlan&, const float*, int, int, const float*,
+                                       long, float*, long, int, hipStream_t);
+template void launch_rmat_block<double>(const BlockPlan&, const double*, int, int,
+                                        const double*, long, double*, long, int, hipStream_t);
+
+}  // namespace kpsb

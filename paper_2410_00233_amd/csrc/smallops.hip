@@ -1,0 +1,51 @@
+// Tiny single-workgroup helpers used between the Gram-Schmidt passes and the
+// small SVDs (bookkeeping of the triangular factor, transposes).
+#include "common.h"
+
+namespace kpsb {
+
+// Rcol[i] += h[i]  (i < m)
+__global__ void add_small_kernel(double* __restrict__ Rcol, const double* __restrict__ h, int m) {
+  const int i = threadIdx.x;
+  if (i < m) Rcol[i] += h[i];
+}
+void launch_add_small(double* Rcol, const double* h, int m, hipStream_t s) {
+  if (m > 0) hipLaunchKernelGGL(add_small_kernel, dim3(1), dim3(64), 0, s, Rcol, h, m);
+}
+
+// After a third Gram-Schmidt pass on the normalized column q = w / r:
+// q = sum_i h3_i v_i + r3 q', hence w = sum_i (R_ij + r h3_i) v_i + r r3 q'.
+__global__ void cgs_fixup_kernel(double* __restrict__ Rcol, int m, const double* __restrict__ h3,
+                                 double* __restrict__ rjj, const double* __restrict__ r3) {
+  const int i = threadIdx.x;
+  const double r = *rjj;
+  if (i < m) Rcol[i] += r * h3[i];
+  __syncthreads();
+  if (i == 0) *rjj = r * (*r3);
+}
+void launch_cgs_fixup(double* Rcol, int m, const double* h3, double* rjj, const double* r3,
+                      hipStream_t s) {
+  hipLaunchKernelGGL(cgs_fixup_kernel, dim3(1), dim3(64), 0, s, Rcol, m, h3, rjj, r3);
+}
+
+// out (nc x m, ld nc) = in^T (in: m x nc, ld m)
+__global__ void transpose_small_kernel(const double* __restrict__ in, int m, int nc,
+                                       double* __restrict__ out) {
+  for (int e = threadIdx.x; e < m * nc; e += blockDim.x) {
+    const int r = e % m, c = e / m;
+    out[c + (long)nc * r] = in[e];
+  }
+}
+void launch_transpose_small(const double* in, int m, int nc, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(transpose_small_kernel, dim3(1), dim3(256), 0, s, in, m, nc, out);
+}
+
+// fill a small FP64 array
+__global__ void fill_small_kernel(double* __restrict__ p, int m, double v) {
+  for (int e = threadIdx.x; e < m; e += blockDim.x) p[e] = v;
+}
+void launch_fill_small(double* p, int m, double v, hipStream_t s) {
+  hipLaunchKernelGGL(fill_small_kernel, dim3(1), dim3(256), 0, s, p, m, v);
+}
+
+}  // namespace kpsb

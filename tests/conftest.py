@@ -26,3 +26,12 @@ def pytest_collection_modifyitems(config, items):
     for item in items:
         if "gpu" in item.keywords:
             item.add_marker(skip)
+
+
+@pytest.fixture(scope="session")
+def ctx():
+    """One library context for the GPU tests (the HIP library must be built)."""
+    from paper_2410_00233_amd import api
+    c = api.Context(0)
+    yield c
+    c.close()

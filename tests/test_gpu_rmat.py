@@ -1,0 +1,82 @@
+"""Parity of the generated-tile products R X / R^T X (block MFMA kernel and the
+matrix-vector kernel) against the oracle, element by element.
+
+Reference: explicit entries of R(A) from the oracle (section 2.1 rearrangement)
+in float64. FP64 kernels: |err| <= 1e-13 max|ref|. FP32 kernels: the forward
+error bound of a length-K dot product, |err| <= c K u (|R||X|) with u = 2^-24;
+we use 4 * sqrt(K) * u as the statistical scale (rounding errors of FP32
+accumulation are random-signed) with a floor of 2 K u max|.|, i.e. the test
+allows |err| <= 2e-6 * (|R| |X|) + 1e-7 * max(|R||X|).
+"""
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle import operator as op
+
+pytestmark = pytest.mark.gpu
+
+
+def _run(ctx, P, cu, cv, n, X, transpose, prec):
+    """X: (n^2,) or (n^2, b) host array; the device block is column-major, i.e. a
+    (b, n^2) row-major tensor."""
+    import torch
+    from paper_2410_00233_amd import api
+    dt = torch.float64 if prec == "f64" else torch.float32
+    Xt = torch.tensor(X if X.ndim == 1 else np.ascontiguousarray(X.T), dtype=dt, device="cuda")
+    Y = ctx.kp_rmat_apply(api.Blur(P, cu, cv, n), Xt, transpose=transpose, prec=prec)
+    torch.cuda.synchronize()
+    Yh = Y.cpu().numpy().astype(np.float64)
+    return Yh if X.ndim == 1 else Yh.T
+
+
+def _check(Y, R, X, prec):
+    ref = R @ X
+    mag = np.abs(R) @ np.abs(X)
+    if prec == "f64":
+        assert np.abs(Y - ref).max() <= 1e-13 * max(mag.max(), 1e-300)
+    else:
+        assert np.all(np.abs(Y - ref) <= 2e-6 * mag + 1e-7 * mag.max())
+
+
+CASES = [(2, (1, 1), 0), (5, (3, 4), 1), (12, (5, 7), 2), (16, (9, 9), 3), (20, (30, 30), 4),
+         (33, (7, 40), 5), (48, (95, 95), 6)]
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+@pytest.mark.parametrize("ncols", [1, 3, 32, 37])
+@pytest.mark.parametrize("n,shape,seed", CASES)
+def test_product_matches_explicit_R(ctx, n, shape, seed, ncols, prec):
+    P, cu, cv = wl.random_psf(shape[0], shape[1], seed)
+    idx = np.arange(n * n)
+    R = op.rmat_entries(P, cu, cv, n, idx, idx)
+    X = np.random.default_rng(seed).standard_normal((n * n, ncols))
+    if prec == "f32":
+        X = X.astype(np.float32).astype(np.float64)
+    for tr in (False, True):
+        Xin = X[:, 0] if ncols == 1 else X
+        Y = _run(ctx, P, cu, cv, n, Xin, tr, prec)
+        _check(Y.reshape(n * n, -1), (R.T if tr else R), X, prec)
+
+
+@pytest.mark.parametrize("n,prec", [(256, "f32"), (512, "f32"), (128, "f64")])
+@pytest.mark.parametrize("ncols", [1, 32])
+def test_product_full_size_sampled_rows(ctx, n, prec, ncols):
+    # the configured workload: rotated Gaussian on the full (2n-1)^2 grid
+    P, cu, cv = wl.gaussian_psf(n)
+    X = np.random.default_rng(n).standard_normal((n * n, ncols))
+    if prec == "f32":
+        X = X.astype(np.float32).astype(np.float64)
+    rows = np.unique(np.r_[0, n * n - 1, n - 1, n * (n - 1),
+                           np.random.default_rng(n + 1).choice(n * n, 24, replace=False)])
+    for tr in (False, True):
+        Y = _run(ctx, P, cu, cv, n, X[:, 0] if ncols == 1 else X, tr, prec).reshape(n * n, -1)
+        Rrows = op.rmat_entries(P.T, cv, cu, n, rows, np.arange(n * n)) if tr else \
+            op.rmat_entries(P, cu, cv, n, rows, np.arange(n * n))
+        _check(Y[rows], Rrows, X, prec)
+        # every row agrees with the (exact-arithmetic-equal) structured product,
+        # componentwise against |R| |X| = R(|P|) |X|
+        Ys = op.rmat_struct_apply(P, cu, cv, n, X, transpose=tr)
+        mag = op.rmat_struct_apply(np.abs(P), cu, cv, n, np.abs(X), transpose=tr)
+        tol = 1e-12 if prec == "f64" else 2e-6
+        assert np.all(np.abs(Y - Ys) <= tol * mag + 0.05 * tol * mag.max())
