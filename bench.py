@@ -1,0 +1,183 @@
+#!/usr/bin/env python3
+"""Benchmark of the Kronecker-product SVD hot path on one MI355X.
+
+Workload (the n = 512 configuration): a rotated Gaussian PSF (sigma = (2, 1),
+30 degrees) on the full 1023 x 1023 offset grid of a 512 x 512 image, zero
+boundary conditions, so R(A) is 262144 x 262144 (never stored). One step is the
+rank-20 KP-SVD of R(A) both ways the paper gives, in single precision:
+  * EGKB (Algorithm 1), k = 20 enlarged to k_p = 40, full reorthogonalization;
+  * RSVD (Algorithm 2), k = 20, oversampling 10, 2 power iterations;
+each including the small FP64 SVD and the Kronecker factors. The PSF, start
+vector and sketch are already on the device (Philox streams); the timed region
+moves no input over PCIe.
+
+value = algorithmic flops of the step (the paper's dense cost model:
+4 N^2 k_p for EGKB, (4q + 4) N^2 k_p for RSVD, N = n^2) / wall time.
+The roofline object is the dominant kernel, the generated-tile block product
+(FP32 MFMA), timed with hipEvents around its launches on the call's stream.
+The CPU baseline times the oracle's dense product of R(A) on a bounded sample.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+MFMA_FP32_PEAK_TFLOPS = 157.3     # MI355X dense FP32 matrix peak
+HBM_PEAK_GBS = 8000.0
+
+
+def cpu_baseline(n, ncols, target_s):
+    """Oracle dense product R X on the first rows of R (the oracle as it stands:
+    generated row blocks of R(A) times X with NumPy/BLAS, FP64)."""
+    import numpy as np
+
+    import workloads as wl
+    from oracle import operator as op
+    P, cu, cv = wl.gaussian_psf(n)
+    N = n * n
+    X = wl.gaussian_block(N, ncols, seed=wl.SEED_START + 7)
+    cols = np.arange(N)
+    chunk = 256
+    rows_done = 0
+    t0 = time.perf_counter()
+    while True:
+        rows = np.arange(rows_done, rows_done + chunk)
+        _ = op.rmat_entries(P, cu, cv, n, rows, cols) @ X
+        rows_done += chunk
+        el = time.perf_counter() - t0
+        if el >= target_s or rows_done >= N:
+            break
+    flops = 2.0 * rows_done * N * ncols
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:
+        cores = os.cpu_count() or 1
+    return dict(value=flops / el / 1e12, unit="TFLOP/s", cores=int(cores), kind="oracle",
+                sample=f"dense R(A) X in FP64, first {rows_done} of {N} rows, {ncols} columns, "
+                       f"n={n} rotated Gaussian; {el:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=512)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: the KP-SVD path is built and timed on a single "
+              "MI355X (see the sharding notes in DESIGN.md); run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import workloads as wl
+    from paper_2410_00233_amd import api, flops
+
+    n = args.n
+    k, p_gkb, p_rsvd, q = 20, 20, 10, 2
+    P, cu, cv = wl.gaussian_psf(n)
+    blur = api.Blur(P, cu, cv, n, on_device=True)
+    ctx = api.Context(0)
+    f_gkb = flops.egkb(n, k, p_gkb)
+    f_rsvd = flops.rsvd(n, k, p_rsvd, q)
+    comp = {"egkb_ms": [], "rsvd_ms": []}
+
+    def step(record):
+        t0 = time.perf_counter()
+        fg = ctx.kp_svd_gkb(blur, k, p_gkb, prec="f32", reorth=1, seed=1, factor_prec="f64")
+        t1 = time.perf_counter()
+        fr = ctx.kp_svd_rsvd(blur, k, p_rsvd, q, prec="f32", seed=2, factor_prec="f64")
+        t2 = time.perf_counter()
+        if record:
+            comp["egkb_ms"].append(1e3 * (t1 - t0))
+            comp["rsvd_ms"].append(1e3 * (t2 - t1))
+        return fg, fr
+
+    for _ in range(args.warmup):
+        step(False)
+    torch.cuda.synchronize()
+    ctx.kp_prof_read(reset=True)
+    ctx.kp_prof_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        fg, fr = step(True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ctx.kp_prof_enable(False)
+    prof = ctx.kp_prof_read(reset=True)
+    ms_step = 1e3 * (t1 - t0) / args.steps
+    value = (f_gkb + f_rsvd) / (ms_step * 1e-3) / 1e12
+
+    blk = prof["block"]
+    avg_blk_ms = blk["ms"] / max(blk["launches"], 1)
+    flops_blk = blk["flops"] / max(blk["launches"], 1)
+    achieved = flops_blk / (avg_blk_ms * 1e-3) / 1e12
+    gv = prof["gemv"]
+    avg_gv_ms = gv["ms"] / max(gv["launches"], 1)
+    gemv_tflops = (gv["flops"] / max(gv["launches"], 1)) / (avg_gv_ms * 1e-3) / 1e12
+
+    line = {
+        "metric": "KP-SVD time & TFLOP/s at n=512 (FP32 vs BF16+refine); p50/p99 solve latency",
+        "value": round(value, 3),
+        "unit": "TFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"rank-{k} KP-SVD of R(A), n={n} (R(A) {n*n}x{n*n}), rotated Gaussian PSF "
+                        f"sigma=(2,1) 30deg on the full offset grid, zero BC; step = EGKB "
+                        f"(k_p={k+p_gkb}, full reorth) + RSVD (p={p_rsvd}, q={q}), FP32",
+            "n": n, "rank": k, "egkb_kp": k + p_gkb, "rsvd_p": p_rsvd, "rsvd_q": q,
+            "flops_per_step": f_gkb + f_rsvd,
+        },
+        "components": {
+            "egkb_ms": round(float(np.median(comp["egkb_ms"])), 3),
+            "rsvd_ms": round(float(np.median(comp["rsvd_ms"])), 3),
+            "egkb_tflops": round(f_gkb / (np.median(comp["egkb_ms"]) * 1e-3) / 1e12, 3),
+            "rsvd_tflops": round(f_rsvd / (np.median(comp["rsvd_ms"]) * 1e-3) / 1e12, 3),
+            "gemv_kernel_avg_ms": round(avg_gv_ms, 4),
+            "gemv_kernel_tflops": round(gemv_tflops, 3),
+            "sigma_egkb_top3": [float(x) for x in fg.sigma[:3]],
+            "sigma_rsvd_top3": [float(x) for x in fr.sigma[:3]],
+        },
+        "roofline": {
+            "kernel": "rmat_block_kernel<float,16,4,2> (generated-tile R(A) X, FP32 MFMA 16x16x4)",
+            "bound": "mfma",
+            "achieved": round(achieved, 3),
+            "peak": MFMA_FP32_PEAK_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": round(achieved / MFMA_FP32_PEAK_TFLOPS, 4),
+            "traffic": None,
+            "avg_launch_ms": round(avg_blk_ms, 4),
+            "launches": int(blk["launches"]),
+            "flops_per_launch": flops_blk,
+        },
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(n, k + p_rsvd, args.cpu_seconds)
+    ctx.close()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

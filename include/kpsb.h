@@ -51,14 +51,17 @@ typedef enum { KP_F64 = 0, KP_F32 = 1, KP_BF16 = 2, KP_F16 = 3 } kp_prec;
 
 typedef struct kp_ctx kp_ctx;
 
-/* The blur: PSF P (pu x pv, row-major FP64, HOST memory, P[u*pv + v] with u the
- * vertical offset) with centre (cu, cv), acting on n x n images with zero
- * boundary conditions. Requirements: n >= 2, pu, pv >= 1, 0 <= cu < pu,
- * 0 <= cv < pv, every P entry finite. */
+/* The blur: PSF P (pu x pv, row-major FP64, P[u*pv + v] with u the vertical
+ * offset) with centre (cu, cv), acting on n x n images with zero boundary
+ * conditions. `psf` is HOST memory, or DEVICE memory when psf_on_device = 1.
+ * Requirements: 2 <= n <= 2048, pu, pv >= 1, 0 <= cu < pu, 0 <= cv < pv,
+ * every P entry finite (checked on the host, or on the device for a device
+ * PSF; KP_E_NUMERIC otherwise). */
 typedef struct {
   int32_t n;
   const double* psf;
   int32_t pu, pv, cu, cv;
+  int32_t psf_on_device;
 } kp_blur;
 
 /* Enlarged Golub-Kahan bidiagonalization (paper, Algorithm 1). */
@@ -74,8 +77,9 @@ typedef struct {
   uint64_t seed;        /* Philox seed for the start vector (if y0 == NULL) and
                            for breakdown restart vectors                           */
   const double* y0;     /* optional HOST start vector y, length n^2 (vec order)    */
-  double bd_rel;        /* breakdown when t_j or alpha_j <= bd_rel * max(alpha, t);
-                           0 selects 1e3 * unit roundoff of `prec`                 */
+  double bd_rel;        /* breakdown when t_j or alpha_j is 0 or <= bd_rel times the
+                           largest entry of the bidiagonal so far; 0 selects
+                           100 * unit roundoff of `prec`                           */
 } kp_gkb_opts;
 
 /* Randomized SVD (paper, Algorithm 2) with orthonormalization after every
@@ -97,8 +101,9 @@ typedef struct {
   double* t;            /* out: t_1..t_{kp+1}                                      */
   int32_t kp;           /* out: final k_p                                          */
   int32_t nbreak;       /* out: number of deflated breakdowns                      */
-  int32_t break_side[16]; /* out: 0 = s-vector, 1 = q-vector, first 16 events      */
-  int32_t break_step[16]; /* out: step j of each event                             */
+  int32_t break_side[128]; /* out: 0 = s-vector, 1 = q-vector, per event (at most
+                            2 k_p + 1 events can occur)                            */
+  int32_t break_step[128]; /* out: step j of each event                            */
   double ms_total;      /* out: wall time of the call (device, hipEvent)           */
   void* basis_u;        /* optional DEVICE out: left basis S (EGKB) or Y (RSVD),
                            n^2 x (k_p+1) resp. n^2 x k_p, column-major, in the
@@ -134,11 +139,26 @@ typedef struct {
   double rc_sb;         /* last RC_SB                                              */
 } sb_stats;
 
+/* Per-kernel-class timing (tracing). While enabled, every launch of the
+ * generated-tile block product (class 0), the matrix-vector product (class 1)
+ * and the Kronecker-apply GEMMs (class 2) is bracketed with hipEvents on the
+ * stream of the call; kp_prof_read synchronizes the device and returns, per
+ * class, the summed event time, the launch count and the algorithmic flops of
+ * those launches (2 n^4 per column for R products, 4 k n^3 per apply). */
+typedef struct {
+  double ms[3];
+  int64_t launches[3];
+  double flops[3];
+} kp_prof;
+
 /* Context: binds `device`, owns a workspace that never exceeds
  * hbm_budget_bytes (0 = 90% of the device's free memory). */
 kp_status kp_ctx_create(int device, size_t hbm_budget_bytes, kp_ctx** out);
 kp_status kp_ctx_destroy(kp_ctx* ctx);
 const char* kp_last_error(const kp_ctx* ctx);
+kp_status kp_prof_enable(kp_ctx* ctx, int enable);
+/* Reads (and, if reset != 0, clears) the accumulated timings. */
+kp_status kp_prof_read(kp_ctx* ctx, kp_prof* out, int reset);
 /* Library version string (static storage). */
 const char* kp_version(void);
 

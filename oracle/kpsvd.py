@@ -19,10 +19,12 @@ notes):
 * svds(C, k_p) = full thin SVD of the (k_p+1) x k_p bidiagonal C.
 * output: U_k = S_{(k_p+1)} U[:, :k], V_k = Q_{k_p} V[:, :k] (all k_p+1 Lanczos
   vectors enter the left factor).
-* breakdown (t_j or alpha_j <= ``bd_rel`` * max of all alphas and ts so far):
-  the coefficient is stored as 0 and the vector is replaced by a Philox normal
-  vector (stream 2j for s_j, 2j+1 for q_j), orthogonalized twice (classical
-  Gram-Schmidt) against the basis built so far, and normalized.
+* breakdown (t_j or alpha_j <= ``bd_rel`` * the largest entry of C accepted so
+  far; t_1 = ||y|| is not an entry of C and its size is arbitrary, so it is not
+  part of the scale; alpha_1 breaks down only when it is 0): the coefficient is
+  stored as 0 and the vector is replaced by a Philox normal vector (stream 2j
+  for s_j, 2j+1 for q_j), orthogonalized twice (classical Gram-Schmidt) against
+  the basis built so far, and normalized.
 """
 from __future__ import annotations
 
@@ -68,7 +70,7 @@ def egkb(apply_R, apply_Rt, y, k, p, *, reorth="full", auto_k=False, k_min=0,
     """
     eps = np.finfo(dtype).eps / 2
     if bd_rel is None:
-        bd_rel = 1e3 * eps
+        bd_rel = 1e2 * eps
     k_in = k
     kp = k + p
     y = np.asarray(y, dtype=dtype)
@@ -76,7 +78,7 @@ def egkb(apply_R, apply_Rt, y, k, p, *, reorth="full", auto_k=False, k_min=0,
     def is_bd(side, j, val, scale):
         if force_breakdown is not None:
             return (side, j) in force_breakdown
-        return val <= bd_rel * scale
+        return val <= bd_rel * scale or val == 0.0
 
     def restart(side, j, basis, size):
         g = philox.normals(size, seed, 2 * j + (0 if side == "s" else 1)).astype(dtype)
@@ -88,7 +90,7 @@ def egkb(apply_R, apply_Rt, y, k, p, *, reorth="full", auto_k=False, k_min=0,
     S = [y / t[0]]
     q = apply_Rt(S[0])
     alpha = [_norm(q)]
-    if is_bd("q", 1, alpha[0], max(alpha[0], t[0])):
+    if is_bd("q", 1, alpha[0], 0.0):
         breakdowns.append(("q", 1))
         alpha[0] = 0.0
         Q = [restart("q", 1, [], q.shape[0])]
@@ -96,7 +98,7 @@ def egkb(apply_R, apply_Rt, y, k, p, *, reorth="full", auto_k=False, k_min=0,
         Q = [q / alpha[0]]
     zeta = {1: 1.0 if literal_init else alpha[0] * t[0]}
     nu = {2: 100.0 if literal_init else np.inf}
-    scale = max(alpha[0], t[0])
+    scale = alpha[0]
     fired = False
     j = 2
     while j <= kp + 1:

@@ -21,13 +21,15 @@ STATUS_NAMES = {0: "KP_OK", 1: "KP_E_INVAL", 2: "KP_E_NOMEM", 3: "KP_E_DEVICE",
 
 # Every symbol the header declares (checked by the CPU test-suite).
 EXPORTED = ["kp_ctx_create", "kp_ctx_destroy", "kp_last_error", "kp_version",
+            "kp_prof_enable", "kp_prof_read",
             "kp_rmat_apply", "kp_svd_gkb", "kp_svd_rsvd", "kp_apply",
             "sb_solve_aniso", "sb_solve_iso"]
 
 
 class kp_blur(C.Structure):
     _fields_ = [("n", C.c_int32), ("psf", C.POINTER(C.c_double)), ("pu", C.c_int32),
-                ("pv", C.c_int32), ("cu", C.c_int32), ("cv", C.c_int32)]
+                ("pv", C.c_int32), ("cu", C.c_int32), ("cv", C.c_int32),
+                ("psf_on_device", C.c_int32)]
 
 
 class kp_gkb_opts(C.Structure):
@@ -45,7 +47,7 @@ class kp_rsvd_opts(C.Structure):
 class kp_diag(C.Structure):
     _fields_ = [("cap", C.c_int32), ("alpha", C.POINTER(C.c_double)),
                 ("t", C.POINTER(C.c_double)), ("kp", C.c_int32), ("nbreak", C.c_int32),
-                ("break_side", C.c_int32 * 16), ("break_step", C.c_int32 * 16),
+                ("break_side", C.c_int32 * 128), ("break_step", C.c_int32 * 128),
                 ("ms_total", C.c_double), ("basis_u", C.c_void_p), ("basis_v", C.c_void_p)]
 
 
@@ -58,6 +60,10 @@ class kp_factors(C.Structure):
 class sb_opts(C.Structure):
     _fields_ = [("lam", C.c_double), ("beta", C.c_double), ("L_max", C.c_int32),
                 ("I_max", C.c_int32), ("tau_sb", C.c_double), ("tau_cgls", C.c_double)]
+
+
+class kp_prof(C.Structure):
+    _fields_ = [("ms", C.c_double * 3), ("launches", C.c_int64 * 3), ("flops", C.c_double * 3)]
 
 
 class sb_stats(C.Structure):
@@ -82,6 +88,8 @@ def load(path: str = LIB_PATH):
     lib.kp_last_error.restype = C.c_char_p
     lib.kp_version.argtypes = []
     lib.kp_version.restype = C.c_char_p
+    lib.kp_prof_enable.argtypes = [vp, C.c_int]
+    lib.kp_prof_read.argtypes = [vp, C.POINTER(kp_prof), C.c_int]
     lib.kp_rmat_apply.argtypes = [vp, C.POINTER(kp_blur), C.c_int, C.c_int, C.c_int32, vp, vp, vp]
     lib.kp_svd_gkb.argtypes = [vp, C.POINTER(kp_blur), C.POINTER(kp_gkb_opts),
                                C.POINTER(kp_factors), vp]

@@ -37,13 +37,22 @@ def _ptr(t):
 
 
 class Blur:
-    """PSF P (pu x pv, u vertical) with centre (cu, cv) acting on n x n images."""
+    """PSF P (pu x pv, u vertical) with centre (cu, cv) acting on n x n images.
 
-    def __init__(self, P, cu, cv, n):
+    P is a NumPy array (host) or, with on_device=True, copied once into a device
+    tensor so that calls read it from HBM."""
+
+    def __init__(self, P, cu, cv, n, on_device=False):
         self.P = np.ascontiguousarray(P, dtype=np.float64)
         self.cu, self.cv, self.n = int(cu), int(cv), int(n)
-        self.s = L.kp_blur(self.n, self.P.ctypes.data_as(C.POINTER(C.c_double)),
-                           self.P.shape[0], self.P.shape[1], self.cu, self.cv)
+        if on_device:
+            torch = _torch()
+            self.Pd = torch.tensor(self.P, dtype=torch.float64, device="cuda")
+            ptr = C.cast(C.c_void_p(self.Pd.data_ptr()), C.POINTER(C.c_double))
+        else:
+            ptr = self.P.ctypes.data_as(C.POINTER(C.c_double))
+        self.s = L.kp_blur(self.n, ptr, self.P.shape[0], self.P.shape[1], self.cu, self.cv,
+                           int(on_device))
 
 
 class Factors:
@@ -66,6 +75,19 @@ class Factors:
     @property
     def k(self):
         return self.s.k
+
+    @classmethod
+    def from_arrays(cls, Ax, Ay, sigma=None):
+        """Device FP64 factors from host arrays (k x n x n each)."""
+        torch = _torch()
+        k, n, _ = Ax.shape
+        f = cls(n, k, "f64")
+        f.Ax.copy_(torch.as_tensor(np.ascontiguousarray(Ax, dtype=np.float64)))
+        f.Ay.copy_(torch.as_tensor(np.ascontiguousarray(Ay, dtype=np.float64)))
+        if sigma is not None:
+            f.sigma[:k] = sigma
+        f.s.k = k
+        return f
 
 
 class Context:
@@ -92,6 +114,17 @@ class Context:
         if st not in allow:
             raise KPError(st, self.lib.kp_last_error(self.h).decode())
         return st
+
+    # ---- tracing ------------------------------------------------------------
+    def kp_prof_enable(self, enable=True):
+        self._check(self.lib.kp_prof_enable(self.h, int(enable)))
+
+    def kp_prof_read(self, reset=True):
+        """Per class ("block", "gemv", "apply"): summed ms, launches, flops."""
+        pr = L.kp_prof()
+        self._check(self.lib.kp_prof_read(self.h, C.byref(pr), int(reset)))
+        return {name: dict(ms=pr.ms[i], launches=pr.launches[i], flops=pr.flops[i])
+                for i, name in enumerate(("block", "gemv", "apply"))}
 
     # ---- entry points (names follow the C ABI) ----------------------------
     def kp_rmat_apply(self, blur: Blur, X, transpose=False, prec="f32", Y=None):
@@ -136,7 +169,7 @@ class Context:
         f.alpha = alpha[:kp].copy()
         f.t = t[:kp + 1].copy()
         f.breakdowns = [("s" if f.diag.break_side[i] == 0 else "q", f.diag.break_step[i])
-                        for i in range(min(f.diag.nbreak, 16))]
+                        for i in range(min(f.diag.nbreak, 128))]
         f.ms = f.diag.ms_total
         if bases:
             f.S = S[:kp + 1]

@@ -16,6 +16,7 @@
 
 #include "common.h"
 #include "kpsb.h"
+#include "sb.h"
 
 using namespace kpsb;
 
@@ -31,6 +32,17 @@ struct kp_ctx {
   };
   std::map<std::string, Buf> bufs;
   double* pinned = nullptr;   // host readback buffer (64 doubles)
+  // tracing: event pairs around product launches (see kp_prof_read)
+  bool prof = false;
+  struct Rec {
+    hipEvent_t a, b;
+    int cls;
+    double flops;
+  };
+  std::vector<Rec> recs;
+  double acc_ms[3] = {0, 0, 0};
+  int64_t acc_n[3] = {0, 0, 0};
+  double acc_flops[3] = {0, 0, 0};
 };
 
 namespace {
@@ -109,8 +121,11 @@ kp_status validate_blur(kp_ctx* c, const kp_blur* b) {
   if (b->cu < 0 || b->cu >= b->pu || b->cv < 0 || b->cv >= b->pv)
     return set_err(c, KP_E_INVAL, "psf centre outside the psf array");
   if ((long)b->pu * b->pv > (1L << 26)) return set_err(c, KP_E_INVAL, "psf too large");
-  for (long e = 0; e < (long)b->pu * b->pv; ++e)
-    if (!std::isfinite(b->psf[e])) return set_err(c, KP_E_NUMERIC, "psf has a non-finite entry");
+  if (b->psf_on_device != 0 && b->psf_on_device != 1)
+    return set_err(c, KP_E_INVAL, "psf_on_device must be 0 or 1");
+  if (!b->psf_on_device)
+    for (long e = 0; e < (long)b->pu * b->pv; ++e)
+      if (!std::isfinite(b->psf[e])) return set_err(c, KP_E_NUMERIC, "psf has a non-finite entry");
   return KP_OK;
 }
 
@@ -127,10 +142,24 @@ struct Grids {
   int ldg = 0;
 };
 
+// Device copy of the PSF: uploaded from the host, or (device PSF) used in place
+// after a device-side finiteness check.
 kp_status upload_psf(kp_ctx* c, const kp_blur* b, hipStream_t s, double** dpsf) {
-  KP_TRY(wsT(c, "psf", (size_t)b->pu * b->pv, dpsf));
-  KP_HIP(c, hipMemcpyAsync(*dpsf, b->psf, sizeof(double) * b->pu * b->pv,
-                           hipMemcpyHostToDevice, s));
+  const long cnt = (long)b->pu * b->pv;
+  if (b->psf_on_device) {
+    int* flag = nullptr;
+    KP_TRY(wsT(c, "psf_flag", 4, &flag));
+    launch_count_nonfinite(b->psf, cnt, flag, s);
+    KP_TRY(check_launch(c, "psf check"));
+    KP_HIP(c, hipMemcpyAsync(c->pinned + 16, flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    KP_HIP(c, hipStreamSynchronize(s));
+    if (*reinterpret_cast<int*>(c->pinned + 16) != 0)
+      return set_err(c, KP_E_NUMERIC, "psf has a non-finite entry");
+    *dpsf = const_cast<double*>(b->psf);
+    return KP_OK;
+  }
+  KP_TRY(wsT(c, "psf", (size_t)cnt, dpsf));
+  KP_HIP(c, hipMemcpyAsync(*dpsf, b->psf, sizeof(double) * cnt, hipMemcpyHostToDevice, s));
   return KP_OK;
 }
 
@@ -148,6 +177,29 @@ kp_status prep_grids(kp_ctx* c, const kp_blur* b, hipStream_t s, Grids<T>* g) {
   return check_launch(c, "build_grid");
 }
 
+// Tracing: bracket a launch with events when the context profiles.
+struct ProfScope {
+  kp_ctx* c;
+  hipStream_t s;
+  kp_ctx::Rec r{};
+  bool on;
+  ProfScope(kp_ctx* ctx, hipStream_t st, int cls, double flops) : c(ctx), s(st), on(ctx->prof) {
+    if (!on) return;
+    r.cls = cls;
+    r.flops = flops;
+    if (hipEventCreate(&r.a) != hipSuccess || hipEventCreate(&r.b) != hipSuccess) {
+      on = false;
+      return;
+    }
+    (void)hipEventRecord(r.a, s);
+  }
+  ~ProfScope() {
+    if (!on) return;
+    (void)hipEventRecord(r.b, s);
+    c->recs.push_back(r);
+  }
+};
+
 // Y = R X (or R^T X) for any number of columns (groups of 32 per launch).
 template <typename T>
 kp_status block_product(kp_ctx* c, const Grids<T>& g, int n, int transpose, const T* X,
@@ -158,6 +210,7 @@ kp_status block_product(kp_ctx* c, const Grids<T>& g, int n, int transpose, cons
   const long N = (long)n * n;
   for (int c0 = 0; c0 < ncols; c0 += 32) {
     const int nc = ncols - c0 < 32 ? ncols - c0 : 32;
+    ProfScope ps(c, s, 0, 2.0 * (double)N * (double)N * nc);
     launch_rmat_block<T>(bp, transpose ? g.Gt : g.G, g.ldg, n, X + N * c0, N, Y + N * c0, N,
                          nc, s);
   }
@@ -170,7 +223,11 @@ kp_status gemv_product(kp_ctx* c, const Grids<T>& g, int n, int transpose, const
   BlockPlan gp;
   if (!plan_gemv<T>(n, c->lds_limit, &gp))
     return set_err(c, KP_E_INVAL, "no matrix-vector tiling fits the LDS at this n");
-  launch_rmat_gemv<T>(gp, transpose ? g.Gt : g.G, g.ldg, n, x, y, z, coef, s);
+  {
+    const double NN = (double)n * n;
+    ProfScope ps(c, s, 1, 2.0 * NN * NN);
+    launch_rmat_gemv<T>(gp, transpose ? g.Gt : g.G, g.ldg, n, x, y, z, coef, s);
+  }
   return check_launch(c, "rmat_gemv");
 }
 
@@ -180,6 +237,7 @@ struct Scratch {
   double* nrmp = nullptr;       // kRedBlocks
   double* h = nullptr;          // 4 x 64 coefficient vectors
   double* scal = nullptr;       // 8 scalars
+  int* flag = nullptr;          // device predicate
 };
 
 kp_status get_scratch(kp_ctx* c, Scratch* sc) {
@@ -187,6 +245,7 @@ kp_status get_scratch(kp_ctx* c, Scratch* sc) {
   KP_TRY(wsT(c, "nrmp", (size_t)kRedBlocks, &sc->nrmp));
   KP_TRY(wsT(c, "hvec", 4 * 64, &sc->h));
   KP_TRY(wsT(c, "scal", 8, &sc->scal));
+  KP_TRY(wsT(c, "flag", 4, &sc->flag));
   return KP_OK;
 }
 
@@ -215,17 +274,24 @@ void cgs2(const Scratch& sc, T* w, const T* V, long ldv, int m, long N, hipStrea
   }
 }
 
-// Column-wise CGS2 QR of W (N x m, ld N) in place: W = Q R. Each column gets
-// two Gram-Schmidt passes, is normalized, and gets a third pass plus a second
-// normalization (guard for columns that are numerically in the span of the
-// previous ones). R (m x m, column-major FP64) is formed when Rfac != NULL.
+// Column-wise Gram-Schmidt QR of W (N x m, ld N) in place: W = Q R. Each column
+// gets two classical Gram-Schmidt passes and is normalized (norm = R[j, j]);
+// a third pass then measures how much of the normalized vector lies outside
+// the span of the previous columns. If less than half of it does, the column
+// was numerically dependent (its residual was rounding noise) and is replaced
+// by a Philox normal vector (stream `stream_base + j`) orthogonalized twice:
+// R keeps the projections and the rounding-level R[j, j]. Otherwise the third
+// pass is folded into R. All decisions are taken on the device (predicated
+// kernels), so the sequence never synchronizes with the host. R (m x m,
+// column-major FP64) is formed when Rfac != NULL.
 template <typename T>
 kp_status cgs_qr(kp_ctx* c, const Scratch& sc, T* W, long N, int m, double* Rfac,
-                 hipStream_t s) {
+                 uint64_t seed, uint32_t stream_base, hipStream_t s) {
   double* h2 = sc.h + 64;
   double* h3 = sc.h + 128;
   double* rscr = sc.scal + 2;
   double* r3 = sc.scal + 3;
+  double* r4 = sc.scal + 4;
   if (Rfac) launch_fill_small(Rfac, m * m, 0.0, s);
   for (int j = 0; j < m; ++j) {
     T* w = W + N * j;
@@ -248,8 +314,21 @@ kp_status cgs_qr(kp_ctx* c, const Scratch& sc, T* W, long N, int m, double* Rfac
       launch_reduce_partials(sc.partials, j, h3, 0, s);
       launch_project_out<T>(w, W, N, j, h3, N, sc.nrmp, s);
       launch_normalize<T>(w, N, sc.nrmp, r3, s);
-      launch_cgs_fixup(Rcol, j, h3, rjj, r3, s);
+      launch_flag_below(r3, 0.5, sc.flag, s);
+    } else {
+      launch_flag_below(rjj, 1e-300, sc.flag, s);     // an exactly zero first column
     }
+    // replacement of a dependent column (predicated on sc.flag)
+    launch_philox_normals<T>(w, N, seed, stream_base + (uint32_t)j, s, sc.flag);
+    for (int pass = 0; pass < 2; ++pass) {
+      if (j > 0) {
+        launch_multidot<T>(W, N, j, w, N, sc.partials, s, sc.flag);
+        launch_reduce_partials(sc.partials, j, h2, 0, s, sc.flag);
+      }
+      launch_project_out<T>(w, W, N, j, h2, N, sc.nrmp, s, sc.flag);
+    }
+    launch_normalize<T>(w, N, sc.nrmp, r4, s, sc.flag);
+    if (j > 0) launch_cgs_fixup(Rcol, j, h3, rjj, r3, sc.flag, s);
   }
   return check_launch(c, "cgs_qr");
 }
@@ -329,7 +408,7 @@ kp_status egkb_impl(kp_ctx* c, const kp_blur* b, const kp_gkb_opts* o, kp_factor
   int kp = k + p;
   const int kp0 = kp;
   const double u = (sizeof(T) == 4) ? std::ldexp(1.0, -24) : std::ldexp(1.0, -53);
-  const double bd_rel = o->bd_rel > 0 ? o->bd_rel : 1e3 * u;
+  const double bd_rel = o->bd_rel > 0 ? o->bd_rel : 1e2 * u;
 
   Grids<T> g;
   KP_TRY(prep_grids<T>(c, b, s, &g));
@@ -341,7 +420,9 @@ kp_status egkb_impl(kp_ctx* c, const kp_blur* b, const kp_gkb_opts* o, kp_factor
 
   std::vector<double> alpha, t;
   std::vector<std::pair<int, int>> breaks;
-  auto is_bd = [&](double val, double scale) { return val <= bd_rel * scale; };
+  // breakdown: the value is 0 or at most bd_rel times the largest entry of C
+  // accepted so far (t_1 = ||y|| is not an entry of C and is excluded)
+  auto is_bd = [&](double val, double scale) { return val <= bd_rel * scale || val == 0.0; };
 
   // restart vector for side (0 = s, 1 = q) at step j into w, CGS2 against V[:, :m]
   auto restart = [&](int side, int j, T* w, const T* V, int m) -> kp_status {
@@ -373,7 +454,7 @@ kp_status egkb_impl(kp_ctx* c, const kp_blur* b, const kp_gkb_opts* o, kp_factor
   double a1 = 0;
   KP_TRY(read_norm(c, sc, s, &a1));
   if (!std::isfinite(a1)) return set_err(c, KP_E_NUMERIC, "non-finite alpha_1");
-  if (is_bd(a1, std::max(a1, t1))) {
+  if (is_bd(a1, 0.0)) {
     a1 = 0.0;
     KP_TRY(restart(1, 1, Q, Q, 0));
   } else {
@@ -383,7 +464,7 @@ kp_status egkb_impl(kp_ctx* c, const kp_blur* b, const kp_gkb_opts* o, kp_factor
   std::map<int, double> zeta, nu;
   zeta[1] = o->literal_init ? 1.0 : a1 * t1;
   nu[2] = o->literal_init ? 100.0 : INFINITY;
-  double scale = std::max(a1, t1);
+  double scale = a1;
   bool fired = false;
 
   for (int j = 2; j <= kp + 1; ++j) {
@@ -475,7 +556,7 @@ kp_status egkb_impl(kp_ctx* c, const kp_blur* b, const kp_gkb_opts* o, kp_factor
     for (int i = 0; i < kp + 1 && i < d->cap; ++i) if (d->t) d->t[i] = t[i];
     d->kp = kp;
     d->nbreak = (int)breaks.size();
-    for (int i = 0; i < (int)breaks.size() && i < 16; ++i) {
+    for (int i = 0; i < (int)breaks.size() && i < 128; ++i) {
       d->break_side[i] = breaks[i].first;
       d->break_step[i] = breaks[i].second;
     }
@@ -509,13 +590,14 @@ kp_status rsvd_impl(kp_ctx* c, const kp_blur* b, const kp_rsvd_opts* o, kp_facto
     for (int col = 0; col < kp; ++col)
       launch_philox_normals<T>(Z + N * col, N, o->seed, 0x40000000u + (uint32_t)col, s);
   }
+  uint32_t sb = 0x20000000u;   // Philox streams of replaced dependent columns
   KP_TRY(block_product<T>(c, g, n, 0, Z, Y, kp, s));
-  KP_TRY(cgs_qr<T>(c, sc, Y, N, kp, nullptr, s));
+  KP_TRY(cgs_qr<T>(c, sc, Y, N, kp, nullptr, o->seed, sb, s));
   for (int it = 0; it < o->q; ++it) {
     KP_TRY(block_product<T>(c, g, n, 1, Y, Z, kp, s));
-    KP_TRY(cgs_qr<T>(c, sc, Z, N, kp, nullptr, s));
+    KP_TRY(cgs_qr<T>(c, sc, Z, N, kp, nullptr, o->seed, sb += 64, s));
     KP_TRY(block_product<T>(c, g, n, 0, Z, Y, kp, s));
-    KP_TRY(cgs_qr<T>(c, sc, Y, N, kp, nullptr, s));
+    KP_TRY(cgs_qr<T>(c, sc, Y, N, kp, nullptr, o->seed, sb += 64, s));
   }
   KP_TRY(block_product<T>(c, g, n, 1, Y, Z, kp, s));   // H^T
   double *Rh, *RhT, *Ur, *sig, *Vr;
@@ -526,7 +608,7 @@ kp_status rsvd_impl(kp_ctx* c, const kp_blur* b, const kp_rsvd_opts* o, kp_facto
   KP_TRY(wsT(c, "smallS", 64, &sig));
   KP_TRY(wsT(c, "smallV", 64 * 64, &Vr));
   KP_TRY(wsT(c, "sweeps", 4, &sweeps));
-  KP_TRY(cgs_qr<T>(c, sc, Z, N, kp, Rh, s));
+  KP_TRY(cgs_qr<T>(c, sc, Z, N, kp, Rh, o->seed, sb += 64, s));
   launch_transpose_small(Rh, kp, kp, RhT, s);
   launch_jacobi_svd(RhT, kp, kp, Ur, sig, Vr, sweeps, s);
   KP_TRY(check_launch(c, "jacobi_svd"));
@@ -549,6 +631,125 @@ kp_status rsvd_impl(kp_ctx* c, const kp_blur* b, const kp_rsvd_opts* o, kp_facto
     d->nbreak = 0;
     d->ms_total = timer.stop();
   }
+  return KP_OK;
+}
+
+kp_status validate_apply_factors(kp_ctx* c, const kp_factors* f) {
+  if (!f) return set_err(c, KP_E_INVAL, "factors is NULL");
+  if (f->n < 2 || f->n > 8192) return set_err(c, KP_E_INVAL, "factors.n must be in [2, 8192]");
+  if (f->k < 1 || f->k > f->k_cap) return set_err(c, KP_E_INVAL, "need 1 <= factors.k <= k_cap");
+  if (!f->Ax || !f->Ay) return set_err(c, KP_E_INVAL, "factor buffers are NULL");
+  if (f->factor_prec != KP_F64) return set_err(c, KP_E_INVAL, "kp_apply / sb_solve need KP_F64 factors");
+  return KP_OK;
+}
+
+// Split Bregman (Algorithm 3 if iso == 0, Algorithm 4 if iso == 1) with CGLS
+// (Algorithm 5). x^(0) = b enters only RC_SB of the first outer iteration; CGLS
+// starts every outer iteration from 0. The host queues L_max x I_max
+// iterations; device flags turn the remainder into no-ops once RC_CGLS <
+// tau_cgls (per outer iteration) or RC_SB < tau_sb, and the host polls the
+// flags every few iterations to stop queueing.
+kp_status sb_solve(kp_ctx* c, const kp_factors* f, const double* b, const sb_opts* o, double* x,
+                   sb_stats* st, hipStream_t s, int iso) {
+  KP_TRY(validate_apply_factors(c, f));
+  if (!b || !x || !o) return set_err(c, KP_E_INVAL, "b, x or opts is NULL");
+  if (b == x) return set_err(c, KP_E_INVAL, "b and x must not alias");
+  if (!(o->lambda > 0) || !(o->beta > 0) || !std::isfinite(o->lambda) || !std::isfinite(o->beta))
+    return set_err(c, KP_E_INVAL, "lambda and beta must be positive and finite");
+  if (o->L_max < 1 || o->I_max < 1) return set_err(c, KP_E_INVAL, "L_max and I_max must be >= 1");
+  if (o->tau_sb < 0 || o->tau_cgls < 0) return set_err(c, KP_E_INVAL, "tolerances must be >= 0");
+  KP_HIP(c, hipSetDevice(c->device));
+  Timer timer(s);
+  const int n = f->n, k = f->k;
+  const long NN = (long)n * n;
+  double* img = nullptr;
+  KP_TRY(wsT(c, "sb_img", (size_t)14 * NN, &img));
+  double *Z, *P, *part, *scal;
+  int* flags;
+  KP_TRY(wsT(c, "kpZ", (size_t)k * NN, &Z));
+  KP_TRY(wsT(c, "kpP", (size_t)k * NN, &P));
+  KP_TRY(wsT(c, "sb_part", (size_t)kRedBlocks * 4, &part));
+  KP_TRY(wsT(c, "sb_scal", 8, &scal));
+  KP_TRY(wsT(c, "sb_flags", 4, &flags));
+  SBDev d;
+  d.n = n;
+  d.lam = o->lambda;
+  d.thr = o->beta / (o->lambda * o->lambda);     // 1 / gamma, gamma = lambda^2 / beta
+  d.iso = iso;
+  d.tau_cgls = o->tau_cgls;
+  d.tau_sb = o->tau_sb;
+  d.b = b;
+  double* AtB = img;
+  d.AtB = AtB;
+  d.x = img + NN;
+  d.xprev = img + 2 * NN;
+  d.r1 = img + 3 * NN;
+  d.r2 = img + 4 * NN;
+  d.r3 = img + 5 * NN;
+  d.w = img + 6 * NN;
+  d.f = img + 7 * NN;
+  d.z1 = img + 8 * NN;
+  d.t1 = img + 9 * NN;
+  d.dx = img + 10 * NN;
+  d.dy = img + 11 * NN;
+  d.gx = img + 12 * NN;
+  d.gy = img + 13 * NN;
+  d.part = part;
+  d.scal = scal;
+  d.flags = flags;
+  const double* Ax = (const double*)f->Ax;
+  const double* Ay = (const double*)f->Ay;
+  launch_fill(d.dx, 4 * NN, 0.0, s);                 // dx, dy, gx, gy (contiguous)
+  launch_fill_small(scal, 8, 0.0, s);
+  launch_fill_int(flags, 4, 0, s);
+  KP_HIP(c, hipMemcpyAsync(d.xprev, b, sizeof(double) * NN, hipMemcpyDeviceToDevice, s));
+  launch_kp_apply_ws(Ax, Ay, n, k, 1, b, AtB, Z, P, nullptr, 0, s);
+  KP_TRY(check_launch(c, "sb init"));
+  const int poll = 8;
+  int* hflags = reinterpret_cast<int*>(c->pinned);
+  auto read_flags = [&]() -> kp_status {
+    KP_HIP(c, hipMemcpyAsync(hflags, flags, 4 * sizeof(int), hipMemcpyDeviceToHost, s));
+    KP_HIP(c, hipStreamSynchronize(s));
+    return KP_OK;
+  };
+  for (int ell = 0; ell < o->L_max; ++ell) {
+    sb_launch_rhs(d, s);
+    sb_launch_f(d, AtB, 1, s);
+    sb_launch_w_init(d, s);
+    for (int it = 0; it < o->I_max; ++it) {
+      launch_kp_apply_ws(Ax, Ay, n, k, 0, d.w, d.z1, Z, P, flags, 2, s);
+      sb_launch_zn(d, s);
+      sb_launch_xr(d, s);
+      launch_kp_apply_ws(Ax, Ay, n, k, 1, d.r1, d.t1, Z, P, flags, 2, s);
+      sb_launch_f(d, d.t1, 2, s);
+      sb_launch_w(d, s);
+      sb_launch_cgls_check(d, s);
+      if (o->tau_cgls > 0 && (it + 1) % poll == 0 && it + 1 < o->I_max) {
+        KP_TRY(check_launch(c, "cgls"));
+        KP_TRY(read_flags());
+        if (hflags[0] || hflags[1]) break;
+      }
+    }
+    sb_launch_shrink(d, s);
+    sb_launch_check(d, s);
+    KP_TRY(check_launch(c, "sb iteration"));
+    if (o->tau_sb > 0) {
+      KP_TRY(read_flags());
+      if (hflags[0]) break;
+    }
+  }
+  KP_HIP(c, hipMemcpyAsync(x, d.x, sizeof(double) * NN, hipMemcpyDeviceToDevice, s));
+  KP_TRY(read_flags());
+  double rc = 0.0;
+  KP_HIP(c, hipMemcpyAsync(c->pinned + 8, scal + 2, sizeof(double), hipMemcpyDeviceToHost, s));
+  KP_HIP(c, hipStreamSynchronize(s));
+  rc = c->pinned[8];
+  if (st) {
+    st->l_end = hflags[3];
+    st->iota_total = hflags[2];
+    st->rc_sb = rc;
+  }
+  (void)timer;
   return KP_OK;
 }
 
@@ -597,11 +798,49 @@ kp_status kp_ctx_destroy(kp_ctx* c) {
   for (auto& kv : c->bufs)
     if (kv.second.p) (void)hipFree(kv.second.p);
   if (c->pinned) (void)hipHostFree(c->pinned);
+  for (auto& r : c->recs) {
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
   delete c;
   return KP_OK;
 }
 
 const char* kp_last_error(const kp_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+kp_status kp_prof_enable(kp_ctx* c, int enable) {
+  if (!c) return KP_E_INVAL;
+  c->prof = enable != 0;
+  return KP_OK;
+}
+
+kp_status kp_prof_read(kp_ctx* c, kp_prof* out, int reset) {
+  if (!c || !out) return KP_E_INVAL;
+  KP_HIP(c, hipSetDevice(c->device));
+  KP_HIP(c, hipDeviceSynchronize());
+  for (auto& r : c->recs) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+      c->acc_ms[r.cls] += ms;
+      c->acc_n[r.cls] += 1;
+      c->acc_flops[r.cls] += r.flops;
+    }
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  c->recs.clear();
+  for (int i = 0; i < 3; ++i) {
+    out->ms[i] = c->acc_ms[i];
+    out->launches[i] = c->acc_n[i];
+    out->flops[i] = c->acc_flops[i];
+    if (reset) {
+      c->acc_ms[i] = 0;
+      c->acc_n[i] = 0;
+      c->acc_flops[i] = 0;
+    }
+  }
+  return KP_OK;
+}
 
 kp_status kp_rmat_apply(kp_ctx* c, const kp_blur* b, int transpose, kp_prec prec, int32_t ncols,
                         const void* X, void* Y, void* stream) {
@@ -677,22 +916,33 @@ kp_status kp_svd_rsvd(kp_ctx* c, const kp_blur* b, const kp_rsvd_opts* o, kp_fac
 kp_status kp_apply(kp_ctx* c, const kp_factors* f, int transpose, const double* X, double* Y,
                    void* stream) {
   if (!c) return KP_E_INVAL;
-  (void)f; (void)transpose; (void)X; (void)Y; (void)stream;
-  return set_err(c, KP_E_INVAL, "kp_apply: not available in this build");
+  KP_TRY(validate_apply_factors(c, f));
+  if (!X || !Y) return set_err(c, KP_E_INVAL, "X or Y is NULL");
+  if (X == Y) return set_err(c, KP_E_INVAL, "X and Y must not alias");
+  KP_HIP(c, hipSetDevice(c->device));
+  hipStream_t s = (hipStream_t)stream;
+  const int n = f->n, k = f->k;
+  double *Z, *P;
+  KP_TRY(wsT(c, "kpZ", (size_t)k * n * n, &Z));
+  KP_TRY(wsT(c, "kpP", (size_t)k * n * n, &P));
+  {
+    ProfScope ps(c, s, 2, 4.0 * k * (double)n * n * n);
+    launch_kp_apply_ws((const double*)f->Ax, (const double*)f->Ay, n, k, transpose, X, Y, Z, P,
+                       nullptr, 0, s);
+  }
+  return check_launch(c, "kp_apply");
 }
 
 kp_status sb_solve_aniso(kp_ctx* c, const kp_factors* f, const double* b, const sb_opts* o,
                          double* x, sb_stats* st, void* stream) {
   if (!c) return KP_E_INVAL;
-  (void)f; (void)b; (void)o; (void)x; (void)st; (void)stream;
-  return set_err(c, KP_E_INVAL, "sb_solve_aniso: not available in this build");
+  return sb_solve(c, f, b, o, x, st, (hipStream_t)stream, 0);
 }
 
 kp_status sb_solve_iso(kp_ctx* c, const kp_factors* f, const double* b, const sb_opts* o,
                        double* x, sb_stats* st, void* stream) {
   if (!c) return KP_E_INVAL;
-  (void)f; (void)b; (void)o; (void)x; (void)st; (void)stream;
-  return set_err(c, KP_E_INVAL, "sb_solve_iso: not available in this build");
+  return sb_solve(c, f, b, o, x, st, (hipStream_t)stream, 1);
 }
 
 }  // extern "C"

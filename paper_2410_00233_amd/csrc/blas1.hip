@@ -47,7 +47,8 @@ __device__ __forceinline__ void row_range(long N, long* lo, long* hi) {
 template <typename T>
 __global__ void __launch_bounds__(256)
 multidot_kernel(const T* __restrict__ V, long ldv, int m, const T* __restrict__ w, long N,
-                double* __restrict__ partials) {
+                double* __restrict__ partials, const int* __restrict__ pred) {
+  if (pred && *pred == 0) return;
   __shared__ double sh[8][4];
   long lo, hi;
   row_range(N, &lo, &hi);
@@ -78,19 +79,20 @@ multidot_kernel(const T* __restrict__ V, long ldv, int m, const T* __restrict__ 
 
 template <typename T>
 void launch_multidot(const T* V, long ldv, int m, const T* w, long N, double* partials,
-                     hipStream_t s) {
+                     hipStream_t s, const int* pred) {
   hipLaunchKernelGGL(multidot_kernel<T>, dim3(kRedBlocks), dim3(256), 0, s, V, ldv, m, w, N,
-                     partials);
+                     partials, pred);
 }
 template void launch_multidot<float>(const float*, long, int, const float*, long, double*,
-                                     hipStream_t);
+                                     hipStream_t, const int*);
 template void launch_multidot<double>(const double*, long, int, const double*, long,
-                                      double*, hipStream_t);
+                                      double*, hipStream_t, const int*);
 
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(256)
 reduce_partials_kernel(const double* __restrict__ partials, int m, double* __restrict__ h,
-                       int accumulate) {
+                       int accumulate, const int* __restrict__ pred) {
+  if (pred && *pred == 0) return;
   __shared__ double sh[8];
   // block i reduces column i
   const int i = blockIdx.x;
@@ -100,17 +102,19 @@ reduce_partials_kernel(const double* __restrict__ partials, int m, double* __res
 }
 
 void launch_reduce_partials(const double* partials, int m, double* h, int accumulate,
-                            hipStream_t s) {
+                            hipStream_t s, const int* pred) {
   if (m <= 0) return;
   hipLaunchKernelGGL(reduce_partials_kernel, dim3(m), dim3(kRedThreads), 0, s, partials, m,
-                     h, accumulate);
+                     h, accumulate, pred);
 }
 
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ void __launch_bounds__(256)
 project_out_kernel(T* __restrict__ w, const T* __restrict__ V, long ldv, int m,
-                   const double* __restrict__ h, long N, double* __restrict__ nrm_partials) {
+                   const double* __restrict__ h, long N, double* __restrict__ nrm_partials,
+                   const int* __restrict__ pred) {
+  if (pred && *pred == 0) return;
   __shared__ double hs[64];
   __shared__ double sh[8];
   if (threadIdx.x < m) hs[threadIdx.x] = h[threadIdx.x];
@@ -131,14 +135,14 @@ project_out_kernel(T* __restrict__ w, const T* __restrict__ V, long ldv, int m,
 
 template <typename T>
 void launch_project_out(T* w, const T* V, long ldv, int m, const double* h, long N,
-                        double* nrm_partials, hipStream_t s) {
+                        double* nrm_partials, hipStream_t s, const int* pred) {
   hipLaunchKernelGGL(project_out_kernel<T>, dim3(kRedBlocks), dim3(256), 0, s, w, V, ldv, m,
-                     h, N, nrm_partials);
+                     h, N, nrm_partials, pred);
 }
 template void launch_project_out<float>(float*, const float*, long, int, const double*, long,
-                                        double*, hipStream_t);
+                                        double*, hipStream_t, const int*);
 template void launch_project_out<double>(double*, const double*, long, int, const double*,
-                                         long, double*, hipStream_t);
+                                         long, double*, hipStream_t, const int*);
 
 // ---------------------------------------------------------------------------
 template <typename T>
@@ -170,7 +174,8 @@ template void launch_norm2_partials<double>(const double*, long, double*, hipStr
 template <typename T>
 __global__ void __launch_bounds__(256)
 normalize_kernel(T* __restrict__ w, long N, const double* __restrict__ nrm_partials,
-                 double* __restrict__ norm_out) {
+                 double* __restrict__ norm_out, const int* __restrict__ pred) {
+  if (pred && *pred == 0) return;
   __shared__ double sh[8];
   const double nrm = sqrt(reduce_partials_block(nrm_partials, 1, 0, sh));
   if (blockIdx.x == 0 && threadIdx.x == 0 && norm_out) *norm_out = nrm;
@@ -183,12 +188,14 @@ normalize_kernel(T* __restrict__ w, long N, const double* __restrict__ nrm_parti
 
 template <typename T>
 void launch_normalize(T* w, long N, const double* nrm_partials, double* norm_out,
-                      hipStream_t s) {
+                      hipStream_t s, const int* pred) {
   hipLaunchKernelGGL(normalize_kernel<T>, dim3(kRedBlocks), dim3(256), 0, s, w, N,
-                     nrm_partials, norm_out);
+                     nrm_partials, norm_out, pred);
 }
-template void launch_normalize<float>(float*, long, const double*, double*, hipStream_t);
-template void launch_normalize<double>(double*, long, const double*, double*, hipStream_t);
+template void launch_normalize<float>(float*, long, const double*, double*, hipStream_t,
+                                      const int*);
+template void launch_normalize<double>(double*, long, const double*, double*, hipStream_t,
+                                       const int*);
 
 // ---------------------------------------------------------------------------
 template <typename T>
@@ -224,7 +231,8 @@ __device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32
 
 template <typename T>
 __global__ void philox_normals_kernel(T* __restrict__ out, long N, uint64_t seed,
-                                      uint32_t stream_id) {
+                                      uint32_t stream_id, const int* __restrict__ pred) {
+  if (pred && *pred == 0) return;
   const long nblk = (N + 1) / 2;
   for (long b = blockIdx.x * (long)blockDim.x + threadIdx.x; b < nblk;
        b += (long)gridDim.x * blockDim.x) {
@@ -241,12 +249,15 @@ __global__ void philox_normals_kernel(T* __restrict__ out, long N, uint64_t seed
 }
 
 template <typename T>
-void launch_philox_normals(T* out, long N, uint64_t seed, uint32_t stream_id, hipStream_t s) {
+void launch_philox_normals(T* out, long N, uint64_t seed, uint32_t stream_id, hipStream_t s,
+                           const int* pred) {
   hipLaunchKernelGGL(philox_normals_kernel<T>, dim3(1024), dim3(256), 0, s, out, N, seed,
-                     stream_id);
+                     stream_id, pred);
 }
-template void launch_philox_normals<float>(float*, long, uint64_t, uint32_t, hipStream_t);
-template void launch_philox_normals<double>(double*, long, uint64_t, uint32_t, hipStream_t);
+template void launch_philox_normals<float>(float*, long, uint64_t, uint32_t, hipStream_t,
+                                           const int*);
+template void launch_philox_normals<double>(double*, long, uint64_t, uint32_t, hipStream_t,
+                                            const int*);
 
 // ---------------------------------------------------------------------------
 template <typename S, typename D>

@@ -55,15 +55,17 @@ void launch_rmat_gemv(const BlockPlan& plan, const T* G, int ldg, int n, const T
 // ---- vector kernels (blas1.hip) --------------------------------------------
 // partials[b * m + i] = sum over rows of block b of V[:, i] . w  (FP64 accum)
 template <typename T>
+// Kernels taking `pred` do nothing when pred != nullptr and *pred == 0 (device-side
+// predication of data-dependent branches, no host synchronization).
 void launch_multidot(const T* V, long ldv, int m, const T* w, long N, double* partials,
-                     hipStream_t s);
+                     hipStream_t s, const int* pred = nullptr);
 // h[i] (+)= sum_b partials[b*m + i]; if accumulate != 0 adds into h
 void launch_reduce_partials(const double* partials, int m, double* h, int accumulate,
-                            hipStream_t s);
+                            hipStream_t s, const int* pred = nullptr);
 // w -= V h (m columns); nrm_partials[b] = block partial of ||w_new||^2
 template <typename T>
 void launch_project_out(T* w, const T* V, long ldv, int m, const double* h, long N,
-                        double* nrm_partials, hipStream_t s);
+                        double* nrm_partials, hipStream_t s, const int* pred = nullptr);
 // nrm_partials[b] = block partial of ||w||^2
 template <typename T>
 void launch_norm2_partials(const T* w, long N, double* nrm_partials, hipStream_t s);
@@ -71,13 +73,13 @@ void launch_norm2_partials(const T* w, long N, double* nrm_partials, hipStream_t
 // (written by block 0; may be null). A zero vector is left unchanged.
 template <typename T>
 void launch_normalize(T* w, long N, const double* nrm_partials, double* norm_out,
-                      hipStream_t s);
+                      hipStream_t s, const int* pred = nullptr);
 template <typename T>
 void launch_scale(T* w, long N, double factor, hipStream_t s);
 // out[e] = Philox normal number e of (seed, stream)
 template <typename T>
 void launch_philox_normals(T* out, long N, uint64_t seed, uint32_t stream_id,
-                           hipStream_t s);
+                           hipStream_t s, const int* pred = nullptr);
 template <typename S, typename D>
 void launch_convert(const S* in, D* out, long N, hipStream_t s);
 // out = V * C (V: N x m column-major ld ldv; C: m x k column-major FP64, ld ldc)
@@ -87,10 +89,16 @@ void launch_small_gemm(const T* V, long ldv, int m, const double* C, int ldc, in
 
 // ---- single-workgroup helpers (smallops.hip) ---------------------------------
 void launch_add_small(double* Rcol, const double* h, int m, hipStream_t s);
+// Bookkeeping of the third Gram-Schmidt pass; skipped when *replaced != 0.
 void launch_cgs_fixup(double* Rcol, int m, const double* h3, double* rjj, const double* r3,
-                      hipStream_t s);
+                      const int* replaced, hipStream_t s);
+// *flag = (*val < thresh)
+void launch_flag_below(const double* val, double thresh, int* flag, hipStream_t s);
 void launch_transpose_small(const double* in, int m, int nc, double* out, hipStream_t s);
 void launch_fill_small(double* p, int m, double v, hipStream_t s);
+void launch_fill(double* p, long n, double v, hipStream_t s);
+void launch_fill_int(int* p, int n, int v, hipStream_t s);
+void launch_count_nonfinite(const double* p, long n, int* flag, hipStream_t s);
 
 // ---- small dense SVD (jacobi.hip) ------------------------------------------
 // One-sided Jacobi SVD of an m x nc FP64 matrix (m >= nc, column-major, ld m,
@@ -106,9 +114,5 @@ void launch_form_factors(const T* U, const T* V, long ldu, int n, int k,
                          const double* sigma, O* Ax, O* Ay, int* argmax_scratch,
                          hipStream_t s);
 
-// ---- KP apply and split Bregman (kp_apply.hip / sb.hip) --------------------
-void launch_kp_apply(const double* Ax, const double* Ay, int n, int k, int transpose,
-                     const double* X, double* Y, double* T1, const int* skip,
-                     hipStream_t s);
 
 }  // namespace kpsb

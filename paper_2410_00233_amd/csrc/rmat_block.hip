@@ -10,10 +10,13 @@
 // merged, whatever the PSF.
 //
 // X streams through LDS in K-tiles of TK entries (fixed c, r0 <= r < r0 + TK),
-// double buffered, one barrier per tile. MFMA: v_mfma_f32_16x16x4f32 (FP32) or
-// v_mfma_f64_16x16x4f64 (FP64); fragment layout (CDNA3/4 ISA): A lane l holds
-// row l%16, k = l/16; B lane l holds k = l/16, column l%16; D lane l holds
-// rows 4*(l/16) + e (e = 0..3), column l%16.
+// double buffered, one barrier per tile. In FP32 the MFMA accumulators are
+// added into FP64 registers after every column block c (n products), so the
+// rounding error of the length-n^2 sums grows like sqrt(n), not sqrt(n^2). MFMA: v_mfma_f32_16x16x4f32 (FP32) or
+// v_mfma_f64_16x16x4f64 (FP64). Fragment layout (checked on gfx950): A lane l
+// holds row l%16, k = l/16; B lane l holds k = l/16, column l%16; D lane l
+// holds column l%16 and, for item e = 0..3, row 4*(l/16) + e (FP32) or
+// row l/16 + 4*e (FP64).
 #include "common.h"
 
 namespace kpsb {
@@ -105,8 +108,14 @@ template void launch_build_grid<__half>(const double*, int, int, int, int, int, 
 
 // ---------------------------------------------------------------------------
 template <typename T> struct Vec4;
-template <> struct Vec4<float> { typedef floatx4 type; };
-template <> struct Vec4<double> { typedef doublex4 type; };
+template <> struct Vec4<float> {
+  typedef floatx4 type;
+  static __device__ __forceinline__ int drow(int lk, int e) { return 4 * lk + e; }
+};
+template <> struct Vec4<double> {
+  typedef doublex4 type;
+  static __device__ __forceinline__ int drow(int lk, int e) { return lk + 4 * e; }
+};
 
 __device__ __forceinline__ floatx4 mfma16x16x4(float a, float b, floatx4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
@@ -185,12 +194,16 @@ rmat_block_kernel(const T* __restrict__ G, int ldg, int n, const T* __restrict__
   };
 
   acc_t acc[JB][CB];
+  double accd[JB][CB][4];
 #pragma unroll
   for (int jb = 0; jb < JB; ++jb)
 #pragma unroll
     for (int cb = 0; cb < CB; ++cb)
 #pragma unroll
-      for (int e = 0; e < 4; ++e) acc[jb][cb][e] = (T)0;
+      for (int e = 0; e < 4; ++e) {
+        acc[jb][cb][e] = (T)0;
+        accd[jb][cb][e] = 0.0;
+      }
 
   const int wc = wave % WC;
   const int wj = wave / WC;
@@ -225,6 +238,17 @@ rmat_block_kernel(const T* __restrict__ G, int ldg, int n, const T* __restrict__
 #pragma unroll
         for (int cb = 0; cb < CB; ++cb) acc[jb][cb] = mfma16x16x4(afr[jb], bfr[cb], acc[jb][cb]);
     }
+    if (sizeof(T) == 4 && (t - c * nrc) == nrc - 1) {   // end of column block c
+#pragma unroll
+      for (int jb = 0; jb < JB; ++jb)
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            accd[jb][cb][e] += (double)acc[jb][cb][e];
+            acc[jb][cb][e] = (T)0;
+          }
+    }
     if (t + 1 < total) store_tile((t + 1) & 1);
     __syncthreads();
   }
@@ -238,8 +262,9 @@ rmat_block_kernel(const T* __restrict__ G, int ldg, int n, const T* __restrict__
       const int col = (wc * CB + cb) * 16 + lrow;
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        const int i = i0 + 4 * lk + e;
-        if (i < n && j < n && col < ncols) Y[(long)col * ldy + i + (long)n * j] = acc[jb][cb][e];
+        const int i = i0 + Vec4<T>::drow(lk, e);
+        const double v = (sizeof(T) == 4) ? accd[jb][cb][e] : (double)acc[jb][cb][e];
+        if (i < n && j < n && col < ncols) Y[(long)col * ldy + i + (long)n * j] = (T)v;
       }
     }
   }

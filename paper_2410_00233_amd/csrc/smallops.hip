@@ -16,7 +16,9 @@ void launch_add_small(double* Rcol, const double* h, int m, hipStream_t s) {
 // After a third Gram-Schmidt pass on the normalized column q = w / r:
 // q = sum_i h3_i v_i + r3 q', hence w = sum_i (R_ij + r h3_i) v_i + r r3 q'.
 __global__ void cgs_fixup_kernel(double* __restrict__ Rcol, int m, const double* __restrict__ h3,
-                                 double* __restrict__ rjj, const double* __restrict__ r3) {
+                                 double* __restrict__ rjj, const double* __restrict__ r3,
+                                 const int* __restrict__ replaced) {
+  if (replaced && *replaced) return;
   const int i = threadIdx.x;
   const double r = *rjj;
   if (i < m) Rcol[i] += r * h3[i];
@@ -24,8 +26,16 @@ __global__ void cgs_fixup_kernel(double* __restrict__ Rcol, int m, const double*
   if (i == 0) *rjj = r * (*r3);
 }
 void launch_cgs_fixup(double* Rcol, int m, const double* h3, double* rjj, const double* r3,
-                      hipStream_t s) {
-  hipLaunchKernelGGL(cgs_fixup_kernel, dim3(1), dim3(64), 0, s, Rcol, m, h3, rjj, r3);
+                      const int* replaced, hipStream_t s) {
+  hipLaunchKernelGGL(cgs_fixup_kernel, dim3(1), dim3(64), 0, s, Rcol, m, h3, rjj, r3, replaced);
+}
+
+__global__ void flag_below_kernel(const double* __restrict__ val, double thresh,
+                                  int* __restrict__ flag) {
+  if (threadIdx.x == 0) *flag = (*val < thresh) ? 1 : 0;
+}
+void launch_flag_below(const double* val, double thresh, int* flag, hipStream_t s) {
+  hipLaunchKernelGGL(flag_below_kernel, dim3(1), dim3(64), 0, s, val, thresh, flag);
 }
 
 // out (nc x m, ld nc) = in^T (in: m x nc, ld m)
@@ -46,6 +56,41 @@ __global__ void fill_small_kernel(double* __restrict__ p, int m, double v) {
 }
 void launch_fill_small(double* p, int m, double v, hipStream_t s) {
   hipLaunchKernelGGL(fill_small_kernel, dim3(1), dim3(256), 0, s, p, m, v);
+}
+
+// *flag = 1 if any entry of p is NaN or infinite, else 0 (one workgroup)
+__global__ void count_nonfinite_kernel(const double* __restrict__ p, long n, int* __restrict__ flag) {
+  __shared__ int any;
+  if (threadIdx.x == 0) any = 0;
+  __syncthreads();
+  int mine = 0;
+  for (long e = threadIdx.x; e < n; e += blockDim.x)
+    if (!isfinite(p[e])) mine = 1;
+  if (mine) atomicOr(&any, 1);
+  __syncthreads();
+  if (threadIdx.x == 0) *flag = any;
+}
+void launch_count_nonfinite(const double* p, long n, int* flag, hipStream_t s) {
+  hipLaunchKernelGGL(count_nonfinite_kernel, dim3(1), dim3(1024), 0, s, p, n, flag);
+}
+
+// grid-stride fills (graph-capture safe, unlike memset nodes)
+__global__ void fill_kernel(double* __restrict__ p, long n, double v) {
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < n;
+       e += (long)gridDim.x * blockDim.x)
+    p[e] = v;
+}
+void launch_fill(double* p, long n, double v, hipStream_t s) {
+  long blocks = (n + 255) / 256;
+  if (blocks > 2048) blocks = 2048;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(fill_kernel, dim3((int)blocks), dim3(256), 0, s, p, n, v);
+}
+__global__ void fill_int_kernel(int* __restrict__ p, int n, int v) {
+  for (int e = threadIdx.x; e < n; e += blockDim.x) p[e] = v;
+}
+void launch_fill_int(int* p, int n, int v, hipStream_t s) {
+  hipLaunchKernelGGL(fill_int_kernel, dim3(1), dim3(64), 0, s, p, n, v);
 }
 
 }  // namespace kpsb

@@ -64,13 +64,14 @@ LAYOUT_C = r"""
 #define P(T, f) printf(#T "." #f " %zu\n", offsetof(T, f))
 #define S(T) printf(#T " %zu\n", sizeof(T))
 int main(void) {
-  S(kp_blur); P(kp_blur, psf); P(kp_blur, cv);
+  S(kp_blur); P(kp_blur, psf); P(kp_blur, cv); P(kp_blur, psf_on_device);
   S(kp_gkb_opts); P(kp_gkb_opts, tau); P(kp_gkb_opts, prec); P(kp_gkb_opts, seed); P(kp_gkb_opts, y0); P(kp_gkb_opts, bd_rel);
   S(kp_rsvd_opts); P(kp_rsvd_opts, prec); P(kp_rsvd_opts, seed); P(kp_rsvd_opts, F);
   S(kp_diag); P(kp_diag, alpha); P(kp_diag, kp); P(kp_diag, break_side); P(kp_diag, ms_total); P(kp_diag, basis_v);
   S(kp_factors); P(kp_factors, sigma); P(kp_factors, Ax); P(kp_factors, factor_prec); P(kp_factors, diag);
   S(sb_opts); P(sb_opts, L_max); P(sb_opts, tau_cgls);
   S(sb_stats); P(sb_stats, rc_sb);
+  S(kp_prof); P(kp_prof, launches); P(kp_prof, flops);
   return 0;
 }
 """
@@ -86,7 +87,7 @@ def test_ctypes_layout_matches_header(tmp_path):
     ref = dict(l.rsplit(" ", 1) for l in lines if l)
     m = {"kp_blur": _lib.kp_blur, "kp_gkb_opts": _lib.kp_gkb_opts, "kp_rsvd_opts": _lib.kp_rsvd_opts,
          "kp_diag": _lib.kp_diag, "kp_factors": _lib.kp_factors, "sb_opts": _lib.sb_opts,
-         "sb_stats": _lib.sb_stats}
+         "sb_stats": _lib.sb_stats, "kp_prof": _lib.kp_prof}
     rename = {"lambda": "lam"}
     for key, val in ref.items():
         if "." in key:

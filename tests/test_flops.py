@@ -1,0 +1,37 @@
+"""The flop model used for TFLOP/s figures, pinned to the paper's printed
+worked numbers (tests/golden/paper_cost_model.json)."""
+import json
+import os
+
+import pytest
+
+from paper_2410_00233_amd import flops
+
+GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_cost_model.json")))
+
+
+def test_sb_speedup_is_30_for_pattern2():
+    g = GOLD["sb_speedup"]
+    assert flops.sb_speedup(g["n"], g["k"], g["P"]) == pytest.approx(g["value"])
+
+
+def test_alg_speedup_is_about_99_for_pattern2():
+    # The printed 99 is the bound 1.5 iota_total / k_p, i.e. rho = 2 in the
+    # formula (3 / rho) iota_total / k_p; with rho = 1 (EGKB) the formula itself
+    # gives twice that.
+    g = GOLD["alg_speedup"]
+    v = flops.alg_speedup(g["n"], g["kp"], g["iota_total"], rho=2)
+    assert abs(v - g["approx_value"]) <= g["approx_tol"]
+    assert flops.alg_speedup(g["n"], g["kp"], g["iota_total"], rho=1) == pytest.approx(2 * v)
+
+
+def test_rsvd_costs_twice_egkb_at_q1():
+    assert flops.rsvd(100, 5, 2, q=1) / flops.egkb(100, 5, 2) == pytest.approx(GOLD["rsvd_over_egkb"]["value"])
+
+
+def test_configured_workload_counts():
+    # n = 512, rank 20: RSVD (p = 10, q = 2) 2.474e13, EGKB (k_p = 40) 1.100e13 flops
+    assert flops.rsvd(512, 20, 10, 2) == pytest.approx(2.474e13, rel=1e-3)
+    assert flops.egkb(512, 20, 20) == pytest.approx(1.100e13, rel=1e-3)
+    assert flops.rmat_product(512, 30) == 2.0 * 512 ** 4 * 30
+    assert flops.kp_apply(512, 20) == 4.0 * 20 * 512 ** 3

@@ -57,11 +57,18 @@ def test_egkb_f64_n32_matches_oracle(ctx, reorth):
     S = f.S.cpu().numpy().T
     Q = f.Q.cpu().numpy().T
     assert np.linalg.norm(R(Q) - S @ ref["C"]) <= 1e-12 * s1
-    # factors: same sign convention on both sides
+    # factors: the sign of a term is only unique up to ties of the largest |v|
+    # entry (the rotated Gaussian is point-symmetric, so mirrored entries tie);
+    # compare after aligning each term's sign, and check the rule on each side.
     Ax_ref, Ay_ref = kpsvd.kp_terms(ref["sigma"], ref["U"], ref["V"], n)
     _, _, _, Ax, Ay = _uv_from_factors(f)
-    assert np.abs(Ax - Ax_ref).max() <= 1e-9 * np.abs(Ax_ref).max()
-    assert np.abs(Ay - Ay_ref).max() <= 1e-9 * np.abs(Ay_ref).max()
+    for t_ in range(k):
+        sg = np.sign(np.sum(Ay[t_] * Ay_ref[t_]))
+        assert np.abs(Ax[t_] - sg * Ax_ref[t_]).max() <= 1e-9 * np.abs(Ax_ref).max()
+        assert np.abs(Ay[t_] - sg * Ay_ref[t_]).max() <= 1e-9 * np.abs(Ay_ref).max()
+        v = Ay[t_].flatten(order="F")
+        m = np.argmax(np.abs(v))
+        assert v[m] > 0
 
 
 def test_egkb_disk_breakdown_is_exact(ctx):
@@ -89,6 +96,12 @@ def test_egkb_f32_matches_oracle(ctx, n, psf, k, p):
     s1 = ref["sigma"][0]
     err = np.abs(f.sigma[:k] - ref["sigma"]).max() / s1
     print(f"EGKB f32 n={n} {psf}: max|dsigma|/sigma1 = {err:.2e}, breakdowns {f.breakdowns}")
+    print("  gpu sigma/s1", np.array2string(f.sigma[:k] / s1, precision=3))
+    print("  ref sigma/s1", np.array2string(ref["sigma"] / s1, precision=3))
+    print("  gpu alpha", np.array2string(f.alpha / s1, precision=3))
+    print("  ref alpha", np.array2string(ref["alpha"] / s1, precision=3))
+    print("  gpu t", np.array2string(f.t / s1, precision=3))
+    print("  ref t", np.array2string(ref["t"] / s1, precision=3))
     assert err <= 1e-5
     # quality against the exact KP-SVD (reported), and the approximation error
     s_ex = op.exact_kpsvd(P, cu, cv, n, k)[0]
@@ -102,6 +115,7 @@ def test_egkb_f32_matches_oracle(ctx, n, psf, k, p):
 
 @pytest.mark.parametrize("n,psf,k,p,q", [(32, "gaussian", 5, 5, 1), (256, "gaussian", 20, 10, 2),
                                          (128, "speckle", 20, 10, 2), (512, "gaussian", 20, 10, 2),
+                                         (64, "disk", 20, 10, 2), (256, "disk", 20, 10, 2),
                                          (512, "disk", 20, 10, 2)])
 @pytest.mark.parametrize("prec", ["f32", "f64"])
 def test_rsvd_matches_oracle(ctx, n, psf, k, p, q, prec):
@@ -117,12 +131,17 @@ def test_rsvd_matches_oracle(ctx, n, psf, k, p, q, prec):
     s1 = ref["sigma"][0]
     err = np.abs(f.sigma[:k] - ref["sigma"]).max() / s1
     print(f"RSVD {prec} n={n} {psf}: max|dsigma|/sigma1 = {err:.2e}")
+    if err > 1e-5:
+        print("  gpu sigma/s1", np.array2string(f.sigma[:k] / s1, precision=3))
+        print("  ref sigma/s1", np.array2string(ref["sigma"] / s1, precision=3))
     assert err <= (1e-12 if prec == "f64" else 1e-5)
     s, U, V, _, _ = _uv_from_factors(f)
     e_gpu = metrics.kp_rel_error(P, cu, cv, n, s, U, V)
     e_ref = metrics.kp_rel_error(P, cu, cv, n, ref["sigma"], ref["U"], ref["V"])
     print(f"  ||A-A_k||/||A|| gpu {e_gpu:.4e}  oracle {e_ref:.4e}")
-    assert e_gpu <= e_ref + (1e-10 if prec == "f64" else 1e-5)
+    # the expansion of ||R - U S V^T||^2 cancels to ~1e-14 relative, so errors
+    # below ~1e-7 are not resolved; FP32 factors sit near 1e-5
+    assert e_gpu <= e_ref + (1e-6 if prec == "f64" else 5e-5)
 
 
 def test_sp_and_dp_errors_are_comparable(ctx):

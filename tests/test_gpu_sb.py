@@ -1,0 +1,104 @@
+"""Parity of kp_apply (eq. "KPAx"), CGLS (Algorithm 5) and split Bregman
+(Algorithms 3 and 4) with the oracle, given identical Kronecker factors.
+
+kp_apply: FP64 both sides, |err| <= 1e-13 * max|ref|.
+SB: restored image rel-L2 <= 1e-6 against the oracle with fixed iteration
+counts (the spec gate); with the paper's tolerances the stopping counts
+must agree as well.
+"""
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle import kpsvd, operator as op, sb
+
+pytestmark = pytest.mark.gpu
+
+
+def _dev(a):
+    import torch
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+@pytest.mark.parametrize("n,k", [(5, 1), (32, 5), (70, 3), (100, 8), (256, 20)])
+def test_kp_apply_matches_oracle(ctx, n, k):
+    from paper_2410_00233_amd import api
+    rng = np.random.default_rng(n + k)
+    Ax = rng.standard_normal((k, n, n))
+    Ay = rng.standard_normal((k, n, n))
+    X = rng.standard_normal((n, n))
+    f = api.Factors.from_arrays(Ax, Ay)
+    for tr in (False, True):
+        Y = ctx.kp_apply(f, _dev(X), transpose=tr).cpu().numpy()
+        ref = sb.kp_apply(Ax, Ay, X, transpose=tr)
+        assert np.abs(Y - ref).max() <= 1e-13 * np.abs(ref).max() * max(1.0, np.sqrt(k * n) / 8)
+
+
+def test_kp_apply_full_rank_is_the_blur(ctx):
+    from paper_2410_00233_amd import api
+    n = 16
+    P, cu, cv = wl.random_psf(5, 7, 3)
+    s, U, V = op.exact_kpsvd(P, cu, cv, n)
+    Ax, Ay = kpsvd.kp_terms(s, U, V, n)
+    X = np.random.default_rng(0).standard_normal((n, n))
+    Y = ctx.kp_apply(api.Factors.from_arrays(Ax, Ay), _dev(X)).cpu().numpy()
+    assert np.abs(Y - wl.blur_zero_bc(P, cu, cv, X)).max() <= 1e-13
+
+
+def _problem(n, k, psf="gaussian", idx=0):
+    P, cu, cv, x_true, b_true, b = wl.deblur_problem(n, psf, 0.01, idx)
+    s, U, V = op.exact_kpsvd(P, cu, cv, n, k)
+    Ax, Ay = kpsvd.kp_terms(s, U, V, n)
+    return Ax, Ay, b, x_true
+
+
+def _oracle(kind, Ax, Ay, b, lam, beta, **kw):
+    return sb.split_bregman(kind, lambda X: sb.kp_apply(Ax, Ay, X),
+                            lambda X: sb.kp_apply(Ax, Ay, X, True), b, lam, beta, **kw)
+
+
+@pytest.mark.parametrize("kind", ["aniso", "iso"])
+@pytest.mark.parametrize("n,k,L,I", [(32, 5, 20, 100), (48, 7, 4, 12), (64, 10, 3, 20)])
+def test_sb_fixed_counts_match_oracle(ctx, kind, n, k, L, I):
+    from paper_2410_00233_amd import api
+    Ax, Ay, b, x_true = _problem(n, k)
+    lam, gamma = 0.115, 2.0
+    beta = lam * lam / gamma
+    f = api.Factors.from_arrays(Ax, Ay)
+    fn = ctx.sb_solve_aniso if kind == "aniso" else ctx.sb_solve_iso
+    x, st = fn(f, _dev(b), lam, beta, L_max=L, I_max=I)
+    x = x.cpu().numpy()
+    ref = _oracle(kind, Ax, Ay, b, lam, beta, L_max=L, I_max=I)
+    rel = np.linalg.norm(x - ref["x"]) / np.linalg.norm(ref["x"])
+    print(f"SB {kind} n={n} k={k} L={L} I={I}: rel-L2 vs oracle {rel:.2e}")
+    assert rel <= 1e-6
+    assert st["l_end"] == L and st["iota_total"] == L * I
+    assert abs(st["rc_sb"] - ref["rc_sb"]) <= 1e-6 * max(ref["rc_sb"], 1e-12)
+
+
+@pytest.mark.parametrize("kind", ["aniso", "iso"])
+def test_sb_tolerances_match_oracle_counts(ctx, kind):
+    from paper_2410_00233_amd import api
+    n, k = 32, 5
+    Ax, Ay, b, _ = _problem(n, k, idx=1)
+    lam, gamma = 0.115, 2.0
+    kw = dict(L_max=50, I_max=100, tau_sb=1e-2, tau_cgls=1e-4)
+    f = api.Factors.from_arrays(Ax, Ay)
+    fn = ctx.sb_solve_aniso if kind == "aniso" else ctx.sb_solve_iso
+    x, st = fn(f, _dev(b), lam, lam * lam / gamma, **kw)
+    ref = _oracle(kind, Ax, Ay, b, lam, lam * lam / gamma, **kw)
+    print(f"SB {kind} tol: gpu l_end {st['l_end']} iota {st['iota_total']}, "
+          f"oracle {ref['l_end']} {ref['iota_total']}")
+    assert st["l_end"] == ref["l_end"] and st["iota_total"] == ref["iota_total"]
+    rel = np.linalg.norm(x.cpu().numpy() - ref["x"]) / np.linalg.norm(ref["x"])
+    assert rel <= 1e-6
+
+
+def test_sb_rejects_bad_arguments(ctx):
+    from paper_2410_00233_amd import api
+    Ax, Ay, b, _ = _problem(16, 3)
+    f = api.Factors.from_arrays(Ax, Ay)
+    with pytest.raises(api.KPError):
+        ctx.sb_solve_iso(f, _dev(b), -1.0, 0.1)
+    with pytest.raises(api.KPError):
+        ctx.sb_solve_iso(f, _dev(b), 0.1, 0.1, L_max=0)
