@@ -11,8 +11,9 @@
 
 namespace kpsb {
 
-constexpr int kTKV = 256;   // x entries staged per chunk
+constexpr int kTKV = 256;   // x entries staged per chunk (FP64 kernel)
 
+// FP64 kernel: x chunks of kTKV entries, scalar LDS reads.
 template <typename T, int TJ>
 __global__ void __launch_bounds__(256)
 rmat_gemv_kernel(const T* __restrict__ G, int ldg, int n, const T* __restrict__ x,
@@ -63,7 +64,6 @@ rmat_gemv_kernel(const T* __restrict__ G, int ldg, int n, const T* __restrict__ 
   __syncthreads();
 
   double acc = 0.0;
-  T accT = (T)0;
   for (int t = 0; t < total; ++t) {
     if (t + 1 < total) st = load(t + 1);
     const int c = t / nrc;
@@ -74,12 +74,10 @@ rmat_gemv_kernel(const T* __restrict__ G, int ldg, int n, const T* __restrict__ 
     T part = (T)0;
 #pragma unroll 8
     for (int k = h; k < kend; k += H) part += ap[k] * xs[k];
-    accT += part;
-    if ((t & 7) == 7) { acc += (double)accT; accT = (T)0; }
+    acc += (double)part;
     if (t + 1 < total) xbuf[((t + 1) & 1) * kTKV + tid] = st;
     __syncthreads();
   }
-  acc += (double)accT;
 
   if (H > 1) {
     red[tid] = acc;
@@ -100,8 +98,122 @@ rmat_gemv_kernel(const T* __restrict__ G, int ldg, int n, const T* __restrict__ 
   }
 }
 
+// FP32 kernel. For every column block c the staged x covers
+// r in [r0_c, r0_c + LEN) with r0_c = -((n - 1 - c) mod 4), so the first slab
+// column it meets, r0_c - c + n - 1, is a multiple of 4: both the slab row and
+// the staged x are then read as aligned float4 (0.5 LDS reads per FMA). Entries
+// with r outside [0, n) are staged as 0. Products of one c (LEN terms) are summed
+// in FP32 and added into an FP64 accumulator.
+template <int TJ>
+__global__ void __launch_bounds__(256)
+rmat_gemv4_kernel(const float* __restrict__ G, int ldg, int n, const float* __restrict__ x,
+                  float* __restrict__ y, const float* __restrict__ z, double coef, int SW,
+                  int LEN) {
+  constexpr int SR = 16 + TJ - 1;
+  constexpr int ROWS = 16 * TJ;
+  constexpr int H = 256 / ROWS;
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  float* slab = reinterpret_cast<float*>(lds_raw);
+  float* xbuf = slab + SR * SW;                // 2 x LEN
+  __shared__ double red[256];
+
+  const int tid = threadIdx.x;
+  const int n_it = (n + 15) >> 4;
+  const int it = blockIdx.x % n_it;
+  const int jt = blockIdx.x / n_it;
+  const int i0 = it * 16;
+  const int j0 = jt * TJ;
+  const int g2 = 2 * n - 1;
+  const int a0 = i0 - j0 - (TJ - 1) + n - 1;
+
+  for (int al = 0; al < SR; ++al) {
+    const int a = a0 + al;
+    const bool rowok = (a >= 0) && (a < g2);
+    const float* src = G + (long)(rowok ? a : 0) * ldg;
+    for (int col = tid; col < SW; col += 256) {
+      float v = 0.f;
+      if (rowok && col < g2) v = src[col];
+      slab[al * SW + col] = v;
+    }
+  }
+
+  const int rr = tid % ROWS;
+  const int h = tid / ROWS;
+  const int li = rr & 15;
+  const int jg = rr >> 4;
+  const float* arow = slab + (li + (TJ - 1) - jg) * SW;
+  const int nv = LEN >> 2;                 // float4 per column block
+  constexpr int MAXL = 8;                  // staged x entries per thread (LEN <= 2048)
+  float st[MAXL];
+  auto load = [&](int c) {
+    const int r0 = -((n - 1 - c) & 3);
+#pragma unroll
+    for (int m = 0; m < MAXL; ++m) {
+      const int kk = tid + 256 * m;
+      const int r = r0 + kk;
+      st[m] = (kk < LEN && r >= 0 && r < n) ? x[(long)n * c + r] : 0.f;
+    }
+  };
+  auto store = [&](int buf) {
+    float* xs = xbuf + buf * LEN;
+#pragma unroll
+    for (int m = 0; m < MAXL; ++m) {
+      const int kk = tid + 256 * m;
+      if (kk < LEN) xs[kk] = st[m];
+    }
+  };
+  load(0);
+  store(0);
+  __syncthreads();
+
+  double acc = 0.0;
+  for (int c = 0; c < n; ++c) {
+    if (c + 1 < n) load(c + 1);
+    const int base = -((n - 1 - c) & 3) - c + n - 1;      // multiple of 4
+    const float4* ap = reinterpret_cast<const float4*>(arow + base);
+    const float4* xs = reinterpret_cast<const float4*>(xbuf + (c & 1) * LEN);
+    float p0 = 0.f, p1 = 0.f, p2 = 0.f, p3 = 0.f;
+#pragma unroll 4
+    for (int v = h; v < nv; v += H) {
+      const float4 a = ap[v];
+      const float4 b = xs[v];
+      p0 = fmaf(a.x, b.x, p0);
+      p1 = fmaf(a.y, b.y, p1);
+      p2 = fmaf(a.z, b.z, p2);
+      p3 = fmaf(a.w, b.w, p3);
+    }
+    acc += (double)((p0 + p1) + (p2 + p3));
+    if (c + 1 < n) store((c + 1) & 1);
+    __syncthreads();
+  }
+
+  if (H > 1) {
+    red[tid] = acc;
+    __syncthreads();
+    if (h == 0) {
+      for (int q = 1; q < H; ++q) acc += red[tid + q * ROWS];
+    }
+  }
+  if (h == 0) {
+    const int i = i0 + li;
+    const int j = j0 + jg;
+    if (i < n && j < n) {
+      const long row = i + (long)n * j;
+      double v = acc;
+      if (z) v -= coef * (double)z[row];
+      y[row] = (float)v;
+    }
+  }
+}
+
+static int gemv4_len(int n) { return ((n + 3 + 3) / 4) * 4; }
+
 template <typename T>
 static int gemv_stride(int n) {
+  if (sizeof(T) == 4) {
+    const int W = n + gemv4_len(n) - 1;           // largest slab column + 1
+    return ((W + 63) / 64) * 64 + 4;               // multiple of 4 floats
+  }
   const int nrc = (n + kTKV - 1) / kTKV;
   const int W = nrc * kTKV + n - 1;
   return ((W + 31) / 32) * 32 + 1;
@@ -109,7 +221,8 @@ static int gemv_stride(int n) {
 
 template <typename T>
 static size_t gemv_lds(int n, int TJ) {
-  return sizeof(T) * ((size_t)(16 + TJ - 1) * gemv_stride<T>(n) + 2 * kTKV);
+  const size_t xs = sizeof(T) == 4 ? 2 * (size_t)gemv4_len(n) : 2 * (size_t)kTKV;
+  return sizeof(T) * ((size_t)(16 + TJ - 1) * gemv_stride<T>(n) + xs);
 }
 
 template <typename T>
@@ -117,6 +230,7 @@ bool plan_gemv(int n, size_t lds_limit, BlockPlan* plan) {
   static const int cand[] = {16, 8, 4, 2, 1};
   int forced = 0;
   if (const char* e = getenv("KPSB_GEMV_TJ")) forced = atoi(e);
+  if (sizeof(T) == 4 && gemv4_len(n) > 2048) return false;   // staged x per thread
   // the static reduction buffer (2 KB) shares the LDS budget
   size_t limit = lds_limit > 4096 ? lds_limit - 4096 : 0;
   for (int TJ : cand) {
@@ -143,6 +257,43 @@ static void gemv_tj(const BlockPlan& p, const T* G, int ldg, int n, const T* x, 
     (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)p.lds);
   hipLaunchKernelGGL(kern, dim3(p.grid), dim3(256), p.lds, s, G, ldg, n, x, y, z, coef, p.SW);
+}
+
+template <int TJ>
+static void gemv4_tj(const BlockPlan& p, const float* G, int ldg, int n, const float* x,
+                     float* y, const float* z, double coef, hipStream_t s) {
+  auto kern = rmat_gemv4_kernel<TJ>;
+  if (p.lds > 65536)
+    (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)p.lds);
+  hipLaunchKernelGGL(kern, dim3(p.grid), dim3(256), p.lds, s, G, ldg, n, x, y, z, coef, p.SW,
+                     gemv4_len(n));
+}
+
+template <>
+void gemv_tj<float, 16>(const BlockPlan& p, const float* G, int ldg, int n, const float* x,
+                        float* y, const float* z, double coef, hipStream_t s) {
+  gemv4_tj<16>(p, G, ldg, n, x, y, z, coef, s);
+}
+template <>
+void gemv_tj<float, 8>(const BlockPlan& p, const float* G, int ldg, int n, const float* x,
+                       float* y, const float* z, double coef, hipStream_t s) {
+  gemv4_tj<8>(p, G, ldg, n, x, y, z, coef, s);
+}
+template <>
+void gemv_tj<float, 4>(const BlockPlan& p, const float* G, int ldg, int n, const float* x,
+                       float* y, const float* z, double coef, hipStream_t s) {
+  gemv4_tj<4>(p, G, ldg, n, x, y, z, coef, s);
+}
+template <>
+void gemv_tj<float, 2>(const BlockPlan& p, const float* G, int ldg, int n, const float* x,
+                       float* y, const float* z, double coef, hipStream_t s) {
+  gemv4_tj<2>(p, G, ldg, n, x, y, z, coef, s);
+}
+template <>
+void gemv_tj<float, 1>(const BlockPlan& p, const float* G, int ldg, int n, const float* x,
+                       float* y, const float* z, double coef, hipStream_t s) {
+  gemv4_tj<1>(p, G, ldg, n, x, y, z, coef, s);
 }
 
 template <typename T>

@@ -58,20 +58,22 @@ void launch_fill_small(double* p, int m, double v, hipStream_t s) {
   hipLaunchKernelGGL(fill_small_kernel, dim3(1), dim3(256), 0, s, p, m, v);
 }
 
-// *flag = 1 if any entry of p is NaN or infinite, else 0 (one workgroup)
+void launch_fill_int(int* p, int n, int v, hipStream_t s);
+
+// *flag |= 1 if any entry of p is NaN or infinite (caller zeroes *flag first)
 __global__ void count_nonfinite_kernel(const double* __restrict__ p, long n, int* __restrict__ flag) {
-  __shared__ int any;
-  if (threadIdx.x == 0) any = 0;
-  __syncthreads();
   int mine = 0;
-  for (long e = threadIdx.x; e < n; e += blockDim.x)
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < n;
+       e += (long)gridDim.x * blockDim.x)
     if (!isfinite(p[e])) mine = 1;
-  if (mine) atomicOr(&any, 1);
-  __syncthreads();
-  if (threadIdx.x == 0) *flag = any;
+  if (__any(mine) && (threadIdx.x & 63) == 0) atomicOr(flag, 1);
 }
 void launch_count_nonfinite(const double* p, long n, int* flag, hipStream_t s) {
-  hipLaunchKernelGGL(count_nonfinite_kernel, dim3(1), dim3(1024), 0, s, p, n, flag);
+  launch_fill_int(flag, 1, 0, s);
+  long blocks = (n + 255) / 256;
+  if (blocks > 1024) blocks = 1024;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(count_nonfinite_kernel, dim3((int)blocks), dim3(256), 0, s, p, n, flag);
 }
 
 // grid-stride fills (graph-capture safe, unlike memset nodes)
