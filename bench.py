@@ -31,6 +31,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 MFMA_FP32_PEAK_TFLOPS = 157.3     # MI355X dense FP32 matrix peak
+MFMA_BF16_PEAK_TFLOPS = 2500.0    # MI355X dense BF16 matrix peak
 HBM_PEAK_GBS = 8000.0
 
 
@@ -122,6 +123,24 @@ def main():
     ms_step = 1e3 * (t1 - t0) / args.steps
     value = (f_gkb + f_rsvd) / (ms_step * 1e-3) / 1e12
 
+    # the reduced-precision variant: RSVD with BF16 block products + refinement
+    f_ref = flops.rmat_product(n, k)
+    ctx.kp_svd_rsvd(blur, k, p_rsvd, q, prec="bf16", refine=True, seed=2, factor_prec="f64")
+    torch.cuda.synchronize()
+    ctx.kp_prof_enable(True)
+    tb = []
+    for _ in range(args.steps):
+        ta = time.perf_counter()
+        fb = ctx.kp_svd_rsvd(blur, k, p_rsvd, q, prec="bf16", refine=True, seed=2, factor_prec="f64")
+        tb.append(1e3 * (time.perf_counter() - ta))
+    ctx.kp_prof_enable(False)
+    prof16 = ctx.kp_prof_read(reset=True)
+    b16 = prof16["block16"]
+    avg16 = b16["ms"] / max(b16["launches"], 1)
+    ach16 = (b16["flops"] / max(b16["launches"], 1)) / (avg16 * 1e-3) / 1e12
+    bf_ms = float(np.median(tb))
+    sig_diff = float(np.abs(fb.sigma[:k] - fr.sigma[:k]).max() / fr.sigma[0])
+
     blk = prof["block"]
     avg_blk_ms = blk["ms"] / max(blk["launches"], 1)
     flops_blk = blk["flops"] / max(blk["launches"], 1)
@@ -159,6 +178,16 @@ def main():
             "gemv_kernel_tflops": round(gemv_tflops, 3),
             "sigma_egkb_top3": [float(x) for x in fg.sigma[:3]],
             "sigma_rsvd_top3": [float(x) for x in fr.sigma[:3]],
+            "rsvd_bf16_refine_ms": round(bf_ms, 3),
+            "rsvd_bf16_refine_tflops": round((f_rsvd + f_ref) / (bf_ms * 1e-3) / 1e12, 3),
+            "rsvd_bf16_refine_speedup_vs_fp32": round(float(np.median(comp["rsvd_ms"])) / bf_ms, 3),
+            "rsvd_bf16_refine_max_sigma_diff_vs_fp32_over_sigma1": sig_diff,
+        },
+        "roofline_bf16": {
+            "kernel": "rmat_block16_kernel<bf16> (generated-tile R(A) X, BF16 MFMA 16x16x32, FP32 accumulate)",
+            "bound": "mfma", "achieved": round(ach16, 3), "peak": MFMA_BF16_PEAK_TFLOPS,
+            "unit": "TFLOP/s", "frac": round(ach16 / MFMA_BF16_PEAK_TFLOPS, 4),
+            "avg_launch_ms": round(avg16, 4), "launches": int(b16["launches"]),
         },
         "roofline": {
             "kernel": "rmat_block_kernel<float,16,4,2> (generated-tile R(A) X, FP32 MFMA 16x16x4)",

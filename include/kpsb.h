@@ -139,16 +139,17 @@ typedef struct {
   double rc_sb;         /* last RC_SB                                              */
 } sb_stats;
 
-/* Per-kernel-class timing (tracing). While enabled, every launch of the
- * generated-tile block product (class 0), the matrix-vector product (class 1)
- * and the Kronecker-apply GEMMs (class 2) is bracketed with hipEvents on the
- * stream of the call; kp_prof_read synchronizes the device and returns, per
- * class, the summed event time, the launch count and the algorithmic flops of
- * those launches (2 n^4 per column for R products, 4 k n^3 per apply). */
+/* Per-kernel-class timing (tracing). While enabled, every launch of the FP32 /
+ * FP64 generated-tile block product (class 0), the matrix-vector product
+ * (class 1), the Kronecker-apply GEMMs (class 2) and the 16-bit block product
+ * (class 3) is bracketed with hipEvents on the stream of the call;
+ * kp_prof_read synchronizes the device and returns, per class, the summed event
+ * time, the launch count and the algorithmic flops of those launches (2 n^4 per
+ * column for R products, 4 k n^3 per apply). */
 typedef struct {
-  double ms[3];
-  int64_t launches[3];
-  double flops[3];
+  double ms[4];
+  int64_t launches[4];
+  double flops[4];
 } kp_prof;
 
 /* Context: binds `device`, owns a workspace that never exceeds

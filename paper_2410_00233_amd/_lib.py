@@ -63,7 +63,7 @@ class sb_opts(C.Structure):
 
 
 class kp_prof(C.Structure):
-    _fields_ = [("ms", C.c_double * 3), ("launches", C.c_int64 * 3), ("flops", C.c_double * 3)]
+    _fields_ = [("ms", C.c_double * 4), ("launches", C.c_int64 * 4), ("flops", C.c_double * 4)]
 
 
 class sb_stats(C.Structure):

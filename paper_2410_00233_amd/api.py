@@ -124,7 +124,7 @@ class Context:
         pr = L.kp_prof()
         self._check(self.lib.kp_prof_read(self.h, C.byref(pr), int(reset)))
         return {name: dict(ms=pr.ms[i], launches=pr.launches[i], flops=pr.flops[i])
-                for i, name in enumerate(("block", "gemv", "apply"))}
+                for i, name in enumerate(("block", "gemv", "apply", "block16"))}
 
     # ---- entry points (names follow the C ABI) ----------------------------
     def kp_rmat_apply(self, blur: Blur, X, transpose=False, prec="f32", Y=None):

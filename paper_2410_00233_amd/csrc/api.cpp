@@ -11,6 +11,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <type_traits>
 #include <string>
 #include <vector>
 
@@ -40,9 +41,9 @@ struct kp_ctx {
     double flops;
   };
   std::vector<Rec> recs;
-  double acc_ms[3] = {0, 0, 0};
-  int64_t acc_n[3] = {0, 0, 0};
-  double acc_flops[3] = {0, 0, 0};
+  double acc_ms[4] = {0, 0, 0, 0};
+  int64_t acc_n[4] = {0, 0, 0, 0};
+  double acc_flops[4] = {0, 0, 0, 0};
 };
 
 namespace {
@@ -164,17 +165,23 @@ kp_status upload_psf(kp_ctx* c, const kp_blur* b, hipStream_t s, double** dpsf) 
 }
 
 template <typename T>
-kp_status prep_grids(kp_ctx* c, const kp_blur* b, hipStream_t s, Grids<T>* g) {
-  double* dpsf = nullptr;
-  KP_TRY(upload_psf(c, b, s, &dpsf));
+kp_status build_grids(kp_ctx* c, const kp_blur* b, const double* dpsf, hipStream_t s,
+                      Grids<T>* g) {
   const int n = b->n;
-  g->ldg = ((2 * n - 1) + 3) & ~3;
+  g->ldg = ((2 * n - 1) + 7) & ~7;
   const size_t cnt = (size_t)(2 * n - 1) * g->ldg;
   KP_TRY(wsT(c, std::string("G_") + tname<T>(), cnt, &g->G));
   KP_TRY(wsT(c, std::string("Gt_") + tname<T>(), cnt, &g->Gt));
   launch_build_grid<T>(dpsf, b->pu, b->pv, b->cu, b->cv, n, 0, g->G, g->ldg, s);
   launch_build_grid<T>(dpsf, b->pu, b->pv, b->cu, b->cv, n, 1, g->Gt, g->ldg, s);
   return check_launch(c, "build_grid");
+}
+
+template <typename T>
+kp_status prep_grids(kp_ctx* c, const kp_blur* b, hipStream_t s, Grids<T>* g) {
+  double* dpsf = nullptr;
+  KP_TRY(upload_psf(c, b, s, &dpsf));
+  return build_grids<T>(c, b, dpsf, s, g);
 }
 
 // Tracing: bracket a launch with events when the context profiles.
@@ -215,6 +222,27 @@ kp_status block_product(kp_ctx* c, const Grids<T>& g, int n, int transpose, cons
                          nc, s);
   }
   return check_launch(c, "rmat_block");
+}
+
+// Y = R X with 16-bit inputs (H = __hip_bfloat16 or __half) and FP32 output; X is
+// rounded to H into a workspace copy first.
+template <typename H>
+kp_status block_product16(kp_ctx* c, const Grids<H>& g, int n, int transpose, const float* X,
+                          float* Y, int ncols, hipStream_t s) {
+  BlockPlan bp;
+  if (!plan_block16(n, c->lds_limit, &bp))
+    return set_err(c, KP_E_INVAL, "no 16-bit block-product tiling fits the LDS at this n");
+  const long N = (long)n * n;
+  H* X16 = nullptr;
+  KP_TRY(wsT(c, "x16", (size_t)N * ncols, &X16));
+  launch_to16<H>(X, X16, N * ncols, s);
+  for (int c0 = 0; c0 < ncols; c0 += 32) {
+    const int nc = ncols - c0 < 32 ? ncols - c0 : 32;
+    ProfScope ps(c, s, 3, 2.0 * (double)N * (double)N * nc);
+    launch_rmat_block16<H>(bp, transpose ? g.Gt : g.G, g.ldg, n, X16 + N * c0, N, Y + N * c0, N,
+                           nc, s);
+  }
+  return check_launch(c, "rmat_block16");
 }
 
 template <typename T>
@@ -569,6 +597,11 @@ kp_status egkb_impl(kp_ctx* c, const kp_blur* b, const kp_gkb_opts* o, kp_factor
 // RSVD (Algorithm 2): Y = orth(B F); q times Z = orth(B^T Y), Y = orth(B Z);
 // H^T = B^T Y = Q_h R_h (CGS2 QR), R_h^T = U_r S V_r^T (Jacobi), so
 // H = U_r S (Q_h V_r)^T: U_k = Y U_r[:, :k], V_k = Q_h V_r[:, :k].
+// With KP_BF16 / KP_F16 every product with B runs on the 16-bit kernel (vectors
+// stay FP32). The optional refinement reorthogonalizes V_k once more, forms
+// W = B V_k with the FP32 (FP64) kernel and takes the SVD of W through its CGS2
+// QR: W = Q_w R_w, R_w = U_w S Z^T, so the triplets become (Q_w U_w, S, V_k Z)
+// (one-sided Rayleigh-Ritz on range(V_k)).
 template <typename T>
 kp_status rsvd_impl(kp_ctx* c, const kp_blur* b, const kp_rsvd_opts* o, kp_factors* f,
                     hipStream_t s) {
@@ -577,8 +610,22 @@ kp_status rsvd_impl(kp_ctx* c, const kp_blur* b, const kp_rsvd_opts* o, kp_facto
   const long N = (long)n * n;
   const int k = o->k;
   const int kp = o->k + o->p;
+  const kp_prec pp = o->prec;
+  double* dpsf = nullptr;
+  KP_TRY(upload_psf(c, b, s, &dpsf));
   Grids<T> g;
-  KP_TRY(prep_grids<T>(c, b, s, &g));
+  KP_TRY(build_grids<T>(c, b, dpsf, s, &g));
+  Grids<__hip_bfloat16> gb;
+  Grids<__half> gh;
+  if (pp == KP_BF16) KP_TRY(build_grids<__hip_bfloat16>(c, b, dpsf, s, &gb));
+  if (pp == KP_F16) KP_TRY(build_grids<__half>(c, b, dpsf, s, &gh));
+  auto prod = [&](int tr, const T* X, T* Yo, int nc) -> kp_status {
+    if constexpr (std::is_same<T, float>::value) {
+      if (pp == KP_BF16) return block_product16<__hip_bfloat16>(c, gb, n, tr, X, Yo, nc, s);
+      if (pp == KP_F16) return block_product16<__half>(c, gh, n, tr, X, Yo, nc, s);
+    }
+    return block_product<T>(c, g, n, tr, X, Yo, nc, s);
+  };
   Scratch sc;
   KP_TRY(get_scratch(c, &sc));
   T *Y = nullptr, *Z = nullptr;
@@ -591,15 +638,17 @@ kp_status rsvd_impl(kp_ctx* c, const kp_blur* b, const kp_rsvd_opts* o, kp_facto
       launch_philox_normals<T>(Z + N * col, N, o->seed, 0x40000000u + (uint32_t)col, s);
   }
   uint32_t sb = 0x20000000u;   // Philox streams of replaced dependent columns
-  KP_TRY(block_product<T>(c, g, n, 0, Z, Y, kp, s));
+  KP_TRY(prod(0, Z, Y, kp));
   KP_TRY(cgs_qr<T>(c, sc, Y, N, kp, nullptr, o->seed, sb, s));
   for (int it = 0; it < o->q; ++it) {
-    KP_TRY(block_product<T>(c, g, n, 1, Y, Z, kp, s));
+    KP_TRY(prod(1, Y, Z, kp));
     KP_TRY(cgs_qr<T>(c, sc, Z, N, kp, nullptr, o->seed, sb += 64, s));
-    KP_TRY(block_product<T>(c, g, n, 0, Z, Y, kp, s));
+    KP_TRY(prod(0, Z, Y, kp));
     KP_TRY(cgs_qr<T>(c, sc, Y, N, kp, nullptr, o->seed, sb += 64, s));
   }
-  KP_TRY(block_product<T>(c, g, n, 1, Y, Z, kp, s));   // H^T
+  if (f->diag && f->diag->basis_u)
+    KP_HIP(c, hipMemcpyAsync(f->diag->basis_u, Y, sizeof(T) * N * kp, hipMemcpyDeviceToDevice, s));
+  KP_TRY(prod(1, Y, Z, kp));   // H^T
   double *Rh, *RhT, *Ur, *sig, *Vr;
   int* sweeps;
   KP_TRY(wsT(c, "smallR", 64 * 64, &Rh));
@@ -619,10 +668,20 @@ kp_status rsvd_impl(kp_ctx* c, const kp_blur* b, const kp_rsvd_opts* o, kp_facto
   launch_small_gemm<T, double>(Y, N, kp, Ur, kp, kout, N, Ud, N, s);
   launch_small_gemm<T, double>(Z, N, kp, Vr, kp, kout, N, Vd, N, s);
   KP_TRY(check_launch(c, "small_gemm"));
+  if (o->refine) {
+    T* Vf = Y;   // N x kout, reuses the sketch buffers
+    T* W = Z;
+    launch_convert<double, T>(Vd, Vf, N * kout, s);
+    KP_TRY(cgs_qr<T>(c, sc, Vf, N, kout, nullptr, o->seed, sb += 64, s));
+    KP_TRY(block_product<T>(c, g, n, 0, Vf, W, kout, s));
+    KP_TRY(cgs_qr<T>(c, sc, W, N, kout, Rh, o->seed, sb += 64, s));
+    launch_jacobi_svd(Rh, kout, kout, Ur, sig, Vr, sweeps, s);
+    launch_small_gemm<T, double>(W, N, kout, Ur, kout, kout, N, Ud, N, s);
+    launch_small_gemm<T, double>(Vf, N, kout, Vr, kout, kout, N, Vd, N, s);
+    KP_TRY(check_launch(c, "refine"));
+  }
   KP_TRY(write_factors(c, Ud, Vd, sig, n, kout, f, s));
   KP_HIP(c, hipMemcpyAsync(c->pinned, sig, sizeof(double) * kout, hipMemcpyDeviceToHost, s));
-  if (f->diag && f->diag->basis_u)
-    KP_HIP(c, hipMemcpyAsync(f->diag->basis_u, Y, sizeof(T) * N * kp, hipMemcpyDeviceToDevice, s));
   KP_HIP(c, hipStreamSynchronize(s));
   for (int i = 0; i < kout; ++i) f->sigma[i] = c->pinned[i];
   f->k = kout;
@@ -829,7 +888,7 @@ kp_status kp_prof_read(kp_ctx* c, kp_prof* out, int reset) {
     (void)hipEventDestroy(r.b);
   }
   c->recs.clear();
-  for (int i = 0; i < 3; ++i) {
+  for (int i = 0; i < 4; ++i) {
     out->ms[i] = c->acc_ms[i];
     out->launches[i] = c->acc_n[i];
     out->flops[i] = c->acc_flops[i];
@@ -866,6 +925,18 @@ kp_status kp_rmat_apply(kp_ctx* c, const kp_blur* b, int transpose, kp_prec prec
       return gemv_product<double>(c, g, n, transpose, (const double*)X, (double*)Y, nullptr,
                                   0.0, s);
     return block_product<double>(c, g, n, transpose, (const double*)X, (double*)Y, ncols, s);
+  }
+  if (prec == KP_BF16 || prec == KP_F16) {
+    double* dpsf = nullptr;
+    KP_TRY(upload_psf(c, b, s, &dpsf));
+    if (prec == KP_BF16) {
+      Grids<__hip_bfloat16> g;
+      KP_TRY(build_grids<__hip_bfloat16>(c, b, dpsf, s, &g));
+      return block_product16<__hip_bfloat16>(c, g, n, transpose, (const float*)X, (float*)Y, ncols, s);
+    }
+    Grids<__half> g;
+    KP_TRY(build_grids<__half>(c, b, dpsf, s, &g));
+    return block_product16<__half>(c, g, n, transpose, (const float*)X, (float*)Y, ncols, s);
   }
   return set_err(c, KP_E_INVAL, "precision not supported by kp_rmat_apply");
 }
@@ -908,9 +979,11 @@ kp_status kp_svd_rsvd(kp_ctx* c, const kp_blur* b, const kp_rsvd_opts* o, kp_fac
       if (!std::isfinite(o->F[e])) return set_err(c, KP_E_NUMERIC, "F has a non-finite entry");
   KP_HIP(c, hipSetDevice(c->device));
   hipStream_t s = (hipStream_t)stream;
-  if (o->prec == KP_F32) return rsvd_impl<float>(c, b, o, f, s);
+  if (o->refine != 0 && o->refine != 1) return set_err(c, KP_E_INVAL, "refine must be 0 or 1");
+  if (o->prec == KP_F32 || o->prec == KP_BF16 || o->prec == KP_F16)
+    return rsvd_impl<float>(c, b, o, f, s);
   if (o->prec == KP_F64) return rsvd_impl<double>(c, b, o, f, s);
-  return set_err(c, KP_E_INVAL, "RSVD precision not supported yet");
+  return set_err(c, KP_E_INVAL, "unknown RSVD precision");
 }
 
 kp_status kp_apply(kp_ctx* c, const kp_factors* f, int transpose, const double* X, double* Y,

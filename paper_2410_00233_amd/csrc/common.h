@@ -38,12 +38,14 @@ template <typename T>
 void launch_rmat_block(const BlockPlan& plan, const T* G, int ldg, int n, const T* X,
                        long ldx, T* Y, long ldy, int ncols, hipStream_t s);
 
-// 16-bit-input variant: X (float) and the 16-bit grid; FP32 accumulate.
+// 16-bit-input variant (H = __hip_bfloat16 or __half): 16-bit grid and X,
+// FP32 accumulation, FP32 output. launch_to16 rounds an FP32 block to H.
 bool plan_block16(int n, size_t lds_limit, BlockPlan* plan);
 template <typename H>
-void launch_rmat_block16(const BlockPlan& plan, const H* G16, int ldg, int n,
-                         const float* X, long ldx, float* Y, long ldy, int ncols,
-                         hipStream_t s);
+void launch_rmat_block16(const BlockPlan& plan, const H* G16, int ldg, int n, const H* X16,
+                         long ldx, float* Y, long ldy, int ncols, hipStream_t s);
+template <typename H>
+void launch_to16(const float* in, H* out, long N, hipStream_t s);
 
 template <typename T>
 bool plan_gemv(int n, size_t lds_limit, BlockPlan* plan);

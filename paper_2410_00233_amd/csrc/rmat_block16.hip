@@ -1,0 +1,248 @@
+// Generated-tile block product Y = R X with 16-bit inputs (BF16 or FP16) and
+// FP32 accumulation on v_mfma_f32_16x16x32_{bf16,f16}: the reduced-precision
+// mode of the block products (precision subsystem; accuracy is won back by the
+// Rayleigh-Ritz refinement in the RSVD driver).
+//
+// Layout as in the FP32 kernel: a workgroup owns 16 rows i in each of TJ row
+// blocks j and keeps the 16 + TJ - 1 grid rows they touch in LDS (16-bit). The
+// MFMA takes 8 consecutive K entries per lane (A lane l: row l%16,
+// k = 8*(l/16) + 0..7; B lane l: column l%16, same k; D lane l item e: row
+// 4*(l/16) + e, column l%16 -- checked on gfx950). To read those 8 entries as
+// one aligned 16-byte LDS load, the K range of column block c is shifted to
+// r in [r0_c, r0_c + LEN) with r0_c = -((n - 1 - c) mod 8): its first slab
+// column r0_c - c + n - 1 is then a multiple of 8. Entries with r outside
+// [0, n) are staged as 0 (LEN = n + 7 rounded up to 32: at most 39 extra
+// zero products per column block). X arrives already converted to 16 bits.
+#include "common.h"
+
+namespace kpsb {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+
+template <typename H> struct Mfma16;
+template <> struct Mfma16<__hip_bfloat16> {
+  typedef bf16x8 vec;
+  static __device__ __forceinline__ floatx4 mma(vec a, vec b, floatx4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+  }
+};
+template <> struct Mfma16<__half> {
+  typedef f16x8 vec;
+  static __device__ __forceinline__ floatx4 mma(vec a, vec b, floatx4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+  }
+};
+
+constexpr int kTK16 = 32;   // K entries per staged tile (= one MFMA K step)
+constexpr int kXS16 = 40;   // LDS row stride of the staged X tile (16-bit elements)
+
+template <typename H, int TJ, int JB, int CB>
+__global__ void __launch_bounds__(64 * (2 * TJ) / (JB * CB))
+rmat_block16_kernel(const H* __restrict__ G, int ldg, int n, const H* __restrict__ X, long ldx,
+                    float* __restrict__ Y, long ldy, int ncols, int SW, int LEN) {
+  constexpr int WAVES = (2 * TJ) / (JB * CB);
+  constexpr int NT = 64 * WAVES;
+  constexpr int SR = 16 + TJ - 1;
+  constexpr int WC = 2 / CB;
+  constexpr int LPT = (kTK16 * 32 + NT - 1) / NT;
+  typedef typename Mfma16<H>::vec vec;
+  typedef unsigned short u16;
+
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  u16* slab = reinterpret_cast<u16*>(lds_raw);
+  u16* xbuf = slab + SR * SW;                       // 2 x 32 columns x kXS16
+  const u16* Gb = reinterpret_cast<const u16*>(G);
+  const u16* Xb = reinterpret_cast<const u16*>(X);
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int n_it = (n + 15) >> 4;
+  const int it = blockIdx.x % n_it;
+  const int jt = blockIdx.x / n_it;
+  const int i0 = it * 16;
+  const int j0 = jt * TJ;
+  const int g2 = 2 * n - 1;
+  const int a0 = i0 - j0 - (TJ - 1) + n - 1;
+
+  for (int al = 0; al < SR; ++al) {
+    const int a = a0 + al;
+    const bool rowok = (a >= 0) && (a < g2);
+    const u16* src = Gb + (long)(rowok ? a : 0) * ldg;
+    for (int col = tid; col < SW; col += NT) {
+      u16 v = 0;
+      if (rowok && col < g2) v = src[col];
+      slab[al * SW + col] = v;
+    }
+  }
+
+  const int ntc = LEN / kTK16;                 // tiles per column block c
+  const int total = n * ntc;
+  u16 stage[LPT];
+  auto load_tile = [&](int t) {
+    const int c = t / ntc;
+    const int r0 = -((n - 1 - c) & 7) + (t - c * ntc) * kTK16;
+#pragma unroll
+    for (int m = 0; m < LPT; ++m) {
+      const int e = tid + NT * m;
+      const int kk = e % kTK16;
+      const int col = e / kTK16;
+      const int r = r0 + kk;
+      u16 v = 0;
+      if (e < kTK16 * 32 && r >= 0 && r < n && col < ncols) v = Xb[(long)col * ldx + (long)n * c + r];
+      stage[m] = v;
+    }
+  };
+  auto store_tile = [&](int buf) {
+    u16* xs = xbuf + buf * (32 * kXS16);
+#pragma unroll
+    for (int m = 0; m < LPT; ++m) {
+      const int e = tid + NT * m;
+      if (e < kTK16 * 32) xs[(e / kTK16) * kXS16 + (e % kTK16)] = stage[m];
+    }
+  };
+
+  floatx4 acc[JB][CB];
+  double accd[JB][CB][4];
+#pragma unroll
+  for (int jb = 0; jb < JB; ++jb)
+#pragma unroll
+    for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        acc[jb][cb][e] = 0.f;
+        accd[jb][cb][e] = 0.0;
+      }
+
+  const int wc = wave % WC;
+  const int wj = wave / WC;
+  const int lrow = lane & 15;
+  const int lg = lane >> 4;                    // k group: entries 8*lg .. 8*lg + 7
+  int arow[JB];
+#pragma unroll
+  for (int jb = 0; jb < JB; ++jb) arow[jb] = (lrow + (TJ - 1) - (wj * JB + jb)) * SW;
+
+  load_tile(0);
+  store_tile(0);
+  __syncthreads();
+
+  for (int t = 0; t < total; ++t) {
+    if (t + 1 < total) load_tile(t + 1);
+    const int c = t / ntc;
+    const int tt = t - c * ntc;
+    const int colbase = -((n - 1 - c) & 7) - c + n - 1 + tt * kTK16;   // multiple of 8
+    const u16* xs = xbuf + (t & 1) * (32 * kXS16);
+    vec bfr[CB];
+#pragma unroll
+    for (int cb = 0; cb < CB; ++cb)
+      bfr[cb] = *reinterpret_cast<const vec*>(xs + ((wc * CB + cb) * 16 + lrow) * kXS16 + 8 * lg);
+#pragma unroll
+    for (int jb = 0; jb < JB; ++jb) {
+      const vec afr = *reinterpret_cast<const vec*>(slab + arow[jb] + colbase + 8 * lg);
+#pragma unroll
+      for (int cb = 0; cb < CB; ++cb) acc[jb][cb] = Mfma16<H>::mma(afr, bfr[cb], acc[jb][cb]);
+    }
+    if (tt == ntc - 1) {
+#pragma unroll
+      for (int jb = 0; jb < JB; ++jb)
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            accd[jb][cb][e] += (double)acc[jb][cb][e];
+            acc[jb][cb][e] = 0.f;
+          }
+    }
+    if (t + 1 < total) store_tile((t + 1) & 1);
+    __syncthreads();
+  }
+
+#pragma unroll
+  for (int jb = 0; jb < JB; ++jb) {
+    const int j = j0 + wj * JB + jb;
+#pragma unroll
+    for (int cb = 0; cb < CB; ++cb) {
+      const int col = (wc * CB + cb) * 16 + lrow;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int i = i0 + 4 * lg + e;
+        if (i < n && j < n && col < ncols) Y[(long)col * ldy + i + (long)n * j] = (float)accd[jb][cb][e];
+      }
+    }
+  }
+}
+
+static int len16(int n) { return ((n + 7 + kTK16 - 1) / kTK16) * kTK16; }
+
+static int stride16(int n) {
+  const int W = n + len16(n) - 1;          // largest slab column + 1
+  return ((W + 63) / 64) * 64 + 8;         // multiple of 8 (16-byte rows)
+}
+
+static size_t lds16(int n, int TJ) {
+  return 2 * ((size_t)(16 + TJ - 1) * stride16(n) + 2 * 32 * kXS16);
+}
+
+bool plan_block16(int n, size_t lds_limit, BlockPlan* plan) {
+  static const int cand[] = {32, 16, 8, 4};
+  int forced = 0;
+  if (const char* e = getenv("KPSB_BLOCK16_TJ")) forced = atoi(e);
+  for (int TJ : cand) {
+    if (forced && TJ != forced) continue;
+    size_t lds = lds16(n, TJ);
+    if (lds <= lds_limit) {
+      plan->TJ = TJ;
+      plan->SW = stride16(n);
+      plan->lds = lds;
+      plan->grid = ((n + 15) / 16) * ((n + TJ - 1) / TJ);
+      return true;
+    }
+  }
+  return false;
+}
+
+template <typename H, int TJ, int JB, int CB>
+static void launch16_tj(const BlockPlan& p, const H* G, int ldg, int n, const H* X, long ldx,
+                        float* Y, long ldy, int ncols, hipStream_t s) {
+  auto kern = rmat_block16_kernel<H, TJ, JB, CB>;
+  constexpr int threads = 64 * (2 * TJ) / (JB * CB);
+  if (p.lds > 65536)
+    (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)p.lds);
+  hipLaunchKernelGGL(kern, dim3(p.grid), dim3(threads), p.lds, s, G, ldg, n, X, ldx, Y, ldy,
+                     ncols, p.SW, len16(n));
+}
+
+template <typename H>
+void launch_rmat_block16(const BlockPlan& p, const H* G16, int ldg, int n, const H* X16,
+                         long ldx, float* Y, long ldy, int ncols, hipStream_t s) {
+  switch (p.TJ) {
+    case 32: launch16_tj<H, 32, 4, 2>(p, G16, ldg, n, X16, ldx, Y, ldy, ncols, s); break;
+    case 16: launch16_tj<H, 16, 4, 2>(p, G16, ldg, n, X16, ldx, Y, ldy, ncols, s); break;
+    case 8: launch16_tj<H, 8, 2, 2>(p, G16, ldg, n, X16, ldx, Y, ldy, ncols, s); break;
+    default: launch16_tj<H, 4, 1, 2>(p, G16, ldg, n, X16, ldx, Y, ldy, ncols, s); break;
+  }
+}
+template void launch_rmat_block16<__hip_bfloat16>(const BlockPlan&, const __hip_bfloat16*, int,
+                                                  int, const __hip_bfloat16*, long, float*,
+                                                  long, int, hipStream_t);
+template void launch_rmat_block16<__half>(const BlockPlan&, const __half*, int, int,
+                                          const __half*, long, float*, long, int, hipStream_t);
+
+// FP32 -> 16-bit conversion of a block of vectors (round to nearest even)
+__device__ __forceinline__ void cvt16(float v, __hip_bfloat16* o) { *o = __float2bfloat16(v); }
+__device__ __forceinline__ void cvt16(float v, __half* o) { *o = __float2half(v); }
+template <typename H>
+__global__ void to16_kernel(const float* __restrict__ in, H* __restrict__ out, long N) {
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < N; e += (long)gridDim.x * blockDim.x)
+    cvt16(in[e], out + e);
+}
+template <typename H>
+void launch_to16(const float* in, H* out, long N, hipStream_t s) {
+  hipLaunchKernelGGL(to16_kernel<H>, dim3(2048), dim3(256), 0, s, in, out, N);
+}
+template void launch_to16<__hip_bfloat16>(const float*, __hip_bfloat16*, long, hipStream_t);
+template void launch_to16<__half>(const float*, __half*, long, hipStream_t);
+
+}  // namespace kpsb

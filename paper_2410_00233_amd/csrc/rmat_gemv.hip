@@ -104,18 +104,18 @@ rmat_gemv_kernel(const T* __restrict__ G, int ldg, int n, const T* __restrict__ 
 // the staged x are then read as aligned float4 (0.5 LDS reads per FMA). Entries
 // with r outside [0, n) are staged as 0. Products of one c (LEN terms) are summed
 // in FP32 and added into an FP64 accumulator.
-template <int TJ>
-__global__ void __launch_bounds__(256)
+template <int TJ, int NT>
+__global__ void __launch_bounds__(NT)
 rmat_gemv4_kernel(const float* __restrict__ G, int ldg, int n, const float* __restrict__ x,
                   float* __restrict__ y, const float* __restrict__ z, double coef, int SW,
                   int LEN) {
   constexpr int SR = 16 + TJ - 1;
   constexpr int ROWS = 16 * TJ;
-  constexpr int H = 256 / ROWS;
+  constexpr int H = NT / ROWS;
   extern __shared__ __align__(16) unsigned char lds_raw[];
   float* slab = reinterpret_cast<float*>(lds_raw);
   float* xbuf = slab + SR * SW;                // 2 x LEN
-  __shared__ double red[256];
+  double* red = reinterpret_cast<double*>(xbuf + 2 * LEN);   // NT (H > 1)
 
   const int tid = threadIdx.x;
   const int n_it = (n + 15) >> 4;
@@ -130,7 +130,7 @@ rmat_gemv4_kernel(const float* __restrict__ G, int ldg, int n, const float* __re
     const int a = a0 + al;
     const bool rowok = (a >= 0) && (a < g2);
     const float* src = G + (long)(rowok ? a : 0) * ldg;
-    for (int col = tid; col < SW; col += 256) {
+    for (int col = tid; col < SW; col += NT) {
       float v = 0.f;
       if (rowok && col < g2) v = src[col];
       slab[al * SW + col] = v;
@@ -143,13 +143,13 @@ rmat_gemv4_kernel(const float* __restrict__ G, int ldg, int n, const float* __re
   const int jg = rr >> 4;
   const float* arow = slab + (li + (TJ - 1) - jg) * SW;
   const int nv = LEN >> 2;                 // float4 per column block
-  constexpr int MAXL = 8;                  // staged x entries per thread (LEN <= 2048)
+  constexpr int MAXL = (2048 + NT - 1) / NT;   // staged x entries per thread (LEN <= 2048)
   float st[MAXL];
   auto load = [&](int c) {
     const int r0 = -((n - 1 - c) & 3);
 #pragma unroll
     for (int m = 0; m < MAXL; ++m) {
-      const int kk = tid + 256 * m;
+      const int kk = tid + NT * m;
       const int r = r0 + kk;
       st[m] = (kk < LEN && r >= 0 && r < n) ? x[(long)n * c + r] : 0.f;
     }
@@ -158,7 +158,7 @@ rmat_gemv4_kernel(const float* __restrict__ G, int ldg, int n, const float* __re
     float* xs = xbuf + buf * LEN;
 #pragma unroll
     for (int m = 0; m < MAXL; ++m) {
-      const int kk = tid + 256 * m;
+      const int kk = tid + NT * m;
       if (kk < LEN) xs[kk] = st[m];
     }
   };
@@ -219,10 +219,14 @@ static int gemv_stride(int n) {
   return ((W + 31) / 32) * 32 + 1;
 }
 
+constexpr int kGemvNT = 1024;   // threads of the FP32 kernel (H = 1024 / (16 TJ) per row)
+
 template <typename T>
 static size_t gemv_lds(int n, int TJ) {
-  const size_t xs = sizeof(T) == 4 ? 2 * (size_t)gemv4_len(n) : 2 * (size_t)kTKV;
-  return sizeof(T) * ((size_t)(16 + TJ - 1) * gemv_stride<T>(n) + xs);
+  if (sizeof(T) == 4)
+    return 4 * ((size_t)(16 + TJ - 1) * gemv_stride<T>(n) + 2 * (size_t)gemv4_len(n)) +
+           8 * (size_t)kGemvNT;
+  return sizeof(T) * ((size_t)(16 + TJ - 1) * gemv_stride<T>(n) + 2 * (size_t)kTKV);
 }
 
 template <typename T>
@@ -231,7 +235,7 @@ bool plan_gemv(int n, size_t lds_limit, BlockPlan* plan) {
   int forced = 0;
   if (const char* e = getenv("KPSB_GEMV_TJ")) forced = atoi(e);
   if (sizeof(T) == 4 && gemv4_len(n) > 2048) return false;   // staged x per thread
-  // the static reduction buffer (2 KB) shares the LDS budget
+  // the FP64 kernel's static reduction buffer (2 KB) shares the LDS budget
   size_t limit = lds_limit > 4096 ? lds_limit - 4096 : 0;
   for (int TJ : cand) {
     if (forced && TJ != forced) continue;
@@ -262,12 +266,12 @@ static void gemv_tj(const BlockPlan& p, const T* G, int ldg, int n, const T* x, 
 template <int TJ>
 static void gemv4_tj(const BlockPlan& p, const float* G, int ldg, int n, const float* x,
                      float* y, const float* z, double coef, hipStream_t s) {
-  auto kern = rmat_gemv4_kernel<TJ>;
+  auto kern = rmat_gemv4_kernel<TJ, kGemvNT>;
   if (p.lds > 65536)
     (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)p.lds);
-  hipLaunchKernelGGL(kern, dim3(p.grid), dim3(256), p.lds, s, G, ldg, n, x, y, z, coef, p.SW,
-                     gemv4_len(n));
+  hipLaunchKernelGGL(kern, dim3(p.grid), dim3(kGemvNT), p.lds, s, G, ldg, n, x, y, z, coef,
+                     p.SW, gemv4_len(n));
 }
 
 template <>

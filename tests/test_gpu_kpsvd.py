@@ -171,3 +171,31 @@ def test_auto_k_matches_oracle_index(ctx):
     ref = kpsvd.egkb(R, Rt, y, 20, 4, auto_k=True, k_min=2, force_breakdown=_force(f))
     assert f.k == ref["k"] and f.diag.kp == ref["kp"]
     assert np.abs(f.sigma[:f.k] - ref["sigma"]).max() <= 1e-12 * ref["sigma"][0]
+
+
+@pytest.mark.parametrize("prec", ["bf16", "f16", "f32"])
+@pytest.mark.parametrize("n,psf", [(128, "speckle"), (512, "gaussian")])
+def test_rsvd_reduced_precision_with_refine(ctx, prec, n, psf):
+    """16-bit block products + second reorthogonalization + Rayleigh-Ritz
+    refinement vs the oracle's RSVD followed by the same refinement:
+    sigma within 1e-4 sigma_1 (normwise)."""
+    from paper_2410_00233_amd import api
+    k, p, q = 20, 10, 2
+    P, cu, cv = wl.gaussian_psf(n) if psf == "gaussian" else wl.speckle_psf(n, seed=1002)
+    F = wl.gaussian_block(n * n, k + p, seed=wl.SEED_START + 2)
+    blur = api.Blur(P, cu, cv, n)
+    R, Rt = _ops(P, cu, cv, n)
+    ref = kpsvd.rsvd(R, Rt, F, k, q)
+    ref_r = kpsvd.refine(R, ref["V"])
+    s1 = ref["sigma"][0]
+    raw = ctx.kp_svd_rsvd(blur, k, p, q, prec=prec, F=F)
+    f = ctx.kp_svd_rsvd(blur, k, p, q, prec=prec, F=F, refine=True)
+    e_raw = np.abs(raw.sigma[:k] - ref["sigma"]).max() / s1
+    e_ref = np.abs(f.sigma[:k] - ref_r["sigma"]).max() / s1
+    s, U, V, _, _ = _uv_from_factors(f)
+    e_kp = metrics.kp_rel_error(P, cu, cv, n, s, U, V)
+    e_kp_ref = metrics.kp_rel_error(P, cu, cv, n, ref_r["sigma"], ref_r["U"], ref_r["V"])
+    print(f"RSVD {prec} n={n} {psf}: unrefined {e_raw:.2e}, refined {e_ref:.2e} (sigma err / s1); "
+          f"||A-A_k||/||A|| {e_kp:.3e} vs oracle {e_kp_ref:.3e}")
+    assert e_ref <= 1e-4
+    assert e_kp <= e_kp_ref + 1e-4

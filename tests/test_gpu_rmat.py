@@ -22,7 +22,7 @@ def _run(ctx, P, cu, cv, n, X, transpose, prec):
     (b, n^2) row-major tensor."""
     import torch
     from paper_2410_00233_amd import api
-    dt = torch.float64 if prec == "f64" else torch.float32
+    dt = torch.float64 if prec == "f64" else torch.float32   # 16-bit modes take FP32 X
     Xt = torch.tensor(X if X.ndim == 1 else np.ascontiguousarray(X.T), dtype=dt, device="cuda")
     Y = ctx.kp_rmat_apply(api.Blur(P, cu, cv, n), Xt, transpose=transpose, prec=prec)
     torch.cuda.synchronize()
@@ -80,3 +80,44 @@ def test_product_full_size_sampled_rows(ctx, n, prec, ncols):
         mag = op.rmat_struct_apply(np.abs(P), cu, cv, n, np.abs(X), transpose=tr)
         tol = 1e-12 if prec == "f64" else 2e-6
         assert np.all(np.abs(Y - Ys) <= tol * mag + 0.05 * tol * mag.max())
+
+
+def _round16(a, prec):
+    """Round like the kernel: FP64 -> FP32 -> 16-bit, round to nearest even."""
+    a32 = np.asarray(a, dtype=np.float32)
+    if prec == "f16":
+        return a32.astype(np.float16).astype(np.float64)
+    u = a32.view(np.uint32).astype(np.uint64)
+    u = ((u + (((u >> 16) & 1) + 0x7FFF)) >> 16) << 16
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+@pytest.mark.parametrize("prec", ["bf16", "f16"])
+@pytest.mark.parametrize("n,shape,seed,ncols", [(5, (3, 4), 1, 3), (16, (9, 9), 3, 32),
+                                                (33, (7, 40), 5, 37), (48, (95, 95), 6, 20)])
+def test_product16_matches_rounded_explicit_R(ctx, n, shape, seed, ncols, prec):
+    P, cu, cv = wl.random_psf(shape[0], shape[1], seed)
+    idx = np.arange(n * n)
+    X = np.random.default_rng(seed).standard_normal((n * n, ncols)).astype(np.float32).astype(np.float64)
+    for tr in (False, True):
+        R = op.rmat_entries(P, cu, cv, n, idx, idx)
+        R = R.T if tr else R
+        Y = _run(ctx, P, cu, cv, n, X, tr, prec).reshape(n * n, -1)
+        R16, X16 = _round16(R, prec), _round16(X, prec)
+        ref = R16 @ X16
+        mag = np.abs(R16) @ np.abs(X16)
+        assert np.all(np.abs(Y - ref) <= 2e-6 * mag + 1e-7 * mag.max())
+
+
+@pytest.mark.parametrize("prec", ["bf16", "f16"])
+def test_product16_full_size_sampled_rows(ctx, prec):
+    n = 512
+    P, cu, cv = wl.gaussian_psf(n)
+    X = np.random.default_rng(7).standard_normal((n * n, 30)).astype(np.float32).astype(np.float64)
+    rows = np.unique(np.r_[0, n * n - 1, np.random.default_rng(8).choice(n * n, 16, replace=False)])
+    Y = _run(ctx, P, cu, cv, n, X, False, prec).reshape(n * n, -1)
+    R16 = _round16(op.rmat_entries(P, cu, cv, n, rows, np.arange(n * n)), prec)
+    X16 = _round16(X, prec)
+    ref = R16 @ X16
+    mag = np.abs(R16) @ np.abs(X16)
+    assert np.all(np.abs(Y[rows] - ref) <= 2e-6 * mag + 1e-7 * mag.max())
