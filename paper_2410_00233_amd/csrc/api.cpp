@@ -233,14 +233,15 @@ kp_status block_product16(kp_ctx* c, const Grids<H>& g, int n, int transpose, co
   if (!plan_block16(n, c->lds_limit, &bp))
     return set_err(c, KP_E_INVAL, "no 16-bit block-product tiling fits the LDS at this n");
   const long N = (long)n * n;
+  const long ld16 = x16_column_len(n);
   H* X16 = nullptr;
-  KP_TRY(wsT(c, "x16", (size_t)N * ncols, &X16));
-  launch_to16<H>(X, X16, N * ncols, s);
+  KP_TRY(wsT(c, "x16", (size_t)ld16 * ncols, &X16));
+  launch_to16_shifted<H>(X, N, n, ncols, X16, ld16, s);
   for (int c0 = 0; c0 < ncols; c0 += 32) {
     const int nc = ncols - c0 < 32 ? ncols - c0 : 32;
     ProfScope ps(c, s, 3, 2.0 * (double)N * (double)N * nc);
-    launch_rmat_block16<H>(bp, transpose ? g.Gt : g.G, g.ldg, n, X16 + N * c0, N, Y + N * c0, N,
-                           nc, s);
+    launch_rmat_block16<H>(bp, transpose ? g.Gt : g.G, g.ldg, n, X16 + ld16 * c0, ld16,
+                           Y + N * c0, N, nc, s);
   }
   return check_launch(c, "rmat_block16");
 }

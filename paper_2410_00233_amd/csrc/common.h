@@ -39,13 +39,16 @@ void launch_rmat_block(const BlockPlan& plan, const T* G, int ldg, int n, const 
                        long ldx, T* Y, long ldy, int ncols, hipStream_t s);
 
 // 16-bit-input variant (H = __hip_bfloat16 or __half): 16-bit grid and X,
-// FP32 accumulation, FP32 output. launch_to16 rounds an FP32 block to H.
+// FP32 accumulation, FP32 output. X16 is the pre-shifted 16-bit copy made by
+// launch_to16_shifted, x16_column_len(n) elements per column.
 bool plan_block16(int n, size_t lds_limit, BlockPlan* plan);
 template <typename H>
 void launch_rmat_block16(const BlockPlan& plan, const H* G16, int ldg, int n, const H* X16,
                          long ldx, float* Y, long ldy, int ncols, hipStream_t s);
+long x16_column_len(int n);
 template <typename H>
-void launch_to16(const float* in, H* out, long N, hipStream_t s);
+void launch_to16_shifted(const float* in, long ldx, int n, int ncols, H* out, long ldo,
+                         hipStream_t s);
 
 template <typename T>
 bool plan_gemv(int n, size_t lds_limit, BlockPlan* plan);

@@ -218,27 +218,30 @@ rmat_block_kernel(const T* __restrict__ G, int ldg, int n, const T* __restrict__
   store_tile(0);
   __syncthreads();
 
-  for (int t = 0; t < total; ++t) {
-    if (t + 1 < total) load_tile(t + 1);
-    const int c = t / nrc;
-    const int r0 = (t - c * nrc) * kTK;
-    const int colbase = r0 - c + n - 1;
-    const T* xs = xbuf + (t & 1) * (kTK * kXS);
+  for (int c = 0; c < n; ++c) {
+    for (int rt = 0; rt < nrc; ++rt) {
+      const int t = c * nrc + rt;
+      if (t + 1 < total) load_tile(t + 1);
+      const int colbase = rt * kTK - c + n - 1;
+      const T* xs = xbuf + (t & 1) * (kTK * kXS);
 #pragma unroll
-    for (int s = 0; s < kTK / 4; ++s) {
-      const int kk = 4 * s + lk;
-      T bfr[CB];
+      for (int s = 0; s < kTK / 4; ++s) {
+        const int kk = 4 * s + lk;
+        T bfr[CB];
 #pragma unroll
-      for (int cb = 0; cb < CB; ++cb) bfr[cb] = xs[kk * kXS + (wc * CB + cb) * 16 + lrow];
-      T afr[JB];
+        for (int cb = 0; cb < CB; ++cb) bfr[cb] = xs[kk * kXS + (wc * CB + cb) * 16 + lrow];
+        T afr[JB];
 #pragma unroll
-      for (int jb = 0; jb < JB; ++jb) afr[jb] = slab[arow[jb] + colbase + kk];
+        for (int jb = 0; jb < JB; ++jb) afr[jb] = slab[arow[jb] + colbase + kk];
 #pragma unroll
-      for (int jb = 0; jb < JB; ++jb)
+        for (int jb = 0; jb < JB; ++jb)
 #pragma unroll
-        for (int cb = 0; cb < CB; ++cb) acc[jb][cb] = mfma16x16x4(afr[jb], bfr[cb], acc[jb][cb]);
+          for (int cb = 0; cb < CB; ++cb) acc[jb][cb] = mfma16x16x4(afr[jb], bfr[cb], acc[jb][cb]);
+      }
+      if (t + 1 < total) store_tile((t + 1) & 1);
+      __syncthreads();
     }
-    if (sizeof(T) == 4 && (t - c * nrc) == nrc - 1) {   // end of column block c
+    if (sizeof(T) == 4) {   // end of column block c: fold into the FP64 accumulators
 #pragma unroll
       for (int jb = 0; jb < JB; ++jb)
 #pragma unroll
@@ -249,8 +252,6 @@ rmat_block_kernel(const T* __restrict__ G, int ldg, int n, const T* __restrict__
             acc[jb][cb][e] = (T)0;
           }
     }
-    if (t + 1 < total) store_tile((t + 1) & 1);
-    __syncthreads();
   }
 
   // ---- epilogue -----------------------------------------------------------
@@ -319,9 +320,20 @@ static void launch_tj(const BlockPlan& p, const T* G, int ldg, int n, const T* X
 template <typename T>
 void launch_rmat_block(const BlockPlan& p, const T* G, int ldg, int n, const T* X, long ldx,
                        T* Y, long ldy, int ncols, hipStream_t s) {
+  // waves per workgroup (measured on gfx950 at n = 256 / 512: 16 waves beat 8 and 4,
+  // more waves per SIMD hide the LDS latency of the fragment loads)
+  const int waves = getenv("KPSB_BLOCK_WAVES") ? atoi(getenv("KPSB_BLOCK_WAVES")) : 16;
+  if (p.TJ == 16 && waves == 8) {
+    launch_tj<T, 16, 2, 2>(p, G, ldg, n, X, ldx, Y, ldy, ncols, s);
+    return;
+  }
+  if (p.TJ == 16 && waves == 4) {
+    launch_tj<T, 16, 4, 2>(p, G, ldg, n, X, ldx, Y, ldy, ncols, s);
+    return;
+  }
   switch (p.TJ) {
-    case 16: launch_tj<T, 16, 4, 2>(p, G, ldg, n, X, ldx, Y, ldy, ncols, s); break;
-    case 8: launch_tj<T, 8, 2, 2>(p, G, ldg, n, X, ldx, Y, ldy, ncols, s); break;
+    case 16: launch_tj<T, 16, 1, 2>(p, G, ldg, n, X, ldx, Y, ldy, ncols, s); break;
+    case 8: launch_tj<T, 8, 1, 2>(p, G, ldg, n, X, ldx, Y, ldy, ncols, s); break;
     case 4: launch_tj<T, 4, 1, 2>(p, G, ldg, n, X, ldx, Y, ldy, ncols, s); break;
     case 2: launch_tj<T, 2, 1, 1>(p, G, ldg, n, X, ldx, Y, ldy, ncols, s); break;
     default: launch_tj<T, 1, 1, 1>(p, G, ldg, n, X, ldx, Y, ldy, ncols, s); break;

@@ -34,9 +34,14 @@ template <> struct Mfma16<__half> {
   }
 };
 
-constexpr int kTK16 = 32;   // K entries per staged tile (= one MFMA K step)
-constexpr int kXS16 = 40;   // LDS row stride of the staged X tile (16-bit elements)
+constexpr int kKS = 32;      // K entries per MFMA step
+constexpr int kSPT = 4;      // MFMA K steps per staged tile (one barrier per tile)
+constexpr int kXS16 = kKS * kSPT + 8;   // LDS row stride of the staged X tile (16-bit elements)
 
+// X16 is the pre-shifted 16-bit copy of X (launch_to16_shifted): column `col`,
+// K step ks = c * (LEN/32) + tt holds the 32 entries r0_c + 32 tt + (0..31) of
+// column block c at X16[col * ldx + 32 ks + (0..31)], zero outside [0, n). A tile
+// is kSPT consecutive K steps (it may span two column blocks).
 template <typename H, int TJ, int JB, int CB>
 __global__ void __launch_bounds__(64 * (2 * TJ) / (JB * CB))
 rmat_block16_kernel(const H* __restrict__ G, int ldg, int n, const H* __restrict__ X, long ldx,
@@ -45,7 +50,9 @@ rmat_block16_kernel(const H* __restrict__ G, int ldg, int n, const H* __restrict
   constexpr int NT = 64 * WAVES;
   constexpr int SR = 16 + TJ - 1;
   constexpr int WC = 2 / CB;
-  constexpr int LPT = (kTK16 * 32 + NT - 1) / NT;
+  constexpr int TILE = kKS * kSPT;                    // 128 K entries
+  constexpr int V8 = TILE * 32 / 8;                   // 16-byte chunks per tile (512)
+  constexpr int LPT = (V8 + NT - 1) / NT;
   typedef typename Mfma16<H>::vec vec;
   typedef unsigned short u16;
 
@@ -53,7 +60,6 @@ rmat_block16_kernel(const H* __restrict__ G, int ldg, int n, const H* __restrict
   u16* slab = reinterpret_cast<u16*>(lds_raw);
   u16* xbuf = slab + SR * SW;                       // 2 x 32 columns x kXS16
   const u16* Gb = reinterpret_cast<const u16*>(G);
-  const u16* Xb = reinterpret_cast<const u16*>(X);
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -77,20 +83,20 @@ rmat_block16_kernel(const H* __restrict__ G, int ldg, int n, const H* __restrict
     }
   }
 
-  const int ntc = LEN / kTK16;                 // tiles per column block c
-  const int total = n * ntc;
-  u16 stage[LPT];
+  const int ntc = LEN / kKS;                   // K steps per column block
+  const int total_ks = n * ntc;
+  const int ntiles = (total_ks + kSPT - 1) / kSPT;
+  const long xlen = (long)total_ks * kKS;      // valid entries per column of X16
+  uint4 stage[LPT];
   auto load_tile = [&](int t) {
-    const int c = t / ntc;
-    const int r0 = -((n - 1 - c) & 7) + (t - c * ntc) * kTK16;
 #pragma unroll
     for (int m = 0; m < LPT; ++m) {
-      const int e = tid + NT * m;
-      const int kk = e % kTK16;
-      const int col = e / kTK16;
-      const int r = r0 + kk;
-      u16 v = 0;
-      if (e < kTK16 * 32 && r >= 0 && r < n && col < ncols) v = Xb[(long)col * ldx + (long)n * c + r];
+      const int e = tid + NT * m;              // 16-byte chunk: column e / 16, part e % 16
+      const int col = e >> 4;
+      const long off = (long)t * TILE + (e & 15) * 8;
+      uint4 v = make_uint4(0, 0, 0, 0);
+      if (e < V8 && col < ncols && off < xlen)
+        v = *reinterpret_cast<const uint4*>(reinterpret_cast<const u16*>(X) + (long)col * ldx + off);
       stage[m] = v;
     }
   };
@@ -99,7 +105,7 @@ rmat_block16_kernel(const H* __restrict__ G, int ldg, int n, const H* __restrict
 #pragma unroll
     for (int m = 0; m < LPT; ++m) {
       const int e = tid + NT * m;
-      if (e < kTK16 * 32) xs[(e / kTK16) * kXS16 + (e % kTK16)] = stage[m];
+      if (e < V8) *reinterpret_cast<uint4*>(xs + (e >> 4) * kXS16 + (e & 15) * 8) = stage[m];
     }
   };
 
@@ -127,34 +133,41 @@ rmat_block16_kernel(const H* __restrict__ G, int ldg, int n, const H* __restrict
   store_tile(0);
   __syncthreads();
 
-  for (int t = 0; t < total; ++t) {
-    if (t + 1 < total) load_tile(t + 1);
-    const int c = t / ntc;
-    const int tt = t - c * ntc;
-    const int colbase = -((n - 1 - c) & 7) - c + n - 1 + tt * kTK16;   // multiple of 8
+  for (int t = 0; t < ntiles; ++t) {
+    if (t + 1 < ntiles) load_tile(t + 1);
     const u16* xs = xbuf + (t & 1) * (32 * kXS16);
-    vec bfr[CB];
 #pragma unroll
-    for (int cb = 0; cb < CB; ++cb)
-      bfr[cb] = *reinterpret_cast<const vec*>(xs + ((wc * CB + cb) * 16 + lrow) * kXS16 + 8 * lg);
-#pragma unroll
-    for (int jb = 0; jb < JB; ++jb) {
-      const vec afr = *reinterpret_cast<const vec*>(slab + arow[jb] + colbase + 8 * lg);
-#pragma unroll
-      for (int cb = 0; cb < CB; ++cb) acc[jb][cb] = Mfma16<H>::mma(afr, bfr[cb], acc[jb][cb]);
-    }
-    if (tt == ntc - 1) {
-#pragma unroll
-      for (int jb = 0; jb < JB; ++jb)
+    for (int s = 0; s < kSPT; ++s) {
+      const int ks = t * kSPT + s;
+      if (ks < total_ks) {
+        const int c = ks / ntc;
+        const int tt = ks - c * ntc;
+        const int colbase = -((n - 1 - c) & 7) - c + n - 1 + tt * kKS;   // multiple of 8
+        vec bfr[CB];
 #pragma unroll
         for (int cb = 0; cb < CB; ++cb)
+          bfr[cb] = *reinterpret_cast<const vec*>(xs + ((wc * CB + cb) * 16 + lrow) * kXS16 +
+                                                  s * kKS + 8 * lg);
 #pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            accd[jb][cb][e] += (double)acc[jb][cb][e];
-            acc[jb][cb][e] = 0.f;
-          }
+        for (int jb = 0; jb < JB; ++jb) {
+          const vec afr = *reinterpret_cast<const vec*>(slab + arow[jb] + colbase + 8 * lg);
+#pragma unroll
+          for (int cb = 0; cb < CB; ++cb) acc[jb][cb] = Mfma16<H>::mma(afr, bfr[cb], acc[jb][cb]);
+        }
+        if (tt == ntc - 1) {       // end of column block c
+#pragma unroll
+          for (int jb = 0; jb < JB; ++jb)
+#pragma unroll
+            for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+              for (int e = 0; e < 4; ++e) {
+                accd[jb][cb][e] += (double)acc[jb][cb][e];
+                acc[jb][cb][e] = 0.f;
+              }
+        }
+      }
     }
-    if (t + 1 < total) store_tile((t + 1) & 1);
+    if (t + 1 < ntiles) store_tile((t + 1) & 1);
     __syncthreads();
   }
 
@@ -173,7 +186,7 @@ rmat_block16_kernel(const H* __restrict__ G, int ldg, int n, const H* __restrict
   }
 }
 
-static int len16(int n) { return ((n + 7 + kTK16 - 1) / kTK16) * kTK16; }
+static int len16(int n) { return ((n + 7 + kKS - 1) / kKS) * kKS; }
 
 static int stride16(int n) {
   const int W = n + len16(n) - 1;          // largest slab column + 1
@@ -182,6 +195,14 @@ static int stride16(int n) {
 
 static size_t lds16(int n, int TJ) {
   return 2 * ((size_t)(16 + TJ - 1) * stride16(n) + 2 * 32 * kXS16);
+}
+
+// Length (16-bit elements) of one column of the pre-shifted X16 copy, padded to
+// whole tiles so that tile loads never leave the buffer.
+long x16_column_len(int n) {
+  const long total = (long)n * len16(n);
+  const long tile = kKS * kSPT;
+  return ((total + tile - 1) / tile) * tile;
 }
 
 bool plan_block16(int n, size_t lds_limit, BlockPlan* plan) {
@@ -230,19 +251,37 @@ template void launch_rmat_block16<__hip_bfloat16>(const BlockPlan&, const __hip_
 template void launch_rmat_block16<__half>(const BlockPlan&, const __half*, int, int,
                                           const __half*, long, float*, long, int, hipStream_t);
 
-// FP32 -> 16-bit conversion of a block of vectors (round to nearest even)
+// FP32 X (N x ncols, ld ldx) -> pre-shifted 16-bit copy (see rmat_block16_kernel):
+// out[col * ldo + c * LEN + kk] = X[col * ldx + c * n + r0_c + kk] for
+// 0 <= r0_c + kk < n, else 0; r0_c = -((n - 1 - c) mod 8). Round to nearest even.
 __device__ __forceinline__ void cvt16(float v, __hip_bfloat16* o) { *o = __float2bfloat16(v); }
 __device__ __forceinline__ void cvt16(float v, __half* o) { *o = __float2half(v); }
 template <typename H>
-__global__ void to16_kernel(const float* __restrict__ in, H* __restrict__ out, long N) {
-  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < N; e += (long)gridDim.x * blockDim.x)
-    cvt16(in[e], out + e);
+__global__ void to16_shifted_kernel(const float* __restrict__ in, long ldx, int n, int ncols,
+                                    int LEN, H* __restrict__ out, long ldo) {
+  const long per_col = (long)n * LEN;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < (long)ldo * ncols;
+       e += (long)gridDim.x * blockDim.x) {
+    const int col = (int)(e / ldo);
+    const long o = e - (long)col * ldo;
+    float v = 0.f;
+    if (o < per_col) {
+      const int c = (int)(o / LEN);
+      const int kk = (int)(o - (long)c * LEN);
+      const int r = -((n - 1 - c) & 7) + kk;
+      if (r >= 0 && r < n) v = in[(long)col * ldx + (long)n * c + r];
+    }
+    cvt16(v, out + e);
+  }
 }
 template <typename H>
-void launch_to16(const float* in, H* out, long N, hipStream_t s) {
-  hipLaunchKernelGGL(to16_kernel<H>, dim3(2048), dim3(256), 0, s, in, out, N);
+void launch_to16_shifted(const float* in, long ldx, int n, int ncols, H* out, long ldo,
+                         hipStream_t s) {
+  hipLaunchKernelGGL(to16_shifted_kernel<H>, dim3(2048), dim3(256), 0, s, in, ldx, n, ncols,
+                     len16(n), out, ldo);
 }
-template void launch_to16<__hip_bfloat16>(const float*, __hip_bfloat16*, long, hipStream_t);
-template void launch_to16<__half>(const float*, __half*, long, hipStream_t);
+template void launch_to16_shifted<__hip_bfloat16>(const float*, long, int, int, __hip_bfloat16*,
+                                                  long, hipStream_t);
+template void launch_to16_shifted<__half>(const float*, long, int, int, __half*, long, hipStream_t);
 
 }  // namespace kpsb
