@@ -44,10 +44,15 @@ typedef enum {
   KP_E_NOMEM = 2,       /* workspace would exceed the context's HBM budget    */
   KP_E_DEVICE = 3,      /* a HIP runtime call failed                           */
   KP_E_NUMERIC = 4,     /* non-finite value met (e.g. NaN in the PSF)          */
+  KP_E_BUSY = 5,        /* server queue full (nothing was queued)              */
+  KP_E_TIMEOUT = 6,     /* kp_server_wait timed out; the request still runs     */
   KP_W_BREAKDOWN = 100  /* result valid; a Lanczos breakdown was deflated     */
 } kp_status;
 
 typedef enum { KP_F64 = 0, KP_F32 = 1, KP_BF16 = 2, KP_F16 = 3 } kp_prec;
+
+/* KP-SVD method: Algorithm 1 (EGKB) or Algorithm 2 (RSVD). */
+typedef enum { KP_METHOD_GKB = 0, KP_METHOD_RSVD = 1 } kp_method;
 
 typedef struct kp_ctx kp_ctx;
 
@@ -194,6 +199,104 @@ kp_status sb_solve_aniso(kp_ctx* ctx, const kp_factors* f, const double* b,
                          const sb_opts* opts, double* x, sb_stats* stats, void* stream);
 kp_status sb_solve_iso(kp_ctx* ctx, const kp_factors* f, const double* b,
                        const sb_opts* opts, double* x, sb_stats* stats, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Batched KP-SVD: many independent problems (different n, PSF, method, rank).
+ *
+ * Problem i is (blurs[i], method[i], opts[i], out[i]) with opts[i] pointing to
+ * a kp_gkb_opts (method KP_METHOD_GKB) or a kp_rsvd_opts (KP_METHOD_RSVD); each
+ * is exactly the problem of the single call kp_svd_gkb / kp_svd_rsvd with the
+ * same arguments and gives the same result (same kernels, same reduction
+ * order). The problems run concurrently on `nworkers` worker contexts
+ * (0 selects 4; at most 16), each with its own stream and workspace charged to
+ * ctx's HBM budget; workers take problems largest first (estimated time). Every
+ * worker stream first waits for the work already queued on `stream`, and
+ * `stream` waits for all workers at the end. The call returns when every
+ * problem is finished (host outputs written).
+ * status: optional HOST out [nprob], the status of each problem.
+ * Returns KP_OK when every problem returned KP_OK, KP_W_BREAKDOWN when some
+ * returned that warning and none failed, otherwise the status of the failing
+ * problem with the lowest index (kp_last_error names it). */
+kp_status kp_svd_batched(kp_ctx* ctx, int32_t nprob, const kp_blur* blurs,
+                         const int32_t* method, const void* const* opts, kp_factors* out,
+                         kp_status* status, int32_t nworkers, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Deblurring server: a request loop that runs split Bregman solves
+ * (Algorithms 3-5) of different sizes concurrently, keeps the Kronecker factors
+ * of recurring PSFs resident in HBM, and admits queued requests as solve slots
+ * and memory free up (continuous batching: a request that arrives while others
+ * run starts as soon as a slot and its memory footprint are available, and its
+ * kernels overlap theirs on the device).
+ *
+ * Admission. A request's footprint is its solve workspace plus, on a factor
+ * cache miss, its KP-SVD workspace and the new cache entry. Requests are taken
+ * in arrival order; one that does not fit may be passed by later ones that do,
+ * at most 8 times, after which it blocks the queue until it fits. Least
+ * recently used factor sets that no running request holds are evicted when
+ * memory or the entry limit requires. A request whose footprint alone exceeds
+ * the budget is refused by kp_server_submit (KP_E_NOMEM).
+ *
+ * Results. Each request runs on one worker with its own stream and workspace,
+ * so its output does not depend on what else runs (the same kernels and
+ * reduction order as sb_solve_iso / sb_solve_aniso with the same factors). */
+typedef struct kp_server kp_server;
+
+typedef struct {
+  int32_t slots;            /* concurrent solves (worker streams), 0 = 4, at most 16 */
+  size_t hbm_budget_bytes;  /* admission budget for factor cache and workspaces;
+                               0 = what the context's budget has left               */
+  int32_t max_pending;      /* queued (not yet admitted) requests; 0 = 4096         */
+  int32_t cache_entries;    /* resident factor sets; 0 = 64                         */
+} kp_server_cfg;
+
+typedef struct {
+  uint64_t psf_key;         /* nonzero: factors are cached under (psf_key, n, method,
+                               options); the key must identify the PSF and start
+                               data. 0: factors are computed for this request only */
+  kp_blur blur;             /* read only on a cache miss                             */
+  int32_t method;           /* kp_method used on a miss                              */
+  kp_gkb_opts gkb;          /* options when method == KP_METHOD_GKB                  */
+  kp_rsvd_opts rsvd;        /* options when method == KP_METHOD_RSVD                 */
+  int32_t k_cap;            /* terms kept (>= the method's k)                        */
+  int32_t iso;              /* 1: isotropic (Algorithm 4), 0: anisotropic (Alg. 3)   */
+  sb_opts sb;
+  const double* b;          /* DEVICE n x n row-major blurred image, fully written
+                               before submit                                         */
+  double* x;                /* DEVICE n x n row-major output                         */
+} kp_request;
+
+typedef struct {
+  kp_status status;
+  sb_stats stats;
+  int32_t k;                /* Kronecker terms used                                  */
+  int32_t cache_hit;        /* 1 when the factors were resident                      */
+  double queue_ms;          /* submit -> admitted (host clock)                       */
+  double factor_ms;         /* KP-SVD time on a miss, else 0                         */
+  double solve_ms;          /* split Bregman time                                    */
+  double total_ms;          /* submit -> result complete                             */
+  char msg[160];            /* error text when status is an error                    */
+} kp_result;
+
+/* Creates a server on ctx's device with cfg->slots worker threads. ctx must
+ * outlive the server; the server does not use ctx's workspace. */
+kp_status kp_server_create(kp_ctx* ctx, const kp_server_cfg* cfg, kp_server** out);
+/* Queues a request (copied; the pointers it holds, including the host PSF and
+ * y0 / F, must stay valid until kp_server_wait has returned its result).
+ * Non-blocking. *ticket identifies the request for kp_server_wait. */
+kp_status kp_server_submit(kp_server* srv, const kp_request* req, uint64_t* ticket);
+/* Waits up to timeout_s seconds (< 0: no limit) for a request. On completion
+ * fills *res (HOST), forgets the ticket and returns KP_OK (the request's own
+ * status is res->status); x is then complete in device memory. Returns
+ * KP_E_TIMEOUT if the request is still queued or running, KP_E_INVAL for an
+ * unknown ticket. */
+kp_status kp_server_wait(kp_server* srv, uint64_t ticket, double timeout_s, kp_result* res);
+/* Server counters (HOST): [0] submitted, [1] completed, [2] cache hits,
+ * [3] cache misses, [4] evictions, [5] bypasses of a blocked request,
+ * [6] peak concurrently running requests, [7] resident factor sets. */
+kp_status kp_server_stats(kp_server* srv, int64_t out[8]);
+/* Finishes every submitted request, then frees the server's memory. */
+kp_status kp_server_destroy(kp_server* srv);
 
 #ifdef __cplusplus
 }

@@ -13,17 +13,21 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libkpsb.so")
 
 KP_OK, KP_E_INVAL, KP_E_NOMEM, KP_E_DEVICE, KP_E_NUMERIC = 0, 1, 2, 3, 4
+KP_E_BUSY, KP_E_TIMEOUT = 5, 6
 KP_W_BREAKDOWN = 100
 KP_F64, KP_F32, KP_BF16, KP_F16 = 0, 1, 2, 3
+KP_METHOD_GKB, KP_METHOD_RSVD = 0, 1
 
 STATUS_NAMES = {0: "KP_OK", 1: "KP_E_INVAL", 2: "KP_E_NOMEM", 3: "KP_E_DEVICE",
-                4: "KP_E_NUMERIC", 100: "KP_W_BREAKDOWN"}
+                4: "KP_E_NUMERIC", 5: "KP_E_BUSY", 6: "KP_E_TIMEOUT", 100: "KP_W_BREAKDOWN"}
 
 # Every symbol the header declares (checked by the CPU test-suite).
 EXPORTED = ["kp_ctx_create", "kp_ctx_destroy", "kp_last_error", "kp_version",
             "kp_prof_enable", "kp_prof_read",
             "kp_rmat_apply", "kp_svd_gkb", "kp_svd_rsvd", "kp_apply",
-            "sb_solve_aniso", "sb_solve_iso"]
+            "sb_solve_aniso", "sb_solve_iso", "kp_svd_batched",
+            "kp_server_create", "kp_server_submit", "kp_server_wait", "kp_server_stats",
+            "kp_server_destroy"]
 
 
 class kp_blur(C.Structure):
@@ -70,6 +74,23 @@ class sb_stats(C.Structure):
     _fields_ = [("l_end", C.c_int32), ("iota_total", C.c_int32), ("rc_sb", C.c_double)]
 
 
+class kp_server_cfg(C.Structure):
+    _fields_ = [("slots", C.c_int32), ("hbm_budget_bytes", C.c_size_t),
+                ("max_pending", C.c_int32), ("cache_entries", C.c_int32)]
+
+
+class kp_request(C.Structure):
+    _fields_ = [("psf_key", C.c_uint64), ("blur", kp_blur), ("method", C.c_int32),
+                ("gkb", kp_gkb_opts), ("rsvd", kp_rsvd_opts), ("k_cap", C.c_int32),
+                ("iso", C.c_int32), ("sb", sb_opts), ("b", C.c_void_p), ("x", C.c_void_p)]
+
+
+class kp_result(C.Structure):
+    _fields_ = [("status", C.c_int), ("stats", sb_stats), ("k", C.c_int32),
+                ("cache_hit", C.c_int32), ("queue_ms", C.c_double), ("factor_ms", C.c_double),
+                ("solve_ms", C.c_double), ("total_ms", C.c_double), ("msg", C.c_char * 160)]
+
+
 _lib = None
 
 
@@ -99,6 +120,14 @@ def load(path: str = LIB_PATH):
     lib.sb_solve_aniso.argtypes = [vp, C.POINTER(kp_factors), vp, C.POINTER(sb_opts), vp,
                                    C.POINTER(sb_stats), vp]
     lib.sb_solve_iso.argtypes = lib.sb_solve_aniso.argtypes
+    lib.kp_svd_batched.argtypes = [vp, C.c_int32, C.POINTER(kp_blur), C.POINTER(C.c_int32),
+                                   C.POINTER(vp), C.POINTER(kp_factors), C.POINTER(C.c_int),
+                                   C.c_int32, vp]
+    lib.kp_server_create.argtypes = [vp, C.POINTER(kp_server_cfg), C.POINTER(vp)]
+    lib.kp_server_submit.argtypes = [vp, C.POINTER(kp_request), C.POINTER(C.c_uint64)]
+    lib.kp_server_wait.argtypes = [vp, C.c_uint64, C.c_double, C.POINTER(kp_result)]
+    lib.kp_server_stats.argtypes = [vp, C.POINTER(C.c_int64)]
+    lib.kp_server_destroy.argtypes = [vp]
     for name in EXPORTED:
         if name not in ("kp_last_error", "kp_version"):
             getattr(lib, name).restype = C.c_int

@@ -176,6 +176,39 @@ class Context:
             f.Q = Q[:kp]
         return f
 
+    @staticmethod
+    def gkb_opts(k, p, *, k_min=0, auto_k=False, tau=0.0, literal_init=False, reorth=1,
+                 prec="f32", seed=0, y0=None, bd_rel=0.0):
+        """kp_gkb_opts; a host start vector y0 must outlive the call using it."""
+        ptr = None if y0 is None else y0.ctypes.data_as(C.POINTER(C.c_double))
+        return L.kp_gkb_opts(k, p, k_min, int(auto_k), tau, int(literal_init), reorth,
+                             PREC[prec], seed, ptr, bd_rel)
+
+    @staticmethod
+    def rsvd_opts(k, p, q, *, prec="f32", refine=False, seed=0, F=None):
+        ptr = None if F is None else F.ctypes.data_as(C.POINTER(C.c_double))
+        return L.kp_rsvd_opts(k, p, q, PREC[prec], int(refine), seed, ptr)
+
+    def kp_svd_batched(self, problems, nworkers=0, factor_prec="f64"):
+        """problems: list of (Blur, "gkb" | "rsvd", opts struct, k_cap). Returns
+        (list of Factors, list of per-problem statuses)."""
+        m = len(problems)
+        blurs = (L.kp_blur * m)(*[p[0].s for p in problems])
+        meth = (C.c_int32 * m)(*[L.KP_METHOD_GKB if p[1] == "gkb" else L.KP_METHOD_RSVD
+                                 for p in problems])
+        opts = [p[2] for p in problems]
+        optp = (C.c_void_p * m)(*[C.cast(C.pointer(o), C.c_void_p) for o in opts])
+        facs = [Factors(p[0].n, p[3], factor_prec) for p in problems]
+        outs = (L.kp_factors * m)(*[f.s for f in facs])
+        status = (C.c_int * m)()
+        self._check(self.lib.kp_svd_batched(self.h, m, blurs, meth, optp, outs, status,
+                                            int(nworkers), _stream()),
+                    allow=(L.KP_OK, L.KP_W_BREAKDOWN))
+        for i, f in enumerate(facs):
+            f.s.k = outs[i].k
+            f.status = status[i]
+        return facs, list(status)
+
     def kp_svd_rsvd(self, blur: Blur, k, p, q, *, prec="f32", refine=False, seed=0, F=None,
                     factor_prec="f64", k_cap=None, bases=False):
         torch = _torch()
@@ -223,3 +256,74 @@ class Context:
                      x=None):
         return self._sb(self.lib.sb_solve_iso, f, b, lam, beta, L_max, I_max, tau_sb,
                         tau_cgls, x)
+
+
+class Server:
+    """The request server (kp_server_*): submit() is non-blocking, wait()
+    returns the per-request result. Device images b and x, and host PSF arrays,
+    must stay alive until wait() has returned for their ticket."""
+
+    def __init__(self, ctx: Context, slots=0, hbm_budget=0, max_pending=0, cache_entries=0):
+        self.ctx, self.lib = ctx, ctx.lib
+        cfg = L.kp_server_cfg(int(slots), C.c_size_t(hbm_budget), int(max_pending),
+                              int(cache_entries))
+        h = C.c_void_p()
+        ctx._check(self.lib.kp_server_create(ctx.h, C.byref(cfg), C.byref(h)))
+        self.h = h
+        self._keep = {}
+
+    def submit(self, blur: Blur, b, x, *, psf_key=0, method="rsvd", k=20, p=10, q=2,
+               prec="f32", refine=False, seed=0, k_cap=None, iso=True, lam=0.115,
+               beta=0.0066, L_max=50, I_max=100, tau_sb=0.0, tau_cgls=1e-4, gkb=None,
+               rsvd=None):
+        req = L.kp_request()
+        req.psf_key = psf_key
+        req.blur = blur.s
+        req.method = L.KP_METHOD_GKB if method == "gkb" else L.KP_METHOD_RSVD
+        req.gkb = gkb if gkb is not None else Context.gkb_opts(k, p, prec=prec, seed=seed)
+        req.rsvd = rsvd if rsvd is not None else Context.rsvd_opts(k, p, q, prec=prec,
+                                                                  refine=refine, seed=seed)
+        req.k_cap = k_cap or k
+        req.iso = int(iso)
+        req.sb = L.sb_opts(lam, beta, L_max, I_max, tau_sb, tau_cgls)
+        req.b = b.data_ptr()
+        req.x = x.data_ptr()
+        # the server's streams read b: it must be complete before submit
+        _torch().cuda.current_stream().synchronize()
+        t = C.c_uint64()
+        st = self.lib.kp_server_submit(self.h, C.byref(req), C.byref(t))
+        if st != L.KP_OK:
+            raise KPError(st, self.lib.kp_last_error(self.ctx.h).decode())
+        self._keep[t.value] = (blur, b, x)
+        return t.value
+
+    def wait(self, ticket, timeout=-1.0):
+        r = L.kp_result()
+        st = self.lib.kp_server_wait(self.h, C.c_uint64(ticket), float(timeout), C.byref(r))
+        if st == L.KP_E_TIMEOUT:
+            return None
+        if st != L.KP_OK:
+            raise KPError(st, self.lib.kp_last_error(self.ctx.h).decode())
+        self._keep.pop(ticket, None)
+        return dict(status=r.status, l_end=r.stats.l_end, iota_total=r.stats.iota_total,
+                    rc_sb=r.stats.rc_sb, k=r.k, cache_hit=bool(r.cache_hit),
+                    queue_ms=r.queue_ms, factor_ms=r.factor_ms, solve_ms=r.solve_ms,
+                    total_ms=r.total_ms, msg=r.msg.decode())
+
+    def stats(self):
+        out = (C.c_int64 * 8)()
+        self.lib.kp_server_stats(self.h, out)
+        names = ("submitted", "completed", "hits", "misses", "evictions", "bypasses",
+                 "peak_running", "resident")
+        return dict(zip(names, list(out)))
+
+    def close(self):
+        if self.h:
+            self.lib.kp_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -16,35 +16,12 @@
 #include <vector>
 
 #include "common.h"
+#include "ctx.h"
 #include "kpsb.h"
 #include "sb.h"
 
 using namespace kpsb;
 
-struct kp_ctx {
-  int device = 0;
-  size_t budget = 0;
-  size_t used = 0;
-  size_t lds_limit = 65536;
-  std::string err;
-  struct Buf {
-    void* p = nullptr;
-    size_t bytes = 0;
-  };
-  std::map<std::string, Buf> bufs;
-  double* pinned = nullptr;   // host readback buffer (64 doubles)
-  // tracing: event pairs around product launches (see kp_prof_read)
-  bool prof = false;
-  struct Rec {
-    hipEvent_t a, b;
-    int cls;
-    double flops;
-  };
-  std::vector<Rec> recs;
-  double acc_ms[4] = {0, 0, 0, 0};
-  int64_t acc_n[4] = {0, 0, 0, 0};
-  double acc_flops[4] = {0, 0, 0, 0};
-};
 
 namespace {
 
@@ -80,16 +57,28 @@ kp_status ws(kp_ctx* c, const std::string& name, size_t bytes, void** out) {
     return KP_OK;
   }
   bytes = (bytes + 255) & ~(size_t)255;
-  size_t freed = b.bytes;
-  if (c->used - freed + bytes > c->budget)
-    return set_err(c, KP_E_NOMEM, "workspace '" + name + "' of " + std::to_string(bytes) +
-                                      " bytes exceeds the HBM budget (" +
-                                      std::to_string(c->budget) + " bytes, " +
-                                      std::to_string(c->used) + " in use)");
+  kp_pool& pool = *c->pool;
+  {
+    std::lock_guard<std::mutex> lk(pool.m);
+    if (pool.used - b.bytes + bytes > pool.budget)
+      return set_err(c, KP_E_NOMEM, "workspace '" + name + "' of " + std::to_string(bytes) +
+                                        " bytes exceeds the HBM budget (" +
+                                        std::to_string(pool.budget) + " bytes, " +
+                                        std::to_string(pool.used) + " in use)");
+    pool.used += bytes;   // reserve before allocating
+  }
+  auto unreserve = [&](size_t v) {
+    std::lock_guard<std::mutex> lk(pool.m);
+    pool.used -= v;
+  };
   if (b.p) {
-    KP_HIP(c, hipDeviceSynchronize());
-    KP_HIP(c, hipFree(b.p));
-    c->used -= b.bytes;
+    hipError_t e1 = hipDeviceSynchronize();
+    hipError_t e2 = e1 == hipSuccess ? hipFree(b.p) : e1;
+    if (e2 != hipSuccess) {
+      unreserve(bytes);
+      return set_err(c, KP_E_DEVICE, std::string("freeing workspace: ") + hipGetErrorString(e2));
+    }
+    unreserve(b.bytes);
     b.p = nullptr;
     b.bytes = 0;
   }
@@ -97,11 +86,11 @@ kp_status ws(kp_ctx* c, const std::string& name, size_t bytes, void** out) {
   hipError_t e = hipMalloc(&p, bytes);
   if (e != hipSuccess) {
     (void)hipGetLastError();
+    unreserve(bytes);
     return set_err(c, KP_E_NOMEM, "hipMalloc of workspace '" + name + "' failed");
   }
   b.p = p;
   b.bytes = bytes;
-  c->used += bytes;
   *out = p;
   return KP_OK;
 }
@@ -815,6 +804,71 @@ kp_status sb_solve(kp_ctx* c, const kp_factors* f, const double* b, const sb_opt
 
 }  // namespace
 
+namespace kpsb {
+
+kp_ctx* ctx_new(int device, std::shared_ptr<kp_pool> pool, size_t budget) {
+  if (hipSetDevice(device) != hipSuccess) return nullptr;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) != hipSuccess) return nullptr;
+  kp_ctx* c = new kp_ctx();
+  c->device = device;
+  c->lds_limit = prop.sharedMemPerBlock;
+  if (prop.maxSharedMemoryPerMultiProcessor > 0 &&
+      (size_t)prop.maxSharedMemoryPerMultiProcessor < c->lds_limit)
+    c->lds_limit = prop.maxSharedMemoryPerMultiProcessor;
+  if (pool) {
+    c->pool = std::move(pool);
+  } else {
+    size_t freeb = 0, totalb = 0;
+    if (hipMemGetInfo(&freeb, &totalb) != hipSuccess) {
+      delete c;
+      return nullptr;
+    }
+    c->pool = std::make_shared<kp_pool>();
+    c->pool->budget = budget ? budget : (size_t)(0.9 * (double)freeb);
+  }
+  if (hipHostMalloc((void**)&c->pinned, 64 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+    delete c;
+    return nullptr;
+  }
+  return c;
+}
+
+size_t ctx_held(const kp_ctx* c) {
+  size_t h = 0;
+  for (auto& kv : c->bufs) h += kv.second.bytes;
+  return h;
+}
+
+void ctx_trim(kp_ctx* c) {
+  (void)hipSetDevice(c->device);
+  (void)hipDeviceSynchronize();
+  size_t freed = 0;
+  for (auto& kv : c->bufs)
+    if (kv.second.p) {
+      (void)hipFree(kv.second.p);
+      freed += kv.second.bytes;
+    }
+  c->bufs.clear();
+  std::lock_guard<std::mutex> lk(c->pool->m);
+  c->pool->used -= freed;
+}
+
+void ctx_free(kp_ctx* c) {
+  for (kp_ctx* w : c->workers) ctx_free(w);
+  c->workers.clear();
+  ctx_trim(c);
+  if (c->pinned) (void)hipHostFree(c->pinned);
+  for (auto& r : c->recs) {
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  if (c->own_stream) (void)hipStreamDestroy(c->own_stream);
+  delete c;
+}
+
+}  // namespace kpsb
+
 // ===========================================================================
 extern "C" {
 
@@ -825,44 +879,15 @@ kp_status kp_ctx_create(int device, size_t hbm_budget_bytes, kp_ctx** out) {
   *out = nullptr;
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return KP_E_DEVICE;
-  if (hipSetDevice(device) != hipSuccess) return KP_E_DEVICE;
-  kp_ctx* c = new kp_ctx();
-  c->device = device;
-  hipDeviceProp_t prop;
-  if (hipGetDeviceProperties(&prop, device) != hipSuccess) {
-    delete c;
-    return KP_E_DEVICE;
-  }
-  c->lds_limit = prop.sharedMemPerBlock;
-  if (prop.maxSharedMemoryPerMultiProcessor > 0 &&
-      (size_t)prop.maxSharedMemoryPerMultiProcessor < c->lds_limit)
-    c->lds_limit = prop.maxSharedMemoryPerMultiProcessor;
-  size_t freeb = 0, totalb = 0;
-  if (hipMemGetInfo(&freeb, &totalb) != hipSuccess) {
-    delete c;
-    return KP_E_DEVICE;
-  }
-  c->budget = hbm_budget_bytes ? hbm_budget_bytes : (size_t)(0.9 * (double)freeb);
-  if (hipHostMalloc((void**)&c->pinned, 64 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
-    delete c;
-    return KP_E_DEVICE;
-  }
+  kp_ctx* c = ctx_new(device, nullptr, hbm_budget_bytes);
+  if (!c) return KP_E_DEVICE;
   *out = c;
   return KP_OK;
 }
 
 kp_status kp_ctx_destroy(kp_ctx* c) {
   if (!c) return KP_E_INVAL;
-  (void)hipSetDevice(c->device);
-  (void)hipDeviceSynchronize();
-  for (auto& kv : c->bufs)
-    if (kv.second.p) (void)hipFree(kv.second.p);
-  if (c->pinned) (void)hipHostFree(c->pinned);
-  for (auto& r : c->recs) {
-    (void)hipEventDestroy(r.a);
-    (void)hipEventDestroy(r.b);
-  }
-  delete c;
+  ctx_free(c);
   return KP_OK;
 }
 
@@ -871,24 +896,32 @@ const char* kp_last_error(const kp_ctx* c) { return c ? c->err.c_str() : "null c
 kp_status kp_prof_enable(kp_ctx* c, int enable) {
   if (!c) return KP_E_INVAL;
   c->prof = enable != 0;
+  for (kp_ctx* w : c->workers) w->prof = c->prof;
   return KP_OK;
 }
 
-kp_status kp_prof_read(kp_ctx* c, kp_prof* out, int reset) {
-  if (!c || !out) return KP_E_INVAL;
-  KP_HIP(c, hipSetDevice(c->device));
-  KP_HIP(c, hipDeviceSynchronize());
+namespace {
+void prof_collect(kp_ctx* c, kp_ctx* into) {
   for (auto& r : c->recs) {
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
-      c->acc_ms[r.cls] += ms;
-      c->acc_n[r.cls] += 1;
-      c->acc_flops[r.cls] += r.flops;
+      into->acc_ms[r.cls] += ms;
+      into->acc_n[r.cls] += 1;
+      into->acc_flops[r.cls] += r.flops;
     }
     (void)hipEventDestroy(r.a);
     (void)hipEventDestroy(r.b);
   }
   c->recs.clear();
+}
+}  // namespace
+
+kp_status kp_prof_read(kp_ctx* c, kp_prof* out, int reset) {
+  if (!c || !out) return KP_E_INVAL;
+  KP_HIP(c, hipSetDevice(c->device));
+  KP_HIP(c, hipDeviceSynchronize());
+  prof_collect(c, c);
+  for (kp_ctx* w : c->workers) prof_collect(w, c);
   for (int i = 0; i < 4; ++i) {
     out->ms[i] = c->acc_ms[i];
     out->launches[i] = c->acc_n[i];

@@ -1,0 +1,62 @@
+// Internal definition of kp_ctx, shared by the entry points (api.cpp) and the
+// concurrent runtime (runtime.cpp: batched KP-SVD and the request server).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "kpsb.h"
+
+// HBM budget shared by a context and the worker contexts it spawns: every
+// workspace allocation of any of them is charged here.
+struct kp_pool {
+  std::mutex m;
+  size_t budget = 0;
+  size_t used = 0;
+};
+
+struct kp_ctx {
+  int device = 0;
+  std::shared_ptr<kp_pool> pool;
+  size_t lds_limit = 65536;
+  std::string err;
+  struct Buf {
+    void* p = nullptr;
+    size_t bytes = 0;
+  };
+  std::map<std::string, Buf> bufs;
+  double* pinned = nullptr;   // host readback buffer (64 doubles)
+  // tracing: event pairs around product launches (see kp_prof_read)
+  bool prof = false;
+  struct Rec {
+    hipEvent_t a, b;
+    int cls;
+    double flops;
+  };
+  std::vector<Rec> recs;
+  double acc_ms[4] = {0, 0, 0, 0};
+  int64_t acc_n[4] = {0, 0, 0, 0};
+  double acc_flops[4] = {0, 0, 0, 0};
+  // worker contexts (each with its own workspace and stream) used by the
+  // batched call; created on first use and kept with their workspaces.
+  std::vector<kp_ctx*> workers;
+  hipStream_t own_stream = nullptr;   // set for worker contexts only
+};
+
+namespace kpsb {
+
+// Creates a context bound to `device` that charges `pool` (the parent's, or a
+// new one when pool is empty). Returns nullptr on a device error.
+kp_ctx* ctx_new(int device, std::shared_ptr<kp_pool> pool, size_t budget);
+// Frees a context's workspace, pinned buffer, events, workers and stream.
+void ctx_free(kp_ctx* c);
+// Frees every workspace buffer of `c` (after synchronizing the device).
+void ctx_trim(kp_ctx* c);
+// Bytes of workspace currently held by `c` itself.
+size_t ctx_held(const kp_ctx* c);
+
+}  // namespace kpsb

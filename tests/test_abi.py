@@ -47,6 +47,12 @@ def test_null_arguments_are_rejected(lib):
     assert lib.kp_ctx_destroy(None) == _lib.KP_E_INVAL
     assert lib.kp_svd_gkb(None, None, None, None, None) == _lib.KP_E_INVAL
     assert lib.kp_last_error(None) == b"null context"
+    assert lib.kp_svd_batched(None, 0, None, None, None, None, None, 0, None) == _lib.KP_E_INVAL
+    assert lib.kp_server_create(None, None, None) == _lib.KP_E_INVAL
+    assert lib.kp_server_submit(None, None, None) == _lib.KP_E_INVAL
+    assert lib.kp_server_wait(None, 0, 0.0, None) == _lib.KP_E_INVAL
+    assert lib.kp_server_stats(None, None) == _lib.KP_E_INVAL
+    assert lib.kp_server_destroy(None) == _lib.KP_E_INVAL
 
 
 def test_ctx_without_gpu_reports_device_error(lib):
@@ -72,6 +78,11 @@ int main(void) {
   S(sb_opts); P(sb_opts, L_max); P(sb_opts, tau_cgls);
   S(sb_stats); P(sb_stats, rc_sb);
   S(kp_prof); P(kp_prof, launches); P(kp_prof, flops);
+  S(kp_server_cfg); P(kp_server_cfg, hbm_budget_bytes); P(kp_server_cfg, cache_entries);
+  S(kp_request); P(kp_request, blur); P(kp_request, method); P(kp_request, gkb); P(kp_request, rsvd);
+  P(kp_request, k_cap); P(kp_request, iso); P(kp_request, sb); P(kp_request, b); P(kp_request, x);
+  S(kp_result); P(kp_result, stats); P(kp_result, k); P(kp_result, queue_ms); P(kp_result, total_ms);
+  P(kp_result, msg);
   return 0;
 }
 """
@@ -87,7 +98,9 @@ def test_ctypes_layout_matches_header(tmp_path):
     ref = dict(l.rsplit(" ", 1) for l in lines if l)
     m = {"kp_blur": _lib.kp_blur, "kp_gkb_opts": _lib.kp_gkb_opts, "kp_rsvd_opts": _lib.kp_rsvd_opts,
          "kp_diag": _lib.kp_diag, "kp_factors": _lib.kp_factors, "sb_opts": _lib.sb_opts,
-         "sb_stats": _lib.sb_stats, "kp_prof": _lib.kp_prof}
+         "sb_stats": _lib.sb_stats, "kp_prof": _lib.kp_prof,
+         "kp_server_cfg": _lib.kp_server_cfg, "kp_request": _lib.kp_request,
+         "kp_result": _lib.kp_result}
     rename = {"lambda": "lam"}
     for key, val in ref.items():
         if "." in key:

@@ -1,0 +1,265 @@
+"""The concurrent runtime: batched KP-SVD and the deblurring server.
+
+Every problem in a batch, and every request in a server mix, runs the same
+kernels in the same order as its single-problem entry point on a stream of its
+own, so its result must equal the single call's bit for bit; the single calls
+are themselves checked against the oracle (here again at small n).
+"""
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle import operator as op, sb
+
+pytestmark = pytest.mark.gpu
+
+
+def _dev(a):
+    import torch
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+def _mix(count=7):
+    return wl.batched_mix(count, sizes=(16, 24, 32, 40), ranks=(3, 8), p=4, seed=77)
+
+
+def _problems(api, mix):
+    probs = []
+    for i, d in enumerate(mix):
+        blur = api.Blur(d["P"], d["cu"], d["cv"], d["n"])
+        if i % 2 == 0:
+            o = api.Context.rsvd_opts(d["k"], d["p"], 2, prec="f32", seed=d["seed"])
+            probs.append((blur, "rsvd", o, d["k"]))
+        else:
+            o = api.Context.gkb_opts(d["k"], d["p"], prec="f32", seed=d["seed"])
+            probs.append((blur, "gkb", o, d["k"]))
+    return probs
+
+
+@pytest.mark.parametrize("nworkers", [1, 3])
+def test_batched_equals_single_calls(ctx, nworkers):
+    from paper_2410_00233_amd import api
+    import torch
+    mix = _mix()
+    probs = _problems(api, mix)
+    facs, status = ctx.kp_svd_batched(probs, nworkers=nworkers)
+    torch.cuda.synchronize()
+    for (blur, meth, o, kcap), f, st in zip(probs, facs, status):
+        assert st in (0, 100)
+        if meth == "rsvd":
+            g = ctx.kp_svd_rsvd(blur, o.k, o.p, o.q, prec="f32", seed=o.seed)
+        else:
+            g = ctx.kp_svd_gkb(blur, o.k, o.p, prec="f32", seed=o.seed)
+        assert f.k == g.k
+        assert np.array_equal(f.sigma[:f.k], g.sigma[:g.k])
+        assert torch.equal(f.Ax[:f.k], g.Ax[:g.k]) and torch.equal(f.Ay[:f.k], g.Ay[:g.k])
+
+
+def test_batched_sigma_against_exact(ctx):
+    """Quality check of a batch against the exact KP-SVD (c.1): RSVD with q = 2
+    and EGKB at these small sizes recover the leading sigma to FP32 level."""
+    from paper_2410_00233_amd import api
+    mix = _mix(5)
+    probs = _problems(api, mix)
+    facs, _ = ctx.kp_svd_batched(probs)
+    for d, f in zip(mix, facs):
+        s_exact = op.exact_kpsvd(d["P"], d["cu"], d["cv"], d["n"], 3)[0]
+        assert np.abs(f.sigma[:3] - s_exact[:3]).max() <= 1e-4 * s_exact[0]
+
+
+def test_batched_reports_a_bad_problem_and_finishes_the_rest(ctx):
+    from paper_2410_00233_amd import api
+    mix = _mix(3)
+    probs = _problems(api, mix)
+    bad = api.Context.rsvd_opts(0, 4, 1)          # k = 0 is invalid
+    probs[1] = (probs[1][0], "rsvd", bad, 1)
+    with pytest.raises(api.KPError) as ei:
+        ctx.kp_svd_batched(probs, nworkers=2)
+    assert ei.value.status == 1 and "problem 1" in str(ei.value)
+
+
+def test_batched_empty_and_single(ctx):
+    from paper_2410_00233_amd import api
+    facs, status = ctx.kp_svd_batched([])
+    assert facs == [] and status == []
+    probs = _problems(api, _mix(1))
+    facs, status = ctx.kp_svd_batched(probs, nworkers=4)
+    assert len(facs) == 1 and status[0] in (0, 100) and facs[0].k == probs[0][2].k
+
+
+# ---------------------------------------------------------------------------
+# server
+
+SB_KW = dict(lam=0.115, beta=0.0066, L_max=6, I_max=15, tau_sb=0.0, tau_cgls=0.0)
+
+
+def _request_data(n, psf_id, idx):
+    P, cu, cv = wl.serving_psf(psf_id, n)
+    x_true = wl.rectangles_image(n, seed=wl.SEED_IMAGE + idx)
+    b = wl.add_noise(wl.blur_zero_bc(P, cu, cv, x_true), 0.01, seed=wl.SEED_NOISE + idx)
+    return P, cu, cv, b
+
+
+def _direct(ctx, api, P, cu, cv, n, b, iso, k=5):
+    """The same request through the single-call entry points."""
+    f = ctx.kp_svd_rsvd(api.Blur(P, cu, cv, n), k, 4, 2, prec="f32", seed=9)
+    fn = ctx.sb_solve_iso if iso else ctx.sb_solve_aniso
+    x, st = fn(f, _dev(b), **{k2: v for k2, v in SB_KW.items()})
+    return f, x, st
+
+
+def _submit(srv, api, P, cu, cv, n, b, x, iso, key, k=5):
+    return srv.submit(api.Blur(P, cu, cv, n), b, x, psf_key=key, method="rsvd", k=k, p=4,
+                      q=2, prec="f32", seed=9, iso=iso, **SB_KW)
+
+
+def test_server_result_is_the_same_alone_and_in_the_mix(ctx):
+    from paper_2410_00233_amd import api
+    import torch
+    specs = [(16, 0, True), (24, 1, False), (32, 2, True), (16, 3, False), (40, 4, True),
+             (24, 0, True)]
+    data = [_request_data(n, pid, i) for i, (n, pid, _) in enumerate(specs)]
+    # alone: one at a time through a 1-slot server, and through the direct calls
+    alone = []
+    srv1 = api.Server(ctx, slots=1)
+    for (n, pid, iso), (P, cu, cv, b) in zip(specs, data):
+        bd = _dev(b)
+        x = torch.empty_like(bd)
+        t = _submit(srv1, api, P, cu, cv, n, bd, x, iso, key=100 + pid)
+        r = srv1.wait(t)
+        assert r["status"] == 0, r["msg"]
+        alone.append(x.clone())
+        f, xd, st = _direct(ctx, api, P, cu, cv, n, b, iso)
+        assert torch.equal(x, xd)
+        assert r["iota_total"] == st["iota_total"] and r["l_end"] == st["l_end"]
+    srv1.close()
+    # in the mix: all submitted at once to a 4-slot server
+    srv = api.Server(ctx, slots=4)
+    xs, tickets = [], []
+    for (n, pid, iso), (P, cu, cv, b) in zip(specs, data):
+        bd = _dev(b)
+        x = torch.empty_like(bd)
+        xs.append((bd, x))
+        tickets.append(_submit(srv, api, P, cu, cv, n, bd, x, iso, key=100 + pid))
+    res = [srv.wait(t) for t in tickets]
+    for r, (bd, x), xa in zip(res, xs, alone):
+        assert r["status"] == 0, r["msg"]
+        assert torch.equal(x, xa)
+    st = srv.stats()
+    assert st["completed"] == len(specs) and st["peak_running"] >= 2
+    srv.close()
+
+
+def test_server_restored_image_matches_oracle(ctx):
+    """The server's output against the oracle's split Bregman run with the
+    server's own factors (restored image rel-L2 <= 1e-6)."""
+    from paper_2410_00233_amd import api
+    import torch
+    n = 24
+    P, cu, cv, b = _request_data(n, 5, 11)
+    f, _, _ = _direct(ctx, api, P, cu, cv, n, b, True)
+    srv = api.Server(ctx, slots=2)
+    bd = _dev(b)
+    x = torch.empty_like(bd)
+    r = srv.wait(_submit(srv, api, P, cu, cv, n, bd, x, True, key=0))
+    srv.close()
+    assert r["status"] == 0 and not r["cache_hit"]
+    Ax = f.Ax[:f.k].cpu().numpy()
+    Ay = f.Ay[:f.k].cpu().numpy()
+    ref = sb.split_bregman("iso", lambda X: sb.kp_apply(Ax, Ay, X),
+                           lambda X: sb.kp_apply(Ax, Ay, X, True), b, SB_KW["lam"],
+                           SB_KW["beta"], L_max=SB_KW["L_max"], I_max=SB_KW["I_max"],
+                           tau_sb=0.0, tau_cgls=0.0)["x"]
+    xr = x.cpu().numpy()
+    assert np.linalg.norm(xr - ref) <= 1e-6 * np.linalg.norm(ref)
+
+
+def test_server_cache_hits_and_eviction(ctx):
+    from paper_2410_00233_amd import api
+    import torch
+    n = 16
+    srv = api.Server(ctx, slots=2, cache_entries=2)
+    keys = [1, 2, 1, 3, 1, 2]
+    out = []
+    for i, key in enumerate(keys):
+        P, cu, cv, b = _request_data(n, key, i)
+        bd = _dev(b)
+        x = torch.empty_like(bd)
+        r = srv.wait(_submit(srv, api, P, cu, cv, n, bd, x, True, key=key))
+        assert r["status"] == 0, r["msg"]
+        out.append(r)
+    hits = [r["cache_hit"] for r in out]
+    assert hits[:3] == [False, False, True]
+    st = srv.stats()
+    assert st["evictions"] >= 1 and st["resident"] <= 2
+    assert st["hits"] + st["misses"] == len(keys)
+    srv.close()
+
+
+def test_server_admission_under_a_small_budget(ctx):
+    """A budget that holds one request at a time still completes every request,
+    one after the other."""
+    from paper_2410_00233_amd import api
+    import torch
+    n = 32
+    budget = 48 << 20            # one request's footprint (~33 MB on a miss) but not two
+    srv = api.Server(ctx, slots=4, hbm_budget=budget, cache_entries=4)
+    ts, keep = [], []
+    for i in range(4):
+        P, cu, cv, b = _request_data(n, i, 20 + i)
+        bd = _dev(b)
+        x = torch.empty_like(bd)
+        keep.append((bd, x))
+        ts.append(_submit(srv, api, P, cu, cv, n, bd, x, bool(i % 2), key=200 + i))
+    res = [srv.wait(t) for t in ts]
+    assert all(r["status"] == 0 for r in res), [r["msg"] for r in res]
+    st = srv.stats()
+    assert st["peak_running"] == 1 and st["completed"] == 4
+    srv.close()
+
+
+def test_server_rejects_bad_requests(ctx):
+    from paper_2410_00233_amd import api
+    import torch
+    n = 16
+    P, cu, cv, b = _request_data(n, 0, 0)
+    bd = _dev(b)
+    x = torch.empty_like(bd)
+    srv = api.Server(ctx, slots=1, hbm_budget=1 << 20)
+    with pytest.raises(api.KPError) as ei:                      # footprint > budget
+        _submit(srv, api, P, cu, cv, n, bd, x, True, key=1)
+    assert ei.value.status == 2
+    srv.close()
+    srv = api.Server(ctx, slots=1)
+    with pytest.raises(api.KPError) as ei:                      # b aliases x
+        _submit(srv, api, P, cu, cv, n, bd, bd, True, key=1)
+    assert ei.value.status == 1
+    with pytest.raises(api.KPError):                            # unknown ticket
+        srv.wait(12345)
+    with pytest.raises(api.KPError) as ei:                      # k_cap < k
+        srv.submit(api.Blur(P, cu, cv, n), bd, x, k=5, k_cap=3)
+    assert ei.value.status == 1
+    srv.close()
+
+
+def test_server_queue_limit(ctx):
+    from paper_2410_00233_amd import api
+    import torch
+    n = 48
+    srv = api.Server(ctx, slots=1, max_pending=1)
+    P, cu, cv, b = _request_data(n, 0, 0)
+    keep, ts, busy = [], [], 0
+    for i in range(3):
+        bd = _dev(b)
+        x = torch.empty_like(bd)
+        keep.append((bd, x))
+        try:
+            ts.append(srv.submit(api.Blur(P, cu, cv, n), bd, x, psf_key=0, k=5, p=4, q=2,
+                                 L_max=20, I_max=30, tau_cgls=0.0))
+        except api.KPError as e:
+            assert e.status == 5
+            busy += 1
+    assert busy >= 1
+    for t in ts:
+        assert srv.wait(t)["status"] == 0
+    srv.close()

@@ -214,3 +214,63 @@ def deblur_problem(n: int, psf: str = "gaussian", noise: float = 0.01, idx: int 
     b_true = blur_zero_bc(P, cu, cv, x_true)
     b = add_noise(b_true, noise, seed=SEED_NOISE + idx)
     return P, cu, cv, x_true, b_true, b
+
+
+# ---------------------------------------------------------------------------
+# Mixed workloads: many problems of uneven size and PSF (batched KP-SVD) and a
+# request stream with recurring PSFs (deblurring server).
+
+FAMILIES = ("gaussian", "motion", "disk")
+
+
+def mixed_psf(n: int, family: str, rng: np.random.Generator):
+    """One PSF of the given family with randomly drawn shape parameters:
+    Gaussian sigma1 ~ U[1, 3], sigma2 ~ U[0.5, sigma1], theta ~ U[0, 180) deg;
+    motion length 15 at theta ~ U[0, pi); disk radius ~ U[3, 8]."""
+    if family == "gaussian":
+        s1 = float(rng.uniform(1.0, 3.0))
+        s2 = float(rng.uniform(0.5, s1))
+        return gaussian_psf(n, (s1, s2), float(rng.uniform(0.0, 180.0)))
+    if family == "motion":
+        return motion_psf(n, 15, float(rng.uniform(0.0, math.pi)))
+    if family == "disk":
+        return disk_psf(n, float(rng.uniform(3.0, 8.0)))
+    raise ValueError(family)
+
+
+def batched_mix(count: int = 64, sizes=(128, 192, 256, 384, 512), ranks=(10, 30),
+                p: int = 10, seed: int = SEED_PSF + 500):
+    """``count`` KP-SVD problems: n ~ U(sizes), family ~ U(FAMILIES),
+    rank k ~ U{ranks[0] .. ranks[1]}, oversampling / enlargement p."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(count):
+        n = int(rng.choice(sizes))
+        fam = FAMILIES[int(rng.integers(0, len(FAMILIES)))]
+        P, cu, cv = mixed_psf(n, fam, rng)
+        k = int(rng.integers(ranks[0], ranks[1] + 1))
+        out.append(dict(n=n, family=fam, P=P, cu=cu, cv=cv, k=k, p=p, seed=SEED_START + i))
+    return out
+
+
+def serving_psf(psf_id: int, n: int):
+    """PSF number ``psf_id`` of the recurring set, on the offset grid of n:
+    the family cycles through FAMILIES and the shape parameters are drawn from
+    a generator seeded by the id, so a PSF is the same for every image size."""
+    rng = np.random.default_rng(SEED_PSF + 700 + psf_id)
+    return mixed_psf(n, FAMILIES[psf_id % len(FAMILIES)], rng)
+
+
+def serving_stream(count: int = 2000, rate: float = 200.0, sizes=(128, 256, 512, 1024),
+                   weights=(4, 3, 2, 1), n_psf: int = 16, seed: int = SEED_ARRIVALS):
+    """Open-loop Poisson request stream: exponential inter-arrival times of
+    mean 1/rate seconds, n drawn with the given weights, PSF id ~ U{0..n_psf-1},
+    isotropic or anisotropic with probability 1/2 each."""
+    rng = np.random.default_rng(seed)
+    w = np.asarray(weights, dtype=np.float64)
+    t = np.cumsum(rng.exponential(1.0 / rate, size=count))
+    n = rng.choice(np.asarray(sizes), size=count, p=w / w.sum())
+    psf = rng.integers(0, n_psf, size=count)
+    iso = rng.integers(0, 2, size=count)
+    return [dict(t=float(t[i]), n=int(n[i]), psf_id=int(psf[i]), iso=bool(iso[i]))
+            for i in range(count)]
