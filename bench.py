@@ -35,6 +35,11 @@ MFMA_BF16_PEAK_TFLOPS = 2500.0    # MI355X dense BF16 matrix peak
 HBM_PEAK_GBS = 8000.0
 
 
+def log(msg):
+    """Progress on stderr (stdout carries only the JSON line)."""
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
 def cpu_baseline(n, ncols, target_s):
     """Oracle dense product R X on the first rows of R (the oracle as it stands:
     generated row blocks of R(A) times X with NumPy/BLAS, FP64)."""
@@ -67,6 +72,139 @@ def cpu_baseline(n, ncols, target_s):
                        f"n={n} rotated Gaussian; {el:.1f} s")
 
 
+def bench_batched(ctx, count):
+    """Mixed batch: `count` RSVD KP-SVDs (FP32, q = 2, p = 10, rank 10..30) of
+    n in {128, 192, 256, 384, 512} with Gaussian / motion / disk PSFs, through
+    kp_svd_batched, against the same problems as single calls one after another."""
+    import numpy as np
+    import torch
+
+    import workloads as wl
+    from paper_2410_00233_amd import api, flops
+    mix = wl.batched_mix(count)
+    probs = []
+    for d in mix:
+        blur = api.Blur(d["P"], d["cu"], d["cv"], d["n"], on_device=True)
+        o = api.Context.rsvd_opts(d["k"], d["p"], 2, prec="f32", seed=d["seed"])
+        probs.append((blur, "rsvd", o, d["k"]))
+    fl = sum(flops.rsvd(d["n"], d["k"], d["p"], 2) for d in mix)
+    ctx.kp_svd_batched(probs[:4])              # workers and kernels warm
+    torch.cuda.synchronize()
+    log("batched: timed run")
+    t0 = time.perf_counter()
+    facs, status = ctx.kp_svd_batched(probs)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    log(f"batched: {1e3 * t_batch:.0f} ms; the same problems one by one")
+    t0 = time.perf_counter()
+    solo = []
+    for (blur, _, o, kc) in probs:
+        solo.append(ctx.kp_svd_rsvd(blur, o.k, o.p, o.q, prec="f32", seed=o.seed))
+    torch.cuda.synchronize()
+    t_solo = time.perf_counter() - t0
+    same = all(np.array_equal(f.sigma[:f.k], g.sigma[:g.k]) for f, g in zip(facs, solo))
+    sizes = [d["n"] for d in mix]
+    return {
+        "workload": f"{count} RSVD KP-SVDs (FP32, p=10, q=2, rank 10-30), n in "
+                    "{128,192,256,384,512}, Gaussian/motion/disk PSFs, 4 worker streams",
+        "problems": count, "n_hist": {str(v): sizes.count(v) for v in sorted(set(sizes))},
+        "flops": fl, "batched_ms": round(1e3 * t_batch, 2), "solo_sum_ms": round(1e3 * t_solo, 2),
+        "batched_tflops": round(fl / t_batch / 1e12, 3), "solo_tflops": round(fl / t_solo / 1e12, 3),
+        "speedup_vs_solo": round(t_solo / t_batch, 3),
+        "sigma_equal_to_solo": bool(same),
+        "statuses_ok": bool(all(s_ in (0, 100) for s_ in status)),
+    }
+
+
+def bench_serving(ctx, count, rate, sizes):
+    """Open-loop serving: Poisson arrivals at `rate`/s, n drawn 4:3:2:1 over
+    `sizes`, 16 recurring PSFs, iso/aniso 50/50, split Bregman 50 outer
+    iterations with CGLS tau 1e-4 (I_max 100), rank-20 FP32 RSVD factors kept
+    per PSF. The factor cache is warmed first (the cold misses are reported
+    separately); latency = completion - scheduled arrival."""
+    import threading
+
+    import numpy as np
+    import torch
+
+    import workloads as wl
+    from paper_2410_00233_amd import api
+    weights = (4, 3, 2, 1)[:len(sizes)]
+    stream = wl.serving_stream(count, rate, sizes=sizes, weights=weights)
+    kw = dict(method="rsvd", k=20, p=10, q=2, prec="f32", seed=11, lam=0.115,
+              beta=0.115 ** 2 / 2.0, L_max=50, I_max=100, tau_sb=0.0, tau_cgls=1e-4)
+    blurs, imgs = {}, {}
+    for i, r in enumerate(stream):
+        key = (r["psf_id"], r["n"])
+        if key not in blurs:
+            P, cu, cv = wl.serving_psf(r["psf_id"], r["n"])
+            blurs[key] = api.Blur(P, cu, cv, r["n"])
+        x_true = wl.rectangles_image(r["n"], seed=wl.SEED_IMAGE + 100 + i)
+        P = blurs[key].P
+        b = wl.add_noise(wl.blur_zero_bc(P, blurs[key].cu, blurs[key].cv, x_true), 0.01,
+                         seed=wl.SEED_NOISE + 100 + i)
+        imgs[i] = torch.tensor(b, dtype=torch.float64, device="cuda")
+    log(f"serving: inputs ready ({len(blurs)} PSF/size pairs); warming the factor cache")
+    srv = api.Server(ctx, slots=4)
+    # warm the factor cache: one cheap solve per (PSF, n) computes its factors
+    cold = {}
+    warm_kw = dict(kw, L_max=1, I_max=1)
+    for (pid, nn), blur in blurs.items():
+        b = imgs[next(i for i, r in enumerate(stream) if (r["psf_id"], r["n"]) == (pid, nn))]
+        x = torch.empty_like(b)
+        res = srv.wait(srv.submit(blur, b, x, psf_key=1 + pid, **warm_kw))
+        cold.setdefault(str(nn), []).append(res["factor_ms"])
+    outs = {i: torch.empty_like(imgs[i]) for i in imgs}
+    tickets = {}
+    t_sub = {}
+    t0 = time.perf_counter()
+
+    def submitter():
+        for i, r in enumerate(stream):
+            dt = t0 + r["t"] - time.perf_counter()
+            if dt > 0:
+                time.sleep(dt)
+            key = (r["psf_id"], r["n"])
+            t_sub[i] = time.perf_counter()
+            tickets[i] = srv.submit(blurs[key], imgs[i], outs[i], psf_key=1 + r["psf_id"],
+                                    iso=r["iso"], **kw)
+
+    log("serving: open-loop run")
+    th = threading.Thread(target=submitter)
+    th.start()
+    th.join()
+    res = {}
+    for i, t in tickets.items():
+        res[i] = srv.wait(t)
+        log(f"serving: request {i} (n={stream[i]['n']}) done, {res[i]['total_ms']:.0f} ms")
+    t_end = time.perf_counter()
+    lat = np.array([(t_sub[i] - (t0 + stream[i]["t"])) * 1e3 + res[i]["total_ms"]
+                    for i in range(count)])
+    per_n = {}
+    for i, r in enumerate(stream):
+        per_n.setdefault(str(r["n"]), []).append(lat[i])
+    st = srv.stats()
+    srv.close()
+    return {
+        "workload": f"{count} requests, Poisson {rate}/s, n in {list(sizes)} weighted "
+                    f"{list(weights)}, 16 recurring PSFs (Gaussian/motion/disk), iso/aniso 50/50, "
+                    "SB 50 outer iterations, CGLS tau 1e-4 (I_max 100), rank-20 FP32 RSVD factors "
+                    "cached per PSF, 4 slots",
+        "p50_ms": round(float(np.percentile(lat, 50)), 2),
+        "p99_ms": round(float(np.percentile(lat, 99)), 2),
+        "solves_per_s": round(count / (t_end - t0), 3),
+        "per_n_p50_ms": {k_: round(float(np.percentile(v, 50)), 2) for k_, v in per_n.items()},
+        "per_n_count": {k_: len(v) for k_, v in per_n.items()},
+        "mean_solve_ms": round(float(np.mean([r["solve_ms"] for r in res.values()])), 2),
+        "mean_queue_ms": round(float(np.mean([r["queue_ms"] for r in res.values()])), 2),
+        "cache_hits": int(sum(r["cache_hit"] for r in res.values())),
+        "cold_factor_ms_p50_per_n": {k_: round(float(np.median(v)), 1) for k_, v in cold.items()},
+        "peak_concurrent": int(st["peak_running"]),
+        "iota_total_mean": round(float(np.mean([r["iota_total"] for r in res.values()])), 1),
+        "all_ok": bool(all(r["status"] == 0 for r in res.values())),
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -76,6 +214,13 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--sb-solves", type=int, default=5)
+    ap.add_argument("--batched", type=int, default=64,
+                    help="problems in the batched KP-SVD run (0 skips it)")
+    ap.add_argument("--serve", type=int, default=24,
+                    help="requests in the serving run (0 skips it)")
+    ap.add_argument("--serve-rate", type=float, default=2.0,
+                    help="offered Poisson arrival rate of the serving run (requests/s)")
+    ap.add_argument("--serve-sizes", type=str, default="128,256,512,1024")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the KP-SVD path is built and timed on a single "
@@ -108,6 +253,7 @@ def main():
             comp["rsvd_ms"].append(1e3 * (t2 - t1))
         return fg, fr
 
+    log(f"KP-SVD step at n={n}: {args.warmup} warm-up + {args.steps} timed")
     for _ in range(args.warmup):
         step(False)
     torch.cuda.synchronize()
@@ -124,6 +270,7 @@ def main():
     ms_step = 1e3 * (t1 - t0) / args.steps
     value = (f_gkb + f_rsvd) / (ms_step * 1e-3) / 1e12
 
+    log(f"step {ms_step:.1f} ms ({value:.1f} TFLOP/s); BF16 + refinement RSVD")
     # the reduced-precision variant: RSVD with BF16 block products + refinement
     f_ref = flops.rmat_product(n, k)
     ctx.kp_svd_rsvd(blur, k, p_rsvd, q, prec="bf16", refine=True, seed=2, factor_prec="f64")
@@ -144,6 +291,7 @@ def main():
 
     # split Bregman solve latency at n = 256 (isotropic, 50 outer iterations,
     # CGLS tau = 1e-4, I_max = 100) with FP64 factors from the FP32 RSVD
+    log("split Bregman latency at n=256")
     ns = 256
     Ps, cus, cvs, xs_true, bs_true, bs = wl.deblur_problem(ns, "gaussian", 0.01, 0)
     blur_s = api.Blur(Ps, cus, cvs, ns, on_device=True)
@@ -233,7 +381,15 @@ def main():
             "flops_per_launch": flops_blk,
         },
     }
+    if args.batched > 0:
+        log(f"batched KP-SVD, {args.batched} problems")
+        line["batched"] = bench_batched(ctx, args.batched)
+    if args.serve > 0:
+        sizes = tuple(int(v) for v in args.serve_sizes.split(","))
+        log(f"serving, {args.serve} requests at {args.serve_rate}/s")
+        line["serving"] = bench_serving(ctx, args.serve, args.serve_rate, sizes)
     if not args.no_cpu_baseline:
+        log("CPU oracle baseline")
         line["cpu_baseline"] = cpu_baseline(n, k + p_rsvd, args.cpu_seconds)
     ctx.close()
     print(json.dumps(line), flush=True)

@@ -761,18 +761,18 @@ kp_status sb_solve(kp_ctx* c, const kp_factors* f, const double* b, const sb_opt
     KP_HIP(c, hipStreamSynchronize(s));
     return KP_OK;
   };
+  const KpApplyPlan plan = kp_apply_plan(n, k);
   for (int ell = 0; ell < o->L_max; ++ell) {
     sb_launch_rhs(d, s);
-    sb_launch_f(d, AtB, 1, s);
+    sb_launch_f(d, AtB, 1, 1, s);
     sb_launch_w_init(d, s);
     for (int it = 0; it < o->I_max; ++it) {
-      launch_kp_apply_ws(Ax, Ay, n, k, 0, d.w, d.z1, Z, P, flags, 2, s);
-      sb_launch_zn(d, s);
+      launch_kp_apply_parts(Ax, Ay, n, k, 0, d.w, Z, P, plan, flags, 2, s);
+      sb_launch_zn(d, P, plan.ngroups, s);
       sb_launch_xr(d, s);
-      launch_kp_apply_ws(Ax, Ay, n, k, 1, d.r1, d.t1, Z, P, flags, 2, s);
-      sb_launch_f(d, d.t1, 2, s);
+      launch_kp_apply_parts(Ax, Ay, n, k, 1, d.r1, Z, P, plan, flags, 2, s);
+      sb_launch_f(d, P, plan.ngroups, 2, s);
       sb_launch_w(d, s);
-      sb_launch_cgls_check(d, s);
       if (o->tau_cgls > 0 && (it + 1) % poll == 0 && it + 1 < o->I_max) {
         KP_TRY(check_launch(c, "cgls"));
         KP_TRY(read_flags());

@@ -19,16 +19,32 @@ struct SBDev {
   int* flags;        // [0] SB done  [1] CGLS done  [2] iota_total  [3] l_end
 };
 
+// Kronecker apply tiling: output tile (64 or 32), terms accumulated per
+// workgroup of the second GEMM, and the resulting number of partial images.
+struct KpApplyPlan {
+  int tile = 64;
+  int group = 1;
+  int ngroups = 1;
+};
+KpApplyPlan kp_apply_plan(int n, int k);
+
 void sb_launch_rhs(const SBDev& d, hipStream_t s);
-void sb_launch_f(const SBDev& d, const double* T, int levels, hipStream_t s);
+// f from T = sum of the ng partial images at T (stride n^2)
+void sb_launch_f(const SBDev& d, const double* T, int ng, int levels, hipStream_t s);
 void sb_launch_w_init(const SBDev& d, hipStream_t s);
-void sb_launch_zn(const SBDev& d, hipStream_t s);
+// z1 = sum of the ng partial images at P, and ||z||^2 partials
+void sb_launch_zn(const SBDev& d, const double* P, int ng, hipStream_t s);
 void sb_launch_xr(const SBDev& d, hipStream_t s);
+// w update and the CGLS stopping test
 void sb_launch_w(const SBDev& d, hipStream_t s);
-void sb_launch_cgls_check(const SBDev& d, hipStream_t s);
 void sb_launch_shrink(const SBDev& d, hipStream_t s);
 void sb_launch_check(const SBDev& d, hipStream_t s);
 
+// A_k X (or A_k^T X) as plan.ngroups partial images in P; Z (k x n x n) is
+// workspace. Skipped when any of flags[0..nflags) is nonzero.
+void launch_kp_apply_parts(const double* Ax, const double* Ay, int n, int k, int transpose,
+                           const double* X, double* Z, double* P, const KpApplyPlan& plan,
+                           const int* flags, int nflags, hipStream_t s);
 // kp_apply with caller workspace Z, P (k x n x n each); skipped when any of
 // flags[0..nflags) is nonzero.
 void launch_kp_apply_ws(const double* Ax, const double* Ay, int n, int k, int transpose,

@@ -86,16 +86,26 @@ __global__ void __launch_bounds__(256) sb_rhs_kernel(SBDev d) {
   if (blockIdx.x == 0 && threadIdx.x == 0) d.flags[1] = 0;
 }
 
-// f = T + lam (L_x^T r2 + L_y^T r3), partial ||f||^2 in slot 0
+// sum of the ng partial images at P (stride NN), fixed order
+__device__ __forceinline__ double sb_sum_parts(const double* __restrict__ P, int ng, long NN,
+                                               long e) {
+  double v = P[e];
+  for (int g = 1; g < ng; ++g) v += P[(long)g * NN + e];
+  return v;
+}
+
+// f = T + lam (L_x^T r2 + L_y^T r3) with T the sum of ng partial images,
+// partial ||f||^2 in slot 0
 __global__ void __launch_bounds__(256) cgls_f_kernel(SBDev d, const double* __restrict__ T,
-                                                     int levels) {
+                                                     int ng, int levels) {
   if (sb_skip(d, levels)) return;
   __shared__ double sh[4];
   SB_ROWS
   double acc = 0.0;
   for (long e = lo + threadIdx.x; e < hi; e += 256) {
     const int r = (int)(e / d.n), c = (int)(e - (long)r * d.n);
-    const double v = T[e] + d.lam * (dLxT(d.r2, d.n, r, c) + dLyT(d.r3, d.n, r, c));
+    const double v = sb_sum_parts(T, ng, NN, e) +
+                     d.lam * (dLxT(d.r2, d.n, r, c) + dLyT(d.r3, d.n, r, c));
     d.f[e] = v;
     acc += v * v;
   }
@@ -116,15 +126,18 @@ __global__ void __launch_bounds__(256) cgls_w_init_kernel(SBDev d) {
   }
 }
 
-// partial ||z||^2 = ||A w||^2 + lam^2 (||L_x w||^2 + ||L_y w||^2) in slot 1
-__global__ void __launch_bounds__(256) cgls_zn_kernel(SBDev d) {
+// z1 = A w (the sum of the ng partial images at P); partial
+// ||z||^2 = ||A w||^2 + lam^2 (||L_x w||^2 + ||L_y w||^2) in slot 1
+__global__ void __launch_bounds__(256) cgls_zn_kernel(SBDev d, const double* __restrict__ P,
+                                                      int ng) {
   if (sb_skip(d, 2)) return;
   __shared__ double sh[4];
   SB_ROWS
   double acc = 0.0;
   for (long e = lo + threadIdx.x; e < hi; e += 256) {
     const int r = (int)(e / d.n), c = (int)(e - (long)r * d.n);
-    const double z1 = d.z1[e];
+    const double z1 = sb_sum_parts(P, ng, NN, e);
+    d.z1[e] = z1;
     const double lx = d.lam * dLx(d.w, d.n, r, c);
     const double ly = d.lam * dLy(d.w, d.n, r, c);
     acc += z1 * z1 + lx * lx + ly * ly;
@@ -162,7 +175,10 @@ __global__ void __launch_bounds__(256) cgls_xr_kernel(SBDev d) {
   if (blockIdx.x == 0 && threadIdx.x == 0) d.scal[5] = tau;   // tau of this iteration
 }
 
-// tau' = ||f||^2, delta = tau'/tau, w = f + delta w; RC_CGLS into scal[3]
+// tau' = ||f||^2, delta = tau'/tau, w = f + delta w; RC_CGLS into scal[3];
+// block 0 counts the iteration and applies the stopping test. Blocks that
+// start after the test has fired skip their w update, which the solve no
+// longer reads (the next outer iteration restarts CGLS from w = f).
 __global__ void __launch_bounds__(256) cgls_w_kernel(SBDev d) {
   if (sb_skip(d, 2)) return;
   __shared__ double sh[4];
@@ -173,16 +189,12 @@ __global__ void __launch_bounds__(256) cgls_w_kernel(SBDev d) {
   const double s2 = sb_partials(d.part, 2, sh);
   const double s3 = sb_partials(d.part, 3, sh);
   if (blockIdx.x == 0 && threadIdx.x == 0) {
+    const double rc = s3 > 0.0 ? sqrt(s2) / sqrt(s3) : 0.0;
     d.scal[0] = tau_new;
-    d.scal[3] = s3 > 0.0 ? sqrt(s2) / sqrt(s3) : 0.0;
+    d.scal[3] = rc;
+    d.flags[2] += 1;
+    if ((d.tau_cgls > 0.0 && rc < d.tau_cgls) || tau_new == 0.0) d.flags[1] = 1;
   }
-}
-
-// count the iteration and apply the CGLS stopping test (single thread)
-__global__ void cgls_check_kernel(SBDev d) {
-  if (threadIdx.x != 0 || sb_skip(d, 2)) return;
-  d.flags[2] += 1;
-  if ((d.tau_cgls > 0.0 && d.scal[3] < d.tau_cgls) || d.scal[0] == 0.0) d.flags[1] = 1;
 }
 
 // c = L x + g, shrink, g = c - d; RC_SB partials; xprev = x
@@ -241,23 +253,20 @@ static dim3 grid_red() { return dim3(kRedBlocks); }
 void sb_launch_rhs(const SBDev& d, hipStream_t s) {
   hipLaunchKernelGGL(sb_rhs_kernel, grid_red(), dim3(256), 0, s, d);
 }
-void sb_launch_f(const SBDev& d, const double* T, int levels, hipStream_t s) {
-  hipLaunchKernelGGL(cgls_f_kernel, grid_red(), dim3(256), 0, s, d, T, levels);
+void sb_launch_f(const SBDev& d, const double* T, int ng, int levels, hipStream_t s) {
+  hipLaunchKernelGGL(cgls_f_kernel, grid_red(), dim3(256), 0, s, d, T, ng, levels);
 }
 void sb_launch_w_init(const SBDev& d, hipStream_t s) {
   hipLaunchKernelGGL(cgls_w_init_kernel, grid_red(), dim3(256), 0, s, d);
 }
-void sb_launch_zn(const SBDev& d, hipStream_t s) {
-  hipLaunchKernelGGL(cgls_zn_kernel, grid_red(), dim3(256), 0, s, d);
+void sb_launch_zn(const SBDev& d, const double* P, int ng, hipStream_t s) {
+  hipLaunchKernelGGL(cgls_zn_kernel, grid_red(), dim3(256), 0, s, d, P, ng);
 }
 void sb_launch_xr(const SBDev& d, hipStream_t s) {
   hipLaunchKernelGGL(cgls_xr_kernel, grid_red(), dim3(256), 0, s, d);
 }
 void sb_launch_w(const SBDev& d, hipStream_t s) {
   hipLaunchKernelGGL(cgls_w_kernel, grid_red(), dim3(256), 0, s, d);
-}
-void sb_launch_cgls_check(const SBDev& d, hipStream_t s) {
-  hipLaunchKernelGGL(cgls_check_kernel, dim3(1), dim3(64), 0, s, d);
 }
 void sb_launch_shrink(const SBDev& d, hipStream_t s) {
   hipLaunchKernelGGL(sb_shrink_kernel, grid_red(), dim3(256), 0, s, d);

@@ -173,10 +173,14 @@ def blur_zero_bc(P: np.ndarray, cu: int, cv: int, X: np.ndarray) -> np.ndarray:
     """Forward model B = A X (zero boundary conditions) via full 2-D convolution.
 
     B[r, i] = sum_{c,j} P[cu + r - c, cv + i - j] X[c, j] is the window
-    [cu : cu+n, cv : cv+n] of the full linear convolution of X with P.
+    [cu : cu+n, cv : cv+n] of the full linear convolution of X with P (a direct
+    sum for small sizes, an FP64 FFT convolution for large ones).
     """
     n = X.shape[0]
-    full = scipy.signal.convolve2d(X, P, mode="full")
+    if n * n * P.size <= (1 << 26):
+        full = scipy.signal.convolve2d(X, P, mode="full")      # direct sum
+    else:
+        full = scipy.signal.fftconvolve(X, P, mode="full")     # FP64 FFT, large images
     return full[cu:cu + n, cv:cv + n].copy()
 
 
