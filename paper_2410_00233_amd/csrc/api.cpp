@@ -157,7 +157,7 @@ template <typename T>
 kp_status build_grids(kp_ctx* c, const kp_blur* b, const double* dpsf, hipStream_t s,
                       Grids<T>* g) {
   const int n = b->n;
-  g->ldg = ((2 * n - 1) + 7) & ~7;
+  g->ldg = grid_ld(n);
   const size_t cnt = (size_t)(2 * n - 1) * g->ldg;
   KP_TRY(wsT(c, std::string("G_") + tname<T>(), cnt, &g->G));
   KP_TRY(wsT(c, std::string("Gt_") + tname<T>(), cnt, &g->Gt));
@@ -238,11 +238,18 @@ kp_status block_product16(kp_ctx* c, const Grids<H>& g, int n, int transpose, co
 template <typename T>
 kp_status gemv_product(kp_ctx* c, const Grids<T>& g, int n, int transpose, const T* x, T* y,
                        const T* z, double coef, hipStream_t s) {
+  const double NN = (double)n * n;
+  if constexpr (std::is_same<T, float>::value) {
+    float* xt = nullptr;
+    KP_TRY(wsT(c, "gemv_xt", (size_t)gemv_sx_xt_len(n), &xt));
+    ProfScope ps(c, s, 1, 2.0 * NN * NN);
+    launch_rmat_gemv_sx(transpose ? g.Gt : g.G, g.ldg, n, x, xt, y, z, coef, s);
+    return check_launch(c, "rmat_gemv_sx");
+  }
   BlockPlan gp;
   if (!plan_gemv<T>(n, c->lds_limit, &gp))
     return set_err(c, KP_E_INVAL, "no matrix-vector tiling fits the LDS at this n");
   {
-    const double NN = (double)n * n;
     ProfScope ps(c, s, 1, 2.0 * NN * NN);
     launch_rmat_gemv<T>(gp, transpose ? g.Gt : g.G, g.ldg, n, x, y, z, coef, s);
   }

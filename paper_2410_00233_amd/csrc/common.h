@@ -50,6 +50,16 @@ template <typename H>
 void launch_to16_shifted(const float* in, long ldx, int n, int ncols, H* out, long ldo,
                          hipStream_t s);
 
+// Grid row stride for n: the 2n - 1 entries of a row plus at least 48 zero
+// columns (read by the scalar-x matrix-vector kernel), a multiple of 8.
+inline int grid_ld(int n) { return ((2 * n - 1 + 48) + 7) & ~7; }
+
+// FP32 y = R x - coef * z with x in scalar registers; xt is workspace of
+// gemv_sx_xt_len(n) floats. G must have the row stride grid_ld(n).
+long gemv_sx_xt_len(int n);
+void launch_rmat_gemv_sx(const float* G, int ldg, int n, const float* x, float* xt, float* y,
+                         const float* z, double coef, hipStream_t s);
+
 template <typename T>
 bool plan_gemv(int n, size_t lds_limit, BlockPlan* plan);
 // y = R x - coef * z   (z may be null)

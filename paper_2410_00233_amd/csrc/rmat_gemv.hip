@@ -1,12 +1,15 @@
 // Generated-tile matrix-vector product y = R x - coef * z for the single-vector
 // recurrences of Algorithm 1 (EGKB): s_j = B q_{j-1} - alpha_{j-1} s_{j-1} and
-// q_j = B^T s_j - t_j q_{j-1}. Each generated entry of R is used once, so this
-// is bound by the rate at which the tile is read from LDS, not by MFMA.
+// q_j = B^T s_j - t_j q_{j-1}. Each generated entry of R is used once (one FMA
+// per entry, no MFMA shape), so the kernels are bound by operand delivery and
+// the vector FMA rate.
 //
-// Layout as in the block product: a workgroup owns 16 rows i in each of TJ row
-// blocks j; the 16 + TJ - 1 grid rows they touch sit in LDS. x streams through
-// LDS in chunks of kTKV entries (fixed c), double buffered. With 256 threads and
-// 16*TJ rows, H = 256 / (16*TJ) threads share a row and split its K range.
+// FP64 kernel (the plain double-precision path): as in the block product, a
+// workgroup owns 16 rows i in each of TJ row blocks j; the 16 + TJ - 1 grid
+// rows they touch sit in LDS. x streams through LDS in chunks of kTKV entries
+// (fixed c), double buffered. With 256 threads and 16*TJ rows,
+// H = 256 / (16*TJ) threads share a row and split its K range.
+// FP32 kernel: x in scalar registers, see rmat_gemv_sx_kernel below.
 #include "common.h"
 
 namespace kpsb {
@@ -98,134 +101,163 @@ rmat_gemv_kernel(const T* __restrict__ G, int ldg, int n, const T* __restrict__ 
   }
 }
 
-// FP32 kernel. For every column block c the staged x covers
-// r in [r0_c, r0_c + LEN) with r0_c = -((n - 1 - c) mod 4), so the first slab
-// column it meets, r0_c - c + n - 1, is a multiple of 4: both the slab row and
-// the staged x are then read as aligned float4 (0.5 LDS reads per FMA). Entries
-// with r outside [0, n) are staged as 0. Products of one c (LEN terms) are summed
-// in FP32 and added into an FP64 accumulator.
-template <int TJ, int NT>
-__global__ void __launch_bounds__(NT)
-rmat_gemv4_kernel(const float* __restrict__ G, int ldg, int n, const float* __restrict__ x,
-                  float* __restrict__ y, const float* __restrict__ z, double coef, int SW,
-                  int LEN) {
-  constexpr int SR = 16 + TJ - 1;
-  constexpr int ROWS = 16 * TJ;
-  constexpr int H = NT / ROWS;
-  extern __shared__ __align__(16) unsigned char lds_raw[];
-  float* slab = reinterpret_cast<float*>(lds_raw);
-  float* xbuf = slab + SR * SW;                // 2 x LEN
-  double* red = reinterpret_cast<double*>(xbuf + 2 * LEN);   // NT (H > 1)
+// ---------------------------------------------------------------------------
+// FP32 matrix-vector product with x in scalar registers.
+//
+// All 64 lanes of a wave walk the same sequence of (r, c), so the x entries
+// are the same for the whole wave and are read with scalar loads; each FMA
+// takes x from an SGPR. A lane owns kSxP rows (i, j) of R and reuses every x
+// entry for all of them. Row (i, j) of R is G[a][r - c + n - 1] with
+// a = i - j + n - 1: for a chunk of kSxR consecutive r and c stepping down
+// from n - 1, the needed grid entries slide up by one per step, so each row
+// keeps a register window of its grid row, refilled with one 16-byte load per
+// 4 steps (a ring of four 4-entry slots). Every entry of R is still formed and
+// multiplied (2 n^4 flops per product).
+//
+// x is first re-laid out (launch_gemv_xt) as xt[ch][u][q] = x[r + n c] with
+// r = kSxR ch + q, c = n - 1 - u, zero for r >= n or u >= n, U = steps per
+// chunk rounded up to 16; those zero steps and rows meet zero grid padding
+// (a grid row carries at least 48 zero columns), so they add exact zeros.
+// Workgroup: 16 i x 16 j rows; lane l owns i = i0 + l % 16 and
+// j = j0 + l / 16 + 4 p (p < kSxP); its 4 waves take every 4th chunk of the same
+// rows and their FP64 sums are added in a fixed order. Products of 8 steps are
+// summed in FP32 per row and flushed into FP64.
+constexpr int kSxR = 8;   // r entries per chunk
 
-  const int tid = threadIdx.x;
+__global__ void gemv_xt_kernel(const float* __restrict__ x, int n, int U, int nch,
+                               float* __restrict__ xt) {
+  const long total = (long)nch * U * kSxR;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total;
+       e += (long)gridDim.x * blockDim.x) {
+    const int q = (int)(e % kSxR);
+    const long t = e / kSxR;
+    const int u = (int)(t % U);
+    const int ch = (int)(t / U);
+    const int r = ch * kSxR + q;
+    float v = 0.f;
+    if (r < n && u < n) v = x[r + (long)n * (n - 1 - u)];
+    xt[e] = v;
+  }
+}
+
+// kSxP rows per lane; kSxV waves own different rows (4 kSxP j values each) and
+// walk the same chunks at the same time (their x reads share the scalar cache);
+// kSxW waves per row set split the chunks (r-parts).
+template <int kSxP, int kSxV, int kSxW>
+__global__ void __launch_bounds__(64 * kSxV * kSxW)
+rmat_gemv_sx_kernel(const float* __restrict__ G, int ldg, int n, const float* __restrict__ xt,
+                    int U, float* __restrict__ y, const float* __restrict__ z, double coef) {
+  __shared__ double red[kSxW][kSxV][kSxP][64];
+  const int lane = threadIdx.x & 63;
+  const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int wave = wid / kSxV;          // r-part
+  const int rw = wid % kSxV;            // row set
   const int n_it = (n + 15) >> 4;
-  const int it = blockIdx.x % n_it;
-  const int jt = blockIdx.x / n_it;
-  const int i0 = it * 16;
-  const int j0 = jt * TJ;
-  const int g2 = 2 * n - 1;
-  const int a0 = i0 - j0 - (TJ - 1) + n - 1;
-
-  for (int al = 0; al < SR; ++al) {
-    const int a = a0 + al;
-    const bool rowok = (a >= 0) && (a < g2);
-    const float* src = G + (long)(rowok ? a : 0) * ldg;
-    for (int col = tid; col < SW; col += NT) {
-      float v = 0.f;
-      if (rowok && col < g2) v = src[col];
-      slab[al * SW + col] = v;
+  const int it = blockIdx.x % n_it, jt = blockIdx.x / n_it;
+  const int i = it * 16 + (lane & 15);
+  const int jb = (jt * kSxV + rw) * 4 * kSxP + (lane >> 4);
+  const float* grow[kSxP];
+#pragma unroll
+  for (int p = 0; p < kSxP; ++p) {
+    const int j = jb + 4 * p;
+    const bool ok = i < n && j < n;
+    grow[p] = G + (long)(ok ? i - j + n - 1 : 0) * ldg;
+  }
+  const int nch = (n + kSxR - 1) / kSxR;
+  const int ngrp = U / 4;                 // groups of 4 steps (multiple of 4)
+  double acc[kSxP];
+#pragma unroll
+  for (int p = 0; p < kSxP; ++p) acc[p] = 0.0;
+  for (int ch = wave; ch < nch; ch += kSxW) {
+    const int r0 = ch * kSxR;
+    const float* xp = xt + (long)ch * U * kSxR;
+    float4 S[kSxP][4];
+#pragma unroll
+    for (int p = 0; p < kSxP; ++p)
+#pragma unroll
+      for (int t = 0; t < 3; ++t) S[p][t] = *reinterpret_cast<const float4*>(grow[p] + r0 + 4 * t);
+    float pp[kSxP];
+    for (int g0 = 0; g0 < ngrp; g0 += 4) {
+#pragma unroll
+      for (int gg = 0; gg < 4; ++gg) {
+        const int g = g0 + gg;
+        // slot (g + 3) % 4 <- entries 4(g + 3) .. 4(g + 3) + 3 of the window
+#pragma unroll
+        for (int p = 0; p < kSxP; ++p)
+          S[p][(gg + 3) & 3] = *reinterpret_cast<const float4*>(grow[p] + r0 + 4 * (g + 3));
+        const float* xg = xp + (long)g * 4 * kSxR;   // 4 steps x kSxR entries
+        if ((gg & 1) == 0) {
+#pragma unroll
+          for (int p = 0; p < kSxP; ++p) pp[p] = 0.f;
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+#pragma unroll
+          for (int q = 0; q < kSxR; ++q) {
+            const float xv = xg[v * kSxR + q];
+            const int w = v + q;                   // window entry, 0 .. 10
+            const int sl = (gg + (w >> 2)) & 3;
+#pragma unroll
+            for (int p = 0; p < kSxP; ++p) {
+              const float4 sv = S[p][sl];
+              const float gv = (w & 3) == 0 ? sv.x : (w & 3) == 1 ? sv.y : (w & 3) == 2 ? sv.z : sv.w;
+              pp[p] = fmaf(gv, xv, pp[p]);
+            }
+          }
+        if (gg & 1) {   // 8 steps (64 products per row) summed in FP32
+#pragma unroll
+          for (int p = 0; p < kSxP; ++p) acc[p] += (double)pp[p];
+        }
+      }
     }
   }
-
-  const int rr = tid % ROWS;
-  const int h = tid / ROWS;
-  const int li = rr & 15;
-  const int jg = rr >> 4;
-  const float* arow = slab + (li + (TJ - 1) - jg) * SW;
-  const int nv = LEN >> 2;                 // float4 per column block
-  constexpr int MAXL = (2048 + NT - 1) / NT;   // staged x entries per thread (LEN <= 2048)
-  float st[MAXL];
-  auto load = [&](int c) {
-    const int r0 = -((n - 1 - c) & 3);
 #pragma unroll
-    for (int m = 0; m < MAXL; ++m) {
-      const int kk = tid + NT * m;
-      const int r = r0 + kk;
-      st[m] = (kk < LEN && r >= 0 && r < n) ? x[(long)n * c + r] : 0.f;
-    }
-  };
-  auto store = [&](int buf) {
-    float* xs = xbuf + buf * LEN;
-#pragma unroll
-    for (int m = 0; m < MAXL; ++m) {
-      const int kk = tid + NT * m;
-      if (kk < LEN) xs[kk] = st[m];
-    }
-  };
-  load(0);
-  store(0);
+  for (int p = 0; p < kSxP; ++p) red[wave][rw][p][lane] = acc[p];
   __syncthreads();
-
-  double acc = 0.0;
-  for (int c = 0; c < n; ++c) {
-    if (c + 1 < n) load(c + 1);
-    const int base = -((n - 1 - c) & 3) - c + n - 1;      // multiple of 4
-    const float4* ap = reinterpret_cast<const float4*>(arow + base);
-    const float4* xs = reinterpret_cast<const float4*>(xbuf + (c & 1) * LEN);
-    float p0 = 0.f, p1 = 0.f, p2 = 0.f, p3 = 0.f;
-#pragma unroll 4
-    for (int v = h; v < nv; v += H) {
-      const float4 a = ap[v];
-      const float4 b = xs[v];
-      p0 = fmaf(a.x, b.x, p0);
-      p1 = fmaf(a.y, b.y, p1);
-      p2 = fmaf(a.z, b.z, p2);
-      p3 = fmaf(a.w, b.w, p3);
-    }
-    acc += (double)((p0 + p1) + (p2 + p3));
-    if (c + 1 < n) store((c + 1) & 1);
-    __syncthreads();
-  }
-
-  if (H > 1) {
-    red[tid] = acc;
-    __syncthreads();
-    if (h == 0) {
-      for (int q = 1; q < H; ++q) acc += red[tid + q * ROWS];
-    }
-  }
-  if (h == 0) {
-    const int i = i0 + li;
-    const int j = j0 + jg;
-    if (i < n && j < n) {
-      const long row = i + (long)n * j;
-      double v = acc;
-      if (z) v -= coef * (double)z[row];
-      y[row] = (float)v;
+  if (wave == 0) {
+#pragma unroll
+    for (int p = 0; p < kSxP; ++p) {
+      const int j = jb + 4 * p;
+      if (i < n && j < n) {
+        double v = red[0][rw][p][lane];
+#pragma unroll
+        for (int w = 1; w < kSxW; ++w) v += red[w][rw][p][lane];
+        const long row = i + (long)n * j;
+        if (z) v -= coef * (double)z[row];
+        y[row] = (float)v;
+      }
     }
   }
 }
 
-static int gemv4_len(int n) { return ((n + 3 + 3) / 4) * 4; }
+int gemv_sx_steps(int n) { return ((n + 15) / 16) * 16; }
+long gemv_sx_xt_len(int n) { return (long)((n + kSxR - 1) / kSxR) * gemv_sx_steps(n) * kSxR; }
+
+void launch_rmat_gemv_sx(const float* G, int ldg, int n, const float* x, float* xt, float* y,
+                         const float* z, double coef, hipStream_t s) {
+  const int U = gemv_sx_steps(n);
+  const int nch = (n + kSxR - 1) / kSxR;
+  const long tot = gemv_sx_xt_len(n);
+  long blocks = (tot + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(gemv_xt_kernel, dim3((int)blocks), dim3(256), 0, s, x, n, U, nch, xt);
+  // one row per lane, 8 waves splitting the chunks: the fastest of the shapes
+  // measured (rows per lane 1-8, row-sharing waves 1-8, r-parts 1-16)
+  constexpr int P = 1, V = 1, W = 8;
+  const int grid = ((n + 15) / 16) * ((n + 4 * P * V - 1) / (4 * P * V));
+  hipLaunchKernelGGL((rmat_gemv_sx_kernel<P, V, W>), dim3(grid), dim3(64 * V * W), 0, s, G, ldg,
+                     n, xt, U, y, z, coef);
+}
 
 template <typename T>
 static int gemv_stride(int n) {
-  if (sizeof(T) == 4) {
-    const int W = n + gemv4_len(n) - 1;           // largest slab column + 1
-    return ((W + 63) / 64) * 64 + 4;               // multiple of 4 floats
-  }
   const int nrc = (n + kTKV - 1) / kTKV;
   const int W = nrc * kTKV + n - 1;
   return ((W + 31) / 32) * 32 + 1;
 }
 
-constexpr int kGemvNT = 1024;   // threads of the FP32 kernel (H = 1024 / (16 TJ) per row)
-
 template <typename T>
 static size_t gemv_lds(int n, int TJ) {
-  if (sizeof(T) == 4)
-    return 4 * ((size_t)(16 + TJ - 1) * gemv_stride<T>(n) + 2 * (size_t)gemv4_len(n)) +
-           8 * (size_t)kGemvNT;
   return sizeof(T) * ((size_t)(16 + TJ - 1) * gemv_stride<T>(n) + 2 * (size_t)kTKV);
 }
 
@@ -234,7 +266,6 @@ bool plan_gemv(int n, size_t lds_limit, BlockPlan* plan) {
   static const int cand[] = {16, 8, 4, 2, 1};
   int forced = 0;
   if (const char* e = getenv("KPSB_GEMV_TJ")) forced = atoi(e);
-  if (sizeof(T) == 4 && gemv4_len(n) > 2048) return false;   // staged x per thread
   // the FP64 kernel's static reduction buffer (2 KB) shares the LDS budget
   size_t limit = lds_limit > 4096 ? lds_limit - 4096 : 0;
   for (int TJ : cand) {
@@ -250,7 +281,6 @@ bool plan_gemv(int n, size_t lds_limit, BlockPlan* plan) {
   }
   return false;
 }
-template bool plan_gemv<float>(int, size_t, BlockPlan*);
 template bool plan_gemv<double>(int, size_t, BlockPlan*);
 
 template <typename T, int TJ>
@@ -261,43 +291,6 @@ static void gemv_tj(const BlockPlan& p, const T* G, int ldg, int n, const T* x, 
     (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)p.lds);
   hipLaunchKernelGGL(kern, dim3(p.grid), dim3(256), p.lds, s, G, ldg, n, x, y, z, coef, p.SW);
-}
-
-template <int TJ>
-static void gemv4_tj(const BlockPlan& p, const float* G, int ldg, int n, const float* x,
-                     float* y, const float* z, double coef, hipStream_t s) {
-  auto kern = rmat_gemv4_kernel<TJ, kGemvNT>;
-  if (p.lds > 65536)
-    (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)p.lds);
-  hipLaunchKernelGGL(kern, dim3(p.grid), dim3(kGemvNT), p.lds, s, G, ldg, n, x, y, z, coef,
-                     p.SW, gemv4_len(n));
-}
-
-template <>
-void gemv_tj<float, 16>(const BlockPlan& p, const float* G, int ldg, int n, const float* x,
-                        float* y, const float* z, double coef, hipStream_t s) {
-  gemv4_tj<16>(p, G, ldg, n, x, y, z, coef, s);
-}
-template <>
-void gemv_tj<float, 8>(const BlockPlan& p, const float* G, int ldg, int n, const float* x,
-                       float* y, const float* z, double coef, hipStream_t s) {
-  gemv4_tj<8>(p, G, ldg, n, x, y, z, coef, s);
-}
-template <>
-void gemv_tj<float, 4>(const BlockPlan& p, const float* G, int ldg, int n, const float* x,
-                       float* y, const float* z, double coef, hipStream_t s) {
-  gemv4_tj<4>(p, G, ldg, n, x, y, z, coef, s);
-}
-template <>
-void gemv_tj<float, 2>(const BlockPlan& p, const float* G, int ldg, int n, const float* x,
-                       float* y, const float* z, double coef, hipStream_t s) {
-  gemv4_tj<2>(p, G, ldg, n, x, y, z, coef, s);
-}
-template <>
-void gemv_tj<float, 1>(const BlockPlan& p, const float* G, int ldg, int n, const float* x,
-                       float* y, const float* z, double coef, hipStream_t s) {
-  gemv4_tj<1>(p, G, ldg, n, x, y, z, coef, s);
 }
 
 template <typename T>
@@ -311,8 +304,6 @@ void launch_rmat_gemv(const BlockPlan& p, const T* G, int ldg, int n, const T* x
     default: gemv_tj<T, 1>(p, G, ldg, n, x, y, z, coef, s); break;
   }
 }
-template void launch_rmat_gemv<float>(const BlockPlan&, const float*, int, int, const float*,
-                                      float*, const float*, double, hipStream_t);
 template void launch_rmat_gemv<double>(const BlockPlan&, const double*, int, int,
                                        const double*, double*, const double*, double,
                                        hipStream_t);
