@@ -31,6 +31,25 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 MFMA_FP32_PEAK_TFLOPS = 157.3     # MI355X dense FP32 matrix peak
+
+# HBM bytes per launch of the FP32 block kernel (R X, 30 columns, n = 512) from
+# rocprofv3 FETCH_SIZE / WRITE_SIZE scaled by a plain copy of known size
+# (profiles/rmat_products_n512_hbm_counters.md), valid while the kernel source
+# is the one the counters were taken on.
+BLOCK_TRAFFIC_BYTES = 1.110e9
+BLOCK_TRAFFIC_SRC_SHA1 = "900841815ebad8708d42797b02e9c12854a339c1"
+BLOCK16_TRAFFIC_BYTES = 3.22e8
+BLOCK16_TRAFFIC_SRC_SHA1 = "b418f88af4c618522def266074c50afa02bf3108"
+
+
+def counted_traffic(src, sha, value):
+    """The counter-derived traffic, or None once the kernel source changed."""
+    import hashlib
+    try:
+        with open(os.path.join(ROOT, "paper_2410_00233_amd", "csrc", src), "rb") as f:
+            return value if hashlib.sha1(f.read()).hexdigest() == sha else None
+    except OSError:
+        return None
 MFMA_BF16_PEAK_TFLOPS = 2500.0    # MI355X dense BF16 matrix peak
 HBM_PEAK_GBS = 8000.0
 
@@ -367,6 +386,8 @@ def main():
             "bound": "mfma", "achieved": round(ach16, 3), "peak": MFMA_BF16_PEAK_TFLOPS,
             "unit": "TFLOP/s", "frac": round(ach16 / MFMA_BF16_PEAK_TFLOPS, 4),
             "avg_launch_ms": round(avg16, 4), "launches": int(b16["launches"]),
+            "traffic": counted_traffic("rmat_block16.hip", BLOCK16_TRAFFIC_SRC_SHA1,
+                                       BLOCK16_TRAFFIC_BYTES) if n == 512 else None,
         },
         "roofline": {
             "kernel": "rmat_block_kernel<float,16,1,2> (generated-tile R(A) X, FP32 MFMA 16x16x4)",
@@ -375,7 +396,9 @@ def main():
             "peak": MFMA_FP32_PEAK_TFLOPS,
             "unit": "TFLOP/s",
             "frac": round(achieved / MFMA_FP32_PEAK_TFLOPS, 4),
-            "traffic": None,
+            "traffic": counted_traffic("rmat_block.hip", BLOCK_TRAFFIC_SRC_SHA1,
+                                       BLOCK_TRAFFIC_BYTES) if n == 512 else None,
+            "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE)",
             "avg_launch_ms": round(avg_blk_ms, 4),
             "launches": int(blk["launches"]),
             "flops_per_launch": flops_blk,
