@@ -124,7 +124,7 @@ __device__ __forceinline__ doublex4 mfma16x16x4(double a, double b, doublex4 c) 
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
-constexpr int kTK = 32;   // K-tile (entries of r per staged X tile)
+constexpr int kTK = 64;   // K-tile (entries of r per staged X tile)
 constexpr int kXS = 48;   // LDS row stride of the staged X tile (bank-conflict free)
 
 template <typename T, int TJ, int JB, int CB>
@@ -168,7 +168,8 @@ rmat_block_kernel(const T* __restrict__ G, int ldg, int n, const T* __restrict__
   const int nrc = (n + kTK - 1) / kTK;       // r-chunks per column block c
   const int total = n * nrc;
 
-  // staged X element e = tid + NT*m: kk = e % kTK, col = e / kTK
+  // staged X element e = tid + NT*m: col = e % 32, kk = e / 32 (a wave writes
+  // whole rows of the staged tile: no LDS bank conflicts on the stores)
   T stage[LPT];
   auto load_tile = [&](int t) {
     const int c = t / nrc;
@@ -176,8 +177,8 @@ rmat_block_kernel(const T* __restrict__ G, int ldg, int n, const T* __restrict__
 #pragma unroll
     for (int m = 0; m < LPT; ++m) {
       const int e = tid + NT * m;
-      const int kk = e % kTK;
-      const int col = e / kTK;
+      const int col = e % 32;
+      const int kk = e / 32;
       const int r = r0 + kk;
       T v = (T)0;
       if (r < n && col < ncols) v = X[(long)col * ldx + (long)n * c + r];
@@ -189,7 +190,7 @@ rmat_block_kernel(const T* __restrict__ G, int ldg, int n, const T* __restrict__
 #pragma unroll
     for (int m = 0; m < LPT; ++m) {
       const int e = tid + NT * m;
-      xs[(e % kTK) * kXS + e / kTK] = stage[m];
+      xs[(e / 32) * kXS + e % 32] = stage[m];
     }
   };
 
@@ -275,7 +276,7 @@ template <typename T>
 static int slab_stride(int n) {
   const int nrc = (n + kTK - 1) / kTK;
   const int W = nrc * kTK + n - 1;
-  if (sizeof(T) == 4) return ((W + 63) / 64) * 64 + 4;     // 4 (mod 64) floats
+  if (sizeof(T) == 4) return ((W + 63) / 64) * 64 + 2;     // 2 (mod 64) floats
   return ((W + 31) / 32) * 32 + 2;                         // 2 (mod 32) doubles
 }
 
