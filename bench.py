@@ -291,25 +291,32 @@ def main():
 
     log(f"step {ms_step:.1f} ms ({value:.1f} TFLOP/s); BF16 + refinement RSVD")
     # the reduced-precision variant: RSVD with BF16 block products + refinement
+    # (refine = 2: the refinement product from split FP16 MFMA products; the
+    # refine = 1 variant with an FP32 product is timed beside it)
     f_ref = flops.rmat_product(n, k)
-    ctx.kp_svd_rsvd(blur, k, p_rsvd, q, prec="bf16", refine=True, seed=2, factor_prec="f64")
+    ctx.kp_svd_rsvd(blur, k, p_rsvd, q, prec="bf16", refine=2, seed=2, factor_prec="f64")
     torch.cuda.synchronize()
     ctx.kp_prof_enable(True)
     tb = []
     for _ in range(args.steps):
         ta = time.perf_counter()
-        fb = ctx.kp_svd_rsvd(blur, k, p_rsvd, q, prec="bf16", refine=True, seed=2, factor_prec="f64")
+        fb = ctx.kp_svd_rsvd(blur, k, p_rsvd, q, prec="bf16", refine=2, seed=2, factor_prec="f64")
         tb.append(1e3 * (time.perf_counter() - ta))
     ctx.kp_prof_enable(False)
     prof16 = ctx.kp_prof_read(reset=True)
+    tb1 = []
+    for _ in range(args.steps):
+        ta = time.perf_counter()
+        fb1 = ctx.kp_svd_rsvd(blur, k, p_rsvd, q, prec="bf16", refine=1, seed=2, factor_prec="f64")
+        tb1.append(1e3 * (time.perf_counter() - ta))
     b16 = prof16["block16"]
     avg16 = b16["ms"] / max(b16["launches"], 1)
     ach16 = (b16["flops"] / max(b16["launches"], 1)) / (avg16 * 1e-3) / 1e12
     bf_ms = float(np.median(tb))
+    bf1_ms = float(np.median(tb1))
     sig_diff = float(np.abs(fb.sigma[:k] - fr.sigma[:k]).max() / fr.sigma[0])
+    sig_diff1 = float(np.abs(fb1.sigma[:k] - fr.sigma[:k]).max() / fr.sigma[0])
 
-    # split Bregman solve latency at n = 256 (isotropic, 50 outer iterations,
-    # CGLS tau = 1e-4, I_max = 100) with FP64 factors from the FP32 RSVD
     log("split Bregman latency at n=256")
     ns = 256
     Ps, cus, cvs, xs_true, bs_true, bs = wl.deblur_problem(ns, "gaussian", 0.01, 0)
@@ -370,6 +377,9 @@ def main():
             "rsvd_bf16_refine_tflops": round((f_rsvd + f_ref) / (bf_ms * 1e-3) / 1e12, 3),
             "rsvd_bf16_refine_speedup_vs_fp32": round(float(np.median(comp["rsvd_ms"])) / bf_ms, 3),
             "rsvd_bf16_refine_max_sigma_diff_vs_fp32_over_sigma1": sig_diff,
+            "rsvd_bf16_refine_product": "split FP16 (three FP16 MFMA products of two-term splits)",
+            "rsvd_bf16_refine_fp32_product_ms": round(bf1_ms, 3),
+            "rsvd_bf16_refine_fp32_product_max_sigma_diff_vs_fp32_over_sigma1": sig_diff1,
         },
         "sb_solve_n256": {
             "kind": "isotropic split Bregman, 50 outer iterations, CGLS tau 1e-4 (I_max 100), "

@@ -94,7 +94,10 @@ typedef struct {
   kp_prec prec;         /* KP_F32, KP_F64, or KP_BF16 / KP_F16 (block products in
                            16-bit inputs with FP32 accumulation)                   */
   int32_t refine;       /* 1: second reorthogonalization + Rayleigh-Ritz refinement
-                           of the rank-k factors with an FP32 product              */
+                           of the rank-k factors with an FP32 product W = R V;
+                           2: the same with W from three FP16 MFMA products of
+                           two-term FP16 splits of R and V (about 2^-22 relative,
+                           FP32-level); 0: none                                    */
   uint64_t seed;        /* Philox seed for F when F == NULL                        */
   const double* F;      /* optional HOST sketch, n^2 x (k+p) column-major          */
 } kp_rsvd_opts;

@@ -235,6 +235,41 @@ kp_status block_product16(kp_ctx* c, const Grids<H>& g, int n, int transpose, co
   return check_launch(c, "rmat_block16");
 }
 
+// W = R V (ncols columns, FP32 in and out) to about FP32 accuracy from three
+// FP16 MFMA products: with R s = G_hi + G_lo and V 2^kSplitXExp = V_hi + V_lo
+// (two-term FP16 splits, power-of-2 scalings), W = (G_hi V_hi + G_hi V_lo +
+// G_lo V_hi) / (s 2^kSplitXExp); the dropped G_lo V_lo term is about 2^-22 of
+// the product. Accumulated in FP64 inside each product, in FP32 across them.
+kp_status split16_product(kp_ctx* c, const kp_blur* b, const double* dpsf, int n,
+                          const float* V, float* W, int ncols, hipStream_t s) {
+  BlockPlan bp;
+  if (!plan_block16(n, c->lds_limit, &bp))
+    return set_err(c, KP_E_INVAL, "no 16-bit block-product tiling fits the LDS at this n");
+  const long N = (long)n * n;
+  const int ldg = grid_ld(n);
+  const size_t gcount = (size_t)(2 * n - 1) * ldg;
+  double* scal = nullptr;
+  __half *Ghi = nullptr, *Glo = nullptr, *Xhi = nullptr, *Xlo = nullptr;
+  KP_TRY(wsT(c, "split_scal", 2, &scal));
+  KP_TRY(wsT(c, "G_split_hi", gcount, &Ghi));
+  KP_TRY(wsT(c, "G_split_lo", gcount, &Glo));
+  const long ld16 = x16_column_len(n);
+  KP_TRY(wsT(c, "x_split_hi", (size_t)ld16 * ncols, &Xhi));
+  KP_TRY(wsT(c, "x_split_lo", (size_t)ld16 * ncols, &Xlo));
+  launch_psf_split_scale(dpsf, (long)b->pu * b->pv, scal, s);
+  launch_build_grid_split(dpsf, b->pu, b->pv, b->cu, b->cv, n, 0, scal, 0, Ghi, ldg, s);
+  launch_build_grid_split(dpsf, b->pu, b->pv, b->cu, b->cv, n, 0, scal, 1, Glo, ldg, s);
+  launch_to16_split(V, N, n, ncols, Xhi, Xlo, ld16, s);
+  for (int c0 = 0; c0 < ncols; c0 += 32) {
+    const int nc = ncols - c0 < 32 ? ncols - c0 : 32;
+    float* Wc = W + N * c0;
+    launch_rmat_block16<__half>(bp, Ghi, ldg, n, Xhi + ld16 * c0, ld16, Wc, N, nc, s, scal + 1, 0);
+    launch_rmat_block16<__half>(bp, Ghi, ldg, n, Xlo + ld16 * c0, ld16, Wc, N, nc, s, scal + 1, 1);
+    launch_rmat_block16<__half>(bp, Glo, ldg, n, Xhi + ld16 * c0, ld16, Wc, N, nc, s, scal + 1, 1);
+  }
+  return check_launch(c, "split16_product");
+}
+
 template <typename T>
 kp_status gemv_product(kp_ctx* c, const Grids<T>& g, int n, int transpose, const T* x, T* y,
                        const T* z, double coef, hipStream_t s) {
@@ -670,7 +705,12 @@ kp_status rsvd_impl(kp_ctx* c, const kp_blur* b, const kp_rsvd_opts* o, kp_facto
     T* W = Z;
     launch_convert<double, T>(Vd, Vf, N * kout, s);
     KP_TRY(cgs_qr<T>(c, sc, Vf, N, kout, nullptr, o->seed, sb += 64, s));
-    KP_TRY(block_product<T>(c, g, n, 0, Vf, W, kout, s));
+    if constexpr (std::is_same<T, float>::value) {
+      if (o->refine == 2) KP_TRY(split16_product(c, b, dpsf, n, Vf, W, kout, s));
+      else KP_TRY(block_product<T>(c, g, n, 0, Vf, W, kout, s));
+    } else {
+      KP_TRY(block_product<T>(c, g, n, 0, Vf, W, kout, s));
+    }
     KP_TRY(cgs_qr<T>(c, sc, W, N, kout, Rh, o->seed, sb += 64, s));
     launch_jacobi_svd(Rh, kout, kout, Ur, sig, Vr, sweeps, s);
     launch_small_gemm<T, double>(W, N, kout, Ur, kout, kout, N, Ud, N, s);
@@ -1020,7 +1060,7 @@ kp_status kp_svd_rsvd(kp_ctx* c, const kp_blur* b, const kp_rsvd_opts* o, kp_fac
       if (!std::isfinite(o->F[e])) return set_err(c, KP_E_NUMERIC, "F has a non-finite entry");
   KP_HIP(c, hipSetDevice(c->device));
   hipStream_t s = (hipStream_t)stream;
-  if (o->refine != 0 && o->refine != 1) return set_err(c, KP_E_INVAL, "refine must be 0 or 1");
+  if (o->refine < 0 || o->refine > 2) return set_err(c, KP_E_INVAL, "refine must be 0, 1 or 2");
   if (o->prec == KP_F32 || o->prec == KP_BF16 || o->prec == KP_F16)
     return rsvd_impl<float>(c, b, o, f, s);
   if (o->prec == KP_F64) return rsvd_impl<double>(c, b, o, f, s);

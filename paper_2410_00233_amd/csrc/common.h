@@ -42,9 +42,26 @@ void launch_rmat_block(const BlockPlan& plan, const T* G, int ldg, int n, const 
 // FP32 accumulation, FP32 output. X16 is the pre-shifted 16-bit copy made by
 // launch_to16_shifted, x16_column_len(n) elements per column.
 bool plan_block16(int n, size_t lds_limit, BlockPlan* plan);
+// inv_scale (device, may be null) multiplies the result (undoes power-of-2
+// operand scaling); accumulate != 0 adds the result into Y.
 template <typename H>
 void launch_rmat_block16(const BlockPlan& plan, const H* G16, int ldg, int n, const H* X16,
-                         long ldx, float* Y, long ldy, int ncols, hipStream_t s);
+                         long ldx, float* Y, long ldy, int ncols, hipStream_t s,
+                         const double* inv_scale = nullptr, int accumulate = 0);
+
+// Split FP16 operands of the refinement product (FP32-level accuracy from three
+// FP16 products): X scaled by 2^kSplitXExp into hi + lo; the grid scaled by a
+// power of two computed on the device (launch_psf_split_scale) into hi + lo.
+constexpr int kSplitXExp = 11;
+void launch_to16_split(const float* in, long ldx, int n, int ncols, __half* hi, __half* lo,
+                       long ldo, hipStream_t s);
+// scal[0] = 2^e with e the largest integer such that max|P| * 2^e <= 1024;
+// scal[1] = 1 / (scal[0] * 2^kSplitXExp). Device only, no host sync.
+void launch_psf_split_scale(const double* psf, long count, double* scal, hipStream_t s);
+// FP16 grid of the scaled PSF: part 0 = fp16(P s), part 1 = fp16(P s - part 0).
+void launch_build_grid_split(const double* psf, int pu, int pv, int cu, int cv, int n,
+                             int transpose, const double* scal, int part, __half* G, int ldg,
+                             hipStream_t s);
 long x16_column_len(int n);
 template <typename H>
 void launch_to16_shifted(const float* in, long ldx, int n, int ncols, H* out, long ldo,

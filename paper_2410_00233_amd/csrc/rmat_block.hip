@@ -88,6 +88,70 @@ __global__ void build_grid_kernel<__half>(const double* __restrict__ psf, int pu
   }
 }
 
+__global__ void psf_split_scale_kernel(const double* __restrict__ psf, long count,
+                                       double* __restrict__ scal) {
+  __shared__ double sh[256];
+  double m = 0.0;
+  for (long e = threadIdx.x; e < count; e += 256) m = fmax(m, fabs(psf[e]));
+  sh[threadIdx.x] = m;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    double sc = 1.0;
+    const double mx = sh[0];
+    if (mx > 0.0) {
+      int ex = 0;
+      (void)frexp(1024.0 / mx, &ex);      // 1024 / mx = f 2^ex, f in [0.5, 1)
+      sc = ldexp(1.0, ex - 1);            // largest 2^e <= 1024 / mx
+    }
+    scal[0] = sc;
+    scal[1] = 1.0 / (sc * (double)(1 << kSplitXExp));
+  }
+}
+
+void launch_psf_split_scale(const double* psf, long count, double* scal, hipStream_t s) {
+  hipLaunchKernelGGL(psf_split_scale_kernel, dim3(1), dim3(256), 0, s, psf, count, scal);
+}
+
+__device__ __forceinline__ __half d2h(double v) { return __half_raw{static_cast<_Float16>(v)}; }
+
+__global__ void build_grid_split_kernel(const double* __restrict__ psf, int pu, int pv, int cu,
+                                        int cv, int n, int transpose,
+                                        const double* __restrict__ scal, int part,
+                                        __half* __restrict__ G, int ldg) {
+  const int g2 = 2 * n - 1;
+  const long total = (long)g2 * ldg;
+  const double sc = scal[0];
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total;
+       e += (long)gridDim.x * blockDim.x) {
+    int a = (int)(e / ldg);
+    int b = (int)(e - (long)a * ldg);
+    double v = 0.0;
+    if (b < g2) {
+      int aa = transpose ? b : a;
+      int bb = transpose ? a : b;
+      int u = cu + bb - (n - 1);
+      int w = cv + aa - (n - 1);
+      if (u >= 0 && u < pu && w >= 0 && w < pv) v = psf[(long)u * pv + w] * sc;
+    }
+    const __half h = d2h(v);
+    G[e] = part == 0 ? h : d2h(v - (double)__half2float(h));
+  }
+}
+
+void launch_build_grid_split(const double* psf, int pu, int pv, int cu, int cv, int n,
+                             int transpose, const double* scal, int part, __half* G, int ldg,
+                             hipStream_t s) {
+  long total = (long)(2 * n - 1) * ldg;
+  int blocks = (int)((total + 255) / 256);
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(build_grid_split_kernel, dim3(blocks), dim3(256), 0, s, psf, pu, pv, cu,
+                     cv, n, transpose, scal, part, G, ldg);
+}
+
 template <typename T>
 void launch_build_grid(const double* psf, int pu, int pv, int cu, int cv, int n,
                        int transpose, T* G, int ldg, hipStream_t s) {

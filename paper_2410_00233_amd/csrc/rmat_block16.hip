@@ -45,7 +45,8 @@ constexpr int kXS16 = kKS * kSPT + 8;   // LDS row stride of the staged X tile (
 template <typename H, int TJ, int JB, int CB>
 __global__ void __launch_bounds__(64 * (2 * TJ) / (JB * CB))
 rmat_block16_kernel(const H* __restrict__ G, int ldg, int n, const H* __restrict__ X, long ldx,
-                    float* __restrict__ Y, long ldy, int ncols, int SW, int LEN) {
+                    float* __restrict__ Y, long ldy, int ncols, int SW, int LEN,
+                    const double* __restrict__ inv_scale, int accumulate) {
   constexpr int WAVES = (2 * TJ) / (JB * CB);
   constexpr int NT = 64 * WAVES;
   constexpr int SR = 16 + TJ - 1;
@@ -171,6 +172,7 @@ rmat_block16_kernel(const H* __restrict__ G, int ldg, int n, const H* __restrict
     __syncthreads();
   }
 
+  const double osc = inv_scale ? *inv_scale : 1.0;   // undo the operands' power-of-2 scaling
 #pragma unroll
   for (int jb = 0; jb < JB; ++jb) {
     const int j = j0 + wj * JB + jb;
@@ -180,7 +182,11 @@ rmat_block16_kernel(const H* __restrict__ G, int ldg, int n, const H* __restrict
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const int i = i0 + 4 * lg + e;
-        if (i < n && j < n && col < ncols) Y[(long)col * ldy + i + (long)n * j] = (float)accd[jb][cb][e];
+        if (i < n && j < n && col < ncols) {
+          float* yp = Y + (long)col * ldy + i + (long)n * j;
+          const double v = accd[jb][cb][e] * osc;
+          *yp = accumulate ? (float)((double)*yp + v) : (float)v;
+        }
       }
     }
   }
@@ -225,31 +231,34 @@ bool plan_block16(int n, size_t lds_limit, BlockPlan* plan) {
 
 template <typename H, int TJ, int JB, int CB>
 static void launch16_tj(const BlockPlan& p, const H* G, int ldg, int n, const H* X, long ldx,
-                        float* Y, long ldy, int ncols, hipStream_t s) {
+                        float* Y, long ldy, int ncols, const double* inv_scale, int accumulate,
+                        hipStream_t s) {
   auto kern = rmat_block16_kernel<H, TJ, JB, CB>;
   constexpr int threads = 64 * (2 * TJ) / (JB * CB);
   if (p.lds > 65536)
     (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)p.lds);
   hipLaunchKernelGGL(kern, dim3(p.grid), dim3(threads), p.lds, s, G, ldg, n, X, ldx, Y, ldy,
-                     ncols, p.SW, len16(n));
+                     ncols, p.SW, len16(n), inv_scale, accumulate);
 }
 
 template <typename H>
 void launch_rmat_block16(const BlockPlan& p, const H* G16, int ldg, int n, const H* X16,
-                         long ldx, float* Y, long ldy, int ncols, hipStream_t s) {
+                         long ldx, float* Y, long ldy, int ncols, hipStream_t s,
+                         const double* inv_scale, int accumulate) {
   switch (p.TJ) {
-    case 32: launch16_tj<H, 32, 4, 2>(p, G16, ldg, n, X16, ldx, Y, ldy, ncols, s); break;
-    case 16: launch16_tj<H, 16, 4, 2>(p, G16, ldg, n, X16, ldx, Y, ldy, ncols, s); break;
-    case 8: launch16_tj<H, 8, 2, 2>(p, G16, ldg, n, X16, ldx, Y, ldy, ncols, s); break;
-    default: launch16_tj<H, 4, 1, 2>(p, G16, ldg, n, X16, ldx, Y, ldy, ncols, s); break;
+    case 32: launch16_tj<H, 32, 4, 2>(p, G16, ldg, n, X16, ldx, Y, ldy, ncols, inv_scale, accumulate, s); break;
+    case 16: launch16_tj<H, 16, 4, 2>(p, G16, ldg, n, X16, ldx, Y, ldy, ncols, inv_scale, accumulate, s); break;
+    case 8: launch16_tj<H, 8, 2, 2>(p, G16, ldg, n, X16, ldx, Y, ldy, ncols, inv_scale, accumulate, s); break;
+    default: launch16_tj<H, 4, 1, 2>(p, G16, ldg, n, X16, ldx, Y, ldy, ncols, inv_scale, accumulate, s); break;
   }
 }
 template void launch_rmat_block16<__hip_bfloat16>(const BlockPlan&, const __hip_bfloat16*, int,
                                                   int, const __hip_bfloat16*, long, float*,
-                                                  long, int, hipStream_t);
+                                                  long, int, hipStream_t, const double*, int);
 template void launch_rmat_block16<__half>(const BlockPlan&, const __half*, int, int,
-                                          const __half*, long, float*, long, int, hipStream_t);
+                                          const __half*, long, float*, long, int, hipStream_t,
+                                          const double*, int);
 
 // FP32 X (N x ncols, ld ldx) -> pre-shifted 16-bit copy (see rmat_block16_kernel):
 // out[col * ldo + c * LEN + kk] = X[col * ldx + c * n + r0_c + kk] for
@@ -283,5 +292,37 @@ void launch_to16_shifted(const float* in, long ldx, int n, int ncols, H* out, lo
 template void launch_to16_shifted<__hip_bfloat16>(const float*, long, int, int, __hip_bfloat16*,
                                                   long, hipStream_t);
 template void launch_to16_shifted<__half>(const float*, long, int, int, __half*, long, hipStream_t);
+
+// Two-term FP16 split of the pre-shifted copy: with v' = v * 2^kSplitXExp,
+// hi = fp16(v') and lo = fp16(v' - hi) (the residual is exact in FP32), so
+// hi + lo carries about 22 significant bits of v. Columns of unit norm have
+// |v| <= 1, i.e. |v'| <= 2048, inside FP16's range; the scaling keeps their
+// entries away from FP16's subnormal range.
+__global__ void to16_split_kernel(const float* __restrict__ in, long ldx, int n, int ncols,
+                                  int LEN, __half* __restrict__ hi, __half* __restrict__ lo,
+                                  long ldo) {
+  const long per_col = (long)n * LEN;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < (long)ldo * ncols;
+       e += (long)gridDim.x * blockDim.x) {
+    const int col = (int)(e / ldo);
+    const long o = e - (long)col * ldo;
+    float v = 0.f;
+    if (o < per_col) {
+      const int c = (int)(o / LEN);
+      const int kk = (int)(o - (long)c * LEN);
+      const int r = -((n - 1 - c) & 7) + kk;
+      if (r >= 0 && r < n) v = in[(long)col * ldx + (long)n * c + r];
+    }
+    const float vs = v * (float)(1 << kSplitXExp);
+    const __half h = __float2half(vs);
+    hi[e] = h;
+    lo[e] = __float2half(vs - __half2float(h));
+  }
+}
+void launch_to16_split(const float* in, long ldx, int n, int ncols, __half* hi, __half* lo,
+                       long ldo, hipStream_t s) {
+  hipLaunchKernelGGL(to16_split_kernel, dim3(2048), dim3(256), 0, s, in, ldx, n, ncols,
+                     len16(n), hi, lo, ldo);
+}
 
 }  // namespace kpsb

@@ -199,3 +199,32 @@ def test_rsvd_reduced_precision_with_refine(ctx, prec, n, psf):
           f"||A-A_k||/||A|| {e_kp:.3e} vs oracle {e_kp_ref:.3e}")
     assert e_ref <= 1e-4
     assert e_kp <= e_kp_ref + 1e-4
+
+
+@pytest.mark.parametrize("prec", ["bf16", "f16"])
+@pytest.mark.parametrize("n,psf", [(128, "speckle"), (512, "gaussian"), (96, "disk")])
+def test_rsvd_refine_with_split_fp16_product(ctx, prec, n, psf):
+    """refine = 2 forms the refinement product W = R V from three FP16 products
+    of two-term splits: sigma within the FP32 gate (1e-5 sigma_1) of the oracle's
+    refined sigma, and within 1e-6 sigma_1 of the FP32-product refinement."""
+    from paper_2410_00233_amd import api
+    k, p, q = 20, 10, 2
+    if psf == "gaussian":
+        P, cu, cv = wl.gaussian_psf(n)
+    elif psf == "disk":
+        P, cu, cv = wl.disk_psf(n)
+    else:
+        P, cu, cv = wl.speckle_psf(n, seed=1002)
+    F = wl.gaussian_block(n * n, k + p, seed=wl.SEED_START + 2)
+    blur = api.Blur(P, cu, cv, n)
+    R, Rt = _ops(P, cu, cv, n)
+    ref = kpsvd.rsvd(R, Rt, F, k, q)
+    ref_r = kpsvd.refine(R, ref["V"])
+    s1 = ref["sigma"][0]
+    f1 = ctx.kp_svd_rsvd(blur, k, p, q, prec=prec, F=F, refine=1)
+    f2 = ctx.kp_svd_rsvd(blur, k, p, q, prec=prec, F=F, refine=2)
+    e2 = np.abs(f2.sigma[:k] - ref_r["sigma"]).max() / s1
+    d12 = np.abs(f2.sigma[:k] - f1.sigma[:k]).max() / s1
+    print(f"RSVD {prec} n={n} {psf}: split-FP16 refine err {e2:.2e}, vs FP32 refine {d12:.2e}")
+    assert e2 <= 1e-5
+    assert d12 <= 1e-6
