@@ -102,3 +102,28 @@ def test_sb_rejects_bad_arguments(ctx):
         ctx.sb_solve_iso(f, _dev(b), -1.0, 0.1)
     with pytest.raises(api.KPError):
         ctx.sb_solve_iso(f, _dev(b), 0.1, 0.1, L_max=0)
+
+
+@pytest.mark.parametrize("kind,taus", [("iso", (0.0, 0.0)), ("aniso", (1e-2, 1e-4))])
+def test_sb_graph_replays_equal_eager_launches(ctx, kind, taus, monkeypatch):
+    """The CGLS iterations run as replays of a captured HIP graph (8 iterations
+    per replay, host flag polls and synchronizations between replays); every
+    replay must compute what the eager launches compute, so the whole solve is
+    bit-identical with graphs on and off."""
+    from paper_2410_00233_amd import api
+    import torch
+    n, k = 48, 6
+    Ax, Ay, b, _ = _problem(n, k, idx=3)
+    f = api.Factors.from_arrays(Ax, Ay)
+    fn = ctx.sb_solve_aniso if kind == "aniso" else ctx.sb_solve_iso
+    kw = dict(L_max=6, I_max=21, tau_sb=taus[0], tau_cgls=taus[1])
+    out = {}
+    for mode in ("1", "0", "1"):
+        monkeypatch.setenv("KPSB_SB_GRAPH", mode)
+        x, st = fn(f, _dev(b), 0.115, 0.115 ** 2 / 2.0, **kw)
+        torch.cuda.synchronize()
+        out.setdefault(mode, []).append((x.cpu().numpy(), st))
+    xg, sg = out["1"][0]
+    xe, se = out["0"][0]
+    assert np.array_equal(xg, xe) and sg == se
+    assert np.array_equal(out["1"][1][0], xg)
