@@ -28,6 +28,7 @@ void launch_build_grid(const double* psf, int pu, int pv, int cu, int cv, int n,
 // ---- generated-tile products (rmat_block.hip / rmat_gemv.hip) --------------
 struct BlockPlan {
   int TJ;      // j-blocks (16 rows each) per workgroup
+  int CP = 0;  // column blocks per slab phase (FP32/FP64 block product)
   int SW;      // LDS slab row stride (elements)
   size_t lds;  // dynamic LDS bytes
   int grid;    // workgroups

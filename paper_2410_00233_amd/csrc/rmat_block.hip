@@ -194,7 +194,7 @@ constexpr int kXS = 48;   // LDS row stride of the staged X tile (bank-conflict 
 template <typename T, int TJ, int JB, int CB>
 __global__ void __launch_bounds__(64 * (2 * TJ) / (JB * CB))
 rmat_block_kernel(const T* __restrict__ G, int ldg, int n, const T* __restrict__ X, long ldx,
-                  T* __restrict__ Y, long ldy, int ncols, int SW) {
+                  T* __restrict__ Y, long ldy, int ncols, int SW, int CP) {
   constexpr int WAVES = (2 * TJ) / (JB * CB);
   constexpr int NT = 64 * WAVES;
   constexpr int SR = 16 + TJ - 1;
@@ -217,17 +217,24 @@ rmat_block_kernel(const T* __restrict__ G, int ldg, int n, const T* __restrict__
   const int g2 = 2 * n - 1;
   const int a0 = i0 - j0 - (TJ - 1) + n - 1;
 
-  // ---- slab: grid rows a0 .. a0 + SR - 1, zero outside the grid ----------
-  for (int al = 0; al < SR; ++al) {
-    const int a = a0 + al;
-    const bool rowok = (a >= 0) && (a < g2);
-    const T* src = G + (long)(rowok ? a : 0) * ldg;
-    for (int col = tid; col < SW; col += NT) {
-      T v = (T)0;
-      if (rowok && col < g2) v = src[col];
-      slab[al * SW + col] = v;
+  // ---- slab: grid rows a0 .. a0 + SR - 1, zero outside the grid. Column
+  // blocks c are processed in phases of CP; a phase needs the slab columns
+  // [n - c0 - CP, n - c0 - CP + SW) only (all of them when CP = n).
+  auto load_slab = [&](int c0) {
+    const int cbase = n - c0 - CP;
+    for (int al = 0; al < SR; ++al) {
+      const int a = a0 + al;
+      const bool rowok = (a >= 0) && (a < g2);
+      const T* src = G + (long)(rowok ? a : 0) * ldg;
+      for (int col = tid; col < SW; col += NT) {
+        const int gc = cbase + col;
+        T v = (T)0;
+        if (rowok && gc >= 0 && gc < g2) v = src[gc];
+        slab[al * SW + col] = v;
+      }
     }
-  }
+  };
+  load_slab(0);
 
   const int nrc = (n + kTK - 1) / kTK;       // r-chunks per column block c
   const int total = n * nrc;
@@ -284,10 +291,15 @@ rmat_block_kernel(const T* __restrict__ G, int ldg, int n, const T* __restrict__
   __syncthreads();
 
   for (int c = 0; c < n; ++c) {
+    if (c > 0 && c % CP == 0) {     // next phase: every wave is past the last tile's barrier
+      load_slab(c);
+      __syncthreads();
+    }
+    const int c0 = c - c % CP;
     for (int rt = 0; rt < nrc; ++rt) {
       const int t = c * nrc + rt;
       if (t + 1 < total) load_tile(t + 1);
-      const int colbase = rt * kTK - c + n - 1;
+      const int colbase = rt * kTK - c + c0 + CP - 1;   // slab column of r = rt * kTK
       const T* xs = xbuf + (t & 1) * (kTK * kXS);
 #pragma unroll
       for (int s = 0; s < kTK / 4; ++s) {
@@ -336,33 +348,43 @@ rmat_block_kernel(const T* __restrict__ G, int ldg, int n, const T* __restrict__
   }
 }
 
+// Slab row stride for phases of CP column blocks: r covers nrc whole K tiles
+// and c spans CP values, so a row needs nrc * kTK + CP - 1 columns.
 template <typename T>
-static int slab_stride(int n) {
+static int slab_stride(int n, int CP) {
   const int nrc = (n + kTK - 1) / kTK;
-  const int W = nrc * kTK + n - 1;
+  const int W = nrc * kTK + CP - 1;
   if (sizeof(T) == 4) return ((W + 63) / 64) * 64 + 2;     // 2 (mod 64) floats
   return ((W + 31) / 32) * 32 + 2;                         // 2 (mod 32) doubles
 }
 
 template <typename T>
-static size_t block_lds(int n, int TJ) {
-  return sizeof(T) * ((size_t)(16 + TJ - 1) * slab_stride<T>(n) + 2 * kTK * kXS);
+static size_t block_lds(int n, int TJ, int CP) {
+  return sizeof(T) * ((size_t)(16 + TJ - 1) * slab_stride<T>(n, CP) + 2 * kTK * kXS);
 }
 
+// The largest row-block count TJ whose slab fits the LDS with whole column
+// blocks in one phase or, for large n, in phases of CP >= 64 column blocks
+// (the slab is reloaded per phase: (n / CP) x SR rows per workgroup).
 template <typename T>
 bool plan_block(int n, size_t lds_limit, BlockPlan* plan) {
   static const int cand[] = {16, 8, 4, 2, 1};
-  int forced = 0;
+  int forced = 0, cp_max = n;
   if (const char* e = getenv("KPSB_BLOCK_TJ")) forced = atoi(e);
+  if (const char* e = getenv("KPSB_BLOCK_CP")) cp_max = std::max(1, std::min(n, atoi(e)));
   for (int TJ : cand) {
     if (forced && TJ != forced) continue;
-    size_t lds = block_lds<T>(n, TJ);
-    if (lds <= lds_limit) {
-      plan->TJ = TJ;
-      plan->SW = slab_stride<T>(n);
-      plan->lds = lds;
-      plan->grid = ((n + 15) / 16) * ((n + TJ - 1) / TJ);
-      return true;
+    for (int CP = cp_max; CP >= 1; CP = (CP > 64 ? (CP + 1) / 2 : 0)) {
+      const size_t lds = block_lds<T>(n, TJ, CP);
+      if (lds <= lds_limit) {
+        plan->TJ = TJ;
+        plan->CP = CP;
+        plan->SW = slab_stride<T>(n, CP);
+        plan->lds = lds;
+        plan->grid = ((n + 15) / 16) * ((n + TJ - 1) / TJ);
+        return true;
+      }
+      if (CP <= 64) break;
     }
   }
   return false;
@@ -379,7 +401,7 @@ static void launch_tj(const BlockPlan& p, const T* G, int ldg, int n, const T* X
     (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)p.lds);
   hipLaunchKernelGGL(kern, dim3(p.grid), dim3(threads), p.lds, s, G, ldg, n, X, ldx, Y, ldy,
-                     ncols, p.SW);
+                     ncols, p.SW, p.CP);
 }
 
 template <typename T>

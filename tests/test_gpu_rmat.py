@@ -59,7 +59,24 @@ def test_product_matches_explicit_R(ctx, n, shape, seed, ncols, prec):
         _check(Y.reshape(n * n, -1), (R.T if tr else R), X, prec)
 
 
-@pytest.mark.parametrize("n,prec", [(256, "f32"), (512, "f32"), (128, "f64")])
+@pytest.mark.parametrize("n,cp", [(48, 16), (33, 10), (70, 64), (16, 1)])
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_block_product_in_column_phases(ctx, n, cp, prec, monkeypatch):
+    """The slab of grid columns reloaded per phase of cp column blocks (how large
+    n fits the LDS), forced at small n, including a ragged last phase."""
+    monkeypatch.setenv("KPSB_BLOCK_CP", str(cp))
+    P, cu, cv = wl.random_psf(2 * n - 1, 2 * n - 1, n + cp)
+    idx = np.arange(n * n)
+    R = op.rmat_entries(P, cu, cv, n, idx, idx)
+    X = np.random.default_rng(cp).standard_normal((n * n, 32))
+    if prec == "f32":
+        X = X.astype(np.float32).astype(np.float64)
+    for tr in (False, True):
+        Y = _run(ctx, P, cu, cv, n, X, tr, prec).reshape(n * n, -1)
+        _check(Y, (R.T if tr else R), X, prec)
+
+
+@pytest.mark.parametrize("n,prec", [(256, "f32"), (512, "f32"), (128, "f64"), (1024, "f32")])
 @pytest.mark.parametrize("ncols", [1, 32])
 def test_product_full_size_sampled_rows(ctx, n, prec, ncols):
     # the configured workload: rotated Gaussian on the full (2n-1)^2 grid
