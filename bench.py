@@ -421,6 +421,7 @@ def main():
         sizes = tuple(int(v) for v in args.serve_sizes.split(","))
         log(f"serving, {args.serve} requests at {args.serve_rate}/s")
         line["serving"] = bench_serving(ctx, args.serve, args.serve_rate, sizes)
+    line["autotune"] = ctx.kp_tune_report()
     if not args.no_cpu_baseline:
         log("CPU oracle baseline")
         line["cpu_baseline"] = cpu_baseline(n, k + p_rsvd, args.cpu_seconds)

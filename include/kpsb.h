@@ -170,6 +170,15 @@ kp_status kp_prof_enable(kp_ctx* ctx, int enable);
 kp_status kp_prof_read(kp_ctx* ctx, kp_prof* out, int reset);
 /* Library version string (static storage). */
 const char* kp_version(void);
+/* Autotuner report: the launch variant chosen for every (operation, size) met so
+ * far in this process and the measured cost of each candidate (ms per row of R
+ * for the block products, ms per apply for the Kronecker GEMMs), as JSON text.
+ * The first call of an operation at a new size times its candidates on the
+ * call's stream (one warm-up and two sample launches each) and keeps the
+ * fastest; all candidates give bitwise-identical results. KPSB_AUTOTUNE=0 in
+ * the environment keeps every operation at its first variant. out: HOST buffer
+ * of cap bytes, NUL-terminated, truncated if short. */
+kp_status kp_tune_report(char* out, size_t cap);
 
 /* Y = R X (transpose = 0) or Y = R^T X (transpose = 1), the dense product with
  * generated tiles of R(A) (the dominant step of both Algorithms 1 and 2,

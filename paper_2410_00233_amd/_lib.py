@@ -27,7 +27,7 @@ EXPORTED = ["kp_ctx_create", "kp_ctx_destroy", "kp_last_error", "kp_version",
             "kp_rmat_apply", "kp_svd_gkb", "kp_svd_rsvd", "kp_apply",
             "sb_solve_aniso", "sb_solve_iso", "kp_svd_batched",
             "kp_server_create", "kp_server_submit", "kp_server_wait", "kp_server_stats",
-            "kp_server_destroy"]
+            "kp_server_destroy", "kp_tune_report"]
 
 
 class kp_blur(C.Structure):
@@ -128,6 +128,7 @@ def load(path: str = LIB_PATH):
     lib.kp_server_wait.argtypes = [vp, C.c_uint64, C.c_double, C.POINTER(kp_result)]
     lib.kp_server_stats.argtypes = [vp, C.POINTER(C.c_int64)]
     lib.kp_server_destroy.argtypes = [vp]
+    lib.kp_tune_report.argtypes = [C.c_char_p, C.c_size_t]
     for name in EXPORTED:
         if name not in ("kp_last_error", "kp_version"):
             getattr(lib, name).restype = C.c_int

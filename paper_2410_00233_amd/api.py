@@ -115,6 +115,14 @@ class Context:
             raise KPError(st, self.lib.kp_last_error(self.h).decode())
         return st
 
+    # ---- autotuner ------------------------------------------------------------
+    def kp_tune_report(self):
+        """Chosen launch variants and measured candidate costs (list of dicts)."""
+        import json
+        buf = C.create_string_buffer(1 << 16)
+        self._check(self.lib.kp_tune_report(buf, len(buf)))
+        return json.loads(buf.value.decode())
+
     # ---- tracing ------------------------------------------------------------
     def kp_prof_enable(self, enable=True):
         self._check(self.lib.kp_prof_enable(self.h, int(enable)))

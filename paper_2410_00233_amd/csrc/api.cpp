@@ -196,13 +196,44 @@ struct ProfScope {
   }
 };
 
+// Autotuned launch shapes of the block products: the cost of a variant is the
+// time of a sample launch (the first 1024 workgroups) per row of R it covers.
+constexpr int kSampleWG = 1024;
+struct BlockVariant {
+  int TJ, waves;
+};
+constexpr BlockVariant kBlockVariants[] = {{16, 16}, {16, 8}, {8, 8}, {8, 16}};
+constexpr int kBlock16Variants[] = {32, 16};
+
+template <typename T>
+kp_status choose_block_plan(kp_ctx* c, const Grids<T>& g, int n, const T* X, T* Y, int nc,
+                            hipStream_t s, BlockPlan* bp) {
+  const long N = (long)n * n;
+  const int v = tune_pick(kTuneBlock, n, (int)sizeof(T), 0, 4, [&](int k) -> double {
+    BlockPlan p;
+    if (!plan_block_tj<T>(n, c->lds_limit, kBlockVariants[k].TJ, &p)) return -1.0;
+    p.waves = kBlockVariants[k].waves;
+    p.grid_limit = std::min(p.grid, kSampleWG);
+    const double ms = time_launches(s, 2, [&]() {
+      launch_rmat_block<T>(p, g.G, g.ldg, n, X, N, Y, N, nc, s);
+    });
+    return ms < 0 ? -1.0 : ms / ((double)std::min(p.grid, kSampleWG) * 16.0 * p.TJ);
+  });
+  if (!plan_block_tj<T>(n, c->lds_limit, kBlockVariants[v].TJ, bp)) {
+    if (!plan_block<T>(n, c->lds_limit, bp))
+      return set_err(c, KP_E_INVAL, "no block-product tiling fits the LDS at this n");
+    return KP_OK;
+  }
+  bp->waves = kBlockVariants[v].waves;
+  return KP_OK;
+}
+
 // Y = R X (or R^T X) for any number of columns (groups of 32 per launch).
 template <typename T>
 kp_status block_product(kp_ctx* c, const Grids<T>& g, int n, int transpose, const T* X,
                         T* Y, int ncols, hipStream_t s) {
   BlockPlan bp;
-  if (!plan_block<T>(n, c->lds_limit, &bp))
-    return set_err(c, KP_E_INVAL, "no block-product tiling fits the LDS at this n");
+  KP_TRY(choose_block_plan<T>(c, g, n, X, Y, std::min(ncols, 32), s, &bp));
   const long N = (long)n * n;
   for (int c0 = 0; c0 < ncols; c0 += 32) {
     const int nc = ncols - c0 < 32 ? ncols - c0 : 32;
@@ -213,19 +244,37 @@ kp_status block_product(kp_ctx* c, const Grids<T>& g, int n, int transpose, cons
   return check_launch(c, "rmat_block");
 }
 
+template <typename H>
+kp_status choose_block16_plan(kp_ctx* c, const Grids<H>& g, int n, const H* X16, long ld16,
+                              float* Y, int nc, hipStream_t s, BlockPlan* bp) {
+  const long N = (long)n * n;
+  const int v = tune_pick(kTuneBlock16, n, (int)sizeof(H), 0, 2, [&](int k) -> double {
+    BlockPlan p;
+    if (!plan_block16_tj(n, c->lds_limit, kBlock16Variants[k], &p)) return -1.0;
+    p.grid_limit = std::min(p.grid, kSampleWG);
+    const double ms = time_launches(s, 2, [&]() {
+      launch_rmat_block16<H>(p, g.G, g.ldg, n, X16, ld16, Y, N, nc, s);
+    });
+    return ms < 0 ? -1.0 : ms / ((double)std::min(p.grid, kSampleWG) * 16.0 * p.TJ);
+  });
+  if (!plan_block16_tj(n, c->lds_limit, kBlock16Variants[v], bp) &&
+      !plan_block16(n, c->lds_limit, bp))
+    return set_err(c, KP_E_INVAL, "no 16-bit block-product tiling fits the LDS at this n");
+  return KP_OK;
+}
+
 // Y = R X with 16-bit inputs (H = __hip_bfloat16 or __half) and FP32 output; X is
 // rounded to H into a workspace copy first.
 template <typename H>
 kp_status block_product16(kp_ctx* c, const Grids<H>& g, int n, int transpose, const float* X,
                           float* Y, int ncols, hipStream_t s) {
-  BlockPlan bp;
-  if (!plan_block16(n, c->lds_limit, &bp))
-    return set_err(c, KP_E_INVAL, "no 16-bit block-product tiling fits the LDS at this n");
   const long N = (long)n * n;
   const long ld16 = x16_column_len(n);
   H* X16 = nullptr;
   KP_TRY(wsT(c, "x16", (size_t)ld16 * ncols, &X16));
   launch_to16_shifted<H>(X, N, n, ncols, X16, ld16, s);
+  BlockPlan bp;
+  KP_TRY(choose_block16_plan<H>(c, g, n, X16, ld16, Y, std::min(ncols, 32), s, &bp));
   for (int c0 = 0; c0 < ncols; c0 += 32) {
     const int nc = ncols - c0 < 32 ? ncols - c0 : 32;
     ProfScope ps(c, s, 3, 2.0 * (double)N * (double)N * nc);
@@ -963,6 +1012,15 @@ void ctx_free(kp_ctx* c) {
 extern "C" {
 
 const char* kp_version(void) { return "kpsb 0.1 (gfx950)"; }
+
+kp_status kp_tune_report(char* out, size_t cap) {
+  if (!out || cap == 0) return KP_E_INVAL;
+  const std::string t = tune_table();
+  const size_t m = t.size() < cap - 1 ? t.size() : cap - 1;
+  std::memcpy(out, t.data(), m);
+  out[m] = 0;
+  return KP_OK;
+}
 
 kp_status kp_ctx_create(int device, size_t hbm_budget_bytes, kp_ctx** out) {
   if (!out) return KP_E_INVAL;

@@ -6,6 +6,8 @@
 #include <hip/hip_fp16.h>
 
 #include <cstdint>
+#include <functional>
+#include <string>
 
 namespace kpsb {
 
@@ -32,9 +34,14 @@ struct BlockPlan {
   int SW;      // LDS slab row stride (elements)
   size_t lds;  // dynamic LDS bytes
   int grid;    // workgroups
+  int waves = 0;       // waves per workgroup (0: the default for TJ)
+  int grid_limit = 0;  // > 0: launch only the first grid_limit workgroups (tuning samples)
 };
 template <typename T>
 bool plan_block(int n, size_t lds_limit, BlockPlan* plan);
+// The plan with exactly TJ row blocks per workgroup (false if it cannot fit).
+template <typename T>
+bool plan_block_tj(int n, size_t lds_limit, int TJ, BlockPlan* plan);
 template <typename T>
 void launch_rmat_block(const BlockPlan& plan, const T* G, int ldg, int n, const T* X,
                        long ldx, T* Y, long ldy, int ncols, hipStream_t s);
@@ -43,6 +50,7 @@ void launch_rmat_block(const BlockPlan& plan, const T* G, int ldg, int n, const 
 // FP32 accumulation, FP32 output. X16 is the pre-shifted 16-bit copy made by
 // launch_to16_shifted, x16_column_len(n) elements per column.
 bool plan_block16(int n, size_t lds_limit, BlockPlan* plan);
+bool plan_block16_tj(int n, size_t lds_limit, int TJ, BlockPlan* plan);
 // inv_scale (device, may be null) multiplies the result (undoes power-of-2
 // operand scaling); accumulate != 0 adds the result into Y.
 template <typename H>
@@ -84,6 +92,18 @@ bool plan_gemv(int n, size_t lds_limit, BlockPlan* plan);
 template <typename T>
 void launch_rmat_gemv(const BlockPlan& plan, const T* G, int ldg, int n, const T* x,
                       T* y, const T* z, double coef, hipStream_t s);
+
+// ---- autotuner (tune.cpp) ---------------------------------------------------
+constexpr int kTuneBlock = 1;     // FP32 / FP64 block product: (TJ, waves)
+constexpr int kTuneBlock16 = 2;   // 16-bit block product: TJ
+constexpr int kTuneApply = 3;     // FP64 Kronecker apply GEMMs: (tile, K tile)
+bool tune_enabled();   // KPSB_AUTOTUNE=0 keeps every operation at its variant 0
+// Average ms of `reps` launches after one warm-up (hipEvents on s; synchronizes).
+double time_launches(hipStream_t s, int reps, const std::function<void()>& launch);
+// The variant of (op, n, a, b) to use: on first use, cost(v) is evaluated for
+// every v < ncand (negative = not applicable) and the cheapest is kept.
+int tune_pick(int op, int n, int a, int b, int ncand, const std::function<double(int)>& cost);
+std::string tune_table();   // JSON list of the choices and measured costs
 
 // ---- vector kernels (blas1.hip) --------------------------------------------
 // partials[b * m + i] = sum over rows of block b of V[:, i] . w  (FP64 accum)

@@ -196,7 +196,6 @@ KpApplyPlan kp_apply_plan(int n, int k) {
   const long t64 = (long)((n + 63) / 64) * ((n + 63) / 64);
   const long t32 = (long)((n + 31) / 32) * ((n + 31) / 32);
   p.tile = t64 * k >= 1024 ? 64 : 32;
-  if (const char* e = getenv("KPSB_GEMM_TILE")) p.tile = atoi(e) == 64 ? 64 : 32;
   const long tiles = p.tile == 64 ? t64 : t32;
   p.group = (int)std::max<long>(1, std::min<long>(k, tiles * k / 1024));
   p.ngroups = (k + p.group - 1) / p.group;
@@ -209,11 +208,14 @@ static void gemm_launch(const GemmArgs& g, int zdim, hipStream_t s) {
   hipLaunchKernelGGL((gemm_f64_kernel<T, T, KT>), grid, dim3(256), 0, s, g);
 }
 
-static void gemm(const GemmArgs& g, int tile, int zdim, hipStream_t s) {
-  static const int kt32 = getenv("KPSB_GEMM_KT32") ? atoi(getenv("KPSB_GEMM_KT32")) : 32;
-  if (tile == 64) gemm_launch<64, 16>(g, zdim, s);
-  else if (kt32 == 16) gemm_launch<32, 16>(g, zdim, s);
-  else gemm_launch<32, 32>(g, zdim, s);
+// Launch variants (output tile, K tile), picked by the autotuner; the order of
+// accumulation of every output element is the same in all of them.
+static void gemm(const GemmArgs& g, int variant, int zdim, hipStream_t s) {
+  switch (variant) {
+    case 1: gemm_launch<32, 32>(g, zdim, s); break;
+    case 2: gemm_launch<32, 16>(g, zdim, s); break;
+    default: gemm_launch<64, 16>(g, zdim, s); break;
+  }
 }
 
 // Z (k x n x n) is workspace; P receives plan.ngroups partial images.
@@ -223,11 +225,20 @@ void launch_kp_apply_parts(const double* Ax, const double* Ay, int n, int k, int
   const long NN = (long)n * n;
   // Z_t = X * (transpose ? Ax_t : Ax_t^T)
   GemmArgs g1{X, n, 0, 0, Ax, n, NN, transpose ? 0 : 1, Z, n, NN, n, n, n, k, 1, flags, nflags};
-  gemm(g1, plan.tile, k, s);
   // P_g = sum_{t in g} (transpose ? Ay_t^T : Ay_t) * Z_t
   GemmArgs g2{Ay, n, NN, transpose ? 1 : 0, Z, n, NN, 0, P, n, NN, n, n, n, k, plan.group,
               flags, nflags};
-  gemm(g2, plan.tile, plan.ngroups, s);
+  const int v = tune_pick(kTuneApply, n, k, transpose, 3, [&](int vv) -> double {
+    GemmArgs a = g1, b = g2;
+    a.flags = b.flags = nullptr;   // the sample launches always run
+    a.nflags = b.nflags = 0;
+    return time_launches(s, 2, [&]() {
+      gemm(a, vv, k, s);
+      gemm(b, vv, plan.ngroups, s);
+    });
+  });
+  gemm(g1, v, k, s);
+  gemm(g2, v, plan.ngroups, s);
 }
 
 void launch_kp_apply_ws(const double* Ax, const double* Ay, int n, int k, int transpose,

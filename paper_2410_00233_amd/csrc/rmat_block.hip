@@ -17,6 +17,8 @@
 // holds row l%16, k = l/16; B lane l holds k = l/16, column l%16; D lane l
 // holds column l%16 and, for item e = 0..3, row 4*(l/16) + e (FP32) or
 // row l/16 + 4*e (FP64).
+#include <algorithm>
+
 #include "common.h"
 
 namespace kpsb {
@@ -367,30 +369,41 @@ static size_t block_lds(int n, int TJ, int CP) {
 // blocks in one phase or, for large n, in phases of CP >= 64 column blocks
 // (the slab is reloaded per phase: (n / CP) x SR rows per workgroup).
 template <typename T>
+bool plan_block_tj(int n, size_t lds_limit, int TJ, BlockPlan* plan) {
+  int cp_max = n;
+  if (const char* e = getenv("KPSB_BLOCK_CP")) cp_max = std::max(1, std::min(n, atoi(e)));
+  for (int CP = cp_max; CP >= 1; CP = (CP > 64 ? (CP + 1) / 2 : 0)) {
+    const size_t lds = block_lds<T>(n, TJ, CP);
+    if (lds <= lds_limit) {
+      plan->TJ = TJ;
+      plan->CP = CP;
+      plan->SW = slab_stride<T>(n, CP);
+      plan->lds = lds;
+      plan->grid = ((n + 15) / 16) * ((n + TJ - 1) / TJ);
+      plan->waves = 0;
+      plan->grid_limit = 0;
+      return true;
+    }
+    if (CP <= 64) break;
+  }
+  return false;
+}
+
+template <typename T>
 bool plan_block(int n, size_t lds_limit, BlockPlan* plan) {
   static const int cand[] = {16, 8, 4, 2, 1};
-  int forced = 0, cp_max = n;
+  int forced = 0;
   if (const char* e = getenv("KPSB_BLOCK_TJ")) forced = atoi(e);
-  if (const char* e = getenv("KPSB_BLOCK_CP")) cp_max = std::max(1, std::min(n, atoi(e)));
   for (int TJ : cand) {
     if (forced && TJ != forced) continue;
-    for (int CP = cp_max; CP >= 1; CP = (CP > 64 ? (CP + 1) / 2 : 0)) {
-      const size_t lds = block_lds<T>(n, TJ, CP);
-      if (lds <= lds_limit) {
-        plan->TJ = TJ;
-        plan->CP = CP;
-        plan->SW = slab_stride<T>(n, CP);
-        plan->lds = lds;
-        plan->grid = ((n + 15) / 16) * ((n + TJ - 1) / TJ);
-        return true;
-      }
-      if (CP <= 64) break;
-    }
+    if (plan_block_tj<T>(n, lds_limit, TJ, plan)) return true;
   }
   return false;
 }
 template bool plan_block<float>(int, size_t, BlockPlan*);
 template bool plan_block<double>(int, size_t, BlockPlan*);
+template bool plan_block_tj<float>(int, size_t, int, BlockPlan*);
+template bool plan_block_tj<double>(int, size_t, int, BlockPlan*);
 
 template <typename T, int TJ, int JB, int CB>
 static void launch_tj(const BlockPlan& p, const T* G, int ldg, int n, const T* X, long ldx,
@@ -400,22 +413,22 @@ static void launch_tj(const BlockPlan& p, const T* G, int ldg, int n, const T* X
   if (p.lds > 65536)
     (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)p.lds);
-  hipLaunchKernelGGL(kern, dim3(p.grid), dim3(threads), p.lds, s, G, ldg, n, X, ldx, Y, ldy,
+  const int grid = p.grid_limit > 0 && p.grid_limit < p.grid ? p.grid_limit : p.grid;
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(threads), p.lds, s, G, ldg, n, X, ldx, Y, ldy,
                      ncols, p.SW, p.CP);
 }
 
 template <typename T>
 void launch_rmat_block(const BlockPlan& p, const T* G, int ldg, int n, const T* X, long ldx,
                        T* Y, long ldy, int ncols, hipStream_t s) {
-  // waves per workgroup (measured on gfx950 at n = 256 / 512: 16 waves beat 8 and 4,
-  // more waves per SIMD hide the LDS latency of the fragment loads)
-  const int waves = getenv("KPSB_BLOCK_WAVES") ? atoi(getenv("KPSB_BLOCK_WAVES")) : 16;
-  if (p.TJ == 16 && waves == 8) {
+  // waves per workgroup: TJ = 16 -> 16 (JB = 1) or 8 (JB = 2); TJ = 8 -> 8 (CB = 2)
+  // or 16 (CB = 1); chosen by the autotuner, 16 and 8 by default
+  if (p.TJ == 16 && p.waves == 8) {
     launch_tj<T, 16, 2, 2>(p, G, ldg, n, X, ldx, Y, ldy, ncols, s);
     return;
   }
-  if (p.TJ == 16 && waves == 4) {
-    launch_tj<T, 16, 4, 2>(p, G, ldg, n, X, ldx, Y, ldy, ncols, s);
+  if (p.TJ == 8 && p.waves == 16) {
+    launch_tj<T, 8, 1, 1>(p, G, ldg, n, X, ldx, Y, ldy, ncols, s);
     return;
   }
   switch (p.TJ) {

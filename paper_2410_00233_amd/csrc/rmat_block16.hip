@@ -211,20 +211,25 @@ long x16_column_len(int n) {
   return ((total + tile - 1) / tile) * tile;
 }
 
+bool plan_block16_tj(int n, size_t lds_limit, int TJ, BlockPlan* plan) {
+  const size_t lds = lds16(n, TJ);
+  if (lds > lds_limit) return false;
+  plan->TJ = TJ;
+  plan->SW = stride16(n);
+  plan->lds = lds;
+  plan->grid = ((n + 15) / 16) * ((n + TJ - 1) / TJ);
+  plan->waves = 0;
+  plan->grid_limit = 0;
+  return true;
+}
+
 bool plan_block16(int n, size_t lds_limit, BlockPlan* plan) {
   static const int cand[] = {32, 16, 8, 4};
   int forced = 0;
   if (const char* e = getenv("KPSB_BLOCK16_TJ")) forced = atoi(e);
   for (int TJ : cand) {
     if (forced && TJ != forced) continue;
-    size_t lds = lds16(n, TJ);
-    if (lds <= lds_limit) {
-      plan->TJ = TJ;
-      plan->SW = stride16(n);
-      plan->lds = lds;
-      plan->grid = ((n + 15) / 16) * ((n + TJ - 1) / TJ);
-      return true;
-    }
+    if (plan_block16_tj(n, lds_limit, TJ, plan)) return true;
   }
   return false;
 }
@@ -238,7 +243,8 @@ static void launch16_tj(const BlockPlan& p, const H* G, int ldg, int n, const H*
   if (p.lds > 65536)
     (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)p.lds);
-  hipLaunchKernelGGL(kern, dim3(p.grid), dim3(threads), p.lds, s, G, ldg, n, X, ldx, Y, ldy,
+  const int grid = p.grid_limit > 0 && p.grid_limit < p.grid ? p.grid_limit : p.grid;
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(threads), p.lds, s, G, ldg, n, X, ldx, Y, ldy,
                      ncols, p.SW, len16(n), inv_scale, accumulate);
 }
 

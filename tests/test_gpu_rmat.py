@@ -138,3 +138,42 @@ def test_product16_full_size_sampled_rows(ctx, prec):
     ref = R16 @ X16
     mag = np.abs(R16) @ np.abs(X16)
     assert np.all(np.abs(Y[rows] - ref) <= 2e-6 * mag + 1e-7 * mag.max())
+
+
+@pytest.mark.parametrize("prec,nvar", [("f32", 4), ("f64", 4), ("bf16", 2)])
+@pytest.mark.parametrize("n", [40, 256])
+def test_autotuner_variants_agree_bitwise(ctx, prec, nvar, n, monkeypatch):
+    """Every launch variant the autotuner chooses among computes the same bits."""
+    import torch
+    from paper_2410_00233_amd import api
+    P, cu, cv = wl.gaussian_psf(n, (2.5, 1.2), 17.0)
+    dt = torch.float64 if prec == "f64" else torch.float32
+    X = torch.tensor(np.random.default_rng(n).standard_normal((30, n * n)), dtype=dt,
+                     device="cuda")
+    blur = api.Blur(P, cu, cv, n)
+    outs = []
+    for v in range(nvar):
+        monkeypatch.setenv("KPSB_TUNE_FORCE", str(v))
+        outs.append(ctx.kp_rmat_apply(blur, X, prec=prec).cpu())
+    monkeypatch.delenv("KPSB_TUNE_FORCE")
+    outs.append(ctx.kp_rmat_apply(blur, X, prec=prec).cpu())     # the tuned choice
+    for o in outs[1:]:
+        assert torch.equal(o, outs[0])
+    rep = ctx.kp_tune_report()
+    assert any(r["n"] == n for r in rep)
+
+
+@pytest.mark.parametrize("n,k", [(96, 7), (256, 20)])
+def test_apply_variants_agree_bitwise(ctx, n, k, monkeypatch):
+    import torch
+    from paper_2410_00233_amd import api
+    rng = np.random.default_rng(n)
+    f = api.Factors.from_arrays(rng.standard_normal((k, n, n)), rng.standard_normal((k, n, n)))
+    X = torch.tensor(rng.standard_normal((n, n)), dtype=torch.float64, device="cuda")
+    for tr in (False, True):
+        outs = []
+        for v in range(3):
+            monkeypatch.setenv("KPSB_TUNE_FORCE", str(v))
+            outs.append(ctx.kp_apply(f, X, transpose=tr).cpu())
+        for o in outs[1:]:
+            assert torch.equal(o, outs[0])
