@@ -37,9 +37,12 @@ MFMA_FP32_PEAK_TFLOPS = 157.3     # MI355X dense FP32 matrix peak
 # (profiles/rmat_products_n512_hbm_counters.md), valid while the kernel source
 # is the one the counters were taken on.
 BLOCK_TRAFFIC_BYTES = 1.110e9
-BLOCK_TRAFFIC_SRC_SHA1 = "900841815ebad8708d42797b02e9c12854a339c1"
-BLOCK16_TRAFFIC_BYTES = 3.22e8
-BLOCK16_TRAFFIC_SRC_SHA1 = "b418f88af4c618522def266074c50afa02bf3108"
+BLOCK_TRAFFIC_SRC_SHA1 = "9e9452d8bf8baab4b0a5fcbce0b7173d6ed4a848"
+BLOCK16_TRAFFIC_BYTES = 3.23e8
+# template arguments <TJ, JB, CB> of the FP32 block kernel per autotuner variant
+BLOCK_VARIANT_TEMPLATE = {0: "16,1,2", 1: "16,2,2", 2: "8,1,2", 3: "8,1,1"}
+BLOCK16_VARIANT_TEMPLATE = {0: "32,4,2", 1: "16,4,2"}
+BLOCK16_TRAFFIC_SRC_SHA1 = "4e421df2669a63a3f8c5b9481e7943524a84e512"
 
 
 def counted_traffic(src, sha, value):
@@ -344,6 +347,9 @@ def main():
     avg_gv_ms = gv["ms"] / max(gv["launches"], 1)
     gemv_tflops = (gv["flops"] / max(gv["launches"], 1)) / (avg_gv_ms * 1e-3) / 1e12
 
+    tune = ctx.kp_tune_report()
+    v32 = next((t["variant"] for t in tune if t["op"] == "block32" and t["n"] == n and t["a"] == 4), None)
+    v16 = next((t["variant"] for t in tune if t["op"] == "block16" and t["n"] == n), None)
     line = {
         "metric": "KP-SVD time & TFLOP/s at n=512 (FP32 vs BF16+refine); p50/p99 solve latency",
         "value": round(value, 3),
@@ -392,7 +398,8 @@ def main():
                                  / (float(np.percentile(lat, 50)) * 1e-3) / 1e12, 3),
         },
         "roofline_bf16": {
-            "kernel": "rmat_block16_kernel<bf16> (generated-tile R(A) X, BF16 MFMA 16x16x32, FP32 accumulate)",
+            "kernel": f"rmat_block16_kernel<bf16,{BLOCK16_VARIANT_TEMPLATE.get(v16, '?')}> "
+                      "(generated-tile R(A) X, BF16 MFMA 16x16x32, FP32 accumulate)",
             "bound": "mfma", "achieved": round(ach16, 3), "peak": MFMA_BF16_PEAK_TFLOPS,
             "unit": "TFLOP/s", "frac": round(ach16 / MFMA_BF16_PEAK_TFLOPS, 4),
             "avg_launch_ms": round(avg16, 4), "launches": int(b16["launches"]),
@@ -400,7 +407,8 @@ def main():
                                        BLOCK16_TRAFFIC_BYTES) if n == 512 else None,
         },
         "roofline": {
-            "kernel": "rmat_block_kernel<float,16,1,2> (generated-tile R(A) X, FP32 MFMA 16x16x4)",
+            "kernel": f"rmat_block_kernel<float,{BLOCK_VARIANT_TEMPLATE.get(v32, '?')}> "
+                      "(generated-tile R(A) X, FP32 MFMA 16x16x4)",
             "bound": "mfma",
             "achieved": round(achieved, 3),
             "peak": MFMA_FP32_PEAK_TFLOPS,
