@@ -44,6 +44,36 @@ def blur_matrix(P, cu, cv, n):
     return A
 
 
+def _reflect_images(k, n):
+    """Positions that the half-sample symmetric (reflexive) extension of a
+    length-n signal maps onto index k: k + 2nm and -1 - k + 2nm, m = -1, 0, 1
+    (enough for PSF extents below 3n)."""
+    return [k + 2 * n * m for m in (-1, 0, 1)] + [-1 - k + 2 * n * m for m in (-1, 0, 1)]
+
+
+def blur_matrix_reflexive(P, cu, cv, n):
+    """Explicit reflexive-BC blur matrix (n^2 x n^2): the image is extended
+    beyond its edges by reflection about the edge of the last pixel
+    (x[-1 - k] = x[k], x[n + k] = x[n - 1 - k]), so
+
+        A[r + n*i, c + n*j] = sum over images c~ of c and j~ of j of
+                              P[cu + r - c~, cv + i - j~].
+    """
+    N = n * n
+    A = np.zeros((N, N), dtype=P.dtype)
+    r = np.arange(n)[:, None]
+    c = np.arange(n)[None, :]
+    cimg = _reflect_images(c, n)           # list of (1, n) arrays
+    for i in range(n):
+        for j in range(n):
+            blk = np.zeros((n, n), dtype=P.dtype)
+            for jj in _reflect_images(j, n):
+                for cc in cimg:
+                    blk += _psf_at(P, cu, cv, r - cc, np.full((1, 1), i - jj))
+            A[n * i:n * i + n, n * j:n * j + n] = blk
+    return A
+
+
 def rearrange(A, m1, n1, m2, n2):
     """R(A) by the literal reordering of eq. "initial rearrange A".
 

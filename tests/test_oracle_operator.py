@@ -201,3 +201,33 @@ def test_configured_psfs_are_normalized_and_nonseparable():
     assert len(widths) == 6
     s, _, _ = op.exact_kpsvd(P, cu, cv, n)
     assert s[5] > 1e-8 * s[0] and s[6] < 1e-12 * s[0]
+
+
+@pytest.mark.parametrize("n,shape,seed", [(6, (3, 5), 1), (9, (7, 7), 2), (12, (11, 5), 3)])
+def test_reflexive_blur_matrix_is_ndimage_reflect_convolution(n, shape, seed):
+    """Reflexive boundary conditions (half-sample symmetric extension): the
+    explicit matrix against scipy.ndimage.convolve(mode="reflect"), an
+    independent implementation; mode="constant" reproduces the zero-BC matrix."""
+    import scipy.ndimage as nd
+    rng = np.random.default_rng(seed)
+    P = rng.uniform(0, 1, shape)
+    cu, cv = shape[0] // 2, shape[1] // 2          # ndimage's kernel centre
+    X = rng.standard_normal((n, n))
+    Ar = op.blur_matrix_reflexive(P, cu, cv, n)
+    Az = op.blur_matrix(P, cu, cv, n)
+    vec = lambda M: M.flatten(order="F")
+    assert np.allclose(Ar @ vec(X), vec(nd.convolve(X, P, mode="reflect")), rtol=0, atol=1e-12)
+    assert np.allclose(Az @ vec(X), vec(nd.convolve(X, P, mode="constant", cval=0.0)),
+                       rtol=0, atol=1e-12)
+    # the reflected part is a nonzero, separately structured correction
+    assert np.abs(Ar - Az).max() > 1e-3
+
+
+def test_reflexive_blur_of_constant_image_is_constant():
+    """With a unit-sum PSF whose extent is below n, reflection preserves a
+    constant image exactly (no boundary darkening, unlike zero BC)."""
+    n = 10
+    P = np.random.default_rng(4).uniform(0, 1, (5, 7))
+    P /= P.sum()
+    Ar = op.blur_matrix_reflexive(P, 2, 3, n)
+    assert np.allclose(Ar @ np.ones(n * n), 1.0, atol=1e-13)
