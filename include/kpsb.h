@@ -310,6 +310,41 @@ kp_status kp_server_stats(kp_server* srv, int64_t out[8]);
 /* Finishes every submitted request, then frees the server's memory. */
 kp_status kp_server_destroy(kp_server* srv);
 
+/* ---------------------------------------------------------------------------
+ * Explicit-matrix path: the paper's own pipeline stores the blur matrix A and
+ * reorders it into R(A) (section 2.1, eq. "initial rearrange A"); this path
+ * serves any A (any boundary condition, e.g. reflexive, or a spatially variant
+ * blur). A and R are N x N with N = n^2 (2 <= n <= 1024), row-major, FP32
+ * (KP_F32) or FP64 (KP_F64), DEVICE memory owned by the caller; every product
+ * streams the stored R from HBM.
+ *
+ * R[i + n*j, r + n*c] = A[r + n*i, c + n*j]. A and R must not overlap. */
+kp_status kp_rmat_reorder(kp_ctx* ctx, int32_t n, kp_prec prec, const void* A, void* R,
+                          void* stream);
+/* Y = R X or R^T X with the stored R (X, Y: DEVICE N x ncols column-major;
+ * ncols == 1 uses the matrix-vector kernels). */
+kp_status kp_rmat_apply_stored(kp_ctx* ctx, int32_t n, kp_prec prec, const void* R,
+                               int transpose, int32_t ncols, const void* X, void* Y,
+                               void* stream);
+/* KP-SVD by EGKB (Algorithm 1) / RSVD (Algorithm 2) of a stored R; the element
+ * type of R is opts->prec (KP_F32 or KP_F64; RSVD's 16-bit modes and the
+ * split-FP16 refinement need a PSF and are not available here: refine = 2
+ * uses the FP32 product). Same outputs and conventions as kp_svd_gkb /
+ * kp_svd_rsvd. */
+kp_status kp_svd_gkb_stored(kp_ctx* ctx, int32_t n, const void* R, const kp_gkb_opts* opts,
+                            kp_factors* out, void* stream);
+kp_status kp_svd_rsvd_stored(kp_ctx* ctx, int32_t n, const void* R, const kp_rsvd_opts* opts,
+                             kp_factors* out, void* stream);
+/* Split Bregman (Algorithms 3 / 4 with CGLS, Algorithm 5) with A itself in
+ * place of A_k: the paper's method (i) of Table 1, against which it measures
+ * the speed-up of the Kronecker approximation. A: DEVICE N x N row-major FP64
+ * acting on the column-major vec of an image; b, x: DEVICE n x n row-major
+ * images. */
+kp_status sb_solve_aniso_direct(kp_ctx* ctx, int32_t n, const double* A, const double* b,
+                                const sb_opts* opts, double* x, sb_stats* stats, void* stream);
+kp_status sb_solve_iso_direct(kp_ctx* ctx, int32_t n, const double* A, const double* b,
+                              const sb_opts* opts, double* x, sb_stats* stats, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -27,7 +27,9 @@ EXPORTED = ["kp_ctx_create", "kp_ctx_destroy", "kp_last_error", "kp_version",
             "kp_rmat_apply", "kp_svd_gkb", "kp_svd_rsvd", "kp_apply",
             "sb_solve_aniso", "sb_solve_iso", "kp_svd_batched",
             "kp_server_create", "kp_server_submit", "kp_server_wait", "kp_server_stats",
-            "kp_server_destroy", "kp_tune_report"]
+            "kp_server_destroy", "kp_tune_report", "kp_rmat_reorder", "kp_rmat_apply_stored",
+            "kp_svd_gkb_stored", "kp_svd_rsvd_stored", "sb_solve_aniso_direct",
+            "sb_solve_iso_direct"]
 
 
 class kp_blur(C.Structure):
@@ -129,6 +131,16 @@ def load(path: str = LIB_PATH):
     lib.kp_server_stats.argtypes = [vp, C.POINTER(C.c_int64)]
     lib.kp_server_destroy.argtypes = [vp]
     lib.kp_tune_report.argtypes = [C.c_char_p, C.c_size_t]
+    lib.kp_rmat_reorder.argtypes = [vp, C.c_int32, C.c_int, vp, vp, vp]
+    lib.kp_rmat_apply_stored.argtypes = [vp, C.c_int32, C.c_int, vp, C.c_int, C.c_int32, vp, vp,
+                                         vp]
+    lib.kp_svd_gkb_stored.argtypes = [vp, C.c_int32, vp, C.POINTER(kp_gkb_opts),
+                                      C.POINTER(kp_factors), vp]
+    lib.kp_svd_rsvd_stored.argtypes = [vp, C.c_int32, vp, C.POINTER(kp_rsvd_opts),
+                                       C.POINTER(kp_factors), vp]
+    lib.sb_solve_aniso_direct.argtypes = [vp, C.c_int32, vp, vp, C.POINTER(sb_opts), vp,
+                                          C.POINTER(sb_stats), vp]
+    lib.sb_solve_iso_direct.argtypes = lib.sb_solve_aniso_direct.argtypes
     for name in EXPORTED:
         if name not in ("kp_last_error", "kp_version"):
             getattr(lib, name).restype = C.c_int

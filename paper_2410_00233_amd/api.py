@@ -149,9 +149,11 @@ class Context:
 
     def kp_svd_gkb(self, blur: Blur, k, p, *, k_min=0, auto_k=False, tau=0.0,
                    literal_init=False, reorth=1, prec="f32", seed=0, y0=None, bd_rel=0.0,
-                   factor_prec="f64", k_cap=None, bases=False):
+                   factor_prec="f64", k_cap=None, bases=False, stored=None):
+        """stored=(n, R): the KP-SVD of a stored R (device tensor N x N, the
+        element type given by prec) instead of the blur's generated R."""
         torch = _torch()
-        n = blur.n
+        n = blur.n if stored is None else stored[0]
         f = Factors(n, k_cap or k, factor_prec)
         y0a = None if y0 is None else np.ascontiguousarray(y0, dtype=np.float64)
         o = L.kp_gkb_opts(k, p, k_min, int(auto_k), tau, int(literal_init), reorth, PREC[prec],
@@ -170,8 +172,12 @@ class Context:
             Q = torch.zeros((k + p, n * n), dtype=dt, device="cuda")
             f.diag.basis_u = S.data_ptr()
             f.diag.basis_v = Q.data_ptr()
-        st = self._check(self.lib.kp_svd_gkb(self.h, C.byref(blur.s), C.byref(o), C.byref(f.s),
-                                             _stream()), allow=(L.KP_OK, L.KP_W_BREAKDOWN))
+        if stored is None:
+            st = self.lib.kp_svd_gkb(self.h, C.byref(blur.s), C.byref(o), C.byref(f.s), _stream())
+        else:
+            st = self.lib.kp_svd_gkb_stored(self.h, n, _ptr(stored[1]), C.byref(o), C.byref(f.s),
+                                            _stream())
+        st = self._check(st, allow=(L.KP_OK, L.KP_W_BREAKDOWN))
         f.status = st
         kp = f.diag.kp
         f.alpha = alpha[:kp].copy()
@@ -218,9 +224,10 @@ class Context:
         return facs, list(status)
 
     def kp_svd_rsvd(self, blur: Blur, k, p, q, *, prec="f32", refine=False, seed=0, F=None,
-                    factor_prec="f64", k_cap=None, bases=False):
+                    factor_prec="f64", k_cap=None, bases=False, stored=None):
+        """stored=(n, R) as in kp_svd_gkb."""
         torch = _torch()
-        n = blur.n
+        n = blur.n if stored is None else stored[0]
         f = Factors(n, k_cap or k, factor_prec)
         Fa = None if F is None else np.asfortranarray(F, dtype=np.float64)
         o = L.kp_rsvd_opts(k, p, q, PREC[prec], int(refine), seed,
@@ -230,12 +237,57 @@ class Context:
             dt = torch.float64 if prec == "f64" else torch.float32
             Y = torch.zeros((k + p, n * n), dtype=dt, device="cuda")
             f.diag.basis_u = Y.data_ptr()
-        f.status = self._check(self.lib.kp_svd_rsvd(self.h, C.byref(blur.s), C.byref(o),
-                                                    C.byref(f.s), _stream()))
+        if stored is None:
+            st = self.lib.kp_svd_rsvd(self.h, C.byref(blur.s), C.byref(o), C.byref(f.s), _stream())
+        else:
+            st = self.lib.kp_svd_rsvd_stored(self.h, n, _ptr(stored[1]), C.byref(o), C.byref(f.s),
+                                             _stream())
+        f.status = self._check(st)
         f.ms = f.diag.ms_total
         if bases:
             f.Y = Y
         return f
+
+    def kp_rmat_reorder(self, n, A, R=None):
+        """R(A) from a stored blur matrix A (device tensor N x N, FP32 or FP64)."""
+        torch = _torch()
+        if R is None:
+            R = torch.empty_like(A)
+        prec = "f64" if A.dtype == torch.float64 else "f32"
+        self._check(self.lib.kp_rmat_reorder(self.h, int(n), PREC[prec], _ptr(A), _ptr(R),
+                                             _stream()))
+        return R
+
+    def kp_rmat_apply_stored(self, n, R, X, transpose=False, Y=None):
+        torch = _torch()
+        if Y is None:
+            Y = torch.empty_like(X)
+        prec = "f64" if R.dtype == torch.float64 else "f32"
+        ncols = 1 if X.dim() == 1 else X.shape[0]
+        self._check(self.lib.kp_rmat_apply_stored(self.h, int(n), PREC[prec], _ptr(R),
+                                                  int(transpose), ncols, _ptr(X), _ptr(Y),
+                                                  _stream()))
+        return Y
+
+    def sb_solve_aniso_direct(self, n, A, b, lam, beta, L_max=50, I_max=100, tau_sb=0.0,
+                              tau_cgls=0.0, x=None):
+        return self._sb_direct(self.lib.sb_solve_aniso_direct, n, A, b, lam, beta, L_max, I_max,
+                               tau_sb, tau_cgls, x)
+
+    def sb_solve_iso_direct(self, n, A, b, lam, beta, L_max=50, I_max=100, tau_sb=0.0,
+                            tau_cgls=0.0, x=None):
+        return self._sb_direct(self.lib.sb_solve_iso_direct, n, A, b, lam, beta, L_max, I_max,
+                               tau_sb, tau_cgls, x)
+
+    def _sb_direct(self, fn, n, A, b, lam, beta, L_max, I_max, tau_sb, tau_cgls, x):
+        torch = _torch()
+        if x is None:
+            x = torch.empty_like(b)
+        o = L.sb_opts(lam, beta, L_max, I_max, tau_sb, tau_cgls)
+        st = L.sb_stats()
+        self._check(fn(self.h, int(n), _ptr(A), _ptr(b), C.byref(o), _ptr(x), C.byref(st),
+                       _stream()))
+        return x, dict(l_end=st.l_end, iota_total=st.iota_total, rc_sb=st.rc_sb)
 
     def kp_apply(self, f: Factors, X, transpose=False, Y=None):
         torch = _torch()

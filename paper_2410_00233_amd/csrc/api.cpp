@@ -499,6 +499,58 @@ kp_status write_factors(kp_ctx* c, const double* Ud, const double* Vd, const dou
 }
 
 // ---------------------------------------------------------------------------
+// The matrix B = R(A) of the KP-SVD drivers: generated tile by tile from a PSF
+// (a blur with zero boundary conditions), or stored in HBM as an N x N
+// row-major matrix (the reordered explicit A of any blur).
+template <typename T>
+struct RmatOp {
+  int n = 0;
+  const kp_blur* blur = nullptr;   // generated
+  const double* dpsf = nullptr;
+  Grids<T> g;
+  const T* R = nullptr;            // stored
+  double* gv_ws = nullptr;         // stored R^T x partial sums
+
+  kp_status gemv(kp_ctx* c, int tr, const T* x, T* y, const T* z, double coef,
+                 hipStream_t s) const {
+    if (R) {
+      const double NN = (double)n * n;
+      ProfScope ps(c, s, 1, 2.0 * NN * NN);
+      launch_stored_gemv<T>(R, (long)n * n, tr, x, y, z, coef, gv_ws, s);
+      return check_launch(c, "stored_gemv");
+    }
+    return gemv_product<T>(c, g, n, tr, x, y, z, coef, s);
+  }
+  kp_status block(kp_ctx* c, int tr, const T* X, T* Y, int ncols, hipStream_t s) const {
+    if (R) {
+      const long N = (long)n * n;
+      for (int c0 = 0; c0 < ncols; c0 += 32) {
+        const int nc = ncols - c0 < 32 ? ncols - c0 : 32;
+        ProfScope ps(c, s, 0, 2.0 * (double)N * (double)N * nc);
+        launch_stored_block<T>(R, N, tr, X + N * c0, Y + N * c0, nc, s);
+      }
+      return check_launch(c, "stored_block");
+    }
+    return block_product<T>(c, g, n, tr, X, Y, ncols, s);
+  }
+};
+
+template <typename T>
+kp_status make_generated_op(kp_ctx* c, const kp_blur* b, hipStream_t s, RmatOp<T>* op) {
+  op->n = b->n;
+  op->blur = b;
+  KP_TRY(upload_psf(c, b, s, const_cast<double**>(&op->dpsf)));
+  return build_grids<T>(c, b, op->dpsf, s, &op->g);
+}
+
+template <typename T>
+kp_status make_stored_op(kp_ctx* c, int n, const T* R, RmatOp<T>* op) {
+  op->n = n;
+  op->R = R;
+  return wsT(c, "stored_gv", (size_t)stored_gemv_ws((long)n * n), &op->gv_ws);
+}
+
+// ---------------------------------------------------------------------------
 // EGKB (Algorithm 1). Readings as in the oracle: nu_{j+1} = sqrt(zeta_j
 // zeta_{j-1}); zeta_1 = alpha_1 t_1, nu_2 = +inf (or the printed 1 and 100);
 // j = 2 .. k_p + 1; the nu test fires at most once, for j > k_min and
@@ -506,10 +558,10 @@ kp_status write_factors(kp_ctx* c, const double* Ud, const double* Vd, const dou
 // breakdown stores 0 and restarts with a Philox vector (stream 2j for s_j,
 // 2j + 1 for q_j) orthogonalized against the basis.
 template <typename T>
-kp_status egkb_impl(kp_ctx* c, const kp_blur* b, const kp_gkb_opts* o, kp_factors* f,
+kp_status egkb_impl(kp_ctx* c, const RmatOp<T>& op, const kp_gkb_opts* o, kp_factors* f,
                     hipStream_t s) {
   Timer timer(s);
-  const int n = b->n;
+  const int n = op.n;
   const long N = (long)n * n;
   int k = o->k;
   const int p = o->p;
@@ -519,8 +571,6 @@ kp_status egkb_impl(kp_ctx* c, const kp_blur* b, const kp_gkb_opts* o, kp_factor
   const double u = (sizeof(T) == 4) ? std::ldexp(1.0, -24) : std::ldexp(1.0, -53);
   const double bd_rel = o->bd_rel > 0 ? o->bd_rel : 1e2 * u;
 
-  Grids<T> g;
-  KP_TRY(prep_grids<T>(c, b, s, &g));
   Scratch sc;
   KP_TRY(get_scratch(c, &sc));
   T *S = nullptr, *Q = nullptr;
@@ -558,7 +608,7 @@ kp_status egkb_impl(kp_ctx* c, const kp_blur* b, const kp_gkb_opts* o, kp_factor
   t.push_back(t1);
 
   // q = B^T s_1, alpha_1 = ||q||
-  KP_TRY(gemv_product<T>(c, g, n, 1, S, Q, nullptr, 0.0, s));
+  KP_TRY(op.gemv(c, 1, S, Q, nullptr, 0.0, s));
   launch_norm2_partials<T>(Q, N, sc.nrmp, s);
   double a1 = 0;
   KP_TRY(read_norm(c, sc, s, &a1));
@@ -581,7 +631,7 @@ kp_status egkb_impl(kp_ctx* c, const kp_blur* b, const kp_gkb_opts* o, kp_factor
     const T* sprev = S + N * (j - 2);
     const T* qprev = Q + N * (j - 2);
     // s_j = B q_{j-1} - alpha_{j-1} s_{j-1}
-    KP_TRY(gemv_product<T>(c, g, n, 0, qprev, sj, sprev, alpha.back(), s));
+    KP_TRY(op.gemv(c, 0, qprev, sj, sprev, alpha.back(), s));
     if (o->reorth == 1)
       cgs2<T>(sc, sj, S, N, j - 1, N, s);
     else
@@ -600,7 +650,7 @@ kp_status egkb_impl(kp_ctx* c, const kp_blur* b, const kp_gkb_opts* o, kp_factor
     if (j <= kp) {
       T* qj = Q + N * (j - 1);
       // q_j = B^T s_j - t_j q_{j-1}, reorthogonalized against Q (step 6)
-      KP_TRY(gemv_product<T>(c, g, n, 1, sj, qj, qprev, tj, s));
+      KP_TRY(op.gemv(c, 1, sj, qj, qprev, tj, s));
       cgs2<T>(sc, qj, Q, N, j - 1, N, s);
       double aj = 0;
       KP_TRY(read_norm(c, sc, s, &aj));
@@ -684,28 +734,25 @@ kp_status egkb_impl(kp_ctx* c, const kp_blur* b, const kp_gkb_opts* o, kp_factor
 // QR: W = Q_w R_w, R_w = U_w S Z^T, so the triplets become (Q_w U_w, S, V_k Z)
 // (one-sided Rayleigh-Ritz on range(V_k)).
 template <typename T>
-kp_status rsvd_impl(kp_ctx* c, const kp_blur* b, const kp_rsvd_opts* o, kp_factors* f,
+kp_status rsvd_impl(kp_ctx* c, const RmatOp<T>& op, const kp_rsvd_opts* o, kp_factors* f,
                     hipStream_t s) {
   Timer timer(s);
-  const int n = b->n;
+  const int n = op.n;
   const long N = (long)n * n;
   const int k = o->k;
   const int kp = o->k + o->p;
   const kp_prec pp = o->prec;
-  double* dpsf = nullptr;
-  KP_TRY(upload_psf(c, b, s, &dpsf));
-  Grids<T> g;
-  KP_TRY(build_grids<T>(c, b, dpsf, s, &g));
+  const kp_blur* b = op.blur;            // generated operator only (16-bit modes)
   Grids<__hip_bfloat16> gb;
   Grids<__half> gh;
-  if (pp == KP_BF16) KP_TRY(build_grids<__hip_bfloat16>(c, b, dpsf, s, &gb));
-  if (pp == KP_F16) KP_TRY(build_grids<__half>(c, b, dpsf, s, &gh));
+  if (pp == KP_BF16) KP_TRY(build_grids<__hip_bfloat16>(c, b, op.dpsf, s, &gb));
+  if (pp == KP_F16) KP_TRY(build_grids<__half>(c, b, op.dpsf, s, &gh));
   auto prod = [&](int tr, const T* X, T* Yo, int nc) -> kp_status {
     if constexpr (std::is_same<T, float>::value) {
       if (pp == KP_BF16) return block_product16<__hip_bfloat16>(c, gb, n, tr, X, Yo, nc, s);
       if (pp == KP_F16) return block_product16<__half>(c, gh, n, tr, X, Yo, nc, s);
     }
-    return block_product<T>(c, g, n, tr, X, Yo, nc, s);
+    return op.block(c, tr, X, Yo, nc, s);
   };
   Scratch sc;
   KP_TRY(get_scratch(c, &sc));
@@ -755,10 +802,10 @@ kp_status rsvd_impl(kp_ctx* c, const kp_blur* b, const kp_rsvd_opts* o, kp_facto
     launch_convert<double, T>(Vd, Vf, N * kout, s);
     KP_TRY(cgs_qr<T>(c, sc, Vf, N, kout, nullptr, o->seed, sb += 64, s));
     if constexpr (std::is_same<T, float>::value) {
-      if (o->refine == 2) KP_TRY(split16_product(c, b, dpsf, n, Vf, W, kout, s));
-      else KP_TRY(block_product<T>(c, g, n, 0, Vf, W, kout, s));
+      if (o->refine == 2 && b) KP_TRY(split16_product(c, b, op.dpsf, n, Vf, W, kout, s));
+      else KP_TRY(op.block(c, 0, Vf, W, kout, s));
     } else {
-      KP_TRY(block_product<T>(c, g, n, 0, Vf, W, kout, s));
+      KP_TRY(op.block(c, 0, Vf, W, kout, s));
     }
     KP_TRY(cgs_qr<T>(c, sc, W, N, kout, Rh, o->seed, sb += 64, s));
     launch_jacobi_svd(Rh, kout, kout, Ur, sig, Vr, sweeps, s);
@@ -794,25 +841,60 @@ kp_status validate_apply_factors(kp_ctx* c, const kp_factors* f) {
 // iterations; device flags turn the remainder into no-ops once RC_CGLS <
 // tau_cgls (per outer iteration) or RC_SB < tau_sb, and the host polls the
 // flags every few iterations to stop queueing.
-kp_status sb_solve(kp_ctx* c, const kp_factors* f, const double* b, const sb_opts* o, double* x,
-                   sb_stats* st, hipStream_t s, int iso) {
-  KP_TRY(validate_apply_factors(c, f));
+// The blur operator of a split Bregman solve: the Kronecker sum A_k (factors)
+// or an explicit N x N matrix A in HBM (the paper's method (i) of Table 1).
+// apply(tr, v, P, flags, s) enqueues op(A) v as `ngroups` partial images in P.
+struct SbOp {
+  int n = 0;
+  const kp_factors* f = nullptr;
+  const double* A = nullptr;
+  KpApplyPlan plan;
+  double *Z = nullptr, *gv = nullptr, *tv = nullptr, *ty = nullptr;
+  int ngroups() const { return A ? 1 : plan.ngroups; }
+  void apply(int tr, const double* v, double* P, const int* flags, int nflags,
+             hipStream_t s) const {
+    if (A) {
+      // images are row-major (pixel (r, c) at r n + c); A acts on vec (r + n c)
+      launch_transpose_image(v, tv, n, flags, nflags, s);
+      launch_stored_gemv<double>(A, (long)n * n, tr, tv, ty, nullptr, 0.0, gv, s, flags, nflags);
+      launch_transpose_image(ty, P, n, flags, nflags, s);
+      return;
+    }
+    launch_kp_apply_parts((const double*)f->Ax, (const double*)f->Ay, n, f->k, tr, v, Z, P,
+                          plan, flags, nflags, s);
+  }
+};
+
+kp_status sb_check_opts(kp_ctx* c, const double* b, const sb_opts* o, double* x) {
   if (!b || !x || !o) return set_err(c, KP_E_INVAL, "b, x or opts is NULL");
   if (b == x) return set_err(c, KP_E_INVAL, "b and x must not alias");
   if (!(o->lambda > 0) || !(o->beta > 0) || !std::isfinite(o->lambda) || !std::isfinite(o->beta))
     return set_err(c, KP_E_INVAL, "lambda and beta must be positive and finite");
   if (o->L_max < 1 || o->I_max < 1) return set_err(c, KP_E_INVAL, "L_max and I_max must be >= 1");
   if (o->tau_sb < 0 || o->tau_cgls < 0) return set_err(c, KP_E_INVAL, "tolerances must be >= 0");
+  return KP_OK;
+}
+
+kp_status sb_solve_impl(kp_ctx* c, SbOp& op, const double* b, const sb_opts* o, double* x,
+                        sb_stats* st, hipStream_t s, int iso) {
   KP_HIP(c, hipSetDevice(c->device));
   Timer timer(s);
-  const int n = f->n, k = f->k;
+  const int n = op.n;
   const long NN = (long)n * n;
   double* img = nullptr;
   KP_TRY(wsT(c, "sb_img", (size_t)14 * NN, &img));
-  double *Z, *P, *part, *scal;
+  double *P, *part, *scal;
   int* flags;
-  KP_TRY(wsT(c, "kpZ", (size_t)k * NN, &Z));
-  KP_TRY(wsT(c, "kpP", (size_t)k * NN, &P));
+  if (op.A) {
+    KP_TRY(wsT(c, "kpP", (size_t)NN, &P));
+    KP_TRY(wsT(c, "sb_gv", (size_t)stored_gemv_ws(NN), &op.gv));
+    KP_TRY(wsT(c, "sb_tv", (size_t)2 * NN, &op.tv));
+    op.ty = op.tv + NN;
+  } else {
+    KP_TRY(wsT(c, "kpZ", (size_t)op.f->k * NN, &op.Z));
+    KP_TRY(wsT(c, "kpP", (size_t)op.f->k * NN, &P));
+    op.plan = kp_apply_plan(n, op.f->k);
+  }
   KP_TRY(wsT(c, "sb_part", (size_t)kRedBlocks * 4, &part));
   KP_TRY(wsT(c, "sb_scal", 8, &scal));
   KP_TRY(wsT(c, "sb_flags", 4, &flags));
@@ -842,13 +924,12 @@ kp_status sb_solve(kp_ctx* c, const kp_factors* f, const double* b, const sb_opt
   d.part = part;
   d.scal = scal;
   d.flags = flags;
-  const double* Ax = (const double*)f->Ax;
-  const double* Ay = (const double*)f->Ay;
   launch_fill(d.dx, 4 * NN, 0.0, s);                 // dx, dy, gx, gy (contiguous)
   launch_fill_small(scal, 8, 0.0, s);
   launch_fill_int(flags, 4, 0, s);
   KP_HIP(c, hipMemcpyAsync(d.xprev, b, sizeof(double) * NN, hipMemcpyDeviceToDevice, s));
-  launch_kp_apply_ws(Ax, Ay, n, k, 1, b, AtB, Z, P, nullptr, 0, s);
+  op.apply(1, b, P, nullptr, 0, s);
+  launch_sum_parts(P, op.ngroups(), NN, AtB, s);
   KP_TRY(check_launch(c, "sb init"));
   const int poll = 8;
   int* hflags = reinterpret_cast<int*>(c->pinned);
@@ -857,13 +938,13 @@ kp_status sb_solve(kp_ctx* c, const kp_factors* f, const double* b, const sb_opt
     KP_HIP(c, hipStreamSynchronize(s));
     return KP_OK;
   };
-  const KpApplyPlan plan = kp_apply_plan(n, k);
+  const int ng = op.ngroups();
   auto cgls_iteration = [&](hipStream_t st) {
-    launch_kp_apply_parts(Ax, Ay, n, k, 0, d.w, Z, P, plan, flags, 2, st);
-    sb_launch_zn(d, P, plan.ngroups, st);
+    op.apply(0, d.w, P, flags, 2, st);
+    sb_launch_zn(d, P, ng, st);
     sb_launch_xr(d, st);
-    launch_kp_apply_parts(Ax, Ay, n, k, 1, d.r1, Z, P, plan, flags, 2, st);
-    sb_launch_f(d, P, plan.ngroups, 2, st);
+    op.apply(1, d.r1, P, flags, 2, st);
+    sb_launch_f(d, P, ng, 2, st);
     sb_launch_w(d, st);
   };
   // With KPSB_SB_GRAPH=1, `poll` CGLS iterations (8 x 8 kernels) are captured
@@ -939,6 +1020,27 @@ kp_status sb_solve(kp_ctx* c, const kp_factors* f, const double* b, const sb_opt
   }
   (void)timer;
   return KP_OK;
+}
+
+kp_status sb_solve(kp_ctx* c, const kp_factors* f, const double* b, const sb_opts* o, double* x,
+                   sb_stats* st, hipStream_t s, int iso) {
+  KP_TRY(validate_apply_factors(c, f));
+  KP_TRY(sb_check_opts(c, b, o, x));
+  SbOp op;
+  op.n = f->n;
+  op.f = f;
+  return sb_solve_impl(c, op, b, o, x, st, s, iso);
+}
+
+kp_status sb_solve_direct(kp_ctx* c, int n, const double* A, const double* b, const sb_opts* o,
+                          double* x, sb_stats* st, hipStream_t s, int iso) {
+  if (n < 2 || n > 1024) return set_err(c, KP_E_INVAL, "n must be in [2, 1024]");
+  if (!A) return set_err(c, KP_E_INVAL, "A is NULL");
+  KP_TRY(sb_check_opts(c, b, o, x));
+  SbOp op;
+  op.n = n;
+  op.A = A;
+  return sb_solve_impl(c, op, b, o, x, st, s, iso);
 }
 
 }  // namespace
@@ -1123,13 +1225,11 @@ kp_status kp_rmat_apply(kp_ctx* c, const kp_blur* b, int transpose, kp_prec prec
   return set_err(c, KP_E_INVAL, "precision not supported by kp_rmat_apply");
 }
 
-kp_status kp_svd_gkb(kp_ctx* c, const kp_blur* b, const kp_gkb_opts* o, kp_factors* f,
-                     void* stream) {
-  if (!c) return KP_E_INVAL;
-  KP_TRY(validate_blur(c, b));
+namespace {
+kp_status check_gkb(kp_ctx* c, const kp_gkb_opts* o, kp_factors* f, int n) {
   if (!o) return set_err(c, KP_E_INVAL, "opts is NULL");
-  KP_TRY(validate_factors_out(c, f, b->n));
-  const long N = (long)b->n * b->n;
+  KP_TRY(validate_factors_out(c, f, n));
+  const long N = (long)n * n;
   if (o->k < 1 || o->p < 0) return set_err(c, KP_E_INVAL, "need k >= 1 and p >= 0");
   if (o->k + o->p + 1 > 64) return set_err(c, KP_E_INVAL, "k + p must be <= 63");
   if (o->k + o->p + 1 > N) return set_err(c, KP_E_INVAL, "k + p must be < n^2");
@@ -1138,34 +1238,140 @@ kp_status kp_svd_gkb(kp_ctx* c, const kp_blur* b, const kp_gkb_opts* o, kp_facto
   if (o->y0)
     for (long e = 0; e < N; ++e)
       if (!std::isfinite(o->y0[e])) return set_err(c, KP_E_NUMERIC, "y0 has a non-finite entry");
+  if (o->prec != KP_F32 && o->prec != KP_F64)
+    return set_err(c, KP_E_INVAL, "EGKB precision must be KP_F32 or KP_F64");
+  return KP_OK;
+}
+
+kp_status check_rsvd(kp_ctx* c, const kp_rsvd_opts* o, kp_factors* f, int n) {
+  if (!o) return set_err(c, KP_E_INVAL, "opts is NULL");
+  KP_TRY(validate_factors_out(c, f, n));
+  const long N = (long)n * n;
+  if (o->k < 1 || o->p < 0 || o->q < 0) return set_err(c, KP_E_INVAL, "need k >= 1, p >= 0, q >= 0");
+  if (o->k + o->p > 64) return set_err(c, KP_E_INVAL, "k + p must be <= 64");
+  if (o->k + o->p > N) return set_err(c, KP_E_INVAL, "k + p must be <= n^2");
+  if (f->k_cap < 1) return set_err(c, KP_E_INVAL, "factors.k_cap must be >= 1");
+  if (o->refine < 0 || o->refine > 2) return set_err(c, KP_E_INVAL, "refine must be 0, 1 or 2");
+  if (o->F)
+    for (long e = 0; e < N * (o->k + o->p); ++e)
+      if (!std::isfinite(o->F[e])) return set_err(c, KP_E_NUMERIC, "F has a non-finite entry");
+  if (o->prec != KP_F32 && o->prec != KP_F64 && o->prec != KP_BF16 && o->prec != KP_F16)
+    return set_err(c, KP_E_INVAL, "unknown RSVD precision");
+  return KP_OK;
+}
+
+kp_status check_stored(kp_ctx* c, int n, const void* R, kp_prec prec) {
+  if (n < 2 || n > 1024) return set_err(c, KP_E_INVAL, "n must be in [2, 1024]");
+  if (!R) return set_err(c, KP_E_INVAL, "R is NULL");
+  if (prec != KP_F32 && prec != KP_F64)
+    return set_err(c, KP_E_INVAL, "a stored R is KP_F32 or KP_F64");
+  return KP_OK;
+}
+}  // namespace
+
+kp_status kp_svd_gkb(kp_ctx* c, const kp_blur* b, const kp_gkb_opts* o, kp_factors* f,
+                     void* stream) {
+  if (!c) return KP_E_INVAL;
+  KP_TRY(validate_blur(c, b));
+  KP_TRY(check_gkb(c, o, f, b->n));
   KP_HIP(c, hipSetDevice(c->device));
   hipStream_t s = (hipStream_t)stream;
-  if (o->prec == KP_F32) return egkb_impl<float>(c, b, o, f, s);
-  if (o->prec == KP_F64) return egkb_impl<double>(c, b, o, f, s);
-  return set_err(c, KP_E_INVAL, "EGKB precision must be KP_F32 or KP_F64");
+  if (o->prec == KP_F32) {
+    RmatOp<float> op;
+    KP_TRY(make_generated_op<float>(c, b, s, &op));
+    return egkb_impl<float>(c, op, o, f, s);
+  }
+  RmatOp<double> op;
+  KP_TRY(make_generated_op<double>(c, b, s, &op));
+  return egkb_impl<double>(c, op, o, f, s);
 }
 
 kp_status kp_svd_rsvd(kp_ctx* c, const kp_blur* b, const kp_rsvd_opts* o, kp_factors* f,
                       void* stream) {
   if (!c) return KP_E_INVAL;
   KP_TRY(validate_blur(c, b));
-  if (!o) return set_err(c, KP_E_INVAL, "opts is NULL");
-  KP_TRY(validate_factors_out(c, f, b->n));
-  const long N = (long)b->n * b->n;
-  if (o->k < 1 || o->p < 0 || o->q < 0) return set_err(c, KP_E_INVAL, "need k >= 1, p >= 0, q >= 0");
-  if (o->k + o->p > 64) return set_err(c, KP_E_INVAL, "k + p must be <= 64");
-  if (o->k + o->p > N) return set_err(c, KP_E_INVAL, "k + p must be <= n^2");
-  if (f->k_cap < 1) return set_err(c, KP_E_INVAL, "factors.k_cap must be >= 1");
-  if (o->F)
-    for (long e = 0; e < N * (o->k + o->p); ++e)
-      if (!std::isfinite(o->F[e])) return set_err(c, KP_E_NUMERIC, "F has a non-finite entry");
+  KP_TRY(check_rsvd(c, o, f, b->n));
   KP_HIP(c, hipSetDevice(c->device));
   hipStream_t s = (hipStream_t)stream;
-  if (o->refine < 0 || o->refine > 2) return set_err(c, KP_E_INVAL, "refine must be 0, 1 or 2");
-  if (o->prec == KP_F32 || o->prec == KP_BF16 || o->prec == KP_F16)
-    return rsvd_impl<float>(c, b, o, f, s);
-  if (o->prec == KP_F64) return rsvd_impl<double>(c, b, o, f, s);
-  return set_err(c, KP_E_INVAL, "unknown RSVD precision");
+  if (o->prec == KP_F64) {
+    RmatOp<double> op;
+    KP_TRY(make_generated_op<double>(c, b, s, &op));
+    return rsvd_impl<double>(c, op, o, f, s);
+  }
+  RmatOp<float> op;
+  KP_TRY(make_generated_op<float>(c, b, s, &op));
+  return rsvd_impl<float>(c, op, o, f, s);
+}
+
+kp_status kp_rmat_reorder(kp_ctx* c, int32_t n, kp_prec prec, const void* A, void* R,
+                          void* stream) {
+  if (!c) return KP_E_INVAL;
+  KP_TRY(check_stored(c, n, R, prec));
+  if (!A) return set_err(c, KP_E_INVAL, "A is NULL");
+  const size_t bytes = (size_t)n * n * (size_t)n * n * (prec == KP_F64 ? 8 : 4);
+  const char* a = (const char*)A;
+  const char* r = (const char*)R;
+  if (a < r + bytes && r < a + bytes) return set_err(c, KP_E_INVAL, "A and R overlap");
+  KP_HIP(c, hipSetDevice(c->device));
+  hipStream_t s = (hipStream_t)stream;
+  if (prec == KP_F64) launch_reorder<double>((const double*)A, (double*)R, n, s);
+  else launch_reorder<float>((const float*)A, (float*)R, n, s);
+  return check_launch(c, "reorder");
+}
+
+kp_status kp_rmat_apply_stored(kp_ctx* c, int32_t n, kp_prec prec, const void* R, int transpose,
+                               int32_t ncols, const void* X, void* Y, void* stream) {
+  if (!c) return KP_E_INVAL;
+  KP_TRY(check_stored(c, n, R, prec));
+  if (ncols < 1 || ncols > 4096) return set_err(c, KP_E_INVAL, "ncols must be in [1, 4096]");
+  if (!X || !Y) return set_err(c, KP_E_INVAL, "X or Y is NULL");
+  if (X == Y) return set_err(c, KP_E_INVAL, "X and Y must not alias");
+  KP_HIP(c, hipSetDevice(c->device));
+  hipStream_t s = (hipStream_t)stream;
+  if (prec == KP_F64) {
+    RmatOp<double> op;
+    KP_TRY(make_stored_op<double>(c, n, (const double*)R, &op));
+    return ncols == 1 ? op.gemv(c, transpose, (const double*)X, (double*)Y, nullptr, 0.0, s)
+                      : op.block(c, transpose, (const double*)X, (double*)Y, ncols, s);
+  }
+  RmatOp<float> op;
+  KP_TRY(make_stored_op<float>(c, n, (const float*)R, &op));
+  return ncols == 1 ? op.gemv(c, transpose, (const float*)X, (float*)Y, nullptr, 0.0, s)
+                    : op.block(c, transpose, (const float*)X, (float*)Y, ncols, s);
+}
+
+kp_status kp_svd_gkb_stored(kp_ctx* c, int32_t n, const void* R, const kp_gkb_opts* o,
+                            kp_factors* f, void* stream) {
+  if (!c) return KP_E_INVAL;
+  KP_TRY(check_gkb(c, o, f, n));
+  KP_TRY(check_stored(c, n, R, o->prec));
+  KP_HIP(c, hipSetDevice(c->device));
+  hipStream_t s = (hipStream_t)stream;
+  if (o->prec == KP_F32) {
+    RmatOp<float> op;
+    KP_TRY(make_stored_op<float>(c, n, (const float*)R, &op));
+    return egkb_impl<float>(c, op, o, f, s);
+  }
+  RmatOp<double> op;
+  KP_TRY(make_stored_op<double>(c, n, (const double*)R, &op));
+  return egkb_impl<double>(c, op, o, f, s);
+}
+
+kp_status kp_svd_rsvd_stored(kp_ctx* c, int32_t n, const void* R, const kp_rsvd_opts* o,
+                             kp_factors* f, void* stream) {
+  if (!c) return KP_E_INVAL;
+  KP_TRY(check_rsvd(c, o, f, n));
+  KP_TRY(check_stored(c, n, R, o->prec));
+  KP_HIP(c, hipSetDevice(c->device));
+  hipStream_t s = (hipStream_t)stream;
+  if (o->prec == KP_F32) {
+    RmatOp<float> op;
+    KP_TRY(make_stored_op<float>(c, n, (const float*)R, &op));
+    return rsvd_impl<float>(c, op, o, f, s);
+  }
+  RmatOp<double> op;
+  KP_TRY(make_stored_op<double>(c, n, (const double*)R, &op));
+  return rsvd_impl<double>(c, op, o, f, s);
 }
 
 kp_status kp_apply(kp_ctx* c, const kp_factors* f, int transpose, const double* X, double* Y,
@@ -1198,6 +1404,18 @@ kp_status sb_solve_iso(kp_ctx* c, const kp_factors* f, const double* b, const sb
                        double* x, sb_stats* st, void* stream) {
   if (!c) return KP_E_INVAL;
   return sb_solve(c, f, b, o, x, st, (hipStream_t)stream, 1);
+}
+
+kp_status sb_solve_aniso_direct(kp_ctx* c, int32_t n, const double* A, const double* b,
+                                const sb_opts* o, double* x, sb_stats* st, void* stream) {
+  if (!c) return KP_E_INVAL;
+  return sb_solve_direct(c, n, A, b, o, x, st, (hipStream_t)stream, 0);
+}
+
+kp_status sb_solve_iso_direct(kp_ctx* c, int32_t n, const double* A, const double* b,
+                              const sb_opts* o, double* x, sb_stats* st, void* stream) {
+  if (!c) return KP_E_INVAL;
+  return sb_solve_direct(c, n, A, b, o, x, st, (hipStream_t)stream, 1);
 }
 
 }  // extern "C"

@@ -93,6 +93,25 @@ template <typename T>
 void launch_rmat_gemv(const BlockPlan& plan, const T* G, int ldg, int n, const T* x,
                       T* y, const T* z, double coef, hipStream_t s);
 
+// ---- explicit-matrix path (stored.hip) --------------------------------------
+// R[i + n j, r + n c] = A[r + n i, c + n j] (A, R row-major N x N, N = n^2)
+template <typename T>
+void launch_reorder(const T* A, T* R, int n, hipStream_t s);
+// y = op(R) x - coef z (op = R or R^T); ws: stored_gemv_ws(N) doubles
+long stored_gemv_ws(long N);
+template <typename T>
+void launch_stored_gemv(const T* R, long N, int transpose, const T* x, T* y, const T* z,
+                        double coef, double* ws, hipStream_t s, const int* flags = nullptr,
+                        int nflags = 0);
+// out[r + n c] = in[r n + c] (row-major image <-> column-major vec); skipped
+// when any of flags[0..nflags) is set
+void launch_transpose_image(const double* in, double* out, int n, const int* flags, int nflags,
+                            hipStream_t s);
+// Y = op(R) X, X and Y column-major N x ncols (ncols <= 32)
+template <typename T>
+void launch_stored_block(const T* R, long N, int transpose, const T* X, T* Y, int ncols,
+                         hipStream_t s);
+
 // ---- autotuner (tune.cpp) ---------------------------------------------------
 constexpr int kTuneBlock = 1;     // FP32 / FP64 block product: (TJ, waves)
 constexpr int kTuneBlock16 = 2;   // 16-bit block product: TJ

@@ -241,6 +241,13 @@ void launch_kp_apply_parts(const double* Ax, const double* Ay, int n, int k, int
   gemm(g2, v, plan.ngroups, s);
 }
 
+void launch_sum_parts(const double* P, int ng, long NN, double* Y, hipStream_t s) {
+  long blocks = (NN + 255) / 256;
+  if (blocks > 2048) blocks = 2048;
+  hipLaunchKernelGGL(sum_terms_kernel, dim3((int)blocks), dim3(256), 0, s, P, ng, NN, Y,
+                     (const int*)nullptr, 0);
+}
+
 void launch_kp_apply_ws(const double* Ax, const double* Ay, int n, int k, int transpose,
                         const double* X, double* Y, double* Z, double* P, const int* flags,
                         int nflags, hipStream_t s) {

@@ -45,6 +45,8 @@ void sb_launch_check(const SBDev& d, hipStream_t s);
 void launch_kp_apply_parts(const double* Ax, const double* Ay, int n, int k, int transpose,
                            const double* X, double* Z, double* P, const KpApplyPlan& plan,
                            const int* flags, int nflags, hipStream_t s);
+// Y = sum of the ng partial images at P (stride NN), fixed order
+void launch_sum_parts(const double* P, int ng, long NN, double* Y, hipStream_t s);
 // kp_apply with caller workspace Z, P (k x n x n each); skipped when any of
 // flags[0..nflags) is nonzero.
 void launch_kp_apply_ws(const double* Ax, const double* Ay, int n, int k, int transpose,

@@ -1,0 +1,268 @@
+// The explicit-matrix path: R(A) formed by reordering a dense blur matrix A
+// held in HBM (the paper's own pipeline stores A and rearranges it,
+// section 2.1, eq. "initial rearrange A"), and the products with the stored
+// R used by the KP-SVD drivers, as well as A x for split Bregman with A itself
+// (the paper's method (i) of Table 1). Works for any A (any boundary
+// condition, spatially variant blur); R is N x N with N = n^2, so the path
+// needs 2 N^2 elements of HBM (A and R) and every product streams R from HBM.
+//
+// Layouts: A and R are row-major N x N. X, Y blocks are column-major N x b.
+#include "common.h"
+
+namespace kpsb {
+
+// R[i + n j, r + n c] = A[r + n i, c + n j]: row (i + n j) of R is the column-
+// major vec of block A_{i,j}. One workgroup per (block, 32 x 32 sub-tile),
+// transposed through LDS so that both the read (along c) and the write
+// (along r) are contiguous.
+template <typename T>
+__global__ void __launch_bounds__(256)
+reorder_kernel(const T* __restrict__ A, T* __restrict__ R, int n) {
+  __shared__ T tile[32][33];
+  const long N = (long)n * n;
+  const int tpb = (n + 31) / 32;                 // 32-wide sub-tiles per block side
+  const long blk = blockIdx.x / (tpb * tpb);     // block index i + n j
+  const int sub = blockIdx.x % (tpb * tpb);
+  const int i = (int)(blk % n), j = (int)(blk / n);
+  const int r0 = (sub % tpb) * 32, c0 = (sub / tpb) * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 32 x 8
+  for (int rr = ty; rr < 32; rr += 8) {         // read rows r of the block, c contiguous
+    const int r = r0 + rr, c = c0 + tx;
+    tile[rr][tx] = (r < n && c < n) ? A[(long)(r + (long)n * i) * N + c + (long)n * j] : (T)0;
+  }
+  __syncthreads();
+  for (int cc = ty; cc < 32; cc += 8) {         // write R row blk, r contiguous
+    const int c = c0 + cc, r = r0 + tx;
+    if (r < n && c < n) R[blk * N + r + (long)n * c] = tile[tx][cc];
+  }
+}
+
+template <typename T>
+void launch_reorder(const T* A, T* R, int n, hipStream_t s) {
+  const int tpb = (n + 31) / 32;
+  const long grid = (long)n * n * tpb * tpb;
+  hipLaunchKernelGGL(reorder_kernel<T>, dim3((unsigned)grid), dim3(256), 0, s, A, R, n);
+}
+template void launch_reorder<float>(const float*, float*, int, hipStream_t);
+template void launch_reorder<double>(const double*, double*, int, hipStream_t);
+
+// ---------------------------------------------------------------------------
+// y = M x - coef z with M = R (transpose = 0) or R^T, R row-major N x N; FP64
+// accumulation. Row product: one wave per row, coalesced along the row.
+__device__ __forceinline__ bool any_flag(const int* flags, int nflags) {
+  if (flags)
+    for (int i = 0; i < nflags; ++i)
+      if (flags[i]) return true;
+  return false;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+stored_gemv_rows_kernel(const T* __restrict__ R, long N, const T* __restrict__ x,
+                        T* __restrict__ y, const T* __restrict__ z, double coef,
+                        const int* __restrict__ flags, int nflags) {
+  if (any_flag(flags, nflags)) return;
+  const int lane = threadIdx.x & 63;
+  const long row = (long)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row >= N) return;
+  const T* rp = R + row * N;
+  double acc = 0.0;
+  for (long c = lane; c < N; c += 64) acc += (double)rp[c] * (double)x[c];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+  if (lane == 0) {
+    double v = acc;
+    if (z) v -= coef * (double)z[row];
+    y[row] = (T)v;
+  }
+}
+
+// Column product (R^T w): workgroup (column strip of 256, row chunk) writes a
+// partial sum per column; the chunks are then added in a fixed order.
+constexpr int kGvChunks = 16;
+template <typename T>
+__global__ void __launch_bounds__(256)
+stored_gemv_cols_kernel(const T* __restrict__ R, long N, const T* __restrict__ w,
+                        double* __restrict__ part, const int* __restrict__ flags, int nflags) {
+  if (any_flag(flags, nflags)) return;
+  const long col = (long)blockIdx.x * 256 + threadIdx.x;
+  const int chunk = blockIdx.y;
+  const long rows = (N + kGvChunks - 1) / kGvChunks;
+  const long r0 = chunk * rows, r1 = r0 + rows < N ? r0 + rows : N;
+  if (col >= N) return;
+  double acc = 0.0;
+  for (long r = r0; r < r1; ++r) acc += (double)R[r * N + col] * (double)w[r];
+  part[(long)chunk * N + col] = acc;
+}
+
+template <typename T>
+__global__ void stored_gemv_sum_kernel(const double* __restrict__ part, long N,
+                                       T* __restrict__ y, const T* __restrict__ z, double coef,
+                                       const int* __restrict__ flags, int nflags) {
+  if (any_flag(flags, nflags)) return;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < N;
+       e += (long)gridDim.x * blockDim.x) {
+    double v = 0.0;
+    for (int ch = 0; ch < kGvChunks; ++ch) v += part[(long)ch * N + e];
+    if (z) v -= coef * (double)z[e];
+    y[e] = (T)v;
+  }
+}
+
+long stored_gemv_ws(long N) { return (long)kGvChunks * N; }
+
+template <typename T>
+void launch_stored_gemv(const T* R, long N, int transpose, const T* x, T* y, const T* z,
+                        double coef, double* ws, hipStream_t s, const int* flags, int nflags) {
+  if (!transpose) {
+    hipLaunchKernelGGL(stored_gemv_rows_kernel<T>, dim3((unsigned)((N + 3) / 4)), dim3(256), 0,
+                       s, R, N, x, y, z, coef, flags, nflags);
+    return;
+  }
+  hipLaunchKernelGGL(stored_gemv_cols_kernel<T>, dim3((unsigned)((N + 255) / 256), kGvChunks),
+                     dim3(256), 0, s, R, N, x, ws, flags, nflags);
+  long blocks = (N + 255) / 256;
+  if (blocks > 2048) blocks = 2048;
+  hipLaunchKernelGGL(stored_gemv_sum_kernel<T>, dim3((unsigned)blocks), dim3(256), 0, s, ws, N,
+                     y, z, coef, flags, nflags);
+}
+template void launch_stored_gemv<float>(const float*, long, int, const float*, float*,
+                                        const float*, double, double*, hipStream_t, const int*,
+                                        int);
+template void launch_stored_gemv<double>(const double*, long, int, const double*, double*,
+                                         const double*, double, double*, hipStream_t,
+                                         const int*, int);
+
+// out[r + n c] = in[r n + c]: an n x n image (row-major) to its column-major
+// vec and back (the same map); skipped when a flag is set.
+__global__ void transpose_image_kernel(const double* __restrict__ in, double* __restrict__ out,
+                                       int n, const int* __restrict__ flags, int nflags) {
+  if (any_flag(flags, nflags)) return;
+  __shared__ double tile[32][33];
+  const int r0 = blockIdx.y * 32, c0 = blockIdx.x * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  for (int rr = ty; rr < 32; rr += 8) {
+    const int r = r0 + rr, c = c0 + tx;
+    tile[rr][tx] = (r < n && c < n) ? in[(long)r * n + c] : 0.0;
+  }
+  __syncthreads();
+  for (int cc = ty; cc < 32; cc += 8) {
+    const int c = c0 + cc, r = r0 + tx;
+    if (r < n && c < n) out[r + (long)n * c] = tile[tx][cc];
+  }
+}
+
+void launch_transpose_image(const double* in, double* out, int n, const int* flags, int nflags,
+                            hipStream_t s) {
+  const int t = (n + 31) / 32;
+  hipLaunchKernelGGL(transpose_image_kernel, dim3(t, t), dim3(256), 0, s, in, out, n, flags,
+                     nflags);
+}
+
+// ---------------------------------------------------------------------------
+// Y = op(R) X for up to 32 columns on MFMA: a workgroup owns 64 rows of op(R)
+// (4 waves x 16 rows, each wave 2 x 16 columns) and streams K in tiles of 64:
+// the 64 x 64 tile of op(R) (read along R's rows in both orientations, stored
+// k-major in LDS) and the 64 x 32 tile of X. R is read once per product; FP32
+// accumulators are flushed into FP64 after every K tile.
+template <typename T> struct MfmaT;
+template <> struct MfmaT<float> {
+  typedef floatx4 acc;
+  static __device__ __forceinline__ acc mma(float a, float b, acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int drow(int lk, int e) { return 4 * lk + e; }
+};
+template <> struct MfmaT<double> {
+  typedef doublex4 acc;
+  static __device__ __forceinline__ acc mma(double a, double b, acc c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int drow(int lk, int e) { return lk + 4 * e; }
+};
+
+constexpr int kSgM = 64, kSgK = 64, kSgAS = kSgM + 1, kSgXS = 32 + 1;
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+stored_block_kernel(const T* __restrict__ R, long N, int transpose, const T* __restrict__ X,
+                    T* __restrict__ Y, int ncols) {
+  __shared__ T As[kSgK][kSgAS];   // As[k][m] = op(R)[m0 + m][k0 + k]
+  __shared__ T Xs[kSgK][kSgXS];   // Xs[k][col] = X[k0 + k, col]
+  typedef typename MfmaT<T>::acc acc_t;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const long m0 = (long)blockIdx.x * kSgM;
+  const int lrow = lane & 15, lk = lane >> 4;
+  acc_t acc[2];
+  double accd[2][4];
+#pragma unroll
+  for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      acc[cb][e] = (T)0;
+      accd[cb][e] = 0.0;
+    }
+  for (long k0 = 0; k0 < N; k0 += kSgK) {
+    // op(R) tile: 64 x 64 elements, 16 per thread, contiguous along R's rows
+#pragma unroll 4
+    for (int q = 0; q < (kSgM * kSgK) / 256; ++q) {
+      const int e = tid + 256 * q;
+      const int fast = e & 63, slow = e >> 6;
+      T v = (T)0;
+      if (!transpose) {            // op(R)[m][k] = R[m0 + slow][k0 + fast]
+        const long m = m0 + slow, k = k0 + fast;
+        if (m < N && k < N) v = R[m * N + k];
+        As[fast][slow] = v;
+      } else {                     // op(R)[m][k] = R[k0 + slow][m0 + fast]
+        const long k = k0 + slow, m = m0 + fast;
+        if (m < N && k < N) v = R[k * N + m];
+        As[slow][fast] = v;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < (kSgK * 32) / 256; ++q) {
+      const int e = tid + 256 * q;
+      const int kk = e & 63, col = e >> 6;
+      const long k = k0 + kk;
+      Xs[kk][col] = (col < ncols && k < N) ? X[(long)col * N + k] : (T)0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s4 = 0; s4 < kSgK / 4; ++s4) {
+      const int kk = 4 * s4 + lk;
+      const T a = As[kk][wave * 16 + lrow];
+#pragma unroll
+      for (int cb = 0; cb < 2; ++cb) acc[cb] = MfmaT<T>::mma(a, Xs[kk][cb * 16 + lrow], acc[cb]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        accd[cb][e] += (double)acc[cb][e];
+        acc[cb][e] = (T)0;
+      }
+  }
+#pragma unroll
+  for (int cb = 0; cb < 2; ++cb) {
+    const int col = cb * 16 + lrow;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const long m = m0 + wave * 16 + MfmaT<T>::drow(lk, e);
+      if (m < N && col < ncols) Y[(long)col * N + m] = (T)accd[cb][e];
+    }
+  }
+}
+
+template <typename T>
+void launch_stored_block(const T* R, long N, int transpose, const T* X, T* Y, int ncols,
+                         hipStream_t s) {
+  hipLaunchKernelGGL(stored_block_kernel<T>, dim3((unsigned)((N + kSgM - 1) / kSgM)), dim3(256),
+                     0, s, R, N, transpose, X, Y, ncols);
+}
+template void launch_stored_block<float>(const float*, long, int, const float*, float*, int,
+                                         hipStream_t);
+template void launch_stored_block<double>(const double*, long, int, const double*, double*,
+                                          int, hipStream_t);
+
+}  // namespace kpsb
