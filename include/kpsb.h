@@ -319,6 +319,13 @@ kp_status kp_server_destroy(kp_server* srv);
  * streams the stored R from HBM.
  *
  * R[i + n*j, r + n*c] = A[r + n*i, c + n*j]. A and R must not overlap. */
+/* The explicit A of a blur (PSF as in kp_blur) with boundary conditions bc:
+ * 0 = zero, 1 = reflexive (the image extended by reflection about the edge of
+ * its last pixel, as in the paper's "Medium" example):
+ * A[r + n*i, c + n*j] = sum over the reflected images c~ of c and j~ of j of
+ * P[cu + r - c~, cv + i - j~] (for bc = 0 only c~ = c, j~ = j). */
+kp_status kp_blur_matrix(kp_ctx* ctx, const kp_blur* blur, int32_t bc, kp_prec prec, void* A,
+                         void* stream);
 kp_status kp_rmat_reorder(kp_ctx* ctx, int32_t n, kp_prec prec, const void* A, void* R,
                           void* stream);
 /* Y = R X or R^T X with the stored R (X, Y: DEVICE N x ncols column-major;

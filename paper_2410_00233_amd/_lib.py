@@ -29,7 +29,7 @@ EXPORTED = ["kp_ctx_create", "kp_ctx_destroy", "kp_last_error", "kp_version",
             "kp_server_create", "kp_server_submit", "kp_server_wait", "kp_server_stats",
             "kp_server_destroy", "kp_tune_report", "kp_rmat_reorder", "kp_rmat_apply_stored",
             "kp_svd_gkb_stored", "kp_svd_rsvd_stored", "sb_solve_aniso_direct",
-            "sb_solve_iso_direct"]
+            "sb_solve_iso_direct", "kp_blur_matrix"]
 
 
 class kp_blur(C.Structure):
@@ -132,6 +132,7 @@ def load(path: str = LIB_PATH):
     lib.kp_server_destroy.argtypes = [vp]
     lib.kp_tune_report.argtypes = [C.c_char_p, C.c_size_t]
     lib.kp_rmat_reorder.argtypes = [vp, C.c_int32, C.c_int, vp, vp, vp]
+    lib.kp_blur_matrix.argtypes = [vp, C.POINTER(kp_blur), C.c_int32, C.c_int, vp, vp]
     lib.kp_rmat_apply_stored.argtypes = [vp, C.c_int32, C.c_int, vp, C.c_int, C.c_int32, vp, vp,
                                          vp]
     lib.kp_svd_gkb_stored.argtypes = [vp, C.c_int32, vp, C.POINTER(kp_gkb_opts),

@@ -248,6 +248,17 @@ class Context:
             f.Y = Y
         return f
 
+    def kp_blur_matrix(self, blur: Blur, bc="zero", prec="f64", A=None):
+        """Explicit blur matrix (device N x N) with zero or reflexive BC."""
+        torch = _torch()
+        N = blur.n * blur.n
+        if A is None:
+            A = torch.empty((N, N), dtype=torch.float64 if prec == "f64" else torch.float32,
+                            device="cuda")
+        self._check(self.lib.kp_blur_matrix(self.h, C.byref(blur.s), 1 if bc == "reflexive" else 0,
+                                            PREC[prec], _ptr(A), _stream()))
+        return A
+
     def kp_rmat_reorder(self, n, A, R=None):
         """R(A) from a stored blur matrix A (device tensor N x N, FP32 or FP64)."""
         torch = _torch()

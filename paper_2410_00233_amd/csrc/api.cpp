@@ -1303,6 +1303,23 @@ kp_status kp_svd_rsvd(kp_ctx* c, const kp_blur* b, const kp_rsvd_opts* o, kp_fac
   return rsvd_impl<float>(c, op, o, f, s);
 }
 
+kp_status kp_blur_matrix(kp_ctx* c, const kp_blur* b, int32_t bc, kp_prec prec, void* A,
+                         void* stream) {
+  if (!c) return KP_E_INVAL;
+  KP_TRY(validate_blur(c, b));
+  KP_TRY(check_stored(c, b->n, A, prec));
+  if (bc != 0 && bc != 1) return set_err(c, KP_E_INVAL, "bc must be 0 (zero) or 1 (reflexive)");
+  KP_HIP(c, hipSetDevice(c->device));
+  hipStream_t s = (hipStream_t)stream;
+  double* dpsf = nullptr;
+  KP_TRY(upload_psf(c, b, s, &dpsf));
+  if (prec == KP_F64)
+    launch_blur_matrix<double>(dpsf, b->pu, b->pv, b->cu, b->cv, b->n, bc, (double*)A, s);
+  else
+    launch_blur_matrix<float>(dpsf, b->pu, b->pv, b->cu, b->cv, b->n, bc, (float*)A, s);
+  return check_launch(c, "blur_matrix");
+}
+
 kp_status kp_rmat_reorder(kp_ctx* c, int32_t n, kp_prec prec, const void* A, void* R,
                           void* stream) {
   if (!c) return KP_E_INVAL;

@@ -94,6 +94,11 @@ void launch_rmat_gemv(const BlockPlan& plan, const T* G, int ldg, int n, const T
                       T* y, const T* z, double coef, hipStream_t s);
 
 // ---- explicit-matrix path (stored.hip) --------------------------------------
+// A (N x N row-major) of the blur with PSF psf (device) and boundary
+// conditions bc (0 zero, 1 reflexive)
+template <typename T>
+void launch_blur_matrix(const double* psf, int pu, int pv, int cu, int cv, int n, int bc, T* A,
+                        hipStream_t s);
 // R[i + n j, r + n c] = A[r + n i, c + n j] (A, R row-major N x N, N = n^2)
 template <typename T>
 void launch_reorder(const T* A, T* R, int n, hipStream_t s);
