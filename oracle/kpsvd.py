@@ -151,6 +151,95 @@ def egkb(apply_R, apply_Rt, y, k, p, *, reorth="full", auto_k=False, k_min=0,
                 k=k, kp=kp, breakdowns=breakdowns, Uc=Uc, Vc=Vct.T)
 
 
+def _gs_column(w, basis, passes=2):
+    """Classical Gram-Schmidt of w against the columns of ``basis`` (N x m),
+    ``passes`` times; returns (w orthogonalized, total coefficients)."""
+    h = np.zeros(basis.shape[1])
+    for _ in range(passes):
+        if basis.shape[1] == 0:
+            break
+        hp = basis.T @ w
+        w = w - basis @ hp
+        h += hp
+    return w, h
+
+
+def block_egkb(apply_R, apply_Rt, Y, k, p, *, bd_rel=None, seed=0, dtype=np.float64):
+    """Block Golub-Kahan bidiagonalization with b = Y.shape[1] start vectors
+    (Golub, Luk & Overton 1981): the block analogue of Algorithm 1 with full
+    reorthogonalization, enlarged to k_p = k + p columns rounded up to whole
+    blocks (nb blocks of b).
+
+        U_1 = qr(Y),             V_1 L_1^T = B^T U_1,
+        U_{j+1} R_j = B V_j - U_j L_j,     V_{j+1} L_{j+1}^T = B^T U_{j+1} - V_j R_j^T,
+
+    so that B [V_1 .. V_nb] = [U_1 .. U_nb+1] C with C block lower bidiagonal
+    (L_j on the diagonal, R_j below). Each new block is orthonormalized column
+    by column with classical Gram-Schmidt applied twice against all previous
+    vectors of its basis (which subtracts U_j L_j and V_j R_j^T and
+    reorthogonalizes in one step); the coefficients on the block's own earlier
+    columns and the norms form R_j (resp. L_{j+1}^T). With b = 1 this is
+    Algorithm 1 with full reorthogonalization.
+
+    Breakdown: a norm that is 0 or <= bd_rel times the largest norm accepted so
+    far in C stores 0 and replaces the column by a Philox normal vector
+    orthogonalized twice against its basis (stream 2(m+1) for column m of U,
+    2(m+1)+1 for column m of V: for b = 1 the streams of Algorithm 1's s_{m+1},
+    q_{m+1}). The start block's own factor is not part of C (as t_1).
+    Returns dict(sigma, U, V, Ub, Vb, C, kp, breakdowns).
+    """
+    eps = np.finfo(dtype).eps / 2
+    if bd_rel is None:
+        bd_rel = 1e2 * eps
+    Y = np.asarray(Y, dtype=dtype)
+    N, b = Y.shape
+    nb = -(-(k + p) // b)
+    kp = nb * b
+    breakdowns = []
+    scale = [0.0]
+
+    def orth_block(W, basis, side, col0, in_c):
+        """Columns of W against `basis` then each other; returns (Q, own R)."""
+        Q = np.zeros_like(W)
+        Rown = np.zeros((W.shape[1], W.shape[1]))
+        for c in range(W.shape[1]):
+            full = np.concatenate([basis, Q[:, :c]], axis=1)
+            w, h = _gs_column(W[:, c], full)
+            nr = _norm(w)
+            Rown[:c, c] = h[basis.shape[1]:]
+            m = col0 + c
+            if nr == 0.0 or (in_c and nr <= bd_rel * scale[0]):
+                breakdowns.append((side, m))
+                g = philox.normals(N, seed, 2 * (m + 1) + (0 if side == "u" else 1)).astype(dtype)
+                g, _ = _gs_column(g, full)
+                w, nr_store = g / _norm(g), 0.0
+            else:
+                w, nr_store = w / nr, nr
+                if in_c:
+                    scale[0] = max(scale[0], nr)
+            Rown[c, c] = nr_store
+            Q[:, c] = w
+        return Q, Rown
+
+    U = np.zeros((N, 0), dtype=dtype)
+    V = np.zeros((N, 0), dtype=dtype)
+    U1, _ = orth_block(Y, U, "u", 0, False)
+    U = U1
+    C = np.zeros((kp + b, kp))
+    for j in range(nb):
+        W = apply_Rt(U[:, j * b:(j + 1) * b])
+        Vj, Lt = orth_block(W, V, "v", j * b, True)
+        V = np.concatenate([V, Vj], axis=1)
+        C[j * b:(j + 1) * b, j * b:(j + 1) * b] = Lt.T
+        Z = apply_R(Vj)
+        Uj, Rj = orth_block(Z, U, "u", (j + 1) * b, True)
+        U = np.concatenate([U, Uj], axis=1)
+        C[(j + 1) * b:(j + 2) * b, j * b:(j + 1) * b] = Rj
+    Uc, sc, Vct = np.linalg.svd(C, full_matrices=False)
+    return dict(sigma=sc[:k].copy(), sigma_all=sc, U=U @ Uc[:, :k], V=V @ Vct[:k].T, Ub=U,
+                Vb=V, C=C, kp=kp, breakdowns=breakdowns)
+
+
 def orth(X):
     """Orthonormal basis of range(X) (Householder QR, reduced)."""
     Qm, _ = np.linalg.qr(X)

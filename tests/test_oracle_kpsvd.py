@@ -177,3 +177,67 @@ def test_kp_terms_reconstruct_A_with_full_rank():
     for t in range(Ay.shape[0]):
         flat = Ay[t].flatten(order="F")
         assert flat[np.argmax(np.abs(flat))] > 0
+
+
+# ---------------------------------------------------------------------------
+# block Golub-Kahan (the block analogue of Algorithm 1)
+
+@pytest.mark.parametrize("b", [2, 4, 5])
+def test_block_egkb_relation_orthogonality_and_structure(b):
+    n = 16
+    P, cu, cv = wl.speckle_psf(n, seed=1003)
+    R, Rt = _ops(P, cu, cv, n)
+    Y = wl.gaussian_block(n * n, b, seed=4003)
+    out = kpsvd.block_egkb(R, Rt, Y, k=6, p=6)
+    U, V, C, kp = out["Ub"], out["Vb"], out["C"], out["kp"]
+    s1 = op.exact_kpsvd(P, cu, cv, n, 1)[0][0]
+    assert kp % b == 0 and kp >= 12 and U.shape[1] == kp + b and V.shape[1] == kp
+    assert np.linalg.norm(R(V) - U @ C) <= 1e-12 * s1          # B V = U C
+    assert np.abs(U.T @ U - np.eye(kp + b)).max() <= 1e-12
+    assert np.abs(V.T @ V - np.eye(kp)).max() <= 1e-12
+    # C is block lower bidiagonal: lower-triangular L_j on the diagonal,
+    # upper-triangular R_j below it, zero elsewhere
+    for j in range(kp // b):
+        for i in range(kp // b + 1):
+            blk = C[i * b:(i + 1) * b, j * b:(j + 1) * b]
+            if i == j:
+                assert np.all(np.triu(blk, 1) == 0)
+            elif i == j + 1:
+                assert np.all(np.tril(blk, -1) == 0)
+            else:
+                assert np.all(blk == 0)
+    # the first right block spans B^T Y
+    G = Rt(Y)
+    assert np.linalg.norm(G - V[:, :b] @ (V[:, :b].T @ G)) <= 1e-12 * np.linalg.norm(G)
+
+
+def test_block_egkb_with_one_vector_is_egkb():
+    n = 12
+    P, cu, cv = wl.speckle_psf(n, seed=1004)
+    R, Rt = _ops(P, cu, cv, n)
+    y = wl.gaussian_block(n * n, 1, seed=4004)
+    blk = kpsvd.block_egkb(R, Rt, y, k=5, p=5)
+    ref = kpsvd.egkb(R, Rt, y[:, 0], k=5, p=5, reorth="full")
+    s1 = ref["sigma"][0]
+    assert np.abs(blk["sigma"] - ref["sigma"]).max() <= 1e-12 * s1
+    # the bidiagonal itself: alpha on the diagonal, t on the subdiagonal
+    assert np.allclose(np.diag(blk["C"]), ref["alpha"], atol=1e-12 * s1)
+    assert np.allclose(np.diag(blk["C"], -1), ref["t"][1:], atol=1e-12 * s1)
+
+
+def test_block_egkb_exact_for_low_rank_and_interlacing():
+    """kp >= rank(B): the Ritz values are the singular values (the disk PSF
+    has Kronecker rank 6); below that they interlace."""
+    n = 20
+    P, cu, cv = wl.disk_psf(n, 8.0)
+    R, Rt = _ops(P, cu, cv, n)
+    exact = op.exact_kpsvd(P, cu, cv, n, 8)[0]
+    Y = wl.gaussian_block(n * n, 3, seed=4005)
+    out = kpsvd.block_egkb(R, Rt, Y, k=6, p=3)          # kp = 9 >= 6, breakdowns follow
+    assert np.abs(out["sigma"][:6] - exact[:6]).max() <= 1e-12 * exact[0]
+    assert len(out["breakdowns"]) > 0
+    P2, cu2, cv2 = wl.speckle_psf(n, seed=1005)
+    R2, Rt2 = _ops(P2, cu2, cv2, n)
+    ex2 = op.exact_kpsvd(P2, cu2, cv2, n, 6)[0]
+    out2 = kpsvd.block_egkb(R2, Rt2, Y, k=6, p=3)
+    assert np.all(out2["sigma"] <= ex2 * (1 + 1e-12))
