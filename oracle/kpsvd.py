@@ -164,7 +164,8 @@ def _gs_column(w, basis, passes=2):
     return w, h
 
 
-def block_egkb(apply_R, apply_Rt, Y, k, p, *, bd_rel=None, seed=0, dtype=np.float64):
+def block_egkb(apply_R, apply_Rt, Y, k, p, *, bd_rel=None, seed=0, dtype=np.float64,
+               force_breakdown=None):
     """Block Golub-Kahan bidiagonalization with b = Y.shape[1] start vectors
     (Golub, Luk & Overton 1981): the block analogue of Algorithm 1 with full
     reorthogonalization, enlarged to k_p = k + p columns rounded up to whole
@@ -186,6 +187,9 @@ def block_egkb(apply_R, apply_Rt, Y, k, p, *, bd_rel=None, seed=0, dtype=np.floa
     orthogonalized twice against its basis (stream 2(m+1) for column m of U,
     2(m+1)+1 for column m of V: for b = 1 the streams of Algorithm 1's s_{m+1},
     q_{m+1}). The start block's own factor is not part of C (as t_1).
+    force_breakdown: optional set of ("u"|"v", m) taking the breakdown branch at
+    exactly those columns (and nowhere else), to follow a run whose decisions
+    were taken in another precision.
     Returns dict(sigma, U, V, Ub, Vb, C, kp, breakdowns).
     """
     eps = np.finfo(dtype).eps / 2
@@ -208,7 +212,11 @@ def block_egkb(apply_R, apply_Rt, Y, k, p, *, bd_rel=None, seed=0, dtype=np.floa
             nr = _norm(w)
             Rown[:c, c] = h[basis.shape[1]:]
             m = col0 + c
-            if nr == 0.0 or (in_c and nr <= bd_rel * scale[0]):
+            if force_breakdown is not None:
+                broken = (side, m) in force_breakdown
+            else:
+                broken = nr == 0.0 or (in_c and nr <= bd_rel * scale[0])
+            if broken:
                 breakdowns.append((side, m))
                 g = philox.normals(N, seed, 2 * (m + 1) + (0 if side == "u" else 1)).astype(dtype)
                 g, _ = _gs_column(g, full)

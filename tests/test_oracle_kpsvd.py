@@ -241,3 +241,31 @@ def test_block_egkb_exact_for_low_rank_and_interlacing():
     ex2 = op.exact_kpsvd(P2, cu2, cv2, n, 6)[0]
     out2 = kpsvd.block_egkb(R2, Rt2, Y, k=6, p=3)
     assert np.all(out2["sigma"] <= ex2 * (1 + 1e-12))
+
+
+def test_block_egkb_forced_breakdown_keeps_the_relation():
+    """A breakdown forced at one column of each basis stores 0 on C's diagonal
+    there, restarts from the stated Philox stream and keeps both bases
+    orthonormal (B V = U C no longer holds: the forced columns' residuals, which
+    are not negligible here, are dropped)."""
+    n, b = 14, 3
+    P, cu, cv = wl.speckle_psf(n, seed=1006)
+    R, Rt = _ops(P, cu, cv, n)
+    Y = wl.gaussian_block(n * n, b, seed=4006)
+    force = {("v", 4), ("u", 7)}
+    out = kpsvd.block_egkb(R, Rt, Y, k=5, p=4, force_breakdown=force, seed=9)
+    U, V, C, kp = out["Ub"], out["Vb"], out["C"], out["kp"]
+    s1 = op.exact_kpsvd(P, cu, cv, n, 1)[0][0]
+    assert sorted(out["breakdowns"]) == sorted(force)
+    assert C[4, 4] == 0.0                      # column 4 of V: L_2^T diagonal
+    assert C[7, 4] == 0.0                      # column 7 of U: R_2 diagonal (block 1 of V)
+    assert np.abs(U.T @ U - np.eye(kp + b)).max() <= 1e-12
+    assert np.abs(V.T @ V - np.eye(kp)).max() <= 1e-12
+    # columns before the first forced one still satisfy the relation
+    assert np.linalg.norm(R(V[:, :3]) - U @ C[:, :3]) <= 1e-12 * s1
+    # the restart direction is the stream-2(m+1)+1 Philox vector made orthogonal
+    # to V[:, :4]: V[:, 4] is its normalized residual
+    from oracle import philox
+    g = philox.normals(n * n, 9, 2 * 5 + 1)
+    g = g - V[:, :4] @ (V[:, :4].T @ g)
+    assert np.allclose(V[:, 4], g / np.linalg.norm(g), atol=1e-12)
