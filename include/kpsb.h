@@ -81,10 +81,25 @@ typedef struct {
   kp_prec prec;         /* KP_F32 (paper's SP) or KP_F64                           */
   uint64_t seed;        /* Philox seed for the start vector (if y0 == NULL) and
                            for breakdown restart vectors                           */
-  const double* y0;     /* optional HOST start vector y, length n^2 (vec order)    */
+  const double* y0;     /* optional HOST start vector y, length n^2 (vec order);
+                           with block = b >= 1 the start block, n^2 x b
+                           column-major                                            */
   double bd_rel;        /* breakdown when t_j or alpha_j is 0 or <= bd_rel times the
                            largest entry of the bidiagonal so far; 0 selects
                            100 * unit roundoff of `prec`                           */
+  int32_t block;        /* 0: Algorithm 1 (one start vector). b >= 1: the block
+                           Golub-Kahan bidiagonalization with b start vectors
+                           (Golub, Luk & Overton 1981), the block analogue of
+                           Algorithm 1 with full reorthogonalization, run for
+                           ceil((k+p)/b) = nb blocks; needs (nb+1) b <= 64 and
+                           auto_k = 0 (reorth and literal_init are ignored).
+                           Without y0 column c of the start block is Philox
+                           stream 0 (c = 0) or 2^31 + c. A breakdown of column m
+                           of the left (right) basis is restarted from stream
+                           2(m+1) (2(m+1)+1) and reported with break_side 0 (1)
+                           and break_step m; diag.kp = nb b, diag.alpha/t are not
+                           written, basis_u holds n^2 x (nb+1) b and basis_v
+                           n^2 x nb b                                              */
 } kp_gkb_opts;
 
 /* Randomized SVD (paper, Algorithm 2) with orthonormalization after every

@@ -42,7 +42,8 @@ class kp_gkb_opts(C.Structure):
     _fields_ = [("k", C.c_int32), ("p", C.c_int32), ("k_min", C.c_int32),
                 ("auto_k", C.c_int32), ("tau", C.c_double), ("literal_init", C.c_int32),
                 ("reorth", C.c_int32), ("prec", C.c_int), ("seed", C.c_uint64),
-                ("y0", C.POINTER(C.c_double)), ("bd_rel", C.c_double)]
+                ("y0", C.POINTER(C.c_double)), ("bd_rel", C.c_double),
+                ("block", C.c_int32)]
 
 
 class kp_rsvd_opts(C.Structure):

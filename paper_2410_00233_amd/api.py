@@ -149,16 +149,21 @@ class Context:
 
     def kp_svd_gkb(self, blur: Blur, k, p, *, k_min=0, auto_k=False, tau=0.0,
                    literal_init=False, reorth=1, prec="f32", seed=0, y0=None, bd_rel=0.0,
-                   factor_prec="f64", k_cap=None, bases=False, stored=None):
+                   factor_prec="f64", k_cap=None, bases=False, stored=None, block=0):
         """stored=(n, R): the KP-SVD of a stored R (device tensor N x N, the
-        element type given by prec) instead of the blur's generated R."""
+        element type given by prec) instead of the blur's generated R.
+        block=b >= 1: block Golub-Kahan bidiagonalization with b start vectors
+        (y0 then an N x b array); breakdowns are reported as ("u" | "v", m)."""
         torch = _torch()
         n = blur.n if stored is None else stored[0]
         f = Factors(n, k_cap or k, factor_prec)
-        y0a = None if y0 is None else np.ascontiguousarray(y0, dtype=np.float64)
+        y0a = None
+        if y0 is not None:
+            y0a = np.asarray(y0, dtype=np.float64)
+            y0a = np.ascontiguousarray(y0a.T if y0a.ndim == 2 else y0a)   # columns contiguous
         o = L.kp_gkb_opts(k, p, k_min, int(auto_k), tau, int(literal_init), reorth, PREC[prec],
                           seed, None if y0a is None else y0a.ctypes.data_as(C.POINTER(C.c_double)),
-                          bd_rel)
+                          bd_rel, block)
         cap = k + p + 2
         alpha = np.zeros(cap)
         t = np.zeros(cap)
@@ -166,10 +171,15 @@ class Context:
         f.diag.alpha = alpha.ctypes.data_as(C.POINTER(C.c_double))
         f.diag.t = t.ctypes.data_as(C.POINTER(C.c_double))
         S = Q = None
+        if block >= 1:
+            nu_cols = (-(-(k + p) // block) + 1) * block
+            nv_cols = nu_cols - block
+        else:
+            nu_cols, nv_cols = k + p + 1, k + p
         if bases:
             dt = torch.float32 if prec == "f32" else torch.float64
-            S = torch.zeros((k + p + 1, n * n), dtype=dt, device="cuda")
-            Q = torch.zeros((k + p, n * n), dtype=dt, device="cuda")
+            S = torch.zeros((nu_cols, n * n), dtype=dt, device="cuda")
+            Q = torch.zeros((nv_cols, n * n), dtype=dt, device="cuda")
             f.diag.basis_u = S.data_ptr()
             f.diag.basis_v = Q.data_ptr()
         if stored is None:
@@ -182,21 +192,23 @@ class Context:
         kp = f.diag.kp
         f.alpha = alpha[:kp].copy()
         f.t = t[:kp + 1].copy()
-        f.breakdowns = [("s" if f.diag.break_side[i] == 0 else "q", f.diag.break_step[i])
+        names = ("u", "v") if block >= 1 else ("s", "q")
+        f.breakdowns = [(names[f.diag.break_side[i]], f.diag.break_step[i])
                         for i in range(min(f.diag.nbreak, 128))]
         f.ms = f.diag.ms_total
         if bases:
-            f.S = S[:kp + 1]
+            f.S = S[:nu_cols] if block >= 1 else S[:kp + 1]
             f.Q = Q[:kp]
         return f
 
     @staticmethod
     def gkb_opts(k, p, *, k_min=0, auto_k=False, tau=0.0, literal_init=False, reorth=1,
-                 prec="f32", seed=0, y0=None, bd_rel=0.0):
-        """kp_gkb_opts; a host start vector y0 must outlive the call using it."""
+                 prec="f32", seed=0, y0=None, bd_rel=0.0, block=0):
+        """kp_gkb_opts; a host start vector (block: n^2 x b column-major array)
+        y0 must outlive the call using it."""
         ptr = None if y0 is None else y0.ctypes.data_as(C.POINTER(C.c_double))
         return L.kp_gkb_opts(k, p, k_min, int(auto_k), tau, int(literal_init), reorth,
-                             PREC[prec], seed, ptr, bd_rel)
+                             PREC[prec], seed, ptr, bd_rel, block)
 
     @staticmethod
     def rsvd_opts(k, p, q, *, prec="f32", refine=False, seed=0, F=None):

@@ -725,6 +725,176 @@ kp_status egkb_impl(kp_ctx* c, const RmatOp<T>& op, const kp_gkb_opts* o, kp_fac
 }
 
 // ---------------------------------------------------------------------------
+// Block Golub-Kahan bidiagonalization (Golub, Luk & Overton 1981) with b start
+// vectors: the block analogue of Algorithm 1 with full reorthogonalization.
+// U_1 = orth(Y); for j = 1 .. nb: V_j L_j^T = B^T U_j - V_{j-1} R_{j-1}^T and
+// U_{j+1} R_j = B V_j - U_j L_j, so that B [V_1 .. V_nb] = [U_1 .. U_nb+1] C with
+// C block lower bidiagonal ((nb+1) b x nb b). Every new block is orthonormalized
+// column by column with two classical Gram-Schmidt passes against all earlier
+// vectors of its basis; the summed coefficients on the block's own earlier
+// columns and the column norms are the entries of L_j^T (resp. R_j). Each
+// column's norm is read back to take the breakdown decision of Algorithm 1
+// (0, or at most bd_rel times the largest norm so far in C); a broken-down
+// column stores 0 and is replaced by a Philox vector (stream 2(m+1) for column m
+// of U, 2(m+1)+1 for column m of V) orthogonalized twice against its basis. The
+// products with B and B^T are block products of b columns (the MFMA kernels),
+// which is what the block form buys over Algorithm 1's matrix-vector products.
+template <typename T>
+kp_status egkb_block_impl(kp_ctx* c, const RmatOp<T>& op, const kp_gkb_opts* o, kp_factors* f,
+                          hipStream_t s) {
+  Timer timer(s);
+  const int n = op.n;
+  const long N = (long)n * n;
+  const int b = o->block;
+  const int k = o->k;
+  const int nb = (o->k + o->p + b - 1) / b;
+  const int kp = nb * b;
+  const int rows = kp + b;
+  const double u = (sizeof(T) == 4) ? std::ldexp(1.0, -24) : std::ldexp(1.0, -53);
+  const double bd_rel = o->bd_rel > 0 ? o->bd_rel : 1e2 * u;
+
+  Scratch sc;
+  KP_TRY(get_scratch(c, &sc));
+  double* hcol = sc.h;
+  double* h2 = sc.h + 64;
+  T *U = nullptr, *V = nullptr;
+  KP_TRY(wsT(c, std::string("egkbS_") + tname<T>(), (size_t)N * rows, &U));
+  KP_TRY(wsT(c, std::string("egkbQ_") + tname<T>(), (size_t)N * kp, &V));
+
+  std::vector<double> C((size_t)rows * kp, 0.0);
+  std::vector<std::pair<int, int>> breaks;
+  double scale = 0.0;
+
+  // Column m of basis B0 (ld N) against its m predecessors, two CGS passes;
+  // returns the norm and the coefficients on the last `nown` predecessors.
+  auto gs_column = [&](T* B0, int m, int nown, double* own, double* nr) -> kp_status {
+    T* w = B0 + N * m;
+    if (m == 0) {
+      launch_norm2_partials<T>(w, N, sc.nrmp, s);
+    } else {
+      launch_multidot<T>(B0, N, m, w, N, sc.partials, s);
+      launch_reduce_partials(sc.partials, m, hcol, 0, s);
+      launch_project_out<T>(w, B0, N, m, hcol, N, nullptr, s);
+      launch_multidot<T>(B0, N, m, w, N, sc.partials, s);
+      launch_reduce_partials(sc.partials, m, h2, 0, s);
+      launch_project_out<T>(w, B0, N, m, h2, N, sc.nrmp, s);
+      launch_add_small(hcol, h2, m, s);
+    }
+    launch_reduce_partials(sc.nrmp, 1, sc.scal, 0, s);
+    KP_TRY(check_launch(c, "block_gs"));
+    KP_HIP(c, hipMemcpyAsync(c->pinned, sc.scal, sizeof(double), hipMemcpyDeviceToHost, s));
+    if (nown > 0)
+      KP_HIP(c, hipMemcpyAsync(c->pinned + 1, hcol + (m - nown), sizeof(double) * nown,
+                               hipMemcpyDeviceToHost, s));
+    KP_HIP(c, hipStreamSynchronize(s));
+    *nr = std::sqrt(c->pinned[0]);
+    for (int i = 0; i < nown; ++i) own[i] = c->pinned[1 + i];
+    return KP_OK;
+  };
+
+  // Orthonormalize column m (side 0 = U, 1 = V); *diag = stored norm.
+  auto new_column = [&](T* B0, int m, int nown, int side, bool in_c, double* own,
+                        double* diag) -> kp_status {
+    double nr = 0.0;
+    KP_TRY(gs_column(B0, m, nown, own, &nr));
+    if (!std::isfinite(nr)) return set_err(c, KP_E_NUMERIC, "non-finite block column norm");
+    T* w = B0 + N * m;
+    if (nr == 0.0 || (in_c && nr <= bd_rel * scale)) {
+      breaks.push_back({side, m});
+      launch_philox_normals<T>(w, N, o->seed, (uint32_t)(2 * (m + 1) + side), s);
+      cgs2<T>(sc, w, B0, N, m, N, s);
+      double g = 0.0;
+      KP_TRY(read_norm(c, sc, s, &g));
+      if (g > 0) launch_scale<T>(w, N, 1.0 / g, s);
+      *diag = 0.0;
+    } else {
+      launch_scale<T>(w, N, 1.0 / nr, s);
+      *diag = nr;
+      if (in_c) scale = std::max(scale, nr);
+    }
+    return check_launch(c, "block_column");
+  };
+
+  auto product = [&](int tr, const T* X, T* Y) -> kp_status {
+    return b == 1 ? op.gemv(c, tr, X, Y, nullptr, 0.0, s) : op.block(c, tr, X, Y, b, s);
+  };
+
+  // start block U_1 = orth(Y) (its own triangular factor is not part of C)
+  if (o->y0) {
+    KP_TRY(upload_block<T>(c, o->y0, N * b, U, s));
+  } else {
+    for (int col = 0; col < b; ++col)
+      launch_philox_normals<T>(U + N * col, N, o->seed, col == 0 ? 0u : 0x80000000u + col, s);
+  }
+  double own[64], d = 0.0;
+  for (int col = 0; col < b; ++col) KP_TRY(new_column(U, col, 0, 0, false, own, &d));
+
+  for (int j = 0; j < nb; ++j) {
+    const long jb = (long)j * b;
+    // V_{j+1} L^T = B^T U_{j+1} (minus the earlier V, through the Gram-Schmidt)
+    KP_TRY(product(1, U + N * jb, V + N * jb));
+    for (int col = 0; col < b; ++col) {
+      KP_TRY(new_column(V, (int)jb + col, col, 1, true, own, &d));
+      for (int r = 0; r < col; ++r) C[(jb + col) + (size_t)rows * (jb + r)] = own[r];
+      C[(jb + col) + (size_t)rows * (jb + col)] = d;
+    }
+    // U_{j+2} R = B V_{j+1} (minus the earlier U)
+    const long ub = jb + b;
+    KP_TRY(product(0, V + N * jb, U + N * ub));
+    for (int col = 0; col < b; ++col) {
+      KP_TRY(new_column(U, (int)ub + col, col, 0, true, own, &d));
+      for (int r = 0; r < col; ++r) C[(ub + r) + (size_t)rows * (jb + col)] = own[r];
+      C[(ub + col) + (size_t)rows * (jb + col)] = d;
+    }
+  }
+  KP_TRY(check_launch(c, "block egkb loop"));
+
+  double *dC, *Uc, *sig, *Vc;
+  int* sweeps;
+  KP_TRY(wsT(c, "smallA", 64 * 64, &dC));
+  KP_TRY(wsT(c, "smallU", 64 * 64, &Uc));
+  KP_TRY(wsT(c, "smallS", 64, &sig));
+  KP_TRY(wsT(c, "smallV", 64 * 64, &Vc));
+  KP_TRY(wsT(c, "sweeps", 4, &sweeps));
+  KP_HIP(c, hipMemcpyAsync(dC, C.data(), sizeof(double) * C.size(), hipMemcpyHostToDevice, s));
+  launch_jacobi_svd(dC, rows, kp, Uc, sig, Vc, sweeps, s);
+  KP_TRY(check_launch(c, "jacobi_svd"));
+
+  const int kout = std::min(k, f->k_cap);
+  double *Ud, *Vd;
+  KP_TRY(wsT(c, "Ud", (size_t)N * kout, &Ud));
+  KP_TRY(wsT(c, "Vd", (size_t)N * kout, &Vd));
+  launch_small_gemm<T, double>(U, N, rows, Uc, rows, kout, N, Ud, N, s);
+  launch_small_gemm<T, double>(V, N, kp, Vc, kp, kout, N, Vd, N, s);
+  KP_TRY(check_launch(c, "small_gemm"));
+  KP_TRY(write_factors(c, Ud, Vd, sig, n, kout, f, s));
+  KP_HIP(c, hipMemcpyAsync(c->pinned, sig, sizeof(double) * kout, hipMemcpyDeviceToHost, s));
+  if (f->diag && f->diag->basis_u)
+    KP_HIP(c, hipMemcpyAsync(f->diag->basis_u, U, sizeof(T) * N * rows, hipMemcpyDeviceToDevice, s));
+  if (f->diag && f->diag->basis_v)
+    KP_HIP(c, hipMemcpyAsync(f->diag->basis_v, V, sizeof(T) * N * kp, hipMemcpyDeviceToDevice, s));
+  KP_HIP(c, hipStreamSynchronize(s));
+  for (int i = 0; i < kout; ++i) f->sigma[i] = c->pinned[i];
+  f->k = kout;
+  if (kp_diag* dg = f->diag) {
+    dg->kp = kp;
+    dg->nbreak = (int)breaks.size();
+    for (int i = 0; i < (int)breaks.size() && i < 128; ++i) {
+      dg->break_side[i] = breaks[i].first;
+      dg->break_step[i] = breaks[i].second;
+    }
+    dg->ms_total = timer.stop();
+  }
+  return breaks.empty() ? KP_OK : KP_W_BREAKDOWN;
+}
+
+template <typename T>
+kp_status gkb_run(kp_ctx* c, const RmatOp<T>& op, const kp_gkb_opts* o, kp_factors* f,
+                  hipStream_t s) {
+  return o->block >= 1 ? egkb_block_impl<T>(c, op, o, f, s) : egkb_impl<T>(c, op, o, f, s);
+}
+
+// ---------------------------------------------------------------------------
 // RSVD (Algorithm 2): Y = orth(B F); q times Z = orth(B^T Y), Y = orth(B Z);
 // H^T = B^T Y = Q_h R_h (CGS2 QR), R_h^T = U_r S V_r^T (Jacobi), so
 // H = U_r S (Q_h V_r)^T: U_k = Y U_r[:, :k], V_k = Q_h V_r[:, :k].
@@ -1235,8 +1405,19 @@ kp_status check_gkb(kp_ctx* c, const kp_gkb_opts* o, kp_factors* f, int n) {
   if (o->k + o->p + 1 > N) return set_err(c, KP_E_INVAL, "k + p must be < n^2");
   if (o->reorth != 0 && o->reorth != 1) return set_err(c, KP_E_INVAL, "reorth must be 0 or 1");
   if (f->k_cap < 1) return set_err(c, KP_E_INVAL, "factors.k_cap must be >= 1");
+  if (o->block < 0) return set_err(c, KP_E_INVAL, "block must be >= 0");
+  long ny = N;
+  if (o->block >= 1) {
+    const long b = o->block;
+    const long nb = (o->k + o->p + b - 1) / b;
+    if ((nb + 1) * b > 64)
+      return set_err(c, KP_E_INVAL, "block GKB needs (ceil((k+p)/b) + 1) * b <= 64");
+    if ((nb + 1) * b > N) return set_err(c, KP_E_INVAL, "block GKB needs (nb + 1) * b <= n^2");
+    if (o->auto_k) return set_err(c, KP_E_INVAL, "auto_k is not supported with block >= 1");
+    ny = N * b;
+  }
   if (o->y0)
-    for (long e = 0; e < N; ++e)
+    for (long e = 0; e < ny; ++e)
       if (!std::isfinite(o->y0[e])) return set_err(c, KP_E_NUMERIC, "y0 has a non-finite entry");
   if (o->prec != KP_F32 && o->prec != KP_F64)
     return set_err(c, KP_E_INVAL, "EGKB precision must be KP_F32 or KP_F64");
@@ -1279,11 +1460,11 @@ kp_status kp_svd_gkb(kp_ctx* c, const kp_blur* b, const kp_gkb_opts* o, kp_facto
   if (o->prec == KP_F32) {
     RmatOp<float> op;
     KP_TRY(make_generated_op<float>(c, b, s, &op));
-    return egkb_impl<float>(c, op, o, f, s);
+    return gkb_run<float>(c, op, o, f, s);
   }
   RmatOp<double> op;
   KP_TRY(make_generated_op<double>(c, b, s, &op));
-  return egkb_impl<double>(c, op, o, f, s);
+  return gkb_run<double>(c, op, o, f, s);
 }
 
 kp_status kp_svd_rsvd(kp_ctx* c, const kp_blur* b, const kp_rsvd_opts* o, kp_factors* f,
@@ -1367,11 +1548,11 @@ kp_status kp_svd_gkb_stored(kp_ctx* c, int32_t n, const void* R, const kp_gkb_op
   if (o->prec == KP_F32) {
     RmatOp<float> op;
     KP_TRY(make_stored_op<float>(c, n, (const float*)R, &op));
-    return egkb_impl<float>(c, op, o, f, s);
+    return gkb_run<float>(c, op, o, f, s);
   }
   RmatOp<double> op;
   KP_TRY(make_stored_op<double>(c, n, (const double*)R, &op));
-  return egkb_impl<double>(c, op, o, f, s);
+  return gkb_run<double>(c, op, o, f, s);
 }
 
 kp_status kp_svd_rsvd_stored(kp_ctx* c, int32_t n, const void* R, const kp_rsvd_opts* o,
