@@ -289,6 +289,28 @@ def bench_serving(ctx, count, rate, sizes):
     }
 
 
+def nonzero_fractions(P, cu, cv, n):
+    """Fractions of the rows, columns and entries of R(A) that are nonzero for
+    the PSF rounded to FP32 (R[i+nj, r+nc] = P[cu+r-c, cv+i-j]; the offset d of
+    a row or column occurs n - |d| times). Every product still multiplies the
+    whole dense R(A): these numbers say how much of that work meets zeros."""
+    import numpy as np
+    P32 = np.asarray(P, dtype=np.float32) != 0
+    off = np.arange(-(n - 1), n)
+    w = (n - np.abs(off)).astype(np.float64)
+    sub = np.zeros((2 * n - 1, 2 * n - 1), dtype=bool)       # [e (u offset), d (v offset)]
+    uu = cu + off
+    vv = cv + off
+    ok_u = (uu >= 0) & (uu < P.shape[0])
+    ok_v = (vv >= 0) & (vv < P.shape[1])
+    sub[np.ix_(ok_u, ok_v)] = P32[np.ix_(uu[ok_u], vv[ok_v])]
+    N2 = float(n) ** 2
+    rows = float(w[sub.any(axis=0)].sum() / N2)
+    cols = float(w[sub.any(axis=1)].sum() / N2)
+    ents = float((w[:, None] * w[None, :])[sub].sum() / N2 ** 2)
+    return {"rows": round(rows, 5), "cols": round(cols, 5), "entries": round(ents, 6)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -305,6 +327,8 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=2.0,
                     help="offered Poisson arrival rate of the serving run (requests/s)")
     ap.add_argument("--serve-sizes", type=str, default="128,256,512,1024")
+    ap.add_argument("--gkb-block", type=int, default=20,
+                    help="block size b of the timed block Golub-Kahan run")
     ap.add_argument("--no-paper-pipeline", action="store_true",
                     help="skip the explicit-matrix run on the paper's n = 128 setting")
     args = ap.parse_args()
@@ -322,6 +346,7 @@ def main():
     n = args.n
     k, p_gkb, p_rsvd, q = 20, 20, 10, 2
     P, cu, cv = wl.gaussian_psf(n)
+    nz = nonzero_fractions(P, cu, cv, n)
     blur = api.Blur(P, cu, cv, n, on_device=True)
     ctx = api.Context(0)
     f_gkb = flops.egkb(n, k, p_gkb)
@@ -356,7 +381,23 @@ def main():
     ms_step = 1e3 * (t1 - t0) / args.steps
     value = (f_gkb + f_rsvd) / (ms_step * 1e-3) / 1e12
 
-    log(f"step {ms_step:.1f} ms ({value:.1f} TFLOP/s); BF16 + refinement RSVD")
+    log(f"step {ms_step:.1f} ms ({value:.1f} TFLOP/s); block GKB (b = {args.gkb_block})")
+    # the block form of Algorithm 1 on the same workload and k_p: its products
+    # with B and B^T are block products of b columns on the MFMA kernel
+    b_blk = args.gkb_block
+    nb_blk = -(-(k + p_gkb) // b_blk)
+    f_blk = flops.egkb(n, k, nb_blk * b_blk - k)
+    fblk = ctx.kp_svd_gkb(blur, k, p_gkb, prec="f32", seed=1, factor_prec="f64", block=b_blk)
+    tblk = []
+    for _ in range(args.steps):
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        fblk = ctx.kp_svd_gkb(blur, k, p_gkb, prec="f32", seed=1, factor_prec="f64", block=b_blk)
+        tblk.append(1e3 * (time.perf_counter() - ta))
+    blk_ms = float(np.median(tblk))
+    blk_diff = float(np.abs(fblk.sigma[:k] - fg.sigma[:k]).max() / fg.sigma[0])
+
+    log("BF16 + refinement RSVD")
     # the reduced-precision variant: RSVD with BF16 block products + refinement
     # (refine = 2: the refinement product from split FP16 MFMA products; the
     # refine = 1 variant with an FP32 product is timed beside it)
@@ -433,6 +474,7 @@ def main():
                         f"(k_p={k+p_gkb}, full reorth) + RSVD (p={p_rsvd}, q={q}), FP32",
             "n": n, "rank": k, "egkb_kp": k + p_gkb, "rsvd_p": p_rsvd, "rsvd_q": q,
             "flops_per_step": f_gkb + f_rsvd,
+            "rmat_nonzero_fractions_fp32": nz,
         },
         "components": {
             "egkb_ms": round(float(np.median(comp["egkb_ms"])), 3),
@@ -441,6 +483,13 @@ def main():
             "rsvd_tflops": round(f_rsvd / (np.median(comp["rsvd_ms"]) * 1e-3) / 1e12, 3),
             "gemv_kernel_avg_ms": round(avg_gv_ms, 4),
             "gemv_kernel_tflops": round(gemv_tflops, 3),
+            "egkb_block_b": b_blk,
+            "egkb_block_kp": nb_blk * b_blk,
+            "egkb_block_ms": round(blk_ms, 3),
+            "egkb_block_tflops": round(f_blk / (blk_ms * 1e-3) / 1e12, 3),
+            "egkb_block_speedup_vs_egkb": round(float(np.median(comp["egkb_ms"])) / blk_ms, 3),
+            "egkb_block_breakdowns": len(fblk.breakdowns),
+            "egkb_block_max_sigma_diff_vs_egkb_over_sigma1": blk_diff,
             "sigma_egkb_top3": [float(x) for x in fg.sigma[:3]],
             "sigma_rsvd_top3": [float(x) for x in fr.sigma[:3]],
             "rsvd_bf16_refine_ms": round(bf_ms, 3),

@@ -35,3 +35,25 @@ def test_configured_workload_counts():
     assert flops.egkb(512, 20, 20) == pytest.approx(1.100e13, rel=1e-3)
     assert flops.rmat_product(512, 30) == 2.0 * 512 ** 4 * 30
     assert flops.kp_apply(512, 20) == 4.0 * 20 * 512 ** 3
+
+
+def test_bench_nonzero_fractions_match_explicit_R():
+    """The bench's zero-fraction report equals a count over the explicit R(A)."""
+    import importlib.util
+    import os
+    import workloads as wl
+    from oracle import operator as op
+    spec = importlib.util.spec_from_file_location(
+        "bench_mod", os.path.join(os.path.dirname(__file__), "..", "bench.py"))
+    bench = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(bench)
+    n = 9
+    P, cu, cv = wl.random_psf(5, 7, 11, cu=1, cv=4)
+    P[:, 0] = 0.0                   # a zero column and row of the PSF
+    P[3, :] = 0.0
+    R = op.rearrange(op.blur_matrix(P, cu, cv, n), n, n, n, n) != 0
+    got = bench.nonzero_fractions(P, cu, cv, n)
+    N = n * n
+    assert abs(got["rows"] - R.any(axis=1).sum() / N) < 1e-5
+    assert abs(got["cols"] - R.any(axis=0).sum() / N) < 1e-5
+    assert abs(got["entries"] - R.sum() / N ** 2) < 1e-6
