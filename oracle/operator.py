@@ -74,6 +74,45 @@ def blur_matrix_reflexive(P, cu, cv, n):
     return A
 
 
+def _periodic_images(k, n):
+    """Positions that the periodic extension of a length-n signal maps onto
+    index k: k + nm, m = -2 .. 2 (enough for PSFs reaching at most 2n pixels
+    from their centre)."""
+    return [k + n * m for m in (-2, -1, 0, 1, 2)]
+
+
+def blur_matrix_periodic(P, cu, cv, n):
+    """Explicit periodic-BC blur matrix (n^2 x n^2): the image repeats with
+    period n in both directions (x[k + n] = x[k]), so
+
+        A[r + n*i, c + n*j] = sum over images c~ of c and j~ of j of
+                              P[cu + r - c~, cv + i - j~].
+    """
+    N = n * n
+    A = np.zeros((N, N), dtype=P.dtype)
+    r = np.arange(n)[:, None]
+    c = np.arange(n)[None, :]
+    cimg = _periodic_images(c, n)
+    for i in range(n):
+        for j in range(n):
+            blk = np.zeros((n, n), dtype=P.dtype)
+            for jj in _periodic_images(j, n):
+                for cc in cimg:
+                    blk += _psf_at(P, cu, cv, r - cc, np.full((1, 1), i - jj))
+            A[n * i:n * i + n, n * j:n * j + n] = blk
+    return A
+
+
+def _images(bc, k, n):
+    if bc == "zero":
+        return [k]
+    if bc == "reflexive":
+        return _reflect_images(k, n)
+    if bc == "periodic":
+        return _periodic_images(k, n)
+    raise ValueError(bc)
+
+
 def rearrange(A, m1, n1, m2, n2):
     """R(A) by the literal reordering of eq. "initial rearrange A".
 
@@ -88,24 +127,34 @@ def rearrange(A, m1, n1, m2, n2):
     return R
 
 
-def rmat_entries(P, cu, cv, n, rows, cols):
+def rmat_entries(P, cu, cv, n, rows, cols, bc="zero"):
     """Entries R[rows, cols] of R(A) from the PSF (outer product of indices).
 
-    rows index i + n*j, cols index r + n*c; R[i+n*j, r+n*c] = P[cu+r-c, cv+i-j].
+    rows index i + n*j, cols index r + n*c; R[i+n*j, r+n*c] = A[r+n*i, c+n*j],
+    which for zero boundary conditions is P[cu+r-c, cv+i-j] and otherwise the
+    sum of P[cu+r-c~, cv+i-j~] over the images c~ of c and j~ of j of the
+    extended image (bc = "reflexive" or "periodic", as in blur_matrix_*).
     """
     rows = np.asarray(rows)[:, None]
     cols = np.asarray(cols)[None, :]
     i, j = rows % n, rows // n
     r, c = cols % n, cols // n
-    return _psf_at(P, cu, cv, r - c, i - j)
+    if bc == "zero":
+        return _psf_at(P, cu, cv, r - c, i - j)
+    out = np.zeros(np.broadcast(rows, cols).shape, dtype=P.dtype)
+    for jj in _images(bc, j, n):
+        for cc in _images(bc, c, n):
+            out += _psf_at(P, cu, cv, r - cc, i - jj)
+    return out
 
 
-def rmat_dense_apply(P, cu, cv, n, X, transpose=False, row_chunk=256):
+def rmat_dense_apply(P, cu, cv, n, X, transpose=False, row_chunk=256, bc="zero"):
     """Y = R X (or R^T X) as a dense product over generated row blocks of R.
 
     The paper treats B = R(A) as an unstructured matrix (section 4.1); this is
     that product, with R's rows produced ``row_chunk`` at a time from the PSF
-    and multiplied with BLAS. X may be 1-D or 2-D.
+    (boundary conditions ``bc`` as in rmat_entries) and multiplied with BLAS.
+    X may be 1-D or 2-D.
     """
     N = n * n
     X = np.asarray(X)
@@ -117,12 +166,12 @@ def rmat_dense_apply(P, cu, cv, n, X, transpose=False, row_chunk=256):
         Y = np.zeros((N, Xm.shape[1]), dtype=dt)
         for r0 in range(0, N, row_chunk):
             rows = np.arange(r0, min(N, r0 + row_chunk))
-            Y[rows] = rmat_entries(P, cu, cv, n, rows, cols).astype(dt) @ Xm
+            Y[rows] = rmat_entries(P, cu, cv, n, rows, cols, bc).astype(dt) @ Xm
     else:
         Y = np.zeros((N, Xm.shape[1]), dtype=dt)
         for r0 in range(0, N, row_chunk):
             rows = np.arange(r0, min(N, r0 + row_chunk))
-            Y += rmat_entries(P, cu, cv, n, rows, cols).astype(dt).T @ Xm[rows]
+            Y += rmat_entries(P, cu, cv, n, rows, cols, bc).astype(dt).T @ Xm[rows]
     return Y[:, 0] if vec else Y
 
 

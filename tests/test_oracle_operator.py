@@ -231,3 +231,72 @@ def test_reflexive_blur_of_constant_image_is_constant():
     P /= P.sum()
     Ar = op.blur_matrix_reflexive(P, 2, 3, n)
     assert np.allclose(Ar @ np.ones(n * n), 1.0, atol=1e-13)
+
+
+@pytest.mark.parametrize("n,shape,centre,seed", [(6, (3, 5), None, 1), (5, (9, 9), None, 2),
+                                                 (5, (13, 11), None, 3), (3, (13, 13), (6, 6), 4),
+                                                 (4, (3, 9), (0, 8), 5)])
+def test_periodic_blur_matrix_is_circular_convolution(n, shape, centre, seed):
+    """Periodic boundary conditions: A is block circulant with circulant
+    blocks, i.e. a circular convolution with the PSF aliased onto the n x n
+    torus, computed here by the 2-D FFT. PSFs reaching up to 2n pixels from
+    their centre (the extent the image set covers) are included."""
+    rng = np.random.default_rng(seed)
+    P = rng.uniform(-1, 1, shape)
+    cu, cv = centre if centre else (shape[0] // 2, shape[1] // 2)
+    Ap = op.blur_matrix_periodic(P, cu, cv, n)
+    K = np.zeros((n, n))
+    for u in range(shape[0]):
+        for v in range(shape[1]):
+            K[(u - cu) % n, (v - cv) % n] += P[u, v]
+    X = rng.standard_normal((n, n))
+    Y = np.real(np.fft.ifft2(np.fft.fft2(K) * np.fft.fft2(X)))
+    vec = lambda M: M.flatten(order="F")
+    assert np.allclose(Ap @ vec(X), vec(Y), rtol=0, atol=1e-12)
+    if centre is None:                   # ndimage's kernel centre convention
+        import scipy.ndimage as nd
+        assert np.allclose(Ap @ vec(X), vec(nd.convolve(X, P, mode="grid-wrap")), rtol=0,
+                           atol=1e-12)
+
+
+@pytest.mark.parametrize("n,shape,seed", [(5, (9, 9), 6), (4, (9, 7), 7), (5, (13, 11), 8)])
+def test_reflexive_blur_matrix_with_psf_larger_than_the_image(n, shape, seed):
+    """PSFs larger than the image reflect more than once; the image set of
+    the oracle still reproduces scipy.ndimage.convolve(mode="reflect")."""
+    import scipy.ndimage as nd
+    rng = np.random.default_rng(seed)
+    P = rng.uniform(0, 1, shape)
+    Ar = op.blur_matrix_reflexive(P, shape[0] // 2, shape[1] // 2, n)
+    X = rng.standard_normal((n, n))
+    vec = lambda M: M.flatten(order="F")
+    assert np.allclose(Ar @ vec(X), vec(nd.convolve(X, P, mode="reflect")), rtol=0, atol=1e-12)
+
+
+@pytest.mark.parametrize("bc", ["zero", "reflexive", "periodic"])
+def test_rmat_entries_with_boundary_conditions_are_the_rearranged_matrix(bc):
+    """R(A) entries generated from the PSF equal the literal reorder of the
+    explicit blur matrix (integer PSF, so every sum is exact)."""
+    n = 7
+    rng = np.random.default_rng(9)
+    P = rng.integers(-5, 6, (9, 13)).astype(np.float64)
+    cu, cv = 2, 9
+    A = {"zero": op.blur_matrix, "reflexive": op.blur_matrix_reflexive,
+         "periodic": op.blur_matrix_periodic}[bc](P, cu, cv, n)
+    R = op.rearrange(A, n, n, n, n)
+    N = n * n
+    assert np.array_equal(op.rmat_entries(P, cu, cv, n, np.arange(N), np.arange(N), bc), R)
+    X = rng.standard_normal((N, 3))
+    assert np.allclose(op.rmat_dense_apply(P, cu, cv, n, X, bc=bc, row_chunk=10), R @ X,
+                       rtol=0, atol=1e-12)
+    assert np.allclose(op.rmat_dense_apply(P, cu, cv, n, X, transpose=True, bc=bc, row_chunk=10),
+                       R.T @ X, rtol=0, atol=1e-12)
+
+
+def test_periodic_blur_of_constant_image_is_constant():
+    """A unit-sum PSF of any extent up to 2n maps a constant image to itself
+    under periodic boundary conditions."""
+    n = 4
+    P = np.random.default_rng(10).uniform(0, 1, (15, 11))
+    P /= P.sum()
+    Ap = op.blur_matrix_periodic(P, 7, 3, n)
+    assert np.allclose(Ap @ np.ones(n * n), 1.0, atol=1e-13)
