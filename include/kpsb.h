@@ -56,17 +56,34 @@ typedef enum { KP_METHOD_GKB = 0, KP_METHOD_RSVD = 1 } kp_method;
 
 typedef struct kp_ctx kp_ctx;
 
+/* Boundary conditions of the blur: how the image is extended beyond its
+ * edges. Zero: by zeros (R[i+n*j, r+n*c] = P[cu+r-c, cv+i-j], section 2.1).
+ * Reflexive: by reflection about the edge of the last pixel, x[-1-k] = x[k],
+ * x[n+k] = x[n-1-k] (the paper's "Medium" example). Periodic: x[k+n] = x[k].
+ * Then A[r + n*i, c + n*j] = sum over the images c~ of c and j~ of j of
+ * P[cu + r - c~, cv + i - j~], with images k + 2n m and -1 - k + 2n m
+ * (m = -1, 0, 1) for reflexive and k + n m (m = -2 .. 2) for periodic: exact
+ * for PSFs that reach at most 2n pixels from their centre (required). */
+typedef enum { KP_BC_ZERO = 0, KP_BC_REFLEXIVE = 1, KP_BC_PERIODIC = 2 } kp_bc;
+
 /* The blur: PSF P (pu x pv, row-major FP64, P[u*pv + v] with u the vertical
- * offset) with centre (cu, cv), acting on n x n images with zero boundary
- * conditions. `psf` is HOST memory, or DEVICE memory when psf_on_device = 1.
- * Requirements: 2 <= n <= 2048, pu, pv >= 1, 0 <= cu < pu, 0 <= cv < pv,
- * every P entry finite (checked on the host, or on the device for a device
- * PSF; KP_E_NUMERIC otherwise). */
+ * offset) with centre (cu, cv), acting on n x n images with boundary
+ * conditions bc (kp_bc). `psf` is HOST memory, or DEVICE memory when
+ * psf_on_device = 1. Requirements: 2 <= n <= 2048, pu, pv >= 1,
+ * 0 <= cu < pu, 0 <= cv < pv, every P entry finite (checked on the host, or on
+ * the device for a device PSF; KP_E_NUMERIC otherwise); for bc != KP_BC_ZERO
+ * cu, pu-1-cu, cv, pv-1-cv <= 2n.
+ * R(A) is generated from the PSF: one term for zero and periodic boundary
+ * conditions (periodic: a grid summing the PSF at shifts of n), four for
+ * reflexive ones (the mirrored images become Toeplitz terms after reversing
+ * the block index j or c), so every product with a reflexive R(A) executes four
+ * generated products. */
 typedef struct {
   int32_t n;
   const double* psf;
   int32_t pu, pv, cu, cv;
   int32_t psf_on_device;
+  int32_t bc;           /* kp_bc */
 } kp_blur;
 
 /* Enlarged Golub-Kahan bidiagonalization (paper, Algorithm 1). */
@@ -334,13 +351,10 @@ kp_status kp_server_destroy(kp_server* srv);
  * streams the stored R from HBM.
  *
  * R[i + n*j, r + n*c] = A[r + n*i, c + n*j]. A and R must not overlap. */
-/* The explicit A of a blur (PSF as in kp_blur) with boundary conditions bc:
- * 0 = zero, 1 = reflexive (the image extended by reflection about the edge of
- * its last pixel, as in the paper's "Medium" example):
- * A[r + n*i, c + n*j] = sum over the reflected images c~ of c and j~ of j of
- * P[cu + r - c~, cv + i - j~] (for bc = 0 only c~ = c, j~ = j). */
-kp_status kp_blur_matrix(kp_ctx* ctx, const kp_blur* blur, int32_t bc, kp_prec prec, void* A,
-                         void* stream);
+/* The explicit A of a blur with its boundary conditions (blur->bc, kp_bc):
+ * A[r + n*i, c + n*j] = sum over the images c~ of c and j~ of j of
+ * P[cu + r - c~, cv + i - j~] (zero: only c~ = c, j~ = j). */
+kp_status kp_blur_matrix(kp_ctx* ctx, const kp_blur* blur, kp_prec prec, void* A, void* stream);
 kp_status kp_rmat_reorder(kp_ctx* ctx, int32_t n, kp_prec prec, const void* A, void* R,
                           void* stream);
 /* Y = R X or R^T X with the stored R (X, Y: DEVICE N x ncols column-major;

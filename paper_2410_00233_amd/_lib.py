@@ -17,6 +17,7 @@ KP_E_BUSY, KP_E_TIMEOUT = 5, 6
 KP_W_BREAKDOWN = 100
 KP_F64, KP_F32, KP_BF16, KP_F16 = 0, 1, 2, 3
 KP_METHOD_GKB, KP_METHOD_RSVD = 0, 1
+KP_BC_ZERO, KP_BC_REFLEXIVE, KP_BC_PERIODIC = 0, 1, 2
 
 STATUS_NAMES = {0: "KP_OK", 1: "KP_E_INVAL", 2: "KP_E_NOMEM", 3: "KP_E_DEVICE",
                 4: "KP_E_NUMERIC", 5: "KP_E_BUSY", 6: "KP_E_TIMEOUT", 100: "KP_W_BREAKDOWN"}
@@ -35,7 +36,7 @@ EXPORTED = ["kp_ctx_create", "kp_ctx_destroy", "kp_last_error", "kp_version",
 class kp_blur(C.Structure):
     _fields_ = [("n", C.c_int32), ("psf", C.POINTER(C.c_double)), ("pu", C.c_int32),
                 ("pv", C.c_int32), ("cu", C.c_int32), ("cv", C.c_int32),
-                ("psf_on_device", C.c_int32)]
+                ("psf_on_device", C.c_int32), ("bc", C.c_int32)]
 
 
 class kp_gkb_opts(C.Structure):
@@ -133,7 +134,7 @@ def load(path: str = LIB_PATH):
     lib.kp_server_destroy.argtypes = [vp]
     lib.kp_tune_report.argtypes = [C.c_char_p, C.c_size_t]
     lib.kp_rmat_reorder.argtypes = [vp, C.c_int32, C.c_int, vp, vp, vp]
-    lib.kp_blur_matrix.argtypes = [vp, C.POINTER(kp_blur), C.c_int32, C.c_int, vp, vp]
+    lib.kp_blur_matrix.argtypes = [vp, C.POINTER(kp_blur), C.c_int, vp, vp]
     lib.kp_rmat_apply_stored.argtypes = [vp, C.c_int32, C.c_int, vp, C.c_int, C.c_int32, vp, vp,
                                          vp]
     lib.kp_svd_gkb_stored.argtypes = [vp, C.c_int32, vp, C.POINTER(kp_gkb_opts),

@@ -36,15 +36,21 @@ def _ptr(t):
     return C.c_void_p(t.data_ptr())
 
 
+BC = {"zero": L.KP_BC_ZERO, "reflexive": L.KP_BC_REFLEXIVE, "periodic": L.KP_BC_PERIODIC}
+
+
 class Blur:
-    """PSF P (pu x pv, u vertical) with centre (cu, cv) acting on n x n images.
+    """PSF P (pu x pv, u vertical) with centre (cu, cv) acting on n x n images
+    with boundary conditions bc ("zero", "reflexive" or "periodic").
 
     P is a NumPy array (host) or, with on_device=True, copied once into a device
     tensor so that calls read it from HBM."""
 
-    def __init__(self, P, cu, cv, n, on_device=False):
+    def __init__(self, P, cu, cv, n, on_device=False, bc="zero"):
         self.P = np.ascontiguousarray(P, dtype=np.float64)
         self.cu, self.cv, self.n = int(cu), int(cv), int(n)
+        self.bc = bc
+        self.on_device = bool(on_device)
         if on_device:
             torch = _torch()
             self.Pd = torch.tensor(self.P, dtype=torch.float64, device="cuda")
@@ -52,7 +58,16 @@ class Blur:
         else:
             ptr = self.P.ctypes.data_as(C.POINTER(C.c_double))
         self.s = L.kp_blur(self.n, ptr, self.P.shape[0], self.P.shape[1], self.cu, self.cv,
-                           int(on_device))
+                           int(on_device), BC[bc])
+
+    def with_bc(self, bc):
+        """The same PSF (sharing its memory) with other boundary conditions."""
+        other = Blur.__new__(Blur)
+        other.__dict__.update(self.__dict__)
+        other.bc = bc
+        other.s = L.kp_blur(self.s.n, self.s.psf, self.s.pu, self.s.pv, self.s.cu, self.s.cv,
+                            self.s.psf_on_device, BC[bc])
+        return other
 
 
 class Factors:
@@ -260,15 +275,18 @@ class Context:
             f.Y = Y
         return f
 
-    def kp_blur_matrix(self, blur: Blur, bc="zero", prec="f64", A=None):
-        """Explicit blur matrix (device N x N) with zero or reflexive BC."""
+    def kp_blur_matrix(self, blur: Blur, bc=None, prec="f64", A=None):
+        """Explicit blur matrix (device N x N) with the blur's boundary
+        conditions (or bc, if given)."""
         torch = _torch()
+        if bc is not None and bc != blur.bc:
+            blur = blur.with_bc(bc)
         N = blur.n * blur.n
         if A is None:
             A = torch.empty((N, N), dtype=torch.float64 if prec == "f64" else torch.float32,
                             device="cuda")
-        self._check(self.lib.kp_blur_matrix(self.h, C.byref(blur.s), 1 if bc == "reflexive" else 0,
-                                            PREC[prec], _ptr(A), _stream()))
+        self._check(self.lib.kp_blur_matrix(self.h, C.byref(blur.s), PREC[prec], _ptr(A),
+                                            _stream()))
         return A
 
     def kp_rmat_reorder(self, n, A, R=None):

@@ -113,6 +113,15 @@ kp_status validate_blur(kp_ctx* c, const kp_blur* b) {
   if ((long)b->pu * b->pv > (1L << 26)) return set_err(c, KP_E_INVAL, "psf too large");
   if (b->psf_on_device != 0 && b->psf_on_device != 1)
     return set_err(c, KP_E_INVAL, "psf_on_device must be 0 or 1");
+  if (b->bc != KP_BC_ZERO && b->bc != KP_BC_REFLEXIVE && b->bc != KP_BC_PERIODIC)
+    return set_err(c, KP_E_INVAL, "bc must be KP_BC_ZERO, KP_BC_REFLEXIVE or KP_BC_PERIODIC");
+  if (b->bc != KP_BC_ZERO) {
+    const long reach = 2L * b->n;
+    if (b->cu > reach || b->pu - 1 - b->cu > reach || b->cv > reach || b->pv - 1 - b->cv > reach)
+      return set_err(c, KP_E_INVAL,
+                     "with reflexive or periodic boundary conditions the PSF may reach at most "
+                     "2n pixels from its centre");
+  }
   if (!b->psf_on_device)
     for (long e = 0; e < (long)b->pu * b->pv; ++e)
       if (!std::isfinite(b->psf[e])) return set_err(c, KP_E_NUMERIC, "psf has a non-finite entry");
@@ -125,11 +134,75 @@ template <> const char* tname<double>() { return "f64"; }
 template <> const char* tname<__hip_bfloat16>() { return "bf16"; }
 template <> const char* tname<__half>() { return "f16"; }
 
+// Terms of R(A) for the boundary conditions of a blur (every term is a
+// generated operator over its own offset grid). Zero: R = R(G). Periodic: the
+// images j + n m of the extended image only shift the offsets i - j (and
+// r - c) by multiples of n, so R = R(G_per) is one term whose grid sums the
+// PSF at those shifts. Reflexive: the images j + 2n m keep the Toeplitz form
+// (even shifts 2n m), while the mirrored images -1 - j + 2n m depend on i + j;
+// reversing the block index, j -> n-1-j, turns them into offsets i - j shifted
+// by n - 2n m (odd shifts). With J the reversal of the block index of a
+// length-n^2 vector (a + n b -> a + n (n-1-b)),
+//   R = R(G_ee) + R(G_eo) J + J R(G_oe) + J R(G_oo) J,
+// the first letter naming the shifts of the i - j offsets, the second those of
+// the r - c offsets; R^T = sum_t J^{fu} R(G_t)^T J^{fv}. The image sets are
+// m = -1..1 (reflexive) and m = -2..2 (periodic): exact for PSFs that reach at
+// most 2n pixels from their centre.
+struct RmatTerms {
+  int nterm = 1;
+  GridShifts sh[4];
+  int fv[4] = {0, 0, 0, 0};   // term t reverses the row blocks j of R
+  int fu[4] = {0, 0, 0, 0};   // term t reverses the column blocks c of R
+  int nsum_max() const {
+    int m = 1;
+    for (int t = 0; t < nterm; ++t) m = std::max(m, sh[t].nv * sh[t].nu);
+    return m;
+  }
+};
+
+RmatTerms make_terms(int bc, int n) {
+  RmatTerms r;
+  if (bc == KP_BC_PERIODIC) {
+    GridShifts g;
+    g.nv = g.nu = 5;
+    for (int m = -2; m <= 2; ++m) g.sv[m + 2] = g.su[m + 2] = -n * m;
+    r.sh[0] = g;
+  } else if (bc == KP_BC_REFLEXIVE) {
+    int even[3], odd[3];
+    for (int m = -1; m <= 1; ++m) {
+      even[m + 1] = -2 * n * m;
+      odd[m + 1] = n - 2 * n * m;
+    }
+    r.nterm = 4;
+    for (int t = 0; t < 4; ++t) {
+      r.fv[t] = t >> 1;
+      r.fu[t] = t & 1;
+      GridShifts& g = r.sh[t];
+      g.nv = g.nu = 3;
+      for (int x = 0; x < 3; ++x) {
+        g.sv[x] = r.fv[t] ? odd[x] : even[x];
+        g.su[x] = r.fu[t] ? odd[x] : even[x];
+      }
+    }
+  }
+  return r;
+}
+
 template <typename T>
 struct Grids {
-  T* G = nullptr;    // grid of R
-  T* Gt = nullptr;   // grid of R^T
+  T* G = nullptr;    // grid of R (term 0)
+  T* Gt = nullptr;   // grid of R^T (term 0)
   int ldg = 0;
+  RmatTerms terms;
+  T* Gs[4] = {nullptr, nullptr, nullptr, nullptr};    // grid of term t
+  T* Gts[4] = {nullptr, nullptr, nullptr, nullptr};   // its transpose
+  Grids term(int t) const {
+    Grids g;
+    g.G = g.Gs[0] = Gs[t];
+    g.Gt = g.Gts[0] = Gts[t];
+    g.ldg = ldg;
+    return g;
+  }
 };
 
 // Device copy of the PSF: uploaded from the host, or (device PSF) used in place
@@ -158,12 +231,47 @@ kp_status build_grids(kp_ctx* c, const kp_blur* b, const double* dpsf, hipStream
                       Grids<T>* g) {
   const int n = b->n;
   g->ldg = grid_ld(n);
+  g->terms = make_terms(b->bc, n);
   const size_t cnt = (size_t)(2 * n - 1) * g->ldg;
-  KP_TRY(wsT(c, std::string("G_") + tname<T>(), cnt, &g->G));
-  KP_TRY(wsT(c, std::string("Gt_") + tname<T>(), cnt, &g->Gt));
-  launch_build_grid<T>(dpsf, b->pu, b->pv, b->cu, b->cv, n, 0, g->G, g->ldg, s);
-  launch_build_grid<T>(dpsf, b->pu, b->pv, b->cu, b->cv, n, 1, g->Gt, g->ldg, s);
+  for (int t = 0; t < g->terms.nterm; ++t) {
+    const std::string sfx = std::string(tname<T>()) + (t ? "_" + std::to_string(t) : "");
+    KP_TRY(wsT(c, "G_" + sfx, cnt, &g->Gs[t]));
+    KP_TRY(wsT(c, "Gt_" + sfx, cnt, &g->Gts[t]));
+    launch_build_grid<T>(dpsf, b->pu, b->pv, b->cu, b->cv, n, 0, g->terms.sh[t], g->Gs[t],
+                         g->ldg, s);
+    launch_build_grid<T>(dpsf, b->pu, b->pv, b->cu, b->cv, n, 1, g->terms.sh[t], g->Gts[t],
+                         g->ldg, s);
+  }
+  g->G = g->Gs[0];
+  g->Gt = g->Gts[0];
   return check_launch(c, "build_grid");
+}
+
+// Y = sum over the terms of J^{out} op(R_t) J^{in} X (see RmatTerms): prod(t, in,
+// out, first) computes one term's product into out (first: the term written
+// straight into Y, which alone carries any extra operand of the product).
+// One term: prod(0, X, Y, true). Four terms: X reversed once into a
+// workspace, the three other terms into workspaces, then one combining pass.
+template <typename B, typename F>
+kp_status multi_term(kp_ctx* c, const RmatTerms& tm, int n, int tr, const B* X, B* Y,
+                     int ncols, hipStream_t s, F prod) {
+  if (tm.nterm == 1) return prod(0, X, Y, true);
+  const long N = (long)n * n;
+  const size_t cnt = (size_t)N * ncols;
+  B *Xf = nullptr, *T1 = nullptr, *T2 = nullptr, *T3 = nullptr;
+  KP_TRY(wsT(c, std::string("terms_x_") + tname<B>(), cnt, &Xf));
+  KP_TRY(wsT(c, std::string("terms_1_") + tname<B>(), cnt, &T1));
+  KP_TRY(wsT(c, std::string("terms_2_") + tname<B>(), cnt, &T2));
+  KP_TRY(wsT(c, std::string("terms_3_") + tname<B>(), cnt, &T3));
+  launch_flip_blocks<B>(X, Xf, n, N, ncols, s);
+  for (int t = 0; t < tm.nterm; ++t) {
+    const int fo = tr ? tm.fu[t] : tm.fv[t];
+    const int fi = tr ? tm.fv[t] : tm.fu[t];
+    B* dst = !fo ? (!fi ? Y : T1) : (!fi ? T2 : T3);
+    KP_TRY(prod(t, fi ? Xf : X, dst, dst == Y));
+  }
+  launch_combine_terms<B>(Y, T1, T2, T3, n, N, ncols, s);
+  return check_launch(c, "combine_terms");
 }
 
 template <typename T>
@@ -228,10 +336,11 @@ kp_status choose_block_plan(kp_ctx* c, const Grids<T>& g, int n, const T* X, T* 
   return KP_OK;
 }
 
-// Y = R X (or R^T X) for any number of columns (groups of 32 per launch).
+// Y = R X (or R^T X) for any number of columns (groups of 32 per launch), one
+// term.
 template <typename T>
-kp_status block_product(kp_ctx* c, const Grids<T>& g, int n, int transpose, const T* X,
-                        T* Y, int ncols, hipStream_t s) {
+kp_status block_product1(kp_ctx* c, const Grids<T>& g, int n, int transpose, const T* X,
+                         T* Y, int ncols, hipStream_t s) {
   BlockPlan bp;
   KP_TRY(choose_block_plan<T>(c, g, n, X, Y, std::min(ncols, 32), s, &bp));
   const long N = (long)n * n;
@@ -266,8 +375,8 @@ kp_status choose_block16_plan(kp_ctx* c, const Grids<H>& g, int n, const H* X16,
 // Y = R X with 16-bit inputs (H = __hip_bfloat16 or __half) and FP32 output; X is
 // rounded to H into a workspace copy first.
 template <typename H>
-kp_status block_product16(kp_ctx* c, const Grids<H>& g, int n, int transpose, const float* X,
-                          float* Y, int ncols, hipStream_t s) {
+kp_status block_product16_1(kp_ctx* c, const Grids<H>& g, int n, int transpose, const float* X,
+                            float* Y, int ncols, hipStream_t s) {
   const long N = (long)n * n;
   const long ld16 = x16_column_len(n);
   H* X16 = nullptr;
@@ -297,6 +406,7 @@ kp_status split16_product(kp_ctx* c, const kp_blur* b, const double* dpsf, int n
   const long N = (long)n * n;
   const int ldg = grid_ld(n);
   const size_t gcount = (size_t)(2 * n - 1) * ldg;
+  const RmatTerms tm = make_terms(b->bc, n);
   double* scal = nullptr;
   __half *Ghi = nullptr, *Glo = nullptr, *Xhi = nullptr, *Xlo = nullptr;
   KP_TRY(wsT(c, "split_scal", 2, &scal));
@@ -305,23 +415,27 @@ kp_status split16_product(kp_ctx* c, const kp_blur* b, const double* dpsf, int n
   const long ld16 = x16_column_len(n);
   KP_TRY(wsT(c, "x_split_hi", (size_t)ld16 * ncols, &Xhi));
   KP_TRY(wsT(c, "x_split_lo", (size_t)ld16 * ncols, &Xlo));
-  launch_psf_split_scale(dpsf, (long)b->pu * b->pv, scal, s);
-  launch_build_grid_split(dpsf, b->pu, b->pv, b->cu, b->cv, n, 0, scal, 0, Ghi, ldg, s);
-  launch_build_grid_split(dpsf, b->pu, b->pv, b->cu, b->cv, n, 0, scal, 1, Glo, ldg, s);
-  launch_to16_split(V, N, n, ncols, Xhi, Xlo, ld16, s);
-  for (int c0 = 0; c0 < ncols; c0 += 32) {
-    const int nc = ncols - c0 < 32 ? ncols - c0 : 32;
-    float* Wc = W + N * c0;
-    launch_rmat_block16<__half>(bp, Ghi, ldg, n, Xhi + ld16 * c0, ld16, Wc, N, nc, s, scal + 1, 0);
-    launch_rmat_block16<__half>(bp, Ghi, ldg, n, Xlo + ld16 * c0, ld16, Wc, N, nc, s, scal + 1, 1);
-    launch_rmat_block16<__half>(bp, Glo, ldg, n, Xhi + ld16 * c0, ld16, Wc, N, nc, s, scal + 1, 1);
-  }
-  return check_launch(c, "split16_product");
+  launch_psf_split_scale(dpsf, (long)b->pu * b->pv, tm.nsum_max(), scal, s);
+  // the terms run one after another on the stream, so one hi/lo grid pair serves all
+  return multi_term<float>(c, tm, n, 0, V, W, ncols, s,
+                           [&](int t, const float* in, float* out, bool) -> kp_status {
+    launch_build_grid_split(dpsf, b->pu, b->pv, b->cu, b->cv, n, 0, tm.sh[t], scal, 0, Ghi, ldg, s);
+    launch_build_grid_split(dpsf, b->pu, b->pv, b->cu, b->cv, n, 0, tm.sh[t], scal, 1, Glo, ldg, s);
+    launch_to16_split(in, N, n, ncols, Xhi, Xlo, ld16, s);
+    for (int c0 = 0; c0 < ncols; c0 += 32) {
+      const int nc = ncols - c0 < 32 ? ncols - c0 : 32;
+      float* Wc = out + N * c0;
+      launch_rmat_block16<__half>(bp, Ghi, ldg, n, Xhi + ld16 * c0, ld16, Wc, N, nc, s, scal + 1, 0);
+      launch_rmat_block16<__half>(bp, Ghi, ldg, n, Xlo + ld16 * c0, ld16, Wc, N, nc, s, scal + 1, 1);
+      launch_rmat_block16<__half>(bp, Glo, ldg, n, Xhi + ld16 * c0, ld16, Wc, N, nc, s, scal + 1, 1);
+    }
+    return check_launch(c, "split16_product");
+  });
 }
 
 template <typename T>
-kp_status gemv_product(kp_ctx* c, const Grids<T>& g, int n, int transpose, const T* x, T* y,
-                       const T* z, double coef, hipStream_t s) {
+kp_status gemv_product1(kp_ctx* c, const Grids<T>& g, int n, int transpose, const T* x, T* y,
+                        const T* z, double coef, hipStream_t s) {
   const double NN = (double)n * n;
   if constexpr (std::is_same<T, float>::value) {
     float* xt = nullptr;
@@ -338,6 +452,36 @@ kp_status gemv_product(kp_ctx* c, const Grids<T>& g, int n, int transpose, const
     launch_rmat_gemv<T>(gp, transpose ? g.Gt : g.G, g.ldg, n, x, y, z, coef, s);
   }
   return check_launch(c, "rmat_gemv");
+}
+
+// Products over all terms of R (boundary conditions; see RmatTerms).
+template <typename T>
+kp_status block_product(kp_ctx* c, const Grids<T>& g, int n, int tr, const T* X, T* Y,
+                        int ncols, hipStream_t s) {
+  return multi_term<T>(c, g.terms, n, tr, X, Y, ncols, s,
+                       [&](int t, const T* in, T* out, bool) -> kp_status {
+    return block_product1<T>(c, g.term(t), n, tr, in, out, ncols, s);
+  });
+}
+
+template <typename H>
+kp_status block_product16(kp_ctx* c, const Grids<H>& g, int n, int tr, const float* X,
+                          float* Y, int ncols, hipStream_t s) {
+  return multi_term<float>(c, g.terms, n, tr, X, Y, ncols, s,
+                           [&](int t, const float* in, float* out, bool) -> kp_status {
+    return block_product16_1<H>(c, g.term(t), n, tr, in, out, ncols, s);
+  });
+}
+
+// y = R x - coef z (or R^T x - coef z; z may be null).
+template <typename T>
+kp_status gemv_product(kp_ctx* c, const Grids<T>& g, int n, int tr, const T* x, T* y,
+                       const T* z, double coef, hipStream_t s) {
+  return multi_term<T>(c, g.terms, n, tr, x, y, 1, s,
+                       [&](int t, const T* in, T* out, bool first) -> kp_status {
+    return gemv_product1<T>(c, g.term(t), n, tr, in, out, first ? z : nullptr,
+                            first ? coef : 0.0, s);
+  });
 }
 
 // Shared scratch of the vector kernels.
@@ -1484,12 +1628,11 @@ kp_status kp_svd_rsvd(kp_ctx* c, const kp_blur* b, const kp_rsvd_opts* o, kp_fac
   return rsvd_impl<float>(c, op, o, f, s);
 }
 
-kp_status kp_blur_matrix(kp_ctx* c, const kp_blur* b, int32_t bc, kp_prec prec, void* A,
-                         void* stream) {
+kp_status kp_blur_matrix(kp_ctx* c, const kp_blur* b, kp_prec prec, void* A, void* stream) {
   if (!c) return KP_E_INVAL;
   KP_TRY(validate_blur(c, b));
   KP_TRY(check_stored(c, b->n, A, prec));
-  if (bc != 0 && bc != 1) return set_err(c, KP_E_INVAL, "bc must be 0 (zero) or 1 (reflexive)");
+  const int bc = b->bc;
   KP_HIP(c, hipSetDevice(c->device));
   hipStream_t s = (hipStream_t)stream;
   double* dpsf = nullptr;

@@ -23,9 +23,27 @@ constexpr int kRedThreads = 256;
 //   G[a][b] = P[cu + (b - (n-1)), cv + (a - (n-1))],  a, b in [0, 2n-1),
 // so that R[i + n*j, r + n*c] = G[i - j + n - 1][r - c + n - 1]. The grid of
 // R(A)^T is G^T (the blur with PSF P^T and swapped centre).
+//
+// Boundary conditions other than zero add the PSF at shifted offsets: the grid
+// of a term is G[a][b] = sum over s1 in sv, s2 in su of
+// P[cu + (b - (n-1)) + s2, cv + (a - (n-1)) + s1] (periodic: shifts n m,
+// m = -2..2, in both dimensions; reflexive: the even shifts 2n m or the odd
+// shifts n - 2n m, m = -1..1, per dimension, see RmatTerms in the driver).
+struct GridShifts {
+  int nv = 1, nu = 1;
+  int sv[5] = {0, 0, 0, 0, 0};
+  int su[5] = {0, 0, 0, 0, 0};
+};
 template <typename T>
 void launch_build_grid(const double* psf, int pu, int pv, int cu, int cv, int n,
-                       int transpose, T* G, int ldg, hipStream_t s);
+                       int transpose, const GridShifts& sh, T* G, int ldg, hipStream_t s);
+// out = in with the block index b of each length-n^2 column reversed
+// (entry a + n b <- a + n (n-1-b)); Y = (Y + T1) + flip(T2 + T3) entrywise.
+template <typename T>
+void launch_flip_blocks(const T* in, T* out, int n, long ld, int ncols, hipStream_t s);
+template <typename T>
+void launch_combine_terms(T* Y, const T* T1, const T* T2, const T* T3, int n, long ld, int ncols,
+                          hipStream_t s);
 
 // ---- generated-tile products (rmat_block.hip / rmat_gemv.hip) --------------
 struct BlockPlan {
@@ -64,13 +82,16 @@ void launch_rmat_block16(const BlockPlan& plan, const H* G16, int ldg, int n, co
 constexpr int kSplitXExp = 11;
 void launch_to16_split(const float* in, long ldx, int n, int ncols, __half* hi, __half* lo,
                        long ldo, hipStream_t s);
-// scal[0] = 2^e with e the largest integer such that max|P| * 2^e <= 1024;
-// scal[1] = 1 / (scal[0] * 2^kSplitXExp). Device only, no host sync.
-void launch_psf_split_scale(const double* psf, long count, double* scal, hipStream_t s);
-// FP16 grid of the scaled PSF: part 0 = fp16(P s), part 1 = fp16(P s - part 0).
+// scal[0] = 2^e with e the largest integer such that m * 2^e <= 1024, where m
+// bounds every grid entry (max|P| when nsum = 1; min(nsum max|P|, sum|P|) for
+// grids summing up to nsum PSF entries); scal[1] = 1 / (scal[0] * 2^kSplitXExp).
+// Device only, no host sync.
+void launch_psf_split_scale(const double* psf, long count, int nsum, double* scal,
+                            hipStream_t s);
+// FP16 grid of the scaled PSF: part 0 = fp16(G s), part 1 = fp16(G s - part 0).
 void launch_build_grid_split(const double* psf, int pu, int pv, int cu, int cv, int n,
-                             int transpose, const double* scal, int part, __half* G, int ldg,
-                             hipStream_t s);
+                             int transpose, const GridShifts& sh, const double* scal, int part,
+                             __half* G, int ldg, hipStream_t s);
 long x16_column_len(int n);
 template <typename H>
 void launch_to16_shifted(const float* in, long ldx, int n, int ncols, H* out, long ldo,

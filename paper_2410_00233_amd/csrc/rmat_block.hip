@@ -24,86 +24,75 @@
 namespace kpsb {
 
 // ---------------------------------------------------------------------------
+// Offset grid of one term: G[a][b] = sum over s1 in sh.sv, s2 in sh.su of
+// P[cu + (b - (n-1)) + s2, cv + (a - (n-1)) + s1] (0 outside P), summed in FP64
+// in the order of the shift lists and then rounded to T. The transposed grid
+// swaps a and b. Zero boundary conditions: one shift 0 in each dimension.
+__device__ __forceinline__ double grid_value(const double* __restrict__ psf, int pu, int pv,
+                                             int cu, int cv, int n, int a, int b,
+                                             const GridShifts& sh) {
+  double v = 0.0;
+  for (int x = 0; x < sh.nv; ++x) {
+    const int w = cv + a - (n - 1) + sh.sv[x];
+    if (w < 0 || w >= pv) continue;
+    for (int y = 0; y < sh.nu; ++y) {
+      const int u = cu + b - (n - 1) + sh.su[y];
+      if (u >= 0 && u < pu) v += psf[(long)u * pv + w];
+    }
+  }
+  return v;
+}
+
+template <typename T>
+__device__ __forceinline__ T from_double(double v) { return (T)v; }
+template <>
+__device__ __forceinline__ __hip_bfloat16 from_double<__hip_bfloat16>(double v) {
+  return __float2bfloat16((float)v);
+}
+template <>
+__device__ __forceinline__ __half from_double<__half>(double v) { return __float2half((float)v); }
+
 template <typename T>
 __global__ void build_grid_kernel(const double* __restrict__ psf, int pu, int pv, int cu,
-                                  int cv, int n, int transpose, T* __restrict__ G, int ldg) {
+                                  int cv, int n, int transpose, GridShifts sh,
+                                  T* __restrict__ G, int ldg) {
   const int g2 = 2 * n - 1;
   const long total = (long)g2 * ldg;
   for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total;
        e += (long)gridDim.x * blockDim.x) {
-    int a = (int)(e / ldg);
-    int b = (int)(e - (long)a * ldg);
+    const int a = (int)(e / ldg);
+    const int b = (int)(e - (long)a * ldg);
     double v = 0.0;
-    if (b < g2) {
-      // G[a][b] = P[cu + b - (n-1), cv + a - (n-1)]; the transposed grid swaps a, b.
-      int aa = transpose ? b : a;
-      int bb = transpose ? a : b;
-      int u = cu + bb - (n - 1);
-      int w = cv + aa - (n - 1);
-      if (u >= 0 && u < pu && w >= 0 && w < pv) v = psf[(long)u * pv + w];
-    }
-    G[e] = (T)v;
+    if (b < g2) v = transpose ? grid_value(psf, pu, pv, cu, cv, n, b, a, sh)
+                              : grid_value(psf, pu, pv, cu, cv, n, a, b, sh);
+    G[e] = from_double<T>(v);
   }
 }
 
-template <>
-__global__ void build_grid_kernel<__hip_bfloat16>(const double* __restrict__ psf, int pu,
-                                                  int pv, int cu, int cv, int n, int transpose,
-                                                  __hip_bfloat16* __restrict__ G, int ldg) {
-  const int g2 = 2 * n - 1;
-  const long total = (long)g2 * ldg;
-  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total;
-       e += (long)gridDim.x * blockDim.x) {
-    int a = (int)(e / ldg);
-    int b = (int)(e - (long)a * ldg);
-    double v = 0.0;
-    if (b < g2) {
-      int aa = transpose ? b : a;
-      int bb = transpose ? a : b;
-      int u = cu + bb - (n - 1);
-      int w = cv + aa - (n - 1);
-      if (u >= 0 && u < pu && w >= 0 && w < pv) v = psf[(long)u * pv + w];
-    }
-    G[e] = __float2bfloat16((float)v);
-  }
-}
-
-template <>
-__global__ void build_grid_kernel<__half>(const double* __restrict__ psf, int pu, int pv,
-                                          int cu, int cv, int n, int transpose,
-                                          __half* __restrict__ G, int ldg) {
-  const int g2 = 2 * n - 1;
-  const long total = (long)g2 * ldg;
-  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total;
-       e += (long)gridDim.x * blockDim.x) {
-    int a = (int)(e / ldg);
-    int b = (int)(e - (long)a * ldg);
-    double v = 0.0;
-    if (b < g2) {
-      int aa = transpose ? b : a;
-      int bb = transpose ? a : b;
-      int u = cu + bb - (n - 1);
-      int w = cv + aa - (n - 1);
-      if (u >= 0 && u < pu && w >= 0 && w < pv) v = psf[(long)u * pv + w];
-    }
-    G[e] = __float2half((float)v);
-  }
-}
-
-__global__ void psf_split_scale_kernel(const double* __restrict__ psf, long count,
+__global__ void psf_split_scale_kernel(const double* __restrict__ psf, long count, int nsum,
                                        double* __restrict__ scal) {
   __shared__ double sh[256];
-  double m = 0.0;
-  for (long e = threadIdx.x; e < count; e += 256) m = fmax(m, fabs(psf[e]));
+  __shared__ double ss[256];
+  double m = 0.0, t = 0.0;
+  for (long e = threadIdx.x; e < count; e += 256) {
+    m = fmax(m, fabs(psf[e]));
+    t += fabs(psf[e]);
+  }
   sh[threadIdx.x] = m;
+  ss[threadIdx.x] = t;
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
-    if (threadIdx.x < w) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + w]);
+    if (threadIdx.x < w) {
+      sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + w]);
+      ss[threadIdx.x] += ss[threadIdx.x + w];
+    }
     __syncthreads();
   }
   if (threadIdx.x == 0) {
     double sc = 1.0;
-    const double mx = sh[0];
+    // a grid entry is a sum of at most nsum distinct PSF entries, so
+    // min(nsum max|P|, sum|P|) bounds it (max|P| itself when nsum = 1)
+    const double mx = nsum <= 1 ? sh[0] : fmin(nsum * sh[0], ss[0]);
     if (mx > 0.0) {
       int ex = 0;
       (void)frexp(1024.0 / mx, &ex);      // 1024 / mx = f 2^ex, f in [0.5, 1)
@@ -114,14 +103,15 @@ __global__ void psf_split_scale_kernel(const double* __restrict__ psf, long coun
   }
 }
 
-void launch_psf_split_scale(const double* psf, long count, double* scal, hipStream_t s) {
-  hipLaunchKernelGGL(psf_split_scale_kernel, dim3(1), dim3(256), 0, s, psf, count, scal);
+void launch_psf_split_scale(const double* psf, long count, int nsum, double* scal,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(psf_split_scale_kernel, dim3(1), dim3(256), 0, s, psf, count, nsum, scal);
 }
 
 __device__ __forceinline__ __half d2h(double v) { return __half_raw{static_cast<_Float16>(v)}; }
 
 __global__ void build_grid_split_kernel(const double* __restrict__ psf, int pu, int pv, int cu,
-                                        int cv, int n, int transpose,
+                                        int cv, int n, int transpose, GridShifts sh,
                                         const double* __restrict__ scal, int part,
                                         __half* __restrict__ G, int ldg) {
   const int g2 = 2 * n - 1;
@@ -129,48 +119,103 @@ __global__ void build_grid_split_kernel(const double* __restrict__ psf, int pu, 
   const double sc = scal[0];
   for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total;
        e += (long)gridDim.x * blockDim.x) {
-    int a = (int)(e / ldg);
-    int b = (int)(e - (long)a * ldg);
+    const int a = (int)(e / ldg);
+    const int b = (int)(e - (long)a * ldg);
     double v = 0.0;
-    if (b < g2) {
-      int aa = transpose ? b : a;
-      int bb = transpose ? a : b;
-      int u = cu + bb - (n - 1);
-      int w = cv + aa - (n - 1);
-      if (u >= 0 && u < pu && w >= 0 && w < pv) v = psf[(long)u * pv + w] * sc;
-    }
+    if (b < g2) v = sc * (transpose ? grid_value(psf, pu, pv, cu, cv, n, b, a, sh)
+                                    : grid_value(psf, pu, pv, cu, cv, n, a, b, sh));
     const __half h = d2h(v);
     G[e] = part == 0 ? h : d2h(v - (double)__half2float(h));
   }
 }
 
 void launch_build_grid_split(const double* psf, int pu, int pv, int cu, int cv, int n,
-                             int transpose, const double* scal, int part, __half* G, int ldg,
-                             hipStream_t s) {
+                             int transpose, const GridShifts& sh, const double* scal, int part,
+                             __half* G, int ldg, hipStream_t s) {
   long total = (long)(2 * n - 1) * ldg;
   int blocks = (int)((total + 255) / 256);
   if (blocks > 4096) blocks = 4096;
   hipLaunchKernelGGL(build_grid_split_kernel, dim3(blocks), dim3(256), 0, s, psf, pu, pv, cu,
-                     cv, n, transpose, scal, part, G, ldg);
+                     cv, n, transpose, sh, scal, part, G, ldg);
 }
 
 template <typename T>
 void launch_build_grid(const double* psf, int pu, int pv, int cu, int cv, int n,
-                       int transpose, T* G, int ldg, hipStream_t s) {
+                       int transpose, const GridShifts& sh, T* G, int ldg, hipStream_t s) {
   long total = (long)(2 * n - 1) * ldg;
   int blocks = (int)((total + 255) / 256);
   if (blocks > 4096) blocks = 4096;
   hipLaunchKernelGGL(build_grid_kernel<T>, dim3(blocks), dim3(256), 0, s, psf, pu, pv, cu,
-                     cv, n, transpose, G, ldg);
+                     cv, n, transpose, sh, G, ldg);
 }
-template void launch_build_grid<float>(const double*, int, int, int, int, int, int, float*,
-                                       int, hipStream_t);
+
+// ---------------------------------------------------------------------------
+// Terms of the reflexive operator: out[a + n b + ld col] = in[a + n (n-1-b) + ld col]
+// (reversal of the block index b of every column).
+template <typename T>
+__global__ void flip_blocks_kernel(const T* __restrict__ in, T* __restrict__ out, int n,
+                                   long ld, int ncols) {
+  const long N = (long)n * n;
+  const long total = N * ncols;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total;
+       e += (long)gridDim.x * blockDim.x) {
+    const long col = e / N;
+    const long q = e - col * N;
+    const long b = q / n;
+    const long a = q - b * n;
+    out[col * ld + q] = in[col * ld + a + (long)n * (n - 1 - b)];
+  }
+}
+
+// Y = (Y + T1) + (T2 + T3)[flipped]: the four terms of a reflexive product.
+template <typename T>
+__global__ void combine_terms_kernel(T* __restrict__ Y, const T* __restrict__ T1,
+                                     const T* __restrict__ T2, const T* __restrict__ T3, int n,
+                                     long ld, int ncols) {
+  const long N = (long)n * n;
+  const long total = N * ncols;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total;
+       e += (long)gridDim.x * blockDim.x) {
+    const long col = e / N;
+    const long q = e - col * N;
+    const long b = q / n;
+    const long a = q - b * n;
+    const long f = col * ld + a + (long)n * (n - 1 - b);
+    const long o = col * ld + q;
+    Y[o] = (Y[o] + T1[o]) + (T2[f] + T3[f]);
+  }
+}
+
+template <typename T>
+void launch_flip_blocks(const T* in, T* out, int n, long ld, int ncols, hipStream_t s) {
+  const long total = (long)n * n * ncols;
+  int blocks = (int)std::min<long>((total + 255) / 256, 8192);
+  hipLaunchKernelGGL(flip_blocks_kernel<T>, dim3(blocks), dim3(256), 0, s, in, out, n, ld, ncols);
+}
+
+template <typename T>
+void launch_combine_terms(T* Y, const T* T1, const T* T2, const T* T3, int n, long ld, int ncols,
+                          hipStream_t s) {
+  const long total = (long)n * n * ncols;
+  int blocks = (int)std::min<long>((total + 255) / 256, 8192);
+  hipLaunchKernelGGL(combine_terms_kernel<T>, dim3(blocks), dim3(256), 0, s, Y, T1, T2, T3, n, ld,
+                     ncols);
+}
+template void launch_flip_blocks<float>(const float*, float*, int, long, int, hipStream_t);
+template void launch_flip_blocks<double>(const double*, double*, int, long, int, hipStream_t);
+template void launch_combine_terms<float>(float*, const float*, const float*, const float*, int,
+                                          long, int, hipStream_t);
+template void launch_combine_terms<double>(double*, const double*, const double*, const double*,
+                                           int, long, int, hipStream_t);
+template void launch_build_grid<float>(const double*, int, int, int, int, int, int,
+                                       const GridShifts&, float*, int, hipStream_t);
 template void launch_build_grid<double>(const double*, int, int, int, int, int, int,
-                                        double*, int, hipStream_t);
-template void launch_build_grid<__hip_bfloat16>(const double*, int, int, int, int, int,
-                                                int, __hip_bfloat16*, int, hipStream_t);
+                                        const GridShifts&, double*, int, hipStream_t);
+template void launch_build_grid<__hip_bfloat16>(const double*, int, int, int, int, int, int,
+                                                const GridShifts&, __hip_bfloat16*, int,
+                                                hipStream_t);
 template void launch_build_grid<__half>(const double*, int, int, int, int, int, int,
-                                        __half*, int, hipStream_t);
+                                        const GridShifts&, __half*, int, hipStream_t);
 
 // ---------------------------------------------------------------------------
 template <typename T> struct Vec4;

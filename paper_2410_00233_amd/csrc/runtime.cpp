@@ -58,12 +58,16 @@ int rank_of(int32_t method, const void* opts) {
 }
 
 // Estimated device time of a problem, for largest-first ordering: R products
-// cost 2 n^4 per column; the single-vector products of EGKB run about three
-// times slower per flop than the block products of RSVD.
+// cost 2 n^4 per column (four generated products for reflexive boundary
+// conditions); the single-vector products of EGKB run about three times slower
+// per flop than the block products of RSVD.
 double est_cost(const kp_blur& b, int32_t method, const void* opts) {
-  const double n4 = std::pow((double)b.n, 4.0);
+  const double n4 = std::pow((double)b.n, 4.0) * (b.bc == KP_BC_REFLEXIVE ? 4.0 : 1.0);
   const int kp = rank_of(method, opts);
-  if (method == KP_METHOD_GKB) return 3.0 * 4.0 * n4 * kp;
+  if (method == KP_METHOD_GKB) {
+    const bool blk = opts && static_cast<const kp_gkb_opts*>(opts)->block >= 1;
+    return (blk ? 1.6 : 3.0) * 4.0 * n4 * kp;
+  }
   const int q = opts ? static_cast<const kp_rsvd_opts*>(opts)->q : 1;
   return (4.0 * q + 4.0) * n4 * kp;
 }
@@ -108,23 +112,34 @@ size_t svd_bytes(const kp_request& r) {
   const size_t N = (size_t)n * n;
   const size_t grid = (size_t)(2 * n - 1) * (size_t)(((2 * n - 1) + 7) & ~7);
   size_t b = round256((size_t)r.blur.pu * r.blur.pv * 8);
+  // reflexive boundary conditions: four grid pairs, the reversed input and
+  // three term outputs of the widest product
+  const size_t terms = r.blur.bc == KP_BC_REFLEXIVE ? 4 : 1;
   if (r.method == KP_METHOD_GKB) {
     const size_t es = r.gkb.prec == KP_F64 ? 8 : 4;
-    const int kp = r.gkb.k + r.gkb.p;
-    b += 2 * round256(grid * es);
-    b += round256(N * (kp + 1) * es) + round256(N * kp * es);
+    int ucols = r.gkb.k + r.gkb.p + 1, vcols = r.gkb.k + r.gkb.p, wide = 1;
+    if (r.gkb.block >= 1) {
+      const int bs = r.gkb.block, nb = (r.gkb.k + r.gkb.p + bs - 1) / bs;
+      ucols = (nb + 1) * bs;
+      vcols = nb * bs;
+      wide = bs;
+    }
+    b += 2 * terms * round256(grid * es);
+    b += round256(N * ucols * es) + round256(N * vcols * es);
     b += 2 * round256(N * (size_t)r.k_cap * 8);
-    if (r.gkb.y0) b += round256(N * 8);
+    if (terms > 1) b += 4 * round256(N * wide * es);
+    if (r.gkb.y0) b += round256(N * (r.gkb.block >= 1 ? r.gkb.block : 1) * 8);
   } else {
     const size_t es = r.rsvd.prec == KP_F64 ? 8 : 4;
     const int kp = r.rsvd.k + r.rsvd.p;
-    b += 2 * round256(grid * es);
+    b += 2 * terms * round256(grid * es);
     if (r.rsvd.prec == KP_BF16 || r.rsvd.prec == KP_F16) {
-      b += 2 * round256(grid * 2);
+      b += 2 * terms * round256(grid * 2);
       b += round256((N + 8 * (size_t)n) * kp * 2);
     }
     b += 2 * round256(N * kp * es);
     b += 2 * round256(N * (size_t)r.k_cap * 8);
+    if (terms > 1) b += 4 * round256(N * kp * es);
     if (r.rsvd.F) b += round256(N * kp * 8);
   }
   return b + kSlack;
@@ -134,7 +149,7 @@ size_t factor_bytes(int n, int k_cap) { return 2 * round256((size_t)k_cap * n * 
 
 struct CacheKey {
   uint64_t psf_key;
-  int32_t n, method, k, p, q, prec, refine, reorth, auto_k, k_min, literal_init, k_cap, pad;
+  int32_t n, method, k, p, q, prec, refine, reorth, auto_k, k_min, literal_init, k_cap, bc, block;
   uint64_t seed;
   double tau, bd_rel;
   bool operator<(const CacheKey& o) const { return std::memcmp(this, &o, sizeof(CacheKey)) < 0; }
@@ -145,6 +160,7 @@ CacheKey key_of(const kp_request& r) {
   std::memset(&k, 0, sizeof(k));   // padding participates in the ordering
   k.psf_key = r.psf_key;
   k.n = r.blur.n;
+  k.bc = r.blur.bc;
   k.method = r.method;
   k.k_cap = r.k_cap;
   if (r.method == KP_METHOD_GKB) {
@@ -158,6 +174,7 @@ CacheKey key_of(const kp_request& r) {
     k.seed = r.gkb.seed;
     k.tau = r.gkb.tau;
     k.bd_rel = r.gkb.bd_rel;
+    k.block = r.gkb.block;
   } else {
     k.k = r.rsvd.k;
     k.p = r.rsvd.p;

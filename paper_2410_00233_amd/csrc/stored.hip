@@ -48,28 +48,32 @@ template void launch_reorder<double>(const double*, double*, int, hipStream_t);
 
 // Explicit blur matrix from a PSF: A[r + n i, c + n j] = sum over the images
 // c~ of c and j~ of j of P[cu + r - c~, cv + i - j~], where the images are c
-// itself (zero boundary conditions, bc = 0) or, for reflexive boundary
-// conditions (bc = 1: the image extended by reflection about the edge of its
-// last pixel, x[-1-k] = x[k], x[n+k] = x[n-1-k]), c + 2n m and -1 - c + 2n m for
-// m = -1, 0, 1. One thread per entry, FP64 sums.
+// itself (zero boundary conditions, bc = 0), c + 2n m and -1 - c + 2n m for
+// m = -1, 0, 1 (reflexive, bc = 1: the image extended by reflection about the
+// edge of its last pixel, x[-1-k] = x[k], x[n+k] = x[n-1-k]) or c + n m for
+// m = -2 .. 2 (periodic, bc = 2). One thread per entry, FP64 sums.
+__device__ __forceinline__ int image_of(int bc, int k, int a, int n) {
+  if (bc == 1) return a < 3 ? k + 2 * n * (a - 1) : -1 - k + 2 * n * (a - 4);
+  if (bc == 2) return k + n * (a - 2);
+  return k;
+}
+
 template <typename T>
 __global__ void blur_matrix_kernel(const double* __restrict__ psf, int pu, int pv, int cu,
                                    int cv, int n, int bc, T* __restrict__ A) {
   const long N = (long)n * n;
+  const int nim = bc == 1 ? 6 : (bc == 2 ? 5 : 1);
   for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < N * N;
        e += (long)gridDim.x * blockDim.x) {
     const long p = e / N, q = e - p * N;
     const int r = (int)(p % n), i = (int)(p / n);
     const int c = (int)(q % n), j = (int)(q / n);
-    const int nim = bc ? 6 : 1;
     double v = 0.0;
     for (int a = 0; a < nim; ++a) {
-      const int jj = a < 3 ? j + 2 * n * (a - 1) : -1 - j + 2 * n * (a - 4);
-      const int w = cv + i - (bc ? jj : j);
+      const int w = cv + i - image_of(bc, j, a, n);
       if (w < 0 || w >= pv) continue;
       for (int b = 0; b < nim; ++b) {
-        const int cc = b < 3 ? c + 2 * n * (b - 1) : -1 - c + 2 * n * (b - 4);
-        const int u = cu + r - (bc ? cc : c);
+        const int u = cu + r - image_of(bc, c, b, n);
         if (u >= 0 && u < pu) v += psf[(long)u * pv + w];
       }
     }
