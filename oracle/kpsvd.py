@@ -165,7 +165,7 @@ def _gs_column(w, basis, passes=2):
 
 
 def block_egkb(apply_R, apply_Rt, Y, k, p, *, bd_rel=None, seed=0, dtype=np.float64,
-               force_breakdown=None):
+               force_breakdown=None, auto_k=False, k_min=0, tau=0.0, literal_init=False):
     """Block Golub-Kahan bidiagonalization with b = Y.shape[1] start vectors
     (Golub, Luk & Overton 1981): the block analogue of Algorithm 1 with full
     reorthogonalization, enlarged to k_p = k + p columns rounded up to whole
@@ -190,7 +190,17 @@ def block_egkb(apply_R, apply_Rt, Y, k, p, *, bd_rel=None, seed=0, dtype=np.floa
     force_breakdown: optional set of ("u"|"v", m) taking the breakdown branch at
     exactly those columns (and nowhere else), to follow a run whose decisions
     were taken in another precision.
-    Returns dict(sigma, U, V, Ub, Vb, C, kp, breakdowns).
+
+    auto_k: the stopping rule of Algorithm 1 (eq. "stopnu") applied to the
+    columns in order: column m (0-based, j = m + 1) contributes
+    alpha_j = C[m, m] (the diagonal of L) and t_j = the stored norm of column m
+    of U (the start block's own norms for m < b, C[m, m - b] after), so that
+    zeta_j = alpha_j t_j and nu_{j+1} = sqrt(zeta_j zeta_{j-1}), with
+    zeta_1 = alpha_1 t_1 and nu_2 = +inf (literal_init: 1 and 100). The first
+    j > k_min (j >= 2) with nu_{j+1} > nu_j or nu_j < tau sets
+    k = min(j, k), k_p = k + p and nb = ceil(k_p / b); the block that holds
+    column j is finished. With b = 1 these are Algorithm 1's alpha, t and rule.
+    Returns dict(sigma, U, V, Ub, Vb, C, kp, k, breakdowns, zeta, nu).
     """
     eps = np.finfo(dtype).eps / 2
     if bd_rel is None:
@@ -218,7 +228,8 @@ def block_egkb(apply_R, apply_Rt, Y, k, p, *, bd_rel=None, seed=0, dtype=np.floa
                 broken = nr == 0.0 or (in_c and nr <= bd_rel * scale[0])
             if broken:
                 breakdowns.append((side, m))
-                g = philox.normals(N, seed, 2 * (m + 1) + (0 if side == "u" else 1)).astype(dtype)
+                g = philox.normals(W.shape[0], seed,
+                                   2 * (m + 1) + (0 if side == "u" else 1)).astype(dtype)
                 g, _ = _gs_column(g, full)
                 w, nr_store = g / _norm(g), 0.0
             else:
@@ -230,22 +241,49 @@ def block_egkb(apply_R, apply_Rt, Y, k, p, *, bd_rel=None, seed=0, dtype=np.floa
         return Q, Rown
 
     U = np.zeros((N, 0), dtype=dtype)
-    V = np.zeros((N, 0), dtype=dtype)
-    U1, _ = orth_block(Y, U, "u", 0, False)
+    V = None                                # sized by the first product with B^T
+    U1, R0 = orth_block(Y, U, "u", 0, False)
     U = U1
+    tcol = list(np.diag(R0))                # t of every U column, in order
     C = np.zeros((kp + b, kp))
-    for j in range(nb):
+    k_in = k
+    zeta, nu = {}, {}
+    fired = False
+    j = 0
+    while j < nb:
         W = apply_Rt(U[:, j * b:(j + 1) * b])
+        if V is None:
+            V = np.zeros((W.shape[0], 0), dtype=dtype)
         Vj, Lt = orth_block(W, V, "v", j * b, True)
         V = np.concatenate([V, Vj], axis=1)
         C[j * b:(j + 1) * b, j * b:(j + 1) * b] = Lt.T
+        for c in range(b):                  # the stopping rule, column by column
+            m = j * b + c
+            jj = m + 1
+            zeta[jj] = Lt[c, c] * tcol[m]
+            if jj == 1:
+                if literal_init:
+                    zeta[1] = 1.0
+                nu[2] = 100.0 if literal_init else np.inf
+                continue
+            nu[jj + 1] = float(np.sqrt(zeta[jj] * zeta[jj - 1]))
+            if auto_k and not fired and jj > k_min:
+                if nu[jj + 1] > nu[jj] or nu[jj] < tau:
+                    fired = True
+                    k = min(jj, k_in)
+                    kp = k + p
+                    nb = -(-kp // b)
         Z = apply_R(Vj)
         Uj, Rj = orth_block(Z, U, "u", (j + 1) * b, True)
         U = np.concatenate([U, Uj], axis=1)
+        tcol.extend(np.diag(Rj))
         C[(j + 1) * b:(j + 2) * b, j * b:(j + 1) * b] = Rj
+        j += 1
+    kp = nb * b
+    U, V, C = U[:, :kp + b], V[:, :kp], C[:kp + b, :kp]
     Uc, sc, Vct = np.linalg.svd(C, full_matrices=False)
     return dict(sigma=sc[:k].copy(), sigma_all=sc, U=U @ Uc[:, :k], V=V @ Vct[:k].T, Ub=U,
-                Vb=V, C=C, kp=kp, breakdowns=breakdowns)
+                Vb=V, C=C, kp=kp, k=k, breakdowns=breakdowns, zeta=zeta, nu=nu)
 
 
 def orth(X):

@@ -269,3 +269,51 @@ def test_block_egkb_forced_breakdown_keeps_the_relation():
     g = philox.normals(n * n, 9, 2 * 5 + 1)
     g = g - V[:, :4] @ (V[:, :4].T @ g)
     assert np.allclose(V[:, 4], g / np.linalg.norm(g), atol=1e-12)
+
+
+def test_block_stopping_rule_with_one_vector_is_algorithm_1():
+    """With b = 1 the block rule is Algorithm 1's (same k, k_p, sigma), with
+    the default and the printed initialization and with a tau clause."""
+    zeta = [1.0, 0.5, 0.3, 0.2, 0.25, 0.4, 0.1, 0.05, 0.04, 0.03, 0.02, 0.01, 0.01, 0.01]
+    B = _bidiag(zeta, [1.0] * (len(zeta) + 1))
+    y = np.zeros(B.shape[0])
+    y[0] = 1.0
+    R = lambda X: B @ X
+    Rt = lambda X: B.T @ X
+    for kw in (dict(), dict(literal_init=True), dict(tau=0.3), dict(k_min=6)):
+        ref = kpsvd.egkb(R, Rt, y, k=10, p=2, auto_k=True, **kw)
+        blk = kpsvd.block_egkb(R, Rt, y[:, None], k=10, p=2, auto_k=True, **kw)
+        assert (blk["k"], blk["kp"]) == (ref["k"], ref["kp"]), kw
+        assert np.allclose(blk["sigma"], ref["sigma"], rtol=1e-13, atol=1e-15)
+
+
+def test_block_stopping_rule_fires_at_hand_computed_column():
+    """b = 2 on the direct sum of two bidiagonals started from their first
+    rows: the block process interleaves the two single-vector processes, so
+    the columns carry zeta = (1, .9, .5, .45, .3, .28, .2, .25, .4, ...) and
+    nu_{j+1} = sqrt(zeta_j zeta_{j-1}) = .949, .671, .474, .367, .290, .237,
+    .224, .316: the first rise is nu_10 > nu_9, at j = 9, so k = 9,
+    k_p = 11 -> 6 blocks of 2."""
+    a1 = [1.0, 0.5, 0.3, 0.2, 0.4, 0.1, 0.05, 0.04, 0.03, 0.02, 0.01, 0.01]
+    a2 = [0.9, 0.45, 0.28, 0.25, 0.1, 0.05, 0.04, 0.03, 0.02, 0.01, 0.01, 0.01]
+    B1 = _bidiag(a1, [1.0] * 13)
+    B2 = _bidiag(a2, [1.0] * 13)
+    B = np.zeros((26, 24))
+    B[:13, :12] = B1
+    B[13:, 12:] = B2
+    Y = np.zeros((26, 2))
+    Y[0, 0] = Y[13, 1] = 1.0
+    out = kpsvd.block_egkb(lambda X: B @ X, lambda X: B.T @ X, Y, k=10, p=2, auto_k=True)
+    assert out["k"] == 9 and out["kp"] == 12
+    z = [out["zeta"][j] for j in range(1, 10)]
+    assert np.allclose(z, [1.0, 0.9, 0.5, 0.45, 0.3, 0.28, 0.2, 0.25, 0.4], atol=1e-14)
+    # without the rule the same run keeps k = 10, k_p = 12
+    out0 = kpsvd.block_egkb(lambda X: B @ X, lambda X: B.T @ X, Y, k=10, p=2)
+    assert out0["k"] == 10 and out0["kp"] == 12
+    # the fired run is exact on the leading part: B has the Ritz values of its
+    # Krylov space, which for these decoupled bidiagonals are sigma of the
+    # leading 6 x 6 (+1 row) sections of B1 and B2
+    s1 = np.linalg.svd(B1[:7, :6], compute_uv=False)
+    s2 = np.linalg.svd(B2[:7, :6], compute_uv=False)
+    assert np.allclose(np.sort(out["sigma_all"])[::-1][:9],
+                       np.sort(np.concatenate([s1, s2]))[::-1][:9], rtol=1e-12)
