@@ -108,8 +108,14 @@ typedef struct {
                            Golub-Kahan bidiagonalization with b start vectors
                            (Golub, Luk & Overton 1981), the block analogue of
                            Algorithm 1 with full reorthogonalization, run for
-                           ceil((k+p)/b) = nb blocks; needs (nb+1) b <= 64 and
-                           auto_k = 0 (reorth and literal_init are ignored).
+                           ceil((k+p)/b) = nb blocks; needs (nb+1) b <= 64
+                           (reorth is ignored). auto_k applies the nu rule
+                           once per block J with zeta_J = the geometric mean of
+                           alpha t over the block's columns (alpha = diagonal of
+                           L_J, t = stored norms of the block's left vectors),
+                           tested for J >= 2, J b > k_min; when it fires,
+                           k = min(J b, k) and nb = ceil((k+p)/b). At b = 1
+                           this is Algorithm 1's rule.
                            Without y0 column c of the start block is Philox
                            stream 0 (c = 0) or 2^31 + c. A breakdown of column m
                            of the left (right) basis is restarted from stream

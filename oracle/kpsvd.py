@@ -191,15 +191,17 @@ def block_egkb(apply_R, apply_Rt, Y, k, p, *, bd_rel=None, seed=0, dtype=np.floa
     exactly those columns (and nowhere else), to follow a run whose decisions
     were taken in another precision.
 
-    auto_k: the stopping rule of Algorithm 1 (eq. "stopnu") applied to the
-    columns in order: column m (0-based, j = m + 1) contributes
-    alpha_j = C[m, m] (the diagonal of L) and t_j = the stored norm of column m
-    of U (the start block's own norms for m < b, C[m, m - b] after), so that
-    zeta_j = alpha_j t_j and nu_{j+1} = sqrt(zeta_j zeta_{j-1}), with
-    zeta_1 = alpha_1 t_1 and nu_2 = +inf (literal_init: 1 and 100). The first
-    j > k_min (j >= 2) with nu_{j+1} > nu_j or nu_j < tau sets
-    k = min(j, k), k_p = k + p and nb = ceil(k_p / b); the block that holds
-    column j is finished. With b = 1 these are Algorithm 1's alpha, t and rule.
+    auto_k: the stopping rule of Algorithm 1 (eq. "stopnu") with one value per
+    block: zeta_J (J = 1 .. nb) is the geometric mean over the b columns m of
+    block J of alpha_m t_m, where alpha_m = C[m, m] (the diagonal of L_J) and
+    t_m is the stored norm of column m of U (the start block's own norms for
+    J = 1, the diagonal of R_{J-1} after), i.e. (|det L_J| |det R_{J-1}|)^(1/b).
+    nu_{J+1} = sqrt(zeta_J zeta_{J-1}), zeta_1 as computed and nu_2 = +inf
+    (literal_init: 1 and 100). The first block J >= 2 with J b > k_min and
+    nu_{J+1} > nu_J or nu_J < tau sets k = min(J b, k), k_p = k + p and
+    nb = ceil(k_p / b). With b = 1 these are Algorithm 1's alpha, t and rule.
+    (Column by column the rule would fire at the first block boundary, where a
+    block's first column is always larger than the last of the previous one.)
     Returns dict(sigma, U, V, Ub, Vb, C, kp, k, breakdowns, zeta, nu).
     """
     eps = np.finfo(dtype).eps / 2
@@ -257,20 +259,21 @@ def block_egkb(apply_R, apply_Rt, Y, k, p, *, bd_rel=None, seed=0, dtype=np.floa
         Vj, Lt = orth_block(W, V, "v", j * b, True)
         V = np.concatenate([V, Vj], axis=1)
         C[j * b:(j + 1) * b, j * b:(j + 1) * b] = Lt.T
-        for c in range(b):                  # the stopping rule, column by column
-            m = j * b + c
-            jj = m + 1
-            zeta[jj] = Lt[c, c] * tcol[m]
-            if jj == 1:
-                if literal_init:
-                    zeta[1] = 1.0
-                nu[2] = 100.0 if literal_init else np.inf
-                continue
-            nu[jj + 1] = float(np.sqrt(zeta[jj] * zeta[jj - 1]))
-            if auto_k and not fired and jj > k_min:
-                if nu[jj + 1] > nu[jj] or nu[jj] < tau:
+        # the stopping rule on block J = j + 1
+        J = j + 1
+        prods = np.array([Lt[c, c] * tcol[j * b + c] for c in range(b)])
+        with np.errstate(divide="ignore"):
+            zeta[J] = float(np.exp(np.mean(np.log(prods))))
+        if J == 1:
+            if literal_init:
+                zeta[1] = 1.0
+            nu[2] = 100.0 if literal_init else np.inf
+        else:
+            nu[J + 1] = float(np.sqrt(zeta[J] * zeta[J - 1]))
+            if auto_k and not fired and J * b > k_min:
+                if nu[J + 1] > nu[J] or nu[J] < tau:
                     fired = True
-                    k = min(jj, k_in)
+                    k = min(J * b, k_in)
                     kp = k + p
                     nb = -(-kp // b)
         Z = apply_R(Vj)

@@ -212,7 +212,7 @@ class Context:
                         for i in range(min(f.diag.nbreak, 128))]
         f.ms = f.diag.ms_total
         if bases:
-            f.S = S[:nu_cols] if block >= 1 else S[:kp + 1]
+            f.S = S[:kp + block] if block >= 1 else S[:kp + 1]
             f.Q = Q[:kp]
         return f
 

@@ -890,10 +890,12 @@ kp_status egkb_block_impl(kp_ctx* c, const RmatOp<T>& op, const kp_gkb_opts* o, 
   const int n = op.n;
   const long N = (long)n * n;
   const int b = o->block;
-  const int k = o->k;
-  const int nb = (o->k + o->p + b - 1) / b;
-  const int kp = nb * b;
-  const int rows = kp + b;
+  const int k_in = o->k;
+  int k = o->k;
+  int nb = (o->k + o->p + b - 1) / b;
+  const int nb0 = nb;
+  const int kp0 = nb0 * b;
+  const int rows0 = kp0 + b;          // C is allocated for the initial k_p
   const double u = (sizeof(T) == 4) ? std::ldexp(1.0, -24) : std::ldexp(1.0, -53);
   const double bd_rel = o->bd_rel > 0 ? o->bd_rel : 1e2 * u;
 
@@ -902,10 +904,13 @@ kp_status egkb_block_impl(kp_ctx* c, const RmatOp<T>& op, const kp_gkb_opts* o, 
   double* hcol = sc.h;
   double* h2 = sc.h + 64;
   T *U = nullptr, *V = nullptr;
-  KP_TRY(wsT(c, std::string("egkbS_") + tname<T>(), (size_t)N * rows, &U));
-  KP_TRY(wsT(c, std::string("egkbQ_") + tname<T>(), (size_t)N * kp, &V));
+  KP_TRY(wsT(c, std::string("egkbS_") + tname<T>(), (size_t)N * rows0, &U));
+  KP_TRY(wsT(c, std::string("egkbQ_") + tname<T>(), (size_t)N * kp0, &V));
 
-  std::vector<double> C((size_t)rows * kp, 0.0);
+  std::vector<double> C((size_t)rows0 * kp0, 0.0);
+  std::vector<double> tcol;            // stored norm of every U column, in order
+  std::map<int, double> zeta, nu;
+  bool fired = false;
   std::vector<std::pair<int, int>> breaks;
   double scale = 0.0;
 
@@ -971,27 +976,57 @@ kp_status egkb_block_impl(kp_ctx* c, const RmatOp<T>& op, const kp_gkb_opts* o, 
       launch_philox_normals<T>(U + N * col, N, o->seed, col == 0 ? 0u : 0x80000000u + col, s);
   }
   double own[64], d = 0.0;
-  for (int col = 0; col < b; ++col) KP_TRY(new_column(U, col, 0, 0, false, own, &d));
+  for (int col = 0; col < b; ++col) {
+    KP_TRY(new_column(U, col, 0, 0, false, own, &d));
+    tcol.push_back(d);
+  }
 
   for (int j = 0; j < nb; ++j) {
     const long jb = (long)j * b;
     // V_{j+1} L^T = B^T U_{j+1} (minus the earlier V, through the Gram-Schmidt)
     KP_TRY(product(1, U + N * jb, V + N * jb));
+    double logsum = 0.0;
     for (int col = 0; col < b; ++col) {
       KP_TRY(new_column(V, (int)jb + col, col, 1, true, own, &d));
-      for (int r = 0; r < col; ++r) C[(jb + col) + (size_t)rows * (jb + r)] = own[r];
-      C[(jb + col) + (size_t)rows * (jb + col)] = d;
+      for (int r = 0; r < col; ++r) C[(jb + col) + (size_t)rows0 * (jb + r)] = own[r];
+      C[(jb + col) + (size_t)rows0 * (jb + col)] = d;
+      logsum += std::log(d * tcol[jb + col]);     // -inf for a stored 0
+    }
+    // stopping rule of Algorithm 1 with one value per block: zeta_J = the
+    // geometric mean of alpha t over the block's columns
+    const int J = j + 1;
+    zeta[J] = std::exp(logsum / b);
+    if (J == 1) {
+      if (o->literal_init) zeta[1] = 1.0;
+      nu[2] = o->literal_init ? 100.0 : INFINITY;
+    } else {
+      nu[J + 1] = std::sqrt(zeta[J] * zeta[J - 1]);
+      if (o->auto_k && !fired && J * b > o->k_min && (nu[J + 1] > nu[J] || nu[J] < o->tau)) {
+        fired = true;
+        k = std::min(J * b, k_in);
+        nb = (k + o->p + b - 1) / b;
+      }
     }
     // U_{j+2} R = B V_{j+1} (minus the earlier U)
     const long ub = jb + b;
     KP_TRY(product(0, V + N * jb, U + N * ub));
     for (int col = 0; col < b; ++col) {
       KP_TRY(new_column(U, (int)ub + col, col, 0, true, own, &d));
-      for (int r = 0; r < col; ++r) C[(ub + r) + (size_t)rows * (jb + col)] = own[r];
-      C[(ub + col) + (size_t)rows * (jb + col)] = d;
+      for (int r = 0; r < col; ++r) C[(ub + r) + (size_t)rows0 * (jb + col)] = own[r];
+      C[(ub + col) + (size_t)rows0 * (jb + col)] = d;
+      tcol.push_back(d);
     }
   }
   KP_TRY(check_launch(c, "block egkb loop"));
+  // the leading (nb+1) b x nb b part of C (nb may have shrunk by the rule)
+  const int kp = nb * b;
+  const int rows = kp + b;
+  if (rows != rows0) {
+    std::vector<double> Cc((size_t)rows * kp);
+    for (int col = 0; col < kp; ++col)
+      for (int r = 0; r < rows; ++r) Cc[r + (size_t)rows * col] = C[r + (size_t)rows0 * col];
+    C.swap(Cc);
+  }
 
   double *dC, *Uc, *sig, *Vc;
   int* sweeps;
@@ -1557,7 +1592,6 @@ kp_status check_gkb(kp_ctx* c, const kp_gkb_opts* o, kp_factors* f, int n) {
     if ((nb + 1) * b > 64)
       return set_err(c, KP_E_INVAL, "block GKB needs (ceil((k+p)/b) + 1) * b <= 64");
     if ((nb + 1) * b > N) return set_err(c, KP_E_INVAL, "block GKB needs (nb + 1) * b <= n^2");
-    if (o->auto_k) return set_err(c, KP_E_INVAL, "auto_k is not supported with block >= 1");
     ny = N * b;
   }
   if (o->y0)

@@ -148,6 +148,73 @@ def test_block_gkb_default_start_block_is_deterministic(ctx):
     assert np.all(f1.sigma[:8] <= s_ex * (1 + 1e-5))
 
 
+def _bidiag(alpha, t):
+    m = len(alpha)
+    B = np.zeros((m + 1, m))
+    for i in range(m):
+        B[i, i] = alpha[i]
+        B[i + 1, i] = t[i + 1]
+    return B
+
+
+def test_block_stopping_rule_fires_at_hand_computed_block(ctx):
+    """The rule on a stored R holding two decoupled bidiagonals (the oracle's
+    hand-computed case): b = 2 fires at block 5 (k = 10, k_p = 12), tau = 0.8
+    at block 3 (k = 6, k_p = 8); b = 1 on one bidiagonal fires where
+    Algorithm 1 does (j = 6), on the device too."""
+    import torch
+    zb = np.array([1.0, 0.5, 0.3, 0.2, 0.4, 0.1, 0.05, 0.04, 0.03, 0.02])
+    fac = np.array([1.2, 1.2, 0.8, 1.5, 0.9, 1.1, 1.0, 1.3, 0.7, 1.0])
+    n = 5
+    R = np.zeros((n * n, n * n))
+    R[:11, :10] = _bidiag(zb * fac, [1.0] * 11)
+    R[11:22, 10:20] = _bidiag(zb / fac, [1.0] * 11)
+    Rd = torch.tensor(R, dtype=torch.float64, device="cuda")
+    Y = np.zeros((n * n, 2))
+    Y[0, 0] = Y[11, 1] = 1.0
+    for tau, k_exp, kp_exp in ((0.0, 10, 12), (0.8, 6, 8)):
+        f = ctx.kp_svd_gkb(None, 12, 2, prec="f64", y0=Y, block=2, auto_k=True, tau=tau,
+                           stored=(n, Rd))
+        ref = kpsvd.block_egkb(lambda X: R @ X, lambda X: R.T @ X, Y, 12, 2, auto_k=True,
+                               tau=tau, force_breakdown=set(f.breakdowns))
+        assert (ref["k"], ref["kp"]) == (k_exp, kp_exp)
+        assert (f.k, f.diag.kp) == (k_exp, kp_exp)
+        assert np.abs(f.sigma[:k_exp] - ref["sigma"]).max() <= 1e-13
+    zeta = [1.0, 0.5, 0.3, 0.2, 0.25, 0.4, 0.1, 0.05, 0.04, 0.03, 0.02, 0.01, 0.01, 0.01]
+    n = 6
+    R1 = np.zeros((n * n, n * n))
+    R1[:15, :14] = _bidiag(zeta, [1.0] * 15)
+    R1d = torch.tensor(R1, dtype=torch.float64, device="cuda")
+    y = np.zeros(n * n)
+    y[0] = 1.0
+    a = ctx.kp_svd_gkb(None, 10, 2, prec="f64", y0=y, auto_k=True, stored=(n, R1d))
+    g = ctx.kp_svd_gkb(None, 10, 2, prec="f64", y0=y[:, None], block=1, auto_k=True,
+                       stored=(n, R1d))
+    assert a.k == g.k == 6 and a.diag.kp == g.diag.kp == 8
+    assert np.abs(a.sigma[:6] - g.sigma[:6]).max() <= 1e-13
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_block_stopping_rule_matches_oracle_on_a_psf(ctx, prec):
+    """auto_k with a tau on the rank-6 disk (b = 3; breakdowns set zeta to 0)
+    and on a speckle PSF (b = 4): k, k_p and sigma as the oracle's, replaying
+    the device's breakdown decisions."""
+    from paper_2410_00233_amd import api
+    for n, (P, cu, cv), b, tau, k, p, k_exp in [(48, wl.disk_psf(48), 3, 1e-3, 18, 3, 12),
+                                                 (40, wl.speckle_psf(40, seed=1011), 4, 0.2, 16,
+                                                  4, 12)]:
+        Y = wl.gaussian_block(n * n, b, seed=51 + n)
+        f = ctx.kp_svd_gkb(api.Blur(P, cu, cv, n), k, p, prec=prec, y0=Y, block=b,
+                           auto_k=True, tau=tau * 1.0, seed=2)
+        R, Rt = _ops(P, cu, cv, n)
+        ref = kpsvd.block_egkb(R, Rt, Y, k, p, seed=2, auto_k=True, tau=tau,
+                               force_breakdown=set(f.breakdowns))
+        assert ref["k"] == k_exp
+        assert (f.k, f.diag.kp) == (ref["k"], ref["kp"]), (n, f.k, f.diag.kp, ref["k"], ref["kp"])
+        tol = 1e-12 if prec == "f64" else 1e-5
+        assert np.abs(f.sigma[:f.k] - ref["sigma"]).max() <= tol * ref["sigma"][0]
+
+
 def test_block_gkb_rejects_bad_arguments(ctx):
     from paper_2410_00233_amd import api
     n = 16
@@ -155,7 +222,5 @@ def test_block_gkb_rejects_bad_arguments(ctx):
     blur = api.Blur(P, cu, cv, n)
     with pytest.raises(api.KPError):          # (ceil(40/30) + 1) * 30 = 90 > 64
         ctx.kp_svd_gkb(blur, 20, 20, prec="f32", block=30)
-    with pytest.raises(api.KPError):          # auto_k is Algorithm 1 only
-        ctx.kp_svd_gkb(blur, 10, 10, prec="f32", block=4, auto_k=True)
     with pytest.raises(api.KPError):
         ctx.kp_svd_gkb(blur, 10, 10, prec="f32", block=-1)

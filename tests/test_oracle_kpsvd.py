@@ -287,33 +287,40 @@ def test_block_stopping_rule_with_one_vector_is_algorithm_1():
         assert np.allclose(blk["sigma"], ref["sigma"], rtol=1e-13, atol=1e-15)
 
 
-def test_block_stopping_rule_fires_at_hand_computed_column():
+def test_block_stopping_rule_fires_at_hand_computed_block():
     """b = 2 on the direct sum of two bidiagonals started from their first
     rows: the block process interleaves the two single-vector processes, so
-    the columns carry zeta = (1, .9, .5, .45, .3, .28, .2, .25, .4, ...) and
-    nu_{j+1} = sqrt(zeta_j zeta_{j-1}) = .949, .671, .474, .367, .290, .237,
-    .224, .316: the first rise is nu_10 > nu_9, at j = 9, so k = 9,
-    k_p = 11 -> 6 blocks of 2."""
-    a1 = [1.0, 0.5, 0.3, 0.2, 0.4, 0.1, 0.05, 0.04, 0.03, 0.02, 0.01, 0.01]
-    a2 = [0.9, 0.45, 0.28, 0.25, 0.1, 0.05, 0.04, 0.03, 0.02, 0.01, 0.01, 0.01]
-    B1 = _bidiag(a1, [1.0] * 13)
-    B2 = _bidiag(a2, [1.0] * 13)
-    B = np.zeros((26, 24))
-    B[:13, :12] = B1
-    B[13:, 12:] = B2
-    Y = np.zeros((26, 2))
-    Y[0, 0] = Y[13, 1] = 1.0
-    out = kpsvd.block_egkb(lambda X: B @ X, lambda X: B.T @ X, Y, k=10, p=2, auto_k=True)
-    assert out["k"] == 9 and out["kp"] == 12
-    z = [out["zeta"][j] for j in range(1, 10)]
-    assert np.allclose(z, [1.0, 0.9, 0.5, 0.45, 0.3, 0.28, 0.2, 0.25, 0.4], atol=1e-14)
-    # without the rule the same run keeps k = 10, k_p = 12
-    out0 = kpsvd.block_egkb(lambda X: B @ X, lambda X: B.T @ X, Y, k=10, p=2)
-    assert out0["k"] == 10 and out0["kp"] == 12
-    # the fired run is exact on the leading part: B has the Ritz values of its
-    # Krylov space, which for these decoupled bidiagonals are sigma of the
-    # leading 6 x 6 (+1 row) sections of B1 and B2
+    block J holds the columns with alpha = a1[J-1], a2[J-1] and t = 1, and its
+    zeta is sqrt(a1 a2) = (1, .5, .3, .2, .4, ...) by construction. Then
+    nu_{J+1} = sqrt(zeta_J zeta_{J-1}) = .707, .387, .245, .283: the first rise
+    is nu_6 > nu_5, at block 5, so k = 10, k_p = 12 -> 6 blocks of 2."""
+    zb = np.array([1.0, 0.5, 0.3, 0.2, 0.4, 0.1, 0.05, 0.04, 0.03, 0.02])
+    f = np.array([1.2, 1.2, 0.8, 1.5, 0.9, 1.1, 1.0, 1.3, 0.7, 1.0])
+    a1, a2 = zb * f, zb / f
+    B1 = _bidiag(a1, [1.0] * 11)
+    B2 = _bidiag(a2, [1.0] * 11)
+    B = np.zeros((22, 20))
+    B[:11, :10] = B1
+    B[11:, 10:] = B2
+    Y = np.zeros((22, 2))
+    Y[0, 0] = Y[11, 1] = 1.0
+    R, Rt = (lambda X: B @ X), (lambda X: B.T @ X)
+    out = kpsvd.block_egkb(R, Rt, Y, k=12, p=2, auto_k=True)
+    assert out["k"] == 10 and out["kp"] == 12
+    assert np.allclose([out["zeta"][J] for J in range(1, 6)], zb[:5], rtol=1e-14)
+    # without the rule the same run keeps k = 12, k_p = 14
+    out0 = kpsvd.block_egkb(R, Rt, Y, k=12, p=2)
+    assert out0["k"] == 12 and out0["kp"] == 14
+    # a tau above nu_3 = .707 fires at block 3 (the test at block 2 compares
+    # nu_2 = +inf), so k = 6, k_p = 8
+    out1 = kpsvd.block_egkb(R, Rt, Y, k=12, p=2, auto_k=True, tau=0.8)
+    assert out1["k"] == 6 and out1["kp"] == 8
+    # k_min = 10 postpones the test to blocks with J b > 10: none rises there
+    # (zeta = .1, .05, ...), so k stays 12
+    out2 = kpsvd.block_egkb(R, Rt, Y, k=12, p=2, auto_k=True, k_min=10)
+    assert out2["k"] == 12
+    # Ritz values: the decoupled Krylov spaces of the fired run are the leading
+    # 6 x 7 sections of B1 and B2
     s1 = np.linalg.svd(B1[:7, :6], compute_uv=False)
     s2 = np.linalg.svd(B2[:7, :6], compute_uv=False)
-    assert np.allclose(np.sort(out["sigma_all"])[::-1][:9],
-                       np.sort(np.concatenate([s1, s2]))[::-1][:9], rtol=1e-12)
+    assert np.allclose(out["sigma_all"], np.sort(np.concatenate([s1, s2]))[::-1], rtol=1e-12)
