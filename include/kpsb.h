@@ -84,6 +84,17 @@ typedef struct {
   int32_t pu, pv, cu, cv;
   int32_t psf_on_device;
   int32_t bc;           /* kp_bc */
+  int32_t compact;      /* 1: the block products skip the tiles of R(A) that lie
+                           outside the rows and columns its PSF grid (in the
+                           working precision) can reach: an all-zero row tile is
+                           written as zeros, and only the K tiles whose offsets
+                           meet the PSF's support are multiplied. Every skipped
+                           product is an exact zero, so the result equals the
+                           dense product for finite X (up to the sign of zero).
+                           Applies to the FP32/FP64 block products and the FP32
+                           matrix-vector product (the 16-bit and FP64
+                           matrix-vector kernels stay dense). 0: the dense
+                           product (the paper's cost model).                  */
 } kp_blur;
 
 /* Enlarged Golub-Kahan bidiagonalization (paper, Algorithm 1). */

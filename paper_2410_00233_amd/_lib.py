@@ -36,7 +36,7 @@ EXPORTED = ["kp_ctx_create", "kp_ctx_destroy", "kp_last_error", "kp_version",
 class kp_blur(C.Structure):
     _fields_ = [("n", C.c_int32), ("psf", C.POINTER(C.c_double)), ("pu", C.c_int32),
                 ("pv", C.c_int32), ("cu", C.c_int32), ("cv", C.c_int32),
-                ("psf_on_device", C.c_int32), ("bc", C.c_int32)]
+                ("psf_on_device", C.c_int32), ("bc", C.c_int32), ("compact", C.c_int32)]
 
 
 class kp_gkb_opts(C.Structure):

@@ -46,10 +46,11 @@ class Blur:
     P is a NumPy array (host) or, with on_device=True, copied once into a device
     tensor so that calls read it from HBM."""
 
-    def __init__(self, P, cu, cv, n, on_device=False, bc="zero"):
+    def __init__(self, P, cu, cv, n, on_device=False, bc="zero", compact=False):
         self.P = np.ascontiguousarray(P, dtype=np.float64)
         self.cu, self.cv, self.n = int(cu), int(cv), int(n)
         self.bc = bc
+        self.compact = bool(compact)
         self.on_device = bool(on_device)
         if on_device:
             torch = _torch()
@@ -58,15 +59,17 @@ class Blur:
         else:
             ptr = self.P.ctypes.data_as(C.POINTER(C.c_double))
         self.s = L.kp_blur(self.n, ptr, self.P.shape[0], self.P.shape[1], self.cu, self.cv,
-                           int(on_device), BC[bc])
+                           int(on_device), BC[bc], int(compact))
 
-    def with_bc(self, bc):
-        """The same PSF (sharing its memory) with other boundary conditions."""
+    def with_bc(self, bc=None, compact=None):
+        """The same PSF (sharing its memory) with other boundary conditions
+        and/or another compaction setting."""
         other = Blur.__new__(Blur)
         other.__dict__.update(self.__dict__)
-        other.bc = bc
+        other.bc = self.bc if bc is None else bc
+        other.compact = self.compact if compact is None else bool(compact)
         other.s = L.kp_blur(self.s.n, self.s.psf, self.s.pu, self.s.pv, self.s.cu, self.s.cv,
-                            self.s.psf_on_device, BC[bc])
+                            self.s.psf_on_device, BC[other.bc], int(other.compact))
         return other
 
 

@@ -113,6 +113,7 @@ kp_status validate_blur(kp_ctx* c, const kp_blur* b) {
   if ((long)b->pu * b->pv > (1L << 26)) return set_err(c, KP_E_INVAL, "psf too large");
   if (b->psf_on_device != 0 && b->psf_on_device != 1)
     return set_err(c, KP_E_INVAL, "psf_on_device must be 0 or 1");
+  if (b->compact != 0 && b->compact != 1) return set_err(c, KP_E_INVAL, "compact must be 0 or 1");
   if (b->bc != KP_BC_ZERO && b->bc != KP_BC_REFLEXIVE && b->bc != KP_BC_PERIODIC)
     return set_err(c, KP_E_INVAL, "bc must be KP_BC_ZERO, KP_BC_REFLEXIVE or KP_BC_PERIODIC");
   if (b->bc != KP_BC_ZERO) {
@@ -196,10 +197,15 @@ struct Grids {
   RmatTerms terms;
   T* Gs[4] = {nullptr, nullptr, nullptr, nullptr};    // grid of term t
   T* Gts[4] = {nullptr, nullptr, nullptr, nullptr};   // its transpose
+  // support boxes of Gs[t] / Gts[t] (device; null: dense products)
+  int* box[4] = {nullptr, nullptr, nullptr, nullptr};
+  int* boxt[4] = {nullptr, nullptr, nullptr, nullptr};
   Grids term(int t) const {
     Grids g;
     g.G = g.Gs[0] = Gs[t];
     g.Gt = g.Gts[0] = Gts[t];
+    g.box[0] = box[t];
+    g.boxt[0] = boxt[t];
     g.ldg = ldg;
     return g;
   }
@@ -241,6 +247,14 @@ kp_status build_grids(kp_ctx* c, const kp_blur* b, const double* dpsf, hipStream
                          g->ldg, s);
     launch_build_grid<T>(dpsf, b->pu, b->pv, b->cu, b->cv, n, 1, g->terms.sh[t], g->Gts[t],
                          g->ldg, s);
+    if (b->compact) {
+      int* part = nullptr;
+      KP_TRY(wsT(c, "gbox_part", (size_t)grid_box_parts(), &part));
+      KP_TRY(wsT(c, "gbox_" + sfx, 8, &g->box[t]));
+      g->boxt[t] = g->box[t] + 4;
+      launch_grid_box<T>(g->Gs[t], g->ldg, n, part, g->box[t], s);
+      launch_grid_box<T>(g->Gts[t], g->ldg, n, part, g->boxt[t], s);
+    }
   }
   g->G = g->Gs[0];
   g->Gt = g->Gts[0];
@@ -348,7 +362,7 @@ kp_status block_product1(kp_ctx* c, const Grids<T>& g, int n, int transpose, con
     const int nc = ncols - c0 < 32 ? ncols - c0 : 32;
     ProfScope ps(c, s, 0, 2.0 * (double)N * (double)N * nc);
     launch_rmat_block<T>(bp, transpose ? g.Gt : g.G, g.ldg, n, X + N * c0, N, Y + N * c0, N,
-                         nc, s);
+                         nc, s, transpose ? g.boxt[0] : g.box[0]);
   }
   return check_launch(c, "rmat_block");
 }
@@ -441,7 +455,8 @@ kp_status gemv_product1(kp_ctx* c, const Grids<T>& g, int n, int transpose, cons
     float* xt = nullptr;
     KP_TRY(wsT(c, "gemv_xt", (size_t)gemv_sx_xt_len(n), &xt));
     ProfScope ps(c, s, 1, 2.0 * NN * NN);
-    launch_rmat_gemv_sx(transpose ? g.Gt : g.G, g.ldg, n, x, xt, y, z, coef, s);
+    launch_rmat_gemv_sx(transpose ? g.Gt : g.G, g.ldg, n, x, xt, y, z, coef, s,
+                        transpose ? g.boxt[0] : g.box[0]);
     return check_launch(c, "rmat_gemv_sx");
   }
   BlockPlan gp;

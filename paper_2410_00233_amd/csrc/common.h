@@ -60,9 +60,17 @@ bool plan_block(int n, size_t lds_limit, BlockPlan* plan);
 // The plan with exactly TJ row blocks per workgroup (false if it cannot fit).
 template <typename T>
 bool plan_block_tj(int n, size_t lds_limit, int TJ, BlockPlan* plan);
+// box (device, optional): the support box of G from launch_grid_box; tiles
+// outside it are skipped (same result for finite X).
 template <typename T>
 void launch_rmat_block(const BlockPlan& plan, const T* G, int ldg, int n, const T* X,
-                       long ldx, T* Y, long ldy, int ncols, hipStream_t s);
+                       long ldx, T* Y, long ldy, int ncols, hipStream_t s,
+                       const int* box = nullptr);
+// box = {a_lo, a_hi, b_lo, b_hi}: the rows and columns of G holding its nonzero
+// entries (a_lo > a_hi for an all-zero grid); part: grid_box_parts() ints.
+template <typename T>
+void launch_grid_box(const T* G, int ldg, int n, int* part, int* box, hipStream_t s);
+int grid_box_parts();
 
 // 16-bit-input variant (H = __hip_bfloat16 or __half): 16-bit grid and X,
 // FP32 accumulation, FP32 output. X16 is the pre-shifted 16-bit copy made by
@@ -105,7 +113,7 @@ inline int grid_ld(int n) { return ((2 * n - 1 + 48) + 7) & ~7; }
 // gemv_sx_xt_len(n) floats. G must have the row stride grid_ld(n).
 long gemv_sx_xt_len(int n);
 void launch_rmat_gemv_sx(const float* G, int ldg, int n, const float* x, float* xt, float* y,
-                         const float* z, double coef, hipStream_t s);
+                         const float* z, double coef, hipStream_t s, const int* box = nullptr);
 
 template <typename T>
 bool plan_gemv(int n, size_t lds_limit, BlockPlan* plan);

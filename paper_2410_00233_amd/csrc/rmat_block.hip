@@ -18,6 +18,7 @@
 // holds column l%16 and, for item e = 0..3, row 4*(l/16) + e (FP32) or
 // row l/16 + 4*e (FP64).
 #include <algorithm>
+#include <climits>
 
 #include "common.h"
 
@@ -238,10 +239,17 @@ __device__ __forceinline__ doublex4 mfma16x16x4(double a, double b, doublex4 c) 
 constexpr int kTK = 64;   // K-tile (entries of r per staged X tile)
 constexpr int kXS = 48;   // LDS row stride of the staged X tile (bank-conflict free)
 
-template <typename T, int TJ, int JB, int CB>
+// box (optional, device): the rows [box[0], box[1]] and columns [box[2], box[3]]
+// of G that hold its nonzero entries. With it, a workgroup whose grid rows are
+// all outside writes zeros, and column block c visits only the K tiles whose
+// grid columns r - c + n - 1 meet the box; every skipped product is an exact
+// zero, so the result equals the dense one (for finite X, up to the sign of
+// zero). Without it every tile of R is multiplied.
+template <typename T, int TJ, int JB, int CB, bool CMP>
 __global__ void __launch_bounds__(64 * (2 * TJ) / (JB * CB))
 rmat_block_kernel(const T* __restrict__ G, int ldg, int n, const T* __restrict__ X, long ldx,
-                  T* __restrict__ Y, long ldy, int ncols, int SW, int CP) {
+                  T* __restrict__ Y, long ldy, int ncols, int SW, int CP,
+                  const int* __restrict__ box) {
   constexpr int WAVES = (2 * TJ) / (JB * CB);
   constexpr int NT = 64 * WAVES;
   constexpr int SR = 16 + TJ - 1;
@@ -264,6 +272,19 @@ rmat_block_kernel(const T* __restrict__ G, int ldg, int n, const T* __restrict__
   const int g2 = 2 * n - 1;
   const int a0 = i0 - j0 - (TJ - 1) + n - 1;
 
+  // grid columns that hold nonzeros (all of them without a box), and the
+  // column blocks c whose r range [0, n) reaches them
+  int bl = 0, bh = g2 - 1;
+  bool active = true;
+  if (CMP) {
+    bl = box[2];
+    bh = box[3];
+    active = box[0] <= box[1] && bl <= bh && a0 <= box[1] && a0 + SR - 1 >= box[0];
+  }
+  const int c_lo = max(0, n - 1 - bh);
+  const int c_hi = min(n - 1, 2 * n - 2 - bl);
+  active = active && c_lo <= c_hi;
+
   // ---- slab: grid rows a0 .. a0 + SR - 1, zero outside the grid. Column
   // blocks c are processed in phases of CP; a phase needs the slab columns
   // [n - c0 - CP, n - c0 - CP + SW) only (all of them when CP = n).
@@ -281,17 +302,17 @@ rmat_block_kernel(const T* __restrict__ G, int ldg, int n, const T* __restrict__
       }
     }
   };
-  load_slab(0);
-
   const int nrc = (n + kTK - 1) / kTK;       // r-chunks per column block c
-  const int total = n * nrc;
+  // K tiles of column block c that meet the box: r in [max(0, bl - n + 1 + c),
+  // min(n - 1, bh - n + 1 + c)] (all nrc tiles without a box)
+  auto rt_lo = [&](int c) { return max(0, bl - n + 1 + c) / kTK; };
+  auto rt_hi = [&](int c) { return min(n - 1, bh - n + 1 + c) / kTK; };
 
   // staged X element e = tid + NT*m: col = e % 32, kk = e / 32 (a wave writes
   // whole rows of the staged tile: no LDS bank conflicts on the stores)
   T stage[LPT];
-  auto load_tile = [&](int t) {
-    const int c = t / nrc;
-    const int r0 = (t - c * nrc) * kTK;
+  auto load_tile = [&](int c, int rt) {
+    const int r0 = rt * kTK;
 #pragma unroll
     for (int m = 0; m < LPT; ++m) {
       const int e = tid + NT * m;
@@ -333,21 +354,73 @@ rmat_block_kernel(const T* __restrict__ G, int ldg, int n, const T* __restrict__
 #pragma unroll
   for (int jb = 0; jb < JB; ++jb) arow[jb] = (lrow + (TJ - 1) - (wj * JB + jb)) * SW;
 
-  load_tile(0);
-  store_tile(0);
-  __syncthreads();
-
-  for (int c = 0; c < n; ++c) {
-    if (c > 0 && c % CP == 0) {     // next phase: every wave is past the last tile's barrier
-      load_slab(c);
-      __syncthreads();
+  if constexpr (!CMP) {
+    // dense: every column block c and every K tile of it, in order
+    load_slab(0);
+    load_tile(0, 0);
+    store_tile(0);
+    __syncthreads();
+    for (int c = 0; c < n; ++c) {
+      if (c > 0 && c % CP == 0) {   // next phase: every wave is past the last tile's barrier
+        load_slab(c);
+        __syncthreads();
+      }
+      const int c0 = c - c % CP;
+      for (int rt = 0; rt < nrc; ++rt) {
+        const int t = c * nrc + rt;
+        const bool more = t + 1 < n * nrc;
+        if (more) load_tile(rt + 1 < nrc ? c : c + 1, rt + 1 < nrc ? rt + 1 : 0);
+        const int colbase = rt * kTK - c + c0 + CP - 1;   // slab column of r = rt * kTK
+        const T* xs = xbuf + (t & 1) * (kTK * kXS);
+#pragma unroll
+        for (int s = 0; s < kTK / 4; ++s) {
+          const int kk = 4 * s + lk;
+          T bfr[CB];
+#pragma unroll
+          for (int cb = 0; cb < CB; ++cb) bfr[cb] = xs[kk * kXS + (wc * CB + cb) * 16 + lrow];
+          T afr[JB];
+#pragma unroll
+          for (int jb = 0; jb < JB; ++jb) afr[jb] = slab[arow[jb] + colbase + kk];
+#pragma unroll
+          for (int jb = 0; jb < JB; ++jb)
+#pragma unroll
+            for (int cb = 0; cb < CB; ++cb)
+              acc[jb][cb] = mfma16x16x4(afr[jb], bfr[cb], acc[jb][cb]);
+        }
+        if (more) store_tile((t + 1) & 1);
+        __syncthreads();
+      }
+      if (sizeof(T) == 4) {   // end of column block c: fold into the FP64 accumulators
+#pragma unroll
+        for (int jb = 0; jb < JB; ++jb)
+#pragma unroll
+          for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+              accd[jb][cb][e] += (double)acc[jb][cb][e];
+              acc[jb][cb][e] = (T)0;
+            }
+      }
     }
-    const int c0 = c - c % CP;
-    for (int rt = 0; rt < nrc; ++rt) {
-      const int t = c * nrc + rt;
-      if (t + 1 < total) load_tile(t + 1);
+  } else if (active) {   // uniform over the workgroup: every barrier below is reached by all
+    load_slab(c_lo - c_lo % CP);
+    int c = c_lo, rt = rt_lo(c_lo);
+    load_tile(c, rt);
+    store_tile(0);
+    __syncthreads();
+
+    for (int q = 0;; ++q) {
+      // the next tile: the next r chunk of c, else the first of c + 1
+      int cn = c, rtn = rt + 1;
+      if (rtn > rt_hi(c)) {
+        cn = c + 1;
+        rtn = cn <= c_hi ? rt_lo(cn) : 0;
+      }
+      const bool more = cn <= c_hi;
+      if (more) load_tile(cn, rtn);
+      const int c0 = c - c % CP;
       const int colbase = rt * kTK - c + c0 + CP - 1;   // slab column of r = rt * kTK
-      const T* xs = xbuf + (t & 1) * (kTK * kXS);
+      const T* xs = xbuf + (q & 1) * (kTK * kXS);
 #pragma unroll
       for (int s = 0; s < kTK / 4; ++s) {
         const int kk = 4 * s + lk;
@@ -362,19 +435,28 @@ rmat_block_kernel(const T* __restrict__ G, int ldg, int n, const T* __restrict__
 #pragma unroll
           for (int cb = 0; cb < CB; ++cb) acc[jb][cb] = mfma16x16x4(afr[jb], bfr[cb], acc[jb][cb]);
       }
-      if (t + 1 < total) store_tile((t + 1) & 1);
+      if (more) store_tile((q + 1) & 1);
       __syncthreads();
-    }
-    if (sizeof(T) == 4) {   // end of column block c: fold into the FP64 accumulators
+      if (cn != c) {
+        if (sizeof(T) == 4) {   // end of column block c: fold into the FP64 accumulators
 #pragma unroll
-      for (int jb = 0; jb < JB; ++jb)
+          for (int jb = 0; jb < JB; ++jb)
 #pragma unroll
-        for (int cb = 0; cb < CB; ++cb)
+            for (int cb = 0; cb < CB; ++cb)
 #pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            accd[jb][cb][e] += (double)acc[jb][cb][e];
-            acc[jb][cb][e] = (T)0;
-          }
+              for (int e = 0; e < 4; ++e) {
+                accd[jb][cb][e] += (double)acc[jb][cb][e];
+                acc[jb][cb][e] = (T)0;
+              }
+        }
+        if (!more) break;
+        if (cn % CP == 0) {   // next phase: every wave is past the last tile's barrier
+          load_slab(cn);
+          __syncthreads();
+        }
+      }
+      c = cn;
+      rt = rtn;
     }
   }
 
@@ -452,41 +534,109 @@ template bool plan_block_tj<double>(int, size_t, int, BlockPlan*);
 
 template <typename T, int TJ, int JB, int CB>
 static void launch_tj(const BlockPlan& p, const T* G, int ldg, int n, const T* X, long ldx,
-                      T* Y, long ldy, int ncols, hipStream_t s) {
-  auto kern = rmat_block_kernel<T, TJ, JB, CB>;
+                      T* Y, long ldy, int ncols, hipStream_t s, const int* box) {
+  auto kern = box ? rmat_block_kernel<T, TJ, JB, CB, true> : rmat_block_kernel<T, TJ, JB, CB, false>;
   constexpr int threads = 64 * (2 * TJ) / (JB * CB);
   if (p.lds > 65536)
     (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)p.lds);
   const int grid = p.grid_limit > 0 && p.grid_limit < p.grid ? p.grid_limit : p.grid;
   hipLaunchKernelGGL(kern, dim3(grid), dim3(threads), p.lds, s, G, ldg, n, X, ldx, Y, ldy,
-                     ncols, p.SW, p.CP);
+                     ncols, p.SW, p.CP, box);
 }
 
 template <typename T>
 void launch_rmat_block(const BlockPlan& p, const T* G, int ldg, int n, const T* X, long ldx,
-                       T* Y, long ldy, int ncols, hipStream_t s) {
+                       T* Y, long ldy, int ncols, hipStream_t s, const int* box) {
   // waves per workgroup: TJ = 16 -> 16 (JB = 1) or 8 (JB = 2); TJ = 8 -> 8 (CB = 2)
   // or 16 (CB = 1); chosen by the autotuner, 16 and 8 by default
   if (p.TJ == 16 && p.waves == 8) {
-    launch_tj<T, 16, 2, 2>(p, G, ldg, n, X, ldx, Y, ldy, ncols, s);
+    launch_tj<T, 16, 2, 2>(p, G, ldg, n, X, ldx, Y, ldy, ncols, s, box);
     return;
   }
   if (p.TJ == 8 && p.waves == 16) {
-    launch_tj<T, 8, 1, 1>(p, G, ldg, n, X, ldx, Y, ldy, ncols, s);
+    launch_tj<T, 8, 1, 1>(p, G, ldg, n, X, ldx, Y, ldy, ncols, s, box);
     return;
   }
   switch (p.TJ) {
-    case 16: launch_tj<T, 16, 1, 2>(p, G, ldg, n, X, ldx, Y, ldy, ncols, s); break;
-    case 8: launch_tj<T, 8, 1, 2>(p, G, ldg, n, X, ldx, Y, ldy, ncols, s); break;
-    case 4: launch_tj<T, 4, 1, 2>(p, G, ldg, n, X, ldx, Y, ldy, ncols, s); break;
-    case 2: launch_tj<T, 2, 1, 1>(p, G, ldg, n, X, ldx, Y, ldy, ncols, s); break;
-    default: launch_tj<T, 1, 1, 1>(p, G, ldg, n, X, ldx, Y, ldy, ncols, s); break;
+    case 16: launch_tj<T, 16, 1, 2>(p, G, ldg, n, X, ldx, Y, ldy, ncols, s, box); break;
+    case 8: launch_tj<T, 8, 1, 2>(p, G, ldg, n, X, ldx, Y, ldy, ncols, s, box); break;
+    case 4: launch_tj<T, 4, 1, 2>(p, G, ldg, n, X, ldx, Y, ldy, ncols, s, box); break;
+    case 2: launch_tj<T, 2, 1, 1>(p, G, ldg, n, X, ldx, Y, ldy, ncols, s, box); break;
+    default: launch_tj<T, 1, 1, 1>(p, G, ldg, n, X, ldx, Y, ldy, ncols, s, box); break;
   }
 }
 template void launch_rmat_block<float>(const BlockPlan&, const float*, int, int, const float*,
-                                       long, float*, long, int, hipStream_t);
+                                       long, float*, long, int, hipStream_t, const int*);
 template void launch_rmat_block<double>(const BlockPlan&, const double*, int, int,
-                                        const double*, long, double*, long, int, hipStream_t);
+                                        const double*, long, double*, long, int, hipStream_t,
+                                        const int*);
+
+// Rows and columns of a grid that hold nonzero entries (support box for the
+// block kernel): partial boxes of kBoxBlocks workgroups, then one reduction.
+// box = {a_lo, a_hi, b_lo, b_hi}; an all-zero grid gives a_lo > a_hi.
+constexpr int kBoxBlocks = 64;
+template <typename T>
+__global__ void grid_box_partial_kernel(const T* __restrict__ G, int ldg, int n,
+                                        int* __restrict__ part) {
+  const int g2 = 2 * n - 1;
+  int alo = INT_MAX, ahi = -1, blo = INT_MAX, bhi = -1;
+  for (int a = blockIdx.x; a < g2; a += gridDim.x) {
+    const T* row = G + (long)a * ldg;
+    for (int b = threadIdx.x; b < g2; b += blockDim.x) {
+      if ((double)row[b] != 0.0) {
+        alo = min(alo, a);
+        ahi = max(ahi, a);
+        blo = min(blo, b);
+        bhi = max(bhi, b);
+      }
+    }
+  }
+  __shared__ int sh[4][256];
+  sh[0][threadIdx.x] = alo;
+  sh[1][threadIdx.x] = ahi;
+  sh[2][threadIdx.x] = blo;
+  sh[3][threadIdx.x] = bhi;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      sh[0][threadIdx.x] = min(sh[0][threadIdx.x], sh[0][threadIdx.x + w]);
+      sh[1][threadIdx.x] = max(sh[1][threadIdx.x], sh[1][threadIdx.x + w]);
+      sh[2][threadIdx.x] = min(sh[2][threadIdx.x], sh[2][threadIdx.x + w]);
+      sh[3][threadIdx.x] = max(sh[3][threadIdx.x], sh[3][threadIdx.x + w]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x < 4) part[blockIdx.x * 4 + threadIdx.x] = sh[threadIdx.x][0];
+}
+
+__global__ void grid_box_final_kernel(const int* __restrict__ part, int nparts,
+                                      int* __restrict__ box) {
+  if (threadIdx.x != 0) return;
+  int alo = INT_MAX, ahi = -1, blo = INT_MAX, bhi = -1;
+  for (int p = 0; p < nparts; ++p) {
+    alo = min(alo, part[4 * p]);
+    ahi = max(ahi, part[4 * p + 1]);
+    blo = min(blo, part[4 * p + 2]);
+    bhi = max(bhi, part[4 * p + 3]);
+  }
+  box[0] = alo;
+  box[1] = ahi;
+  box[2] = blo;
+  box[3] = bhi;
+}
+
+template <typename T>
+void launch_grid_box(const T* G, int ldg, int n, int* part, int* box, hipStream_t s) {
+  hipLaunchKernelGGL(grid_box_partial_kernel<T>, dim3(kBoxBlocks), dim3(256), 0, s, G, ldg, n,
+                     part);
+  hipLaunchKernelGGL(grid_box_final_kernel, dim3(1), dim3(64), 0, s, part, kBoxBlocks, box);
+}
+int grid_box_parts() { return kBoxBlocks * 4; }
+template void launch_grid_box<float>(const float*, int, int, int*, int*, hipStream_t);
+template void launch_grid_box<double>(const double*, int, int, int*, int*, hipStream_t);
+template void launch_grid_box<__hip_bfloat16>(const __hip_bfloat16*, int, int, int*, int*,
+                                              hipStream_t);
+template void launch_grid_box<__half>(const __half*, int, int, int*, int*, hipStream_t);
 
 }  // namespace kpsb

@@ -143,10 +143,18 @@ __global__ void gemv_xt_kernel(const float* __restrict__ x, int n, int U, int nc
 // kSxP rows per lane; kSxV waves own different rows (4 kSxP j values each) and
 // walk the same chunks at the same time (their x reads share the scalar cache);
 // kSxW waves per row set split the chunks (r-parts).
-template <int kSxP, int kSxV, int kSxW>
+//
+// CMP (with box = the support box of G, see launch_grid_box): a workgroup
+// whose grid rows all lie outside the box skips every chunk, and a chunk
+// visits only the aligned runs of 4 step groups whose grid columns
+// [r0 + 4g, r0 + 4g + 10] meet the box. The skipped products are exact zeros
+// and the FP32 partial sums keep their 8-step pairing, so the result equals
+// the dense one (finite x, up to the sign of zero).
+template <int kSxP, int kSxV, int kSxW, bool CMP>
 __global__ void __launch_bounds__(64 * kSxV * kSxW)
 rmat_gemv_sx_kernel(const float* __restrict__ G, int ldg, int n, const float* __restrict__ xt,
-                    int U, float* __restrict__ y, const float* __restrict__ z, double coef) {
+                    int U, float* __restrict__ y, const float* __restrict__ z, double coef,
+                    const int* __restrict__ box) {
   __shared__ double red[kSxW][kSxV][kSxP][64];
   const int lane = threadIdx.x & 63;
   const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -165,19 +173,40 @@ rmat_gemv_sx_kernel(const float* __restrict__ G, int ldg, int n, const float* __
   }
   const int nch = (n + kSxR - 1) / kSxR;
   const int ngrp = U / 4;                 // groups of 4 steps (multiple of 4)
+  int bl = 0, bh = 0;
+  bool active = true;
+  if (CMP) {
+    // grid rows of the workgroup: i in [16 it, 16 it + 15], j in [jw, jw + 4 kSxP kSxV - 1]
+    const int jw = jt * kSxV * 4 * kSxP;
+    const int amin = 16 * it - (jw + 4 * kSxP * kSxV - 1) + n - 1;
+    const int amax = 16 * it + 15 - jw + n - 1;
+    bl = box[2];
+    bh = box[3];
+    active = box[0] <= box[1] && bl <= bh && amin <= box[1] && amax >= box[0];
+  }
   double acc[kSxP];
 #pragma unroll
   for (int p = 0; p < kSxP; ++p) acc[p] = 0.0;
-  for (int ch = wave; ch < nch; ch += kSxW) {
+  for (int ch = wave; active && ch < nch; ch += kSxW) {
     const int r0 = ch * kSxR;
+    int gbeg = 0, gend = ngrp;            // runs of 4 groups [gbeg, gend)
+    if (CMP) {
+      const int lo = bl - r0 - 10;          // 4 g >= lo  and  4 g <= bh - r0
+      const int glo = lo <= 0 ? 0 : (lo + 3) / 4;
+      const int ghi = bh - r0 < 0 ? -1 : (bh - r0) / 4;
+      gbeg = (glo / 4) * 4;
+      gend = min(ngrp, (ghi / 4) * 4 + 4);
+      if (ghi < 0 || glo >= ngrp || gbeg >= gend) continue;
+    }
     const float* xp = xt + (long)ch * U * kSxR;
     float4 S[kSxP][4];
 #pragma unroll
     for (int p = 0; p < kSxP; ++p)
 #pragma unroll
-      for (int t = 0; t < 3; ++t) S[p][t] = *reinterpret_cast<const float4*>(grow[p] + r0 + 4 * t);
+      for (int t = 0; t < 3; ++t)
+        S[p][t] = *reinterpret_cast<const float4*>(grow[p] + r0 + 4 * (gbeg + t));
     float pp[kSxP];
-    for (int g0 = 0; g0 < ngrp; g0 += 4) {
+    for (int g0 = gbeg; g0 < gend; g0 += 4) {
 #pragma unroll
       for (int gg = 0; gg < 4; ++gg) {
         const int g = g0 + gg;
@@ -234,7 +263,7 @@ int gemv_sx_steps(int n) { return ((n + 15) / 16) * 16; }
 long gemv_sx_xt_len(int n) { return (long)((n + kSxR - 1) / kSxR) * gemv_sx_steps(n) * kSxR; }
 
 void launch_rmat_gemv_sx(const float* G, int ldg, int n, const float* x, float* xt, float* y,
-                         const float* z, double coef, hipStream_t s) {
+                         const float* z, double coef, hipStream_t s, const int* box) {
   const int U = gemv_sx_steps(n);
   const int nch = (n + kSxR - 1) / kSxR;
   const long tot = gemv_sx_xt_len(n);
@@ -245,8 +274,12 @@ void launch_rmat_gemv_sx(const float* G, int ldg, int n, const float* x, float* 
   // measured (rows per lane 1-8, row-sharing waves 1-8, r-parts 1-16)
   constexpr int P = 1, V = 1, W = 8;
   const int grid = ((n + 15) / 16) * ((n + 4 * P * V - 1) / (4 * P * V));
-  hipLaunchKernelGGL((rmat_gemv_sx_kernel<P, V, W>), dim3(grid), dim3(64 * V * W), 0, s, G, ldg,
-                     n, xt, U, y, z, coef);
+  if (box)
+    hipLaunchKernelGGL((rmat_gemv_sx_kernel<P, V, W, true>), dim3(grid), dim3(64 * V * W), 0, s,
+                       G, ldg, n, xt, U, y, z, coef, box);
+  else
+    hipLaunchKernelGGL((rmat_gemv_sx_kernel<P, V, W, false>), dim3(grid), dim3(64 * V * W), 0, s,
+                       G, ldg, n, xt, U, y, z, coef, box);
 }
 
 template <typename T>

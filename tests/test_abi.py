@@ -70,7 +70,7 @@ LAYOUT_C = r"""
 #define P(T, f) printf(#T "." #f " %zu\n", offsetof(T, f))
 #define S(T) printf(#T " %zu\n", sizeof(T))
 int main(void) {
-  S(kp_blur); P(kp_blur, psf); P(kp_blur, cv); P(kp_blur, psf_on_device); P(kp_blur, bc);
+  S(kp_blur); P(kp_blur, psf); P(kp_blur, cv); P(kp_blur, psf_on_device); P(kp_blur, bc); P(kp_blur, compact);
   S(kp_gkb_opts); P(kp_gkb_opts, tau); P(kp_gkb_opts, prec); P(kp_gkb_opts, seed); P(kp_gkb_opts, y0); P(kp_gkb_opts, bd_rel); P(kp_gkb_opts, block);
   S(kp_rsvd_opts); P(kp_rsvd_opts, prec); P(kp_rsvd_opts, seed); P(kp_rsvd_opts, F);
   S(kp_diag); P(kp_diag, alpha); P(kp_diag, kp); P(kp_diag, break_side); P(kp_diag, ms_total); P(kp_diag, basis_v);
