@@ -37,10 +37,10 @@ MFMA_FP32_PEAK_TFLOPS = 157.3     # MI355X dense FP32 matrix peak
 # (profiles/rmat_products_n512_hbm_counters.md), valid while the kernel source
 # is the one the counters were taken on.
 BLOCK_TRAFFIC_BYTES = 1.110e9
-BLOCK_TRAFFIC_SRC_SHA1 = "9e9452d8bf8baab4b0a5fcbce0b7173d6ed4a848"
+BLOCK_TRAFFIC_SRC_SHA1 = "8730805467c4d875fb2ddd5cc651507a0b63f037"
 BLOCK16_TRAFFIC_BYTES = 3.23e8
 # template arguments <TJ, JB, CB> of the FP32 block kernel per autotuner variant
-BLOCK_VARIANT_TEMPLATE = {0: "16,1,2", 1: "16,2,2", 2: "8,1,2", 3: "8,1,1"}
+BLOCK_VARIANT_TEMPLATE = {0: "16,1,2,false", 1: "16,2,2,false", 2: "8,1,2,false", 3: "8,1,1,false"}
 BLOCK16_VARIANT_TEMPLATE = {0: "32,4,2", 1: "16,4,2"}
 BLOCK16_TRAFFIC_SRC_SHA1 = "4e421df2669a63a3f8c5b9481e7943524a84e512"
 
@@ -149,9 +149,10 @@ def bench_paper_pipeline(ctx, n=128):
     import workloads as wl
     from paper_2410_00233_amd import api
     P, cu, cv = wl.speckle_psf(8, seed=wl.SEED_PSF + 900)      # 15 x 15 support
-    blur = api.Blur(P, cu, cv, n, on_device=True)
+    blur = api.Blur(P, cu, cv, n, on_device=True, bc="reflexive")
     out = {"workload": f"n={n}, reflexive BC, 15x15 speckle-like PSF, rank 8 (p=4), "
-                       "R(A) stored in HBM (FP32 for the KP-SVD, FP64 A for SB)"}
+                       "R(A) stored in HBM (FP32 for the KP-SVD, FP64 A for SB); the "
+                       "KP-SVDs also with R(A) generated from the PSF"}
 
     def timed(fn):
         torch.cuda.synchronize()
@@ -160,7 +161,7 @@ def bench_paper_pipeline(ctx, n=128):
         torch.cuda.synchronize()
         return r, 1e3 * (time.perf_counter() - t0)
 
-    A32, out["build_A_ms"] = timed(lambda: ctx.kp_blur_matrix(blur, bc="reflexive", prec="f32"))
+    A32, out["build_A_ms"] = timed(lambda: ctx.kp_blur_matrix(blur, prec="f32"))
     R32, _ = timed(lambda: ctx.kp_rmat_reorder(n, A32))
     R32, out["reorder_ms"] = timed(lambda: ctx.kp_rmat_reorder(n, A32, R=R32))
     ctx.kp_svd_gkb(None, 8, 4, prec="f32", seed=1, stored=(n, R32))
@@ -171,8 +172,19 @@ def bench_paper_pipeline(ctx, n=128):
                                                            stored=(n, R32)))
     out["sigma_egkb_vs_rsvd_max_diff_over_sigma1"] = float(
         np.abs(fg.sigma[:8] - fr.sigma[:8]).max() / fr.sigma[0])
+    # the same KP-SVDs with R(A) generated from the PSF (reflexive terms; no A,
+    # no reorder, no stored R)
+    ctx.kp_svd_gkb(blur, 8, 4, prec="f32", seed=1)
+    fgg, out["egkb_sp_generated_ms"] = timed(lambda: ctx.kp_svd_gkb(blur, 8, 4, prec="f32",
+                                                                     seed=1))
+    ctx.kp_svd_rsvd(blur, 8, 4, 1, prec="f32", seed=2)
+    frg, out["rsvd_sp_generated_ms"] = timed(lambda: ctx.kp_svd_rsvd(blur, 8, 4, 1, prec="f32",
+                                                                      seed=2))
+    out["sigma_generated_vs_stored_max_diff_over_sigma1"] = float(max(
+        np.abs(fgg.sigma[:8] - fg.sigma[:8]).max(), np.abs(frg.sigma[:8] - fr.sigma[:8]).max())
+        / fr.sigma[0])
     del A32, R32
-    A64 = ctx.kp_blur_matrix(blur, bc="reflexive", prec="f64")
+    A64 = ctx.kp_blur_matrix(blur, prec="f64")
     x_true = wl.rectangles_image(n, seed=wl.SEED_IMAGE + 900)
     xv = torch.tensor(x_true.flatten(order="F"), dtype=torch.float64, device="cuda")
     bv = ctx.kp_rmat_apply_stored(n, A64, xv).cpu().numpy()
@@ -397,6 +409,39 @@ def main():
     blk_ms = float(np.median(tblk))
     blk_diff = float(np.abs(fblk.sigma[:k] - fg.sigma[:k]).max() / fg.sigma[0])
 
+    log("reflexive boundary conditions (four generated terms)")
+    blur_r = blur.with_bc("reflexive")
+    ctx.kp_svd_rsvd(blur_r, k, p_rsvd, q, prec="f32", seed=2, factor_prec="f64")
+    trf = []
+    for _ in range(max(1, args.steps // 2)):
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        frr = ctx.kp_svd_rsvd(blur_r, k, p_rsvd, q, prec="f32", seed=2, factor_prec="f64")
+        trf.append(1e3 * (time.perf_counter() - ta))
+    refl_ms = float(np.median(trf))
+    refl_diff = float(np.abs(frr.sigma[:k] - fr.sigma[:k]).max() / fr.sigma[0])
+
+    log("support compaction (same results, zero tiles skipped)")
+    blur_c = blur.with_bc(compact=True)
+    ctx.kp_svd_rsvd(blur_c, k, p_rsvd, q, prec="f32", seed=2, factor_prec="f64")
+    tcp = []
+    for _ in range(args.steps):
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        frc = ctx.kp_svd_rsvd(blur_c, k, p_rsvd, q, prec="f32", seed=2, factor_prec="f64")
+        tcp.append(1e3 * (time.perf_counter() - ta))
+    comp_ms = float(np.median(tcp))
+    comp_same = bool(np.array_equal(frc.sigma[:k], fr.sigma[:k]))
+    ctx.kp_svd_gkb(blur_c, k, p_gkb, prec="f32", reorth=1, seed=1, factor_prec="f64")
+    tcg = []
+    for _ in range(args.steps):
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        fgc = ctx.kp_svd_gkb(blur_c, k, p_gkb, prec="f32", reorth=1, seed=1, factor_prec="f64")
+        tcg.append(1e3 * (time.perf_counter() - ta))
+    compg_ms = float(np.median(tcg))
+    compg_same = bool(np.array_equal(fgc.sigma[:k], fg.sigma[:k]))
+
     log("BF16 + refinement RSVD")
     # the reduced-precision variant: RSVD with BF16 block products + refinement
     # (refine = 2: the refinement product from split FP16 MFMA products; the
@@ -490,6 +535,16 @@ def main():
             "egkb_block_speedup_vs_egkb": round(float(np.median(comp["egkb_ms"])) / blk_ms, 3),
             "egkb_block_breakdowns": len(fblk.breakdowns),
             "egkb_block_max_sigma_diff_vs_egkb_over_sigma1": blk_diff,
+            "rsvd_compact_ms": round(comp_ms, 3),
+            "rsvd_compact_speedup_vs_dense": round(float(np.median(comp["rsvd_ms"])) / comp_ms, 3),
+            "rsvd_compact_sigma_bitwise_equal_to_dense": comp_same,
+            "egkb_compact_ms": round(compg_ms, 3),
+            "egkb_compact_speedup_vs_dense": round(float(np.median(comp["egkb_ms"])) / compg_ms, 3),
+            "egkb_compact_sigma_bitwise_equal_to_dense": compg_same,
+            "rsvd_reflexive_ms": round(refl_ms, 3),
+            "rsvd_reflexive_tflops_algorithmic": round(f_rsvd / (refl_ms * 1e-3) / 1e12, 3),
+            "rsvd_reflexive_tflops_executed": round(4 * f_rsvd / (refl_ms * 1e-3) / 1e12, 3),
+            "rsvd_reflexive_max_sigma_diff_vs_zero_bc_over_sigma1": refl_diff,
             "sigma_egkb_top3": [float(x) for x in fg.sigma[:3]],
             "sigma_rsvd_top3": [float(x) for x in fr.sigma[:3]],
             "rsvd_bf16_refine_ms": round(bf_ms, 3),
