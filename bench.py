@@ -40,7 +40,9 @@ BLOCK_TRAFFIC_BYTES = 1.110e9
 BLOCK_TRAFFIC_SRC_SHA1 = "8730805467c4d875fb2ddd5cc651507a0b63f037"
 BLOCK16_TRAFFIC_BYTES = 3.23e8
 # template arguments <TJ, JB, CB> of the FP32 block kernel per autotuner variant
-BLOCK_VARIANT_TEMPLATE = {0: "16,1,2,false", 1: "16,2,2,false", 2: "8,1,2,false", 3: "8,1,1,false"}
+BLOCK_VARIANT_TEMPLATE = {0: "16,1,2,false,64", 1: "16,2,2,false,64", 2: "8,1,2,false,64",
+                          3: "8,1,1,false,64", 4: "16,1,2,false,128", 5: "16,2,2,false,128",
+                          6: "8,1,2,false,128", 7: "8,1,1,false,128"}
 BLOCK16_VARIANT_TEMPLATE = {0: "32,4,2", 1: "16,4,2"}
 BLOCK16_TRAFFIC_SRC_SHA1 = "4e421df2669a63a3f8c5b9481e7943524a84e512"
 
@@ -326,8 +328,8 @@ def nonzero_fractions(P, cu, cv, n):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=512)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -339,6 +341,9 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=2.0,
                     help="offered Poisson arrival rate of the serving run (requests/s)")
     ap.add_argument("--serve-sizes", type=str, default="128,256,512,1024")
+    ap.add_argument("--serve-sweep", type=str, default="",
+                    help="comma-separated offered rates (req/s): run the serving workload at "
+                         "each (sizes 128,256,512; --serve requests each) and report them")
     ap.add_argument("--gkb-block", type=int, default=20,
                     help="block size b of the timed block Golub-Kahan run")
     ap.add_argument("--no-paper-pipeline", action="store_true",
@@ -522,6 +527,9 @@ def main():
             "rmat_nonzero_fractions_fp32": nz,
         },
         "components": {
+            "step_ms_p10": round(float(np.percentile(np.add(comp["egkb_ms"], comp["rsvd_ms"]), 10)), 3),
+            "step_ms_p50": round(float(np.percentile(np.add(comp["egkb_ms"], comp["rsvd_ms"]), 50)), 3),
+            "step_ms_p90": round(float(np.percentile(np.add(comp["egkb_ms"], comp["rsvd_ms"]), 90)), 3),
             "egkb_ms": round(float(np.median(comp["egkb_ms"])), 3),
             "rsvd_ms": round(float(np.median(comp["rsvd_ms"])), 3),
             "egkb_tflops": round(f_gkb / (np.median(comp["egkb_ms"]) * 1e-3) / 1e12, 3),
@@ -593,6 +601,17 @@ def main():
     if args.batched > 0:
         log(f"batched KP-SVD, {args.batched} problems")
         line["batched"] = bench_batched(ctx, args.batched)
+    if args.serve_sweep:
+        sweep = {}
+        for rate in [float(r) for r in args.serve_sweep.split(",") if r]:
+            log(f"serving sweep: {args.serve} requests at {rate}/s")
+            r_ = bench_serving(ctx, args.serve, rate, (128, 256, 512))
+            sweep[str(rate)] = {k_: r_[k_] for k_ in ("p50_ms", "p99_ms", "solves_per_s",
+                                                      "mean_queue_ms", "mean_solve_ms",
+                                                      "per_n_p50_ms", "all_ok")}
+        line["serving_sweep"] = {"workload": f"{args.serve} requests per rate, n in "
+                                             "[128, 256, 512] weighted [4, 3, 2], otherwise as "
+                                             "the serving run", "rates": sweep}
     if args.serve > 0:
         sizes = tuple(int(v) for v in args.serve_sizes.split(","))
         log(f"serving, {args.serve} requests at {args.serve_rate}/s")

@@ -322,18 +322,22 @@ struct ProfScope {
 // time of a sample launch (the first 1024 workgroups) per row of R it covers.
 constexpr int kSampleWG = 1024;
 struct BlockVariant {
-  int TJ, waves;
+  int TJ, waves, TK;
 };
-constexpr BlockVariant kBlockVariants[] = {{16, 16}, {16, 8}, {8, 8}, {8, 16}};
+constexpr BlockVariant kBlockVariants[] = {{16, 16, 64},  {16, 8, 64},  {8, 8, 64},  {8, 16, 64},
+                                           {16, 16, 128}, {16, 8, 128}, {8, 8, 128}, {8, 16, 128}};
+constexpr int kNumBlockVariants = 8;
 constexpr int kBlock16Variants[] = {32, 16};
 
 template <typename T>
 kp_status choose_block_plan(kp_ctx* c, const Grids<T>& g, int n, const T* X, T* Y, int nc,
                             hipStream_t s, BlockPlan* bp) {
   const long N = (long)n * n;
-  const int v = tune_pick(kTuneBlock, n, (int)sizeof(T), 0, 4, [&](int k) -> double {
+  const int v = tune_pick(kTuneBlock, n, (int)sizeof(T), 0, kNumBlockVariants,
+                          [&](int k) -> double {
     BlockPlan p;
-    if (!plan_block_tj<T>(n, c->lds_limit, kBlockVariants[k].TJ, &p)) return -1.0;
+    if (!plan_block_tj<T>(n, c->lds_limit, kBlockVariants[k].TJ, &p, kBlockVariants[k].TK))
+      return -1.0;
     p.waves = kBlockVariants[k].waves;
     p.grid_limit = std::min(p.grid, kSampleWG);
     const double ms = time_launches(s, 2, [&]() {
@@ -341,7 +345,7 @@ kp_status choose_block_plan(kp_ctx* c, const Grids<T>& g, int n, const T* X, T* 
     });
     return ms < 0 ? -1.0 : ms / ((double)std::min(p.grid, kSampleWG) * 16.0 * p.TJ);
   });
-  if (!plan_block_tj<T>(n, c->lds_limit, kBlockVariants[v].TJ, bp)) {
+  if (!plan_block_tj<T>(n, c->lds_limit, kBlockVariants[v].TJ, bp, kBlockVariants[v].TK)) {
     if (!plan_block<T>(n, c->lds_limit, bp))
       return set_err(c, KP_E_INVAL, "no block-product tiling fits the LDS at this n");
     return KP_OK;

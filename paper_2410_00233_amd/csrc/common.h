@@ -53,13 +53,14 @@ struct BlockPlan {
   size_t lds;  // dynamic LDS bytes
   int grid;    // workgroups
   int waves = 0;       // waves per workgroup (0: the default for TJ)
+  int TK = 64;         // K-tile entries (FP32/FP64 block product: 64 or 128)
   int grid_limit = 0;  // > 0: launch only the first grid_limit workgroups (tuning samples)
 };
 template <typename T>
 bool plan_block(int n, size_t lds_limit, BlockPlan* plan);
 // The plan with exactly TJ row blocks per workgroup (false if it cannot fit).
 template <typename T>
-bool plan_block_tj(int n, size_t lds_limit, int TJ, BlockPlan* plan);
+bool plan_block_tj(int n, size_t lds_limit, int TJ, BlockPlan* plan, int TK = 64);
 // box (device, optional): the support box of G from launch_grid_box; tiles
 // outside it are skipped (same result for finite X).
 template <typename T>

@@ -236,7 +236,7 @@ __device__ __forceinline__ doublex4 mfma16x16x4(double a, double b, doublex4 c) 
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
-constexpr int kTK = 64;   // K-tile (entries of r per staged X tile)
+constexpr int kTK = 64;   // default K-tile (entries of r per staged X tile); 128 also built
 constexpr int kXS = 48;   // LDS row stride of the staged X tile (bank-conflict free)
 
 // box (optional, device): the rows [box[0], box[1]] and columns [box[2], box[3]]
@@ -245,7 +245,7 @@ constexpr int kXS = 48;   // LDS row stride of the staged X tile (bank-conflict 
 // grid columns r - c + n - 1 meet the box; every skipped product is an exact
 // zero, so the result equals the dense one (for finite X, up to the sign of
 // zero). Without it every tile of R is multiplied.
-template <typename T, int TJ, int JB, int CB, bool CMP>
+template <typename T, int TJ, int JB, int CB, bool CMP, int KT>
 __global__ void __launch_bounds__(64 * (2 * TJ) / (JB * CB))
 rmat_block_kernel(const T* __restrict__ G, int ldg, int n, const T* __restrict__ X, long ldx,
                   T* __restrict__ Y, long ldy, int ncols, int SW, int CP,
@@ -254,12 +254,12 @@ rmat_block_kernel(const T* __restrict__ G, int ldg, int n, const T* __restrict__
   constexpr int NT = 64 * WAVES;
   constexpr int SR = 16 + TJ - 1;
   constexpr int WC = 2 / CB;                 // waves along the 32 output columns
-  constexpr int LPT = (kTK * 32) / NT;       // X elements staged per thread
+  constexpr int LPT = (KT * 32) / NT;       // X elements staged per thread
   typedef typename Vec4<T>::type acc_t;
 
   extern __shared__ __align__(16) unsigned char lds_raw[];
   T* slab = reinterpret_cast<T*>(lds_raw);
-  T* xbuf = slab + SR * SW;                  // two buffers of kTK * kXS
+  T* xbuf = slab + SR * SW;                  // two buffers of KT * kXS
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -302,17 +302,17 @@ rmat_block_kernel(const T* __restrict__ G, int ldg, int n, const T* __restrict__
       }
     }
   };
-  const int nrc = (n + kTK - 1) / kTK;       // r-chunks per column block c
+  const int nrc = (n + KT - 1) / KT;       // r-chunks per column block c
   // K tiles of column block c that meet the box: r in [max(0, bl - n + 1 + c),
   // min(n - 1, bh - n + 1 + c)] (all nrc tiles without a box)
-  auto rt_lo = [&](int c) { return max(0, bl - n + 1 + c) / kTK; };
-  auto rt_hi = [&](int c) { return min(n - 1, bh - n + 1 + c) / kTK; };
+  auto rt_lo = [&](int c) { return max(0, bl - n + 1 + c) / KT; };
+  auto rt_hi = [&](int c) { return min(n - 1, bh - n + 1 + c) / KT; };
 
   // staged X element e = tid + NT*m: col = e % 32, kk = e / 32 (a wave writes
   // whole rows of the staged tile: no LDS bank conflicts on the stores)
   T stage[LPT];
   auto load_tile = [&](int c, int rt) {
-    const int r0 = rt * kTK;
+    const int r0 = rt * KT;
 #pragma unroll
     for (int m = 0; m < LPT; ++m) {
       const int e = tid + NT * m;
@@ -325,7 +325,7 @@ rmat_block_kernel(const T* __restrict__ G, int ldg, int n, const T* __restrict__
     }
   };
   auto store_tile = [&](int buf) {
-    T* xs = xbuf + buf * (kTK * kXS);
+    T* xs = xbuf + buf * (KT * kXS);
 #pragma unroll
     for (int m = 0; m < LPT; ++m) {
       const int e = tid + NT * m;
@@ -370,10 +370,10 @@ rmat_block_kernel(const T* __restrict__ G, int ldg, int n, const T* __restrict__
         const int t = c * nrc + rt;
         const bool more = t + 1 < n * nrc;
         if (more) load_tile(rt + 1 < nrc ? c : c + 1, rt + 1 < nrc ? rt + 1 : 0);
-        const int colbase = rt * kTK - c + c0 + CP - 1;   // slab column of r = rt * kTK
-        const T* xs = xbuf + (t & 1) * (kTK * kXS);
+        const int colbase = rt * KT - c + c0 + CP - 1;   // slab column of r = rt * KT
+        const T* xs = xbuf + (t & 1) * (KT * kXS);
 #pragma unroll
-        for (int s = 0; s < kTK / 4; ++s) {
+        for (int s = 0; s < KT / 4; ++s) {
           const int kk = 4 * s + lk;
           T bfr[CB];
 #pragma unroll
@@ -419,10 +419,10 @@ rmat_block_kernel(const T* __restrict__ G, int ldg, int n, const T* __restrict__
       const bool more = cn <= c_hi;
       if (more) load_tile(cn, rtn);
       const int c0 = c - c % CP;
-      const int colbase = rt * kTK - c + c0 + CP - 1;   // slab column of r = rt * kTK
-      const T* xs = xbuf + (q & 1) * (kTK * kXS);
+      const int colbase = rt * KT - c + c0 + CP - 1;   // slab column of r = rt * KT
+      const T* xs = xbuf + (q & 1) * (KT * kXS);
 #pragma unroll
-      for (int s = 0; s < kTK / 4; ++s) {
+      for (int s = 0; s < KT / 4; ++s) {
         const int kk = 4 * s + lk;
         T bfr[CB];
 #pragma unroll
@@ -478,33 +478,34 @@ rmat_block_kernel(const T* __restrict__ G, int ldg, int n, const T* __restrict__
 }
 
 // Slab row stride for phases of CP column blocks: r covers nrc whole K tiles
-// and c spans CP values, so a row needs nrc * kTK + CP - 1 columns.
+// and c spans CP values, so a row needs nrc * TK + CP - 1 columns.
 template <typename T>
-static int slab_stride(int n, int CP) {
-  const int nrc = (n + kTK - 1) / kTK;
-  const int W = nrc * kTK + CP - 1;
+static int slab_stride(int n, int CP, int TK) {
+  const int nrc = (n + TK - 1) / TK;
+  const int W = nrc * TK + CP - 1;
   if (sizeof(T) == 4) return ((W + 63) / 64) * 64 + 2;     // 2 (mod 64) floats
   return ((W + 31) / 32) * 32 + 2;                         // 2 (mod 32) doubles
 }
 
 template <typename T>
-static size_t block_lds(int n, int TJ, int CP) {
-  return sizeof(T) * ((size_t)(16 + TJ - 1) * slab_stride<T>(n, CP) + 2 * kTK * kXS);
+static size_t block_lds(int n, int TJ, int CP, int TK) {
+  return sizeof(T) * ((size_t)(16 + TJ - 1) * slab_stride<T>(n, CP, TK) + 2 * TK * kXS);
 }
 
 // The largest row-block count TJ whose slab fits the LDS with whole column
 // blocks in one phase or, for large n, in phases of CP >= 64 column blocks
 // (the slab is reloaded per phase: (n / CP) x SR rows per workgroup).
 template <typename T>
-bool plan_block_tj(int n, size_t lds_limit, int TJ, BlockPlan* plan) {
+bool plan_block_tj(int n, size_t lds_limit, int TJ, BlockPlan* plan, int TK) {
   int cp_max = n;
   if (const char* e = getenv("KPSB_BLOCK_CP")) cp_max = std::max(1, std::min(n, atoi(e)));
   for (int CP = cp_max; CP >= 1; CP = (CP > 64 ? (CP + 1) / 2 : 0)) {
-    const size_t lds = block_lds<T>(n, TJ, CP);
+    const size_t lds = block_lds<T>(n, TJ, CP, TK);
     if (lds <= lds_limit) {
       plan->TJ = TJ;
       plan->CP = CP;
-      plan->SW = slab_stride<T>(n, CP);
+      plan->SW = slab_stride<T>(n, CP, TK);
+      plan->TK = TK;
       plan->lds = lds;
       plan->grid = ((n + 15) / 16) * ((n + TJ - 1) / TJ);
       plan->waves = 0;
@@ -529,13 +530,14 @@ bool plan_block(int n, size_t lds_limit, BlockPlan* plan) {
 }
 template bool plan_block<float>(int, size_t, BlockPlan*);
 template bool plan_block<double>(int, size_t, BlockPlan*);
-template bool plan_block_tj<float>(int, size_t, int, BlockPlan*);
-template bool plan_block_tj<double>(int, size_t, int, BlockPlan*);
+template bool plan_block_tj<float>(int, size_t, int, BlockPlan*, int);
+template bool plan_block_tj<double>(int, size_t, int, BlockPlan*, int);
 
-template <typename T, int TJ, int JB, int CB>
+template <typename T, int TJ, int JB, int CB, int KT = kTK>
 static void launch_tj(const BlockPlan& p, const T* G, int ldg, int n, const T* X, long ldx,
                       T* Y, long ldy, int ncols, hipStream_t s, const int* box) {
-  auto kern = box ? rmat_block_kernel<T, TJ, JB, CB, true> : rmat_block_kernel<T, TJ, JB, CB, false>;
+  auto kern = box ? rmat_block_kernel<T, TJ, JB, CB, true, KT>
+                  : rmat_block_kernel<T, TJ, JB, CB, false, KT>;
   constexpr int threads = 64 * (2 * TJ) / (JB * CB);
   if (p.lds > 65536)
     (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -549,7 +551,19 @@ template <typename T>
 void launch_rmat_block(const BlockPlan& p, const T* G, int ldg, int n, const T* X, long ldx,
                        T* Y, long ldy, int ncols, hipStream_t s, const int* box) {
   // waves per workgroup: TJ = 16 -> 16 (JB = 1) or 8 (JB = 2); TJ = 8 -> 8 (CB = 2)
-  // or 16 (CB = 1); chosen by the autotuner, 16 and 8 by default
+  // or 16 (CB = 1); chosen by the autotuner, 16 and 8 by default; K tiles of 64
+  // or (these four shapes) 128 entries
+  if (p.TK == 128) {
+    if (p.TJ == 16 && p.waves == 8)
+      launch_tj<T, 16, 2, 2, 128>(p, G, ldg, n, X, ldx, Y, ldy, ncols, s, box);
+    else if (p.TJ == 16)
+      launch_tj<T, 16, 1, 2, 128>(p, G, ldg, n, X, ldx, Y, ldy, ncols, s, box);
+    else if (p.TJ == 8 && p.waves == 16)
+      launch_tj<T, 8, 1, 1, 128>(p, G, ldg, n, X, ldx, Y, ldy, ncols, s, box);
+    else
+      launch_tj<T, 8, 1, 2, 128>(p, G, ldg, n, X, ldx, Y, ldy, ncols, s, box);
+    return;
+  }
   if (p.TJ == 16 && p.waves == 8) {
     launch_tj<T, 16, 2, 2>(p, G, ldg, n, X, ldx, Y, ldy, ncols, s, box);
     return;
