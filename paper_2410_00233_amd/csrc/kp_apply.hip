@@ -214,6 +214,7 @@ static void gemm(const GemmArgs& g, int variant, int zdim, hipStream_t s) {
   switch (variant) {
     case 1: gemm_launch<32, 32>(g, zdim, s); break;
     case 2: gemm_launch<32, 16>(g, zdim, s); break;
+    case 3: gemm_launch<64, 8>(g, zdim, s); break;   // half the LDS: twice the resident tiles
     default: gemm_launch<64, 16>(g, zdim, s); break;
   }
 }
@@ -228,7 +229,7 @@ void launch_kp_apply_parts(const double* Ax, const double* Ay, int n, int k, int
   // P_g = sum_{t in g} (transpose ? Ay_t^T : Ay_t) * Z_t
   GemmArgs g2{Ay, n, NN, transpose ? 1 : 0, Z, n, NN, 0, P, n, NN, n, n, n, k, plan.group,
               flags, nflags};
-  const int v = tune_pick(kTuneApply, n, k, transpose, 3, [&](int vv) -> double {
+  const int v = tune_pick(kTuneApply, n, k, transpose, 4, [&](int vv) -> double {
     GemmArgs a = g1, b = g2;
     a.flags = b.flags = nullptr;   // the sample launches always run
     a.nflags = b.nflags = 0;

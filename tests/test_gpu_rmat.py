@@ -172,7 +172,7 @@ def test_apply_variants_agree_bitwise(ctx, n, k, monkeypatch):
     X = torch.tensor(rng.standard_normal((n, n)), dtype=torch.float64, device="cuda")
     for tr in (False, True):
         outs = []
-        for v in range(3):
+        for v in range(4):
             monkeypatch.setenv("KPSB_TUNE_FORCE", str(v))
             outs.append(ctx.kp_apply(f, X, transpose=tr).cpu())
         for o in outs[1:]:
