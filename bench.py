@@ -43,7 +43,7 @@ BLOCK16_TRAFFIC_BYTES = 3.23e8
 BLOCK_VARIANT_TEMPLATE = {0: "16,1,2,false,64", 1: "16,2,2,false,64", 2: "8,1,2,false,64",
                           3: "8,1,1,false,64", 4: "16,1,2,false,128", 5: "16,2,2,false,128",
                           6: "8,1,2,false,128", 7: "8,1,1,false,128"}
-BLOCK16_VARIANT_TEMPLATE = {0: "32,4,2", 1: "16,4,2"}
+BLOCK16_VARIANT_TEMPLATE = {0: "32,4,2", 1: "16,4,2", 2: "32,2,2", 3: "16,2,2", 4: "16,1,2"}
 BLOCK16_TRAFFIC_SRC_SHA1 = "4e421df2669a63a3f8c5b9481e7943524a84e512"
 
 

@@ -327,7 +327,11 @@ struct BlockVariant {
 constexpr BlockVariant kBlockVariants[] = {{16, 16, 64},  {16, 8, 64},  {8, 8, 64},  {8, 16, 64},
                                            {16, 16, 128}, {16, 8, 128}, {8, 8, 128}, {8, 16, 128}};
 constexpr int kNumBlockVariants = 8;
-constexpr int kBlock16Variants[] = {32, 16};
+struct Block16Variant {
+  int TJ, waves;
+};
+constexpr Block16Variant kBlock16Variants[] = {{32, 8}, {16, 4}, {32, 16}, {16, 8}, {16, 16}};
+constexpr int kNumBlock16Variants = 5;
 
 template <typename T>
 kp_status choose_block_plan(kp_ctx* c, const Grids<T>& g, int n, const T* X, T* Y, int nc,
@@ -375,17 +379,22 @@ template <typename H>
 kp_status choose_block16_plan(kp_ctx* c, const Grids<H>& g, int n, const H* X16, long ld16,
                               float* Y, int nc, hipStream_t s, BlockPlan* bp) {
   const long N = (long)n * n;
-  const int v = tune_pick(kTuneBlock16, n, (int)sizeof(H), 0, 2, [&](int k) -> double {
+  const int v = tune_pick(kTuneBlock16, n, (int)sizeof(H), 0, kNumBlock16Variants,
+                          [&](int k) -> double {
     BlockPlan p;
-    if (!plan_block16_tj(n, c->lds_limit, kBlock16Variants[k], &p)) return -1.0;
+    if (!plan_block16_tj(n, c->lds_limit, kBlock16Variants[k].TJ, &p)) return -1.0;
+    p.waves = kBlock16Variants[k].waves;
     p.grid_limit = std::min(p.grid, kSampleWG);
     const double ms = time_launches(s, 2, [&]() {
       launch_rmat_block16<H>(p, g.G, g.ldg, n, X16, ld16, Y, N, nc, s);
     });
     return ms < 0 ? -1.0 : ms / ((double)std::min(p.grid, kSampleWG) * 16.0 * p.TJ);
   });
-  if (!plan_block16_tj(n, c->lds_limit, kBlock16Variants[v], bp) &&
-      !plan_block16(n, c->lds_limit, bp))
+  if (plan_block16_tj(n, c->lds_limit, kBlock16Variants[v].TJ, bp)) {
+    bp->waves = kBlock16Variants[v].waves;
+    return KP_OK;
+  }
+  if (!plan_block16(n, c->lds_limit, bp))
     return set_err(c, KP_E_INVAL, "no 16-bit block-product tiling fits the LDS at this n");
   return KP_OK;
 }
@@ -419,8 +428,7 @@ kp_status block_product16_1(kp_ctx* c, const Grids<H>& g, int n, int transpose, 
 kp_status split16_product(kp_ctx* c, const kp_blur* b, const double* dpsf, int n,
                           const float* V, float* W, int ncols, hipStream_t s) {
   BlockPlan bp;
-  if (!plan_block16(n, c->lds_limit, &bp))
-    return set_err(c, KP_E_INVAL, "no 16-bit block-product tiling fits the LDS at this n");
+  bool planned = false;
   const long N = (long)n * n;
   const int ldg = grid_ld(n);
   const size_t gcount = (size_t)(2 * n - 1) * ldg;
@@ -440,6 +448,13 @@ kp_status split16_product(kp_ctx* c, const kp_blur* b, const double* dpsf, int n
     launch_build_grid_split(dpsf, b->pu, b->pv, b->cu, b->cv, n, 0, tm.sh[t], scal, 0, Ghi, ldg, s);
     launch_build_grid_split(dpsf, b->pu, b->pv, b->cu, b->cv, n, 0, tm.sh[t], scal, 1, Glo, ldg, s);
     launch_to16_split(in, N, n, ncols, Xhi, Xlo, ld16, s);
+    if (!planned) {   // the tuned 16-bit launch shape (its samples write `out` first)
+      Grids<__half> gg;
+      gg.G = gg.Gs[0] = Ghi;
+      gg.ldg = ldg;
+      KP_TRY(choose_block16_plan<__half>(c, gg, n, Xhi, ld16, out, std::min(ncols, 32), s, &bp));
+      planned = true;
+    }
     for (int c0 = 0; c0 < ncols; c0 += 32) {
       const int nc = ncols - c0 < 32 ? ncols - c0 : 32;
       float* Wc = out + N * c0;

@@ -89,7 +89,7 @@ rmat_block16_kernel(const H* __restrict__ G, int ldg, int n, const H* __restrict
   const int ntiles = (total_ks + kSPT - 1) / kSPT;
   const long xlen = (long)total_ks * kKS;      // valid entries per column of X16
   uint4 stage[LPT];
-  auto load_tile = [&](int t) {
+  auto load_tile = [&](int t, uint4* dst) {
 #pragma unroll
     for (int m = 0; m < LPT; ++m) {
       const int e = tid + NT * m;              // 16-byte chunk: column e / 16, part e % 16
@@ -98,7 +98,7 @@ rmat_block16_kernel(const H* __restrict__ G, int ldg, int n, const H* __restrict
       uint4 v = make_uint4(0, 0, 0, 0);
       if (e < V8 && col < ncols && off < xlen)
         v = *reinterpret_cast<const uint4*>(reinterpret_cast<const u16*>(X) + (long)col * ldx + off);
-      stage[m] = v;
+      dst[m] = v;
     }
   };
   auto store_tile = [&](int buf) {
@@ -130,19 +130,19 @@ rmat_block16_kernel(const H* __restrict__ G, int ldg, int n, const H* __restrict
 #pragma unroll
   for (int jb = 0; jb < JB; ++jb) arow[jb] = (lrow + (TJ - 1) - (wj * JB + jb)) * SW;
 
-  load_tile(0);
+  load_tile(0, stage);
   store_tile(0);
   __syncthreads();
 
+  // (c, tt) of K step ks = c * ntc + tt, advanced step by step (no division)
+  int c = 0, tt = 0;
   for (int t = 0; t < ntiles; ++t) {
-    if (t + 1 < ntiles) load_tile(t + 1);
+    if (t + 1 < ntiles) load_tile(t + 1, stage);
     const u16* xs = xbuf + (t & 1) * (32 * kXS16);
 #pragma unroll
     for (int s = 0; s < kSPT; ++s) {
       const int ks = t * kSPT + s;
       if (ks < total_ks) {
-        const int c = ks / ntc;
-        const int tt = ks - c * ntc;
         const int colbase = -((n - 1 - c) & 7) - c + n - 1 + tt * kKS;   // multiple of 8
         vec bfr[CB];
 #pragma unroll
@@ -165,6 +165,10 @@ rmat_block16_kernel(const H* __restrict__ G, int ldg, int n, const H* __restrict
                 accd[jb][cb][e] += (double)acc[jb][cb][e];
                 acc[jb][cb][e] = 0.f;
               }
+          tt = 0;
+          ++c;
+        } else {
+          ++tt;
         }
       }
     }
@@ -252,6 +256,21 @@ template <typename H>
 void launch_rmat_block16(const BlockPlan& p, const H* G16, int ldg, int n, const H* X16,
                          long ldx, float* Y, long ldy, int ncols, hipStream_t s,
                          const double* inv_scale, int accumulate) {
+  // waves per workgroup (p.waves, 0 = the default): more waves hide the LDS
+  // latency of the fragment reads better, fewer row blocks per wave read more
+  // LDS per MFMA; chosen by the autotuner
+  if (p.TJ == 32 && p.waves == 16) {
+    launch16_tj<H, 32, 2, 2>(p, G16, ldg, n, X16, ldx, Y, ldy, ncols, inv_scale, accumulate, s);
+    return;
+  }
+  if (p.TJ == 16 && p.waves == 8) {
+    launch16_tj<H, 16, 2, 2>(p, G16, ldg, n, X16, ldx, Y, ldy, ncols, inv_scale, accumulate, s);
+    return;
+  }
+  if (p.TJ == 16 && p.waves == 16) {
+    launch16_tj<H, 16, 1, 2>(p, G16, ldg, n, X16, ldx, Y, ldy, ncols, inv_scale, accumulate, s);
+    return;
+  }
   switch (p.TJ) {
     case 32: launch16_tj<H, 32, 4, 2>(p, G16, ldg, n, X16, ldx, Y, ldy, ncols, inv_scale, accumulate, s); break;
     case 16: launch16_tj<H, 16, 4, 2>(p, G16, ldg, n, X16, ldx, Y, ldy, ncols, inv_scale, accumulate, s); break;
