@@ -37,14 +37,14 @@ MFMA_FP32_PEAK_TFLOPS = 157.3     # MI355X dense FP32 matrix peak
 # (profiles/rmat_products_n512_hbm_counters.md), valid while the kernel source
 # is the one the counters were taken on.
 BLOCK_TRAFFIC_BYTES = 1.110e9
-BLOCK_TRAFFIC_SRC_SHA1 = "8730805467c4d875fb2ddd5cc651507a0b63f037"
+BLOCK_TRAFFIC_SRC_SHA1 = "1088ed976cc381aa86cc7522512139d0fb1fec01"
 BLOCK16_TRAFFIC_BYTES = 3.23e8
 # template arguments <TJ, JB, CB> of the FP32 block kernel per autotuner variant
 BLOCK_VARIANT_TEMPLATE = {0: "16,1,2,false,64", 1: "16,2,2,false,64", 2: "8,1,2,false,64",
                           3: "8,1,1,false,64", 4: "16,1,2,false,128", 5: "16,2,2,false,128",
                           6: "8,1,2,false,128", 7: "8,1,1,false,128"}
 BLOCK16_VARIANT_TEMPLATE = {0: "32,4,2", 1: "16,4,2", 2: "32,2,2", 3: "16,2,2", 4: "16,1,2"}
-BLOCK16_TRAFFIC_SRC_SHA1 = "4e421df2669a63a3f8c5b9481e7943524a84e512"
+BLOCK16_TRAFFIC_SRC_SHA1 = "99d2488a0a799a69794c5027d6988ff96dd36b57"
 
 
 def counted_traffic(src, sha, value):
