@@ -237,14 +237,28 @@ __device__ __forceinline__ doublex4 mfma16x16x4(double a, double b, doublex4 c) 
 }
 
 constexpr int kTK = 64;   // default K-tile (entries of r per staged X tile); 128 also built
-constexpr int kXS = 48;   // LDS row stride of the staged X tile (bank-conflict free)
+constexpr int kKG = 16;   // K entries per group: 4 MFMA steps, 4 consecutive entries per lane
 
+// Row stride (elements) of the transposed X tile in LDS: KT plus 16 bytes, so that
+// the 16-byte reads of the 16 column lanes fall on distinct banks.
+template <typename T, int KT>
+constexpr int x_stride() { return KT + 16 / (int)sizeof(T); }
+
+// K order. Column block c's range of r is shifted to start at r0(c) in {0,-1,-2,-3}
+// so that every 16-entry group starts at a slab column that is a multiple of 4;
+// in a group, lane group lk (= lane / 16) owns the 4 consecutive entries 4 lk .. 4 lk + 3
+// and MFMA step u (0..3) multiplies entry 4 lk + u. Each lane then reads its A and
+// B operands of a group with 16-byte LDS loads (four MFMA steps' worth), a quarter
+// of the read instructions of one element per step. Entries with r outside [0, n)
+// are staged as zero X. A tile is GPT = KT / 16 consecutive groups of one column
+// block (the last tile of a block may hold fewer; the missing groups are skipped).
+//
 // box (optional, device): the rows [box[0], box[1]] and columns [box[2], box[3]]
 // of G that hold its nonzero entries. With it, a workgroup whose grid rows are
-// all outside writes zeros, and column block c visits only the K tiles whose
+// all outside writes zeros, and column block c visits only the groups whose
 // grid columns r - c + n - 1 meet the box; every skipped product is an exact
 // zero, so the result equals the dense one (for finite X, up to the sign of
-// zero). Without it every tile of R is multiplied.
+// zero). Without it every entry of R is multiplied.
 template <typename T, int TJ, int JB, int CB, bool CMP, int KT>
 __global__ void __launch_bounds__(64 * (2 * TJ) / (JB * CB))
 rmat_block_kernel(const T* __restrict__ G, int ldg, int n, const T* __restrict__ X, long ldx,
@@ -254,12 +268,16 @@ rmat_block_kernel(const T* __restrict__ G, int ldg, int n, const T* __restrict__
   constexpr int NT = 64 * WAVES;
   constexpr int SR = 16 + TJ - 1;
   constexpr int WC = 2 / CB;                 // waves along the 32 output columns
-  constexpr int LPT = (KT * 32) / NT;       // X elements staged per thread
+  constexpr int LPT = (KT * 32) / NT;        // X elements staged per thread
+  constexpr int GPT = KT / kKG;              // groups per tile
+  constexpr int XT = x_stride<T, KT>();
+  constexpr int VEC = 16 / (int)sizeof(T);   // elements per 16-byte LDS read
   typedef typename Vec4<T>::type acc_t;
+  typedef T vec_t __attribute__((ext_vector_type(VEC)));
 
   extern __shared__ __align__(16) unsigned char lds_raw[];
   T* slab = reinterpret_cast<T*>(lds_raw);
-  T* xbuf = slab + SR * SW;                  // two buffers of KT * kXS
+  T* xbuf = slab + SR * SW;                  // two transposed tiles of 32 x XT
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -286,10 +304,10 @@ rmat_block_kernel(const T* __restrict__ G, int ldg, int n, const T* __restrict__
   active = active && c_lo <= c_hi;
 
   // ---- slab: grid rows a0 .. a0 + SR - 1, zero outside the grid. Column
-  // blocks c are processed in phases of CP; a phase needs the slab columns
-  // [n - c0 - CP, n - c0 - CP + SW) only (all of them when CP = n).
+  // blocks c are processed in phases of CP; slab column s of a phase starting at
+  // c0 holds grid column n - c0 - CP - 4 + s (a margin of 4 for r0(c) < 0).
   auto load_slab = [&](int c0) {
-    const int cbase = n - c0 - CP;
+    const int cbase = n - c0 - CP - 4;
     for (int al = 0; al < SR; ++al) {
       const int a = a0 + al;
       const bool rowok = (a >= 0) && (a < g2);
@@ -302,34 +320,36 @@ rmat_block_kernel(const T* __restrict__ G, int ldg, int n, const T* __restrict__
       }
     }
   };
-  const int nrc = (n + KT - 1) / KT;       // r-chunks per column block c
-  // K tiles of column block c that meet the box: r in [max(0, bl - n + 1 + c),
-  // min(n - 1, bh - n + 1 + c)] (all nrc tiles without a box)
-  auto rt_lo = [&](int c) { return max(0, bl - n + 1 + c) / KT; };
-  auto rt_hi = [&](int c) { return min(n - 1, bh - n + 1 + c) / KT; };
 
-  // staged X element e = tid + NT*m: col = e % 32, kk = e / 32 (a wave writes
-  // whole rows of the staged tile: no LDS bank conflicts on the stores)
+  // groups of column block c (with start r0) to visit: all those holding r < n,
+  // or (with a box) those meeting r in [bl - n + 1 + c, bh - n + 1 + c]
+  auto g_lo = [&](int c, int r0) { return CMP ? (max(r0, bl - n + 1 + c) - r0) / kKG : 0; };
+  auto g_hi = [&](int c, int r0) {
+    return (CMP ? min(n - 1, bh - n + 1 + c) - r0 : n - 1 - r0) / kKG;
+  };
+
+  // staged X element e = tid + NT m: column e / KT, entry e % KT of the tile (a
+  // wave reads consecutive r and writes consecutive LDS words)
   T stage[LPT];
-  auto load_tile = [&](int c, int rt) {
-    const int r0 = rt * KT;
+  auto load_tile = [&](int c, int r0, int gb, int gh) {
+    const int rbase = r0 + kKG * gb;
+    const int rend = r0 + kKG * (gh + 1);    // groups beyond gh are staged as zero
 #pragma unroll
     for (int m = 0; m < LPT; ++m) {
       const int e = tid + NT * m;
-      const int col = e % 32;
-      const int kk = e / 32;
-      const int r = r0 + kk;
+      const int col = e / KT;
+      const int r = rbase + e % KT;
       T v = (T)0;
-      if (r < n && col < ncols) v = X[(long)col * ldx + (long)n * c + r];
+      if (col < ncols && r >= 0 && r < n && r < rend) v = X[(long)col * ldx + (long)n * c + r];
       stage[m] = v;
     }
   };
   auto store_tile = [&](int buf) {
-    T* xs = xbuf + buf * (KT * kXS);
+    T* xs = xbuf + buf * (32 * XT);
 #pragma unroll
     for (int m = 0; m < LPT; ++m) {
       const int e = tid + NT * m;
-      xs[(e / 32) * kXS + e % 32] = stage[m];
+      xs[(e / KT) * XT + e % KT] = stage[m];
     }
   };
 
@@ -354,87 +374,95 @@ rmat_block_kernel(const T* __restrict__ G, int ldg, int n, const T* __restrict__
 #pragma unroll
   for (int jb = 0; jb < JB; ++jb) arow[jb] = (lrow + (TJ - 1) - (wj * JB + jb)) * SW;
 
-  if constexpr (!CMP) {
-    // dense: every column block c and every K tile of it, in order
-    load_slab(0);
-    load_tile(0, 0);
-    store_tile(0);
-    __syncthreads();
-    for (int c = 0; c < n; ++c) {
-      if (c > 0 && c % CP == 0) {   // next phase: every wave is past the last tile's barrier
-        load_slab(c);
-        __syncthreads();
+  // Operands of group g of a staged tile whose first group starts at slab column
+  // colbase (a multiple of 4): each lane's 4 consecutive K entries, 16-byte reads.
+  auto read_group = [&](const T* xs, int colbase, int g, T (&a)[JB][4], T (&b)[CB][4]) {
+#pragma unroll
+    for (int h = 0; h < 4 / VEC; ++h) {
+#pragma unroll
+      for (int jb = 0; jb < JB; ++jb) {
+        const vec_t v = *reinterpret_cast<const vec_t*>(
+            slab + arow[jb] + colbase + kKG * g + 4 * lk + VEC * h);
+#pragma unroll
+        for (int u = 0; u < VEC; ++u) a[jb][VEC * h + u] = v[u];
       }
-      const int c0 = c - c % CP;
-      for (int rt = 0; rt < nrc; ++rt) {
-        const int t = c * nrc + rt;
-        const bool more = t + 1 < n * nrc;
-        if (more) load_tile(rt + 1 < nrc ? c : c + 1, rt + 1 < nrc ? rt + 1 : 0);
-        const int colbase = rt * KT - c + c0 + CP - 1;   // slab column of r = rt * KT
-        const T* xs = xbuf + (t & 1) * (KT * kXS);
 #pragma unroll
-        for (int s = 0; s < KT / 4; ++s) {
-          const int kk = 4 * s + lk;
-          T bfr[CB];
+      for (int cb = 0; cb < CB; ++cb) {
+        const vec_t v = *reinterpret_cast<const vec_t*>(
+            xs + ((wc * CB + cb) * 16 + lrow) * XT + kKG * g + 4 * lk + VEC * h);
 #pragma unroll
-          for (int cb = 0; cb < CB; ++cb) bfr[cb] = xs[kk * kXS + (wc * CB + cb) * 16 + lrow];
-          T afr[JB];
-#pragma unroll
-          for (int jb = 0; jb < JB; ++jb) afr[jb] = slab[arow[jb] + colbase + kk];
-#pragma unroll
-          for (int jb = 0; jb < JB; ++jb)
-#pragma unroll
-            for (int cb = 0; cb < CB; ++cb)
-              acc[jb][cb] = mfma16x16x4(afr[jb], bfr[cb], acc[jb][cb]);
-        }
-        if (more) store_tile((t + 1) & 1);
-        __syncthreads();
-      }
-      if (sizeof(T) == 4) {   // end of column block c: fold into the FP64 accumulators
-#pragma unroll
-        for (int jb = 0; jb < JB; ++jb)
-#pragma unroll
-          for (int cb = 0; cb < CB; ++cb)
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-              accd[jb][cb][e] += (double)acc[jb][cb][e];
-              acc[jb][cb][e] = (T)0;
-            }
+        for (int u = 0; u < VEC; ++u) b[cb][VEC * h + u] = v[u];
       }
     }
-  } else if (active) {   // uniform over the workgroup: every barrier below is reached by all
-    load_slab(c_lo - c_lo % CP);
-    int c = c_lo, rt = rt_lo(c_lo);
-    load_tile(c, rt);
+  };
+  auto mma_group = [&](const T (&a)[JB][4], const T (&b)[CB][4]) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int jb = 0; jb < JB; ++jb)
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb)
+          acc[jb][cb] = mfma16x16x4(a[jb][u], b[cb][u], acc[jb][cb]);
+  };
+  // All groups of a full tile in straight-line code, the reads of group g + 1
+  // issued before the MFMAs of group g; the last tile of a column block may hold
+  // fewer groups (a plain loop over them).
+  auto mma_tile = [&](const T* xs, int colbase, int ng) {
+    if (ng == GPT) {
+      T a0[JB][4], b0[CB][4], a1[JB][4], b1[CB][4];
+      read_group(xs, colbase, 0, a0, b0);
+#pragma unroll
+      for (int g = 0; g < GPT; g += 2) {
+        if (g + 1 < GPT) read_group(xs, colbase, g + 1, a1, b1);
+        __builtin_amdgcn_sched_barrier(0);
+        mma_group(a0, b0);
+        __builtin_amdgcn_sched_barrier(0);
+        if (g + 1 < GPT) {
+          if (g + 2 < GPT) read_group(xs, colbase, g + 2, a0, b0);
+          __builtin_amdgcn_sched_barrier(0);
+          mma_group(a1, b1);
+          __builtin_amdgcn_sched_barrier(0);
+        }
+      }
+    } else {
+#pragma unroll 1
+      for (int g = 0; g < ng; ++g) {
+        T a[JB][4], b[CB][4];
+        read_group(xs, colbase, g, a, b);
+        mma_group(a, b);
+      }
+    }
+  };
+
+  if (active) {   // uniform over the workgroup: every barrier below is reached by all
+    // state: column block c, its position cpos in the phase [c0, c0 + CP), its
+    // shift r0, the current tile's first group gb and the block's last group gh
+    int c = c_lo;
+    int cpos = c_lo % CP;
+    int c0 = c_lo - cpos;
+    int r0 = -((CP + 3 - cpos) & 3);
+    int gb = g_lo(c, r0), gh = g_hi(c, r0);
+    load_slab(c0);
+    load_tile(c, r0, gb, gh);
     store_tile(0);
     __syncthreads();
 
     for (int q = 0;; ++q) {
-      // the next tile: the next r chunk of c, else the first of c + 1
-      int cn = c, rtn = rt + 1;
-      if (rtn > rt_hi(c)) {
+      // the next tile: the next groups of c, else the first of c + 1
+      int cn = c, cposn = cpos, r0n = r0, gbn = gb + GPT, ghn = gh;
+      if (gbn > gh) {
         cn = c + 1;
-        rtn = cn <= c_hi ? rt_lo(cn) : 0;
+        cposn = cpos + 1 == CP ? 0 : cpos + 1;
+        r0n = -((CP + 3 - cposn) & 3);
+        if (cn <= c_hi) {
+          gbn = g_lo(cn, r0n);
+          ghn = g_hi(cn, r0n);
+        }
       }
       const bool more = cn <= c_hi;
-      if (more) load_tile(cn, rtn);
-      const int c0 = c - c % CP;
-      const int colbase = rt * KT - c + c0 + CP - 1;   // slab column of r = rt * KT
-      const T* xs = xbuf + (q & 1) * (KT * kXS);
-#pragma unroll
-      for (int s = 0; s < KT / 4; ++s) {
-        const int kk = 4 * s + lk;
-        T bfr[CB];
-#pragma unroll
-        for (int cb = 0; cb < CB; ++cb) bfr[cb] = xs[kk * kXS + (wc * CB + cb) * 16 + lrow];
-        T afr[JB];
-#pragma unroll
-        for (int jb = 0; jb < JB; ++jb) afr[jb] = slab[arow[jb] + colbase + kk];
-#pragma unroll
-        for (int jb = 0; jb < JB; ++jb)
-#pragma unroll
-          for (int cb = 0; cb < CB; ++cb) acc[jb][cb] = mfma16x16x4(afr[jb], bfr[cb], acc[jb][cb]);
-      }
+      if (more) load_tile(cn, r0n, gbn, ghn);
+      // slab column of the tile's first group: r0 + 16 gb - c + c0 + CP - 1 + 4
+      mma_tile(xbuf + (q & 1) * (32 * XT), r0 + kKG * gb - cpos + CP + 3, min(GPT, gh - gb + 1));
       if (more) store_tile((q + 1) & 1);
       __syncthreads();
       if (cn != c) {
@@ -450,13 +478,17 @@ rmat_block_kernel(const T* __restrict__ G, int ldg, int n, const T* __restrict__
               }
         }
         if (!more) break;
-        if (cn % CP == 0) {   // next phase: every wave is past the last tile's barrier
-          load_slab(cn);
+        if (cposn == 0) {   // next phase: every wave is past the last tile's barrier
+          c0 = cn;
+          load_slab(c0);
           __syncthreads();
         }
       }
       c = cn;
-      rt = rtn;
+      cpos = cposn;
+      r0 = r0n;
+      gb = gbn;
+      gh = ghn;
     }
   }
 
@@ -477,29 +509,33 @@ rmat_block_kernel(const T* __restrict__ G, int ldg, int n, const T* __restrict__
   }
 }
 
-// Slab row stride for phases of CP column blocks: r covers nrc whole K tiles
-// and c spans CP values, so a row needs nrc * TK + CP - 1 columns.
+// Slab row stride for phases of CP column blocks: the groups of a column block
+// span 16 ntc entries (ntc = ceil((n + 3) / 16)), c spans CP values and the slab
+// has a margin of 4, so a row needs 16 ntc + CP + 3 columns; padded to 4 (mod 64)
+// words so that the 16-byte reads of the 16 row lanes fall on distinct banks.
 template <typename T>
 static int slab_stride(int n, int CP, int TK) {
-  const int nrc = (n + TK - 1) / TK;
-  const int W = nrc * TK + CP - 1;
-  if (sizeof(T) == 4) return ((W + 63) / 64) * 64 + 2;     // 2 (mod 64) floats
+  (void)TK;
+  const int ntc = (n + 3 + kKG - 1) / kKG;
+  const int W = kKG * ntc + CP + 3;
+  if (sizeof(T) == 4) return ((W + 63) / 64) * 64 + 4;     // 4 (mod 64) floats
   return ((W + 31) / 32) * 32 + 2;                         // 2 (mod 32) doubles
 }
 
 template <typename T>
 static size_t block_lds(int n, int TJ, int CP, int TK) {
-  return sizeof(T) * ((size_t)(16 + TJ - 1) * slab_stride<T>(n, CP, TK) + 2 * TK * kXS);
+  const int XT = TK + 16 / (int)sizeof(T);
+  return sizeof(T) * ((size_t)(16 + TJ - 1) * slab_stride<T>(n, CP, TK) + 2 * 32 * (size_t)XT);
 }
 
 // The largest row-block count TJ whose slab fits the LDS with whole column
-// blocks in one phase or, for large n, in phases of CP >= 64 column blocks
+// blocks in one phase or, for large n, in phases of CP >= 16 column blocks
 // (the slab is reloaded per phase: (n / CP) x SR rows per workgroup).
 template <typename T>
 bool plan_block_tj(int n, size_t lds_limit, int TJ, BlockPlan* plan, int TK) {
   int cp_max = n;
   if (const char* e = getenv("KPSB_BLOCK_CP")) cp_max = std::max(1, std::min(n, atoi(e)));
-  for (int CP = cp_max; CP >= 1; CP = (CP > 64 ? (CP + 1) / 2 : 0)) {
+  for (int CP = cp_max; CP >= 1; CP = (CP > 16 ? (CP + 1) / 2 : 0)) {
     const size_t lds = block_lds<T>(n, TJ, CP, TK);
     if (lds <= lds_limit) {
       plan->TJ = TJ;
@@ -512,7 +548,7 @@ bool plan_block_tj(int n, size_t lds_limit, int TJ, BlockPlan* plan, int TK) {
       plan->grid_limit = 0;
       return true;
     }
-    if (CP <= 64) break;
+    if (CP <= 16) break;
   }
   return false;
 }
