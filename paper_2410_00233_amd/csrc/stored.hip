@@ -102,18 +102,54 @@ __device__ __forceinline__ bool any_flag(const int* flags, int nflags) {
   return false;
 }
 
+constexpr int kGvInFlight = 4;   // 16-byte loads in flight per thread
+
+// Row product (R x): one wave per row. With `vec` (N % VEC == 0, R and x
+// 16-byte aligned) rows are read with 16-byte loads of VEC elements,
+// kGvInFlight of them in flight per lane, into as many FP64 partial sums added
+// in a fixed order; otherwise one element per load.
+template <typename T>
+__device__ __forceinline__ double dot_vec(const T* __restrict__ a, const T* __restrict__ b, long i) {
+  constexpr int VEC = 16 / (int)sizeof(T);
+  typedef T vec_t __attribute__((ext_vector_type(VEC)));
+  const vec_t va = reinterpret_cast<const vec_t*>(a)[i];
+  const vec_t vb = reinterpret_cast<const vec_t*>(b)[i];
+  double s = 0.0;
+#pragma unroll
+  for (int u = 0; u < VEC; ++u) s += (double)va[u] * (double)vb[u];
+  return s;
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256)
 stored_gemv_rows_kernel(const T* __restrict__ R, long N, const T* __restrict__ x,
-                        T* __restrict__ y, const T* __restrict__ z, double coef,
+                        T* __restrict__ y, const T* __restrict__ z, double coef, int vec,
                         const int* __restrict__ flags, int nflags) {
   if (any_flag(flags, nflags)) return;
+  constexpr int VEC = 16 / (int)sizeof(T);
   const int lane = threadIdx.x & 63;
   const long row = (long)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (row >= N) return;
   const T* rp = R + row * N;
-  double acc = 0.0;
-  for (long c = lane; c < N; c += 64) acc += (double)rp[c] * (double)x[c];
+  double acc;
+  if (vec) {
+    const long NV = N / VEC;
+    double a[kGvInFlight];
+#pragma unroll
+    for (int q = 0; q < kGvInFlight; ++q) a[q] = 0.0;
+    long c = lane;
+    for (; c + 64 * (kGvInFlight - 1) < NV; c += 64 * kGvInFlight) {
+#pragma unroll
+      for (int q = 0; q < kGvInFlight; ++q) a[q] += dot_vec<T>(rp, x, c + 64 * q);
+    }
+    for (; c < NV; c += 64) a[0] += dot_vec<T>(rp, x, c);
+    acc = 0.0;
+#pragma unroll
+    for (int q = 0; q < kGvInFlight; ++q) acc += a[q];
+  } else {
+    acc = 0.0;
+    for (long c = lane; c < N; c += 64) acc += (double)rp[c] * (double)x[c];
+  }
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
   if (lane == 0) {
@@ -123,18 +159,52 @@ stored_gemv_rows_kernel(const T* __restrict__ R, long N, const T* __restrict__ x
   }
 }
 
-// Column product (R^T w): workgroup (column strip of 256, row chunk) writes a
-// partial sum per column; the chunks are then added in a fixed order.
-constexpr int kGvChunks = 16;
+// Column product (R^T w): workgroup (strip of 256 x VEC columns, row chunk)
+// writes a partial sum per column; with `vec` (N % VEC == 0, R 16-byte aligned)
+// each thread reads a 16-byte vector of VEC columns per row (kGvInFlight
+// rows in flight), otherwise one column. The chunks are then added in a fixed order.
+constexpr int kGvChunks = 32;
 template <typename T>
 __global__ void __launch_bounds__(256)
 stored_gemv_cols_kernel(const T* __restrict__ R, long N, const T* __restrict__ w,
-                        double* __restrict__ part, const int* __restrict__ flags, int nflags) {
+                        double* __restrict__ part, int vec, const int* __restrict__ flags,
+                        int nflags) {
   if (any_flag(flags, nflags)) return;
-  const long col = (long)blockIdx.x * 256 + threadIdx.x;
+  constexpr int VEC = 16 / (int)sizeof(T);
+  typedef T vec_t __attribute__((ext_vector_type(VEC)));
   const int chunk = blockIdx.y;
   const long rows = (N + kGvChunks - 1) / kGvChunks;
   const long r0 = chunk * rows, r1 = r0 + rows < N ? r0 + rows : N;
+  if (vec) {
+    const long cv = (long)blockIdx.x * 256 + threadIdx.x;   // vector column
+    if (cv * VEC >= N) return;
+    double acc[VEC];
+#pragma unroll
+    for (int u = 0; u < VEC; ++u) acc[u] = 0.0;
+    long r = r0;
+    for (; r + kGvInFlight - 1 < r1; r += kGvInFlight) {
+      vec_t v[kGvInFlight];
+#pragma unroll
+      for (int q = 0; q < kGvInFlight; ++q)
+        v[q] = reinterpret_cast<const vec_t*>(R + (r + q) * N)[cv];
+#pragma unroll
+      for (int q = 0; q < kGvInFlight; ++q) {
+        const double wr = (double)w[r + q];
+#pragma unroll
+        for (int u = 0; u < VEC; ++u) acc[u] += (double)v[q][u] * wr;
+      }
+    }
+    for (; r < r1; ++r) {
+      const vec_t v = reinterpret_cast<const vec_t*>(R + r * N)[cv];
+      const double wr = (double)w[r];
+#pragma unroll
+      for (int u = 0; u < VEC; ++u) acc[u] += (double)v[u] * wr;
+    }
+#pragma unroll
+    for (int u = 0; u < VEC; ++u) part[(long)chunk * N + cv * VEC + u] = acc[u];
+    return;
+  }
+  const long col = (long)blockIdx.x * 256 + threadIdx.x;
   if (col >= N) return;
   double acc = 0.0;
   for (long r = r0; r < r1; ++r) acc += (double)R[r * N + col] * (double)w[r];
@@ -160,13 +230,17 @@ long stored_gemv_ws(long N) { return (long)kGvChunks * N; }
 template <typename T>
 void launch_stored_gemv(const T* R, long N, int transpose, const T* x, T* y, const T* z,
                         double coef, double* ws, hipStream_t s, const int* flags, int nflags) {
+  constexpr int VEC = 16 / (int)sizeof(T);
+  const bool aligned = N % VEC == 0 && (uintptr_t)R % 16 == 0;
   if (!transpose) {
+    const int vec = aligned && (uintptr_t)x % 16 == 0;
     hipLaunchKernelGGL(stored_gemv_rows_kernel<T>, dim3((unsigned)((N + 3) / 4)), dim3(256), 0,
-                       s, R, N, x, y, z, coef, flags, nflags);
+                       s, R, N, x, y, z, coef, vec, flags, nflags);
     return;
   }
-  hipLaunchKernelGGL(stored_gemv_cols_kernel<T>, dim3((unsigned)((N + 255) / 256), kGvChunks),
-                     dim3(256), 0, s, R, N, x, ws, flags, nflags);
+  const long ncv = aligned ? N / VEC : N;     // threads along the columns
+  hipLaunchKernelGGL(stored_gemv_cols_kernel<T>, dim3((unsigned)((ncv + 255) / 256), kGvChunks),
+                     dim3(256), 0, s, R, N, x, ws, (int)aligned, flags, nflags);
   long blocks = (N + 255) / 256;
   if (blocks > 2048) blocks = 2048;
   hipLaunchKernelGGL(stored_gemv_sum_kernel<T>, dim3((unsigned)blocks), dim3(256), 0, s, ws, N,

@@ -54,6 +54,40 @@ def test_stored_products_match_explicit_R(ctx, n, ncols, prec):
             assert np.all(np.abs(Yh - ref) <= 2e-6 * mag + 1e-7 * mag.max())
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("shift_R,shift_x", [(1, 0), (0, 1), (1, 1), (0, 0)])
+def test_stored_gemv_on_offset_views(ctx, prec, shift_R, shift_x):
+    """R and x as views one element into a larger buffer (not 16-byte aligned):
+    the matrix-vector products must read them element-wise and agree with the
+    aligned call to rounding order."""
+    import torch
+    n = 16
+    N = n * n
+    rng = np.random.default_rng(5 + shift_R + 2 * shift_x)
+    R = rng.standard_normal((N, N))
+    x = rng.standard_normal(N)
+    if prec == "f32":
+        R = R.astype(np.float32).astype(np.float64)
+        x = x.astype(np.float32).astype(np.float64)
+    dt = torch.float64 if prec == "f64" else torch.float32
+    Rbuf = torch.zeros(N * N + 1, dtype=dt, device="cuda")
+    Rbuf[shift_R:shift_R + N * N] = torch.tensor(R.ravel(), dtype=dt, device="cuda")
+    xbuf = torch.zeros(N + 1, dtype=dt, device="cuda")
+    xbuf[shift_x:shift_x + N] = torch.tensor(x, dtype=dt, device="cuda")
+    Rd = Rbuf[shift_R:shift_R + N * N].view(N, N)
+    xd = xbuf[shift_x:shift_x + N]
+    for tr in (False, True):
+        y = ctx.kp_rmat_apply_stored(n, Rd, xd, transpose=tr)
+        torch.cuda.synchronize()
+        M = R.T if tr else R
+        ref, mag = M @ x, np.abs(M) @ np.abs(x)
+        err = np.abs(y.cpu().numpy().astype(np.float64) - ref)
+        if prec == "f64":
+            assert err.max() <= 1e-13 * mag.max()
+        else:
+            assert np.all(err <= 2e-6 * mag + 1e-7 * mag.max())
+
+
 def _blur_problem(n, bc, seed):
     P, cu, cv = wl.random_psf(7, 9, seed, cu=3, cv=4)
     A = op.blur_matrix_reflexive(P, cu, cv, n) if bc == "reflexive" else op.blur_matrix(P, cu, cv, n)
