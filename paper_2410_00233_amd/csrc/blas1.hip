@@ -43,6 +43,28 @@ __device__ __forceinline__ void row_range(long N, long* lo, long* hi) {
   *hi = *lo + chunk < N ? *lo + chunk : N;
 }
 
+// Vector paths (16-byte loads of VEC = 16 / sizeof(T) consecutive rows): taken
+// when N, the leading dimension and the pointers allow them. The block's row
+// range is then a multiple of VEC long (the last block's ends at N).
+template <typename T> struct Vec16 {
+  static constexpr int VEC = 16 / (int)sizeof(T);
+  typedef T type __attribute__((ext_vector_type(VEC)));
+};
+
+__device__ __forceinline__ void row_range_vec(long N, int VEC, long* lo, long* hi) {
+  const long nv = N / VEC;
+  const long chunk = ((nv + gridDim.x - 1) / gridDim.x) * VEC;
+  *lo = (long)blockIdx.x * chunk;
+  *hi = *lo + chunk < N ? *lo + chunk : N;
+  if (*lo > N) *lo = N;
+}
+
+template <typename T>
+static bool vec_ok(long N, long ld, const void* a, const void* b) {
+  constexpr int VEC = Vec16<T>::VEC;
+  return N % VEC == 0 && ld % VEC == 0 && (uintptr_t)a % 16 == 0 && (uintptr_t)b % 16 == 0;
+}
+
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ void __launch_bounds__(256)
@@ -77,11 +99,58 @@ multidot_kernel(const T* __restrict__ V, long ldv, int m, const T* __restrict__ 
   }
 }
 
+// Vector form: wave q of the block takes the columns q, q + 4, q + 8, ... over
+// the block's whole row range (lane l: rows lo + VEC (l + 64 t)), eight
+// columns' loads in flight, and writes their block partials from a wave
+// reduction (no barrier). w is read by every wave (served by the cache).
+template <typename T>
+__global__ void __launch_bounds__(256)
+multidot_vec_kernel(const T* __restrict__ V, long ldv, int m, const T* __restrict__ w, long N,
+                    double* __restrict__ partials, const int* __restrict__ pred) {
+  if (pred && *pred == 0) return;
+  constexpr int VEC = Vec16<T>::VEC;
+  typedef typename Vec16<T>::type vec_t;
+  constexpr int CG = 8;                       // columns per round of loads
+  long lo, hi;
+  row_range_vec(N, VEC, &lo, &hi);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int c0 = wave; c0 < m; c0 += 4 * CG) {   // columns c0 + 4 e, e < CG
+    double acc[CG];
+#pragma unroll
+    for (int e = 0; e < CG; ++e) acc[e] = 0.0;
+    for (long r = lo + (long)VEC * lane; r < hi; r += 64L * VEC) {
+      const vec_t wv = *reinterpret_cast<const vec_t*>(w + r);
+      vec_t vv[CG];
+#pragma unroll
+      for (int e = 0; e < CG; ++e)
+        if (c0 + 4 * e < m)
+          vv[e] = *reinterpret_cast<const vec_t*>(V + (long)(c0 + 4 * e) * ldv + r);
+#pragma unroll
+      for (int e = 0; e < CG; ++e)
+        if (c0 + 4 * e < m) {
+          double t = 0.0;
+#pragma unroll
+          for (int u = 0; u < VEC; ++u) t += (double)vv[e][u] * (double)wv[u];
+          acc[e] += t;
+        }
+    }
+#pragma unroll
+    for (int e = 0; e < CG; ++e) {
+      const double v = wave_sum(acc[e]);
+      if (lane == 0 && c0 + 4 * e < m) partials[(long)blockIdx.x * m + c0 + 4 * e] = v;
+    }
+  }
+}
+
 template <typename T>
 void launch_multidot(const T* V, long ldv, int m, const T* w, long N, double* partials,
                      hipStream_t s, const int* pred) {
-  hipLaunchKernelGGL(multidot_kernel<T>, dim3(kRedBlocks), dim3(256), 0, s, V, ldv, m, w, N,
-                     partials, pred);
+  if (vec_ok<T>(N, ldv, V, w))
+    hipLaunchKernelGGL(multidot_vec_kernel<T>, dim3(kRedBlocks), dim3(256), 0, s, V, ldv, m, w,
+                       N, partials, pred);
+  else
+    hipLaunchKernelGGL(multidot_kernel<T>, dim3(kRedBlocks), dim3(256), 0, s, V, ldv, m, w, N,
+                       partials, pred);
 }
 template void launch_multidot<float>(const float*, long, int, const float*, long, double*,
                                      hipStream_t, const int*);
@@ -133,11 +202,61 @@ project_out_kernel(T* __restrict__ w, const T* __restrict__ V, long ldv, int m,
   if (threadIdx.x == 0 && nrm_partials) nrm_partials[blockIdx.x] = nrm;
 }
 
+// Vector form: VEC rows per thread, the columns in rounds of 16 loads in flight.
+template <typename T>
+__global__ void __launch_bounds__(256)
+project_out_vec_kernel(T* __restrict__ w, const T* __restrict__ V, long ldv, int m,
+                       const double* __restrict__ h, long N, double* __restrict__ nrm_partials,
+                       const int* __restrict__ pred) {
+  if (pred && *pred == 0) return;
+  constexpr int VEC = Vec16<T>::VEC;
+  typedef typename Vec16<T>::type vec_t;
+  constexpr int CG = 16;
+  __shared__ double hs[64];
+  __shared__ double sh[8];
+  if (threadIdx.x < m) hs[threadIdx.x] = h[threadIdx.x];
+  __syncthreads();
+  long lo, hi;
+  row_range_vec(N, VEC, &lo, &hi);
+  double nrm = 0.0;
+  for (long r = lo + (long)VEC * threadIdx.x; r < hi; r += 256L * VEC) {
+    const vec_t wv = *reinterpret_cast<const vec_t*>(w + r);
+    double v[VEC];
+#pragma unroll
+    for (int u = 0; u < VEC; ++u) v[u] = (double)wv[u];
+    for (int i0 = 0; i0 < m; i0 += CG) {
+      vec_t vv[CG];
+#pragma unroll
+      for (int e = 0; e < CG; ++e)
+        if (i0 + e < m) vv[e] = *reinterpret_cast<const vec_t*>(V + (long)(i0 + e) * ldv + r);
+#pragma unroll
+      for (int e = 0; e < CG; ++e)
+        if (i0 + e < m) {
+#pragma unroll
+          for (int u = 0; u < VEC; ++u) v[u] -= hs[i0 + e] * (double)vv[e][u];
+        }
+    }
+    vec_t o;
+#pragma unroll
+    for (int u = 0; u < VEC; ++u) {
+      o[u] = (T)v[u];
+      nrm += (double)o[u] * (double)o[u];
+    }
+    *reinterpret_cast<vec_t*>(w + r) = o;
+  }
+  nrm = block_sum(nrm, sh);
+  if (threadIdx.x == 0 && nrm_partials) nrm_partials[blockIdx.x] = nrm;
+}
+
 template <typename T>
 void launch_project_out(T* w, const T* V, long ldv, int m, const double* h, long N,
                         double* nrm_partials, hipStream_t s, const int* pred) {
-  hipLaunchKernelGGL(project_out_kernel<T>, dim3(kRedBlocks), dim3(256), 0, s, w, V, ldv, m,
-                     h, N, nrm_partials, pred);
+  if (vec_ok<T>(N, ldv, V, w))
+    hipLaunchKernelGGL(project_out_vec_kernel<T>, dim3(kRedBlocks), dim3(256), 0, s, w, V, ldv,
+                       m, h, N, nrm_partials, pred);
+  else
+    hipLaunchKernelGGL(project_out_kernel<T>, dim3(kRedBlocks), dim3(256), 0, s, w, V, ldv, m,
+                       h, N, nrm_partials, pred);
 }
 template void launch_project_out<float>(float*, const float*, long, int, const double*, long,
                                         double*, hipStream_t, const int*);
@@ -161,9 +280,31 @@ norm2_partials_kernel(const T* __restrict__ w, long N, double* __restrict__ nrm_
 }
 
 template <typename T>
+__global__ void __launch_bounds__(256)
+norm2_partials_vec_kernel(const T* __restrict__ w, long N, double* __restrict__ nrm_partials) {
+  constexpr int VEC = Vec16<T>::VEC;
+  typedef typename Vec16<T>::type vec_t;
+  __shared__ double sh[8];
+  long lo, hi;
+  row_range_vec(N, VEC, &lo, &hi);
+  double nrm = 0.0;
+  for (long r = lo + (long)VEC * threadIdx.x; r < hi; r += 256L * VEC) {
+    const vec_t v = *reinterpret_cast<const vec_t*>(w + r);
+#pragma unroll
+    for (int u = 0; u < VEC; ++u) nrm += (double)v[u] * (double)v[u];
+  }
+  nrm = block_sum(nrm, sh);
+  if (threadIdx.x == 0) nrm_partials[blockIdx.x] = nrm;
+}
+
+template <typename T>
 void launch_norm2_partials(const T* w, long N, double* nrm_partials, hipStream_t s) {
-  hipLaunchKernelGGL(norm2_partials_kernel<T>, dim3(kRedBlocks), dim3(256), 0, s, w, N,
-                     nrm_partials);
+  if (vec_ok<T>(N, 0, w, w))
+    hipLaunchKernelGGL(norm2_partials_vec_kernel<T>, dim3(kRedBlocks), dim3(256), 0, s, w, N,
+                       nrm_partials);
+  else
+    hipLaunchKernelGGL(norm2_partials_kernel<T>, dim3(kRedBlocks), dim3(256), 0, s, w, N,
+                       nrm_partials);
 }
 template void launch_norm2_partials<float>(const float*, long, double*, hipStream_t);
 template void launch_norm2_partials<double>(const double*, long, double*, hipStream_t);
@@ -187,10 +328,36 @@ normalize_kernel(T* __restrict__ w, long N, const double* __restrict__ nrm_parti
 }
 
 template <typename T>
+__global__ void __launch_bounds__(256)
+normalize_vec_kernel(T* __restrict__ w, long N, const double* __restrict__ nrm_partials,
+                     double* __restrict__ norm_out, const int* __restrict__ pred) {
+  if (pred && *pred == 0) return;
+  constexpr int VEC = Vec16<T>::VEC;
+  typedef typename Vec16<T>::type vec_t;
+  __shared__ double sh[8];
+  const double nrm = sqrt(reduce_partials_block(nrm_partials, 1, 0, sh));
+  if (blockIdx.x == 0 && threadIdx.x == 0 && norm_out) *norm_out = nrm;
+  if (nrm == 0.0) return;
+  const double inv = 1.0 / nrm;
+  long lo, hi;
+  row_range_vec(N, VEC, &lo, &hi);
+  for (long r = lo + (long)VEC * threadIdx.x; r < hi; r += 256L * VEC) {
+    vec_t v = *reinterpret_cast<const vec_t*>(w + r);
+#pragma unroll
+    for (int u = 0; u < VEC; ++u) v[u] = (T)((double)v[u] * inv);
+    *reinterpret_cast<vec_t*>(w + r) = v;
+  }
+}
+
+template <typename T>
 void launch_normalize(T* w, long N, const double* nrm_partials, double* norm_out,
                       hipStream_t s, const int* pred) {
-  hipLaunchKernelGGL(normalize_kernel<T>, dim3(kRedBlocks), dim3(256), 0, s, w, N,
-                     nrm_partials, norm_out, pred);
+  if (vec_ok<T>(N, 0, w, w))
+    hipLaunchKernelGGL(normalize_vec_kernel<T>, dim3(kRedBlocks), dim3(256), 0, s, w, N,
+                       nrm_partials, norm_out, pred);
+  else
+    hipLaunchKernelGGL(normalize_kernel<T>, dim3(kRedBlocks), dim3(256), 0, s, w, N,
+                       nrm_partials, norm_out, pred);
 }
 template void launch_normalize<float>(float*, long, const double*, double*, hipStream_t,
                                       const int*);
