@@ -236,7 +236,7 @@ __device__ __forceinline__ doublex4 mfma16x16x4(double a, double b, doublex4 c) 
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
-constexpr int kTK = 64;   // default K-tile (entries of r per staged X tile); 128 also built
+constexpr int kTK = 64;   // default K-tile (entries of r per staged X tile); 128, 192 also built
 constexpr int kKG = 16;   // K entries per group: 4 MFMA steps, 4 consecutive entries per lane
 
 // Row stride (elements) of the transposed X tile in LDS: KT plus 16 bytes, so that
@@ -588,7 +588,19 @@ void launch_rmat_block(const BlockPlan& p, const T* G, int ldg, int n, const T* 
                        T* Y, long ldy, int ncols, hipStream_t s, const int* box) {
   // waves per workgroup: TJ = 16 -> 16 (JB = 1) or 8 (JB = 2); TJ = 8 -> 8 (CB = 2)
   // or 16 (CB = 1); chosen by the autotuner, 16 and 8 by default; K tiles of 64
-  // or (these four shapes) 128 entries
+  // or (these four shapes) 128 or 192 entries (fewer tiles, so fewer barriers
+  // and partial tiles, per column block; larger X buffers)
+  if (p.TK == 192) {
+    if (p.TJ == 16 && p.waves == 8)
+      launch_tj<T, 16, 2, 2, 192>(p, G, ldg, n, X, ldx, Y, ldy, ncols, s, box);
+    else if (p.TJ == 16)
+      launch_tj<T, 16, 1, 2, 192>(p, G, ldg, n, X, ldx, Y, ldy, ncols, s, box);
+    else if (p.TJ == 8 && p.waves == 16)
+      launch_tj<T, 8, 1, 1, 192>(p, G, ldg, n, X, ldx, Y, ldy, ncols, s, box);
+    else
+      launch_tj<T, 8, 1, 2, 192>(p, G, ldg, n, X, ldx, Y, ldy, ncols, s, box);
+    return;
+  }
   if (p.TK == 128) {
     if (p.TJ == 16 && p.waves == 8)
       launch_tj<T, 16, 2, 2, 128>(p, G, ldg, n, X, ldx, Y, ldy, ncols, s, box);
