@@ -37,7 +37,7 @@ MFMA_FP32_PEAK_TFLOPS = 157.3     # MI355X dense FP32 matrix peak
 # (profiles/rmat_products_n512_hbm_counters.md), valid while the kernel source
 # is the one the counters were taken on.
 BLOCK_TRAFFIC_BYTES = 1.150e9
-BLOCK_TRAFFIC_SRC_SHA1 = "3116adc352c4d928255b0d3572fcc1bc7bf19559"
+BLOCK_TRAFFIC_SRC_SHA1 = "13608c503b486f981cc5c40f2e2508e1eedae50e"
 BLOCK16_TRAFFIC_BYTES = 3.23e8
 # template arguments <TJ, JB, CB> of the FP32 block kernel per autotuner variant
 BLOCK_VARIANT_TEMPLATE = {0: "16,1,2,false,64", 1: "16,2,2,false,64", 2: "8,1,2,false,64",
@@ -113,7 +113,12 @@ def bench_batched(ctx, count):
         o = api.Context.rsvd_opts(d["k"], d["p"], 2, prec="f32", seed=d["seed"])
         probs.append((blur, "rsvd", o, d["k"]))
     fl = sum(flops.rsvd(d["n"], d["k"], d["p"], 2) for d in mix)
-    ctx.kp_svd_batched(probs[:4])              # workers and kernels warm
+    # workers warm and every image size tuned before the timed run (the one-by-one
+    # run below comes after it and so finds everything tuned too)
+    first = {}
+    for pr, d in zip(probs, mix):
+        first.setdefault(d["n"], pr)
+    ctx.kp_svd_batched(list(first.values()))
     torch.cuda.synchronize()
     log("batched: timed run")
     t0 = time.perf_counter()

@@ -157,6 +157,9 @@ double time_launches(hipStream_t s, int reps, const std::function<void()>& launc
 // The variant of (op, n, a, b) to use: on first use, cost(v) is evaluated for
 // every v < ncand (negative = not applicable) and the cheapest is kept.
 int tune_pick(int op, int n, int a, int b, int ncand, const std::function<double(int)>& cost);
+// Whether (op, n, a, b) on the current device has its variant chosen already
+// (true when autotuning is off).
+bool tune_known(int op, int n, int a, int b);
 std::string tune_table();   // JSON list of the choices and measured costs
 
 // ---- vector kernels (blas1.hip) --------------------------------------------

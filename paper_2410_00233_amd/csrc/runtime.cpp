@@ -19,6 +19,7 @@
 #include <thread>
 #include <vector>
 
+#include "common.h"
 #include "ctx.h"
 #include "kpsb.h"
 
@@ -81,6 +82,27 @@ kp_status run_one(kp_ctx* w, const kp_blur* b, int32_t method, const void* opts,
 }
 
 bool is_error(kp_status s) { return s != KP_OK && s != KP_W_BREAKDOWN; }
+
+// Whether a KP-SVD would pick a launch shape the autotuner has not chosen yet:
+// its first call times candidate launches, which must not share the GPU with
+// other problems' work or the samples measure the contention.
+bool needs_tuning(const kp_blur& b, int32_t method, const void* opts) {
+  if (!opts) return false;
+  if (method == KP_METHOD_GKB) {
+    const kp_gkb_opts* o = static_cast<const kp_gkb_opts*>(opts);
+    if (o->block < 1) return false;   // matrix-vector products: not tuned
+    return !tune_known(kTuneBlock, b.n, o->prec == KP_F64 ? 8 : 4, 0);
+  }
+  const kp_rsvd_opts* o = static_cast<const kp_rsvd_opts*>(opts);
+  if (o->prec == KP_BF16 || o->prec == KP_F16)
+    return !tune_known(kTuneBlock16, b.n, 2, 0) ||
+           (o->refine == 1 && !tune_known(kTuneBlock, b.n, 4, 0));
+  return !tune_known(kTuneBlock, b.n, o->prec == KP_F64 ? 8 : 4, 0);
+}
+
+bool apply_needs_tuning(int n, int k) {
+  return !tune_known(kTuneApply, n, k, 0) || !tune_known(kTuneApply, n, k, 1);
+}
 
 double ms_since(std::chrono::steady_clock::time_point t0) {
   return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
@@ -233,9 +255,40 @@ struct kp_server {
   int running = 0;
   int64_t counters[8] = {0, 0, 0, 0, 0, 0, 0, 0};
 
+  // Tuning gate: jobs run under it shared; a job that would make the autotuner
+  // time candidate launches (a new size or rank) runs under it exclusively, so
+  // that no other job's GPU work is in flight while the samples are timed.
+  // Waiting exclusive jobs hold back new shared ones.
+  std::mutex gm;
+  std::condition_variable gcv;
+  int gshared = 0;
+  int gwait = 0;
+  bool gexcl = false;
 };
 
 namespace {
+
+void gate_enter(kp_server* s, bool excl) {
+  std::unique_lock<std::mutex> lk(s->gm);
+  if (excl) {
+    s->gwait += 1;
+    s->gcv.wait(lk, [&] { return !s->gexcl && s->gshared == 0; });
+    s->gwait -= 1;
+    s->gexcl = true;
+  } else {
+    s->gcv.wait(lk, [&] { return !s->gexcl && s->gwait == 0; });
+    s->gshared += 1;
+  }
+}
+
+void gate_leave(kp_server* s, bool excl) {
+  {
+    std::lock_guard<std::mutex> lk(s->gm);
+    if (excl) s->gexcl = false;
+    else s->gshared -= 1;
+  }
+  s->gcv.notify_all();
+}
 
 // Bytes committed by everything except worker `w`: resident or reserved
 // factor sets, the reservations of running workers and (if count_idle) the
@@ -396,6 +449,10 @@ void worker_loop(kp_server* s, int w) {
     const kp_request& r = job.req;
     const int n = r.blur.n;
     kp_status st = KP_OK;
+    const void* ropts = r.method == KP_METHOD_GKB ? (const void*)&r.gkb : (const void*)&r.rsvd;
+    bool excl = (!hit && needs_tuning(r.blur, r.method, ropts)) ||
+                (hit && apply_needs_tuning(n, e->k));
+    gate_enter(s, excl);
     // factors: resident, or computed into a cache entry / a private buffer
     double* Ax = nullptr;
     double* Ay = nullptr;
@@ -428,8 +485,7 @@ void worker_loop(kp_server* s, int w) {
         f.Ax = Ax;
         f.Ay = Ay;
         f.factor_prec = KP_F64;
-        const void* opts = r.method == KP_METHOD_GKB ? (const void*)&r.gkb : (const void*)&r.rsvd;
-        st = run_one(wc, &r.blur, r.method, opts, &f);
+        st = run_one(wc, &r.blur, r.method, ropts, &f);
         if (st == KP_W_BREAKDOWN) st = KP_OK;
         if (is_error(st)) set_msg(&res, wc->err.c_str());
         k = f.k;
@@ -459,6 +515,12 @@ void worker_loop(kp_server* s, int w) {
       f.Ax = Ax;
       f.Ay = Ay;
       f.factor_prec = KP_F64;
+      if (!excl && apply_needs_tuning(n, k)) {   // finish this job alone
+        (void)hipStreamSynchronize(wc->own_stream);
+        gate_leave(s, false);
+        excl = true;
+        gate_enter(s, true);
+      }
       const auto t1 = std::chrono::steady_clock::now();
       st = r.iso ? sb_solve_iso(wc, &f, r.b, &r.sb, r.x, &res.stats, wc->own_stream)
                  : sb_solve_aniso(wc, &f, r.b, &r.sb, r.x, &res.stats, wc->own_stream);
@@ -493,8 +555,9 @@ void worker_loop(kp_server* s, int w) {
         to_free = {Ax, Ay};
       }
     }
+    (void)hipStreamSynchronize(wc->own_stream);
+    gate_leave(s, excl);
     if (!to_free.empty()) {
-      (void)hipStreamSynchronize(wc->own_stream);
       for (void* p : to_free)
         if (p) (void)hipFree(p);
       std::lock_guard<std::mutex> lp(s->pool->m);
@@ -568,16 +631,30 @@ kp_status kp_svd_batched(kp_ctx* c, int32_t nprob, const kp_blur* blurs, const i
   });
   std::vector<kp_status> res(nprob, KP_OK);
   std::vector<std::string> msg(nprob);
+  // Problems that would tune a launch shape run first, one at a time on worker
+  // 0 before the others start (the tuner then times its candidates on an
+  // otherwise idle GPU); the rest are shared out. Results do not depend on it.
+  std::vector<char> done(nprob, 0);
+  for (int wi = 0; wi < nw; ++wi) (void)hipStreamWaitEvent(c->workers[wi]->own_stream, start, 0);
+  for (int t = 0; t < nprob; ++t) {
+    const int i = order[t];
+    if (!needs_tuning(blurs[i], method[i], opts[i])) continue;
+    kp_ctx* w = c->workers[0];
+    (void)hipSetDevice(w->device);
+    res[i] = run_one(w, &blurs[i], method[i], opts[i], &out[i]);
+    if (is_error(res[i])) msg[i] = w->err;
+    done[i] = 1;
+  }
   std::atomic<int> next{0};
   std::vector<hipEvent_t> fin(nw, nullptr);
   auto body = [&](int wi) {
     kp_ctx* w = c->workers[wi];
     (void)hipSetDevice(w->device);
-    (void)hipStreamWaitEvent(w->own_stream, start, 0);
     for (;;) {
       const int t = next.fetch_add(1);
       if (t >= nprob) break;
       const int i = order[t];
+      if (done[i]) continue;
       res[i] = run_one(w, &blurs[i], method[i], opts[i], &out[i]);
       if (is_error(res[i])) msg[i] = w->err;
     }

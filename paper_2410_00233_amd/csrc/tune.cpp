@@ -60,6 +60,14 @@ double time_launches(hipStream_t s, int reps, const std::function<void()>& launc
   return ms < 0 ? -1.0 : (double)ms / reps;
 }
 
+bool tune_known(int op, int n, int a, int b) {
+  if (!tune_enabled()) return true;
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  std::lock_guard<std::mutex> lk(g_mu);
+  return g_table.count(std::make_tuple(op, dev, n, a, b)) != 0;
+}
+
 int tune_pick(int op, int n, int a, int b, int ncand, const std::function<double(int)>& cost) {
   // KPSB_TUNE_FORCE=v pins every operation to its variant v when that variant
   // applies (used to check that all variants agree bit for bit)
