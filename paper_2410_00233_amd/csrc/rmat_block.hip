@@ -239,10 +239,13 @@ __device__ __forceinline__ doublex4 mfma16x16x4(double a, double b, doublex4 c) 
 constexpr int kTK = 64;   // default K-tile (entries of r per staged X tile); 128, 192 also built
 constexpr int kKG = 16;   // K entries per group: 4 MFMA steps, 4 consecutive entries per lane
 
-// Row stride (elements) of the transposed X tile in LDS: KT plus 16 bytes, so that
-// the 16-byte reads of the 16 column lanes fall on distinct banks.
+// Row stride (elements) of the transposed X tile in LDS. The 16-byte reads of a
+// half-wave (16 row lanes x 2 lane groups 4 words apart) fall on distinct banks
+// when the stride is 8 (mod 16) words (measured on gfx950: 128-bit reads are
+// served 32 lanes at a time; 4 or 0 (mod 16) costs about 20 % more LDS
+// cycles): KT + 8 floats. Doubles (lane groups 8 words apart) keep KT + 2.
 template <typename T, int KT>
-constexpr int x_stride() { return KT + 16 / (int)sizeof(T); }
+constexpr int x_stride() { return KT + (sizeof(T) == 4 ? 8 : 2); }
 
 // K order. Column block c's range of r is shifted to start at r0(c) in {0,-1,-2,-3}
 // so that every 16-entry group starts at a slab column that is a multiple of 4;
@@ -511,20 +514,21 @@ rmat_block_kernel(const T* __restrict__ G, int ldg, int n, const T* __restrict__
 
 // Slab row stride for phases of CP column blocks: the groups of a column block
 // span 16 ntc entries (ntc = ceil((n + 3) / 16)), c spans CP values and the slab
-// has a margin of 4, so a row needs 16 ntc + CP + 3 columns; padded to 4 (mod 64)
-// words so that the 16-byte reads of the 16 row lanes fall on distinct banks.
+// has a margin of 4, so a row needs 16 ntc + CP + 3 columns; padded so that the
+// 16-byte reads of a half-wave fall on distinct banks (8 (mod 16) floats, as
+// for the X tile; 2 (mod 32) doubles).
 template <typename T>
 static int slab_stride(int n, int CP, int TK) {
   (void)TK;
   const int ntc = (n + 3 + kKG - 1) / kKG;
   const int W = kKG * ntc + CP + 3;
-  if (sizeof(T) == 4) return ((W + 63) / 64) * 64 + 4;     // 4 (mod 64) floats
+  if (sizeof(T) == 4) return ((W + 15) / 16) * 16 + 8;     // 8 (mod 16) floats
   return ((W + 31) / 32) * 32 + 2;                         // 2 (mod 32) doubles
 }
 
 template <typename T>
 static size_t block_lds(int n, int TJ, int CP, int TK) {
-  const int XT = TK + 16 / (int)sizeof(T);
+  const int XT = TK + (sizeof(T) == 4 ? 8 : 2);   // x_stride<T, TK>()
   return sizeof(T) * ((size_t)(16 + TJ - 1) * slab_stride<T>(n, CP, TK) + 2 * 32 * (size_t)XT);
 }
 

@@ -36,7 +36,9 @@ template <> struct Mfma16<__half> {
 
 constexpr int kKS = 32;      // K entries per MFMA step
 constexpr int kSPT = 4;      // MFMA K steps per staged tile (one barrier per tile)
-constexpr int kXS16 = kKS * kSPT + 8;   // LDS row stride of the staged X tile (16-bit elements)
+// LDS row stride of the staged X tile (16-bit elements): 72 words, 8 (mod 16),
+// so that the 16-byte fragment reads of a half-wave fall on distinct banks
+constexpr int kXS16 = kKS * kSPT + 16;
 
 // X16 is the pre-shifted 16-bit copy of X (launch_to16_shifted): column `col`,
 // K step ks = c * (LEN/32) + tt holds the 32 entries r0_c + 32 tt + (0..31) of
@@ -200,7 +202,7 @@ static int len16(int n) { return ((n + 7 + kKS - 1) / kKS) * kKS; }
 
 static int stride16(int n) {
   const int W = n + len16(n) - 1;          // largest slab column + 1
-  return ((W + 63) / 64) * 64 + 8;         // multiple of 8 (16-byte rows)
+  return ((W + 31) / 32) * 32 + 16;        // 8 (mod 16) words: distinct banks per half-wave
 }
 
 static size_t lds16(int n, int TJ) {
