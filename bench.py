@@ -36,8 +36,8 @@ MFMA_FP32_PEAK_TFLOPS = 157.3     # MI355X dense FP32 matrix peak
 # rocprofv3 FETCH_SIZE / WRITE_SIZE scaled by a plain copy of known size
 # (profiles/rmat_products_n512_hbm_counters.md), valid while the kernel source
 # is the one the counters were taken on.
-BLOCK_TRAFFIC_BYTES = 1.150e9
-BLOCK_TRAFFIC_SRC_SHA1 = "13608c503b486f981cc5c40f2e2508e1eedae50e"
+BLOCK_TRAFFIC_BYTES = 1.149e9
+BLOCK_TRAFFIC_SRC_SHA1 = "82a89990d1461909c142a1d88909d872220c3a00"
 BLOCK16_TRAFFIC_BYTES = 3.23e8
 # template arguments <TJ, JB, CB> of the FP32 block kernel per autotuner variant
 BLOCK_VARIANT_TEMPLATE = {0: "16,1,2,false,64", 1: "16,2,2,false,64", 2: "8,1,2,false,64",
@@ -45,7 +45,7 @@ BLOCK_VARIANT_TEMPLATE = {0: "16,1,2,false,64", 1: "16,2,2,false,64", 2: "8,1,2,
                           6: "8,1,2,false,128", 7: "8,1,1,false,128", 8: "16,1,2,false,192",
                           9: "16,2,2,false,192", 10: "8,1,2,false,192", 11: "8,1,1,false,192"}
 BLOCK16_VARIANT_TEMPLATE = {0: "32,4,2", 1: "16,4,2", 2: "32,2,2", 3: "16,2,2", 4: "16,1,2"}
-BLOCK16_TRAFFIC_SRC_SHA1 = "99d2488a0a799a69794c5027d6988ff96dd36b57"
+BLOCK16_TRAFFIC_SRC_SHA1 = "2b14a0e7ac0db9442062ad35a767984611a98c85"
 
 
 def counted_traffic(src, sha, value):
