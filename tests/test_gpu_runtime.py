@@ -87,6 +87,29 @@ def test_batched_empty_and_single(ctx):
     assert len(facs) == 1 and status[0] in (0, 100) and facs[0].k == probs[0][2].k
 
 
+def test_batched_with_untuned_sizes_equals_single_calls(ctx):
+    """Sizes no other test uses, so the batch meets them untuned: the problems
+    that tune run alone first, the rest concurrently; every result must still
+    equal its single call bit for bit, and the sizes end up tuned."""
+    from paper_2410_00233_amd import api
+    import torch
+    mix = wl.batched_mix(9, sizes=(18, 26, 34), ranks=(3, 6), p=4, seed=78)
+    probs = []
+    for d in mix:
+        blur = api.Blur(d["P"], d["cu"], d["cv"], d["n"])
+        probs.append((blur, "rsvd", api.Context.rsvd_opts(d["k"], d["p"], 2, prec="f32",
+                                                          seed=d["seed"]), d["k"]))
+    facs, status = ctx.kp_svd_batched(probs, nworkers=4)
+    torch.cuda.synchronize()
+    for (blur, _, o, _), f, st in zip(probs, facs, status):
+        assert st in (0, 100)
+        g = ctx.kp_svd_rsvd(blur, o.k, o.p, o.q, prec="f32", seed=o.seed)
+        assert np.array_equal(f.sigma[:f.k], g.sigma[:g.k])
+        assert torch.equal(f.Ax[:f.k], g.Ax[:g.k]) and torch.equal(f.Ay[:f.k], g.Ay[:g.k])
+    tuned = {r["n"] for r in ctx.kp_tune_report() if r["op"] == "block32"}
+    assert {18, 26, 34} <= tuned
+
+
 # ---------------------------------------------------------------------------
 # server
 
@@ -148,6 +171,39 @@ def test_server_result_is_the_same_alone_and_in_the_mix(ctx):
     st = srv.stats()
     assert st["completed"] == len(specs) and st["peak_running"] >= 2
     srv.close()
+
+
+def test_server_untuned_sizes_and_ranks_same_as_direct(ctx):
+    """Requests of sizes and ranks no other test uses, submitted at once to a
+    4-slot server: jobs that would tune run alone (RSVD factors of a new size;
+    EGKB factors tune nothing, but their solve meets a new (n, k) of the apply
+    GEMMs and finishes alone). Each result must equal the direct calls'."""
+    from paper_2410_00233_amd import api
+    import torch
+    specs = [(22, 5, True, "rsvd", 4), (30, 6, False, "gkb", 6), (22, 7, False, "gkb", 7),
+             (38, 8, True, "rsvd", 4), (30, 9, True, "rsvd", 6)]
+    data = [_request_data(n, pid, 50 + i) for i, (n, pid, *_rest) in enumerate(specs)]
+    srv = api.Server(ctx, slots=4)
+    xs, tickets = [], []
+    for (n, pid, iso, meth, k), (P, cu, cv, b) in zip(specs, data):
+        bd = _dev(b)
+        x = torch.empty_like(bd)
+        xs.append(x)
+        tickets.append(srv.submit(api.Blur(P, cu, cv, n), bd, x, psf_key=300 + pid, method=meth,
+                                  k=k, p=4, q=2, prec="f32", seed=9, iso=iso, **SB_KW))
+    res = [srv.wait(t) for t in tickets]
+    srv.close()
+    for (n, pid, iso, meth, k), (P, cu, cv, b), r, x in zip(specs, data, res, xs):
+        assert r["status"] == 0, r["msg"]
+        blur = api.Blur(P, cu, cv, n)
+        if meth == "rsvd":
+            f = ctx.kp_svd_rsvd(blur, k, 4, 2, prec="f32", seed=9)
+        else:
+            f = ctx.kp_svd_gkb(blur, k, 4, prec="f32", seed=9)
+        fn = ctx.sb_solve_iso if iso else ctx.sb_solve_aniso
+        xd, st = fn(f, _dev(b), **SB_KW)
+        assert torch.equal(x, xd)
+        assert r["iota_total"] == st["iota_total"]
 
 
 def test_server_restored_image_matches_oracle(ctx):
