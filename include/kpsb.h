@@ -270,7 +270,10 @@ kp_status sb_solve_iso(kp_ctx* ctx, const kp_factors* f, const double* b,
  * same arguments and gives the same result (same kernels, same reduction
  * order). The problems run concurrently on `nworkers` worker contexts
  * (0 selects 4; at most 16), each with its own stream and workspace charged to
- * ctx's HBM budget; workers take problems largest first (estimated time). Every
+ * ctx's HBM budget; workers take problems largest first (estimated time).
+ * Problems whose launch shapes the autotuner has not chosen yet (a size not
+ * seen before in the process) run first, one at a time, so that the tuner
+ * times its candidates on an otherwise idle GPU. Every
  * worker stream first waits for the work already queued on `stream`, and
  * `stream` waits for all workers at the end. The call returns when every
  * problem is finished (host outputs written).
@@ -297,6 +300,11 @@ kp_status kp_svd_batched(kp_ctx* ctx, int32_t nprob, const kp_blur* blurs,
  * recently used factor sets that no running request holds are evicted when
  * memory or the entry limit requires. A request whose footprint alone exceeds
  * the budget is refused by kp_server_submit (KP_E_NOMEM).
+ *
+ * Tuning. A request that would make the autotuner choose a launch shape (the
+ * first factor computation at a new size, or the first solve at a new size and
+ * rank) waits until the running requests have finished and runs alone; the
+ * others wait for it. This happens once per shape in the process.
  *
  * Results. Each request runs on one worker with its own stream and workspace,
  * so its output does not depend on what else runs (the same kernels and
