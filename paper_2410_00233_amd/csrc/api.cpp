@@ -238,7 +238,7 @@ kp_status build_grids(kp_ctx* c, const kp_blur* b, const double* dpsf, hipStream
   const int n = b->n;
   g->ldg = grid_ld(n);
   g->terms = make_terms(b->bc, n);
-  const size_t cnt = (size_t)(2 * n - 1) * g->ldg;
+  const size_t cnt = (size_t)g->ldg * g->ldg;   // square: see launch_build_grid
   for (int t = 0; t < g->terms.nterm; ++t) {
     const std::string sfx = std::string(tname<T>()) + (t ? "_" + std::to_string(t) : "");
     KP_TRY(wsT(c, "G_" + sfx, cnt, &g->Gs[t]));
@@ -475,7 +475,9 @@ kp_status gemv_product1(kp_ctx* c, const Grids<T>& g, int n, int transpose, cons
     float* xt = nullptr;
     KP_TRY(wsT(c, "gemv_xt", (size_t)gemv_sx_xt_len(n), &xt));
     ProfScope ps(c, s, 1, 2.0 * NN * NN);
-    launch_rmat_gemv_sx(transpose ? g.Gt : g.G, g.ldg, n, x, xt, y, z, coef, s,
+    // the kernel reads the grid of op(R) column by column: from the transposed
+    // grid's rows
+    launch_rmat_gemv_sx(transpose ? g.G : g.Gt, g.ldg, n, x, xt, y, z, coef, s,
                         transpose ? g.boxt[0] : g.box[0]);
     return check_launch(c, "rmat_gemv_sx");
   }

@@ -34,6 +34,8 @@ struct GridShifts {
   int sv[5] = {0, 0, 0, 0, 0};
   int su[5] = {0, 0, 0, 0, 0};
 };
+// G: ldg x ldg, ldg = grid_ld(n); the entries of rows or columns beyond 2n - 1
+// are zero (so the grid may also be read column by column past its edge).
 template <typename T>
 void launch_build_grid(const double* psf, int pu, int pv, int cu, int cv, int n,
                        int transpose, const GridShifts& sh, T* G, int ldg, hipStream_t s);
@@ -111,7 +113,8 @@ void launch_to16_shifted(const float* in, long ldx, int n, int ncols, H* out, lo
 inline int grid_ld(int n) { return ((2 * n - 1 + 48) + 7) & ~7; }
 
 // FP32 y = R x - coef * z with x in scalar registers; xt is workspace of
-// gemv_sx_xt_len(n) floats. G must have the row stride grid_ld(n).
+// gemv_sx_xt_len(n) floats. GT is the TRANSPOSE of the grid of R (entry (a, b)
+// at GT[b * ldg + a]), ldg x ldg with ldg = grid_ld(n) (launch_build_grid).
 long gemv_sx_xt_len(int n);
 void launch_rmat_gemv_sx(const float* G, int ldg, int n, const float* x, float* xt, float* y,
                          const float* z, double coef, hipStream_t s, const int* box = nullptr);

@@ -58,14 +58,14 @@ __global__ void build_grid_kernel(const double* __restrict__ psf, int pu, int pv
                                   int cv, int n, int transpose, GridShifts sh,
                                   T* __restrict__ G, int ldg) {
   const int g2 = 2 * n - 1;
-  const long total = (long)g2 * ldg;
+  const long total = (long)ldg * ldg;   // ldg x ldg: zero rows and columns beyond 2n - 1
   for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total;
        e += (long)gridDim.x * blockDim.x) {
     const int a = (int)(e / ldg);
     const int b = (int)(e - (long)a * ldg);
     double v = 0.0;
-    if (b < g2) v = transpose ? grid_value(psf, pu, pv, cu, cv, n, b, a, sh)
-                              : grid_value(psf, pu, pv, cu, cv, n, a, b, sh);
+    if (a < g2 && b < g2) v = transpose ? grid_value(psf, pu, pv, cu, cv, n, b, a, sh)
+                                        : grid_value(psf, pu, pv, cu, cv, n, a, b, sh);
     G[e] = from_double<T>(v);
   }
 }
@@ -143,7 +143,7 @@ void launch_build_grid_split(const double* psf, int pu, int pv, int cu, int cv, 
 template <typename T>
 void launch_build_grid(const double* psf, int pu, int pv, int cu, int cv, int n,
                        int transpose, const GridShifts& sh, T* G, int ldg, hipStream_t s) {
-  long total = (long)(2 * n - 1) * ldg;
+  long total = (long)ldg * ldg;
   int blocks = (int)((total + 255) / 256);
   if (blocks > 4096) blocks = 4096;
   hipLaunchKernelGGL(build_grid_kernel<T>, dim3(blocks), dim3(256), 0, s, psf, pu, pv, cu,

@@ -110,9 +110,13 @@ rmat_gemv_kernel(const T* __restrict__ G, int ldg, int n, const T* __restrict__ 
 // entry for all of them. Row (i, j) of R is G[a][r - c + n - 1] with
 // a = i - j + n - 1: for a chunk of kSxR consecutive r and c stepping down
 // from n - 1, the needed grid entries slide up by one per step, so each row
-// keeps a register window of its grid row, refilled with one 16-byte load per
-// 4 steps (a ring of four 4-entry slots). Every entry of R is still formed and
-// multiplied (2 n^4 flops per product).
+// keeps a register window of its grid row, refilled with 4 entries per 4 steps
+// (a ring of four 4-entry slots). The grid is read in transposed storage, one
+// column per load: the 64 lanes of a wave need 19 consecutive rows a of the
+// same column, one or two cache lines, where 16-byte loads along the rows would
+// touch 19 lines per load (measured: the row-wise window loads halve the FMA
+// rate; column-wise ones cost about a fifth). Every entry of R is still formed
+// and multiplied (2 n^4 flops per product).
 //
 // x is first re-laid out (launch_gemv_xt) as xt[ch][u][q] = x[r + n c] with
 // r = kSxR ch + q, c = n - 1 - u, zero for r >= n or u >= n, U = steps per
@@ -160,7 +164,7 @@ __global__ void gemv_xt_kernel(const float* __restrict__ x, int n, int U, int nc
 // slower dense and 35-40 % slower with a support box, where chunks are short).
 template <int kSxP, int kSxV, int kSxW, bool CMP>
 __global__ void __launch_bounds__(64 * kSxV * kSxW)
-rmat_gemv_sx_kernel(const float* __restrict__ G, int ldg, int n, const float* __restrict__ xt,
+rmat_gemv_sx_kernel(const float* __restrict__ GT, int ldg, int n, const float* __restrict__ xt,
                     int U, float* __restrict__ y, const float* __restrict__ z, double coef,
                     const int* __restrict__ box) {
   __shared__ double red[kSxW][kSxV][kSxP][64];
@@ -172,13 +176,30 @@ rmat_gemv_sx_kernel(const float* __restrict__ G, int ldg, int n, const float* __
   const int it = blockIdx.x % n_it, jt = blockIdx.x / n_it;
   const int i = it * 16 + (lane & 15);
   const int jb = (jt * kSxV + rw) * 4 * kSxP + (lane >> 4);
-  const float* grow[kSxP];
+  // lane's grid row a = i - j + n - 1, read along its columns b in the
+  // transposed storage (GT[b ldg + a]): the lanes of a wave read the 19
+  // consecutive entries a of one column per load instead of 19 rows
+  // Buffer loads over the ldg x ldg grid: the lane's row is a fixed byte offset,
+  // the column a uniform (scalar) offset, so no per-load address arithmetic.
+  // (lane offsets: the row, plus 0..3 columns; one scalar offset per slot)
+  const int colb = 4 * ldg;   // bytes per grid column in the transposed storage
+  int aoff[kSxP][4];
 #pragma unroll
   for (int p = 0; p < kSxP; ++p) {
     const int j = jb + 4 * p;
     const bool ok = i < n && j < n;
-    grow[p] = G + (long)(ok ? i - j + n - 1 : 0) * ldg;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) aoff[p][k] = 4 * (ok ? i - j + n - 1 : 0) + k * colb;
   }
+  const __amdgpu_buffer_rsrc_t grs = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<float*>(GT), 0, (int)(4L * ldg * ldg), 0x00020000);
+  auto ld1 = [&](int p, int k, int soff) {
+    return __int_as_float(__builtin_amdgcn_raw_buffer_load_b32(grs, aoff[p][k], soff, 0));
+  };
+  auto slot = [&](int p, int b) {   // entries b .. b + 3 of the lane's grid row
+    const int s0 = b * colb;
+    return make_float4(ld1(p, 0, s0), ld1(p, 1, s0), ld1(p, 2, s0), ld1(p, 3, s0));
+  };
   const int nch = (n + kSxR - 1) / kSxR;
   const int ngrp = U / 4;                 // groups of 4 steps (multiple of 4)
   int bl = 0, bh = 0;
@@ -214,7 +235,7 @@ rmat_gemv_sx_kernel(const float* __restrict__ G, int ldg, int n, const float* __
       for (int p = 0; p < kSxP; ++p)
 #pragma unroll
         for (int t = 0; t < 3; ++t)
-          S[p][t] = *reinterpret_cast<const float4*>(grow[p] + r0 + 4 * (gbeg + t));
+          S[p][t] = slot(p, r0 + 4 * (gbeg + t));
       float xa[4 * kSxR], xb[4 * kSxR];
       auto ldx = [&](float (&d)[4 * kSxR], int g) {
         const float* src = xp + (long)g * 4 * kSxR;
@@ -230,7 +251,7 @@ rmat_gemv_sx_kernel(const float* __restrict__ G, int ldg, int n, const float* __
           float(&xn)[4 * kSxR] = (gg & 1) ? xa : xb;
 #pragma unroll
           for (int p = 0; p < kSxP; ++p)
-            S[p][(gg + 3) & 3] = *reinterpret_cast<const float4*>(grow[p] + r0 + 4 * (g + 3));
+            S[p][(gg + 3) & 3] = slot(p, r0 + 4 * (g + 3));
           if ((gg & 1) == 0) {
 #pragma unroll
             for (int p = 0; p < kSxP; ++p) pp[p] = 0.f;

@@ -132,7 +132,7 @@ size_t sb_bytes(int n, int k) {
 size_t svd_bytes(const kp_request& r) {
   const int n = r.blur.n;
   const size_t N = (size_t)n * n;
-  const size_t grid = (size_t)(2 * n - 1) * (size_t)(((2 * n - 1) + 7) & ~7);
+  const size_t grid = (size_t)grid_ld(n) * (size_t)grid_ld(n);
   size_t b = round256((size_t)r.blur.pu * r.blur.pv * 8);
   // reflexive boundary conditions: four grid pairs, the reversed input and
   // three term outputs of the widest product
