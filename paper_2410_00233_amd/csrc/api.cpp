@@ -472,6 +472,10 @@ kp_status gemv_product1(kp_ctx* c, const Grids<T>& g, int n, int transpose, cons
                         const T* z, double coef, hipStream_t s) {
   const double NN = (double)n * n;
   if constexpr (std::is_same<T, float>::value) {
+    // the kernel addresses the ldg x ldg grid through a buffer resource whose
+    // size is a 32-bit byte count (n <= 2048 keeps it under 69 MB)
+    if (4L * g.ldg * g.ldg > 0x7fffffffL)
+      return set_err(c, KP_E_INVAL, "grid too large for the matrix-vector kernel");
     float* xt = nullptr;
     KP_TRY(wsT(c, "gemv_xt", (size_t)gemv_sx_xt_len(n), &xt));
     ProfScope ps(c, s, 1, 2.0 * NN * NN);
