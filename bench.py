@@ -44,7 +44,8 @@ BLOCK_VARIANT_TEMPLATE = {0: "16,1,2,false,64", 1: "16,2,2,false,64", 2: "8,1,2,
                           3: "8,1,1,false,64", 4: "16,1,2,false,128", 5: "16,2,2,false,128",
                           6: "8,1,2,false,128", 7: "8,1,1,false,128", 8: "16,1,2,false,192",
                           9: "16,2,2,false,192", 10: "8,1,2,false,192", 11: "8,1,1,false,192"}
-BLOCK16_VARIANT_TEMPLATE = {0: "32,4,2", 1: "16,4,2", 2: "32,2,2", 3: "16,2,2", 4: "16,1,2"}
+BLOCK16_VARIANT_TEMPLATE = {0: "32,4,2", 1: "16,4,2", 2: "32,2,2", 3: "16,2,2", 4: "16,1,2",
+                            5: "64,4,2"}
 BLOCK16_TRAFFIC_SRC_SHA1 = "2b14a0e7ac0db9442062ad35a767984611a98c85"
 
 

@@ -47,7 +47,7 @@ constexpr int kXS16 = kKS * kSPT + 16;
 template <typename H, int TJ, int JB, int CB>
 __global__ void __launch_bounds__(64 * (2 * TJ) / (JB * CB))
 rmat_block16_kernel(const H* __restrict__ G, int ldg, int n, const H* __restrict__ X, long ldx,
-                    float* __restrict__ Y, long ldy, int ncols, int SW, int LEN,
+                    float* __restrict__ Y, long ldy, int ncols, int SW, int LEN, int CP,
                     const double* __restrict__ inv_scale, int accumulate) {
   constexpr int WAVES = (2 * TJ) / (JB * CB);
   constexpr int NT = 64 * WAVES;
@@ -75,16 +75,27 @@ rmat_block16_kernel(const H* __restrict__ G, int ldg, int n, const H* __restrict
   const int g2 = 2 * n - 1;
   const int a0 = i0 - j0 - (TJ - 1) + n - 1;
 
-  for (int al = 0; al < SR; ++al) {
-    const int a = a0 + al;
-    const bool rowok = (a >= 0) && (a < g2);
-    const u16* src = Gb + (long)(rowok ? a : 0) * ldg;
-    for (int col = tid; col < SW; col += NT) {
-      u16 v = 0;
-      if (rowok && col < g2) v = src[col];
-      slab[al * SW + col] = v;
+  // Slab phases: column blocks c in [c0, c0 + CP) need the grid columns from
+  // gcol0 = floor8(n - 1 - (c_last) - 7) on (slab column s holds grid column
+  // gcol0 + s); CP * ntc is a multiple of kSPT, so a tile never spans two
+  // phases, and the slab is reloaded between tiles.
+  int gcol0 = 0;
+  auto load_slab = [&](int c0) {
+    const int c1 = min(c0 + CP, n);
+    gcol0 = (n - 1 - (c1 - 1) - 7) & ~7;
+    for (int al = 0; al < SR; ++al) {
+      const int a = a0 + al;
+      const bool rowok = (a >= 0) && (a < g2);
+      const u16* src = Gb + (long)(rowok ? a : 0) * ldg;
+      for (int col = tid; col < SW; col += NT) {
+        const int gc = gcol0 + col;
+        u16 v = 0;
+        if (rowok && gc >= 0 && gc < g2) v = src[gc];
+        slab[al * SW + col] = v;
+      }
     }
-  }
+  };
+  load_slab(0);
 
   const int ntc = LEN / kKS;                   // K steps per column block
   const int total_ks = n * ntc;
@@ -145,7 +156,7 @@ rmat_block16_kernel(const H* __restrict__ G, int ldg, int n, const H* __restrict
     for (int s = 0; s < kSPT; ++s) {
       const int ks = t * kSPT + s;
       if (ks < total_ks) {
-        const int colbase = -((n - 1 - c) & 7) - c + n - 1 + tt * kKS;   // multiple of 8
+        const int colbase = -((n - 1 - c) & 7) - c + n - 1 + tt * kKS - gcol0;   // multiple of 8
         vec bfr[CB];
 #pragma unroll
         for (int cb = 0; cb < CB; ++cb)
@@ -176,6 +187,11 @@ rmat_block16_kernel(const H* __restrict__ G, int ldg, int n, const H* __restrict
     }
     if (t + 1 < ntiles) store_tile((t + 1) & 1);
     __syncthreads();
+    const int ks_next = (t + 1) * kSPT;
+    if (ks_next < total_ks && ks_next % (CP * ntc) == 0) {   // next phase (c = ks_next / ntc)
+      load_slab(ks_next / ntc);
+      __syncthreads();
+    }
   }
 
   const double osc = inv_scale ? *inv_scale : 1.0;   // undo the operands' power-of-2 scaling
@@ -200,13 +216,15 @@ rmat_block16_kernel(const H* __restrict__ G, int ldg, int n, const H* __restrict
 
 static int len16(int n) { return ((n + 7 + kKS - 1) / kKS) * kKS; }
 
-static int stride16(int n) {
-  const int W = n + len16(n) - 1;          // largest slab column + 1
+// Slab row stride for phases of CP column blocks: a phase spans at most
+// min(CP, n) + LEN + 13 grid columns from its 8-aligned start.
+static int stride16(int n, int CP) {
+  const int W = std::min(CP, n) + len16(n) + 16;
   return ((W + 31) / 32) * 32 + 16;        // 8 (mod 16) words: distinct banks per half-wave
 }
 
-static size_t lds16(int n, int TJ) {
-  return 2 * ((size_t)(16 + TJ - 1) * stride16(n) + 2 * 32 * kXS16);
+static size_t lds16(int n, int TJ, int CP) {
+  return 2 * ((size_t)(16 + TJ - 1) * stride16(n, CP) + 2 * 32 * kXS16);
 }
 
 // Length (16-bit elements) of one column of the pre-shifted X16 copy, padded to
@@ -217,11 +235,19 @@ long x16_column_len(int n) {
   return ((total + tile - 1) / tile) * tile;
 }
 
+// One phase (CP = n) if the slab fits, else phases of CP column blocks, CP a
+// multiple of kSPT (so phases start on tile boundaries), halved until it fits.
 bool plan_block16_tj(int n, size_t lds_limit, int TJ, BlockPlan* plan) {
-  const size_t lds = lds16(n, TJ);
-  if (lds > lds_limit) return false;
+  int CP = n;
+  if (lds16(n, TJ, CP) > lds_limit) {
+    CP = 512;
+    while (CP >= 16 && (CP >= n || lds16(n, TJ, CP) > lds_limit)) CP /= 2;
+    if (CP < 16) return false;
+  }
+  const size_t lds = lds16(n, TJ, CP);
   plan->TJ = TJ;
-  plan->SW = stride16(n);
+  plan->CP = CP;
+  plan->SW = stride16(n, CP);
   plan->lds = lds;
   plan->grid = ((n + 15) / 16) * ((n + TJ - 1) / TJ);
   plan->waves = 0;
@@ -251,7 +277,7 @@ static void launch16_tj(const BlockPlan& p, const H* G, int ldg, int n, const H*
                               (int)p.lds);
   const int grid = p.grid_limit > 0 && p.grid_limit < p.grid ? p.grid_limit : p.grid;
   hipLaunchKernelGGL(kern, dim3(grid), dim3(threads), p.lds, s, G, ldg, n, X, ldx, Y, ldy,
-                     ncols, p.SW, len16(n), inv_scale, accumulate);
+                     ncols, p.SW, len16(n), p.CP, inv_scale, accumulate);
 }
 
 template <typename H>
@@ -261,6 +287,10 @@ void launch_rmat_block16(const BlockPlan& p, const H* G16, int ldg, int n, const
   // waves per workgroup (p.waves, 0 = the default): more waves hide the LDS
   // latency of the fragment reads better, fewer row blocks per wave read more
   // LDS per MFMA; chosen by the autotuner
+  if (p.TJ == 64) {
+    launch16_tj<H, 64, 4, 2>(p, G16, ldg, n, X16, ldx, Y, ldy, ncols, inv_scale, accumulate, s);
+    return;
+  }
   if (p.TJ == 32 && p.waves == 16) {
     launch16_tj<H, 32, 2, 2>(p, G16, ldg, n, X16, ldx, Y, ldy, ncols, inv_scale, accumulate, s);
     return;
