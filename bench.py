@@ -147,6 +147,41 @@ def bench_batched(ctx, count):
     }
 
 
+def bench_paper_settings(ctx):
+    """The paper's two other KP-SVD settings with R(A) generated from the PSF:
+    n = 100 (7 x 7 speckle-like PSF, zero BC, k = 5, p = 2) and n = 200 (11 x 11,
+    zero BC, k = 16, p = 4); EGKB(SP) with full reorthogonalization and
+    RSVD(SP) with q = 1, FP32, median of 5 calls. The paper's times are quoted
+    as context (Matlab on an Apple M2 Max CPU, with its own PSFs)."""
+    import numpy as np
+    import torch
+
+    import workloads as wl
+    from paper_2410_00233_amd import api
+    out = {}
+    for n, half, k, p, paper in ((100, 4, 5, 2, "Table 4: EGKB(SP) 0.14 s, RSVD(SP) 0.22 s"),
+                                 (200, 6, 16, 4, "Table 8: EGKB(SP) 4.37 s, RSVD(SP) 3.94 s")):
+        P, cu, cv = wl.speckle_psf(half, seed=wl.SEED_PSF + 900 + n)
+        blur = api.Blur(P, cu, cv, n, on_device=True)
+        res = {"workload": f"n={n}, {P.shape[0]}x{P.shape[1]} speckle-like PSF, zero BC, "
+                           f"k={k}, p={p}, FP32, R(A) generated"}
+        for name, fn in (("egkb_sp_ms", lambda: ctx.kp_svd_gkb(blur, k, p, prec="f32", seed=1)),
+                         ("rsvd_sp_ms", lambda: ctx.kp_svd_rsvd(blur, k, p, 1, prec="f32",
+                                                               seed=2))):
+            fn()
+            times = []
+            for _ in range(5):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                fn()
+                torch.cuda.synchronize()
+                times.append(1e3 * (time.perf_counter() - t0))
+            res[name] = round(float(np.median(times)), 3)
+        res["paper_context"] = paper + " (Matlab, Apple M2 Max CPU, its own speckle PSFs)"
+        out[f"n{n}"] = res
+    return out
+
+
 def bench_paper_pipeline(ctx, n=128):
     """The paper's own pipeline on its "Medium" setting (n = 128, reflexive
     boundary conditions, a 15 x 15 speckle-like PSF, k = 8, p = 4): explicit A,
@@ -626,6 +661,8 @@ def main():
     if not args.no_paper_pipeline:
         log("explicit-matrix pipeline at n=128 (reflexive BC)")
         line["paper_pipeline_n128"] = bench_paper_pipeline(ctx)
+        log("the paper's n=100 and n=200 KP-SVD settings")
+        line["paper_settings"] = bench_paper_settings(ctx)
     line["autotune"] = ctx.kp_tune_report()
     if not args.no_cpu_baseline:
         log("CPU oracle baseline")

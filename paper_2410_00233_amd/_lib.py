@@ -105,6 +105,14 @@ def load(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise RuntimeError(f"{path} is missing: build it with `python -m paper_2410_00233_amd.build`")
+    # PyTorch (which owns device memory and streams here) ships its own HIP
+    # runtime; one runtime serves the process, the first one loaded. Load
+    # PyTorch's before the library so that both use it: with the system
+    # runtime loaded first, PyTorch finds no GPU.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = C.CDLL(path)
     vp = C.c_void_p
     lib.kp_ctx_create.argtypes = [C.c_int, C.c_size_t, C.POINTER(vp)]

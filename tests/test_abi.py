@@ -108,3 +108,18 @@ def test_ctypes_layout_matches_header(tmp_path):
             assert getattr(m[t], rename.get(f, f)).offset == int(val), key
         else:
             assert C.sizeof(m[key]) == int(val), key
+
+
+def test_library_loads_after_torch():
+    """PyTorch's HIP runtime must be the process's one (loaded before the
+    library), or PyTorch finds no GPU once the library has initialised HIP:
+    loading the library in a fresh process imports torch first."""
+    import subprocess
+    import sys
+    code = ("import sys; from paper_2410_00233_amd import _lib; "
+            "assert 'torch' not in sys.modules; _lib.load(); "
+            "assert 'torch' in sys.modules; print('ok')")
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True,
+                       cwd=str(__import__("pathlib").Path(__file__).resolve().parents[1]),
+                       timeout=300)
+    assert r.returncode == 0 and r.stdout.strip().endswith("ok"), r.stderr[-2000:]
