@@ -45,7 +45,7 @@ BLOCK_VARIANT_TEMPLATE = {0: "16,1,2,false,64", 1: "16,2,2,false,64", 2: "8,1,2,
                           6: "8,1,2,false,128", 7: "8,1,1,false,128", 8: "16,1,2,false,192",
                           9: "16,2,2,false,192", 10: "8,1,2,false,192", 11: "8,1,1,false,192"}
 BLOCK16_VARIANT_TEMPLATE = {0: "32,4,2", 1: "16,4,2", 2: "32,2,2", 3: "16,2,2", 4: "16,1,2",
-                            5: "64,4,2"}
+                            5: "64,4,2", 6: "64,8,2"}
 BLOCK16_TRAFFIC_SRC_SHA1 = "9a9589ae055b8fff8461014811e8291f323b2f8a"
 
 

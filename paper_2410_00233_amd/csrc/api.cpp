@@ -332,8 +332,8 @@ struct Block16Variant {
   int TJ, waves;
 };
 constexpr Block16Variant kBlock16Variants[] = {{32, 8}, {16, 4}, {32, 16}, {16, 8}, {16, 16},
-                                               {64, 16}};
-constexpr int kNumBlock16Variants = 6;
+                                               {64, 16}, {64, 8}};
+constexpr int kNumBlock16Variants = 7;
 
 template <typename T>
 kp_status choose_block_plan(kp_ctx* c, const Grids<T>& g, int n, const T* X, T* Y, int nc,

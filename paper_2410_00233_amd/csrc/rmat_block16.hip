@@ -287,6 +287,10 @@ void launch_rmat_block16(const BlockPlan& p, const H* G16, int ldg, int n, const
   // waves per workgroup (p.waves, 0 = the default): more waves hide the LDS
   // latency of the fragment reads better, fewer row blocks per wave read more
   // LDS per MFMA; chosen by the autotuner
+  if (p.TJ == 64 && p.waves == 8) {
+    launch16_tj<H, 64, 8, 2>(p, G16, ldg, n, X16, ldx, Y, ldy, ncols, inv_scale, accumulate, s);
+    return;
+  }
   if (p.TJ == 64) {
     launch16_tj<H, 64, 4, 2>(p, G16, ldg, n, X16, ldx, Y, ldy, ncols, inv_scale, accumulate, s);
     return;
