@@ -38,7 +38,7 @@ MFMA_FP32_PEAK_TFLOPS = 157.3     # MI355X dense FP32 matrix peak
 # is the one the counters were taken on.
 BLOCK_TRAFFIC_BYTES = 1.149e9
 BLOCK_TRAFFIC_SRC_SHA1 = "5a4aa3b724db7759838341bf3387aa54d6904547"
-BLOCK16_TRAFFIC_BYTES = 1.94e8
+BLOCK16_TRAFFIC_BYTES = 1.92e8
 # template arguments <TJ, JB, CB> of the FP32 block kernel per autotuner variant
 BLOCK_VARIANT_TEMPLATE = {0: "16,1,2,false,64", 1: "16,2,2,false,64", 2: "8,1,2,false,64",
                           3: "8,1,1,false,64", 4: "16,1,2,false,128", 5: "16,2,2,false,128",
@@ -46,7 +46,7 @@ BLOCK_VARIANT_TEMPLATE = {0: "16,1,2,false,64", 1: "16,2,2,false,64", 2: "8,1,2,
                           9: "16,2,2,false,192", 10: "8,1,2,false,192", 11: "8,1,1,false,192"}
 BLOCK16_VARIANT_TEMPLATE = {0: "32,4,2", 1: "16,4,2", 2: "32,2,2", 3: "16,2,2", 4: "16,1,2",
                             5: "64,4,2", 6: "64,8,2"}
-BLOCK16_TRAFFIC_SRC_SHA1 = "9a9589ae055b8fff8461014811e8291f323b2f8a"
+BLOCK16_TRAFFIC_SRC_SHA1 = "9208c1360feb4fa285b091e09c9a641b7d2a83ac"
 
 
 def counted_traffic(src, sha, value):
