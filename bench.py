@@ -393,7 +393,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the KP-SVD path is built and timed on a single "
-              "MI355X (see the sharding notes in DESIGN.md); run with --gpus 1.", file=sys.stderr)
+              "MI355X (multi-GPU sharding is designed but not built); run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

@@ -28,7 +28,7 @@ constexpr int kRedThreads = 256;
 // of a term is G[a][b] = sum over s1 in sv, s2 in su of
 // P[cu + (b - (n-1)) + s2, cv + (a - (n-1)) + s1] (periodic: shifts n m,
 // m = -2..2, in both dimensions; reflexive: the even shifts 2n m or the odd
-// shifts n - 2n m, m = -1..1, per dimension, see RmatTerms in the driver).
+// shifts n - 2n m, m = -1..1, per dimension; RmatTerms in api.cpp lists them).
 struct GridShifts {
   int nv = 1, nu = 1;
   int sv[5] = {0, 0, 0, 0, 0};

@@ -3,7 +3,7 @@
 
 kp_apply: FP64 both sides, |err| <= 1e-13 * max|ref|.
 SB: restored image rel-L2 <= 1e-6 against the oracle with fixed iteration
-counts (the spec gate); with the paper's tolerances the stopping counts
+counts (the stated tolerance for restored images); with the paper's tolerances the stopping counts
 must agree as well.
 """
 import numpy as np
