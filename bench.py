@@ -43,7 +43,9 @@ BLOCK16_TRAFFIC_BYTES = 1.92e8
 BLOCK_VARIANT_TEMPLATE = {0: "16,1,2,false,64", 1: "16,2,2,false,64", 2: "8,1,2,false,64",
                           3: "8,1,1,false,64", 4: "16,1,2,false,128", 5: "16,2,2,false,128",
                           6: "8,1,2,false,128", 7: "8,1,1,false,128", 8: "16,1,2,false,192",
-                          9: "16,2,2,false,192", 10: "8,1,2,false,192", 11: "8,1,1,false,192"}
+                          9: "16,2,2,false,192", 10: "8,1,2,false,192", 11: "8,1,1,false,192",
+                          12: "16,1,2,false,176", 13: "16,2,2,false,176", 14: "8,1,2,false,176",
+                          15: "8,1,1,false,176"}
 BLOCK16_VARIANT_TEMPLATE = {0: "32,4,2", 1: "16,4,2", 2: "32,2,2", 3: "16,2,2", 4: "16,1,2",
                             5: "64,4,2", 6: "64,8,2"}
 BLOCK16_TRAFFIC_SRC_SHA1 = "9208c1360feb4fa285b091e09c9a641b7d2a83ac"

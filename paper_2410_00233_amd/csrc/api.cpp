@@ -326,8 +326,9 @@ struct BlockVariant {
 };
 constexpr BlockVariant kBlockVariants[] = {{16, 16, 64},  {16, 8, 64},  {8, 8, 64},  {8, 16, 64},
                                            {16, 16, 128}, {16, 8, 128}, {8, 8, 128}, {8, 16, 128},
-                                           {16, 16, 192}, {16, 8, 192}, {8, 8, 192}, {8, 16, 192}};
-constexpr int kNumBlockVariants = 12;
+                                           {16, 16, 192}, {16, 8, 192}, {8, 8, 192}, {8, 16, 192},
+                                           {16, 16, 176}, {16, 8, 176}, {8, 8, 176}, {8, 16, 176}};
+constexpr int kNumBlockVariants = 16;
 struct Block16Variant {
   int TJ, waves;
 };

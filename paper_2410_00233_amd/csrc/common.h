@@ -55,7 +55,7 @@ struct BlockPlan {
   size_t lds;  // dynamic LDS bytes
   int grid;    // workgroups
   int waves = 0;       // waves per workgroup (0: the default for TJ)
-  int TK = 64;         // K-tile entries (FP32/FP64 block product: 64 or 128)
+  int TK = 64;         // K-tile entries (FP32/FP64 block product: 64, 128, 176 or 192)
   int grid_limit = 0;  // > 0: launch only the first grid_limit workgroups (tuning samples)
 };
 template <typename T>

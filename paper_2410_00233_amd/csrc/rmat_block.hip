@@ -236,7 +236,7 @@ __device__ __forceinline__ doublex4 mfma16x16x4(double a, double b, doublex4 c) 
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
-constexpr int kTK = 64;   // default K-tile (entries of r per staged X tile); 128, 192 also built
+constexpr int kTK = 64;   // default K-tile (entries of r per staged X tile); 128, 176, 192 also built
 constexpr int kKG = 16;   // K entries per group: 4 MFMA steps, 4 consecutive entries per lane
 
 // Row stride (elements) of the transposed X tile in LDS. The 16-byte reads of a
@@ -271,7 +271,8 @@ rmat_block_kernel(const T* __restrict__ G, int ldg, int n, const T* __restrict__
   constexpr int NT = 64 * WAVES;
   constexpr int SR = 16 + TJ - 1;
   constexpr int WC = 2 / CB;                 // waves along the 32 output columns
-  constexpr int LPT = (KT * 32) / NT;        // X elements staged per thread
+  constexpr int LPT = (KT * 32 + NT - 1) / NT;   // X elements staged per thread
+  constexpr bool LFULL = (KT * 32) % NT == 0;    // else the last round is partial
   constexpr int GPT = KT / kKG;              // groups per tile
   constexpr int XT = x_stride<T, KT>();
   constexpr int VEC = 16 / (int)sizeof(T);   // elements per 16-byte LDS read
@@ -331,8 +332,8 @@ rmat_block_kernel(const T* __restrict__ G, int ldg, int n, const T* __restrict__
     return (CMP ? min(n - 1, bh - n + 1 + c) - r0 : n - 1 - r0) / kKG;
   };
 
-  // staged X element e = tid + NT m: column e / KT, entry e % KT of the tile (a
-  // wave reads consecutive r and writes consecutive LDS words)
+  // staged X element e = tid + NT m (e < 32 KT): column e / KT, entry e % KT of
+  // the tile (a wave reads consecutive r and writes consecutive LDS words)
   T stage[LPT];
   auto load_tile = [&](int c, int r0, int gb, int gh) {
     const int rbase = r0 + kKG * gb;
@@ -343,7 +344,8 @@ rmat_block_kernel(const T* __restrict__ G, int ldg, int n, const T* __restrict__
       const int col = e / KT;
       const int r = rbase + e % KT;
       T v = (T)0;
-      if (col < ncols && r >= 0 && r < n && r < rend) v = X[(long)col * ldx + (long)n * c + r];
+      if ((LFULL || e < KT * 32) && col < ncols && r >= 0 && r < n && r < rend)
+        v = X[(long)col * ldx + (long)n * c + r];
       stage[m] = v;
     }
   };
@@ -352,7 +354,7 @@ rmat_block_kernel(const T* __restrict__ G, int ldg, int n, const T* __restrict__
 #pragma unroll
     for (int m = 0; m < LPT; ++m) {
       const int e = tid + NT * m;
-      xs[(e / KT) * XT + e % KT] = stage[m];
+      if (LFULL || e < KT * 32) xs[(e / KT) * XT + e % KT] = stage[m];
     }
   };
 
@@ -407,9 +409,9 @@ rmat_block_kernel(const T* __restrict__ G, int ldg, int n, const T* __restrict__
         for (int cb = 0; cb < CB; ++cb)
           acc[jb][cb] = mfma16x16x4(a[jb][u], b[cb][u], acc[jb][cb]);
   };
-  // All groups of a full tile in straight-line code, the reads of group g + 1
-  // issued before the MFMAs of group g; the last tile of a column block may hold
-  // fewer groups (a plain loop over them).
+  // The reads of group g + 1 are issued before the MFMAs of group g: a full
+  // tile in straight-line code; the last tile of a column block, which may hold
+  // fewer groups, in a loop over pairs of groups with the same overlap.
   auto mma_tile = [&](const T* xs, int colbase, int ng) {
     if (ng == GPT) {
       T a0[JB][4], b0[CB][4], a1[JB][4], b1[CB][4];
@@ -427,12 +429,17 @@ rmat_block_kernel(const T* __restrict__ G, int ldg, int n, const T* __restrict__
           __builtin_amdgcn_sched_barrier(0);
         }
       }
-    } else {
+    } else if (ng > 0) {
+      T a0[JB][4], b0[CB][4], a1[JB][4], b1[CB][4];
+      read_group(xs, colbase, 0, a0, b0);
 #pragma unroll 1
-      for (int g = 0; g < ng; ++g) {
-        T a[JB][4], b[CB][4];
-        read_group(xs, colbase, g, a, b);
-        mma_group(a, b);
+      for (int g = 0; g < ng; g += 2) {
+        if (g + 1 < ng) read_group(xs, colbase, g + 1, a1, b1);
+        mma_group(a0, b0);
+        if (g + 1 < ng) {
+          if (g + 2 < ng) read_group(xs, colbase, g + 2, a0, b0);
+          mma_group(a1, b1);
+        }
       }
     }
   };
@@ -592,8 +599,21 @@ void launch_rmat_block(const BlockPlan& p, const T* G, int ldg, int n, const T* 
                        T* Y, long ldy, int ncols, hipStream_t s, const int* box) {
   // waves per workgroup: TJ = 16 -> 16 (JB = 1) or 8 (JB = 2); TJ = 8 -> 8 (CB = 2)
   // or 16 (CB = 1); chosen by the autotuner, 16 and 8 by default; K tiles of 64
-  // or (these four shapes) 128 or 192 entries (fewer tiles, so fewer barriers
-  // and partial tiles, per column block; larger X buffers)
+  // or (these four shapes) 128, 176 or 192 entries (fewer tiles, so fewer
+  // barriers, per column block; larger X buffers). 176 = 11 groups splits the
+  // 33 groups of a column block whose r range starts below 0 into three full
+  // tiles (at n = 512; 192 leaves a last tile of 9).
+  if (p.TK == 176) {
+    if (p.TJ == 16 && p.waves == 8)
+      launch_tj<T, 16, 2, 2, 176>(p, G, ldg, n, X, ldx, Y, ldy, ncols, s, box);
+    else if (p.TJ == 16)
+      launch_tj<T, 16, 1, 2, 176>(p, G, ldg, n, X, ldx, Y, ldy, ncols, s, box);
+    else if (p.TJ == 8 && p.waves == 16)
+      launch_tj<T, 8, 1, 1, 176>(p, G, ldg, n, X, ldx, Y, ldy, ncols, s, box);
+    else
+      launch_tj<T, 8, 1, 2, 176>(p, G, ldg, n, X, ldx, Y, ldy, ncols, s, box);
+    return;
+  }
   if (p.TK == 192) {
     if (p.TJ == 16 && p.waves == 8)
       launch_tj<T, 16, 2, 2, 192>(p, G, ldg, n, X, ldx, Y, ldy, ncols, s, box);

@@ -140,7 +140,7 @@ def test_product16_full_size_sampled_rows(ctx, prec):
     assert np.all(np.abs(Y[rows] - ref) <= 2e-6 * mag + 1e-7 * mag.max())
 
 
-@pytest.mark.parametrize("prec,nvar", [("f32", 12), ("f64", 12), ("bf16", 7)])
+@pytest.mark.parametrize("prec,nvar", [("f32", 16), ("f64", 16), ("bf16", 7)])
 @pytest.mark.parametrize("n", [40, 256])
 def test_autotuner_variants_agree_bitwise(ctx, prec, nvar, n, monkeypatch):
     """Every launch variant the autotuner chooses among computes the same bits."""
