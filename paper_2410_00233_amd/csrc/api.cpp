@@ -565,8 +565,7 @@ void cgs2(const Scratch& sc, T* w, const T* V, long ldv, int m, long N, hipStrea
   }
   for (int pass = 0; pass < 2; ++pass) {
     launch_multidot<T>(V, ldv, m, w, N, sc.partials, s);
-    launch_reduce_partials(sc.partials, m, sc.h, 0, s);
-    launch_project_out<T>(w, V, ldv, m, sc.h, N, sc.nrmp, s);
+    launch_project_out_red<T>(w, V, ldv, m, sc.partials, sc.h, nullptr, N, sc.nrmp, s);
   }
 }
 
@@ -593,35 +592,32 @@ kp_status cgs_qr(kp_ctx* c, const Scratch& sc, T* W, long N, int m, double* Rfac
     T* w = W + N * j;
     double* Rcol = Rfac ? Rfac + (long)m * j : sc.h + 192;
     double* rjj = Rfac ? Rfac + j + (long)m * j : rscr;
+    // (the projections reduce the multidot partials themselves: Rcol = h1,
+    // then h2 is stored and added into Rcol)
     if (j > 0) {
       launch_multidot<T>(W, N, j, w, N, sc.partials, s);
-      launch_reduce_partials(sc.partials, j, Rcol, 0, s);
-      launch_project_out<T>(w, W, N, j, Rcol, N, nullptr, s);
+      launch_project_out_red<T>(w, W, N, j, sc.partials, Rcol, nullptr, N, nullptr, s);
       launch_multidot<T>(W, N, j, w, N, sc.partials, s);
-      launch_reduce_partials(sc.partials, j, h2, 0, s);
-      launch_project_out<T>(w, W, N, j, h2, N, sc.nrmp, s);
-      launch_add_small(Rcol, h2, j, s);
+      launch_project_out_red<T>(w, W, N, j, sc.partials, h2, Rcol, N, sc.nrmp, s);
+      launch_normalize<T>(w, N, sc.nrmp, rjj, s);
+      launch_multidot<T>(W, N, j, w, N, sc.partials, s);
+      launch_project_out_red<T>(w, W, N, j, sc.partials, h3, nullptr, N, sc.nrmp, s);
+      launch_normalize<T>(w, N, sc.nrmp, r3, s, nullptr, sc.flag, 0.5);
     } else {
       launch_norm2_partials<T>(w, N, sc.nrmp, s);
-    }
-    launch_normalize<T>(w, N, sc.nrmp, rjj, s);
-    if (j > 0) {
-      launch_multidot<T>(W, N, j, w, N, sc.partials, s);
-      launch_reduce_partials(sc.partials, j, h3, 0, s);
-      launch_project_out<T>(w, W, N, j, h3, N, sc.nrmp, s);
-      launch_normalize<T>(w, N, sc.nrmp, r3, s);
-      launch_flag_below(r3, 0.5, sc.flag, s);
-    } else {
-      launch_flag_below(rjj, 1e-300, sc.flag, s);     // an exactly zero first column
+      // flag an exactly zero first column
+      launch_normalize<T>(w, N, sc.nrmp, rjj, s, nullptr, sc.flag, 1e-300);
     }
     // replacement of a dependent column (predicated on sc.flag)
     launch_philox_normals<T>(w, N, seed, stream_base + (uint32_t)j, s, sc.flag);
     for (int pass = 0; pass < 2; ++pass) {
       if (j > 0) {
         launch_multidot<T>(W, N, j, w, N, sc.partials, s, sc.flag);
-        launch_reduce_partials(sc.partials, j, h2, 0, s, sc.flag);
+        launch_project_out_red<T>(w, W, N, j, sc.partials, nullptr, nullptr, N, sc.nrmp, s,
+                                  sc.flag);
+      } else {
+        launch_project_out<T>(w, W, N, 0, h2, N, sc.nrmp, s, sc.flag);
       }
-      launch_project_out<T>(w, W, N, j, h2, N, sc.nrmp, s, sc.flag);
     }
     launch_normalize<T>(w, N, sc.nrmp, r4, s, sc.flag);
     if (j > 0) launch_cgs_fixup(Rcol, j, h3, rjj, r3, sc.flag, s);
@@ -965,12 +961,9 @@ kp_status egkb_block_impl(kp_ctx* c, const RmatOp<T>& op, const kp_gkb_opts* o, 
       launch_norm2_partials<T>(w, N, sc.nrmp, s);
     } else {
       launch_multidot<T>(B0, N, m, w, N, sc.partials, s);
-      launch_reduce_partials(sc.partials, m, hcol, 0, s);
-      launch_project_out<T>(w, B0, N, m, hcol, N, nullptr, s);
+      launch_project_out_red<T>(w, B0, N, m, sc.partials, hcol, nullptr, N, nullptr, s);
       launch_multidot<T>(B0, N, m, w, N, sc.partials, s);
-      launch_reduce_partials(sc.partials, m, h2, 0, s);
-      launch_project_out<T>(w, B0, N, m, h2, N, sc.nrmp, s);
-      launch_add_small(hcol, h2, m, s);
+      launch_project_out_red<T>(w, B0, N, m, sc.partials, h2, hcol, N, sc.nrmp, s);
     }
     launch_reduce_partials(sc.nrmp, 1, sc.scal, 0, s);
     KP_TRY(check_launch(c, "block_gs"));

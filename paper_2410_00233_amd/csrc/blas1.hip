@@ -178,16 +178,43 @@ void launch_reduce_partials(const double* partials, int m, double* h, int accumu
 }
 
 // ---------------------------------------------------------------------------
+// Coefficients of a projection into hs[0..m): h itself, or (partials != NULL)
+// the sums over the kRedBlocks multidot partials (layout [block][m]), added in
+// a fixed order (lane l: blocks l, l + 64, l + 128, l + 192, then a wave sum),
+// so every block holds the same values. Block 0 then stores them in h_out
+// and/or adds them into h_add. Ends with a barrier.
+__device__ __forceinline__ void load_coefs(const double* __restrict__ h,
+                                           const double* __restrict__ partials, int m,
+                                           double* __restrict__ h_out,
+                                           double* __restrict__ h_add, double* hs) {
+  if (partials) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int i = wave; i < m; i += 4) {
+      double v = 0.0;
+      for (int t = 0; t < kRedBlocks; t += 64) v += partials[(long)(t + lane) * m + i];
+      v = wave_sum(v);
+      if (lane == 0) hs[i] = v;
+    }
+  } else if ((int)threadIdx.x < m) {
+    hs[threadIdx.x] = h[threadIdx.x];
+  }
+  __syncthreads();
+  if (blockIdx.x == 0 && (int)threadIdx.x < m) {
+    if (h_out) h_out[threadIdx.x] = hs[threadIdx.x];
+    if (h_add) h_add[threadIdx.x] += hs[threadIdx.x];
+  }
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256)
 project_out_kernel(T* __restrict__ w, const T* __restrict__ V, long ldv, int m,
-                   const double* __restrict__ h, long N, double* __restrict__ nrm_partials,
-                   const int* __restrict__ pred) {
+                   const double* __restrict__ h, const double* __restrict__ partials,
+                   double* __restrict__ h_out, double* __restrict__ h_add, long N,
+                   double* __restrict__ nrm_partials, const int* __restrict__ pred) {
   if (pred && *pred == 0) return;
   __shared__ double hs[64];
   __shared__ double sh[8];
-  if (threadIdx.x < m) hs[threadIdx.x] = h[threadIdx.x];
-  __syncthreads();
+  load_coefs(h, partials, m, h_out, h_add, hs);
   long lo, hi;
   row_range(N, &lo, &hi);
   double nrm = 0.0;
@@ -206,16 +233,16 @@ project_out_kernel(T* __restrict__ w, const T* __restrict__ V, long ldv, int m,
 template <typename T>
 __global__ void __launch_bounds__(256)
 project_out_vec_kernel(T* __restrict__ w, const T* __restrict__ V, long ldv, int m,
-                       const double* __restrict__ h, long N, double* __restrict__ nrm_partials,
-                       const int* __restrict__ pred) {
+                       const double* __restrict__ h, const double* __restrict__ partials,
+                       double* __restrict__ h_out, double* __restrict__ h_add, long N,
+                       double* __restrict__ nrm_partials, const int* __restrict__ pred) {
   if (pred && *pred == 0) return;
   constexpr int VEC = Vec16<T>::VEC;
   typedef typename Vec16<T>::type vec_t;
   constexpr int CG = 16;
   __shared__ double hs[64];
   __shared__ double sh[8];
-  if (threadIdx.x < m) hs[threadIdx.x] = h[threadIdx.x];
-  __syncthreads();
+  load_coefs(h, partials, m, h_out, h_add, hs);
   long lo, hi;
   row_range_vec(N, VEC, &lo, &hi);
   double nrm = 0.0;
@@ -249,19 +276,37 @@ project_out_vec_kernel(T* __restrict__ w, const T* __restrict__ V, long ldv, int
 }
 
 template <typename T>
-void launch_project_out(T* w, const T* V, long ldv, int m, const double* h, long N,
-                        double* nrm_partials, hipStream_t s, const int* pred) {
+static void project_out_any(T* w, const T* V, long ldv, int m, const double* h,
+                            const double* partials, double* h_out, double* h_add, long N,
+                            double* nrm_partials, hipStream_t s, const int* pred) {
   if (vec_ok<T>(N, ldv, V, w))
     hipLaunchKernelGGL(project_out_vec_kernel<T>, dim3(kRedBlocks), dim3(256), 0, s, w, V, ldv,
-                       m, h, N, nrm_partials, pred);
+                       m, h, partials, h_out, h_add, N, nrm_partials, pred);
   else
     hipLaunchKernelGGL(project_out_kernel<T>, dim3(kRedBlocks), dim3(256), 0, s, w, V, ldv, m,
-                       h, N, nrm_partials, pred);
+                       h, partials, h_out, h_add, N, nrm_partials, pred);
+}
+template <typename T>
+void launch_project_out(T* w, const T* V, long ldv, int m, const double* h, long N,
+                        double* nrm_partials, hipStream_t s, const int* pred) {
+  project_out_any<T>(w, V, ldv, m, h, nullptr, nullptr, nullptr, N, nrm_partials, s, pred);
+}
+template <typename T>
+void launch_project_out_red(T* w, const T* V, long ldv, int m, const double* partials,
+                            double* h_out, double* h_add, long N, double* nrm_partials,
+                            hipStream_t s, const int* pred) {
+  project_out_any<T>(w, V, ldv, m, nullptr, partials, h_out, h_add, N, nrm_partials, s, pred);
 }
 template void launch_project_out<float>(float*, const float*, long, int, const double*, long,
                                         double*, hipStream_t, const int*);
 template void launch_project_out<double>(double*, const double*, long, int, const double*,
                                          long, double*, hipStream_t, const int*);
+template void launch_project_out_red<float>(float*, const float*, long, int, const double*,
+                                            double*, double*, long, double*, hipStream_t,
+                                            const int*);
+template void launch_project_out_red<double>(double*, const double*, long, int, const double*,
+                                             double*, double*, long, double*, hipStream_t,
+                                             const int*);
 
 // ---------------------------------------------------------------------------
 template <typename T>
@@ -311,15 +356,20 @@ template void launch_norm2_partials<double>(const double*, long, double*, hipStr
 
 // ---------------------------------------------------------------------------
 // w /= ||w|| with ||w||^2 = sum of nrm_partials; block 0 stores ||w|| in
-// *norm_out. A zero vector is left unchanged (and reports norm 0).
+// *norm_out and, with flag_out, *flag_out = (||w|| < thr). A zero vector is
+// left unchanged (and reports norm 0).
 template <typename T>
 __global__ void __launch_bounds__(256)
 normalize_kernel(T* __restrict__ w, long N, const double* __restrict__ nrm_partials,
-                 double* __restrict__ norm_out, const int* __restrict__ pred) {
+                 double* __restrict__ norm_out, const int* __restrict__ pred,
+                 int* __restrict__ flag_out, double thr) {
   if (pred && *pred == 0) return;
   __shared__ double sh[8];
   const double nrm = sqrt(reduce_partials_block(nrm_partials, 1, 0, sh));
-  if (blockIdx.x == 0 && threadIdx.x == 0 && norm_out) *norm_out = nrm;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (norm_out) *norm_out = nrm;
+    if (flag_out) *flag_out = nrm < thr ? 1 : 0;
+  }
   if (nrm == 0.0) return;
   const double inv = 1.0 / nrm;
   long lo, hi;
@@ -330,13 +380,17 @@ normalize_kernel(T* __restrict__ w, long N, const double* __restrict__ nrm_parti
 template <typename T>
 __global__ void __launch_bounds__(256)
 normalize_vec_kernel(T* __restrict__ w, long N, const double* __restrict__ nrm_partials,
-                     double* __restrict__ norm_out, const int* __restrict__ pred) {
+                     double* __restrict__ norm_out, const int* __restrict__ pred,
+                     int* __restrict__ flag_out, double thr) {
   if (pred && *pred == 0) return;
   constexpr int VEC = Vec16<T>::VEC;
   typedef typename Vec16<T>::type vec_t;
   __shared__ double sh[8];
   const double nrm = sqrt(reduce_partials_block(nrm_partials, 1, 0, sh));
-  if (blockIdx.x == 0 && threadIdx.x == 0 && norm_out) *norm_out = nrm;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (norm_out) *norm_out = nrm;
+    if (flag_out) *flag_out = nrm < thr ? 1 : 0;
+  }
   if (nrm == 0.0) return;
   const double inv = 1.0 / nrm;
   long lo, hi;
@@ -351,18 +405,18 @@ normalize_vec_kernel(T* __restrict__ w, long N, const double* __restrict__ nrm_p
 
 template <typename T>
 void launch_normalize(T* w, long N, const double* nrm_partials, double* norm_out,
-                      hipStream_t s, const int* pred) {
+                      hipStream_t s, const int* pred, int* flag_out, double thr) {
   if (vec_ok<T>(N, 0, w, w))
     hipLaunchKernelGGL(normalize_vec_kernel<T>, dim3(kRedBlocks), dim3(256), 0, s, w, N,
-                       nrm_partials, norm_out, pred);
+                       nrm_partials, norm_out, pred, flag_out, thr);
   else
     hipLaunchKernelGGL(normalize_kernel<T>, dim3(kRedBlocks), dim3(256), 0, s, w, N,
-                       nrm_partials, norm_out, pred);
+                       nrm_partials, norm_out, pred, flag_out, thr);
 }
 template void launch_normalize<float>(float*, long, const double*, double*, hipStream_t,
-                                      const int*);
+                                      const int*, int*, double);
 template void launch_normalize<double>(double*, long, const double*, double*, hipStream_t,
-                                       const int*);
+                                       const int*, int*, double);
 
 // ---------------------------------------------------------------------------
 template <typename T>

@@ -179,14 +179,23 @@ void launch_reduce_partials(const double* partials, int m, double* h, int accumu
 template <typename T>
 void launch_project_out(T* w, const T* V, long ldv, int m, const double* h, long N,
                         double* nrm_partials, hipStream_t s, const int* pred = nullptr);
+// the same with h = the sums of the launch_multidot partials (layout [block][m]),
+// formed in every block; block 0 stores h in h_out and/or adds it into h_add
+// (either may be NULL). Replaces a reduce_partials launch before the projection.
+template <typename T>
+void launch_project_out_red(T* w, const T* V, long ldv, int m, const double* partials,
+                            double* h_out, double* h_add, long N, double* nrm_partials,
+                            hipStream_t s, const int* pred = nullptr);
 // nrm_partials[b] = block partial of ||w||^2
 template <typename T>
 void launch_norm2_partials(const T* w, long N, double* nrm_partials, hipStream_t s);
 // Normalize w by the norm reduced from nrm_partials; *norm_out = ||w||
-// (written by block 0; may be null). A zero vector is left unchanged.
+// (written by block 0; may be null) and, with flag_out, *flag_out =
+// (||w|| < thr) (block 0). A zero vector is left unchanged.
 template <typename T>
 void launch_normalize(T* w, long N, const double* nrm_partials, double* norm_out,
-                      hipStream_t s, const int* pred = nullptr);
+                      hipStream_t s, const int* pred = nullptr, int* flag_out = nullptr,
+                      double thr = 0.0);
 template <typename T>
 void launch_scale(T* w, long N, double factor, hipStream_t s);
 // out[e] = Philox normal number e of (seed, stream)
@@ -201,12 +210,9 @@ void launch_small_gemm(const T* V, long ldv, int m, const double* C, int ldc, in
                        long N, O* out, long ldo, hipStream_t s);
 
 // ---- single-workgroup helpers (smallops.hip) ---------------------------------
-void launch_add_small(double* Rcol, const double* h, int m, hipStream_t s);
 // Bookkeeping of the third Gram-Schmidt pass; skipped when *replaced != 0.
 void launch_cgs_fixup(double* Rcol, int m, const double* h3, double* rjj, const double* r3,
                       const int* replaced, hipStream_t s);
-// *flag = (*val < thresh)
-void launch_flag_below(const double* val, double thresh, int* flag, hipStream_t s);
 void launch_transpose_small(const double* in, int m, int nc, double* out, hipStream_t s);
 void launch_fill_small(double* p, int m, double v, hipStream_t s);
 void launch_fill(double* p, long n, double v, hipStream_t s);

@@ -4,15 +4,6 @@
 
 namespace kpsb {
 
-// Rcol[i] += h[i]  (i < m)
-__global__ void add_small_kernel(double* __restrict__ Rcol, const double* __restrict__ h, int m) {
-  const int i = threadIdx.x;
-  if (i < m) Rcol[i] += h[i];
-}
-void launch_add_small(double* Rcol, const double* h, int m, hipStream_t s) {
-  if (m > 0) hipLaunchKernelGGL(add_small_kernel, dim3(1), dim3(64), 0, s, Rcol, h, m);
-}
-
 // After a third Gram-Schmidt pass on the normalized column q = w / r:
 // q = sum_i h3_i v_i + r3 q', hence w = sum_i (R_ij + r h3_i) v_i + r r3 q'.
 __global__ void cgs_fixup_kernel(double* __restrict__ Rcol, int m, const double* __restrict__ h3,
@@ -28,14 +19,6 @@ __global__ void cgs_fixup_kernel(double* __restrict__ Rcol, int m, const double*
 void launch_cgs_fixup(double* Rcol, int m, const double* h3, double* rjj, const double* r3,
                       const int* replaced, hipStream_t s) {
   hipLaunchKernelGGL(cgs_fixup_kernel, dim3(1), dim3(64), 0, s, Rcol, m, h3, rjj, r3, replaced);
-}
-
-__global__ void flag_below_kernel(const double* __restrict__ val, double thresh,
-                                  int* __restrict__ flag) {
-  if (threadIdx.x == 0) *flag = (*val < thresh) ? 1 : 0;
-}
-void launch_flag_below(const double* val, double thresh, int* flag, hipStream_t s) {
-  hipLaunchKernelGGL(flag_below_kernel, dim3(1), dim3(64), 0, s, val, thresh, flag);
 }
 
 // out (nc x m, ld nc) = in^T (in: m x nc, ld m)
