@@ -534,6 +534,7 @@ struct Scratch {
   double* h = nullptr;          // 4 x 64 coefficient vectors
   double* scal = nullptr;       // 8 scalars
   int* flag = nullptr;          // device predicate
+  int* flags = nullptr;         // 64 per-column predicates
 };
 
 kp_status get_scratch(kp_ctx* c, Scratch* sc) {
@@ -542,6 +543,7 @@ kp_status get_scratch(kp_ctx* c, Scratch* sc) {
   KP_TRY(wsT(c, "hvec", 4 * 64, &sc->h));
   KP_TRY(wsT(c, "scal", 8, &sc->scal));
   KP_TRY(wsT(c, "flag", 4, &sc->flag));
+  KP_TRY(wsT(c, "flags", 64, &sc->flags));
   return KP_OK;
 }
 
@@ -576,39 +578,89 @@ void cgs2(const Scratch& sc, T* w, const T* V, long ldv, int m, long N, hipStrea
 // was numerically dependent (its residual was rounding noise) and is replaced
 // by a Philox normal vector (stream `stream_base + j`) orthogonalized twice:
 // R keeps the projections and the rounding-level R[j, j]. Otherwise the third
-// pass is folded into R. All decisions are taken on the device (predicated
-// kernels), so the sequence never synchronizes with the host. R (m x m,
-// column-major FP64) is formed when Rfac != NULL.
+// pass is folded into R. R (m x m, column-major FP64) is formed when
+// Rfac != NULL.
+//
+// Dependent columns are rare, so the columns first run without the
+// replacement kernels, in chunks of kCgsChunk, each column's flag kept; after
+// a chunk the host reads its flags. At the first flagged column j the chunk's
+// columns from j on are restored from a copy of W taken at the start (column
+// j only reads columns < j and writes column j, so nothing else changed) and
+// the QR goes on from j with the replacement kernels predicated on the device
+// flag of each column, the same kernels in the same order as a column that
+// takes them from the start. The result is that of the predicated sequence.
+constexpr int kCgsChunk = 16;
+
+// Passes 1-3 of column j, its dependence flag and, for a kept column, the
+// third pass folded into R (no replacement).
+template <typename T>
+static void cgs_column(const Scratch& sc, T* W, long N, int j, double* Rcol, double* rjj,
+                       int* flag, hipStream_t s) {
+  T* w = W + N * j;
+  double* h2 = sc.h + 64;
+  double* h3 = sc.h + 128;
+  double* r3 = sc.scal + 3;
+  // (the projections reduce the multidot partials themselves: Rcol = h1,
+  // then h2 is stored and added into Rcol)
+  if (j > 0) {
+    launch_multidot<T>(W, N, j, w, N, sc.partials, s);
+    launch_project_out_red<T>(w, W, N, j, sc.partials, Rcol, nullptr, N, nullptr, s);
+    launch_multidot<T>(W, N, j, w, N, sc.partials, s);
+    launch_project_out_red<T>(w, W, N, j, sc.partials, h2, Rcol, N, sc.nrmp, s);
+    launch_normalize<T>(w, N, sc.nrmp, rjj, s);
+    launch_multidot<T>(W, N, j, w, N, sc.partials, s);
+    launch_project_out_red<T>(w, W, N, j, sc.partials, h3, nullptr, N, sc.nrmp, s);
+    // a kept column (r3 >= 0.5) folds the third pass into R here: with
+    // q = w / r = sum_i h3_i v_i + r3 q', w = sum_i (R_ij + r h3_i) v_i + r r3 q'
+    QrFixup fx;
+    fx.rcol = Rcol;
+    fx.m = j;
+    fx.h3 = h3;
+    fx.rjj = rjj;
+    launch_normalize<T>(w, N, sc.nrmp, r3, s, nullptr, flag, 0.5, fx);
+  } else {
+    launch_norm2_partials<T>(w, N, sc.nrmp, s);
+    // flag an exactly zero first column
+    launch_normalize<T>(w, N, sc.nrmp, rjj, s, nullptr, flag, 1e-300);
+  }
+}
+
 template <typename T>
 kp_status cgs_qr(kp_ctx* c, const Scratch& sc, T* W, long N, int m, double* Rfac,
                  uint64_t seed, uint32_t stream_base, hipStream_t s) {
   double* h2 = sc.h + 64;
-  double* h3 = sc.h + 128;
   double* rscr = sc.scal + 2;
-  double* r3 = sc.scal + 3;
   double* r4 = sc.scal + 4;
+  auto rcol = [&](int j) { return Rfac ? Rfac + (long)m * j : sc.h + 192; };
+  auto rdiag = [&](int j) { return Rfac ? Rfac + j + (long)m * j : rscr; };
   if (Rfac) launch_fill_small(Rfac, m * m, 0.0, s);
-  for (int j = 0; j < m; ++j) {
-    T* w = W + N * j;
-    double* Rcol = Rfac ? Rfac + (long)m * j : sc.h + 192;
-    double* rjj = Rfac ? Rfac + j + (long)m * j : rscr;
-    // (the projections reduce the multidot partials themselves: Rcol = h1,
-    // then h2 is stored and added into Rcol)
-    if (j > 0) {
-      launch_multidot<T>(W, N, j, w, N, sc.partials, s);
-      launch_project_out_red<T>(w, W, N, j, sc.partials, Rcol, nullptr, N, nullptr, s);
-      launch_multidot<T>(W, N, j, w, N, sc.partials, s);
-      launch_project_out_red<T>(w, W, N, j, sc.partials, h2, Rcol, N, sc.nrmp, s);
-      launch_normalize<T>(w, N, sc.nrmp, rjj, s);
-      launch_multidot<T>(W, N, j, w, N, sc.partials, s);
-      launch_project_out_red<T>(w, W, N, j, sc.partials, h3, nullptr, N, sc.nrmp, s);
-      launch_normalize<T>(w, N, sc.nrmp, r3, s, nullptr, sc.flag, 0.5);
-    } else {
-      launch_norm2_partials<T>(w, N, sc.nrmp, s);
-      // flag an exactly zero first column
-      launch_normalize<T>(w, N, sc.nrmp, rjj, s, nullptr, sc.flag, 1e-300);
+  T* copy = nullptr;
+  KP_TRY(wsT(c, std::string("cgs_copy_") + tname<T>(), (size_t)N * m, &copy));
+  KP_HIP(c, hipMemcpyAsync(copy, W, sizeof(T) * N * m, hipMemcpyDeviceToDevice, s));
+  int* hflags = reinterpret_cast<int*>(c->pinned + 32);   // kCgsChunk ints
+  int j = 0;
+  while (j < m) {   // unpredicated chunks
+    const int j1 = std::min(m, j + kCgsChunk);
+    for (int q = j; q < j1; ++q) cgs_column<T>(sc, W, N, q, rcol(q), rdiag(q), sc.flags + q, s);
+    KP_TRY(check_launch(c, "cgs_qr"));
+    KP_HIP(c, hipMemcpyAsync(hflags, sc.flags + j, sizeof(int) * (j1 - j),
+                             hipMemcpyDeviceToHost, s));
+    KP_HIP(c, hipStreamSynchronize(s));
+    int first = -1;
+    for (int q = j; q < j1 && first < 0; ++q)
+      if (hflags[q - j]) first = q;
+    if (first < 0) {
+      j = j1;
+      continue;
     }
-    // replacement of a dependent column (predicated on sc.flag)
+    KP_HIP(c, hipMemcpyAsync(W + N * first, copy + N * first, sizeof(T) * N * (j1 - first),
+                             hipMemcpyDeviceToDevice, s));
+    j = first;
+    break;
+  }
+  for (; j < m; ++j) {   // from the first dependent column on: predicated replacement
+    T* w = W + N * j;
+    cgs_column<T>(sc, W, N, j, rcol(j), rdiag(j), sc.flag, s);
     launch_philox_normals<T>(w, N, seed, stream_base + (uint32_t)j, s, sc.flag);
     for (int pass = 0; pass < 2; ++pass) {
       if (j > 0) {
@@ -620,7 +672,6 @@ kp_status cgs_qr(kp_ctx* c, const Scratch& sc, T* W, long N, int m, double* Rfac
       }
     }
     launch_normalize<T>(w, N, sc.nrmp, r4, s, sc.flag);
-    if (j > 0) launch_cgs_fixup(Rcol, j, h3, rjj, r3, sc.flag, s);
   }
   return check_launch(c, "cgs_qr");
 }

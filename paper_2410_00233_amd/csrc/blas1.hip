@@ -356,19 +356,30 @@ template void launch_norm2_partials<double>(const double*, long, double*, hipStr
 
 // ---------------------------------------------------------------------------
 // w /= ||w|| with ||w||^2 = sum of nrm_partials; block 0 stores ||w|| in
-// *norm_out and, with flag_out, *flag_out = (||w|| < thr). A zero vector is
-// left unchanged (and reports norm 0).
+// *norm_out and, with flag_out, *flag_out = (||w|| < thr). With fx.rcol (the
+// third Gram-Schmidt pass of a QR column, ||w|| = r3 < thr meaning the column
+// is replaced) block 0 also folds a kept column's third pass into R:
+// rcol[i] += rjj h3[i] (i < m), then rjj *= r3. A zero vector is left
+// unchanged (and reports norm 0).
 template <typename T>
 __global__ void __launch_bounds__(256)
 normalize_kernel(T* __restrict__ w, long N, const double* __restrict__ nrm_partials,
                  double* __restrict__ norm_out, const int* __restrict__ pred,
-                 int* __restrict__ flag_out, double thr) {
+                 int* __restrict__ flag_out, double thr, QrFixup fx) {
   if (pred && *pred == 0) return;
   __shared__ double sh[8];
   const double nrm = sqrt(reduce_partials_block(nrm_partials, 1, 0, sh));
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    if (norm_out) *norm_out = nrm;
-    if (flag_out) *flag_out = nrm < thr ? 1 : 0;
+  if (blockIdx.x == 0) {
+    if (threadIdx.x == 0) {
+      if (norm_out) *norm_out = nrm;
+      if (flag_out) *flag_out = nrm < thr ? 1 : 0;
+    }
+    if (fx.rcol && !(nrm < thr)) {
+      const double r = *fx.rjj;
+      if ((int)threadIdx.x < fx.m) fx.rcol[threadIdx.x] += r * fx.h3[threadIdx.x];
+      __syncthreads();
+      if (threadIdx.x == 0) *fx.rjj = r * nrm;
+    }
   }
   if (nrm == 0.0) return;
   const double inv = 1.0 / nrm;
@@ -381,15 +392,23 @@ template <typename T>
 __global__ void __launch_bounds__(256)
 normalize_vec_kernel(T* __restrict__ w, long N, const double* __restrict__ nrm_partials,
                      double* __restrict__ norm_out, const int* __restrict__ pred,
-                     int* __restrict__ flag_out, double thr) {
+                     int* __restrict__ flag_out, double thr, QrFixup fx) {
   if (pred && *pred == 0) return;
   constexpr int VEC = Vec16<T>::VEC;
   typedef typename Vec16<T>::type vec_t;
   __shared__ double sh[8];
   const double nrm = sqrt(reduce_partials_block(nrm_partials, 1, 0, sh));
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    if (norm_out) *norm_out = nrm;
-    if (flag_out) *flag_out = nrm < thr ? 1 : 0;
+  if (blockIdx.x == 0) {
+    if (threadIdx.x == 0) {
+      if (norm_out) *norm_out = nrm;
+      if (flag_out) *flag_out = nrm < thr ? 1 : 0;
+    }
+    if (fx.rcol && !(nrm < thr)) {
+      const double r = *fx.rjj;
+      if ((int)threadIdx.x < fx.m) fx.rcol[threadIdx.x] += r * fx.h3[threadIdx.x];
+      __syncthreads();
+      if (threadIdx.x == 0) *fx.rjj = r * nrm;
+    }
   }
   if (nrm == 0.0) return;
   const double inv = 1.0 / nrm;
@@ -405,18 +424,19 @@ normalize_vec_kernel(T* __restrict__ w, long N, const double* __restrict__ nrm_p
 
 template <typename T>
 void launch_normalize(T* w, long N, const double* nrm_partials, double* norm_out,
-                      hipStream_t s, const int* pred, int* flag_out, double thr) {
+                      hipStream_t s, const int* pred, int* flag_out, double thr,
+                      const QrFixup& fx) {
   if (vec_ok<T>(N, 0, w, w))
     hipLaunchKernelGGL(normalize_vec_kernel<T>, dim3(kRedBlocks), dim3(256), 0, s, w, N,
-                       nrm_partials, norm_out, pred, flag_out, thr);
+                       nrm_partials, norm_out, pred, flag_out, thr, fx);
   else
     hipLaunchKernelGGL(normalize_kernel<T>, dim3(kRedBlocks), dim3(256), 0, s, w, N,
-                       nrm_partials, norm_out, pred, flag_out, thr);
+                       nrm_partials, norm_out, pred, flag_out, thr, fx);
 }
 template void launch_normalize<float>(float*, long, const double*, double*, hipStream_t,
-                                      const int*, int*, double);
+                                      const int*, int*, double, const QrFixup&);
 template void launch_normalize<double>(double*, long, const double*, double*, hipStream_t,
-                                       const int*, int*, double);
+                                       const int*, int*, double, const QrFixup&);
 
 // ---------------------------------------------------------------------------
 template <typename T>

@@ -192,10 +192,19 @@ void launch_norm2_partials(const T* w, long N, double* nrm_partials, hipStream_t
 // Normalize w by the norm reduced from nrm_partials; *norm_out = ||w||
 // (written by block 0; may be null) and, with flag_out, *flag_out =
 // (||w|| < thr) (block 0). A zero vector is left unchanged.
+// With fx.rcol != NULL (third pass of a Gram-Schmidt QR column, the norm being
+// r3): unless r3 < thr, block 0 adds rjj h3 into rcol (m entries) and scales
+// rjj by r3.
+struct QrFixup {
+  double* rcol = nullptr;
+  int m = 0;
+  const double* h3 = nullptr;
+  double* rjj = nullptr;
+};
 template <typename T>
 void launch_normalize(T* w, long N, const double* nrm_partials, double* norm_out,
                       hipStream_t s, const int* pred = nullptr, int* flag_out = nullptr,
-                      double thr = 0.0);
+                      double thr = 0.0, const QrFixup& fx = QrFixup());
 template <typename T>
 void launch_scale(T* w, long N, double factor, hipStream_t s);
 // out[e] = Philox normal number e of (seed, stream)
@@ -210,9 +219,6 @@ void launch_small_gemm(const T* V, long ldv, int m, const double* C, int ldc, in
                        long N, O* out, long ldo, hipStream_t s);
 
 // ---- single-workgroup helpers (smallops.hip) ---------------------------------
-// Bookkeeping of the third Gram-Schmidt pass; skipped when *replaced != 0.
-void launch_cgs_fixup(double* Rcol, int m, const double* h3, double* rjj, const double* r3,
-                      const int* replaced, hipStream_t s);
 void launch_transpose_small(const double* in, int m, int nc, double* out, hipStream_t s);
 void launch_fill_small(double* p, int m, double v, hipStream_t s);
 void launch_fill(double* p, long n, double v, hipStream_t s);

@@ -7,23 +7,31 @@
 
 namespace kpsb {
 
-// block t finds argmax_r |V[r, t]| (lowest r on ties)
+// block t finds argmax_r |V[r, t]| (lowest r on ties); 1024 threads, four
+// loads in flight per thread
 template <typename T>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(1024)
 argmax_abs_kernel(const T* __restrict__ V, long ldv, long N, int* __restrict__ out) {
-  __shared__ double bv[256];
-  __shared__ long bi[256];
+  __shared__ double bv[1024];
+  __shared__ long bi[1024];
   const int t = blockIdx.x;
   double best = -1.0;
   long besti = 0;
-  for (long r = threadIdx.x; r < N; r += 256) {
-    const double a = fabs((double)V[(long)t * ldv + r]);
-    if (a > best) { best = a; besti = r; }      // strictly greater keeps the lowest r
+  for (long r0 = threadIdx.x; r0 < N; r0 += 4 * 1024) {
+    double a[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const long r = r0 + 1024L * u;
+      a[u] = r < N ? fabs((double)V[(long)t * ldv + r]) : -1.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)    // increasing r; strictly greater keeps the lowest
+      if (a[u] > best) { best = a[u]; besti = r0 + 1024L * u; }
   }
   bv[threadIdx.x] = best;
   bi[threadIdx.x] = besti;
   __syncthreads();
-  for (int off = 128; off > 0; off >>= 1) {
+  for (int off = 512; off > 0; off >>= 1) {
     if (threadIdx.x < off) {
       const double o = bv[threadIdx.x + off];
       const long oi = bi[threadIdx.x + off];
@@ -78,7 +86,7 @@ template <typename T, typename O>
 void launch_form_factors(const T* U, const T* V, long ldu, int n, int k, const double* sigma,
                          O* Ax, O* Ay, int* argmax_scratch, hipStream_t s) {
   if (k <= 0) return;
-  hipLaunchKernelGGL(argmax_abs_kernel<T>, dim3(k), dim3(256), 0, s, V, ldu, (long)n * n,
+  hipLaunchKernelGGL(argmax_abs_kernel<T>, dim3(k), dim3(1024), 0, s, V, ldu, (long)n * n,
                      argmax_scratch);
   dim3 grid((n + 31) / 32, (n + 31) / 32, k);
   hipLaunchKernelGGL((write_factor_kernel<T, O>), grid, dim3(256), 0, s, U, V, ldu, n, sigma,

@@ -70,19 +70,31 @@ __global__ void build_grid_kernel(const double* __restrict__ psf, int pu, int pv
   }
 }
 
-__global__ void psf_split_scale_kernel(const double* __restrict__ psf, long count, int nsum,
-                                       double* __restrict__ scal) {
-  __shared__ double sh[256];
-  __shared__ double ss[256];
+// One workgroup of 1024 threads; each thread keeps four loads in flight
+// (the PSF of n = 512 on its full offset grid is 8 MB).
+__global__ void __launch_bounds__(1024)
+psf_split_scale_kernel(const double* __restrict__ psf, long count, int nsum,
+                       double* __restrict__ scal) {
+  __shared__ double sh[1024];
+  __shared__ double ss[1024];
   double m = 0.0, t = 0.0;
-  for (long e = threadIdx.x; e < count; e += 256) {
-    m = fmax(m, fabs(psf[e]));
-    t += fabs(psf[e]);
+  for (long e0 = threadIdx.x; e0 < count; e0 += 4 * 1024) {
+    double v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const long e = e0 + 1024L * u;
+      v[u] = e < count ? fabs(psf[e]) : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      m = fmax(m, v[u]);
+      t += v[u];
+    }
   }
   sh[threadIdx.x] = m;
   ss[threadIdx.x] = t;
   __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
+  for (int w = 512; w > 0; w >>= 1) {
     if (threadIdx.x < w) {
       sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + w]);
       ss[threadIdx.x] += ss[threadIdx.x + w];
@@ -106,7 +118,7 @@ __global__ void psf_split_scale_kernel(const double* __restrict__ psf, long coun
 
 void launch_psf_split_scale(const double* psf, long count, int nsum, double* scal,
                             hipStream_t s) {
-  hipLaunchKernelGGL(psf_split_scale_kernel, dim3(1), dim3(256), 0, s, psf, count, nsum, scal);
+  hipLaunchKernelGGL(psf_split_scale_kernel, dim3(1), dim3(1024), 0, s, psf, count, nsum, scal);
 }
 
 __device__ __forceinline__ __half d2h(double v) { return __half_raw{static_cast<_Float16>(v)}; }

@@ -4,23 +4,6 @@
 
 namespace kpsb {
 
-// After a third Gram-Schmidt pass on the normalized column q = w / r:
-// q = sum_i h3_i v_i + r3 q', hence w = sum_i (R_ij + r h3_i) v_i + r r3 q'.
-__global__ void cgs_fixup_kernel(double* __restrict__ Rcol, int m, const double* __restrict__ h3,
-                                 double* __restrict__ rjj, const double* __restrict__ r3,
-                                 const int* __restrict__ replaced) {
-  if (replaced && *replaced) return;
-  const int i = threadIdx.x;
-  const double r = *rjj;
-  if (i < m) Rcol[i] += r * h3[i];
-  __syncthreads();
-  if (i == 0) *rjj = r * (*r3);
-}
-void launch_cgs_fixup(double* Rcol, int m, const double* h3, double* rjj, const double* r3,
-                      const int* replaced, hipStream_t s) {
-  hipLaunchKernelGGL(cgs_fixup_kernel, dim3(1), dim3(64), 0, s, Rcol, m, h3, rjj, r3, replaced);
-}
-
 // out (nc x m, ld nc) = in^T (in: m x nc, ld m)
 __global__ void transpose_small_kernel(const double* __restrict__ in, int m, int nc,
                                        double* __restrict__ out) {
