@@ -9,6 +9,8 @@
 namespace kpsb {
 
 constexpr int kJmax = 64;
+constexpr int kJThreads = 1024;   // 16 waves: every pair of a round has its own wave
+constexpr int kJWaves = kJThreads / 64;
 
 __device__ __forceinline__ double jwave_sum(double v) {
 #pragma unroll
@@ -16,13 +18,12 @@ __device__ __forceinline__ double jwave_sum(double v) {
   return v;
 }
 
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(kJThreads)
 jacobi_svd_kernel(const double* __restrict__ A, int m, int nc, double* __restrict__ U,
                   double* __restrict__ sig, double* __restrict__ V, int* __restrict__ sweeps_out) {
   __shared__ double W[kJmax * kJmax];    // columns of the working matrix (ld kJmax)
   __shared__ double Vs[kJmax * kJmax];   // accumulated right rotations (ld kJmax)
   __shared__ double nrm[kJmax];
-  __shared__ int perm[kJmax];
   __shared__ int order[kJmax];
   __shared__ int rotated;
 
@@ -31,13 +32,21 @@ jacobi_svd_kernel(const double* __restrict__ A, int m, int nc, double* __restric
   const int wave = tid >> 6;
   const int nce = (nc + 1) & ~1;           // even number of columns (zero pad)
 
-  for (int e = tid; e < kJmax * kJmax; e += 256) {
+  for (int e = tid; e < kJmax * kJmax; e += kJThreads) {
     const int r = e % kJmax, c = e / kJmax;
     W[e] = (r < m && c < nc) ? A[r + (long)m * c] : 0.0;
     Vs[e] = (r == c) ? 1.0 : 0.0;
   }
-  if (tid < kJmax) perm[tid] = tid;
   __syncthreads();
+  // Round-robin tournament: in round r of a sweep, position 0 holds column 0
+  // and position i >= 1 holds column 1 + ((i - 1 - r) mod (nce - 1)) (column 0
+  // fixed, the others rotated by one position per round; after nce - 1 rounds
+  // the order is back to the start). Round r pairs positions k and nce - 1 - k.
+  auto pos = [&](int i, int r) {
+    if (i == 0) return 0;
+    const int t = (i - 1 - r) % (nce - 1);
+    return 1 + (t < 0 ? t + nce - 1 : t);
+  };
 
   const double tol = 4.0 * 2.220446049250313e-16;
   int sweep = 0;
@@ -45,10 +54,11 @@ jacobi_svd_kernel(const double* __restrict__ A, int m, int nc, double* __restric
     if (tid == 0) rotated = 0;
     __syncthreads();
     for (int round = 0; round < nce - 1; ++round) {
-      // pairs (perm[k], perm[nce-1-k]) for k < nce/2, four waves at a time
-      for (int k = wave; k < nce / 2; k += 4) {
-        const int p = perm[k];
-        const int q = perm[nce - 1 - k];
+      // the round's nce / 2 disjoint pairs, one per wave (they commute, so the
+      // result does not depend on which wave takes which)
+      for (int k = wave; k < nce / 2; k += kJWaves) {
+        const int p = pos(k, round);
+        const int q = pos(nce - 1 - k, round);
         const double wp = (lane < m) ? W[lane + kJmax * p] : 0.0;
         const double wq = (lane < m) ? W[lane + kJmax * q] : 0.0;
         const double alpha = jwave_sum(wp * wp);
@@ -73,13 +83,6 @@ jacobi_svd_kernel(const double* __restrict__ A, int m, int nc, double* __restric
         }
       }
       __syncthreads();
-      // rotate the tournament: keep perm[0], shift the rest by one
-      if (tid == 0) {
-        const int last = perm[nce - 1];
-        for (int i = nce - 1; i > 1; --i) perm[i] = perm[i - 1];
-        perm[1] = last;
-      }
-      __syncthreads();
     }
     const int any = rotated;
     __syncthreads();
@@ -87,7 +90,7 @@ jacobi_svd_kernel(const double* __restrict__ A, int m, int nc, double* __restric
   }
 
   // singular values = column norms, then order descending (ties: lower index)
-  for (int c = wave; c < nc; c += 4) {
+  for (int c = wave; c < nc; c += kJWaves) {
     const double w = (lane < m) ? W[lane + kJmax * c] : 0.0;
     const double s2 = jwave_sum(w * w);
     if (lane == 0) nrm[c] = sqrt(s2);
@@ -103,13 +106,13 @@ jacobi_svd_kernel(const double* __restrict__ A, int m, int nc, double* __restric
     order[rank] = tid;
   }
   __syncthreads();
-  for (int e = tid; e < m * nc; e += 256) {
+  for (int e = tid; e < m * nc; e += kJThreads) {
     const int r = e % m, j = e / m;
     const int c = order[j];
     const double s = nrm[c];
     U[r + (long)m * j] = (s > 0.0) ? W[r + kJmax * c] / s : 0.0;
   }
-  for (int e = tid; e < nc * nc; e += 256) {
+  for (int e = tid; e < nc * nc; e += kJThreads) {
     const int r = e % nc, j = e / nc;
     V[r + (long)nc * j] = Vs[r + kJmax * order[j]];
   }
@@ -119,7 +122,8 @@ jacobi_svd_kernel(const double* __restrict__ A, int m, int nc, double* __restric
 
 void launch_jacobi_svd(const double* A, int m, int nc, double* U, double* sig, double* V,
                        int* sweeps, hipStream_t s) {
-  hipLaunchKernelGGL(jacobi_svd_kernel, dim3(1), dim3(256), 0, s, A, m, nc, U, sig, V, sweeps);
+  hipLaunchKernelGGL(jacobi_svd_kernel, dim3(1), dim3(kJThreads), 0, s, A, m, nc, U, sig, V,
+                     sweeps);
 }
 
 }  // namespace kpsb
