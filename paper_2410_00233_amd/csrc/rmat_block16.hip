@@ -35,8 +35,8 @@ template <> struct Mfma16<__half> {
 };
 
 constexpr int kKS = 32;      // K entries per MFMA step
-constexpr int kSPT = 4;      // MFMA K steps per staged tile (one barrier per tile)
-// LDS row stride of the staged X tile (16-bit elements): 72 words, 8 (mod 16),
+constexpr int kSPT = 8;      // MFMA K steps per staged tile (one barrier per tile; 4 measured slower)
+// LDS row stride of the staged X tile (16-bit elements): 136 words, 8 (mod 16),
 // so that the 16-byte fragment reads of a half-wave fall on distinct banks
 constexpr int kXS16 = kKS * kSPT + 16;
 
@@ -53,8 +53,9 @@ rmat_block16_kernel(const H* __restrict__ G, int ldg, int n, const H* __restrict
   constexpr int NT = 64 * WAVES;
   constexpr int SR = 16 + TJ - 1;
   constexpr int WC = 2 / CB;
-  constexpr int TILE = kKS * kSPT;                    // 128 K entries
-  constexpr int V8 = TILE * 32 / 8;                   // 16-byte chunks per tile (512)
+  constexpr int TILE = kKS * kSPT;                    // K entries per staged tile
+  constexpr int CPC = TILE / 8;                       // 16-byte chunks per column of a tile
+  constexpr int V8 = 32 * CPC;                        // 16-byte chunks per tile
   constexpr int LPT = (V8 + NT - 1) / NT;
   typedef typename Mfma16<H>::vec vec;
   typedef unsigned short u16;
@@ -105,9 +106,9 @@ rmat_block16_kernel(const H* __restrict__ G, int ldg, int n, const H* __restrict
   auto load_tile = [&](int t, uint4* dst) {
 #pragma unroll
     for (int m = 0; m < LPT; ++m) {
-      const int e = tid + NT * m;              // 16-byte chunk: column e / 16, part e % 16
-      const int col = e >> 4;
-      const long off = (long)t * TILE + (e & 15) * 8;
+      const int e = tid + NT * m;              // 16-byte chunk: column e / CPC, part e % CPC
+      const int col = e / CPC;
+      const long off = (long)t * TILE + (e % CPC) * 8;
       uint4 v = make_uint4(0, 0, 0, 0);
       if (e < V8 && col < ncols && off < xlen)
         v = *reinterpret_cast<const uint4*>(reinterpret_cast<const u16*>(X) + (long)col * ldx + off);
@@ -119,7 +120,7 @@ rmat_block16_kernel(const H* __restrict__ G, int ldg, int n, const H* __restrict
 #pragma unroll
     for (int m = 0; m < LPT; ++m) {
       const int e = tid + NT * m;
-      if (e < V8) *reinterpret_cast<uint4*>(xs + (e >> 4) * kXS16 + (e & 15) * 8) = stage[m];
+      if (e < V8) *reinterpret_cast<uint4*>(xs + (e / CPC) * kXS16 + (e % CPC) * 8) = stage[m];
     }
   };
 
