@@ -36,9 +36,9 @@ MFMA_FP32_PEAK_TFLOPS = 157.3     # MI355X dense FP32 matrix peak
 # rocprofv3 FETCH_SIZE / WRITE_SIZE scaled by a plain copy of known size
 # (profiles/rmat_products_n512_hbm_counters.md), valid while the kernel source
 # is the one the counters were taken on.
-BLOCK_TRAFFIC_BYTES = 1.150e9
+BLOCK_TRAFFIC_BYTES = 1.149e9
 BLOCK_TRAFFIC_SRC_SHA1 = "c9f9d96d94bf60de4d191773a87440e33932a1fa"
-BLOCK16_TRAFFIC_BYTES = 1.92e8
+BLOCK16_TRAFFIC_BYTES = 2.10e8
 # template arguments <TJ, JB, CB> of the FP32 block kernel per autotuner variant
 BLOCK_VARIANT_TEMPLATE = {0: "16,1,2,false,64", 1: "16,2,2,false,64", 2: "8,1,2,false,64",
                           3: "8,1,1,false,64", 4: "16,1,2,false,128", 5: "16,2,2,false,128",
@@ -48,7 +48,7 @@ BLOCK_VARIANT_TEMPLATE = {0: "16,1,2,false,64", 1: "16,2,2,false,64", 2: "8,1,2,
                           15: "8,1,1,false,176"}
 BLOCK16_VARIANT_TEMPLATE = {0: "32,4,2", 1: "16,4,2", 2: "32,2,2", 3: "16,2,2", 4: "16,1,2",
                             5: "64,4,2", 6: "64,8,2"}
-BLOCK16_TRAFFIC_SRC_SHA1 = "9208c1360feb4fa285b091e09c9a641b7d2a83ac"
+BLOCK16_TRAFFIC_SRC_SHA1 = "5a1fa497d43ed0c66b378fccc7483a2fd36397ef"
 
 
 def counted_traffic(src, sha, value):
