@@ -438,7 +438,7 @@ kp_status split16_product(kp_ctx* c, const kp_blur* b, const double* dpsf, int n
   const RmatTerms tm = make_terms(b->bc, n);
   double* scal = nullptr;
   __half *Ghi = nullptr, *Glo = nullptr, *Xhi = nullptr, *Xlo = nullptr;
-  KP_TRY(wsT(c, "split_scal", 2, &scal));
+  KP_TRY(wsT(c, "split_scal", (size_t)psf_split_scale_len(), &scal));
   KP_TRY(wsT(c, "G_split_hi", gcount, &Ghi));
   KP_TRY(wsT(c, "G_split_lo", gcount, &Glo));
   const long ld16 = x16_column_len(n);
@@ -638,8 +638,11 @@ kp_status cgs_qr(kp_ctx* c, const Scratch& sc, T* W, long N, int m, double* Rfac
   KP_TRY(wsT(c, std::string("cgs_copy_") + tname<T>(), (size_t)N * m, &copy));
   KP_HIP(c, hipMemcpyAsync(copy, W, sizeof(T) * N * m, hipMemcpyDeviceToDevice, s));
   int* hflags = reinterpret_cast<int*>(c->pinned + 32);   // kCgsChunk ints
+  // KPSB_CGS_EAGER=1 takes the predicated sequence from the first column (to
+  // check that both orders give the same bits)
+  const char* eager = getenv("KPSB_CGS_EAGER");
   int j = 0;
-  while (j < m) {   // unpredicated chunks
+  while (j < m && !(eager && atoi(eager) != 0)) {   // unpredicated chunks
     const int j1 = std::min(m, j + kCgsChunk);
     for (int q = j; q < j1; ++q) cgs_column<T>(sc, W, N, q, rcol(q), rdiag(q), sc.flags + q, s);
     KP_TRY(check_launch(c, "cgs_qr"));

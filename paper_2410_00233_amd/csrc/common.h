@@ -96,9 +96,11 @@ void launch_to16_split(const float* in, long ldx, int n, int ncols, __half* hi, 
 // scal[0] = 2^e with e the largest integer such that m * 2^e <= 1024, where m
 // bounds every grid entry (max|P| when nsum = 1; min(nsum max|P|, sum|P|) for
 // grids summing up to nsum PSF entries); scal[1] = 1 / (scal[0] * 2^kSplitXExp).
+// scal holds psf_split_scale_len() doubles (the rest: partial maxima and sums).
 // Device only, no host sync.
 void launch_psf_split_scale(const double* psf, long count, int nsum, double* scal,
                             hipStream_t s);
+int psf_split_scale_len();
 // FP16 grid of the scaled PSF: part 0 = fp16(G s), part 1 = fp16(G s - part 0).
 void launch_build_grid_split(const double* psf, int pu, int pv, int cu, int cv, int n,
                              int transpose, const GridShifts& sh, const double* scal, int part,

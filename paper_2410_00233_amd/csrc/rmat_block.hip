@@ -70,42 +70,54 @@ __global__ void build_grid_kernel(const double* __restrict__ psf, int pu, int pv
   }
 }
 
-// One workgroup of 1024 threads; each thread keeps four loads in flight
-// (the PSF of n = 512 on its full offset grid is 8 MB).
-__global__ void __launch_bounds__(1024)
-psf_split_scale_kernel(const double* __restrict__ psf, long count, int nsum,
-                       double* __restrict__ scal) {
-  __shared__ double sh[1024];
-  __shared__ double ss[1024];
-  double m = 0.0, t = 0.0;
-  for (long e0 = threadIdx.x; e0 < count; e0 += 4 * 1024) {
-    double v[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const long e = e0 + 1024L * u;
-      v[u] = e < count ? fabs(psf[e]) : 0.0;
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      m = fmax(m, v[u]);
-      t += v[u];
-    }
-  }
-  sh[threadIdx.x] = m;
-  ss[threadIdx.x] = t;
-  __syncthreads();
-  for (int w = 512; w > 0; w >>= 1) {
-    if (threadIdx.x < w) {
-      sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + w]);
+// Two stages: kScaleParts workgroups write partial max|P| and sum|P| into
+// scal[2 ..], one workgroup adds them in a fixed order (tree over the parts).
+constexpr int kScaleParts = 256;
+
+__device__ __forceinline__ void block_max_sum(double* sm, double* ss) {
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + w]);
       ss[threadIdx.x] += ss[threadIdx.x + w];
     }
     __syncthreads();
   }
+}
+
+__global__ void __launch_bounds__(256)
+psf_scale_partial_kernel(const double* __restrict__ psf, long count, double* __restrict__ part) {
+  __shared__ double sm[256];
+  __shared__ double ss[256];
+  double m = 0.0, t = 0.0;
+  for (long e = blockIdx.x * 256L + threadIdx.x; e < count; e += 256L * kScaleParts) {
+    const double v = fabs(psf[e]);
+    m = fmax(m, v);
+    t += v;
+  }
+  sm[threadIdx.x] = m;
+  ss[threadIdx.x] = t;
+  __syncthreads();
+  block_max_sum(sm, ss);
+  if (threadIdx.x == 0) {
+    part[blockIdx.x] = sm[0];
+    part[kScaleParts + blockIdx.x] = ss[0];
+  }
+}
+
+__global__ void __launch_bounds__(256)
+psf_scale_final_kernel(int nsum, double* __restrict__ scal) {
+  __shared__ double sm[256];
+  __shared__ double ss[256];
+  const double* part = scal + 2;
+  sm[threadIdx.x] = part[threadIdx.x];                 // kScaleParts == 256
+  ss[threadIdx.x] = part[kScaleParts + threadIdx.x];
+  __syncthreads();
+  block_max_sum(sm, ss);
   if (threadIdx.x == 0) {
     double sc = 1.0;
     // a grid entry is a sum of at most nsum distinct PSF entries, so
     // min(nsum max|P|, sum|P|) bounds it (max|P| itself when nsum = 1)
-    const double mx = nsum <= 1 ? sh[0] : fmin(nsum * sh[0], ss[0]);
+    const double mx = nsum <= 1 ? sm[0] : fmin(nsum * sm[0], ss[0]);
     if (mx > 0.0) {
       int ex = 0;
       (void)frexp(1024.0 / mx, &ex);      // 1024 / mx = f 2^ex, f in [0.5, 1)
@@ -116,9 +128,13 @@ psf_split_scale_kernel(const double* __restrict__ psf, long count, int nsum,
   }
 }
 
+int psf_split_scale_len() { return 2 + 2 * kScaleParts; }
+
 void launch_psf_split_scale(const double* psf, long count, int nsum, double* scal,
                             hipStream_t s) {
-  hipLaunchKernelGGL(psf_split_scale_kernel, dim3(1), dim3(1024), 0, s, psf, count, nsum, scal);
+  hipLaunchKernelGGL(psf_scale_partial_kernel, dim3(kScaleParts), dim3(256), 0, s, psf, count,
+                     scal + 2);
+  hipLaunchKernelGGL(psf_scale_final_kernel, dim3(1), dim3(256), 0, s, nsum, scal);
 }
 
 __device__ __forceinline__ __half d2h(double v) { return __half_raw{static_cast<_Float16>(v)}; }

@@ -228,3 +228,23 @@ def test_rsvd_refine_with_split_fp16_product(ctx, prec, n, psf):
     print(f"RSVD {prec} n={n} {psf}: split-FP16 refine err {e2:.2e}, vs FP32 refine {d12:.2e}")
     assert e2 <= 1e-5
     assert d12 <= 1e-6
+
+
+@pytest.mark.parametrize("n,psf,prec", [(64, "disk", "f32"), (48, "disk", "f64"),
+                                        (128, "gaussian", "f32")])
+def test_rsvd_qr_chunks_match_predicated_sequence(ctx, n, psf, prec, monkeypatch):
+    """The QR that first runs its columns without the replacement kernels and
+    restarts at the first dependent column gives the same bits as the
+    predicated sequence from column 0 (the disk PSF has Kronecker rank 6, so
+    columns 7.. of its sketches are replaced)."""
+    import torch
+    from paper_2410_00233_amd import api
+    P, cu, cv = wl.disk_psf(n) if psf == "disk" else wl.gaussian_psf(n)
+    blur = api.Blur(P, cu, cv, n)
+    F = wl.gaussian_block(n * n, 30, seed=wl.SEED_START + 5)
+    f1 = ctx.kp_svd_rsvd(blur, 20, 10, 2, prec=prec, F=F, refine=1 if prec == "f32" else 0)
+    monkeypatch.setenv("KPSB_CGS_EAGER", "1")
+    f2 = ctx.kp_svd_rsvd(blur, 20, 10, 2, prec=prec, F=F, refine=1 if prec == "f32" else 0)
+    monkeypatch.delenv("KPSB_CGS_EAGER")
+    assert np.array_equal(f1.sigma[:f1.k], f2.sigma[:f2.k])
+    assert torch.equal(f1.Ax[:f1.k], f2.Ax[:f2.k]) and torch.equal(f1.Ay[:f1.k], f2.Ay[:f2.k])
