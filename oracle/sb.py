@@ -16,6 +16,12 @@ Readings of open passages:
   is 0 at the first step).
 * CGLS starts from x = 0 at every outer iteration (Algorithm 5).
 * tau_cgls = 0 or tau_sb = 0 means a fixed iteration count.
+
+With the x-update solved exactly, a fixed point of Algorithms 3/4 has d = L x
+and g a subgradient of (beta / lambda^2) TV at L x, so the loop converges to
+the minimizer of ||A x - b||^2 + 2 beta TV(x) (anisotropic: the l1 norms of the
+two difference images; isotropic: the sum of the pixelwise gradient lengths).
+The tests check this against the minimizer computed through the Lagrange dual.
 """
 from __future__ import annotations
 

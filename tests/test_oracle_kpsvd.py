@@ -166,6 +166,43 @@ def test_refine_recovers_exact_triplets_and_improves_perturbed_subspace():
     assert np.all(out["sigma"] <= s_ex * (1 + 1e-12))
 
 
+def test_refine_on_a_rotated_exact_subspace_returns_the_exact_triplets():
+    # V = V_exact Q with a random orthogonal Q spans the exact subspace but
+    # mixes its directions: the refinement must undo the mixing, giving the
+    # exact right and left singular vectors (up to sign) and B V_r = U_r S_r
+    n = 20
+    P, cu, cv = wl.speckle_psf(n, seed=1005)
+    R, Rt = _ops(P, cu, cv, n)
+    k = 8
+    s_ex, U_ex, V_ex = op.exact_kpsvd(P, cu, cv, n, k)
+    assert np.all(np.diff(s_ex) < -1e-3 * s_ex[0])           # distinct sigma
+    Qm, _ = np.linalg.qr(np.random.default_rng(3).standard_normal((k, k)))
+    out = kpsvd.refine(R, V_ex @ Qm)
+    assert np.allclose(out["sigma"], s_ex, rtol=1e-12)
+    for i in range(k):
+        sg = np.sign(out["V"][:, i] @ V_ex[:, i])
+        assert np.abs(out["V"][:, i] - sg * V_ex[:, i]).max() <= 1e-10
+        assert np.abs(out["U"][:, i] - sg * U_ex[:, i]).max() <= 1e-10
+
+
+def test_refine_triplets_satisfy_b_v_equals_u_sigma_on_a_perturbed_subspace():
+    n = 20
+    P, cu, cv = wl.speckle_psf(n, seed=1006)
+    R, Rt = _ops(P, cu, cv, n)
+    k = 10
+    s_ex, _, V_ex = op.exact_kpsvd(P, cu, cv, n, k)
+    rng = np.random.default_rng(4)
+    V = V_ex @ np.linalg.qr(rng.standard_normal((k, k)))[0] + 1e-2 * rng.standard_normal(V_ex.shape) / n
+    out = kpsvd.refine(R, V)
+    Vr, Ur, sr = out["V"], out["U"], out["sigma"]
+    assert np.linalg.norm(R(Vr) - Ur * sr) <= 1e-12 * s_ex[0]
+    assert np.abs(Vr.T @ Vr - np.eye(k)).max() <= 1e-13
+    assert np.abs(Ur.T @ Ur - np.eye(k)).max() <= 1e-13
+    # the refined directions lie in range(V)
+    Qv = np.linalg.qr(V)[0]
+    assert np.linalg.norm(Vr - Qv @ (Qv.T @ Vr)) <= 1e-13
+
+
 def test_kp_terms_reconstruct_A_with_full_rank():
     n = 6
     P, cu, cv = wl.random_psf(4, 5, 21)

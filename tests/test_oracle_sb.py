@@ -201,3 +201,28 @@ def test_philox_normals_are_standard_and_stream_distinct():
     z2 = philox.normals(1000, seed=123, stream=6)
     assert not np.allclose(z[:1000], z2)
     assert np.array_equal(philox.normals(10, 123, 5), z[:10])
+
+
+# ---------------------------------------------------------------------------
+# the loop against the mathematics: Algorithms 3/4 converge to the minimizer of
+# ||A x - b||^2 + 2 beta TV(x) (the factor 2 from the printed threshold 1/gamma),
+# computed independently through the Lagrange dual and certified by its
+# duality gap (tests/_sb_pins.py)
+
+@pytest.mark.parametrize("kind", ["aniso", "iso"])
+def test_sb_converges_to_certified_tv_minimizer(kind):
+    from _sb_pins import loop_error
+    err = loop_error(sb, kind)
+    assert err <= 1e-6, err
+
+
+@pytest.mark.parametrize("kind", ["aniso", "iso"])
+def test_tv_minimizer_changes_with_beta(kind):
+    # the pin resolves the regularization weight: doubling beta (the printed
+    # threshold's factor 2, or gamma inverted) moves the minimizer by far more
+    # than the 1e-6 gate
+    from _sb_pins import BETA, problem, tv_minimizer
+    A, b = problem()
+    x1, _ = tv_minimizer(kind, A, b, BETA)
+    x2, _ = tv_minimizer(kind, A, b, 2 * BETA)
+    assert np.linalg.norm(x1 - x2) >= 1e-2 * np.linalg.norm(x1)
