@@ -238,6 +238,25 @@ kp_status kp_tune_report(char* out, size_t cap);
 kp_status kp_rmat_apply(kp_ctx* ctx, const kp_blur* blur, int transpose, kp_prec prec,
                         int32_t ncols, const void* X, void* Y, void* stream);
 
+/* kp_rmat_apply for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same product, kernels and bits as kp_rmat_apply with the same arguments, but
+ * every workspace buffer (PSF copy, grids of R and R^T, support boxes, staging
+ * vector, term buffers) is carved from a static device array of 64 MiB that
+ * the library holds on each GPU it runs on until the process ends; the call
+ * makes no hipMalloc / hipFree and times no autotuner candidates (a launch shape
+ * not chosen yet in the process takes the tuner's first variant, which gives
+ * the same bits). prec: KP_F32 or KP_F64 (KP_E_INVAL otherwise). A product whose
+ * workspace exceeds the array (PSF entries x 8 + 2 grids of
+ * (2n + 48)^2 elements + ..., e.g. n = 512 with a full (2n-1)^2 PSF needs about
+ * 18 MB in FP32 and 27 MB in FP64) is refused with KP_E_NOMEM before anything
+ * is queued. Every call on one GPU, from any context, uses that GPU's one array,
+ * which keeps the last call's contents: calls that overlap on a GPU (other
+ * threads, other streams not ordered with this one) race and give undefined
+ * results. */
+kp_status kp_rmat_apply_noalloc(kp_ctx* ctx, const kp_blur* blur, int transpose, kp_prec prec,
+                                int32_t ncols, const void* X, void* Y, void* stream);
+
 /* Rank-k KP-SVD of R(A) by EGKB (Algorithm 1). Writes out->k terms. Returns
  * KP_W_BREAKDOWN when a breakdown was deflated (result still valid). */
 kp_status kp_svd_gkb(kp_ctx* ctx, const kp_blur* blur, const kp_gkb_opts* opts,

@@ -30,7 +30,7 @@ EXPORTED = ["kp_ctx_create", "kp_ctx_destroy", "kp_last_error", "kp_version",
             "kp_server_create", "kp_server_submit", "kp_server_wait", "kp_server_stats",
             "kp_server_destroy", "kp_tune_report", "kp_rmat_reorder", "kp_rmat_apply_stored",
             "kp_svd_gkb_stored", "kp_svd_rsvd_stored", "sb_solve_aniso_direct",
-            "sb_solve_iso_direct", "kp_blur_matrix"]
+            "sb_solve_iso_direct", "kp_blur_matrix", "kp_rmat_apply_noalloc"]
 
 
 class kp_blur(C.Structure):
@@ -124,6 +124,7 @@ def load(path: str = LIB_PATH):
     lib.kp_prof_enable.argtypes = [vp, C.c_int]
     lib.kp_prof_read.argtypes = [vp, C.POINTER(kp_prof), C.c_int]
     lib.kp_rmat_apply.argtypes = [vp, C.POINTER(kp_blur), C.c_int, C.c_int, C.c_int32, vp, vp, vp]
+    lib.kp_rmat_apply_noalloc.argtypes = lib.kp_rmat_apply.argtypes
     lib.kp_svd_gkb.argtypes = [vp, C.POINTER(kp_blur), C.POINTER(kp_gkb_opts),
                                C.POINTER(kp_factors), vp]
     lib.kp_svd_rsvd.argtypes = [vp, C.POINTER(kp_blur), C.POINTER(kp_rsvd_opts),

@@ -165,6 +165,19 @@ class Context:
                                            ncols, _ptr(X), _ptr(Y), _stream()))
         return Y
 
+    def kp_rmat_apply_noalloc(self, blur: Blur, X, transpose=False, prec="f32", Y=None):
+        """kp_rmat_apply with every workspace buffer taken from the library's static
+        device scratch (no device allocation by the library)."""
+        torch = _torch()
+        assert X.is_contiguous() and X.shape[-1] == blur.n * blur.n
+        ncols = 1 if X.dim() == 1 else X.shape[0]
+        if Y is None:
+            Y = torch.empty_like(X)
+        self._check(self.lib.kp_rmat_apply_noalloc(self.h, C.byref(blur.s), int(transpose),
+                                                   PREC[prec], ncols, _ptr(X), _ptr(Y),
+                                                   _stream()))
+        return Y
+
     def kp_svd_gkb(self, blur: Blur, k, p, *, k_min=0, auto_k=False, tau=0.0,
                    literal_init=False, reorth=1, prec="f32", seed=0, y0=None, bd_rel=0.0,
                    factor_prec="f64", k_cap=None, bases=False, stored=None, block=0):

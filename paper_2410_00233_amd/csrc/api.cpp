@@ -51,6 +51,15 @@ kp_status check_launch(kp_ctx* c, const char* where) {
 
 // Workspace buffer `name` of at least `bytes` (contents undefined).
 kp_status ws(kp_ctx* c, const std::string& name, size_t bytes, void** out) {
+  if (c->arena_base) {   // allocation-free mode: carve from the caller's scratch
+    const size_t need = (bytes + 255) & ~(size_t)255;
+    if (c->arena_used + need > c->arena_cap)
+      return set_err(c, KP_E_NOMEM, "workspace '" + name + "' does not fit the static scratch (" +
+                                        std::to_string(c->arena_cap) + " bytes)");
+    *out = c->arena_base + c->arena_used;
+    c->arena_used += need;
+    return KP_OK;
+  }
   auto& b = c->bufs[name];
   if (b.bytes >= bytes && b.p) {
     *out = b.p;
@@ -1570,6 +1579,11 @@ kp_status kp_ctx_create(int device, size_t hbm_budget_bytes, kp_ctx** out) {
   if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return KP_E_DEVICE;
   kp_ctx* c = ctx_new(device, nullptr, hbm_budget_bytes);
   if (!c) return KP_E_DEVICE;
+  // the device address of this device's static scratch (device current here)
+  if (scratch_address(device, &c->scratch) != hipSuccess) {
+    ctx_free(c);
+    return KP_E_DEVICE;
+  }
   *out = c;
   return KP_OK;
 }
@@ -1624,15 +1638,40 @@ kp_status kp_prof_read(kp_ctx* c, kp_prof* out, int reset) {
   return KP_OK;
 }
 
-kp_status kp_rmat_apply(kp_ctx* c, const kp_blur* b, int transpose, kp_prec prec, int32_t ncols,
-                        const void* X, void* Y, void* stream) {
-  if (!c) return KP_E_INVAL;
+namespace {
+kp_status check_rmat_apply(kp_ctx* c, const kp_blur* b, int32_t ncols, const void* X, void* Y) {
   KP_TRY(validate_blur(c, b));
   if (ncols < 1 || ncols > 4096) return set_err(c, KP_E_INVAL, "ncols must be in [1, 4096]");
   if (!X || !Y) return set_err(c, KP_E_INVAL, "X or Y is NULL");
   if (X == Y) return set_err(c, KP_E_INVAL, "X and Y must not alias");
+  return KP_OK;
+}
+
+// The workspace an FP32 / FP64 kp_rmat_apply requests, in the order and the
+// 256-byte granules in which ws() carves it: the PSF copy (or the finiteness
+// flag of a device PSF), per term the grids of R and R^T (with compaction their
+// support boxes and the box reduction's partials; for one FP32 column the
+// matrix-vector kernel's staging vector), and with several terms the reversed
+// input and three term outputs of multi_term.
+size_t rmat_apply_ws_bytes(const kp_blur* b, kp_prec prec, int ncols) {
+  auto r = [](size_t x) { return (x + 255) & ~(size_t)255; };
+  const int n = b->n;
+  const size_t es = prec == KP_F64 ? sizeof(double) : sizeof(float);
+  const RmatTerms tm = make_terms(b->bc, n);
+  const size_t ldg = (size_t)grid_ld(n);
+  size_t need = b->psf_on_device ? r(4 * sizeof(int)) : r(sizeof(double) * b->pu * b->pv);
+  for (int t = 0; t < tm.nterm; ++t) {
+    need += 2 * r(ldg * ldg * es);
+    if (b->compact) need += r(sizeof(int) * (size_t)grid_box_parts()) + r(8 * sizeof(int));
+    if (ncols == 1 && prec == KP_F32) need += r(sizeof(float) * (size_t)gemv_sx_xt_len(n));
+  }
+  if (tm.nterm > 1) need += 4 * r((size_t)n * n * ncols * es);
+  return need;
+}
+
+kp_status rmat_apply_body(kp_ctx* c, const kp_blur* b, int transpose, kp_prec prec,
+                          int32_t ncols, const void* X, void* Y, hipStream_t s) {
   KP_HIP(c, hipSetDevice(c->device));
-  hipStream_t s = (hipStream_t)stream;
   const int n = b->n;
   if (prec == KP_F32) {
     Grids<float> g;
@@ -1662,6 +1701,47 @@ kp_status kp_rmat_apply(kp_ctx* c, const kp_blur* b, int transpose, kp_prec prec
     return block_product16<__half>(c, g, n, transpose, (const float*)X, (float*)Y, ncols, s);
   }
   return set_err(c, KP_E_INVAL, "precision not supported by kp_rmat_apply");
+}
+
+// Workspace requests of the context come from the static scratch while alive;
+// the autotuner times nothing meanwhile.
+struct ArenaScope {
+  kp_ctx* c;
+  ArenaScope(kp_ctx* ctx, void* base, size_t cap) : c(ctx) {
+    c->arena_base = static_cast<char*>(base);
+    c->arena_cap = cap;
+    c->arena_used = 0;
+    tune_set_no_timing(true);
+  }
+  ~ArenaScope() {
+    c->arena_base = nullptr;
+    c->arena_cap = c->arena_used = 0;
+    tune_set_no_timing(false);
+  }
+};
+}  // namespace
+
+kp_status kp_rmat_apply(kp_ctx* c, const kp_blur* b, int transpose, kp_prec prec, int32_t ncols,
+                        const void* X, void* Y, void* stream) {
+  if (!c) return KP_E_INVAL;
+  KP_TRY(check_rmat_apply(c, b, ncols, X, Y));
+  return rmat_apply_body(c, b, transpose, prec, ncols, X, Y, (hipStream_t)stream);
+}
+
+kp_status kp_rmat_apply_noalloc(kp_ctx* c, const kp_blur* b, int transpose, kp_prec prec,
+                                int32_t ncols, const void* X, void* Y, void* stream) {
+  if (!c) return KP_E_INVAL;
+  KP_TRY(check_rmat_apply(c, b, ncols, X, Y));
+  if (prec != KP_F32 && prec != KP_F64)
+    return set_err(c, KP_E_INVAL, "kp_rmat_apply_noalloc supports KP_F32 and KP_F64");
+  if (!c->scratch) return set_err(c, KP_E_DEVICE, "the static scratch of this device is unavailable");
+  const size_t need = rmat_apply_ws_bytes(b, prec, ncols);
+  if (need > scratch_capacity())
+    return set_err(c, KP_E_NOMEM, "this product needs " + std::to_string(need) +
+                                      " bytes of scratch; the static scratch holds " +
+                                      std::to_string(scratch_capacity()));
+  ArenaScope arena(c, c->scratch, scratch_capacity());
+  return rmat_apply_body(c, b, transpose, prec, ncols, X, Y, (hipStream_t)stream);
 }
 
 namespace {

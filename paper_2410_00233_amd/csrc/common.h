@@ -166,6 +166,15 @@ int tune_pick(int op, int n, int a, int b, int ncand, const std::function<double
 // (true when autotuning is off).
 bool tune_known(int op, int n, int a, int b);
 std::string tune_table();   // JSON list of the choices and measured costs
+// While set on the calling thread, tune_pick times nothing: it returns the
+// variant already chosen for the key, else variant 0 (without recording it).
+void tune_set_no_timing(bool on);
+
+// ---- static device scratch (noalloc.hip) -----------------------------------
+size_t scratch_capacity();   // bytes
+// Device address of `device`'s copy of the scratch array (call with that device
+// current); looked up once per device, then cached.
+hipError_t scratch_address(int device, void** out);
 
 // ---- vector kernels (blas1.hip) --------------------------------------------
 // partials[b * m + i] = sum over rows of block b of V[:, i] . w  (FP64 accum)

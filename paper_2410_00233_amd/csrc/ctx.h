@@ -45,6 +45,12 @@ struct kp_ctx {
   // batched call; created on first use and kept with their workspaces.
   std::vector<kp_ctx*> workers;
   hipStream_t own_stream = nullptr;   // set for worker contexts only
+  // Allocation-free mode (kp_rmat_apply_noalloc): while arena_base is set, every
+  // workspace request is carved, in order, from arena_base[0, arena_cap) and
+  // nothing is allocated or freed.
+  char* arena_base = nullptr;
+  size_t arena_cap = 0, arena_used = 0;
+  void* scratch = nullptr;   // this device's static scratch array (device address)
 };
 
 namespace kpsb {

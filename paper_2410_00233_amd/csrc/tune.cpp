@@ -26,6 +26,7 @@ struct Choice {
 };
 
 std::mutex g_mu;
+thread_local bool t_no_timing = false;
 std::map<std::tuple<int, int, int, int, int>, Choice> g_table;
 
 const char* op_name(int op) {
@@ -68,7 +69,16 @@ bool tune_known(int op, int n, int a, int b) {
   return g_table.count(std::make_tuple(op, dev, n, a, b)) != 0;
 }
 
+void tune_set_no_timing(bool on) { t_no_timing = on; }
+
 int tune_pick(int op, int n, int a, int b, int ncand, const std::function<double(int)>& cost) {
+  if (t_no_timing) {
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_table.find(std::make_tuple(op, dev, n, a, b));
+    return it != g_table.end() ? it->second.variant : 0;
+  }
   // KPSB_TUNE_FORCE=v pins every operation to its variant v when that variant
   // applies (used to check that all variants agree bit for bit)
   if (const char* f = getenv("KPSB_TUNE_FORCE")) {
