@@ -75,9 +75,14 @@ def egkb(apply_R, apply_Rt, y, k, p, *, reorth="full", auto_k=False, k_min=0,
     kp = k + p
     y = np.asarray(y, dtype=dtype)
 
+    forced = []    # (side, j, own norm, scale) at each forced step
+
     def is_bd(side, j, val, scale):
         if force_breakdown is not None:
-            return (side, j) in force_breakdown
+            if (side, j) in force_breakdown:
+                forced.append((side, j, float(val), float(scale)))
+                return True
+            return False
         return val <= bd_rel * scale or val == 0.0
 
     def restart(side, j, basis, size):
@@ -148,7 +153,7 @@ def egkb(apply_R, apply_Rt, y, k, p, *, reorth="full", auto_k=False, k_min=0,
     V = Qm @ Vct[:k].T
     return dict(sigma=sc[:k].copy(), sigma_all=sc, U=U, V=V, S=Sm, Q=Qm, C=C,
                 alpha=np.array(alpha[:kp]), t=np.array(t[:kp + 1]), nu=nu,
-                k=k, kp=kp, breakdowns=breakdowns, Uc=Uc, Vc=Vct.T)
+                k=k, kp=kp, breakdowns=breakdowns, Uc=Uc, Vc=Vct.T, forced=forced)
 
 
 def _gs_column(w, basis, passes=2):
@@ -212,6 +217,7 @@ def block_egkb(apply_R, apply_Rt, Y, k, p, *, bd_rel=None, seed=0, dtype=np.floa
     nb = -(-(k + p) // b)
     kp = nb * b
     breakdowns = []
+    forced = []    # (side, m, own norm, scale) at each forced column
     scale = [0.0]
 
     def orth_block(W, basis, side, col0, in_c):
@@ -226,6 +232,8 @@ def block_egkb(apply_R, apply_Rt, Y, k, p, *, bd_rel=None, seed=0, dtype=np.floa
             m = col0 + c
             if force_breakdown is not None:
                 broken = (side, m) in force_breakdown
+                if broken:
+                    forced.append((side, m, float(nr), float(scale[0])))
             else:
                 broken = nr == 0.0 or (in_c and nr <= bd_rel * scale[0])
             if broken:
@@ -286,7 +294,7 @@ def block_egkb(apply_R, apply_Rt, Y, k, p, *, bd_rel=None, seed=0, dtype=np.floa
     U, V, C = U[:, :kp + b], V[:, :kp], C[:kp + b, :kp]
     Uc, sc, Vct = np.linalg.svd(C, full_matrices=False)
     return dict(sigma=sc[:k].copy(), sigma_all=sc, U=U @ Uc[:, :k], V=V @ Vct[:k].T, Ub=U,
-                Vb=V, C=C, kp=kp, k=k, breakdowns=breakdowns, zeta=zeta, nu=nu)
+                Vb=V, C=C, kp=kp, k=k, breakdowns=breakdowns, zeta=zeta, nu=nu, forced=forced)
 
 
 def orth(X):

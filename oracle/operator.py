@@ -175,6 +175,37 @@ def rmat_dense_apply(P, cu, cv, n, X, transpose=False, row_chunk=256, bc="zero")
     return Y[:, 0] if vec else Y
 
 
+def rmat_window_apply(P, cu, cv, n, X, blocks=None, dtype=np.float64):
+    """Y = R X (zero boundary conditions) as the same dense product, with each
+    n x n block of R read straight from the PSF instead of gathered entry by
+    entry: block (j, c) of R (rows i + n j, columns r + n c) has entries
+    R[i + n j, r + n c] = P[cu + r - c, cv + i - j], i.e. it is the n x n window
+    of the zero-padded transposed PSF whose top-left corner sits at
+    (cv - j, cu - c). Each window is multiplied with BLAS as a strided view (no
+    copy) in ``dtype``; every block of R is visited, so the work is the dense
+    2 N^2 flops per column.
+
+    blocks: optional range of block rows j (rows n*j .. n*j + n - 1 of Y) to
+    compute; the other rows of Y are left zero. X: N x b (or N).
+    """
+    N = n * n
+    X = np.asarray(X)
+    vec = X.ndim == 1
+    Xm = np.ascontiguousarray((X[:, None] if vec else X).astype(dtype, copy=False))
+    pu, pv = P.shape
+    Tp = np.zeros((pv + 2 * (n - 1), pu + 2 * (n - 1)), dtype=dtype)
+    Tp[n - 1:n - 1 + pv, n - 1:n - 1 + pu] = np.asarray(P, dtype=dtype).T
+    Y = np.zeros((N, Xm.shape[1]), dtype=dtype)
+    for j in (range(n) if blocks is None else blocks):
+        acc = np.zeros((n, Xm.shape[1]), dtype=dtype)
+        a0 = cv - j + n - 1
+        for c in range(n):
+            b0 = cu - c + n - 1
+            acc += Tp[a0:a0 + n, b0:b0 + n] @ Xm[n * c:n * c + n]
+        Y[n * j:n * j + n] = acc
+    return Y[:, 0] if vec else Y
+
+
 def offset_matrix(P, cu, cv, n):
     """M[d1 + n-1, d2 + n-1] = P[cu + d2, cv + d1] on the (2n-1)^2 offset grid.
 

@@ -12,6 +12,7 @@ import numpy as np
 import pytest
 
 import workloads as wl
+from _replay import check_replayed_breakdowns
 from oracle import kpsvd, operator as op
 
 pytestmark = pytest.mark.gpu
@@ -127,10 +128,12 @@ def test_kpsvd_with_boundary_conditions_matches_oracle(ctx, bc):
     F = wl.gaussian_block(n * n, k + p, seed=23)
     g = ctx.kp_svd_gkb(blur, k, p, prec="f64", y0=y)
     ref = kpsvd.egkb(apply_R, apply_Rt, y, k, p, force_breakdown=set(g.breakdowns))
+    check_replayed_breakdowns(ref, "f64")
     s1 = ref["sigma"][0]
     assert np.abs(g.sigma[:k] - ref["sigma"]).max() <= 1e-12 * s1
     gb = ctx.kp_svd_gkb(blur, k, p, prec="f64", y0=Y, block=2)
     refb = kpsvd.block_egkb(apply_R, apply_Rt, Y, k, p, force_breakdown=set(gb.breakdowns))
+    check_replayed_breakdowns(refb, "f64")
     assert np.abs(gb.sigma[:k] - refb["sigma"]).max() <= 1e-12 * s1
     r = ctx.kp_svd_rsvd(blur, k, p, q, prec="f64", F=F)
     refr = kpsvd.rsvd(apply_R, apply_Rt, F, k, q)
@@ -158,6 +161,7 @@ def test_kpsvd_f32_with_boundary_conditions(ctx, bc):
     assert np.abs(r.sigma[:k] - refr["sigma"]).max() <= 1e-5 * s1
     g = ctx.kp_svd_gkb(blur, k, p, prec="f32", y0=y, reorth=1)
     ref = kpsvd.egkb(apply_R, apply_Rt, y, k, p, force_breakdown=set(g.breakdowns))
+    check_replayed_breakdowns(ref, "f32")
     assert np.abs(g.sigma[:k] - ref["sigma"]).max() <= 1e-5 * s1
 
 

@@ -11,6 +11,7 @@ import numpy as np
 import pytest
 
 import workloads as wl
+from _replay import check_replayed_breakdowns
 from oracle import kpsvd, metrics, operator as op
 
 pytestmark = pytest.mark.gpu
@@ -41,6 +42,7 @@ def test_block_gkb_f64_matches_oracle(ctx, b):
                        seed=13)
     R, Rt = _ops(P, cu, cv, n)
     ref = kpsvd.block_egkb(R, Rt, Y, k, p, seed=13, force_breakdown=set(f.breakdowns))
+    check_replayed_breakdowns(ref, "f64")
     s1 = ref["sigma"][0]
     kp = ref["kp"]
     assert f.k == k and f.diag.kp == kp
@@ -90,6 +92,7 @@ def test_block_gkb_disk_breakdown_is_exact(ctx):
     assert metrics.kp_rel_error(P, cu, cv, n, s, U, V) <= 1e-8
     R, Rt = _ops(P, cu, cv, n)
     ref = kpsvd.block_egkb(R, Rt, Y, 6, 3, seed=5, force_breakdown=set(f.breakdowns))
+    check_replayed_breakdowns(ref, "f64")
     assert np.abs(f.sigma[:6] - ref["sigma"]).max() <= 1e-12 * s_ex[0]
 
 
@@ -108,6 +111,7 @@ def test_block_gkb_f32_matches_oracle(ctx, n, psf, b):
     f = ctx.kp_svd_gkb(api.Blur(P, cu, cv, n), k, p, prec="f32", y0=Y, block=b, seed=3)
     R, Rt = _ops(P, cu, cv, n)
     ref = kpsvd.block_egkb(R, Rt, Y, k, p, seed=3, force_breakdown=set(f.breakdowns))
+    check_replayed_breakdowns(ref, "f32")
     s1 = ref["sigma"][0]
     err = np.abs(f.sigma[:k] - ref["sigma"]).max() / s1
     print(f"block GKB f32 n={n} {psf} b={b}: max|dsigma|/sigma1 = {err:.2e}, "
@@ -133,6 +137,7 @@ def test_block_gkb_on_stored_R_matches_oracle(ctx, bc):
     f = ctx.kp_svd_gkb(None, k, p, prec="f64", y0=Y, block=b, stored=(n, Rd))
     ref = kpsvd.block_egkb(lambda X: R @ X, lambda X: R.T @ X, Y, k, p,
                            force_breakdown=set(f.breakdowns))
+    check_replayed_breakdowns(ref, "f64")
     assert np.abs(f.sigma[:k] - ref["sigma"]).max() <= 1e-12 * ref["sigma"][0]
 
 
@@ -177,6 +182,7 @@ def test_block_stopping_rule_fires_at_hand_computed_block(ctx):
                            stored=(n, Rd))
         ref = kpsvd.block_egkb(lambda X: R @ X, lambda X: R.T @ X, Y, 12, 2, auto_k=True,
                                tau=tau, force_breakdown=set(f.breakdowns))
+        check_replayed_breakdowns(ref, "f64")
         assert (ref["k"], ref["kp"]) == (k_exp, kp_exp)
         assert (f.k, f.diag.kp) == (k_exp, kp_exp)
         assert np.abs(f.sigma[:k_exp] - ref["sigma"]).max() <= 1e-13
@@ -209,6 +215,7 @@ def test_block_stopping_rule_matches_oracle_on_a_psf(ctx, prec):
         R, Rt = _ops(P, cu, cv, n)
         ref = kpsvd.block_egkb(R, Rt, Y, k, p, seed=2, auto_k=True, tau=tau,
                                force_breakdown=set(f.breakdowns))
+        check_replayed_breakdowns(ref, prec)
         assert ref["k"] == k_exp
         assert (f.k, f.diag.kp) == (ref["k"], ref["kp"]), (n, f.k, f.diag.kp, ref["k"], ref["kp"])
         tol = 1e-12 if prec == "f64" else 1e-5

@@ -12,6 +12,7 @@ import numpy as np
 import pytest
 
 import workloads as wl
+from _replay import check_replayed_breakdowns
 from oracle import kpsvd, metrics, operator as op
 
 pytestmark = pytest.mark.gpu
@@ -37,6 +38,28 @@ def _force(f):
     return {(s, j) for s, j in f.breakdowns}
 
 
+def _check_leading_factors(s, U, V, ref, eps=1e-6, min_gap=1e-2):
+    """Element-wise comparison of the singular vectors of the well-separated
+    leading terms (relative gap to both neighbours >= min_gap) with the
+    oracle's, after aligning signs: by the sin-theta theorem a perturbation of
+    relative size eps turns a vector by about eps / gap, so each is allowed
+    10 eps / gap (max-norm of the difference of unit vectors)."""
+    rs = ref["sigma"]
+    s1 = rs[0]
+    checked = 0
+    for i in range(min(len(rs), len(s)) - 1):
+        gap = min(rs[i] - rs[i + 1], rs[i - 1] - rs[i] if i > 0 else np.inf) / s1
+        if gap < min_gap:
+            continue
+        sign = np.sign(np.dot(V[:, i], ref["V"][:, i]))
+        tol = 10.0 * eps / gap
+        dv = np.abs(V[:, i] - sign * ref["V"][:, i]).max()
+        du = np.abs(U[:, i] - sign * ref["U"][:, i]).max()
+        assert dv <= tol and du <= tol, (i, gap, dv, du, tol)
+        checked += 1
+    return checked
+
+
 @pytest.mark.parametrize("reorth", [1, 0])
 def test_egkb_f64_n32_matches_oracle(ctx, reorth):
     from paper_2410_00233_amd import api
@@ -48,6 +71,7 @@ def test_egkb_f64_n32_matches_oracle(ctx, reorth):
     R, Rt = _ops(P, cu, cv, n)
     ref = kpsvd.egkb(R, Rt, y, k, p, reorth="full" if reorth else "one_sided",
                      force_breakdown=_force(f), seed=11)
+    check_replayed_breakdowns(ref, "f64")
     s1 = ref["sigma"][0]
     assert f.k == k
     assert np.abs(f.sigma[:k] - ref["sigma"]).max() <= 1e-12 * s1
@@ -93,6 +117,7 @@ def test_egkb_f32_matches_oracle(ctx, n, psf, k, p):
     f = ctx.kp_svd_gkb(api.Blur(P, cu, cv, n), k, p, prec="f32", y0=y, reorth=1, seed=3)
     R, Rt = _ops(P, cu, cv, n)
     ref = kpsvd.egkb(R, Rt, y, k, p, reorth="full", force_breakdown=_force(f), seed=3)
+    check_replayed_breakdowns(ref, "f32")
     s1 = ref["sigma"][0]
     err = np.abs(f.sigma[:k] - ref["sigma"]).max() / s1
     print(f"EGKB f32 n={n} {psf}: max|dsigma|/sigma1 = {err:.2e}, breakdowns {f.breakdowns}")
@@ -106,6 +131,9 @@ def test_egkb_f32_matches_oracle(ctx, n, psf, k, p):
     # quality against the exact KP-SVD (reported), and the approximation error
     s_ex = op.exact_kpsvd(P, cu, cv, n, k)[0]
     s, U, V, _, _ = _uv_from_factors(f)
+    nchk = _check_leading_factors(s, U, V, ref)
+    print(f"  leading factors checked element-wise: {nchk}")
+    assert nchk >= (2 if psf == "gaussian" else 0)
     e_gpu = metrics.kp_rel_error(P, cu, cv, n, s, U, V)
     e_opt = np.sqrt(max(0.0, 1 - np.sum(s_ex ** 2) / op.rmat_fro_norm2(P, cu, cv, n)))
     print(f"  ||A-A_k||/||A|| gpu {e_gpu:.3e}, optimum {e_opt:.3e}, "
@@ -136,6 +164,10 @@ def test_rsvd_matches_oracle(ctx, n, psf, k, p, q, prec):
         print("  ref sigma/s1", np.array2string(ref["sigma"] / s1, precision=3))
     assert err <= (1e-12 if prec == "f64" else 1e-5)
     s, U, V, _, _ = _uv_from_factors(f)
+    if psf != "disk":   # the disk's Kronecker spectrum has repeated values
+        nchk = _check_leading_factors(s, U, V, ref, eps=1e-14 if prec == "f64" else 1e-6)
+        print(f"  leading factors checked element-wise: {nchk}")
+        assert nchk >= (2 if psf == "gaussian" else 0)
     e_gpu = metrics.kp_rel_error(P, cu, cv, n, s, U, V)
     e_ref = metrics.kp_rel_error(P, cu, cv, n, ref["sigma"], ref["U"], ref["V"])
     print(f"  ||A-A_k||/||A|| gpu {e_gpu:.4e}  oracle {e_ref:.4e}")
@@ -169,6 +201,7 @@ def test_auto_k_matches_oracle_index(ctx):
                        k_cap=20)
     R, Rt = _ops(P, cu, cv, n)
     ref = kpsvd.egkb(R, Rt, y, 20, 4, auto_k=True, k_min=2, force_breakdown=_force(f))
+    check_replayed_breakdowns(ref, "f64")
     assert f.k == ref["k"] and f.diag.kp == ref["kp"]
     assert np.abs(f.sigma[:f.k] - ref["sigma"]).max() <= 1e-12 * ref["sigma"][0]
 
@@ -199,6 +232,12 @@ def test_rsvd_reduced_precision_with_refine(ctx, prec, n, psf):
           f"||A-A_k||/||A|| {e_kp:.3e} vs oracle {e_kp_ref:.3e}")
     assert e_ref <= 1e-4
     assert e_kp <= e_kp_ref + 1e-4
+    # the refined triplets themselves, not only relative to the oracle's:
+    # R V = U Sigma and V^T V = I up to FP32 rounding of the refinement
+    res = np.linalg.norm(R(V) - U * s) / s1
+    orth = np.abs(V.T @ V - np.eye(V.shape[1])).max()
+    print(f"  ||R V - U S||_F / s1 = {res:.2e}, max|V^T V - I| = {orth:.2e}")
+    assert res <= 1e-4 and orth <= 1e-5
 
 
 @pytest.mark.parametrize("prec", ["bf16", "f16"])

@@ -58,7 +58,8 @@ def _oracle(kind, Ax, Ay, b, lam, beta, **kw):
 
 
 @pytest.mark.parametrize("kind", ["aniso", "iso"])
-@pytest.mark.parametrize("n,k,L,I", [(32, 5, 20, 100), (48, 7, 4, 12), (64, 10, 3, 20)])
+@pytest.mark.parametrize("n,k,L,I", [(32, 5, 20, 100), (48, 7, 4, 12), (64, 10, 3, 20),
+                                     (256, 20, 3, 10)])
 def test_sb_fixed_counts_match_oracle(ctx, kind, n, k, L, I):
     from paper_2410_00233_amd import api
     Ax, Ay, b, x_true = _problem(n, k)

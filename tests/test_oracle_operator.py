@@ -300,3 +300,24 @@ def test_periodic_blur_of_constant_image_is_constant():
     P /= P.sum()
     Ap = op.blur_matrix_periodic(P, 7, 3, n)
     assert np.allclose(Ap @ np.ones(n * n), 1.0, atol=1e-13)
+
+
+@pytest.mark.parametrize("n,shape,seed", [(2, (1, 1), 0), (7, (3, 5), 1), (12, (9, 13), 2),
+                                          (16, (31, 31), 3), (10, (4, 25), 4)])
+def test_window_product_equals_explicit_R(n, shape, seed):
+    """The window form of the dense product (blocks of R read as windows of the
+    padded transposed PSF) against the explicit R(A) of the paper's
+    rearrangement, including PSFs smaller and larger than the image and
+    off-centre centres, and a subset of block rows."""
+    P, cu, cv = wl.random_psf(shape[0], shape[1], seed)
+    A = op.blur_matrix(P, cu, cv, n)
+    R = op.rearrange(A, n, n, n, n)
+    X = np.random.default_rng(seed).standard_normal((n * n, 3))
+    Y = op.rmat_window_apply(P, cu, cv, n, X)
+    assert np.abs(Y - R @ X).max() <= 1e-13 * max(1.0, np.abs(R @ X).max())
+    js = range(1, n, 2)
+    Yb = op.rmat_window_apply(P, cu, cv, n, X[:, 0], blocks=js)
+    rows = np.concatenate([np.arange(n * j, n * j + n) for j in js])
+    assert np.allclose(Yb[rows], (R @ X[:, 0])[rows], rtol=0, atol=1e-13)
+    other = np.setdiff1d(np.arange(n * n), rows)
+    assert np.all(Yb[other] == 0.0)
