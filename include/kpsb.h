@@ -46,6 +46,8 @@ typedef enum {
   KP_E_NUMERIC = 4,     /* non-finite value met (e.g. NaN in the PSF)          */
   KP_E_BUSY = 5,        /* server queue full (nothing was queued)              */
   KP_E_TIMEOUT = 6,     /* kp_server_wait timed out; the request still runs     */
+  KP_E_CANCELLED = 7,   /* stopped by kp_cancel / kp_server_cancel; outputs are
+                           undefined (work already queued still completes)    */
   KP_W_BREAKDOWN = 100  /* result valid; a Lanczos breakdown was deflated     */
 } kp_status;
 
@@ -214,6 +216,19 @@ typedef struct {
 kp_status kp_ctx_create(int device, size_t hbm_budget_bytes, kp_ctx** out);
 kp_status kp_ctx_destroy(kp_ctx* ctx);
 const char* kp_last_error(const kp_ctx* ctx);
+/* Cancellation token of a context, callable from any thread: the KP-SVD or
+ * split Bregman call in progress on ctx returns KP_E_CANCELLED at its next
+ * cancellation point (every Lanczos step of Algorithm 1, every block of the
+ * block variant, every pass of Algorithm 2, every outer iteration of
+ * Algorithms 3-4 and every 8 CGLS iterations), leaving its outputs undefined.
+ * The request is consumed by the call it stops; made while no call is in
+ * progress, it stops the next one at its first cancellation point. On the
+ * context of kp_svd_batched it stops the problems in progress and marks those
+ * not started KP_E_CANCELLED. */
+kp_status kp_cancel(kp_ctx* ctx);
+/* Bytes of device workspace the context holds now (HOST out): the buffers its
+ * calls have grown, kept between calls and freed by kp_ctx_destroy. */
+kp_status kp_ctx_workspace(const kp_ctx* ctx, size_t* held);
 kp_status kp_prof_enable(kp_ctx* ctx, int enable);
 /* Reads (and, if reset != 0, clears) the accumulated timings. */
 kp_status kp_prof_read(kp_ctx* ctx, kp_prof* out, int reset);
@@ -383,6 +398,21 @@ kp_status kp_server_wait(kp_server* srv, uint64_t ticket, double timeout_s, kp_r
  * [3] cache misses, [4] evictions, [5] bypasses of a blocked request,
  * [6] peak concurrently running requests, [7] resident factor sets. */
 kp_status kp_server_stats(kp_server* srv, int64_t out[8]);
+/* Cancels a request: a queued one is removed and completes at once with status
+ * KP_E_CANCELLED; a running one stops at its next cancellation point (see
+ * kp_cancel) with that status, its factors, if it was computing them, not
+ * cached. A request that has finished keeps its result. The ticket must still
+ * be collected with kp_server_wait. KP_E_INVAL for an unknown ticket. */
+kp_status kp_server_cancel(kp_server* srv, uint64_t ticket);
+/* Admission footprint of a request (HOST out, bytes): out[0] bounds the split
+ * Bregman workspace (sb_solve_iso / sb_solve_aniso with k_cap terms), out[1]
+ * the KP-SVD workspace of a factor-cache miss (kp_svd_gkb / kp_svd_rsvd with the
+ * request's options), out[2] is the factor set (2 k_cap n^2 doubles). A request
+ * is admitted when out[0] (a cache hit) or out[0] + out[1] + out[2] (a miss)
+ * fits beside what is committed. Needs only the request's sizes and options;
+ * KP_E_INVAL for a NULL argument, n outside [2, 2048], k_cap outside [1, 64] or
+ * an unknown method. */
+kp_status kp_request_footprint(const kp_request* req, size_t out[3]);
 /* Finishes every submitted request, then frees the server's memory. */
 kp_status kp_server_destroy(kp_server* srv);
 

@@ -13,14 +13,15 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libkpsb.so")
 
 KP_OK, KP_E_INVAL, KP_E_NOMEM, KP_E_DEVICE, KP_E_NUMERIC = 0, 1, 2, 3, 4
-KP_E_BUSY, KP_E_TIMEOUT = 5, 6
+KP_E_BUSY, KP_E_TIMEOUT, KP_E_CANCELLED = 5, 6, 7
 KP_W_BREAKDOWN = 100
 KP_F64, KP_F32, KP_BF16, KP_F16 = 0, 1, 2, 3
 KP_METHOD_GKB, KP_METHOD_RSVD = 0, 1
 KP_BC_ZERO, KP_BC_REFLEXIVE, KP_BC_PERIODIC = 0, 1, 2
 
 STATUS_NAMES = {0: "KP_OK", 1: "KP_E_INVAL", 2: "KP_E_NOMEM", 3: "KP_E_DEVICE",
-                4: "KP_E_NUMERIC", 5: "KP_E_BUSY", 6: "KP_E_TIMEOUT", 100: "KP_W_BREAKDOWN"}
+                4: "KP_E_NUMERIC", 5: "KP_E_BUSY", 6: "KP_E_TIMEOUT", 7: "KP_E_CANCELLED",
+                100: "KP_W_BREAKDOWN"}
 
 # Every symbol the header declares (checked by the CPU test-suite).
 EXPORTED = ["kp_ctx_create", "kp_ctx_destroy", "kp_last_error", "kp_version",
@@ -30,7 +31,8 @@ EXPORTED = ["kp_ctx_create", "kp_ctx_destroy", "kp_last_error", "kp_version",
             "kp_server_create", "kp_server_submit", "kp_server_wait", "kp_server_stats",
             "kp_server_destroy", "kp_tune_report", "kp_rmat_reorder", "kp_rmat_apply_stored",
             "kp_svd_gkb_stored", "kp_svd_rsvd_stored", "sb_solve_aniso_direct",
-            "sb_solve_iso_direct", "kp_blur_matrix", "kp_rmat_apply_noalloc"]
+            "sb_solve_iso_direct", "kp_blur_matrix", "kp_rmat_apply_noalloc",
+            "kp_ctx_workspace", "kp_request_footprint", "kp_cancel", "kp_server_cancel"]
 
 
 class kp_blur(C.Structure):
@@ -125,6 +127,10 @@ def load(path: str = LIB_PATH):
     lib.kp_prof_read.argtypes = [vp, C.POINTER(kp_prof), C.c_int]
     lib.kp_rmat_apply.argtypes = [vp, C.POINTER(kp_blur), C.c_int, C.c_int, C.c_int32, vp, vp, vp]
     lib.kp_rmat_apply_noalloc.argtypes = lib.kp_rmat_apply.argtypes
+    lib.kp_ctx_workspace.argtypes = [vp, C.POINTER(C.c_size_t)]
+    lib.kp_cancel.argtypes = [vp]
+    lib.kp_server_cancel.argtypes = [vp, C.c_uint64]
+    lib.kp_request_footprint.argtypes = [C.POINTER(kp_request), C.POINTER(C.c_size_t)]
     lib.kp_svd_gkb.argtypes = [vp, C.POINTER(kp_blur), C.POINTER(kp_gkb_opts),
                                C.POINTER(kp_factors), vp]
     lib.kp_svd_rsvd.argtypes = [vp, C.POINTER(kp_blur), C.POINTER(kp_rsvd_opts),

@@ -133,6 +133,16 @@ class Context:
             raise KPError(st, self.lib.kp_last_error(self.h).decode())
         return st
 
+    def kp_cancel(self):
+        """Stops the call in progress on this context (callable from any thread)."""
+        self._check(self.lib.kp_cancel(self.h))
+
+    def kp_ctx_workspace(self):
+        """Bytes of device workspace the context holds."""
+        held = C.c_size_t()
+        self._check(self.lib.kp_ctx_workspace(self.h, C.byref(held)))
+        return int(held.value)
+
     # ---- autotuner ------------------------------------------------------------
     def kp_tune_report(self):
         """Chosen launch variants and measured candidate costs (list of dicts)."""
@@ -389,10 +399,12 @@ class Server:
         self.h = h
         self._keep = {}
 
-    def submit(self, blur: Blur, b, x, *, psf_key=0, method="rsvd", k=20, p=10, q=2,
-               prec="f32", refine=False, seed=0, k_cap=None, iso=True, lam=0.115,
-               beta=0.0066, L_max=50, I_max=100, tau_sb=0.0, tau_cgls=1e-4, gkb=None,
-               rsvd=None):
+    @staticmethod
+    def request(blur: Blur, b=None, x=None, *, psf_key=0, method="rsvd", k=20, p=10, q=2,
+                prec="f32", refine=False, seed=0, k_cap=None, iso=True, lam=0.115,
+                beta=0.0066, L_max=50, I_max=100, tau_sb=0.0, tau_cgls=1e-4, gkb=None,
+                rsvd=None):
+        """The kp_request of a solve (b, x: device images, or None for a size query)."""
         req = L.kp_request()
         req.psf_key = psf_key
         req.blur = blur.s
@@ -403,8 +415,21 @@ class Server:
         req.k_cap = k_cap or k
         req.iso = int(iso)
         req.sb = L.sb_opts(lam, beta, L_max, I_max, tau_sb, tau_cgls)
-        req.b = b.data_ptr()
-        req.x = x.data_ptr()
+        req.b = b.data_ptr() if b is not None else None
+        req.x = x.data_ptr() if x is not None else None
+        return req
+
+    @staticmethod
+    def footprint(blur: Blur, **kw):
+        """kp_request_footprint: (solve workspace, KP-SVD workspace, factor set) bytes."""
+        out = (C.c_size_t * 3)()
+        st = L.load().kp_request_footprint(C.byref(Server.request(blur, **kw)), out)
+        if st != L.KP_OK:
+            raise KPError(st, "kp_request_footprint failed")
+        return tuple(int(v) for v in out)
+
+    def submit(self, blur: Blur, b, x, **kw):
+        req = Server.request(blur, b, x, **kw)
         # the server's streams read b: it must be complete before submit
         _torch().cuda.current_stream().synchronize()
         t = C.c_uint64()
@@ -413,6 +438,13 @@ class Server:
             raise KPError(st, self.lib.kp_last_error(self.ctx.h).decode())
         self._keep[t.value] = (blur, b, x)
         return t.value
+
+    def cancel(self, ticket):
+        """kp_server_cancel: the request completes with KP_E_CANCELLED unless it
+        has finished already; collect it with wait() as usual."""
+        st = self.lib.kp_server_cancel(self.h, C.c_uint64(ticket))
+        if st != L.KP_OK:
+            raise KPError(st, self.lib.kp_last_error(self.ctx.h).decode())
 
     def wait(self, ticket, timeout=-1.0):
         r = L.kp_result()

@@ -11,6 +11,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <type_traits>
 #include <string>
 #include <vector>
@@ -49,7 +50,39 @@ kp_status check_launch(kp_ctx* c, const char* where) {
   return KP_OK;
 }
 
+// Cancellation point (host side, between launches): a pending kp_cancel ends
+// the call with KP_E_CANCELLED; work already queued still runs to completion on
+// the stream, and the call's outputs are undefined.
+kp_status check_cancel(kp_ctx* c) {
+  if (c->parent) {
+    if (c->parent->cancel.load(std::memory_order_acquire) == 0) return KP_OK;
+  } else if (c->cancel.exchange(0, std::memory_order_acq_rel) == 0) {
+    return KP_OK;
+  }
+  return set_err(c, KP_E_CANCELLED, "cancelled by kp_cancel");
+}
+
 // Workspace buffer `name` of at least `bytes` (contents undefined).
+// Host-side fault injection for tests of the error paths: with
+// KPSB_FAULT_INJECT=alloc:N in the environment, the N-th workspace allocation
+// counted from when the variable took its current value fails as if hipMalloc
+// had failed (KP_E_NOMEM; nothing is allocated).
+bool inject_alloc_fault() {
+  static std::mutex mu;
+  static std::string spec;
+  static long count = 0;
+  const char* e = getenv("KPSB_FAULT_INJECT");
+  const std::string now = e ? e : "";
+  std::lock_guard<std::mutex> lk(mu);
+  if (now != spec) {
+    spec = now;
+    count = 0;
+  }
+  if (spec.compare(0, 6, "alloc:") != 0) return false;
+  const long target = atol(spec.c_str() + 6);
+  return ++count == target;
+}
+
 kp_status ws(kp_ctx* c, const std::string& name, size_t bytes, void** out) {
   if (c->arena_base) {   // allocation-free mode: carve from the caller's scratch
     const size_t need = (bytes + 255) & ~(size_t)255;
@@ -92,7 +125,7 @@ kp_status ws(kp_ctx* c, const std::string& name, size_t bytes, void** out) {
     b.bytes = 0;
   }
   void* p = nullptr;
-  hipError_t e = hipMalloc(&p, bytes);
+  hipError_t e = inject_alloc_fault() ? hipErrorOutOfMemory : hipMalloc(&p, bytes);
   if (e != hipSuccess) {
     (void)hipGetLastError();
     unreserve(bytes);
@@ -391,7 +424,8 @@ template <typename H>
 kp_status choose_block16_plan(kp_ctx* c, const Grids<H>& g, int n, const H* X16, long ld16,
                               float* Y, int nc, hipStream_t s, BlockPlan* bp) {
   const long N = (long)n * n;
-  const int v = tune_pick(kTuneBlock16, n, (int)sizeof(H), 0, kNumBlock16Variants,
+  const int v = tune_pick(kTuneBlock16, n, std::is_same<H, __half>::value ? KP_F16 : KP_BF16, 0,
+                          kNumBlock16Variants,
                           [&](int k) -> double {
     BlockPlan p;
     if (!plan_block16_tj(n, c->lds_limit, kBlock16Variants[k].TJ, &p)) return -1.0;
@@ -873,6 +907,7 @@ kp_status egkb_impl(kp_ctx* c, const RmatOp<T>& op, const kp_gkb_opts* o, kp_fac
   bool fired = false;
 
   for (int j = 2; j <= kp + 1; ++j) {
+    KP_TRY(check_cancel(c));
     T* sj = S + N * (j - 1);
     const T* sprev = S + N * (j - 2);
     const T* qprev = Q + N * (j - 2);
@@ -1081,6 +1116,7 @@ kp_status egkb_block_impl(kp_ctx* c, const RmatOp<T>& op, const kp_gkb_opts* o, 
   }
 
   for (int j = 0; j < nb; ++j) {
+    KP_TRY(check_cancel(c));
     const long jb = (long)j * b;
     // V_{j+1} L^T = B^T U_{j+1} (minus the earlier V, through the Gram-Schmidt)
     KP_TRY(product(1, U + N * jb, V + N * jb));
@@ -1217,6 +1253,7 @@ kp_status rsvd_impl(kp_ctx* c, const RmatOp<T>& op, const kp_rsvd_opts* o, kp_fa
   KP_TRY(prod(0, Z, Y, kp));
   KP_TRY(cgs_qr<T>(c, sc, Y, N, kp, nullptr, o->seed, sb, s));
   for (int it = 0; it < o->q; ++it) {
+    KP_TRY(check_cancel(c));
     KP_TRY(prod(1, Y, Z, kp));
     KP_TRY(cgs_qr<T>(c, sc, Z, N, kp, nullptr, o->seed, sb += 64, s));
     KP_TRY(prod(0, Z, Y, kp));
@@ -1224,6 +1261,7 @@ kp_status rsvd_impl(kp_ctx* c, const RmatOp<T>& op, const kp_rsvd_opts* o, kp_fa
   }
   if (f->diag && f->diag->basis_u)
     KP_HIP(c, hipMemcpyAsync(f->diag->basis_u, Y, sizeof(T) * N * kp, hipMemcpyDeviceToDevice, s));
+  KP_TRY(check_cancel(c));
   KP_TRY(prod(1, Y, Z, kp));   // H^T
   double *Rh, *RhT, *Ur, *sig, *Vr;
   int* sweeps;
@@ -1430,6 +1468,7 @@ kp_status sb_solve_impl(kp_ctx* c, SbOp& op, const double* b, const sb_opts* o, 
     }
   } guard{chunk};
   for (int ell = 0; ell < o->L_max; ++ell) {
+    KP_TRY(check_cancel(c));
     sb_launch_rhs(d, s);
     sb_launch_f(d, AtB, 1, 1, s);
     sb_launch_w_init(d, s);
@@ -1441,6 +1480,7 @@ kp_status sb_solve_impl(kp_ctx* c, SbOp& op, const double* b, const sb_opts* o, 
         cgls_iteration(s);
         it += 1;
       }
+      if (it % poll == 0 && it < o->I_max) KP_TRY(check_cancel(c));
       if (o->tau_cgls > 0 && it % poll == 0 && it < o->I_max) {
         KP_TRY(check_launch(c, "cgls"));
         KP_TRY(read_flags());
@@ -1595,6 +1635,18 @@ kp_status kp_ctx_destroy(kp_ctx* c) {
 }
 
 const char* kp_last_error(const kp_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+kp_status kp_cancel(kp_ctx* c) {
+  if (!c) return KP_E_INVAL;
+  c->cancel.store(1, std::memory_order_release);
+  return KP_OK;
+}
+
+kp_status kp_ctx_workspace(const kp_ctx* c, size_t* held) {
+  if (!c || !held) return KP_E_INVAL;
+  *held = ctx_held(c);
+  return KP_OK;
+}
 
 kp_status kp_prof_enable(kp_ctx* c, int enable) {
   if (!c) return KP_E_INVAL;

@@ -3,6 +3,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -51,6 +52,11 @@ struct kp_ctx {
   char* arena_base = nullptr;
   size_t arena_cap = 0, arena_used = 0;
   void* scratch = nullptr;   // this device's static scratch array (device address)
+  // Cancellation (kp_cancel): set from any thread, consumed by the call it
+  // stops. A worker of a batched call watches its parent's flag instead (the
+  // batched call consumes it).
+  std::atomic<int> cancel{0};
+  kp_ctx* parent = nullptr;
 };
 
 namespace kpsb {

@@ -43,6 +43,7 @@ kp_status ensure_workers(kp_ctx* c, int nw) {
       return fail(c, KP_E_DEVICE, "creating a worker stream failed");
     }
     w->prof = c->prof;
+    w->parent = c;   // a kp_cancel of c reaches the problems in progress
     c->workers.push_back(w);
   }
   return KP_OK;
@@ -94,8 +95,13 @@ bool needs_tuning(const kp_blur& b, int32_t method, const void* opts) {
     return !tune_known(kTuneBlock, b.n, o->prec == KP_F64 ? 8 : 4, 0);
   }
   const kp_rsvd_opts* o = static_cast<const kp_rsvd_opts*>(opts);
+  // the 16-bit tuner is keyed on the element type (KP_BF16 / KP_F16); the
+  // split-FP16 refinement product (refine = 2, FP32-vector modes) tunes the
+  // FP16 kernel whatever the sketch precision
+  const bool split16 = o->refine == 2 && o->prec != KP_F64;
+  if (split16 && !tune_known(kTuneBlock16, b.n, KP_F16, 0)) return true;
   if (o->prec == KP_BF16 || o->prec == KP_F16)
-    return !tune_known(kTuneBlock16, b.n, 2, 0) ||
+    return !tune_known(kTuneBlock16, b.n, o->prec, 0) ||
            (o->refine == 1 && !tune_known(kTuneBlock, b.n, 4, 0));
   return !tune_known(kTuneBlock, b.n, o->prec == KP_F64 ? 8 : 4, 0);
 }
@@ -115,7 +121,9 @@ double ms_since(std::chrono::steady_clock::time_point t0) {
 // ===========================================================================
 namespace {
 
-constexpr size_t kSlack = 16u << 20;   // small buffers of a solve or KP-SVD
+// Allowance for the small buffers of a solve or a KP-SVD (reduction partials,
+// flags and scalars, the small SVD's matrices, support boxes): well under it.
+constexpr size_t kSlack = 1u << 20;
 
 size_t round256(size_t b) { return (b + 255) & ~(size_t)255; }
 
@@ -151,18 +159,27 @@ size_t svd_bytes(const kp_request& r) {
     b += 2 * round256(N * (size_t)r.k_cap * 8);
     if (terms > 1) b += 4 * round256(N * wide * es);
     if (r.gkb.y0) b += round256(N * (r.gkb.block >= 1 ? r.gkb.block : 1) * 8);
+    // staging vector of the FP32 matrix-vector kernel (Algorithm 1, b = 1)
+    if (r.gkb.block < 1 && es == 4) b += round256((size_t)gemv_sx_xt_len(n) * 4);
   } else {
     const size_t es = r.rsvd.prec == KP_F64 ? 8 : 4;
     const int kp = r.rsvd.k + r.rsvd.p;
+    const size_t x16 = (size_t)x16_column_len(n);
     b += 2 * terms * round256(grid * es);
     if (r.rsvd.prec == KP_BF16 || r.rsvd.prec == KP_F16) {
       b += 2 * terms * round256(grid * 2);
-      b += round256((N + 8 * (size_t)n) * kp * 2);
+      b += round256(x16 * kp * 2);            // 16-bit copy of the product's input
     }
-    b += 2 * round256(N * kp * es);
+    b += 2 * round256(N * kp * es);           // sketch / range bases Y, Z
+    b += round256(N * kp * es);               // CGS2 QR's copy of the columns
     b += 2 * round256(N * (size_t)r.k_cap * 8);
     if (terms > 1) b += 4 * round256(N * kp * es);
     if (r.rsvd.F) b += round256(N * kp * 8);
+    if (r.rsvd.refine == 2 && r.rsvd.prec != KP_F64) {
+      // split-FP16 refinement: hi / lo FP16 grids and hi / lo FP16 inputs
+      b += 2 * round256((size_t)(2 * n - 1) * grid_ld(n) * 2);
+      b += 2 * round256(x16 * (size_t)r.rsvd.k * 2);
+    }
   }
   return b + kSlack;
 }
@@ -239,6 +256,7 @@ struct kp_server {
   int cache_cap = 64;
   std::vector<kp_ctx*> workers;
   std::vector<size_t> running_ws;    // footprint of the request a worker runs (0 idle)
+  std::vector<uint64_t> running_ticket;   // ticket a worker runs (0 idle)
   std::vector<std::thread> threads;
 
   std::mutex m;
@@ -439,6 +457,7 @@ void worker_loop(kp_server* s, int w) {
         s->cv_work.wait(lk);
       }
       s->running += 1;
+      s->running_ticket[w] = job.ticket;
       s->counters[6] = std::max<int64_t>(s->counters[6], s->running);
       s->counters[hit ? 2 : 3] += 1;
     }
@@ -566,6 +585,8 @@ void worker_loop(kp_server* s, int w) {
     {
       std::lock_guard<std::mutex> lk(s->m);
       s->running_ws[w] = 0;
+      s->running_ticket[w] = 0;
+      wc->cancel.store(0);   // a cancel that came after the job's last check
       s->running -= 1;
       finish_locked(s, job.ticket, res);
     }
@@ -599,6 +620,16 @@ kp_status check_request(kp_server* s, const kp_request* r, std::string* why) {
 
 // ===========================================================================
 extern "C" {
+
+kp_status kp_request_footprint(const kp_request* r, size_t out[3]) {
+  if (!r || !out) return KP_E_INVAL;
+  if (r->blur.n < 2 || r->blur.n > 2048 || r->k_cap < 1 || r->k_cap > 64) return KP_E_INVAL;
+  if (r->method != KP_METHOD_GKB && r->method != KP_METHOD_RSVD) return KP_E_INVAL;
+  out[0] = sb_bytes(r->blur.n, r->k_cap);
+  out[1] = svd_bytes(*r);
+  out[2] = factor_bytes(r->blur.n, r->k_cap);
+  return KP_OK;
+}
 
 kp_status kp_svd_batched(kp_ctx* c, int32_t nprob, const kp_blur* blurs, const int32_t* method,
                          const void* const* opts, kp_factors* out, kp_status* status,
@@ -641,8 +672,13 @@ kp_status kp_svd_batched(kp_ctx* c, int32_t nprob, const kp_blur* blurs, const i
     if (!needs_tuning(blurs[i], method[i], opts[i])) continue;
     kp_ctx* w = c->workers[0];
     (void)hipSetDevice(w->device);
-    res[i] = run_one(w, &blurs[i], method[i], opts[i], &out[i]);
-    if (is_error(res[i])) msg[i] = w->err;
+    if (c->cancel.load(std::memory_order_acquire)) {
+      res[i] = KP_E_CANCELLED;
+      msg[i] = "cancelled before it started";
+    } else {
+      res[i] = run_one(w, &blurs[i], method[i], opts[i], &out[i]);
+      if (is_error(res[i])) msg[i] = w->err;
+    }
     done[i] = 1;
   }
   std::atomic<int> next{0};
@@ -655,6 +691,11 @@ kp_status kp_svd_batched(kp_ctx* c, int32_t nprob, const kp_blur* blurs, const i
       if (t >= nprob) break;
       const int i = order[t];
       if (done[i]) continue;
+      if (c->cancel.load(std::memory_order_acquire)) {
+        res[i] = KP_E_CANCELLED;
+        msg[i] = "cancelled before it started";
+        continue;
+      }
       res[i] = run_one(w, &blurs[i], method[i], opts[i], &out[i]);
       if (is_error(res[i])) msg[i] = w->err;
     }
@@ -671,6 +712,8 @@ kp_status kp_svd_batched(kp_ctx* c, int32_t nprob, const kp_blur* blurs, const i
       (void)hipEventDestroy(fin[wi]);
     }
   (void)hipEventDestroy(start);
+  // a cancel request that stopped problems is consumed by this call
+  if (std::find(res.begin(), res.end(), KP_E_CANCELLED) != res.end()) c->cancel.store(0);
   kp_status worst = KP_OK;
   for (int i = 0; i < nprob; ++i) {
     if (status) status[i] = res[i];
@@ -716,6 +759,7 @@ kp_status kp_server_create(kp_ctx* c, const kp_server_cfg* cfg, kp_server** out)
     s->workers.push_back(wc);
   }
   s->running_ws.assign(s->slots, 0);
+  s->running_ticket.assign(s->slots, 0);
   for (int w = 0; w < s->slots; ++w) s->threads.emplace_back(worker_loop, s, w);
   *out = s;
   return KP_OK;
@@ -756,6 +800,28 @@ kp_status kp_server_wait(kp_server* s, uint64_t ticket, double timeout_s, kp_res
   *res = s->done[ticket];
   s->done.erase(ticket);
   s->live.erase(ticket);
+  return KP_OK;
+}
+
+kp_status kp_server_cancel(kp_server* s, uint64_t ticket) {
+  if (!s) return KP_E_INVAL;
+  std::lock_guard<std::mutex> lk(s->m);
+  if (!s->live.count(ticket)) return fail(s->ctx, KP_E_INVAL, "unknown ticket");
+  if (s->done.count(ticket)) return KP_OK;   // finished already
+  for (auto it = s->queue.begin(); it != s->queue.end(); ++it) {
+    if (it->ticket != ticket) continue;
+    kp_result r;
+    std::memset(&r, 0, sizeof(r));
+    r.status = KP_E_CANCELLED;
+    set_msg(&r, "cancelled before it started");
+    r.queue_ms = r.total_ms = ms_since(it->t_submit);
+    s->queue.erase(it);
+    finish_locked(s, ticket, r);
+    s->cv_work.notify_all();   // the jobs it held back
+    return KP_OK;
+  }
+  for (size_t w = 0; w < s->workers.size(); ++w)
+    if (s->running_ticket[w] == ticket) s->workers[w]->cancel.store(1, std::memory_order_release);
   return KP_OK;
 }
 
