@@ -408,6 +408,10 @@ kp_status choose_block_plan(kp_ctx* c, const Grids<T>& g, int n, const T* X, T* 
 template <typename T>
 kp_status block_product1(kp_ctx* c, const Grids<T>& g, int n, int transpose, const T* X,
                          T* Y, int ncols, hipStream_t s) {
+  if constexpr (std::is_same<T, float>::value) {
+    if (c->batch && !(transpose ? g.boxt[0] : g.box[0]))   // lockstep batch: one launch for all
+      return batch_block_product(c, transpose ? g.Gt : g.G, g.ldg, n, X, Y, ncols, s);
+  }
   BlockPlan bp;
   KP_TRY(choose_block_plan<T>(c, g, n, X, Y, std::min(ncols, 32), s, &bp));
   const long N = (long)n * n;
@@ -1561,6 +1565,17 @@ kp_ctx* ctx_new(int device, std::shared_ptr<kp_pool> pool, size_t budget) {
     return nullptr;
   }
   return c;
+}
+
+bool tuned_block_shape(kp_ctx* c, int n, BlockPlan* shape) {
+  tune_set_no_timing(true);
+  const int v = tune_pick(kTuneBlock, n, (int)sizeof(float), 0, kNumBlockVariants,
+                          [](int) { return -1.0; });
+  tune_set_no_timing(false);
+  if (!plan_block_tj<float>(n, c->lds_limit, kBlockVariants[v].TJ, shape, kBlockVariants[v].TK))
+    return false;
+  shape->waves = kBlockVariants[v].waves;
+  return true;
 }
 
 size_t ctx_held(const kp_ctx* c) {

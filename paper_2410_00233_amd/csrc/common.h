@@ -58,6 +58,17 @@ struct BlockPlan {
   int TK = 64;         // K-tile entries (FP32/FP64 block product: 64, 128, 176 or 192)
   int grid_limit = 0;  // > 0: launch only the first grid_limit workgroups (tuning samples)
 };
+// One product of a persistent block launch (launch_rmat_block_persistent): the
+// arguments of launch_rmat_block for op(R) X of one problem (up to 32 columns),
+// its tile count (grid of its own plan) and the index of its first tile in the
+// launch's list.
+struct BlockJob {
+  const void* G;
+  const void* X;
+  void* Y;
+  long ldx, ldy;
+  int ldg, n, ncols, SW, CP, tiles, first, pad;
+};
 template <typename T>
 bool plan_block(int n, size_t lds_limit, BlockPlan* plan);
 // The plan with exactly TJ row blocks per workgroup (false if it cannot fit).
@@ -151,6 +162,14 @@ void launch_transpose_image(const double* in, double* out, int n, const int* fla
 template <typename T>
 void launch_stored_block(const T* R, long N, int transpose, const T* X, T* Y, int ncols,
                          hipStream_t s);
+
+// All jobs' tiles in one launch of `grid` workgroups, each taking tiles from
+// *counter (reset to 0 here, on the stream) until none is left. The launch shape
+// (TJ, waves, TK of `shape`) is shared by the jobs; each job's SW / CP come from
+// its own plan with that shape; lds: the largest job's dynamic LDS. jobs and
+// counter: device memory.
+void launch_rmat_block_persistent(const BlockPlan& shape, const BlockJob* jobs, int njobs,
+                                  int total, int* counter, size_t lds, int grid, hipStream_t s);
 
 // ---- autotuner (tune.cpp) ---------------------------------------------------
 constexpr int kTuneBlock = 1;     // FP32 / FP64 block product: (TJ, waves)

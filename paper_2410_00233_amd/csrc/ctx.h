@@ -10,7 +10,10 @@
 #include <string>
 #include <vector>
 
+#include "common.h"
 #include "kpsb.h"
+
+struct kp_batch;   // lockstep product batch of kp_svd_batched (runtime.cpp)
 
 // HBM budget shared by a context and the worker contexts it spawns: every
 // workspace allocation of any of them is charged here.
@@ -57,6 +60,12 @@ struct kp_ctx {
   // batched call consumes it).
   std::atomic<int> cancel{0};
   kp_ctx* parent = nullptr;
+  // Set on a worker that runs a problem of a lockstep batch: its generated-tile
+  // FP32 block products are handed to the batch, which runs the products of all
+  // problems in flight as one persistent launch.
+  kp_batch* batch = nullptr;
+  // persistent launches and products of the last kp_svd_batched call
+  int64_t batch_launches = 0, batch_products = 0;
 };
 
 namespace kpsb {
@@ -70,5 +79,14 @@ void ctx_free(kp_ctx* c);
 void ctx_trim(kp_ctx* c);
 // Bytes of workspace currently held by `c` itself.
 size_t ctx_held(const kp_ctx* c);
+// Y = op(R) X (FP32, ncols columns) through the lockstep batch of c (c->batch
+// set): queued with the products of the other problems in flight, which run as
+// one persistent launch; on return `s` waits for that launch. G: the grid of
+// op(R) (ldg x ldg).
+kp_status batch_block_product(kp_ctx* c, const float* G, int ldg, int n, const float* X,
+                              float* Y, int ncols, hipStream_t s);
+// The FP32 block-product launch shape the autotuner chose for n (its first
+// variant if it has not chosen one), without timing anything.
+bool tuned_block_shape(kp_ctx* c, int n, BlockPlan* shape);
 
 }  // namespace kpsb

@@ -11,7 +11,9 @@
 // GEMM kernel: a TM x TN output tile per 256-thread workgroup, each of the 4
 // waves owning a (TM/2) x (TN/2) quadrant of 16 x 16 MFMA blocks; K tiles of KT
 // staged through two LDS buffers, the next tile's global loads in flight in
-// registers while the current one is multiplied (one barrier per K tile).
+// registers while the current one is multiplied (one barrier per K tile). Each
+// operand is read from HBM / L2 along its contiguous direction in whole cache
+// lines, whichever of m, n or k that is.
 #include "common.h"
 #include "sb.h"
 
@@ -35,24 +37,38 @@ struct GemmArgs {
 
 template <int TM, int TN, int KT>
 struct GemmCfg {
-  static constexpr int SA = TM + 16;   // LDS row strides (doubles): consecutive
-  static constexpr int SB = TN + 16;   // rows 32 banks apart
+  // LDS layout of a staged tile (doubles). An operand contiguous along k in
+  // global memory is loaded along k (16 lanes cover a 128-byte line) and staged
+  // [m][k] with row stride KT + 1: the 16 rows of a fragment read then sit 2
+  // banks apart. An operand contiguous along m (or n) is loaded along m and
+  // staged [k][m] with row stride TM + 16.
+  static constexpr int SKA = KT + 1, SMA = TM + 16;
+  static constexpr int SKB = KT + 1, SNB = TN + 16;
+  static constexpr int TILE_A = TM * SKA > KT * SMA ? TM * SKA : KT * SMA;
+  static constexpr int TILE_B = TN * SKB > KT * SNB ? TN * SKB : KT * SNB;
   static constexpr int LA = TM * KT / 256;               // A elements per thread
   static constexpr int LB = TN * KT / 256;
   static constexpr int BI = TM / 32;                     // MFMA blocks per wave (rows)
   static constexpr int BJ = TN / 32;                     //                      (cols)
-  static constexpr int LDS = 2 * KT * (SA + SB);         // doubles
+  static constexpr int LDS = 2 * (TILE_A + TILE_B);      // doubles
 };
 
-template <int TM, int TN, int KT>
+// AKC / BKC: A (B) contiguous along k in global memory (see GemmCfg).
+// FULL: M, N, K are multiples of TM, TN, KT (no bounds checks; the general form
+// zero-fills outside the operands). The term and K offset of the next tile to
+// load advance incrementally, as do the per-thread load pointers, so a K step
+// issues little besides its loads, LDS traffic and MFMAs. D: K tiles whose
+// loads are in flight (a ring of D register slots, the K loop unrolled by D;
+// past the last tile the last one is loaded again and never used).
+template <int TM, int TN, int KT, bool AKC, bool BKC, bool FULL, int D>
 __global__ void __launch_bounds__(256) gemm_f64_kernel(GemmArgs g) {
   using Cfg = GemmCfg<TM, TN, KT>;
   if (g.flags)
     for (int i = 0; i < g.nflags; ++i)
       if (g.flags[i]) return;
   __shared__ double lds[Cfg::LDS];
-  double* As = lds;                         // [2][KT][SA]
-  double* Bs = lds + 2 * KT * Cfg::SA;      // [2][KT][SB]
+  double* As = lds;                         // [2][TILE_A]
+  double* Bs = lds + 2 * Cfg::TILE_A;       // [2][TILE_B]
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
@@ -72,55 +88,77 @@ __global__ void __launch_bounds__(256) gemm_f64_kernel(GemmArgs g) {
   const int nK = (g.K + KT - 1) / KT;
   const int total = (t_end - t_begin) * nK;
 
-  // Element e of a tile: along the contiguous global direction in runs of 4
-  // (32-byte segments) when that direction is k, else along m (or n); the LDS
-  // stores then hit at most two rows at once per bank.
+  // element e = tid + 256 q of a tile -> (row along m or n, kk), following the
+  // contiguous direction; offsets in the tile (global) and in LDS
   auto mapA = [&](int e, int& mm, int& kk) {
-    if (g.transA) { mm = e % TM; kk = e / TM; }
-    else { kk = (e & 3) + 4 * (e / (4 * TM)); mm = (e >> 2) % TM; }
+    if (AKC) { mm = e / KT; kk = e % KT; }
+    else { mm = e % TM; kk = e / TM; }
   };
   auto mapB = [&](int e, int& nn, int& kk) {
-    if (g.transB) { kk = (e & 3) + 4 * (e / (4 * TN)); nn = (e >> 2) % TN; }
+    if (BKC) { nn = e / KT; kk = e % KT; }
     else { nn = e % TN; kk = e / TN; }
   };
-  double ra[Cfg::LA], rb[Cfg::LB];
-  auto load = [&](int it) {
-    const int t = t_begin + it / nK;
-    const int k0 = (it % nK) * KT;
-    const double* A = g.A + (long)t * g.sAz;
-    const double* B = g.B + (long)t * g.sBz;
+  auto offA = [](int mm, int kk) { return AKC ? mm * Cfg::SKA + kk : kk * Cfg::SMA + mm; };
+  auto offB = [](int nn, int kk) { return BKC ? nn * Cfg::SKB + kk : kk * Cfg::SNB + nn; };
+  const long lda = g.lda, ldb = g.ldb;
+  long ga[Cfg::LA], gb[Cfg::LB];       // element offsets from the tile origin
+  int la[Cfg::LA], lb[Cfg::LB];        // LDS offsets
+  int ma[Cfg::LA], ka[Cfg::LA], nb_[Cfg::LB], kb_[Cfg::LB];
+#pragma unroll
+  for (int q = 0; q < Cfg::LA; ++q) {
+    mapA(tid + 256 * q, ma[q], ka[q]);
+    ga[q] = AKC ? (long)ma[q] * lda + ka[q] : (long)ka[q] * lda + ma[q];
+    la[q] = offA(ma[q], ka[q]);
+  }
+#pragma unroll
+  for (int q = 0; q < Cfg::LB; ++q) {
+    mapB(tid + 256 * q, nb_[q], kb_[q]);
+    gb[q] = BKC ? (long)nb_[q] * ldb + kb_[q] : (long)kb_[q] * ldb + nb_[q];
+    lb[q] = offB(nb_[q], kb_[q]);
+  }
+  // tile origin of term t, K offset k0: A + t sAz + (AKC ? m0 lda + k0 : k0 lda + m0)
+  const long a_step = AKC ? KT : (long)KT * lda;    // per K tile
+  const long b_step = BKC ? KT : (long)KT * ldb;
+  const double* a_org = g.A + (AKC ? (long)m0 * lda : m0);
+  const double* b_org = g.B + (BKC ? (long)n0 * ldb : n0);
+  int lt = t_begin, lk0 = 0;                        // the next tile to load
+  int left = total;                                 // tiles not loaded yet
+  const double* pa = a_org + (long)lt * g.sAz;
+  const double* pb = b_org + (long)lt * g.sBz;
+  double ra[D][Cfg::LA], rb[D][Cfg::LB];
+  // loads the next tile into slot u (again the last one once all are loaded)
+  auto load = [&](int u) {
 #pragma unroll
     for (int q = 0; q < Cfg::LA; ++q) {
-      int mm, kk;
-      mapA(tid + 256 * q, mm, kk);
-      const int m = m0 + mm, kg = k0 + kk;
-      ra[q] = (m < g.M && kg < g.K) ? (g.transA ? A[(long)kg * g.lda + m] : A[(long)m * g.lda + kg])
-                                    : 0.0;
+      if (FULL) ra[u][q] = pa[ga[q]];
+      else ra[u][q] = (m0 + ma[q] < g.M && lk0 + ka[q] < g.K) ? pa[ga[q]] : 0.0;
     }
 #pragma unroll
     for (int q = 0; q < Cfg::LB; ++q) {
-      int nn, kk;
-      mapB(tid + 256 * q, nn, kk);
-      const int c = n0 + nn, kb = k0 + kk;
-      rb[q] = (c < g.N && kb < g.K) ? (g.transB ? B[(long)c * g.ldb + kb] : B[(long)kb * g.ldb + c])
-                                    : 0.0;
+      if (FULL) rb[u][q] = pb[gb[q]];
+      else rb[u][q] = (n0 + nb_[q] < g.N && lk0 + kb_[q] < g.K) ? pb[gb[q]] : 0.0;
+    }
+    if (--left > 0) {
+      lk0 += KT;
+      pa += a_step;
+      pb += b_step;
+      if (lk0 >= g.K) {                // next term
+        lk0 = 0;
+        ++lt;
+        pa = a_org + (long)lt * g.sAz;
+        pb = b_org + (long)lt * g.sBz;
+      }
+    } else {
+      left = 0;
     }
   };
-  auto store = [&](int buf) {
-    double* as = As + buf * KT * Cfg::SA;
-    double* bs = Bs + buf * KT * Cfg::SB;
+  auto store = [&](int buf, int u) {
+    double* as = As + buf * Cfg::TILE_A;
+    double* bs = Bs + buf * Cfg::TILE_B;
 #pragma unroll
-    for (int q = 0; q < Cfg::LA; ++q) {
-      int mm, kk;
-      mapA(tid + 256 * q, mm, kk);
-      as[kk * Cfg::SA + mm] = ra[q];
-    }
+    for (int q = 0; q < Cfg::LA; ++q) as[la[q]] = ra[u][q];
 #pragma unroll
-    for (int q = 0; q < Cfg::LB; ++q) {
-      int nn, kk;
-      mapB(tid + 256 * q, nn, kk);
-      bs[kk * Cfg::SB + nn] = rb[q];
-    }
+    for (int q = 0; q < Cfg::LB; ++q) bs[lb[q]] = rb[u][q];
   };
 
   doublex4 acc[Cfg::BI][Cfg::BJ];
@@ -131,32 +169,50 @@ __global__ void __launch_bounds__(256) gemm_f64_kernel(GemmArgs g) {
 #pragma unroll
       for (int e = 0; e < 4; ++e) acc[i][j][e] = 0.0;
 
-  if (total > 0) {
-    load(0);
-    store(0);
-  }
-  __syncthreads();
-  for (int it = 0; it < total; ++it) {
-    const int buf = it & 1;
-    if (it + 1 < total) load(it + 1);
-    const double* as = As + buf * KT * Cfg::SA;
-    const double* bs = Bs + buf * KT * Cfg::SB;
+  auto multiply = [&](int buf) {
+    const double* as = As + buf * Cfg::TILE_A;
+    const double* bs = Bs + buf * Cfg::TILE_B;
 #pragma unroll
     for (int s = 0; s < KT / 4; ++s) {
       const int kk = 4 * s + (lane >> 4);
       double a[Cfg::BI], b[Cfg::BJ];
 #pragma unroll
-      for (int i = 0; i < Cfg::BI; ++i) a[i] = as[kk * Cfg::SA + wm * (TM / 2) + 16 * i + (lane & 15)];
+      for (int i = 0; i < Cfg::BI; ++i) a[i] = as[offA(wm * (TM / 2) + 16 * i + (lane & 15), kk)];
 #pragma unroll
-      for (int j = 0; j < Cfg::BJ; ++j) b[j] = bs[kk * Cfg::SB + wn * (TN / 2) + 16 * j + (lane & 15)];
+      for (int j = 0; j < Cfg::BJ; ++j) b[j] = bs[offB(wn * (TN / 2) + 16 * j + (lane & 15), kk)];
 #pragma unroll
       for (int i = 0; i < Cfg::BI; ++i)
 #pragma unroll
         for (int j = 0; j < Cfg::BJ; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
     }
-    if (it + 1 < total) store(buf ^ 1);
+  };
+
+  if (total > 0) {
+#pragma unroll
+    for (int u = 0; u < D; ++u) load(u);
+    store(0, 0);
     __syncthreads();
+    int it0 = 0;
+    for (; it0 + D <= total; it0 += D) {
+#pragma unroll
+      for (int u = 0; u < D; ++u) {
+        const int it = it0 + u;
+        load(u);                           // slot u held tile it, now in LDS
+        multiply(it & 1);
+        store((it + 1) & 1, (u + 1) % D);  // tile it + 1 (the last tile again at the end)
+        __syncthreads();
+      }
+    }
+#pragma unroll
+    for (int u = 0; u + 1 < D; ++u) {      // the remaining total % D tiles
+      const int it = it0 + u;
+      if (it < total) {
+        multiply(it & 1);
+        if (it + 1 < total) store((it + 1) & 1, (u + 1) % D);
+        __syncthreads();
+      }
+    }
   }
   // D layout of the FP64 MFMA: lane l, item e -> row l/16 + 4e, column l%16
   double* C = g.C + (long)bz * g.sCz;
@@ -168,7 +224,7 @@ __global__ void __launch_bounds__(256) gemm_f64_kernel(GemmArgs g) {
       for (int e = 0; e < 4; ++e) {
         const int m = m0 + wm * (TM / 2) + 16 * i + (lane >> 4) + 4 * e;
         const int c = n0 + wn * (TN / 2) + 16 * j + (lane & 15);
-        if (m < g.M && c < g.N) C[(long)m * g.ldc + c] = acc[i][j][e];
+        if (FULL || (m < g.M && c < g.N)) C[(long)m * g.ldc + c] = acc[i][j][e];
       }
 }
 
@@ -202,19 +258,39 @@ KpApplyPlan kp_apply_plan(int n, int k) {
   return p;
 }
 
-template <int T, int KT>
-static void gemm_launch(const GemmArgs& g, int zdim, hipStream_t s) {
+template <int T, int KT, int D, bool AKC, bool BKC>
+static void gemm_launch2(const GemmArgs& g, int zdim, hipStream_t s) {
   dim3 grid((g.M + T - 1) / T, (g.N + T - 1) / T, zdim);
-  hipLaunchKernelGGL((gemm_f64_kernel<T, T, KT>), grid, dim3(256), 0, s, g);
+  const bool full = g.M % T == 0 && g.N % T == 0 && g.K % KT == 0;
+  if (full)
+    hipLaunchKernelGGL((gemm_f64_kernel<T, T, KT, AKC, BKC, true, D>), grid, dim3(256), 0, s, g);
+  else
+    hipLaunchKernelGGL((gemm_f64_kernel<T, T, KT, AKC, BKC, false, D>), grid, dim3(256), 0, s, g);
+}
+
+// the operand layouts of the two GEMMs of an apply in either direction:
+// (A, B) contiguous along k: (yes, yes), (yes, no) or (no, no)
+template <int T, int KT, int D = 1>
+static void gemm_launch(const GemmArgs& g, int zdim, hipStream_t s) {
+  const bool akc = !g.transA, bkc = g.transB != 0;
+  if (akc && bkc) gemm_launch2<T, KT, D, true, true>(g, zdim, s);
+  else if (akc) gemm_launch2<T, KT, D, true, false>(g, zdim, s);
+  else if (bkc) gemm_launch2<T, KT, D, false, true>(g, zdim, s);
+  else gemm_launch2<T, KT, D, false, false>(g, zdim, s);
 }
 
 // Launch variants (output tile, K tile), picked by the autotuner; the order of
 // accumulation of every output element is the same in all of them.
+constexpr int kNumApplyVariants = 8;
 static void gemm(const GemmArgs& g, int variant, int zdim, hipStream_t s) {
   switch (variant) {
     case 1: gemm_launch<32, 32>(g, zdim, s); break;
     case 2: gemm_launch<32, 16>(g, zdim, s); break;
     case 3: gemm_launch<64, 8>(g, zdim, s); break;   // half the LDS: twice the resident tiles
+    case 4: gemm_launch<32, 16, 4>(g, zdim, s); break;
+    case 5: gemm_launch<32, 32, 2>(g, zdim, s); break;
+    case 6: gemm_launch<64, 16, 2>(g, zdim, s); break;
+    case 7: gemm_launch<64, 8, 4>(g, zdim, s); break;
     default: gemm_launch<64, 16>(g, zdim, s); break;
   }
 }
@@ -229,7 +305,7 @@ void launch_kp_apply_parts(const double* Ax, const double* Ay, int n, int k, int
   // P_g = sum_{t in g} (transpose ? Ay_t^T : Ay_t) * Z_t
   GemmArgs g2{Ay, n, NN, transpose ? 1 : 0, Z, n, NN, 0, P, n, NN, n, n, n, k, plan.group,
               flags, nflags};
-  const int v = tune_pick(kTuneApply, n, k, transpose, 4, [&](int vv) -> double {
+  const int v = tune_pick(kTuneApply, n, k, transpose, kNumApplyVariants, [&](int vv) -> double {
     GemmArgs a = g1, b = g2;
     a.flags = b.flags = nullptr;   // the sample launches always run
     a.nflags = b.nflags = 0;

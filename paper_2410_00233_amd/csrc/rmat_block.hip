@@ -20,6 +20,8 @@
 #include <algorithm>
 #include <climits>
 
+#include <type_traits>
+
 #include "common.h"
 
 namespace kpsb {
@@ -291,10 +293,11 @@ constexpr int x_stride() { return KT + (sizeof(T) == 4 ? 8 : 2); }
 // zero, so the result equals the dense one (for finite X, up to the sign of
 // zero). Without it every entry of R is multiplied.
 template <typename T, int TJ, int JB, int CB, bool CMP, int KT>
-__global__ void __launch_bounds__(64 * (2 * TJ) / (JB * CB))
-rmat_block_kernel(const T* __restrict__ G, int ldg, int n, const T* __restrict__ X, long ldx,
-                  T* __restrict__ Y, long ldy, int ncols, int SW, int CP,
-                  const int* __restrict__ box) {
+__device__ __forceinline__ void rmat_block_tile(const T* __restrict__ G, int ldg, int n,
+                                                const T* __restrict__ X, long ldx,
+                                                T* __restrict__ Y, long ldy, int ncols, int SW,
+                                                int CP, const int* __restrict__ box, int bid,
+                                                unsigned char* lds_raw) {
   constexpr int WAVES = (2 * TJ) / (JB * CB);
   constexpr int NT = 64 * WAVES;
   constexpr int SR = 16 + TJ - 1;
@@ -307,7 +310,6 @@ rmat_block_kernel(const T* __restrict__ G, int ldg, int n, const T* __restrict__
   typedef typename Vec4<T>::type acc_t;
   typedef T vec_t __attribute__((ext_vector_type(VEC)));
 
-  extern __shared__ __align__(16) unsigned char lds_raw[];
   T* slab = reinterpret_cast<T*>(lds_raw);
   T* xbuf = slab + SR * SW;                  // two transposed tiles of 32 x XT
 
@@ -315,8 +317,8 @@ rmat_block_kernel(const T* __restrict__ G, int ldg, int n, const T* __restrict__
   const int lane = tid & 63;
   const int wave = tid >> 6;
   const int n_it = (n + 15) >> 4;
-  const int it = blockIdx.x % n_it;
-  const int jt = blockIdx.x / n_it;
+  const int it = bid % n_it;
+  const int jt = bid / n_it;
   const int i0 = it * 16;
   const int j0 = jt * TJ;
   const int g2 = 2 * n - 1;
@@ -409,7 +411,12 @@ rmat_block_kernel(const T* __restrict__ G, int ldg, int n, const T* __restrict__
 
   // Operands of group g of a staged tile whose first group starts at slab column
   // colbase (a multiple of 4): each lane's 4 consecutive K entries, 16-byte reads.
-  auto read_group = [&](const T* xs, int colbase, int g, T (&a)[JB][4], T (&b)[CB][4]) {
+  // nb (a compile-time count): the column blocks of the wave that hold columns
+  // (CB, or 1 when a launch with CB = 2 has at most 16 columns: the second
+  // block's operands and MFMAs are skipped, its outputs are not written)
+  auto read_group = [&](auto nb, const T* xs, int colbase, int g, T (&a)[JB][4],
+                        T (&b)[CB][4]) {
+    constexpr int NB = decltype(nb)::value;
 #pragma unroll
     for (int h = 0; h < 4 / VEC; ++h) {
 #pragma unroll
@@ -420,7 +427,7 @@ rmat_block_kernel(const T* __restrict__ G, int ldg, int n, const T* __restrict__
         for (int u = 0; u < VEC; ++u) a[jb][VEC * h + u] = v[u];
       }
 #pragma unroll
-      for (int cb = 0; cb < CB; ++cb) {
+      for (int cb = 0; cb < NB; ++cb) {
         const vec_t v = *reinterpret_cast<const vec_t*>(
             xs + ((wc * CB + cb) * 16 + lrow) * XT + kKG * g + 4 * lk + VEC * h);
 #pragma unroll
@@ -428,50 +435,52 @@ rmat_block_kernel(const T* __restrict__ G, int ldg, int n, const T* __restrict__
       }
     }
   };
-  auto mma_group = [&](const T (&a)[JB][4], const T (&b)[CB][4]) {
+  auto mma_group = [&](auto nb, const T (&a)[JB][4], const T (&b)[CB][4]) {
+    constexpr int NB = decltype(nb)::value;
 #pragma unroll
     for (int u = 0; u < 4; ++u)
 #pragma unroll
       for (int jb = 0; jb < JB; ++jb)
 #pragma unroll
-        for (int cb = 0; cb < CB; ++cb)
+        for (int cb = 0; cb < NB; ++cb)
           acc[jb][cb] = mfma16x16x4(a[jb][u], b[cb][u], acc[jb][cb]);
   };
   // The reads of group g + 1 are issued before the MFMAs of group g: a full
   // tile in straight-line code; the last tile of a column block, which may hold
   // fewer groups, in a loop over pairs of groups with the same overlap.
-  auto mma_tile = [&](const T* xs, int colbase, int ng) {
+  auto mma_tile = [&](auto nb, const T* xs, int colbase, int ng) {
     if (ng == GPT) {
       T a0[JB][4], b0[CB][4], a1[JB][4], b1[CB][4];
-      read_group(xs, colbase, 0, a0, b0);
+      read_group(nb, xs, colbase, 0, a0, b0);
 #pragma unroll
       for (int g = 0; g < GPT; g += 2) {
-        if (g + 1 < GPT) read_group(xs, colbase, g + 1, a1, b1);
+        if (g + 1 < GPT) read_group(nb, xs, colbase, g + 1, a1, b1);
         __builtin_amdgcn_sched_barrier(0);
-        mma_group(a0, b0);
+        mma_group(nb, a0, b0);
         __builtin_amdgcn_sched_barrier(0);
         if (g + 1 < GPT) {
-          if (g + 2 < GPT) read_group(xs, colbase, g + 2, a0, b0);
+          if (g + 2 < GPT) read_group(nb, xs, colbase, g + 2, a0, b0);
           __builtin_amdgcn_sched_barrier(0);
-          mma_group(a1, b1);
+          mma_group(nb, a1, b1);
           __builtin_amdgcn_sched_barrier(0);
         }
       }
     } else if (ng > 0) {
       T a0[JB][4], b0[CB][4], a1[JB][4], b1[CB][4];
-      read_group(xs, colbase, 0, a0, b0);
+      read_group(nb, xs, colbase, 0, a0, b0);
 #pragma unroll 1
       for (int g = 0; g < ng; g += 2) {
-        if (g + 1 < ng) read_group(xs, colbase, g + 1, a1, b1);
-        mma_group(a0, b0);
+        if (g + 1 < ng) read_group(nb, xs, colbase, g + 1, a1, b1);
+        mma_group(nb, a0, b0);
         if (g + 1 < ng) {
-          if (g + 2 < ng) read_group(xs, colbase, g + 2, a0, b0);
-          mma_group(a1, b1);
+          if (g + 2 < ng) read_group(nb, xs, colbase, g + 2, a0, b0);
+          mma_group(nb, a1, b1);
         }
       }
     }
   };
 
+  auto main_loop = [&](auto nb) {
   if (active) {   // uniform over the workgroup: every barrier below is reached by all
     // state: column block c, its position cpos in the phase [c0, c0 + CP), its
     // shift r0, the current tile's first group gb and the block's last group gh
@@ -500,7 +509,8 @@ rmat_block_kernel(const T* __restrict__ G, int ldg, int n, const T* __restrict__
       const bool more = cn <= c_hi;
       if (more) load_tile(cn, r0n, gbn, ghn);
       // slab column of the tile's first group: r0 + 16 gb - c + c0 + CP - 1 + 4
-      mma_tile(xbuf + (q & 1) * (32 * XT), r0 + kKG * gb - cpos + CP + 3, min(GPT, gh - gb + 1));
+      mma_tile(nb, xbuf + (q & 1) * (32 * XT), r0 + kKG * gb - cpos + CP + 3,
+               min(GPT, gh - gb + 1));
       if (more) store_tile((q + 1) & 1);
       __syncthreads();
       if (cn != c) {
@@ -529,6 +539,13 @@ rmat_block_kernel(const T* __restrict__ G, int ldg, int n, const T* __restrict__
       gh = ghn;
     }
   }
+  };
+  if constexpr (CB == 2) {
+    if (ncols <= 16) main_loop(std::integral_constant<int, 1>{});
+    else main_loop(std::integral_constant<int, 2>{});
+  } else {
+    main_loop(std::integral_constant<int, CB>{});
+  }
 
   // ---- epilogue -----------------------------------------------------------
 #pragma unroll
@@ -544,6 +561,53 @@ rmat_block_kernel(const T* __restrict__ G, int ldg, int n, const T* __restrict__
         if (i < n && j < n && col < ncols) Y[(long)col * ldy + i + (long)n * j] = (T)v;
       }
     }
+  }
+}
+
+// One workgroup per tile (16 rows i x TJ row blocks j of R).
+template <typename T, int TJ, int JB, int CB, bool CMP, int KT>
+__global__ void __launch_bounds__(64 * (2 * TJ) / (JB * CB))
+rmat_block_kernel(const T* __restrict__ G, int ldg, int n, const T* __restrict__ X, long ldx,
+                  T* __restrict__ Y, long ldy, int ncols, int SW, int CP,
+                  const int* __restrict__ box) {
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  rmat_block_tile<T, TJ, JB, CB, CMP, KT>(G, ldg, n, X, ldx, Y, ldy, ncols, SW, CP, box,
+                                          blockIdx.x, lds_raw);
+}
+
+// Persistent form for many products at once (batched KP-SVD): the tiles of all
+// jobs form one list, job d owning items [jobs[d].first, jobs[d].first +
+// jobs[d].tiles); each workgroup takes the next item from the shared counter
+// (an atomic add by one thread, handed to the others through LDS) until the
+// list is exhausted, so every workgroup leaves the loop. A tile is computed by
+// the same code as in rmat_block_kernel, so each product's bits equal its
+// single launch's.
+template <typename T, int TJ, int JB, int CB, int KT>
+__global__ void __launch_bounds__(64 * (2 * TJ) / (JB * CB))
+rmat_block_persistent_kernel(const BlockJob* __restrict__ jobs, int njobs, int total,
+                             int* __restrict__ counter) {
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  __shared__ int item_s;
+  for (;;) {
+    if (threadIdx.x == 0) item_s = atomicAdd(counter, 1);
+    __syncthreads();
+    // the item and everything derived from it are uniform: keep them in SGPRs
+    const int item = __builtin_amdgcn_readfirstlane(item_s);
+    __syncthreads();                       // read by all before the next fetch
+    if (item >= total) break;
+    int lo = 0, hi = njobs - 1;            // the job holding the item
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (jobs[mid].first <= item) lo = mid;
+      else hi = mid - 1;
+    }
+    lo = __builtin_amdgcn_readfirstlane(lo);
+    const BlockJob& jb = jobs[lo];
+    rmat_block_tile<T, TJ, JB, CB, false, KT>(static_cast<const T*>(jb.G), jb.ldg, jb.n,
+                                              static_cast<const T*>(jb.X), jb.ldx,
+                                              static_cast<T*>(jb.Y), jb.ldy, jb.ncols, jb.SW,
+                                              jb.CP, nullptr, item - jb.first, lds_raw);
+    __syncthreads();                       // the slab and X buffers are free again
   }
 }
 
@@ -685,6 +749,41 @@ template void launch_rmat_block<float>(const BlockPlan&, const float*, int, int,
 template void launch_rmat_block<double>(const BlockPlan&, const double*, int, int,
                                         const double*, long, double*, long, int, hipStream_t,
                                         const int*);
+
+template <int TJ, int JB, int CB, int KT>
+static void launch_persistent_tj(const BlockJob* jobs, int njobs, int total, int* counter,
+                                 size_t lds, int grid, hipStream_t s) {
+  auto kern = rmat_block_persistent_kernel<float, TJ, JB, CB, KT>;
+  constexpr int threads = 64 * (2 * TJ) / (JB * CB);
+  if (lds > 65536)
+    (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)lds);
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(threads), lds, s, jobs, njobs, total, counter);
+}
+
+template <int KT>
+static void launch_persistent_tk(const BlockPlan& p, const BlockJob* jobs, int njobs, int total,
+                                 int* counter, size_t lds, int grid, hipStream_t s) {
+  if (p.TJ == 16 && p.waves == 8)
+    launch_persistent_tj<16, 2, 2, KT>(jobs, njobs, total, counter, lds, grid, s);
+  else if (p.TJ == 16)
+    launch_persistent_tj<16, 1, 2, KT>(jobs, njobs, total, counter, lds, grid, s);
+  else if (p.TJ == 8 && p.waves == 16)
+    launch_persistent_tj<8, 1, 1, KT>(jobs, njobs, total, counter, lds, grid, s);
+  else
+    launch_persistent_tj<8, 1, 2, KT>(jobs, njobs, total, counter, lds, grid, s);
+}
+
+void launch_rmat_block_persistent(const BlockPlan& shape, const BlockJob* jobs, int njobs,
+                                  int total, int* counter, size_t lds, int grid, hipStream_t s) {
+  launch_fill_int(counter, 1, 0, s);
+  switch (shape.TK) {
+    case 176: launch_persistent_tk<176>(shape, jobs, njobs, total, counter, lds, grid, s); break;
+    case 192: launch_persistent_tk<192>(shape, jobs, njobs, total, counter, lds, grid, s); break;
+    case 128: launch_persistent_tk<128>(shape, jobs, njobs, total, counter, lds, grid, s); break;
+    default: launch_persistent_tk<64>(shape, jobs, njobs, total, counter, lds, grid, s); break;
+  }
+}
 
 // Rows and columns of a grid that hold nonzero entries (support box for the
 // block kernel): partial boxes of kBoxBlocks workgroups, then one reduction.

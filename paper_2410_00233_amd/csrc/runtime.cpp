@@ -74,6 +74,17 @@ double est_cost(const kp_blur& b, int32_t method, const void* opts) {
   return (4.0 * q + 4.0) * n4 * kp;
 }
 
+// Problems of a batch whose products can share the persistent launch: RSVD in
+// FP32 (every product a generated-tile FP32 block product) without support
+// compaction. KPSB_BATCH_PERSISTENT=0 runs every problem on its own launches.
+bool lockstep_eligible(const kp_blur& b, int32_t method, const void* opts) {
+  const char* e = getenv("KPSB_BATCH_PERSISTENT");
+  if (e && atoi(e) == 0) return false;
+  if (method != KP_METHOD_RSVD || !opts || b.compact) return false;
+  const kp_rsvd_opts* o = static_cast<const kp_rsvd_opts*>(opts);
+  return o->prec == KP_F32;
+}
+
 kp_status run_one(kp_ctx* w, const kp_blur* b, int32_t method, const void* opts, kp_factors* f) {
   if (method == KP_METHOD_GKB)
     return kp_svd_gkb(w, b, static_cast<const kp_gkb_opts*>(opts), f, w->own_stream);
@@ -115,6 +126,175 @@ double ms_since(std::chrono::steady_clock::time_point t0) {
 }
 
 }  // namespace
+
+// ===========================================================================
+// Lockstep product batch: the FP32 block products of the problems in flight
+// are gathered and run as one persistent launch. Each problem's thread hands
+// over its product (with an event marking its input ready on its stream) and
+// waits; the thread whose request completes the set (every problem in flight
+// has one pending, or has left) launches, and every stream then waits for the
+// launch's completion event.
+struct kp_batch {
+  kp_ctx* parent = nullptr;
+  BlockPlan shape;                 // TJ, waves, TK shared by every product
+  hipStream_t stream = nullptr;    // the persistent launches
+  std::mutex m;
+  std::condition_variable cv;
+  int active = 0;                  // threads that may still hand over a product
+  uint64_t phase = 0;
+  struct Req {
+    hipEvent_t ready;
+    std::vector<BlockJob> jobs;
+    size_t lds;
+  };
+  std::vector<Req> pending;
+  std::vector<BlockJob> host_jobs;
+  BlockJob* djobs = nullptr;
+  int djobs_cap = 0;
+  int* counter = nullptr;
+  hipEvent_t done = nullptr;       // completion of the latest launch
+  kp_status err = KP_OK;
+  std::string msg;
+  int64_t launches = 0, products = 0;
+};
+
+namespace {
+
+// Launches the pending products (caller holds b->m).
+void batch_launch_locked(kp_batch* b) {
+  b->host_jobs.clear();
+  size_t lds = 0;
+  for (auto& r : b->pending) {
+    if (b->err == KP_OK && hipStreamWaitEvent(b->stream, r.ready, 0) != hipSuccess) {
+      b->err = KP_E_DEVICE;
+      b->msg = "hipStreamWaitEvent failed";
+    }
+    (void)hipEventDestroy(r.ready);
+    for (auto& j : r.jobs) b->host_jobs.push_back(j);
+    lds = std::max(lds, r.lds);
+  }
+  // largest tiles first (a tile's work grows as n^2), so that the small ones
+  // fill in at the end
+  std::stable_sort(b->host_jobs.begin(), b->host_jobs.end(),
+                   [](const BlockJob& x, const BlockJob& y) { return x.n > y.n; });
+  int total = 0;
+  for (auto& j : b->host_jobs) {
+    j.first = total;
+    total += j.tiles;
+  }
+  const int nj = (int)b->host_jobs.size();
+  if (b->err == KP_OK && nj > b->djobs_cap) {
+    if (b->djobs) {
+      (void)hipStreamSynchronize(b->stream);
+      (void)hipFree(b->djobs);
+      b->djobs = nullptr;
+    }
+    const int cap = std::max(64, 2 * nj);
+    if (hipMalloc((void**)&b->djobs, sizeof(BlockJob) * cap) != hipSuccess) {
+      (void)hipGetLastError();
+      b->err = KP_E_NOMEM;
+      b->msg = "allocating the batch's job list failed";
+    } else {
+      b->djobs_cap = cap;
+    }
+  }
+  if (b->err == KP_OK && nj > 0) {
+    // pageable source: the copy has consumed host_jobs when the call returns
+    if (hipMemcpyAsync(b->djobs, b->host_jobs.data(), sizeof(BlockJob) * nj,
+                       hipMemcpyHostToDevice, b->stream) != hipSuccess) {
+      b->err = KP_E_DEVICE;
+      b->msg = "copying the batch's job list failed";
+    } else {
+      const int per_cu = lds <= 78 * 1024 ? 2 : 1;
+      const int grid = std::min(total, 256 * per_cu);
+      hipEvent_t e0 = nullptr, e1 = nullptr;
+      const bool prof = b->parent->prof && hipEventCreate(&e0) == hipSuccess &&
+                        hipEventCreate(&e1) == hipSuccess;
+      if (prof) (void)hipEventRecord(e0, b->stream);
+      launch_rmat_block_persistent(b->shape, b->djobs, nj, total, b->counter, lds, grid,
+                                   b->stream);
+      if (prof) {
+        (void)hipEventRecord(e1, b->stream);
+        double fl = 0.0;
+        for (auto& j : b->host_jobs) {
+          const double N = (double)j.n * j.n;
+          fl += 2.0 * N * N * j.ncols;
+        }
+        b->parent->recs.push_back(kp_ctx::Rec{e0, e1, 0, fl});
+      }
+      const hipError_t e = hipGetLastError();
+      if (e != hipSuccess) {
+        b->err = KP_E_DEVICE;
+        b->msg = std::string("persistent block launch: ") + hipGetErrorString(e);
+      }
+      b->launches += 1;
+      b->products += (int64_t)b->pending.size();
+    }
+  }
+  if (hipEventRecord(b->done, b->stream) != hipSuccess && b->err == KP_OK) {
+    b->err = KP_E_DEVICE;
+    b->msg = "hipEventRecord failed";
+  }
+  b->pending.clear();
+  b->phase += 1;
+  b->cv.notify_all();
+}
+
+// A thread of the batch has no more products to hand over.
+void batch_leave(kp_batch* b) {
+  std::lock_guard<std::mutex> lk(b->m);
+  b->active -= 1;
+  if (!b->pending.empty() && (int)b->pending.size() == b->active) batch_launch_locked(b);
+}
+
+}  // namespace
+
+namespace kpsb {
+
+kp_status batch_block_product(kp_ctx* c, const float* G, int ldg, int n, const float* X,
+                              float* Y, int ncols, hipStream_t s) {
+  kp_batch* b = c->batch;
+  BlockPlan p;   // (room for the persistent kernel's own LDS word)
+  if (!plan_block_tj<float>(n, c->lds_limit - 64, b->shape.TJ, &p, b->shape.TK))
+    return fail(c, KP_E_INVAL, "the batch's launch shape does not fit this n");
+  kp_batch::Req r;
+  r.lds = p.lds;
+  const long N = (long)n * n;
+  for (int c0 = 0; c0 < ncols; c0 += 32) {
+    BlockJob j;
+    std::memset(&j, 0, sizeof(j));
+    j.G = G;
+    j.X = X + N * c0;
+    j.Y = Y + N * c0;
+    j.ldx = j.ldy = N;
+    j.ldg = ldg;
+    j.n = n;
+    j.ncols = std::min(32, ncols - c0);
+    j.SW = p.SW;
+    j.CP = p.CP;
+    j.tiles = p.grid;
+    r.jobs.push_back(j);
+  }
+  if (hipEventCreateWithFlags(&r.ready, hipEventDisableTiming) != hipSuccess)
+    return fail(c, KP_E_DEVICE, "hipEventCreate failed");
+  if (hipEventRecord(r.ready, s) != hipSuccess) {
+    (void)hipEventDestroy(r.ready);
+    return fail(c, KP_E_DEVICE, "hipEventRecord failed");
+  }
+  std::unique_lock<std::mutex> lk(b->m);
+  b->pending.push_back(std::move(r));
+  const uint64_t my = b->phase;
+  if ((int)b->pending.size() == b->active) batch_launch_locked(b);
+  else b->cv.wait(lk, [&] { return b->phase != my; });
+  if (b->err != KP_OK) return fail(c, b->err, b->msg);
+  // b->done still marks this phase's launch: the next one needs this thread's
+  // next product
+  if (hipStreamWaitEvent(s, b->done, 0) != hipSuccess)
+    return fail(c, KP_E_DEVICE, "hipStreamWaitEvent failed");
+  return KP_OK;
+}
+
+}  // namespace kpsb
 
 // ===========================================================================
 // Deblurring server
@@ -643,9 +823,14 @@ kp_status kp_svd_batched(kp_ctx* c, int32_t nprob, const kp_blur* blurs, const i
     if (method[i] != KP_METHOD_GKB && method[i] != KP_METHOD_RSVD)
       return fail(c, KP_E_INVAL, "problem " + std::to_string(i) + ": unknown method");
   const int nw = std::min<int>(nworkers ? nworkers : 4, nprob);
+  // problems in flight in the lockstep group (each on its own worker)
+  int n_lock = 0;
+  for (int i = 0; i < nprob; ++i) n_lock += lockstep_eligible(blurs[i], method[i], opts[i]) ? 1 : 0;
+  const int g_lock = n_lock >= 2 ? std::min<int>(nworkers ? nworkers : 16, n_lock) : 0;
   if (hipSetDevice(c->device) != hipSuccess) return fail(c, KP_E_DEVICE, "hipSetDevice failed");
-  kp_status st = ensure_workers(c, nw);
+  kp_status st = ensure_workers(c, std::max(nw, g_lock));
   if (st != KP_OK) return st;
+  const int nw_all = std::max(nw, g_lock);
   hipStream_t s = (hipStream_t)stream;
   // workers start after the work already queued on the caller's stream
   hipEvent_t start;
@@ -666,7 +851,8 @@ kp_status kp_svd_batched(kp_ctx* c, int32_t nprob, const kp_blur* blurs, const i
   // 0 before the others start (the tuner then times its candidates on an
   // otherwise idle GPU); the rest are shared out. Results do not depend on it.
   std::vector<char> done(nprob, 0);
-  for (int wi = 0; wi < nw; ++wi) (void)hipStreamWaitEvent(c->workers[wi]->own_stream, start, 0);
+  for (int wi = 0; wi < nw_all; ++wi)
+    (void)hipStreamWaitEvent(c->workers[wi]->own_stream, start, 0);
   for (int t = 0; t < nprob; ++t) {
     const int i = order[t];
     if (!needs_tuning(blurs[i], method[i], opts[i])) continue;
@@ -681,8 +867,79 @@ kp_status kp_svd_batched(kp_ctx* c, int32_t nprob, const kp_blur* blurs, const i
     }
     done[i] = 1;
   }
+  // Lockstep group: the eligible problems not run yet, largest first, g_lock at
+  // a time; their products run as persistent launches of the batch.
+  std::vector<int> lock_list;
+  for (int t = 0; t < nprob; ++t)
+    if (!done[order[t]] && g_lock > 0 && lockstep_eligible(blurs[order[t]], method[order[t]], opts[order[t]]))
+      lock_list.push_back(order[t]);
+  hipEvent_t lock_done = nullptr;
+  if (lock_list.size() >= 2) {
+    kp_batch b;
+    b.parent = c;
+    int n_max = 0;
+    for (int i : lock_list) n_max = std::max(n_max, blurs[i].n);
+    // the tuned shape of the largest n, except that 16-row-block tiles run with
+    // 8 waves and K tiles of at most 176 entries: in the persistent loop the
+    // 16-wave form (at most 128 registers per lane) would spill
+    bool ok = tuned_block_shape(c, n_max, &b.shape);
+    if (ok && b.shape.TJ == 16) {
+      b.shape.waves = 8;
+      if (b.shape.TK == 192) b.shape.TK = 176;
+    }
+    ok = ok &&
+              hipStreamCreateWithFlags(&b.stream, hipStreamNonBlocking) == hipSuccess &&
+              hipEventCreateWithFlags(&b.done, hipEventDisableTiming) == hipSuccess &&
+              hipMalloc((void**)&b.counter, sizeof(int)) == hipSuccess;
+    if (!ok) {
+      (void)hipGetLastError();
+      for (int i : lock_list) {   // fall back to separate launches
+        (void)i;
+      }
+      lock_list.clear();
+    } else {
+      (void)hipStreamWaitEvent(b.stream, start, 0);
+      const int G = std::min<int>(g_lock, (int)lock_list.size());
+      b.active = G;
+      std::atomic<int> next_l{0};
+      auto body_l = [&](int wi) {
+        kp_ctx* w = c->workers[wi];
+        (void)hipSetDevice(w->device);
+        w->batch = &b;
+        for (;;) {
+          const int t = next_l.fetch_add(1);
+          if (t >= (int)lock_list.size()) break;
+          const int i = lock_list[t];
+          if (c->cancel.load(std::memory_order_acquire)) {
+            res[i] = KP_E_CANCELLED;
+            msg[i] = "cancelled before it started";
+          } else {
+            res[i] = run_one(w, &blurs[i], method[i], opts[i], &out[i]);
+            if (is_error(res[i])) msg[i] = w->err;
+          }
+          done[i] = 1;
+        }
+        w->batch = nullptr;
+        batch_leave(&b);
+      };
+      std::vector<std::thread> thl;
+      for (int wi = 1; wi < G; ++wi) thl.emplace_back(body_l, wi);
+      body_l(0);
+      for (auto& t : thl) t.join();
+      if (hipEventCreateWithFlags(&lock_done, hipEventDisableTiming) == hipSuccess)
+        (void)hipEventRecord(lock_done, b.stream);
+    }
+    if (b.stream) (void)hipStreamSynchronize(b.stream);
+    if (b.djobs) (void)hipFree(b.djobs);
+    if (b.counter) (void)hipFree(b.counter);
+    if (b.done) (void)hipEventDestroy(b.done);
+    if (b.stream) (void)hipStreamDestroy(b.stream);
+    c->batch_launches = b.launches;
+    c->batch_products = b.products;
+  }
+
   std::atomic<int> next{0};
-  std::vector<hipEvent_t> fin(nw, nullptr);
+  std::vector<hipEvent_t> fin(nw_all, nullptr);
   auto body = [&](int wi) {
     kp_ctx* w = c->workers[wi];
     (void)hipSetDevice(w->device);
@@ -706,11 +963,18 @@ kp_status kp_svd_batched(kp_ctx* c, int32_t nprob, const kp_blur* blurs, const i
   for (int wi = 1; wi < nw; ++wi) th.emplace_back(body, wi);
   body(0);
   for (auto& t : th) t.join();
-  for (int wi = 0; wi < nw; ++wi)
+  for (int wi = nw; wi < nw_all; ++wi)   // workers of the lockstep group only
+    if (hipEventCreateWithFlags(&fin[wi], hipEventDisableTiming) == hipSuccess)
+      (void)hipEventRecord(fin[wi], c->workers[wi]->own_stream);
+  for (int wi = 0; wi < nw_all; ++wi)
     if (fin[wi]) {
       (void)hipStreamWaitEvent(s, fin[wi], 0);
       (void)hipEventDestroy(fin[wi]);
     }
+  if (lock_done) {
+    (void)hipStreamWaitEvent(s, lock_done, 0);
+    (void)hipEventDestroy(lock_done);
+  }
   (void)hipEventDestroy(start);
   // a cancel request that stopped problems is consumed by this call
   if (std::find(res.begin(), res.end(), KP_E_CANCELLED) != res.end()) c->cancel.store(0);
