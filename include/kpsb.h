@@ -196,6 +196,9 @@ typedef struct {
   int32_t l_end;        /* outer iterations performed                              */
   int32_t iota_total;   /* total CGLS iterations                                   */
   double rc_sb;         /* last RC_SB                                              */
+  int32_t graph_replays; /* CGLS iterations run as replays of a captured HIP graph
+                            (8 per replay; 0 when the eager launches ran)           */
+  int32_t reserved;
 } sb_stats;
 
 /* Per-kernel-class timing (tracing). While enabled, every launch of the FP32 /

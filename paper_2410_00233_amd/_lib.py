@@ -77,7 +77,8 @@ class kp_prof(C.Structure):
 
 
 class sb_stats(C.Structure):
-    _fields_ = [("l_end", C.c_int32), ("iota_total", C.c_int32), ("rc_sb", C.c_double)]
+    _fields_ = [("l_end", C.c_int32), ("iota_total", C.c_int32), ("rc_sb", C.c_double),
+                ("graph_replays", C.c_int32), ("reserved", C.c_int32)]
 
 
 class kp_server_cfg(C.Structure):

@@ -354,7 +354,8 @@ class Context:
         st = L.sb_stats()
         self._check(fn(self.h, int(n), _ptr(A), _ptr(b), C.byref(o), _ptr(x), C.byref(st),
                        _stream()))
-        return x, dict(l_end=st.l_end, iota_total=st.iota_total, rc_sb=st.rc_sb)
+        return x, dict(l_end=st.l_end, iota_total=st.iota_total, rc_sb=st.rc_sb,
+                       graph_replays=st.graph_replays)
 
     def kp_apply(self, f: Factors, X, transpose=False, Y=None):
         torch = _torch()
@@ -372,7 +373,8 @@ class Context:
         st = L.sb_stats()
         self._check(fn(self.h, C.byref(f.s), _ptr(b), C.byref(o), _ptr(x), C.byref(st),
                        _stream()))
-        return x, dict(l_end=st.l_end, iota_total=st.iota_total, rc_sb=st.rc_sb)
+        return x, dict(l_end=st.l_end, iota_total=st.iota_total, rc_sb=st.rc_sb,
+                       graph_replays=st.graph_replays)
 
     def sb_solve_aniso(self, f, b, lam, beta, L_max=50, I_max=100, tau_sb=0.0, tau_cgls=0.0,
                        x=None):

@@ -46,6 +46,12 @@ bool tune_enabled() {
 }
 
 double time_launches(hipStream_t s, int reps, const std::function<void()>& launch) {
+  // a stream under graph capture cannot be timed: no sample is launched
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &cap) != hipSuccess || cap != hipStreamCaptureStatusNone) {
+    (void)hipGetLastError();
+    return -1.0;
+  }
   hipEvent_t a = nullptr, b = nullptr;
   if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return -1.0;
   launch();                                 // warm-up (instruction cache, clocks)
@@ -108,6 +114,12 @@ int tune_pick(int op, int n, int a, int b, int ncand, const std::function<double
     }
   }
   std::lock_guard<std::mutex> lk(g_mu);
+  if (tune_enabled() && !ch.ms.empty() && ch.variant == 0 && !(ch.ms[0] >= 0)) {
+    // no sample could be timed (for instance under graph capture): variant 0,
+    // not remembered, so that a later call on an ordinary stream tunes the key
+    auto it = g_table.find(key);
+    return it != g_table.end() ? it->second.variant : 0;
+  }
   auto ins = g_table.emplace(key, ch);   // a concurrent tuner of the same key may have won
   return ins.first->second.variant;
 }
