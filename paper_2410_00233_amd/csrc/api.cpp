@@ -508,9 +508,9 @@ kp_status split16_product(kp_ctx* c, const kp_blur* b, const double* dpsf, int n
     for (int c0 = 0; c0 < ncols; c0 += 32) {
       const int nc = ncols - c0 < 32 ? ncols - c0 : 32;
       float* Wc = out + N * c0;
-      launch_rmat_block16<__half>(bp, Ghi, ldg, n, Xhi + ld16 * c0, ld16, Wc, N, nc, s, scal + 1, 0);
-      launch_rmat_block16<__half>(bp, Ghi, ldg, n, Xlo + ld16 * c0, ld16, Wc, N, nc, s, scal + 1, 1);
-      launch_rmat_block16<__half>(bp, Glo, ldg, n, Xhi + ld16 * c0, ld16, Wc, N, nc, s, scal + 1, 1);
+      launch_rmat_block16<__half>(bp, Ghi, ldg, n, Xhi + ld16 * c0, ld16, Wc, N, nc, s, scal + 1, 0, true);
+      launch_rmat_block16<__half>(bp, Ghi, ldg, n, Xlo + ld16 * c0, ld16, Wc, N, nc, s, scal + 1, 1, true);
+      launch_rmat_block16<__half>(bp, Glo, ldg, n, Xhi + ld16 * c0, ld16, Wc, N, nc, s, scal + 1, 1, true);
     }
     return check_launch(c, "split16_product");
   });

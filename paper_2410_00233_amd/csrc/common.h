@@ -92,11 +92,14 @@ int grid_box_parts();
 bool plan_block16(int n, size_t lds_limit, BlockPlan* plan);
 bool plan_block16_tj(int n, size_t lds_limit, int TJ, BlockPlan* plan);
 // inv_scale (device, may be null) multiplies the result (undoes power-of-2
-// operand scaling); accumulate != 0 adds the result into Y.
+// operand scaling); accumulate != 0 adds the result into Y. fold: the FP32
+// partial sums go into FP64 accumulators once per column block of R (the
+// split-FP16 product, which must keep FP32-level accuracy); otherwise the
+// MFMA's FP32 accumulator takes the whole sum.
 template <typename H>
 void launch_rmat_block16(const BlockPlan& plan, const H* G16, int ldg, int n, const H* X16,
                          long ldx, float* Y, long ldy, int ncols, hipStream_t s,
-                         const double* inv_scale = nullptr, int accumulate = 0);
+                         const double* inv_scale = nullptr, int accumulate = 0, bool fold = false);
 
 // Split FP16 operands of the refinement product (FP32-level accuracy from three
 // FP16 products): X scaled by 2^kSplitXExp into hi + lo; the grid scaled by a

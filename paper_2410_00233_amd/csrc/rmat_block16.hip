@@ -13,6 +13,13 @@
 // column r0_c - c + n - 1 is then a multiple of 8. Entries with r outside
 // [0, n) are staged as 0 (LEN = n + 7 rounded up to 32: at most 39 extra
 // zero products per column block). X arrives already converted to 16 bits.
+//
+// Accumulation: the MFMA's FP32 accumulators take the whole sum (FOLD = false:
+// the 16-bit products, whose operand rounding, 2^-9 relative, dwarfs FP32
+// summation error), or are folded into FP64 accumulators at the end of every
+// column block (FOLD = true: the split-FP16 refinement product, which must
+// keep FP32-level accuracy; 64 more registers per 32 outputs per lane and
+// about 15 % of the kernel time at n = 512).
 #include "common.h"
 
 namespace kpsb {
@@ -44,7 +51,7 @@ constexpr int kXS16 = kKS * kSPT + 16;
 // K step ks = c * (LEN/32) + tt holds the 32 entries r0_c + 32 tt + (0..31) of
 // column block c at X16[col * ldx + 32 ks + (0..31)], zero outside [0, n). A tile
 // is kSPT consecutive K steps (it may span two column blocks).
-template <typename H, int TJ, int JB, int CB>
+template <typename H, int TJ, int JB, int CB, bool FOLD>
 __global__ void __launch_bounds__(64 * (2 * TJ) / (JB * CB))
 rmat_block16_kernel(const H* __restrict__ G, int ldg, int n, const H* __restrict__ X, long ldx,
                     float* __restrict__ Y, long ldy, int ncols, int SW, int LEN, int CP,
@@ -170,15 +177,17 @@ rmat_block16_kernel(const H* __restrict__ G, int ldg, int n, const H* __restrict
           for (int cb = 0; cb < CB; ++cb) acc[jb][cb] = Mfma16<H>::mma(afr, bfr[cb], acc[jb][cb]);
         }
         if (tt == ntc - 1) {       // end of column block c
+          if constexpr (FOLD) {
 #pragma unroll
-          for (int jb = 0; jb < JB; ++jb)
+            for (int jb = 0; jb < JB; ++jb)
 #pragma unroll
-            for (int cb = 0; cb < CB; ++cb)
+              for (int cb = 0; cb < CB; ++cb)
 #pragma unroll
-              for (int e = 0; e < 4; ++e) {
-                accd[jb][cb][e] += (double)acc[jb][cb][e];
-                acc[jb][cb][e] = 0.f;
-              }
+                for (int e = 0; e < 4; ++e) {
+                  accd[jb][cb][e] += (double)acc[jb][cb][e];
+                  acc[jb][cb][e] = 0.f;
+                }
+          }
           tt = 0;
           ++c;
         } else {
@@ -207,7 +216,7 @@ rmat_block16_kernel(const H* __restrict__ G, int ldg, int n, const H* __restrict
         const int i = i0 + 4 * lg + e;
         if (i < n && j < n && col < ncols) {
           float* yp = Y + (long)col * ldy + i + (long)n * j;
-          const double v = accd[jb][cb][e] * osc;
+          const double v = (FOLD ? accd[jb][cb][e] : (double)acc[jb][cb][e]) * osc;
           *yp = accumulate ? (float)((double)*yp + v) : (float)v;
         }
       }
@@ -270,8 +279,8 @@ bool plan_block16(int n, size_t lds_limit, BlockPlan* plan) {
 template <typename H, int TJ, int JB, int CB>
 static void launch16_tj(const BlockPlan& p, const H* G, int ldg, int n, const H* X, long ldx,
                         float* Y, long ldy, int ncols, const double* inv_scale, int accumulate,
-                        hipStream_t s) {
-  auto kern = rmat_block16_kernel<H, TJ, JB, CB>;
+                        bool fold, hipStream_t s) {
+  auto kern = fold ? rmat_block16_kernel<H, TJ, JB, CB, true> : rmat_block16_kernel<H, TJ, JB, CB, false>;
   constexpr int threads = 64 * (2 * TJ) / (JB * CB);
   if (p.lds > 65536)
     (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -284,43 +293,44 @@ static void launch16_tj(const BlockPlan& p, const H* G, int ldg, int n, const H*
 template <typename H>
 void launch_rmat_block16(const BlockPlan& p, const H* G16, int ldg, int n, const H* X16,
                          long ldx, float* Y, long ldy, int ncols, hipStream_t s,
-                         const double* inv_scale, int accumulate) {
+                         const double* inv_scale, int accumulate, bool fold) {
   // waves per workgroup (p.waves, 0 = the default): more waves hide the LDS
   // latency of the fragment reads better, fewer row blocks per wave read more
   // LDS per MFMA; chosen by the autotuner
   if (p.TJ == 64 && p.waves == 8) {
-    launch16_tj<H, 64, 8, 2>(p, G16, ldg, n, X16, ldx, Y, ldy, ncols, inv_scale, accumulate, s);
+    launch16_tj<H, 64, 8, 2>(p, G16, ldg, n, X16, ldx, Y, ldy, ncols, inv_scale, accumulate, fold, s);
     return;
   }
   if (p.TJ == 64) {
-    launch16_tj<H, 64, 4, 2>(p, G16, ldg, n, X16, ldx, Y, ldy, ncols, inv_scale, accumulate, s);
+    launch16_tj<H, 64, 4, 2>(p, G16, ldg, n, X16, ldx, Y, ldy, ncols, inv_scale, accumulate, fold, s);
     return;
   }
   if (p.TJ == 32 && p.waves == 16) {
-    launch16_tj<H, 32, 2, 2>(p, G16, ldg, n, X16, ldx, Y, ldy, ncols, inv_scale, accumulate, s);
+    launch16_tj<H, 32, 2, 2>(p, G16, ldg, n, X16, ldx, Y, ldy, ncols, inv_scale, accumulate, fold, s);
     return;
   }
   if (p.TJ == 16 && p.waves == 8) {
-    launch16_tj<H, 16, 2, 2>(p, G16, ldg, n, X16, ldx, Y, ldy, ncols, inv_scale, accumulate, s);
+    launch16_tj<H, 16, 2, 2>(p, G16, ldg, n, X16, ldx, Y, ldy, ncols, inv_scale, accumulate, fold, s);
     return;
   }
   if (p.TJ == 16 && p.waves == 16) {
-    launch16_tj<H, 16, 1, 2>(p, G16, ldg, n, X16, ldx, Y, ldy, ncols, inv_scale, accumulate, s);
+    launch16_tj<H, 16, 1, 2>(p, G16, ldg, n, X16, ldx, Y, ldy, ncols, inv_scale, accumulate, fold, s);
     return;
   }
   switch (p.TJ) {
-    case 32: launch16_tj<H, 32, 4, 2>(p, G16, ldg, n, X16, ldx, Y, ldy, ncols, inv_scale, accumulate, s); break;
-    case 16: launch16_tj<H, 16, 4, 2>(p, G16, ldg, n, X16, ldx, Y, ldy, ncols, inv_scale, accumulate, s); break;
-    case 8: launch16_tj<H, 8, 2, 2>(p, G16, ldg, n, X16, ldx, Y, ldy, ncols, inv_scale, accumulate, s); break;
-    default: launch16_tj<H, 4, 1, 2>(p, G16, ldg, n, X16, ldx, Y, ldy, ncols, inv_scale, accumulate, s); break;
+    case 32: launch16_tj<H, 32, 4, 2>(p, G16, ldg, n, X16, ldx, Y, ldy, ncols, inv_scale, accumulate, fold, s); break;
+    case 16: launch16_tj<H, 16, 4, 2>(p, G16, ldg, n, X16, ldx, Y, ldy, ncols, inv_scale, accumulate, fold, s); break;
+    case 8: launch16_tj<H, 8, 2, 2>(p, G16, ldg, n, X16, ldx, Y, ldy, ncols, inv_scale, accumulate, fold, s); break;
+    default: launch16_tj<H, 4, 1, 2>(p, G16, ldg, n, X16, ldx, Y, ldy, ncols, inv_scale, accumulate, fold, s); break;
   }
 }
 template void launch_rmat_block16<__hip_bfloat16>(const BlockPlan&, const __hip_bfloat16*, int,
                                                   int, const __hip_bfloat16*, long, float*,
-                                                  long, int, hipStream_t, const double*, int);
+                                                  long, int, hipStream_t, const double*, int,
+                                                  bool);
 template void launch_rmat_block16<__half>(const BlockPlan&, const __half*, int, int,
                                           const __half*, long, float*, long, int, hipStream_t,
-                                          const double*, int);
+                                          const double*, int, bool);
 
 // FP32 X (N x ncols, ld ldx) -> pre-shifted 16-bit copy (see rmat_block16_kernel):
 // out[col * ldo + c * LEN + kk] = X[col * ldx + c * n + r0_c + kk] for
