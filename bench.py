@@ -62,7 +62,7 @@ BLOCK_VARIANT_TEMPLATE = {0: "16,1,2,false,64", 1: "16,2,2,false,64", 2: "8,1,2,
 BLOCK16_VARIANT_TEMPLATE = {0: "32,4,2,false", 1: "16,4,2,false", 2: "32,2,2,false",
                             3: "16,2,2,false", 4: "16,1,2,false", 5: "64,4,2,false",
                             6: "64,8,2,false"}
-BLOCK16_TRAFFIC_SRC_SHA1 = "5a1fa497d43ed0c66b378fccc7483a2fd36397ef"
+BLOCK16_TRAFFIC_SRC_SHA1 = "1d396a6114ec7c6b99b29d64d45dd0385a11f690"
 
 
 def counted_traffic(src, sha, value):
