@@ -140,6 +140,29 @@ def test_product16_full_size_sampled_rows(ctx, prec):
     assert np.all(np.abs(Y[rows] - ref) <= 2e-6 * mag + 1e-7 * mag.max())
 
 
+@pytest.mark.parametrize("prec", ["bf16", "f16"])
+@pytest.mark.parametrize("n,force,tr", [(400, "5", False), (417, "5", True), (417, None, False)])
+def test_product16_slab_phases_ragged(ctx, n, force, tr, prec, monkeypatch):
+    """16-bit products with 64 row blocks per workgroup (variant 5): the slab at
+    n = 400 / 417 runs in phases of 256 column blocks, reloaded between X tiles;
+    n = 417 leaves a ragged last row block. Sampled rows (and the first / last)
+    against the FP64 product of the rounded operands, both orientations; the
+    tuned shape at n = 417 as well."""
+    if force is not None:
+        monkeypatch.setenv("KPSB_TUNE_FORCE", force)
+    P, cu, cv = wl.mixed_psf(n, "disk", np.random.default_rng(n))
+    X = np.random.default_rng(n + 1).standard_normal((n * n, 21)).astype(np.float32).astype(np.float64)
+    rng = np.random.default_rng(n + 2)
+    rows = np.unique(np.r_[0, n - 1, n * n - n, n * n - 1, rng.choice(n * n, 14, replace=False)])
+    Y = _run(ctx, P, cu, cv, n, X, tr, prec).reshape(n * n, -1)
+    cols = np.arange(n * n)
+    R = op.rmat_entries(P, cu, cv, n, cols, rows).T if tr else op.rmat_entries(P, cu, cv, n, rows, cols)
+    R16, X16 = _round16(R, prec), _round16(X, prec)
+    ref = R16 @ X16
+    mag = np.abs(R16) @ np.abs(X16)
+    assert np.all(np.abs(Y[rows] - ref) <= 2e-6 * mag + 1e-7 * mag.max())
+
+
 @pytest.mark.parametrize("prec,nvar", [("f32", 16), ("f64", 16), ("bf16", 7)])
 @pytest.mark.parametrize("n", [40, 256])
 def test_autotuner_variants_agree_bitwise(ctx, prec, nvar, n, monkeypatch):
