@@ -58,7 +58,7 @@ BLOCK_VARIANT_TEMPLATE = {0: "16,1,2,false,64", 1: "16,2,2,false,64", 2: "8,1,2,
                           6: "8,1,2,false,128", 7: "8,1,1,false,128", 8: "16,1,2,false,192",
                           9: "16,2,2,false,192", 10: "8,1,2,false,192", 11: "8,1,1,false,192",
                           12: "16,1,2,false,176", 13: "16,2,2,false,176", 14: "8,1,2,false,176",
-                          15: "8,1,1,false,176"}
+                          15: "8,1,1,false,176", 16: "12,1,2,false,176", 17: "12,1,2,false,128"}
 BLOCK16_VARIANT_TEMPLATE = {0: "32,4,2,false", 1: "16,4,2,false", 2: "32,2,2,false",
                             3: "16,2,2,false", 4: "16,1,2,false", 5: "64,4,2,false",
                             6: "64,8,2,false"}

@@ -361,7 +361,10 @@ struct ProfScope {
 };
 
 // Autotuned launch shapes of the block products: the cost of a variant is the
-// time of a sample launch (the first 1024 workgroups) per row of R it covers.
+// time of a sample launch (the first 1024 workgroups, or the whole grid if
+// smaller) scaled to the whole launch by rounds of resident workgroups (a
+// partial last round costs a whole one): ms * ceil(grid / res) /
+// ceil(sample / res), res = 256 CUs x the workgroups the LDS lets share a CU.
 constexpr int kSampleWG = 1024;
 struct BlockVariant {
   int TJ, waves, TK;
@@ -369,8 +372,18 @@ struct BlockVariant {
 constexpr BlockVariant kBlockVariants[] = {{16, 16, 64},  {16, 8, 64},  {8, 8, 64},  {8, 16, 64},
                                            {16, 16, 128}, {16, 8, 128}, {8, 8, 128}, {8, 16, 128},
                                            {16, 16, 192}, {16, 8, 192}, {8, 8, 192}, {8, 16, 192},
-                                           {16, 16, 176}, {16, 8, 176}, {8, 8, 176}, {8, 16, 176}};
-constexpr int kNumBlockVariants = 16;
+                                           {16, 16, 176}, {16, 8, 176}, {8, 8, 176}, {8, 16, 176},
+                                           {12, 12, 176}, {12, 12, 128}};
+constexpr int kNumBlockVariants = 18;
+
+double launch_estimate(double sample_ms, int grid, size_t lds, size_t lds_cap, int threads) {
+  const int sample = std::min(grid, kSampleWG);
+  const int by_lds = lds > 0 ? (int)std::max<size_t>(1, lds_cap / lds) : 8;
+  const int by_waves = std::max(1, 32 / std::max(1, threads / 64));   // 32 waves per CU
+  const long res = 256L * std::max(1, std::min(by_lds, by_waves));
+  const long r_all = (grid + res - 1) / res, r_sample = (sample + res - 1) / res;
+  return sample_ms * (double)r_all / (double)r_sample;
+}
 struct Block16Variant {
   int TJ, waves;
 };
@@ -392,7 +405,7 @@ kp_status choose_block_plan(kp_ctx* c, const Grids<T>& g, int n, const T* X, T* 
     const double ms = time_launches(s, 2, [&]() {
       launch_rmat_block<T>(p, g.G, g.ldg, n, X, N, Y, N, nc, s);
     });
-    return ms < 0 ? -1.0 : ms / ((double)std::min(p.grid, kSampleWG) * 16.0 * p.TJ);
+    return ms < 0 ? -1.0 : launch_estimate(ms, p.grid, p.lds, c->lds_limit, 64 * p.waves);
   });
   if (!plan_block_tj<T>(n, c->lds_limit, kBlockVariants[v].TJ, bp, kBlockVariants[v].TK)) {
     if (!plan_block<T>(n, c->lds_limit, bp))
@@ -438,7 +451,7 @@ kp_status choose_block16_plan(kp_ctx* c, const Grids<H>& g, int n, const H* X16,
     const double ms = time_launches(s, 2, [&]() {
       launch_rmat_block16<H>(p, g.G, g.ldg, n, X16, ld16, Y, N, nc, s);
     });
-    return ms < 0 ? -1.0 : ms / ((double)std::min(p.grid, kSampleWG) * 16.0 * p.TJ);
+    return ms < 0 ? -1.0 : launch_estimate(ms, p.grid, p.lds, c->lds_limit, 64 * p.waves);
   });
   if (plan_block16_tj(n, c->lds_limit, kBlock16Variants[v].TJ, bp)) {
     bp->waves = kBlock16Variants[v].waves;

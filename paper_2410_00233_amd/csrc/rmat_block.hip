@@ -690,16 +690,20 @@ template <typename T>
 void launch_rmat_block(const BlockPlan& p, const T* G, int ldg, int n, const T* X, long ldx,
                        T* Y, long ldy, int ncols, hipStream_t s, const int* box) {
   // waves per workgroup: TJ = 16 -> 16 (JB = 1) or 8 (JB = 2); TJ = 8 -> 8 (CB = 2)
-  // or 16 (CB = 1); chosen by the autotuner, 16 and 8 by default; K tiles of 64
-  // or (these four shapes) 128, 176 or 192 entries (fewer tiles, so fewer
-  // barriers, per column block; larger X buffers). 176 = 11 groups splits the
-  // 33 groups of a column block whose r range starts below 0 into three full
-  // tiles (at n = 512; 192 leaves a last tile of 9).
+  // or 16 (CB = 1); TJ = 12 -> 12 (K tiles of 128 or 176 only: a grid of
+  // whole rounds of 256 workgroups where 8 and 16 leave a partial one, e.g.
+  // 768 tiles at n = 384); chosen by the autotuner, 16 and 8 by default; K
+  // tiles of 64 or (these shapes) 128, 176 or 192 entries (fewer tiles, so
+  // fewer barriers, per column block; larger X buffers). 176 = 11 groups
+  // splits the 33 groups of a column block whose r range starts below 0 into
+  // three full tiles (at n = 512; 192 leaves a last tile of 9).
   if (p.TK == 176) {
     if (p.TJ == 16 && p.waves == 8)
       launch_tj<T, 16, 2, 2, 176>(p, G, ldg, n, X, ldx, Y, ldy, ncols, s, box);
     else if (p.TJ == 16)
       launch_tj<T, 16, 1, 2, 176>(p, G, ldg, n, X, ldx, Y, ldy, ncols, s, box);
+    else if (p.TJ == 12)
+      launch_tj<T, 12, 1, 2, 176>(p, G, ldg, n, X, ldx, Y, ldy, ncols, s, box);
     else if (p.TJ == 8 && p.waves == 16)
       launch_tj<T, 8, 1, 1, 176>(p, G, ldg, n, X, ldx, Y, ldy, ncols, s, box);
     else
@@ -722,6 +726,8 @@ void launch_rmat_block(const BlockPlan& p, const T* G, int ldg, int n, const T* 
       launch_tj<T, 16, 2, 2, 128>(p, G, ldg, n, X, ldx, Y, ldy, ncols, s, box);
     else if (p.TJ == 16)
       launch_tj<T, 16, 1, 2, 128>(p, G, ldg, n, X, ldx, Y, ldy, ncols, s, box);
+    else if (p.TJ == 12)
+      launch_tj<T, 12, 1, 2, 128>(p, G, ldg, n, X, ldx, Y, ldy, ncols, s, box);
     else if (p.TJ == 8 && p.waves == 16)
       launch_tj<T, 8, 1, 1, 128>(p, G, ldg, n, X, ldx, Y, ldy, ncols, s, box);
     else
@@ -761,6 +767,7 @@ static void launch_persistent_tj(const BlockJob* jobs, int njobs, int total, int
   hipLaunchKernelGGL(kern, dim3(grid), dim3(threads), lds, s, jobs, njobs, total, counter);
 }
 
+// shapes of 16 row blocks (8 or 16 waves) or 8 (8 or 16 waves) only
 template <int KT>
 static void launch_persistent_tk(const BlockPlan& p, const BlockJob* jobs, int njobs, int total,
                                  int* counter, size_t lds, int grid, hipStream_t s) {

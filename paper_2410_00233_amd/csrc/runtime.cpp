@@ -883,6 +883,8 @@ kp_status kp_svd_batched(kp_ctx* c, int32_t nprob, const kp_blur* blurs, const i
     // 8 waves and K tiles of at most 176 entries: in the persistent loop the
     // 16-wave form (at most 128 registers per lane) would spill
     bool ok = tuned_block_shape(c, n_max, &b.shape);
+    if (ok && b.shape.TJ == 12)   // the persistent kernel is built for 16 and 8 row blocks
+      ok = plan_block_tj<float>(n_max, c->lds_limit, 16, &b.shape, b.shape.TK);
     if (ok && b.shape.TJ == 16) {
       b.shape.waves = 8;
       if (b.shape.TK == 192) b.shape.TK = 176;
