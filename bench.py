@@ -510,8 +510,9 @@ def main():
                          "(a copy of known size for calibration, the n=512 FP32 / BF16 block "
                          "and FP32 matrix-vector products, the n=256 Kronecker apply and a few "
                          "CGLS iterations) and exit")
-    ap.add_argument("--gkb-block", type=int, default=20,
-                    help="block size b of the timed block Golub-Kahan run")
+    ap.add_argument("--gkb-block", type=int, default=16,
+                    help="block size b of the timed block Golub-Kahan run (16: one MFMA "
+                         "column block, so no padded columns; k_p = b ceil(40 / b))")
     ap.add_argument("--no-paper-pipeline", action="store_true",
                     help="skip the explicit-matrix run on the paper's n = 128 setting")
     args = ap.parse_args()
@@ -567,8 +568,10 @@ def main():
     value = (f_gkb + f_rsvd) / (ms_step * 1e-3) / 1e12
 
     log(f"step {ms_step:.1f} ms ({value:.1f} TFLOP/s); block GKB (b = {args.gkb_block})")
-    # the block form of Algorithm 1 on the same workload and k_p: its products
-    # with B and B^T are block products of b columns on the MFMA kernel
+    # the block form of Algorithm 1 on the same workload, k_p = b ceil(k_p / b)
+    # (48 at b = 16): its products with B and B^T are block products of b
+    # columns on the MFMA kernel (b = 16 fills one 16-column MFMA block; b = 20
+    # would pad every product to 32 columns)
     b_blk = args.gkb_block
     nb_blk = -(-(k + p_gkb) // b_blk)
     f_blk = flops.egkb(n, k, nb_blk * b_blk - k)
