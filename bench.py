@@ -50,7 +50,7 @@ MFMA_FP32_PEAK_TFLOPS = 157.3     # MI355X dense FP32 matrix peak
 # (profiles/rmat_products_n512_hbm_counters.md), valid while the kernel source
 # is the one the counters were taken on.
 BLOCK_TRAFFIC_BYTES = 1.149e9
-BLOCK_TRAFFIC_SRC_SHA1 = "e4e24e0b274e2745d57152c7dc15f14ac8d47558"
+BLOCK_TRAFFIC_SRC_SHA1 = "8437c6e328e38f76a1c577556af9242481da709b"
 BLOCK16_TRAFFIC_BYTES = 2.10e8
 # template arguments <TJ, JB, CB> of the FP32 block kernel per autotuner variant
 BLOCK_VARIANT_TEMPLATE = {0: "16,1,2,false,64", 1: "16,2,2,false,64", 2: "8,1,2,false,64",

@@ -6,6 +6,8 @@
 // so the results do not depend on the choice (checked by the tests).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <map>
@@ -53,18 +55,32 @@ double time_launches(hipStream_t s, int reps, const std::function<void()>& launc
     return -1.0;
   }
   hipEvent_t a = nullptr, b = nullptr;
-  if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return -1.0;
+  if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
+    if (a) (void)hipEventDestroy(a);
+    (void)hipGetLastError();
+    return -1.0;
+  }
+  auto timed = [&](int r_count) -> double {
+    (void)hipEventRecord(a, s);
+    for (int r = 0; r < r_count; ++r) launch();
+    (void)hipEventRecord(b, s);
+    float ms = -1.f;
+    if (hipEventSynchronize(b) != hipSuccess || hipEventElapsedTime(&ms, a, b) != hipSuccess)
+      ms = -1.f;
+    return ms < 0 ? -1.0 : (double)ms / r_count;
+  };
   launch();                                 // warm-up (instruction cache, clocks)
-  (void)hipEventRecord(a, s);
-  for (int r = 0; r < reps; ++r) launch();
-  (void)hipEventRecord(b, s);
-  float ms = -1.f;
-  if (hipEventSynchronize(b) != hipSuccess || hipEventElapsedTime(&ms, a, b) != hipSuccess)
-    ms = -1.f;
+  double per = timed(reps);
+  // short launches: time again over at least 0.5 ms of them (up to 32), so that
+  // the candidates of a small size are not told apart by timer noise
+  if (per >= 0 && per < 0.1) {
+    const int more = (int)std::min(32.0, std::max((double)reps, std::ceil(0.5 / std::max(per, 1e-3))));
+    if (more > reps) per = timed(more);
+  }
   (void)hipEventDestroy(a);
   (void)hipEventDestroy(b);
   (void)hipGetLastError();
-  return ms < 0 ? -1.0 : (double)ms / reps;
+  return per;
 }
 
 bool tune_known(int op, int n, int a, int b) {
