@@ -251,6 +251,63 @@ def bench_batched(ctx, count):
     }
 
 
+def bench_sb_batched(ctx, count):
+    """Mixed batch of `count` isotropic split Bregman solves (FP64, k = 10..20
+    factors from FP32 RSVD, 50 outer x up to 100 CGLS iterations, CGLS tau 1e-4)
+    of n in {64, 128, 192, 256} through sb_solve_batched, against the same
+    solves as single calls one after another."""
+    import numpy as np
+    import torch
+
+    import workloads as wl
+    from paper_2410_00233_amd import api, flops
+    mix = wl.batched_mix(count, sizes=(64, 128, 192, 256), ranks=(10, 20),
+                         seed=wl.SEED_PSF + 900)
+    lam = 0.115
+    probs = []
+    for i, d in enumerate(mix):
+        blur = api.Blur(d["P"], d["cu"], d["cv"], d["n"], on_device=True)
+        f = ctx.kp_svd_rsvd(blur, d["k"], d["p"], 2, prec="f32", seed=d["seed"])
+        x_true = wl.rectangles_image(d["n"], seed=wl.SEED_IMAGE + i)
+        b = wl.add_noise(wl.blur_zero_bc(d["P"], d["cu"], d["cv"], x_true), 0.01,
+                         seed=wl.SEED_NOISE + i)
+        probs.append(dict(f=f, b=torch.tensor(b, dtype=torch.float64, device="cuda"), iso=True,
+                          lam=lam, beta=lam * lam / 2.0, L_max=50, I_max=100, tau_cgls=1e-4))
+    # every (n, k) apply tuned and the workers warm before the timed run
+    first = {}
+    for pr, d in zip(probs, mix):
+        first.setdefault((d["n"], d["k"]), dict(pr, L_max=1, I_max=8))
+    ctx.sb_solve_batched(list(first.values()))
+    torch.cuda.synchronize()
+    log("batched SB: timed run")
+    t0 = time.perf_counter()
+    xs, stats, status = ctx.sb_solve_batched(probs)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    log(f"batched SB: {1e3 * t_batch:.0f} ms; the same solves one by one")
+    t0 = time.perf_counter()
+    solo = [ctx.sb_solve_iso(p["f"], p["b"], p["lam"], p["beta"], L_max=50, I_max=100,
+                             tau_cgls=1e-4) for p in probs]
+    torch.cuda.synchronize()
+    t_solo = time.perf_counter() - t0
+    same = all(torch.equal(x, y[0]) for x, y in zip(xs, solo))
+    fl = sum(st["iota_total"] * flops.cgls_iteration_kp(d["n"], d["k"])
+             for st, d in zip(stats, mix))
+    sizes = [d["n"] for d in mix]
+    return {
+        "workload": f"{count} isotropic split Bregman solves (FP64, 50 outer x <= 100 CGLS, "
+                    "CGLS tau 1e-4, k 10-20), n in {64,128,192,256}, Gaussian/motion/disk PSFs, "
+                    "rectangles image + 1% noise, 4 worker streams",
+        "problems": count, "n_hist": {str(v): sizes.count(v) for v in sorted(set(sizes))},
+        "cgls_iterations": int(sum(st["iota_total"] for st in stats)),
+        "batched_ms": round(1e3 * t_batch, 2), "solo_sum_ms": round(1e3 * t_solo, 2),
+        "batched_cgls_tflops": round(fl / t_batch / 1e12, 3),
+        "speedup_vs_solo": round(t_solo / t_batch, 3),
+        "x_equal_to_solo": bool(same),
+        "statuses_ok": bool(all(s_ in (0, 100) for s_ in status)),
+    }
+
+
 def bench_paper_pipeline(ctx, n=128):
     """The paper's own pipeline on its "Medium" setting (n = 128, reflexive
     boundary conditions, a 15 x 15 speckle-like PSF, k = 8, p = 4): explicit A,
@@ -496,6 +553,8 @@ def main():
     ap.add_argument("--sb-solves", type=int, default=5)
     ap.add_argument("--batched", type=int, default=64,
                     help="problems in the batched KP-SVD run (0 skips it)")
+    ap.add_argument("--sb-batched", type=int, default=16,
+                    help="solves in the batched split Bregman run (0 skips it)")
     ap.add_argument("--serve", type=int, default=32,
                     help="requests in the serving run (0 skips serving)")
     ap.add_argument("--serve-rate", type=float, default=200.0,
@@ -823,6 +882,9 @@ def main():
     if args.batched > 0:
         log(f"batched KP-SVD, {args.batched} problems")
         line["batched"] = bench_batched(ctx, args.batched)
+    if args.sb_batched > 0:
+        log(f"batched split Bregman, {args.sb_batched} solves")
+        line["sb_batched"] = bench_sb_batched(ctx, args.sb_batched)
     if args.serve > 0:
         sizes = tuple(int(v) for v in args.serve_sizes.split(","))
         srv = api.Server(ctx, slots=4)

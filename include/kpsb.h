@@ -238,11 +238,13 @@ kp_status kp_prof_read(kp_ctx* ctx, kp_prof* out, int reset);
 /* Library version string (static storage). */
 const char* kp_version(void);
 /* Autotuner report: the launch variant chosen for every (operation, size) met so
- * far in this process and the measured cost of each candidate (ms per row of R
- * for the block products, ms per apply for the Kronecker GEMMs), as JSON text.
- * The first call of an operation at a new size times its candidates on the
- * call's stream (one warm-up and two sample launches each) and keeps the
- * fastest; all candidates give bitwise-identical results. KPSB_AUTOTUNE=0 in
+ * far in this process and the measured cost of each candidate (for the block
+ * products the sample launch's time scaled to the whole launch by rounds of
+ * resident workgroups, ms; ms per apply for the Kronecker GEMMs), as JSON
+ * text. The first call of an operation at a new size times its candidates on
+ * the call's stream (one warm-up and two sample launches each, more when a
+ * launch is shorter than 0.1 ms) and keeps the fastest; all candidates give
+ * bitwise-identical results. KPSB_AUTOTUNE=0 in
  * the environment keeps every operation at its first variant. out: HOST buffer
  * of cap bytes, NUL-terminated, truncated if short. */
 kp_status kp_tune_report(char* out, size_t cap);
@@ -321,6 +323,33 @@ kp_status sb_solve_iso(kp_ctx* ctx, const kp_factors* f, const double* b,
 kp_status kp_svd_batched(kp_ctx* ctx, int32_t nprob, const kp_blur* blurs,
                          const int32_t* method, const void* const* opts, kp_factors* out,
                          kp_status* status, int32_t nworkers, void* stream);
+
+/* One split Bregman problem of sb_solve_batched: exactly the arguments of a
+ * single sb_solve_iso (iso = 1, Algorithm 4) or sb_solve_aniso (iso = 0,
+ * Algorithm 3) call. f: KP_F64 factors (device); b, x: DEVICE n x n row-major
+ * FP64, b and x not aliased and no x shared by two problems. */
+typedef struct {
+  const kp_factors* f;
+  const double* b;
+  double* x;
+  sb_opts opts;
+  int32_t iso;
+  int32_t reserved;
+} sb_problem;
+
+/* Batched split Bregman (Algorithms 3-5): the problems run concurrently on
+ * `nworkers` worker contexts (0 selects 4; at most 16; the workers of
+ * kp_svd_batched), largest first (n^3 k L_max I_max), each exactly as its
+ * single call (same kernels and reduction order, so the same bits; HIP-graph
+ * replays of the CGLS iterations where the single call uses them). Problems
+ * whose Kronecker-apply launch shape is not tuned yet run first, one at a
+ * time. Every worker stream first waits for the work queued on `stream`, and
+ * `stream` waits for all of them at the end; the call returns when every
+ * problem is finished. stats, status: optional HOST out [nprob]. Returns as
+ * kp_svd_batched; kp_cancel on ctx stops the problems in progress and marks
+ * those not started KP_E_CANCELLED. */
+kp_status sb_solve_batched(kp_ctx* ctx, int32_t nprob, const sb_problem* probs,
+                           sb_stats* stats, kp_status* status, int32_t nworkers, void* stream);
 
 /* ---------------------------------------------------------------------------
  * Deblurring server: a request loop that runs split Bregman solves

@@ -32,7 +32,8 @@ EXPORTED = ["kp_ctx_create", "kp_ctx_destroy", "kp_last_error", "kp_version",
             "kp_server_destroy", "kp_tune_report", "kp_rmat_reorder", "kp_rmat_apply_stored",
             "kp_svd_gkb_stored", "kp_svd_rsvd_stored", "sb_solve_aniso_direct",
             "sb_solve_iso_direct", "kp_blur_matrix", "kp_rmat_apply_noalloc",
-            "kp_ctx_workspace", "kp_request_footprint", "kp_cancel", "kp_server_cancel"]
+            "kp_ctx_workspace", "kp_request_footprint", "kp_cancel", "kp_server_cancel",
+            "sb_solve_batched"]
 
 
 class kp_blur(C.Structure):
@@ -79,6 +80,11 @@ class kp_prof(C.Structure):
 class sb_stats(C.Structure):
     _fields_ = [("l_end", C.c_int32), ("iota_total", C.c_int32), ("rc_sb", C.c_double),
                 ("graph_replays", C.c_int32), ("reserved", C.c_int32)]
+
+
+class sb_problem(C.Structure):
+    _fields_ = [("f", C.POINTER(kp_factors)), ("b", C.c_void_p), ("x", C.c_void_p),
+                ("opts", sb_opts), ("iso", C.c_int32), ("reserved", C.c_int32)]
 
 
 class kp_server_cfg(C.Structure):
@@ -143,6 +149,8 @@ def load(path: str = LIB_PATH):
     lib.kp_svd_batched.argtypes = [vp, C.c_int32, C.POINTER(kp_blur), C.POINTER(C.c_int32),
                                    C.POINTER(vp), C.POINTER(kp_factors), C.POINTER(C.c_int),
                                    C.c_int32, vp]
+    lib.sb_solve_batched.argtypes = [vp, C.c_int32, C.POINTER(sb_problem), C.POINTER(sb_stats),
+                                     C.POINTER(C.c_int), C.c_int32, vp]
     lib.kp_server_create.argtypes = [vp, C.POINTER(kp_server_cfg), C.POINTER(vp)]
     lib.kp_server_submit.argtypes = [vp, C.POINTER(kp_request), C.POINTER(C.c_uint64)]
     lib.kp_server_wait.argtypes = [vp, C.c_uint64, C.c_double, C.POINTER(kp_result)]

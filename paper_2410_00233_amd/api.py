@@ -386,6 +386,31 @@ class Context:
         return self._sb(self.lib.sb_solve_iso, f, b, lam, beta, L_max, I_max, tau_sb,
                         tau_cgls, x)
 
+    def sb_solve_batched(self, problems, nworkers=0):
+        """problems: list of dicts with keys f (Factors), b (device image),
+        iso (bool), lam, beta and optionally L_max, I_max, tau_sb, tau_cgls, x.
+        Returns (list of x, list of stats dicts, list of statuses)."""
+        torch = _torch()
+        m = len(problems)
+        xs = [p.get("x") if p.get("x") is not None else torch.empty_like(p["b"])
+              for p in problems]
+        arr = (L.sb_problem * m)()
+        for i, p in enumerate(problems):
+            arr[i].f = C.pointer(p["f"].s)
+            arr[i].b = _ptr(p["b"])
+            arr[i].x = _ptr(xs[i])
+            arr[i].opts = L.sb_opts(p["lam"], p["beta"], p.get("L_max", 50), p.get("I_max", 100),
+                                    p.get("tau_sb", 0.0), p.get("tau_cgls", 0.0))
+            arr[i].iso = int(bool(p["iso"]))
+        st = (L.sb_stats * m)()
+        status = (C.c_int * m)()
+        self._check(self.lib.sb_solve_batched(self.h, m, arr, st, status, int(nworkers),
+                                              _stream()),
+                    allow=(L.KP_OK, L.KP_W_BREAKDOWN))
+        stats = [dict(l_end=s.l_end, iota_total=s.iota_total, rc_sb=s.rc_sb,
+                      graph_replays=s.graph_replays) for s in st]
+        return xs, stats, list(status)
+
 
 class Server:
     """The request server (kp_server_*): submit() is non-blocking, wait()

@@ -993,6 +993,102 @@ kp_status kp_svd_batched(kp_ctx* c, int32_t nprob, const kp_blur* blurs, const i
   return worst;
 }
 
+kp_status sb_solve_batched(kp_ctx* c, int32_t nprob, const sb_problem* probs, sb_stats* stats,
+                           kp_status* status, int32_t nworkers, void* stream) {
+  if (!c) return KP_E_INVAL;
+  if (nprob < 0) return fail(c, KP_E_INVAL, "nprob must be >= 0");
+  if (nprob == 0) return KP_OK;
+  if (!probs) return fail(c, KP_E_INVAL, "probs is NULL");
+  if (nworkers < 0 || nworkers > 16) return fail(c, KP_E_INVAL, "nworkers must be in [0, 16]");
+  for (int i = 0; i < nprob; ++i)
+    if (!probs[i].f || !probs[i].b || !probs[i].x)
+      return fail(c, KP_E_INVAL, "problem " + std::to_string(i) + ": f, b or x is NULL");
+  const int nw = std::min<int>(nworkers ? nworkers : 4, nprob);
+  if (hipSetDevice(c->device) != hipSuccess) return fail(c, KP_E_DEVICE, "hipSetDevice failed");
+  kp_status st = ensure_workers(c, nw);
+  if (st != KP_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  hipEvent_t start;
+  if (hipEventCreateWithFlags(&start, hipEventDisableTiming) != hipSuccess)
+    return fail(c, KP_E_DEVICE, "hipEventCreate failed");
+  if (hipEventRecord(start, s) != hipSuccess) {
+    (void)hipEventDestroy(start);
+    return fail(c, KP_E_DEVICE, "hipEventRecord failed");
+  }
+  for (int wi = 0; wi < nw; ++wi) (void)hipStreamWaitEvent(c->workers[wi]->own_stream, start, 0);
+  // largest first: 4 k n^3 flops per apply, two applies per CGLS iteration
+  auto cost = [&](int i) {
+    const double n = probs[i].f->n;
+    return n * n * n * (double)probs[i].f->k * probs[i].opts.L_max * probs[i].opts.I_max;
+  };
+  std::vector<int> order(nprob);
+  for (int i = 0; i < nprob; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost(a) > cost(b); });
+  std::vector<kp_status> res(nprob, KP_OK);
+  std::vector<std::string> msg(nprob);
+  std::vector<sb_stats> st_out(nprob);
+  std::vector<char> done(nprob, 0);
+  auto run = [&](kp_ctx* w, int i) {
+    if (c->cancel.load(std::memory_order_acquire)) {
+      res[i] = KP_E_CANCELLED;
+      msg[i] = "cancelled before it started";
+      return;
+    }
+    std::memset(&st_out[i], 0, sizeof(sb_stats));
+    const sb_problem& pr = probs[i];
+    res[i] = pr.iso ? sb_solve_iso(w, pr.f, pr.b, &pr.opts, pr.x, &st_out[i], w->own_stream)
+                    : sb_solve_aniso(w, pr.f, pr.b, &pr.opts, pr.x, &st_out[i], w->own_stream);
+    if (is_error(res[i])) msg[i] = w->err;
+  };
+  // sizes whose apply GEMMs are not tuned yet: alone on worker 0 first
+  for (int t = 0; t < nprob; ++t) {
+    const int i = order[t];
+    if (!apply_needs_tuning(probs[i].f->n, probs[i].f->k)) continue;
+    kp_ctx* w = c->workers[0];
+    (void)hipSetDevice(w->device);
+    run(w, i);
+    (void)hipStreamSynchronize(w->own_stream);
+    done[i] = 1;
+  }
+  std::atomic<int> next{0};
+  std::vector<hipEvent_t> fin(nw, nullptr);
+  auto body = [&](int wi) {
+    kp_ctx* w = c->workers[wi];
+    (void)hipSetDevice(w->device);
+    for (;;) {
+      const int t = next.fetch_add(1);
+      if (t >= nprob) break;
+      const int i = order[t];
+      if (!done[i]) run(w, i);
+    }
+    if (hipEventCreateWithFlags(&fin[wi], hipEventDisableTiming) == hipSuccess)
+      (void)hipEventRecord(fin[wi], w->own_stream);
+  };
+  std::vector<std::thread> th;
+  for (int wi = 1; wi < nw; ++wi) th.emplace_back(body, wi);
+  body(0);
+  for (auto& t : th) t.join();
+  for (int wi = 0; wi < nw; ++wi)
+    if (fin[wi]) {
+      (void)hipStreamWaitEvent(s, fin[wi], 0);
+      (void)hipEventDestroy(fin[wi]);
+    }
+  (void)hipEventDestroy(start);
+  if (std::find(res.begin(), res.end(), KP_E_CANCELLED) != res.end()) c->cancel.store(0);
+  kp_status worst = KP_OK;
+  for (int i = 0; i < nprob; ++i) {
+    if (status) status[i] = res[i];
+    if (stats) stats[i] = st_out[i];
+    if (is_error(res[i]) && !is_error(worst)) {
+      worst = res[i];
+      c->err = "problem " + std::to_string(i) + ": " + msg[i];
+    } else if (res[i] == KP_W_BREAKDOWN && worst == KP_OK) {
+      worst = KP_W_BREAKDOWN;
+    }
+  }
+  return worst;
+}
+
 kp_status kp_server_create(kp_ctx* c, const kp_server_cfg* cfg, kp_server** out) {
   if (!c) return KP_E_INVAL;
   if (!cfg || !out) return fail(c, KP_E_INVAL, "cfg or out is NULL");

@@ -48,6 +48,7 @@ def test_null_arguments_are_rejected(lib):
     assert lib.kp_svd_gkb(None, None, None, None, None) == _lib.KP_E_INVAL
     assert lib.kp_last_error(None) == b"null context"
     assert lib.kp_svd_batched(None, 0, None, None, None, None, None, 0, None) == _lib.KP_E_INVAL
+    assert lib.sb_solve_batched(None, 0, None, None, None, 0, None) == _lib.KP_E_INVAL
     assert lib.kp_server_create(None, None, None) == _lib.KP_E_INVAL
     assert lib.kp_server_submit(None, None, None) == _lib.KP_E_INVAL
     assert lib.kp_server_wait(None, 0, 0.0, None) == _lib.KP_E_INVAL
@@ -76,7 +77,8 @@ int main(void) {
   S(kp_diag); P(kp_diag, alpha); P(kp_diag, kp); P(kp_diag, break_side); P(kp_diag, ms_total); P(kp_diag, basis_v);
   S(kp_factors); P(kp_factors, sigma); P(kp_factors, Ax); P(kp_factors, factor_prec); P(kp_factors, diag);
   S(sb_opts); P(sb_opts, L_max); P(sb_opts, tau_cgls);
-  S(sb_stats); P(sb_stats, rc_sb);
+  S(sb_stats); P(sb_stats, rc_sb); P(sb_stats, graph_replays);
+  S(sb_problem); P(sb_problem, b); P(sb_problem, x); P(sb_problem, opts); P(sb_problem, iso);
   S(kp_prof); P(kp_prof, launches); P(kp_prof, flops);
   S(kp_server_cfg); P(kp_server_cfg, hbm_budget_bytes); P(kp_server_cfg, cache_entries);
   S(kp_request); P(kp_request, blur); P(kp_request, method); P(kp_request, gkb); P(kp_request, rsvd);
@@ -98,7 +100,7 @@ def test_ctypes_layout_matches_header(tmp_path):
     ref = dict(l.rsplit(" ", 1) for l in lines if l)
     m = {"kp_blur": _lib.kp_blur, "kp_gkb_opts": _lib.kp_gkb_opts, "kp_rsvd_opts": _lib.kp_rsvd_opts,
          "kp_diag": _lib.kp_diag, "kp_factors": _lib.kp_factors, "sb_opts": _lib.sb_opts,
-         "sb_stats": _lib.sb_stats, "kp_prof": _lib.kp_prof,
+         "sb_stats": _lib.sb_stats, "sb_problem": _lib.sb_problem, "kp_prof": _lib.kp_prof,
          "kp_server_cfg": _lib.kp_server_cfg, "kp_request": _lib.kp_request,
          "kp_result": _lib.kp_result}
     rename = {"lambda": "lam"}

@@ -97,6 +97,33 @@ def test_batched_cancel_marks_unstarted_problems():
         c.close()
 
 
+def test_batched_sb_cancel_marks_unstarted_problems():
+    from paper_2410_00233_amd import api
+    from paper_2410_00233_amd import _lib as L
+    c = api.Context(0)
+    try:
+        rng = np.random.default_rng(7)
+        probs = []
+        for i, (n, k) in enumerate(((32, 3), (40, 4), (48, 5))):
+            f = api.Factors.from_arrays(rng.standard_normal((k, n, n)),
+                                        rng.standard_normal((k, n, n)))
+            b = torch.tensor(rng.standard_normal((n, n)), dtype=torch.float64, device="cuda")
+            probs.append(dict(f=f, b=b, iso=i % 2 == 0, lam=0.115, beta=0.0066, L_max=3,
+                              I_max=16))
+        ref, _, st = c.sb_solve_batched(probs)
+        assert st == [L.KP_OK] * 3
+        c.kp_cancel()
+        with pytest.raises(api.KPError) as ei:
+            c.sb_solve_batched(probs)
+        assert ei.value.status == L.KP_E_CANCELLED
+        again, _, st = c.sb_solve_batched(probs)
+        torch.cuda.synchronize()
+        assert st == [L.KP_OK] * 3
+        for x, y in zip(ref, again):
+            assert torch.equal(x, y)
+    finally:
+        c.close()
+
 def test_server_cancel_queued_and_running(ctx):
     from paper_2410_00233_amd import api
     from paper_2410_00233_amd import _lib as L

@@ -133,3 +133,68 @@ def test_sb_graph_replays_equal_eager_launches(ctx, kind, taus, monkeypatch):
     assert np.array_equal(xg, xe) and sg == se
     assert np.array_equal(out["1"][1][0], xg)
     assert out["1"][1][1]["graph_replays"] > 0
+
+
+def test_sb_batched_equals_single_calls(ctx):
+    """sb_solve_batched runs the problems concurrently on worker streams
+    (largest first); each restored image and its counters must equal those of
+    the single call on the same problem, bit for bit, and the first image must
+    also match the oracle."""
+    from paper_2410_00233_amd import api
+    import torch
+    specs = [(32, 4, "iso", (0.0, 0.0)), (48, 6, "aniso", (1e-2, 1e-4)),
+             (64, 5, "iso", (1e-2, 1e-4)), (100, 8, "aniso", (0.0, 0.0)),
+             (40, 3, "aniso", (0.0, 0.0)), (72, 7, "iso", (0.0, 0.0))]
+    lam = 0.115
+    beta = lam * lam / 2.0
+    probs, singles = [], []
+    for i, (n, k, kind, taus) in enumerate(specs):
+        Ax, Ay, b, _ = _problem(n, k, idx=i)
+        f = api.Factors.from_arrays(Ax, Ay)
+        kw = dict(L_max=4, I_max=12, tau_sb=taus[0], tau_cgls=taus[1])
+        fn = ctx.sb_solve_aniso if kind == "aniso" else ctx.sb_solve_iso
+        x, st = fn(f, _dev(b), lam, beta, **kw)
+        torch.cuda.synchronize()
+        singles.append((x.cpu().numpy(), st))
+        probs.append(dict(f=f, b=_dev(b), iso=kind == "iso", lam=lam, beta=beta, **kw))
+        if i == 0:
+            ref = _oracle(kind, Ax, Ay, b, lam, beta, L_max=4, I_max=12)
+            assert np.linalg.norm(singles[0][0] - ref["x"]) <= 1e-6 * np.linalg.norm(ref["x"])
+    for nworkers in (0, 3):
+        xs, stats, status = ctx.sb_solve_batched(probs, nworkers=nworkers)
+        torch.cuda.synchronize()
+        assert status == [0] * len(specs)
+        for i, (xb, sb_st) in enumerate(zip(xs, stats)):
+            x1, s1 = singles[i]
+            print(f"batched SB problem {i} n={specs[i][0]} {specs[i][2]}: "
+                  f"l_end {sb_st['l_end']} iota {sb_st['iota_total']}")
+            assert np.array_equal(xb.cpu().numpy(), x1), i
+            for key in ("l_end", "iota_total", "rc_sb"):
+                assert sb_st[key] == s1[key], (i, key)
+
+
+def test_sb_batched_reports_each_problem(ctx):
+    """A bad problem fails alone: its status names the error, the others solve."""
+    import ctypes as C
+    from paper_2410_00233_amd import _lib as L, api
+    import torch
+    Ax, Ay, b, _ = _problem(24, 3, idx=1)
+    f = api.Factors.from_arrays(Ax, Ay)
+    bd = _dev(b)
+    xs = [torch.empty_like(bd) for _ in range(3)]
+    arr = (L.sb_problem * 3)()
+    for i in range(3):
+        arr[i].f = C.pointer(f.s)
+        arr[i].b = C.c_void_p(bd.data_ptr())
+        arr[i].x = C.c_void_p(xs[i].data_ptr())
+        arr[i].opts = L.sb_opts(-1.0 if i == 1 else 0.1, 0.01, 3, 8, 0.0, 0.0)
+        arr[i].iso = i % 2
+    st = (L.sb_stats * 3)()
+    status = (C.c_int * 3)()
+    rc = ctx.lib.sb_solve_batched(ctx.h, 3, arr, st, status, 2,
+                                  C.c_void_p(torch.cuda.current_stream().cuda_stream))
+    torch.cuda.synchronize()
+    assert rc == L.KP_E_INVAL and list(status) == [L.KP_OK, L.KP_E_INVAL, L.KP_OK]
+    assert b"problem 1" in ctx.lib.kp_last_error(ctx.h)
+    assert st[0].l_end == 3 and st[2].l_end == 3
+    assert ctx.lib.sb_solve_batched(ctx.h, 1, arr, st, status, 17, None) == L.KP_E_INVAL
