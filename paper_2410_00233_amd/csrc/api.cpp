@@ -83,6 +83,9 @@ bool inject_alloc_fault() {
   return ++count == target;
 }
 
+// set while this thread captures a graph (and holds capture_mutex() shared)
+thread_local bool t_capturing = false;
+
 kp_status ws(kp_ctx* c, const std::string& name, size_t bytes, void** out) {
   if (c->arena_base) {   // allocation-free mode: carve from the caller's scratch
     const size_t need = (bytes + 255) & ~(size_t)255;
@@ -114,6 +117,11 @@ kp_status ws(kp_ctx* c, const std::string& name, size_t bytes, void** out) {
     pool.used -= v;
   };
   if (b.p) {
+    if (t_capturing) {   // this thread holds the capture lock shared
+      unreserve(bytes);
+      return set_err(c, KP_E_DEVICE, "workspace '" + name + "' would grow during a graph capture");
+    }
+    std::unique_lock<std::shared_mutex> nocap(capture_mutex());
     hipError_t e1 = hipDeviceSynchronize();
     hipError_t e2 = e1 == hipSuccess ? hipFree(b.p) : e1;
     if (e2 != hipSuccess) {
@@ -631,112 +639,16 @@ void cgs2(const Scratch& sc, T* w, const T* V, long ldv, int m, long N, hipStrea
   }
 }
 
-// Column-wise Gram-Schmidt QR of W (N x m, ld N) in place: W = Q R. Each column
-// gets two classical Gram-Schmidt passes and is normalized (norm = R[j, j]);
-// a third pass then measures how much of the normalized vector lies outside
-// the span of the previous columns. If less than half of it does, the column
-// was numerically dependent (its residual was rounding noise) and is replaced
-// by a Philox normal vector (stream `stream_base + j`) orthogonalized twice:
-// R keeps the projections and the rounding-level R[j, j]. Otherwise the third
-// pass is folded into R. R (m x m, column-major FP64) is formed when
-// Rfac != NULL.
-//
-// Dependent columns are rare, so the columns first run without the
-// replacement kernels, in chunks of kCgsChunk, each column's flag kept; after
-// a chunk the host reads its flags. At the first flagged column j the chunk's
-// columns from j on are restored from a copy of W taken at the start (column
-// j only reads columns < j and writes column j, so nothing else changed) and
-// the QR goes on from j with the replacement kernels predicated on the device
-// flag of each column, the same kernels in the same order as a column that
-// takes them from the start. The result is that of the predicated sequence.
-constexpr int kCgsChunk = 16;
-
-// Passes 1-3 of column j, its dependence flag and, for a kept column, the
-// third pass folded into R (no replacement).
+// Orthonormal basis of the N x m block W in place (Householder TSQR), with its R
+// factor in Rfac when that is not NULL.
 template <typename T>
-static void cgs_column(const Scratch& sc, T* W, long N, int j, double* Rcol, double* rjj,
-                       int* flag, hipStream_t s) {
-  T* w = W + N * j;
-  double* h2 = sc.h + 64;
-  double* h3 = sc.h + 128;
-  double* r3 = sc.scal + 3;
-  // (the projections reduce the multidot partials themselves: Rcol = h1,
-  // then h2 is stored and added into Rcol)
-  if (j > 0) {
-    launch_multidot<T>(W, N, j, w, N, sc.partials, s);
-    launch_project_out_red<T>(w, W, N, j, sc.partials, Rcol, nullptr, N, nullptr, s);
-    launch_multidot<T>(W, N, j, w, N, sc.partials, s);
-    launch_project_out_red<T>(w, W, N, j, sc.partials, h2, Rcol, N, sc.nrmp, s);
-    launch_normalize<T>(w, N, sc.nrmp, rjj, s);
-    launch_multidot<T>(W, N, j, w, N, sc.partials, s);
-    launch_project_out_red<T>(w, W, N, j, sc.partials, h3, nullptr, N, sc.nrmp, s);
-    // a kept column (r3 >= 0.5) folds the third pass into R here: with
-    // q = w / r = sum_i h3_i v_i + r3 q', w = sum_i (R_ij + r h3_i) v_i + r r3 q'
-    QrFixup fx;
-    fx.rcol = Rcol;
-    fx.m = j;
-    fx.h3 = h3;
-    fx.rjj = rjj;
-    launch_normalize<T>(w, N, sc.nrmp, r3, s, nullptr, flag, 0.5, fx);
-  } else {
-    launch_norm2_partials<T>(w, N, sc.nrmp, s);
-    // flag an exactly zero first column
-    launch_normalize<T>(w, N, sc.nrmp, rjj, s, nullptr, flag, 1e-300);
-  }
-}
-
-template <typename T>
-kp_status cgs_qr(kp_ctx* c, const Scratch& sc, T* W, long N, int m, double* Rfac,
-                 uint64_t seed, uint32_t stream_base, hipStream_t s) {
-  double* h2 = sc.h + 64;
-  double* rscr = sc.scal + 2;
-  double* r4 = sc.scal + 4;
-  auto rcol = [&](int j) { return Rfac ? Rfac + (long)m * j : sc.h + 192; };
-  auto rdiag = [&](int j) { return Rfac ? Rfac + j + (long)m * j : rscr; };
-  if (Rfac) launch_fill_small(Rfac, m * m, 0.0, s);
-  T* copy = nullptr;
-  KP_TRY(wsT(c, std::string("cgs_copy_") + tname<T>(), (size_t)N * m, &copy));
-  KP_HIP(c, hipMemcpyAsync(copy, W, sizeof(T) * N * m, hipMemcpyDeviceToDevice, s));
-  int* hflags = reinterpret_cast<int*>(c->pinned + 32);   // kCgsChunk ints
-  // KPSB_CGS_EAGER=1 takes the predicated sequence from the first column (to
-  // check that both orders give the same bits)
-  const char* eager = getenv("KPSB_CGS_EAGER");
-  int j = 0;
-  while (j < m && !(eager && atoi(eager) != 0)) {   // unpredicated chunks
-    const int j1 = std::min(m, j + kCgsChunk);
-    for (int q = j; q < j1; ++q) cgs_column<T>(sc, W, N, q, rcol(q), rdiag(q), sc.flags + q, s);
-    KP_TRY(check_launch(c, "cgs_qr"));
-    KP_HIP(c, hipMemcpyAsync(hflags, sc.flags + j, sizeof(int) * (j1 - j),
-                             hipMemcpyDeviceToHost, s));
-    KP_HIP(c, hipStreamSynchronize(s));
-    int first = -1;
-    for (int q = j; q < j1 && first < 0; ++q)
-      if (hflags[q - j]) first = q;
-    if (first < 0) {
-      j = j1;
-      continue;
-    }
-    KP_HIP(c, hipMemcpyAsync(W + N * first, copy + N * first, sizeof(T) * N * (j1 - first),
-                             hipMemcpyDeviceToDevice, s));
-    j = first;
-    break;
-  }
-  for (; j < m; ++j) {   // from the first dependent column on: predicated replacement
-    T* w = W + N * j;
-    cgs_column<T>(sc, W, N, j, rcol(j), rdiag(j), sc.flag, s);
-    launch_philox_normals<T>(w, N, seed, stream_base + (uint32_t)j, s, sc.flag);
-    for (int pass = 0; pass < 2; ++pass) {
-      if (j > 0) {
-        launch_multidot<T>(W, N, j, w, N, sc.partials, s, sc.flag);
-        launch_project_out_red<T>(w, W, N, j, sc.partials, nullptr, nullptr, N, sc.nrmp, s,
-                                  sc.flag);
-      } else {
-        launch_project_out<T>(w, W, N, 0, h2, N, sc.nrmp, s, sc.flag);
-      }
-    }
-    launch_normalize<T>(w, N, sc.nrmp, r4, s, sc.flag);
-  }
-  return check_launch(c, "cgs_qr");
+kp_status tsqr_qr(kp_ctx* c, T* W, long N, int m, double* Rfac, hipStream_t s) {
+  const size_t bytes = tsqr_workspace_bytes(N, m);
+  if (!bytes) return set_err(c, KP_E_INVAL, "QR of an N x m block needs 1 <= m <= 64, N >= m");
+  void* w = nullptr;
+  KP_TRY(ws(c, "tsqr", bytes, &w));
+  launch_tsqr<T>(W, N, m, Rfac, w, s);
+  return check_launch(c, "tsqr");
 }
 
 // Upload an N x m FP64 host block into device type T (through a staging buffer).
@@ -1227,12 +1139,12 @@ kp_status gkb_run(kp_ctx* c, const RmatOp<T>& op, const kp_gkb_opts* o, kp_facto
 
 // ---------------------------------------------------------------------------
 // RSVD (Algorithm 2): Y = orth(B F); q times Z = orth(B^T Y), Y = orth(B Z);
-// H^T = B^T Y = Q_h R_h (CGS2 QR), R_h^T = U_r S V_r^T (Jacobi), so
+// H^T = B^T Y = Q_h R_h (Householder TSQR), R_h^T = U_r S V_r^T (Jacobi), so
 // H = U_r S (Q_h V_r)^T: U_k = Y U_r[:, :k], V_k = Q_h V_r[:, :k].
 // With KP_BF16 / KP_F16 every product with B runs on the 16-bit kernel (vectors
 // stay FP32). The optional refinement reorthogonalizes V_k once more, forms
-// W = B V_k with the FP32 (FP64) kernel and takes the SVD of W through its CGS2
-// QR: W = Q_w R_w, R_w = U_w S Z^T, so the triplets become (Q_w U_w, S, V_k Z)
+// W = B V_k with the FP32 (FP64) kernel and takes the SVD of W through its QR:
+// W = Q_w R_w, R_w = U_w S Z^T, so the triplets become (Q_w U_w, S, V_k Z)
 // (one-sided Rayleigh-Ritz on range(V_k)).
 template <typename T>
 kp_status rsvd_impl(kp_ctx* c, const RmatOp<T>& op, const kp_rsvd_opts* o, kp_factors* f,
@@ -1255,8 +1167,6 @@ kp_status rsvd_impl(kp_ctx* c, const RmatOp<T>& op, const kp_rsvd_opts* o, kp_fa
     }
     return op.block(c, tr, X, Yo, nc, s);
   };
-  Scratch sc;
-  KP_TRY(get_scratch(c, &sc));
   T *Y = nullptr, *Z = nullptr;
   KP_TRY(wsT(c, std::string("rsvdY_") + tname<T>(), (size_t)N * kp, &Y));
   KP_TRY(wsT(c, std::string("rsvdZ_") + tname<T>(), (size_t)N * kp, &Z));
@@ -1266,15 +1176,15 @@ kp_status rsvd_impl(kp_ctx* c, const RmatOp<T>& op, const kp_rsvd_opts* o, kp_fa
     for (int col = 0; col < kp; ++col)
       launch_philox_normals<T>(Z + N * col, N, o->seed, 0x40000000u + (uint32_t)col, s);
   }
-  uint32_t sb = 0x20000000u;   // Philox streams of replaced dependent columns
+  auto qr = [&](T* Wb, int mm, double* Rf) { return tsqr_qr<T>(c, Wb, N, mm, Rf, s); };
   KP_TRY(prod(0, Z, Y, kp));
-  KP_TRY(cgs_qr<T>(c, sc, Y, N, kp, nullptr, o->seed, sb, s));
+  KP_TRY(qr(Y, kp, nullptr));
   for (int it = 0; it < o->q; ++it) {
     KP_TRY(check_cancel(c));
     KP_TRY(prod(1, Y, Z, kp));
-    KP_TRY(cgs_qr<T>(c, sc, Z, N, kp, nullptr, o->seed, sb += 64, s));
+    KP_TRY(qr(Z, kp, nullptr));
     KP_TRY(prod(0, Z, Y, kp));
-    KP_TRY(cgs_qr<T>(c, sc, Y, N, kp, nullptr, o->seed, sb += 64, s));
+    KP_TRY(qr(Y, kp, nullptr));
   }
   if (f->diag && f->diag->basis_u)
     KP_HIP(c, hipMemcpyAsync(f->diag->basis_u, Y, sizeof(T) * N * kp, hipMemcpyDeviceToDevice, s));
@@ -1288,7 +1198,7 @@ kp_status rsvd_impl(kp_ctx* c, const RmatOp<T>& op, const kp_rsvd_opts* o, kp_fa
   KP_TRY(wsT(c, "smallS", 64, &sig));
   KP_TRY(wsT(c, "smallV", 64 * 64, &Vr));
   KP_TRY(wsT(c, "sweeps", 4, &sweeps));
-  KP_TRY(cgs_qr<T>(c, sc, Z, N, kp, Rh, o->seed, sb += 64, s));
+  KP_TRY(qr(Z, kp, Rh));
   launch_transpose_small(Rh, kp, kp, RhT, s);
   launch_jacobi_svd(RhT, kp, kp, Ur, sig, Vr, sweeps, s);
   KP_TRY(check_launch(c, "jacobi_svd"));
@@ -1303,14 +1213,14 @@ kp_status rsvd_impl(kp_ctx* c, const RmatOp<T>& op, const kp_rsvd_opts* o, kp_fa
     T* Vf = Y;   // N x kout, reuses the sketch buffers
     T* W = Z;
     launch_convert<double, T>(Vd, Vf, N * kout, s);
-    KP_TRY(cgs_qr<T>(c, sc, Vf, N, kout, nullptr, o->seed, sb += 64, s));
+    KP_TRY(qr(Vf, kout, nullptr));
     if constexpr (std::is_same<T, float>::value) {
       if (o->refine == 2 && b) KP_TRY(split16_product(c, b, op.dpsf, n, Vf, W, kout, s));
       else KP_TRY(op.block(c, 0, Vf, W, kout, s));
     } else {
       KP_TRY(op.block(c, 0, Vf, W, kout, s));
     }
-    KP_TRY(cgs_qr<T>(c, sc, W, N, kout, Rh, o->seed, sb += 64, s));
+    KP_TRY(qr(W, kout, Rh));
     launch_jacobi_svd(Rh, kout, kout, Ur, sig, Vr, sweeps, s);
     launch_small_gemm<T, double>(W, N, kout, Ur, kout, kout, N, Ud, N, s);
     launch_small_gemm<T, double>(Vf, N, kout, Vr, kout, kout, N, Vd, N, s);
@@ -1467,10 +1377,16 @@ kp_status sb_solve_impl(kp_ctx* c, SbOp& op, const double* b, const sb_opts* o, 
     hipStream_t cs = nullptr;
     KP_HIP(c, hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
     hipGraph_t gr = nullptr;
-    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
-    if (e == hipSuccess) {
-      for (int i = 0; i < poll; ++i) cgls_iteration(cs);
-      e = hipStreamEndCapture(cs, &gr);
+    hipError_t e;
+    {
+      std::shared_lock<std::shared_mutex> cap(capture_mutex());
+      t_capturing = true;
+      e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+      if (e == hipSuccess) {
+        for (int i = 0; i < poll; ++i) cgls_iteration(cs);
+        e = hipStreamEndCapture(cs, &gr);
+      }
+      t_capturing = false;
     }
     if (e == hipSuccess) e = hipGraphInstantiate(&chunk, gr, nullptr, nullptr, 0);
     if (gr) (void)hipGraphDestroy(gr);
@@ -1598,6 +1514,11 @@ bool tuned_block_shape(kp_ctx* c, int n, BlockPlan* shape) {
   return true;
 }
 
+std::shared_mutex& capture_mutex() {
+  static std::shared_mutex m;
+  return m;
+}
+
 size_t ctx_held(const kp_ctx* c) {
   size_t h = 0;
   for (auto& kv : c->bufs) h += kv.second.bytes;
@@ -1606,13 +1527,16 @@ size_t ctx_held(const kp_ctx* c) {
 
 void ctx_trim(kp_ctx* c) {
   (void)hipSetDevice(c->device);
-  (void)hipDeviceSynchronize();
   size_t freed = 0;
-  for (auto& kv : c->bufs)
-    if (kv.second.p) {
-      (void)hipFree(kv.second.p);
-      freed += kv.second.bytes;
-    }
+  {
+    std::unique_lock<std::shared_mutex> nocap(capture_mutex());
+    (void)hipDeviceSynchronize();
+    for (auto& kv : c->bufs)
+      if (kv.second.p) {
+        (void)hipFree(kv.second.p);
+        freed += kv.second.bytes;
+      }
+  }
   c->bufs.clear();
   std::lock_guard<std::mutex> lk(c->pool->m);
   c->pool->used -= freed;
@@ -1622,6 +1546,7 @@ void ctx_free(kp_ctx* c) {
   for (kp_ctx* w : c->workers) ctx_free(w);
   c->workers.clear();
   ctx_trim(c);
+  std::unique_lock<std::shared_mutex> nocap(capture_mutex());
   if (c->pinned) (void)hipHostFree(c->pinned);
   for (auto& r : c->recs) {
     (void)hipEventDestroy(r.a);
@@ -1709,7 +1634,10 @@ void prof_collect(kp_ctx* c, kp_ctx* into) {
 kp_status kp_prof_read(kp_ctx* c, kp_prof* out, int reset) {
   if (!c || !out) return KP_E_INVAL;
   KP_HIP(c, hipSetDevice(c->device));
-  KP_HIP(c, hipDeviceSynchronize());
+  {
+    std::unique_lock<std::shared_mutex> nocap(capture_mutex());
+    KP_HIP(c, hipDeviceSynchronize());
+  }
   prof_collect(c, c);
   for (kp_ctx* w : c->workers) prof_collect(w, c);
   for (int i = 0; i < 4; ++i) {

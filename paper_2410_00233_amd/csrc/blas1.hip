@@ -287,20 +287,11 @@ static void project_out_any(T* w, const T* V, long ldv, int m, const double* h,
                        h, partials, h_out, h_add, N, nrm_partials, pred);
 }
 template <typename T>
-void launch_project_out(T* w, const T* V, long ldv, int m, const double* h, long N,
-                        double* nrm_partials, hipStream_t s, const int* pred) {
-  project_out_any<T>(w, V, ldv, m, h, nullptr, nullptr, nullptr, N, nrm_partials, s, pred);
-}
-template <typename T>
 void launch_project_out_red(T* w, const T* V, long ldv, int m, const double* partials,
                             double* h_out, double* h_add, long N, double* nrm_partials,
                             hipStream_t s, const int* pred) {
   project_out_any<T>(w, V, ldv, m, nullptr, partials, h_out, h_add, N, nrm_partials, s, pred);
 }
-template void launch_project_out<float>(float*, const float*, long, int, const double*, long,
-                                        double*, hipStream_t, const int*);
-template void launch_project_out<double>(double*, const double*, long, int, const double*,
-                                         long, double*, hipStream_t, const int*);
 template void launch_project_out_red<float>(float*, const float*, long, int, const double*,
                                             double*, double*, long, double*, hipStream_t,
                                             const int*);
@@ -353,90 +344,6 @@ void launch_norm2_partials(const T* w, long N, double* nrm_partials, hipStream_t
 }
 template void launch_norm2_partials<float>(const float*, long, double*, hipStream_t);
 template void launch_norm2_partials<double>(const double*, long, double*, hipStream_t);
-
-// ---------------------------------------------------------------------------
-// w /= ||w|| with ||w||^2 = sum of nrm_partials; block 0 stores ||w|| in
-// *norm_out and, with flag_out, *flag_out = (||w|| < thr). With fx.rcol (the
-// third Gram-Schmidt pass of a QR column, ||w|| = r3 < thr meaning the column
-// is replaced) block 0 also folds a kept column's third pass into R:
-// rcol[i] += rjj h3[i] (i < m), then rjj *= r3. A zero vector is left
-// unchanged (and reports norm 0).
-template <typename T>
-__global__ void __launch_bounds__(256)
-normalize_kernel(T* __restrict__ w, long N, const double* __restrict__ nrm_partials,
-                 double* __restrict__ norm_out, const int* __restrict__ pred,
-                 int* __restrict__ flag_out, double thr, QrFixup fx) {
-  if (pred && *pred == 0) return;
-  __shared__ double sh[8];
-  const double nrm = sqrt(reduce_partials_block(nrm_partials, 1, 0, sh));
-  if (blockIdx.x == 0) {
-    if (threadIdx.x == 0) {
-      if (norm_out) *norm_out = nrm;
-      if (flag_out) *flag_out = nrm < thr ? 1 : 0;
-    }
-    if (fx.rcol && !(nrm < thr)) {
-      const double r = *fx.rjj;
-      if ((int)threadIdx.x < fx.m) fx.rcol[threadIdx.x] += r * fx.h3[threadIdx.x];
-      __syncthreads();
-      if (threadIdx.x == 0) *fx.rjj = r * nrm;
-    }
-  }
-  if (nrm == 0.0) return;
-  const double inv = 1.0 / nrm;
-  long lo, hi;
-  row_range(N, &lo, &hi);
-  for (long r = lo + threadIdx.x; r < hi; r += 256) w[r] = (T)((double)w[r] * inv);
-}
-
-template <typename T>
-__global__ void __launch_bounds__(256)
-normalize_vec_kernel(T* __restrict__ w, long N, const double* __restrict__ nrm_partials,
-                     double* __restrict__ norm_out, const int* __restrict__ pred,
-                     int* __restrict__ flag_out, double thr, QrFixup fx) {
-  if (pred && *pred == 0) return;
-  constexpr int VEC = Vec16<T>::VEC;
-  typedef typename Vec16<T>::type vec_t;
-  __shared__ double sh[8];
-  const double nrm = sqrt(reduce_partials_block(nrm_partials, 1, 0, sh));
-  if (blockIdx.x == 0) {
-    if (threadIdx.x == 0) {
-      if (norm_out) *norm_out = nrm;
-      if (flag_out) *flag_out = nrm < thr ? 1 : 0;
-    }
-    if (fx.rcol && !(nrm < thr)) {
-      const double r = *fx.rjj;
-      if ((int)threadIdx.x < fx.m) fx.rcol[threadIdx.x] += r * fx.h3[threadIdx.x];
-      __syncthreads();
-      if (threadIdx.x == 0) *fx.rjj = r * nrm;
-    }
-  }
-  if (nrm == 0.0) return;
-  const double inv = 1.0 / nrm;
-  long lo, hi;
-  row_range_vec(N, VEC, &lo, &hi);
-  for (long r = lo + (long)VEC * threadIdx.x; r < hi; r += 256L * VEC) {
-    vec_t v = *reinterpret_cast<const vec_t*>(w + r);
-#pragma unroll
-    for (int u = 0; u < VEC; ++u) v[u] = (T)((double)v[u] * inv);
-    *reinterpret_cast<vec_t*>(w + r) = v;
-  }
-}
-
-template <typename T>
-void launch_normalize(T* w, long N, const double* nrm_partials, double* norm_out,
-                      hipStream_t s, const int* pred, int* flag_out, double thr,
-                      const QrFixup& fx) {
-  if (vec_ok<T>(N, 0, w, w))
-    hipLaunchKernelGGL(normalize_vec_kernel<T>, dim3(kRedBlocks), dim3(256), 0, s, w, N,
-                       nrm_partials, norm_out, pred, flag_out, thr, fx);
-  else
-    hipLaunchKernelGGL(normalize_kernel<T>, dim3(kRedBlocks), dim3(256), 0, s, w, N,
-                       nrm_partials, norm_out, pred, flag_out, thr, fx);
-}
-template void launch_normalize<float>(float*, long, const double*, double*, hipStream_t,
-                                      const int*, int*, double, const QrFixup&);
-template void launch_normalize<double>(double*, long, const double*, double*, hipStream_t,
-                                       const int*, int*, double, const QrFixup&);
 
 // ---------------------------------------------------------------------------
 template <typename T>

@@ -208,13 +208,10 @@ void launch_multidot(const T* V, long ldv, int m, const T* w, long N, double* pa
 // h[i] (+)= sum_b partials[b*m + i]; if accumulate != 0 adds into h
 void launch_reduce_partials(const double* partials, int m, double* h, int accumulate,
                             hipStream_t s, const int* pred = nullptr);
-// w -= V h (m columns); nrm_partials[b] = block partial of ||w_new||^2
-template <typename T>
-void launch_project_out(T* w, const T* V, long ldv, int m, const double* h, long N,
-                        double* nrm_partials, hipStream_t s, const int* pred = nullptr);
-// the same with h = the sums of the launch_multidot partials (layout [block][m]),
-// formed in every block; block 0 stores h in h_out and/or adds it into h_add
-// (either may be NULL). Replaces a reduce_partials launch before the projection.
+// w -= V h (m columns) with h = the sums of the launch_multidot partials
+// (layout [block][m]), formed in every block; block 0 stores h in h_out and/or
+// adds it into h_add (either may be NULL). Replaces a reduce_partials launch
+// before the projection.
 template <typename T>
 void launch_project_out_red(T* w, const T* V, long ldv, int m, const double* partials,
                             double* h_out, double* h_add, long N, double* nrm_partials,
@@ -222,22 +219,6 @@ void launch_project_out_red(T* w, const T* V, long ldv, int m, const double* par
 // nrm_partials[b] = block partial of ||w||^2
 template <typename T>
 void launch_norm2_partials(const T* w, long N, double* nrm_partials, hipStream_t s);
-// Normalize w by the norm reduced from nrm_partials; *norm_out = ||w||
-// (written by block 0; may be null) and, with flag_out, *flag_out =
-// (||w|| < thr) (block 0). A zero vector is left unchanged.
-// With fx.rcol != NULL (third pass of a Gram-Schmidt QR column, the norm being
-// r3): unless r3 < thr, block 0 adds rjj h3 into rcol (m entries) and scales
-// rjj by r3.
-struct QrFixup {
-  double* rcol = nullptr;
-  int m = 0;
-  const double* h3 = nullptr;
-  double* rjj = nullptr;
-};
-template <typename T>
-void launch_normalize(T* w, long N, const double* nrm_partials, double* norm_out,
-                      hipStream_t s, const int* pred = nullptr, int* flag_out = nullptr,
-                      double thr = 0.0, const QrFixup& fx = QrFixup());
 template <typename T>
 void launch_scale(T* w, long N, double factor, hipStream_t s);
 // out[e] = Philox normal number e of (seed, stream)
@@ -253,6 +234,13 @@ void launch_small_gemm(const T* V, long ldv, int m, const double* C, int ldc, in
 
 // ---- single-workgroup helpers (smallops.hip) ---------------------------------
 void launch_transpose_small(const double* in, int m, int nc, double* out, hipStream_t s);
+// Householder TSQR of a tall N x m block (tsqr.hip): W <- Q with orthonormal
+// columns and, if Rfac != NULL, Rfac <- R (m x m column-major, non-negative
+// diagonal), W = Q R. Needs 1 <= m <= 64 and N >= m (else returns false and
+// launches nothing); ws holds tsqr_workspace_bytes(N, m) bytes.
+size_t tsqr_workspace_bytes(long N, int m);
+template <typename T>
+bool launch_tsqr(T* W, long N, int m, double* Rfac, void* ws, hipStream_t s);
 void launch_fill_small(double* p, int m, double v, hipStream_t s);
 void launch_fill(double* p, long n, double v, hipStream_t s);
 void launch_fill_int(int* p, int n, int v, hipStream_t s);

@@ -7,6 +7,7 @@
 #include <map>
 #include <memory>
 #include <mutex>
+#include <shared_mutex>
 #include <string>
 #include <vector>
 
@@ -69,6 +70,12 @@ struct kp_ctx {
 };
 
 namespace kpsb {
+
+// HIP refuses calls that synchronize the whole device (hipDeviceSynchronize,
+// hipFree) while any stream of the process is capturing a graph, whatever the
+// capture mode. Graph captures hold this lock shared; code that frees device
+// memory or synchronizes the device holds it exclusively.
+std::shared_mutex& capture_mutex();
 
 // Creates a context bound to `device` that charges `pool` (the parent's, or a
 // new one when pool is empty). Returns nullptr on a device error.

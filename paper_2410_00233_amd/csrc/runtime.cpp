@@ -186,6 +186,7 @@ void batch_launch_locked(kp_batch* b) {
   if (b->err == KP_OK && nj > b->djobs_cap) {
     if (b->djobs) {
       (void)hipStreamSynchronize(b->stream);
+      std::unique_lock<std::shared_mutex> nocap(capture_mutex());
       (void)hipFree(b->djobs);
       b->djobs = nullptr;
     }
@@ -351,7 +352,7 @@ size_t svd_bytes(const kp_request& r) {
       b += round256(x16 * kp * 2);            // 16-bit copy of the product's input
     }
     b += 2 * round256(N * kp * es);           // sketch / range bases Y, Z
-    b += round256(N * kp * es);               // CGS2 QR's copy of the columns
+    b += round256(tsqr_workspace_bytes((long)N, kp));   // the QR's reflectors and R factors
     b += 2 * round256(N * (size_t)r.k_cap * 8);
     if (terms > 1) b += 4 * round256(N * kp * es);
     if (r.rsvd.F) b += round256(N * kp * 8);
@@ -511,8 +512,11 @@ bool evict_one_locked(kp_server* s) {
       victim = it;
   if (victim == s->cache.end()) return false;
   (void)hipSetDevice(s->ctx->device);
-  (void)hipFree(victim->second.Ax);
-  (void)hipFree(victim->second.Ay);
+  {
+    std::unique_lock<std::shared_mutex> nocap(capture_mutex());
+    (void)hipFree(victim->second.Ax);
+    (void)hipFree(victim->second.Ay);
+  }
   s->cache_bytes -= victim->second.bytes;
   {
     std::lock_guard<std::mutex> lk(s->pool->m);
@@ -757,8 +761,11 @@ void worker_loop(kp_server* s, int w) {
     (void)hipStreamSynchronize(wc->own_stream);
     gate_leave(s, excl);
     if (!to_free.empty()) {
-      for (void* p : to_free)
-        if (p) (void)hipFree(p);
+      {
+        std::unique_lock<std::shared_mutex> nocap(capture_mutex());
+        for (void* p : to_free)
+          if (p) (void)hipFree(p);
+      }
       std::lock_guard<std::mutex> lp(s->pool->m);
       s->pool->used -= unpool;
     }
@@ -932,8 +939,11 @@ kp_status kp_svd_batched(kp_ctx* c, int32_t nprob, const kp_blur* blurs, const i
         (void)hipEventRecord(lock_done, b.stream);
     }
     if (b.stream) (void)hipStreamSynchronize(b.stream);
-    if (b.djobs) (void)hipFree(b.djobs);
-    if (b.counter) (void)hipFree(b.counter);
+    {
+      std::unique_lock<std::shared_mutex> nocap(capture_mutex());
+      if (b.djobs) (void)hipFree(b.djobs);
+      if (b.counter) (void)hipFree(b.counter);
+    }
     if (b.done) (void)hipEventDestroy(b.done);
     if (b.stream) (void)hipStreamDestroy(b.stream);
     c->batch_launches = b.launches;
@@ -1204,10 +1214,13 @@ kp_status kp_server_destroy(kp_server* s) {
   s->cv_work.notify_all();
   for (auto& t : s->threads) t.join();
   (void)hipSetDevice(s->ctx->device);
-  (void)hipDeviceSynchronize();
-  for (auto& kv : s->cache) {
-    if (kv.second.Ax) (void)hipFree(kv.second.Ax);
-    if (kv.second.Ay) (void)hipFree(kv.second.Ay);
+  {
+    std::unique_lock<std::shared_mutex> nocap(capture_mutex());
+    (void)hipDeviceSynchronize();
+    for (auto& kv : s->cache) {
+      if (kv.second.Ax) (void)hipFree(kv.second.Ax);
+      if (kv.second.Ay) (void)hipFree(kv.second.Ay);
+    }
   }
   for (kp_ctx* w : s->workers) ctx_free(w);
   delete s;

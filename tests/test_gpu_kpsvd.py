@@ -269,21 +269,35 @@ def test_rsvd_refine_with_split_fp16_product(ctx, prec, n, psf):
     assert d12 <= 1e-6
 
 
-@pytest.mark.parametrize("n,psf,prec", [(64, "disk", "f32"), (48, "disk", "f64"),
-                                        (128, "gaussian", "f32")])
-def test_rsvd_qr_chunks_match_predicated_sequence(ctx, n, psf, prec, monkeypatch):
-    """The QR that first runs its columns without the replacement kernels and
-    restarts at the first dependent column gives the same bits as the
-    predicated sequence from column 0 (the disk PSF has Kronecker rank 6, so
-    columns 7.. of its sketches are replaced)."""
+@pytest.mark.parametrize("n,psf,prec", [(64, "gaussian", "f64"), (64, "gaussian", "f32"),
+                                        (417, "gaussian", "f32"), (128, "disk", "f64"),
+                                        (128, "disk", "f32"), (96, "separable", "f64"),
+                                        (33, "gaussian", "f64")])
+def test_rsvd_range_basis_is_orthonormal(ctx, n, psf, prec):
+    """The range finder's QR (Householder TSQR: leaves of at most 512 rows, a
+    tree of stacked R factors, Q formed from the root down) returns an
+    orthonormal basis whatever the rank: n = 417 has ragged leaves, the disk
+    PSF has Kronecker rank 6 < k + p = 30, the separable PSF rank 1 (its sigma_1
+    in closed form), n = 33 a single leaf."""
     import torch
     from paper_2410_00233_amd import api
-    P, cu, cv = wl.disk_psf(n) if psf == "disk" else wl.gaussian_psf(n)
-    blur = api.Blur(P, cu, cv, n)
-    F = wl.gaussian_block(n * n, 30, seed=wl.SEED_START + 5)
-    f1 = ctx.kp_svd_rsvd(blur, 20, 10, 2, prec=prec, F=F, refine=1 if prec == "f32" else 0)
-    monkeypatch.setenv("KPSB_CGS_EAGER", "1")
-    f2 = ctx.kp_svd_rsvd(blur, 20, 10, 2, prec=prec, F=F, refine=1 if prec == "f32" else 0)
-    monkeypatch.delenv("KPSB_CGS_EAGER")
-    assert np.array_equal(f1.sigma[:f1.k], f2.sigma[:f2.k])
-    assert torch.equal(f1.Ax[:f1.k], f2.Ax[:f2.k]) and torch.equal(f1.Ay[:f1.k], f2.Ay[:f2.k])
+    if psf == "separable":
+        a = np.exp(-0.5 * (np.arange(-(n - 1), n) / 2.0) ** 2)
+        c = np.exp(-0.5 * (np.arange(-(n - 1), n) / 1.3) ** 2)
+        P, cu, cv = wl.separable_psf(a / a.sum(), c / c.sum())
+    else:
+        P, cu, cv = wl.disk_psf(n) if psf == "disk" else wl.gaussian_psf(n)
+    k, p = 20, 10
+    f = ctx.kp_svd_rsvd(api.Blur(P, cu, cv, n), k, p, 2, prec=prec, seed=11, bases=True)
+    Y = f.Y.double().cpu().numpy().T                  # N x (k + p)
+    G = Y.T @ Y
+    orth = np.abs(G - np.eye(k + p)).max()
+    print(f"TSQR {prec} n={n} {psf}: max|Y^T Y - I| = {orth:.2e}")
+    assert orth <= (1e-13 if prec == "f64" else 1e-6)
+    if psf == "separable":
+        # R(A) of a separable PSF P = a c^T has rank 1 (c.4 of the pins)
+        s1 = np.sqrt(sum((n - abs(d)) * a[d + n - 1] ** 2 for d in range(-(n - 1), n))) * \
+            np.sqrt(sum((n - abs(d)) * c[d + n - 1] ** 2 for d in range(-(n - 1), n)))
+        s1 /= a.sum() * c.sum()
+        assert abs(f.sigma[0] - s1) <= 1e-12 * s1
+        assert np.all(np.abs(f.sigma[1:f.k]) <= 1e-12 * s1)
