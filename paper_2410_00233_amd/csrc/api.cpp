@@ -526,12 +526,14 @@ kp_status split16_product(kp_ctx* c, const kp_blur* b, const double* dpsf, int n
       KP_TRY(choose_block16_plan<__half>(c, gg, n, Xhi, ld16, out, std::min(ncols, 32), s, &bp));
       planned = true;
     }
+    // only the main term needs the FP64 fold: the two correction terms are
+    // 2^-11 of it, so their FP32 accumulation error is that much smaller too
     for (int c0 = 0; c0 < ncols; c0 += 32) {
       const int nc = ncols - c0 < 32 ? ncols - c0 : 32;
       float* Wc = out + N * c0;
       launch_rmat_block16<__half>(bp, Ghi, ldg, n, Xhi + ld16 * c0, ld16, Wc, N, nc, s, scal + 1, 0, true);
-      launch_rmat_block16<__half>(bp, Ghi, ldg, n, Xlo + ld16 * c0, ld16, Wc, N, nc, s, scal + 1, 1, true);
-      launch_rmat_block16<__half>(bp, Glo, ldg, n, Xhi + ld16 * c0, ld16, Wc, N, nc, s, scal + 1, 1, true);
+      launch_rmat_block16<__half>(bp, Ghi, ldg, n, Xlo + ld16 * c0, ld16, Wc, N, nc, s, scal + 1, 1, false);
+      launch_rmat_block16<__half>(bp, Glo, ldg, n, Xhi + ld16 * c0, ld16, Wc, N, nc, s, scal + 1, 1, false);
     }
     return check_launch(c, "split16_product");
   });
