@@ -301,3 +301,24 @@ def test_rsvd_range_basis_is_orthonormal(ctx, n, psf, prec):
         s1 /= a.sum() * c.sum()
         assert abs(f.sigma[0] - s1) <= 1e-12 * s1
         assert np.all(np.abs(f.sigma[1:f.k]) <= 1e-12 * s1)
+
+
+@pytest.mark.parametrize("k,p,prec", [(54, 10, "f64"), (40, 10, "f32"), (1, 1, "f64"), (12, 4, "f32")])
+def test_rsvd_range_basis_widths(ctx, k, p, prec):
+    """The TSQR's shapes by block width: k + p = 64 (4 columns per wave, leaves of
+    about 250 rows, a fan of 3: a deeper tree), 50, 2 and 16 (one column per
+    wave, leaves of up to 1024 rows); the basis is orthonormal and the leading
+    sigma match the same-algorithm FP64 oracle."""
+    from paper_2410_00233_amd import api
+    n = 64
+    P, cu, cv = wl.gaussian_psf(n)
+    F = wl.gaussian_block(n * n, k + p, seed=wl.SEED_START + 7)
+    f = ctx.kp_svd_rsvd(api.Blur(P, cu, cv, n), k, p, 1, prec=prec, F=F, bases=True)
+    Y = f.Y.double().cpu().numpy().T
+    orth = np.abs(Y.T @ Y - np.eye(k + p)).max()
+    R, Rt = _ops(P, cu, cv, n)
+    ref = kpsvd.rsvd(R, Rt, F, k, 1)
+    err = np.abs(f.sigma[:k] - ref["sigma"]).max() / ref["sigma"][0]
+    print(f"TSQR width {k + p} {prec}: max|Y^T Y - I| = {orth:.2e}, sigma err {err:.2e}")
+    assert orth <= (1e-13 if prec == "f64" else 1e-6)
+    assert err <= (1e-12 if prec == "f64" else 1e-5)
