@@ -31,6 +31,7 @@ exact optimum.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
        python bench.py --profile-products   (the rocprofv3 counter workload)
+       python bench.py --profile-qr         (the same for the Householder TSQR)
 """
 from __future__ import annotations
 
@@ -540,6 +541,27 @@ def nonzero_fractions(P, cu, cv, n):
     return {"rows": round(rows, 5), "cols": round(cols, 5), "entries": round(ents, 6)}
 
 
+def profile_qr():
+    """Workload of the rocprofv3 counter pass over the Householder TSQR: two FP32
+    RSVDs (p = 10, q = 2, rank 20) at n = 512 on the rotated Gaussian PSF, each
+    with five 262144 x 30 QRs (the first RSVD also runs the autotuner's
+    samples of the block products)."""
+    import torch
+
+    import workloads as wl
+    from paper_2410_00233_amd import api
+    n = 512
+    ctx = api.Context(0)
+    P, cu, cv = wl.gaussian_psf(n)
+    blur = api.Blur(P, cu, cv, n, on_device=True)
+    for _ in range(2):
+        ctx.kp_svd_rsvd(blur, 20, 10, 2, prec="f32", seed=2)
+    torch.cuda.synchronize()
+    ctx.close()
+    print("done", flush=True)
+    return 0
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -569,6 +591,9 @@ def main():
                          "(a copy of known size for calibration, the n=512 FP32 / BF16 block "
                          "and FP32 matrix-vector products, the n=256 Kronecker apply and a few "
                          "CGLS iterations) and exit")
+    ap.add_argument("--profile-qr", action="store_true",
+                    help="only run two FP32 RSVDs at n=512 (the workload of the TSQR "
+                         "counter pass) and exit")
     ap.add_argument("--gkb-block", type=int, default=16,
                     help="block size b of the timed block Golub-Kahan run (16: one MFMA "
                          "column block, so no padded columns; k_p = b ceil(40 / b))")
@@ -577,6 +602,8 @@ def main():
     args = ap.parse_args()
     if args.profile_products:
         sys.exit(profile_products())
+    if args.profile_qr:
+        sys.exit(profile_qr())
     if args.gpus != 1:
         print("bench.py measures one GPU only: the KP-SVD path is built and timed on a single "
               "MI355X (multi-GPU sharding is designed but not built); run with --gpus 1.", file=sys.stderr)
