@@ -90,12 +90,19 @@ size_t tsqr_workspace_bytes(long N, int m) {
 }
 
 // v + DPP(v) on both 32-bit halves of a double; lanes the control leaves out
-// (row_mask) add 0
+// (row_mask) add 0. With every row enabled no lane is left out, so the move
+// needs no zeroed destination.
 template <int CTRL, int ROWS>
 __device__ __forceinline__ double tsqr_dpp_add(double v) {
   const long long b = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffff), CTRL, ROWS, 0xf, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROWS, 0xf, false);
+  int lo, hi;
+  if constexpr (ROWS == 0xf) {
+    lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffff), CTRL, 0xf, 0xf, false);
+    hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xf, 0xf, false);
+  } else {
+    lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffff), CTRL, ROWS, 0xf, false);
+    hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROWS, 0xf, false);
+  }
   return v + __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
@@ -156,8 +163,12 @@ __device__ void tsqr_factor_node(double (&x)[CPW][kTsqrRegs / CPW], int rows, in
         if (ss > 0.0) {
           const double nrm = sqrt(alpha * alpha + ss);
           beta = alpha >= 0.0 ? -nrm : nrm;
-          tj = (beta - alpha) / beta;
-          scale = 1.0 / (alpha - beta);
+          // tau = (beta - alpha) / beta, scale = 1 / (alpha - beta), from one
+          // reciprocal (the step's critical path)
+          const double d = beta - alpha;
+          const double r = 1.0 / (beta * d);
+          tj = d * d * r;
+          scale = -beta * r;
         }
 #pragma unroll
         for (int t = 0; t < RPL; ++t) {
