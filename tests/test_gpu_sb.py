@@ -198,3 +198,30 @@ def test_sb_batched_reports_each_problem(ctx):
     assert b"problem 1" in ctx.lib.kp_last_error(ctx.h)
     assert st[0].l_end == 3 and st[2].l_end == 3
     assert ctx.lib.sb_solve_batched(ctx.h, 1, arr, st, status, 17, None) == L.KP_E_INVAL
+
+
+def test_sb_batched_with_untuned_sizes_equals_single_calls(ctx):
+    """Sizes and ranks seen for the first time: the batch runs them first, one
+    at a time (their Kronecker-apply launch shapes are tuned then, without
+    other solves sharing the GPU), then the rest concurrently; each image
+    equals the single call made afterwards, bit for bit."""
+    from paper_2410_00233_amd import api
+    import torch
+    specs = [(88, 9, "iso"), (104, 11, "aniso"), (88, 9, "aniso"), (56, 13, "iso")]
+    lam = 0.115
+    probs, raw = [], []
+    for i, (n, k, kind) in enumerate(specs):
+        Ax, Ay, b, _ = _problem(n, k, idx=10 + i)
+        f = api.Factors.from_arrays(Ax, Ay)
+        probs.append(dict(f=f, b=_dev(b), iso=kind == "iso", lam=lam, beta=lam * lam / 2.0,
+                          L_max=3, I_max=10))
+        raw.append((f, b, kind))
+    xs, stats, status = ctx.sb_solve_batched(probs, nworkers=4)
+    torch.cuda.synchronize()
+    assert status == [0] * len(specs)
+    for (f, b, kind), xb, sb_st in zip(raw, xs, stats):
+        fn = ctx.sb_solve_iso if kind == "iso" else ctx.sb_solve_aniso
+        x1, s1 = fn(f, _dev(b), lam, lam * lam / 2.0, L_max=3, I_max=10)
+        torch.cuda.synchronize()
+        assert torch.equal(xb, x1)
+        assert sb_st["iota_total"] == s1["iota_total"] and sb_st["rc_sb"] == s1["rc_sb"]
