@@ -704,7 +704,7 @@ def main():
     compg_ms = float(np.median(tcg))
     compg_same = bool(np.array_equal(fgc.sigma[:k], fg.sigma[:k]))
 
-    log("BF16 + refinement RSVD")
+    log("BF16 + refinement RSVD; split-FP16 (f16x3) RSVD")
     # the reduced-precision variant: RSVD with BF16 block products + refinement
     # (refine = 2: the refinement product from split FP16 MFMA products; the
     # refine = 1 variant with an FP32 product is timed beside it)
@@ -724,6 +724,15 @@ def main():
         ta = time.perf_counter()
         fb1 = ctx.kp_svd_rsvd(blur, k, p_rsvd, q, prec="bf16", refine=1, seed=2, factor_prec="f64")
         tb1.append(1e3 * (time.perf_counter() - ta))
+    # every product with R or R^T as three FP16 MFMA products of two-term splits
+    ctx.kp_svd_rsvd(blur, k, p_rsvd, q, prec="f16x3", seed=2, factor_prec="f64")
+    t3 = []
+    for _ in range(args.steps):
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        f3 = ctx.kp_svd_rsvd(blur, k, p_rsvd, q, prec="f16x3", seed=2, factor_prec="f64")
+        torch.cuda.synchronize()
+        t3.append(1e3 * (time.perf_counter() - ta))
     cases = []
 
     def case(name, blur_, f, method, seed, refine=0, prec="f32", gate=1e-5, pp=None):
@@ -737,6 +746,7 @@ def main():
     case("gaussian_egkb_fp32", blur, fg, "gkb", 1)
     case("gaussian_rsvd_fp32", blur, fr, "rsvd", 2)
     case("gaussian_rsvd_bf16_refine", blur, fb, "rsvd", 2, refine=2, prec="bf16", gate=1e-4)
+    case("gaussian_rsvd_f16x3", blur, f3, "rsvd", 2, prec="f16x3")
     b16 = prof16["block16"]
     avg16 = b16["ms"] / max(b16["launches"], 1)
     ach16 = (b16["flops"] / max(b16["launches"], 1)) / (avg16 * 1e-3) / 1e12
@@ -744,6 +754,8 @@ def main():
     bf1_ms = float(np.median(tb1))
     sig_diff = float(np.abs(fb.sigma[:k] - fr.sigma[:k]).max() / fr.sigma[0])
     sig_diff1 = float(np.abs(fb1.sigma[:k] - fr.sigma[:k]).max() / fr.sigma[0])
+    f3_ms = float(np.median(t3))
+    sig_diff3 = float(np.abs(f3.sigma[:k] - fr.sigma[:k]).max() / fr.sigma[0])
 
     log("defocus disk r=8 at n=512 (FP32 EGKB and RSVD, BF16 + refinement RSVD)")
     Pd, cud, cvd = wl.disk_psf(n, 8.0)
@@ -780,6 +792,9 @@ def main():
     case("speckle_rsvd_bf16_refine", blur_sp,
          ctx.kp_svd_rsvd(blur_sp, k, p_rsvd, q, prec="bf16", refine=2, seed=2, factor_prec="f64"),
          "rsvd", 2, refine=2, prec="bf16", gate=1e-4)
+    case("speckle_rsvd_f16x3", blur_sp,
+         ctx.kp_svd_rsvd(blur_sp, k, p_rsvd, q, prec="f16x3", seed=2, factor_prec="f64"),
+         "rsvd", 2, prec="f16x3")
 
     log("split Bregman latency at n=256")
     ns = 256
@@ -869,6 +884,10 @@ def main():
             "rsvd_bf16_refine_product": "split FP16 (three FP16 MFMA products of two-term splits)",
             "rsvd_bf16_refine_fp32_product_ms": round(bf1_ms, 3),
             "rsvd_bf16_refine_fp32_product_max_sigma_diff_vs_fp32_over_sigma1": sig_diff1,
+            "rsvd_f16x3_ms": round(f3_ms, 3),
+            "rsvd_f16x3_tflops_algorithmic": round(f_rsvd / (f3_ms * 1e-3) / 1e12, 3),
+            "rsvd_f16x3_speedup_vs_fp32": round(float(np.median(comp["rsvd_ms"])) / f3_ms, 3),
+            "rsvd_f16x3_max_sigma_diff_vs_fp32_over_sigma1": sig_diff3,
         },
         "disk_r8_n512": disk,
         "sb_solve_n256": {

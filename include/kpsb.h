@@ -51,7 +51,11 @@ typedef enum {
   KP_W_BREAKDOWN = 100  /* result valid; a Lanczos breakdown was deflated     */
 } kp_status;
 
-typedef enum { KP_F64 = 0, KP_F32 = 1, KP_BF16 = 2, KP_F16 = 3 } kp_prec;
+/* KP_F16X3 (RSVD only): every product with R or R^T as three FP16 products of
+ * two-term FP16 splits of R and of the input (R_hi X_hi + R_hi X_lo + R_lo X_hi,
+ * FP32 accumulation, the main term folded into FP64 per column block): about
+ * 2^-22 relative, FP32-level accuracy on the 16-bit matrix cores. */
+typedef enum { KP_F64 = 0, KP_F32 = 1, KP_BF16 = 2, KP_F16 = 3, KP_F16X3 = 4 } kp_prec;
 
 /* KP-SVD method: Algorithm 1 (EGKB) or Algorithm 2 (RSVD). */
 typedef enum { KP_METHOD_GKB = 0, KP_METHOD_RSVD = 1 } kp_method;
@@ -142,8 +146,9 @@ typedef struct {
  * application of R or R^T. */
 typedef struct {
   int32_t k, p, q;      /* rank, oversampling, power iterations                    */
-  kp_prec prec;         /* KP_F32, KP_F64, or KP_BF16 / KP_F16 (block products in
-                           16-bit inputs with FP32 accumulation)                   */
+  kp_prec prec;         /* KP_F32, KP_F64, KP_BF16 / KP_F16 (block products in
+                           16-bit inputs with FP32 accumulation) or KP_F16X3
+                           (split-FP16 products, FP32-level accuracy)              */
   int32_t refine;       /* 1: second reorthogonalization + Rayleigh-Ritz refinement
                            of the rank-k factors with an FP32 product W = R V;
                            2: the same with W from three FP16 MFMA products of

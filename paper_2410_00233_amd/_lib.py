@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(HERE, "libkpsb.so")
 KP_OK, KP_E_INVAL, KP_E_NOMEM, KP_E_DEVICE, KP_E_NUMERIC = 0, 1, 2, 3, 4
 KP_E_BUSY, KP_E_TIMEOUT, KP_E_CANCELLED = 5, 6, 7
 KP_W_BREAKDOWN = 100
-KP_F64, KP_F32, KP_BF16, KP_F16 = 0, 1, 2, 3
+KP_F64, KP_F32, KP_BF16, KP_F16, KP_F16X3 = 0, 1, 2, 3, 4
 KP_METHOD_GKB, KP_METHOD_RSVD = 0, 1
 KP_BC_ZERO, KP_BC_REFLEXIVE, KP_BC_PERIODIC = 0, 1, 2
 

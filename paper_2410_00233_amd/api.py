@@ -13,7 +13,8 @@ import numpy as np
 
 from . import _lib as L
 
-PREC = {"f64": L.KP_F64, "f32": L.KP_F32, "bf16": L.KP_BF16, "f16": L.KP_F16}
+PREC = {"f64": L.KP_F64, "f32": L.KP_F32, "bf16": L.KP_BF16, "f16": L.KP_F16,
+        "f16x3": L.KP_F16X3}
 
 
 class KPError(RuntimeError):

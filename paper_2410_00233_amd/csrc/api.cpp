@@ -496,7 +496,7 @@ kp_status block_product16_1(kp_ctx* c, const Grids<H>& g, int n, int transpose, 
 // (two-term FP16 splits, power-of-2 scalings), W = (G_hi V_hi + G_hi V_lo +
 // G_lo V_hi) / (s 2^kSplitXExp); the dropped G_lo V_lo term is about 2^-22 of
 // the product. Accumulated in FP64 inside each product, in FP32 across them.
-kp_status split16_product(kp_ctx* c, const kp_blur* b, const double* dpsf, int n,
+kp_status split16_product(kp_ctx* c, const kp_blur* b, const double* dpsf, int n, int tr,
                           const float* V, float* W, int ncols, hipStream_t s) {
   BlockPlan bp;
   bool planned = false;
@@ -514,10 +514,10 @@ kp_status split16_product(kp_ctx* c, const kp_blur* b, const double* dpsf, int n
   KP_TRY(wsT(c, "x_split_lo", (size_t)ld16 * ncols, &Xlo));
   launch_psf_split_scale(dpsf, (long)b->pu * b->pv, tm.nsum_max(), scal, s);
   // the terms run one after another on the stream, so one hi/lo grid pair serves all
-  return multi_term<float>(c, tm, n, 0, V, W, ncols, s,
+  return multi_term<float>(c, tm, n, tr, V, W, ncols, s,
                            [&](int t, const float* in, float* out, bool) -> kp_status {
-    launch_build_grid_split(dpsf, b->pu, b->pv, b->cu, b->cv, n, 0, tm.sh[t], scal, 0, Ghi, ldg, s);
-    launch_build_grid_split(dpsf, b->pu, b->pv, b->cu, b->cv, n, 0, tm.sh[t], scal, 1, Glo, ldg, s);
+    launch_build_grid_split(dpsf, b->pu, b->pv, b->cu, b->cv, n, tr, tm.sh[t], scal, 0, Ghi, ldg, s);
+    launch_build_grid_split(dpsf, b->pu, b->pv, b->cu, b->cv, n, tr, tm.sh[t], scal, 1, Glo, ldg, s);
     launch_to16_split(in, N, n, ncols, Xhi, Xlo, ld16, s);
     if (!planned) {   // the tuned 16-bit launch shape (its samples write `out` first)
       Grids<__half> gg;
@@ -1166,6 +1166,7 @@ kp_status rsvd_impl(kp_ctx* c, const RmatOp<T>& op, const kp_rsvd_opts* o, kp_fa
     if constexpr (std::is_same<T, float>::value) {
       if (pp == KP_BF16) return block_product16<__hip_bfloat16>(c, gb, n, tr, X, Yo, nc, s);
       if (pp == KP_F16) return block_product16<__half>(c, gh, n, tr, X, Yo, nc, s);
+      if (pp == KP_F16X3) return split16_product(c, b, op.dpsf, n, tr, X, Yo, nc, s);
     }
     return op.block(c, tr, X, Yo, nc, s);
   };
@@ -1217,7 +1218,8 @@ kp_status rsvd_impl(kp_ctx* c, const RmatOp<T>& op, const kp_rsvd_opts* o, kp_fa
     launch_convert<double, T>(Vd, Vf, N * kout, s);
     KP_TRY(qr(Vf, kout, nullptr));
     if constexpr (std::is_same<T, float>::value) {
-      if (o->refine == 2 && b) KP_TRY(split16_product(c, b, op.dpsf, n, Vf, W, kout, s));
+      if ((o->refine == 2 || pp == KP_F16X3) && b)
+        KP_TRY(split16_product(c, b, op.dpsf, n, 0, Vf, W, kout, s));
       else KP_TRY(op.block(c, 0, Vf, W, kout, s));
     } else {
       KP_TRY(op.block(c, 0, Vf, W, kout, s));
@@ -1801,7 +1803,8 @@ kp_status check_rsvd(kp_ctx* c, const kp_rsvd_opts* o, kp_factors* f, int n) {
   if (o->F)
     for (long e = 0; e < N * (o->k + o->p); ++e)
       if (!std::isfinite(o->F[e])) return set_err(c, KP_E_NUMERIC, "F has a non-finite entry");
-  if (o->prec != KP_F32 && o->prec != KP_F64 && o->prec != KP_BF16 && o->prec != KP_F16)
+  if (o->prec != KP_F32 && o->prec != KP_F64 && o->prec != KP_BF16 && o->prec != KP_F16 &&
+      o->prec != KP_F16X3)
     return set_err(c, KP_E_INVAL, "unknown RSVD precision");
   return KP_OK;
 }

@@ -107,10 +107,11 @@ bool needs_tuning(const kp_blur& b, int32_t method, const void* opts) {
   }
   const kp_rsvd_opts* o = static_cast<const kp_rsvd_opts*>(opts);
   // the 16-bit tuner is keyed on the element type (KP_BF16 / KP_F16); the
-  // split-FP16 refinement product (refine = 2, FP32-vector modes) tunes the
-  // FP16 kernel whatever the sketch precision
-  const bool split16 = o->refine == 2 && o->prec != KP_F64;
+  // split-FP16 products (KP_F16X3, and the refinement product of refine = 2 in
+  // the FP32-vector modes) tune the FP16 kernel
+  const bool split16 = (o->refine == 2 && o->prec != KP_F64) || o->prec == KP_F16X3;
   if (split16 && !tune_known(kTuneBlock16, b.n, KP_F16, 0)) return true;
+  if (o->prec == KP_F16X3) return false;   // every product is a split-FP16 one
   if (o->prec == KP_BF16 || o->prec == KP_F16)
     return !tune_known(kTuneBlock16, b.n, o->prec, 0) ||
            (o->refine == 1 && !tune_known(kTuneBlock, b.n, 4, 0));
@@ -356,7 +357,12 @@ size_t svd_bytes(const kp_request& r) {
     b += 2 * round256(N * (size_t)r.k_cap * 8);
     if (terms > 1) b += 4 * round256(N * kp * es);
     if (r.rsvd.F) b += round256(N * kp * 8);
-    if (r.rsvd.refine == 2 && r.rsvd.prec != KP_F64) {
+    if (r.rsvd.prec == KP_F16X3) {
+      // split-FP16 products: hi / lo FP16 grids and hi / lo FP16 inputs of k + p
+      // columns (also used by the refinement)
+      b += 2 * round256((size_t)(2 * n - 1) * grid_ld(n) * 2);
+      b += 2 * round256(x16 * (size_t)kp * 2);
+    } else if (r.rsvd.refine == 2 && r.rsvd.prec != KP_F64) {
       // split-FP16 refinement: hi / lo FP16 grids and hi / lo FP16 inputs
       b += 2 * round256((size_t)(2 * n - 1) * grid_ld(n) * 2);
       b += 2 * round256(x16 * (size_t)r.rsvd.k * 2);

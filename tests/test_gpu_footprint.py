@@ -53,6 +53,7 @@ CONFIGS = {
     "rsvd-bf16-refine2": dict(method="rsvd", prec="bf16", refine=2),
     "rsvd-f16-refine1": dict(method="rsvd", prec="f16", refine=1),
     "rsvd-f64-refine1": dict(method="rsvd", prec="f64", refine=1),
+    "rsvd-f16x3": dict(method="rsvd", prec="f16x3"),
 }
 
 
@@ -61,7 +62,8 @@ CONFIGS = {
 @pytest.mark.parametrize("name", list(CONFIGS))
 def test_kpsvd_workspace_within_footprint(name, n, bc):
     from paper_2410_00233_amd import api
-    if bc == "reflexive" and name not in ("gkb-f32", "rsvd-f32-refine2", "rsvd-bf16-refine2"):
+    if bc == "reflexive" and name not in ("gkb-f32", "rsvd-f32-refine2", "rsvd-bf16-refine2",
+                                          "rsvd-f16x3"):
         pytest.skip("reflexive boundary conditions: one case per product kind")
     cfg = CONFIGS[name]
     P, cu, cv = wl.gaussian_psf(n)

@@ -322,3 +322,39 @@ def test_rsvd_range_basis_widths(ctx, k, p, prec):
     print(f"TSQR width {k + p} {prec}: max|Y^T Y - I| = {orth:.2e}, sigma err {err:.2e}")
     assert orth <= (1e-13 if prec == "f64" else 1e-6)
     assert err <= (1e-12 if prec == "f64" else 1e-5)
+
+
+@pytest.mark.parametrize("n,psf,bc", [(128, "speckle", "zero"), (512, "gaussian", "zero"),
+                                      (96, "disk", "zero"), (64, "gaussian", "reflexive")])
+def test_rsvd_split_fp16_products_match_oracle(ctx, n, psf, bc):
+    """prec = "f16x3": every product with R or R^T as three FP16 products of
+    two-term splits (about 2^-22 relative): the FP32 gate against the
+    same-algorithm FP64 oracle (sigma within 1e-5 sigma_1, leading factors
+    element-wise at the FP32 tolerance, ||A - A_k|| as the oracle's), and
+    within 1e-6 sigma_1 of the FP32 RSVD on the same sketch."""
+    from paper_2410_00233_amd import api
+    k, p, q = 20, 10, 2
+    P, cu, cv = {"gaussian": lambda: wl.gaussian_psf(n), "disk": lambda: wl.disk_psf(n),
+                 "speckle": lambda: wl.speckle_psf(n, seed=1002)}[psf]()
+    F = wl.gaussian_block(n * n, k + p, seed=wl.SEED_START + 2)
+    blur = api.Blur(P, cu, cv, n, bc=bc)
+    f3 = ctx.kp_svd_rsvd(blur, k, p, q, prec="f16x3", F=F)
+    f32 = ctx.kp_svd_rsvd(blur, k, p, q, prec="f32", F=F)
+    d = np.abs(f3.sigma[:k] - f32.sigma[:k]).max() / f32.sigma[0]
+    print(f"RSVD f16x3 n={n} {psf} {bc}: vs FP32 RSVD {d:.2e}")
+    assert d <= 1e-6
+    if bc != "zero":
+        return
+    R, Rt = _ops(P, cu, cv, n)
+    ref = kpsvd.rsvd(R, Rt, F, k, q)
+    s1 = ref["sigma"][0]
+    err = np.abs(f3.sigma[:k] - ref["sigma"]).max() / s1
+    print(f"  vs same-algorithm FP64 oracle {err:.2e}")
+    assert err <= 1e-5
+    s, U, V, _, _ = _uv_from_factors(f3)
+    if psf != "disk":
+        nchk = _check_leading_factors(s, U, V, ref, eps=1e-6)
+        assert nchk >= (2 if psf == "gaussian" else 0)
+    e_gpu = metrics.kp_rel_error(P, cu, cv, n, s, U, V)
+    e_ref = metrics.kp_rel_error(P, cu, cv, n, ref["sigma"], ref["U"], ref["V"])
+    assert e_gpu <= e_ref + 5e-5
