@@ -492,6 +492,35 @@ kp_status sb_solve_aniso_direct(kp_ctx* ctx, int32_t n, const double* A, const d
 kp_status sb_solve_iso_direct(kp_ctx* ctx, int32_t n, const double* A, const double* b,
                               const sb_opts* opts, double* x, sb_stats* stats, void* stream);
 
+/* ---------------------------------------------------------------------------
+ * The blur A through two-dimensional FFTs. For a spatially invariant blur A x
+ * is a convolution, so A (the BTTB matrix of section 1 for zero boundary
+ * conditions, and its reflexive and periodic counterparts) is applied without
+ * being stored: the image is extended by its boundary conditions, convolved
+ * with the PSF in a circular convolution of size M1 x M2 (the powers of two
+ * >= n + pu - 1 and >= n + pv - 1, at most 4096), and cropped; A^T places,
+ * correlates and folds each extended entry back onto its source pixel. FP64
+ * throughout, O(n^2 log n) per product; equal to the product with the matrix
+ * kp_blur_matrix builds up to FFT rounding (about 1e-15 relative).
+ *
+ * Y = A X (transpose = 0) or A^T X for the blur `blur` (PSF, centre, boundary
+ * conditions; blur->compact is ignored). X, Y: DEVICE n x n row-major FP64
+ * images (pixel (r, i) at r n + i; r pairs with the PSF's first index),
+ * distinct. KP_E_INVAL for a bad blur, NULL or aliased images, or
+ * n + pu - 1 or n + pv - 1 above 4096. Uses the context's workspace. */
+kp_status kp_blur_apply(kp_ctx* ctx, const kp_blur* blur, int transpose, const double* X,
+                        double* Y, void* stream);
+/* Split Bregman (Algorithms 3 / 4 with CGLS, Algorithm 5) with A itself
+ * applied through kp_blur_apply's FFT products: the paper's method (i) of
+ * Table 1 without a stored A, for any n the FFT sizes allow. Same options,
+ * statistics, image layout and statuses as sb_solve_iso / sb_solve_aniso; the
+ * same restored image as sb_solve_iso_direct / sb_solve_aniso_direct with the
+ * explicit A up to rounding. */
+kp_status sb_solve_aniso_fft(kp_ctx* ctx, const kp_blur* blur, const double* b,
+                             const sb_opts* opts, double* x, sb_stats* stats, void* stream);
+kp_status sb_solve_iso_fft(kp_ctx* ctx, const kp_blur* blur, const double* b,
+                           const sb_opts* opts, double* x, sb_stats* stats, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

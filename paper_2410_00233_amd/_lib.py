@@ -33,7 +33,7 @@ EXPORTED = ["kp_ctx_create", "kp_ctx_destroy", "kp_last_error", "kp_version",
             "kp_svd_gkb_stored", "kp_svd_rsvd_stored", "sb_solve_aniso_direct",
             "sb_solve_iso_direct", "kp_blur_matrix", "kp_rmat_apply_noalloc",
             "kp_ctx_workspace", "kp_request_footprint", "kp_cancel", "kp_server_cancel",
-            "sb_solve_batched"]
+            "sb_solve_batched", "kp_blur_apply", "sb_solve_aniso_fft", "sb_solve_iso_fft"]
 
 
 class kp_blur(C.Structure):
@@ -168,6 +168,10 @@ def load(path: str = LIB_PATH):
     lib.sb_solve_aniso_direct.argtypes = [vp, C.c_int32, vp, vp, C.POINTER(sb_opts), vp,
                                           C.POINTER(sb_stats), vp]
     lib.sb_solve_iso_direct.argtypes = lib.sb_solve_aniso_direct.argtypes
+    lib.kp_blur_apply.argtypes = [vp, C.POINTER(kp_blur), C.c_int, vp, vp, vp]
+    lib.sb_solve_aniso_fft.argtypes = [vp, C.POINTER(kp_blur), vp, C.POINTER(sb_opts), vp,
+                                       C.POINTER(sb_stats), vp]
+    lib.sb_solve_iso_fft.argtypes = lib.sb_solve_aniso_fft.argtypes
     for name in EXPORTED:
         if name not in ("kp_last_error", "kp_version"):
             getattr(lib, name).restype = C.c_int

@@ -358,6 +358,37 @@ class Context:
         return x, dict(l_end=st.l_end, iota_total=st.iota_total, rc_sb=st.rc_sb,
                        graph_replays=st.graph_replays)
 
+    def kp_blur_apply(self, blur: Blur, X, transpose=False, Y=None):
+        """A X or A^T X (device n x n FP64 images) through FFTs of the image
+        extended by the blur's boundary conditions."""
+        torch = _torch()
+        if Y is None:
+            Y = torch.empty_like(X)
+        self._check(self.lib.kp_blur_apply(self.h, C.byref(blur.s), int(transpose), _ptr(X),
+                                           _ptr(Y), _stream()))
+        return Y
+
+    def sb_solve_aniso_fft(self, blur: Blur, b, lam, beta, L_max=50, I_max=100, tau_sb=0.0,
+                           tau_cgls=0.0, x=None):
+        return self._sb_fft(self.lib.sb_solve_aniso_fft, blur, b, lam, beta, L_max, I_max,
+                            tau_sb, tau_cgls, x)
+
+    def sb_solve_iso_fft(self, blur: Blur, b, lam, beta, L_max=50, I_max=100, tau_sb=0.0,
+                         tau_cgls=0.0, x=None):
+        return self._sb_fft(self.lib.sb_solve_iso_fft, blur, b, lam, beta, L_max, I_max,
+                            tau_sb, tau_cgls, x)
+
+    def _sb_fft(self, fn, blur, b, lam, beta, L_max, I_max, tau_sb, tau_cgls, x):
+        torch = _torch()
+        if x is None:
+            x = torch.empty_like(b)
+        o = L.sb_opts(lam, beta, L_max, I_max, tau_sb, tau_cgls)
+        st = L.sb_stats()
+        self._check(fn(self.h, C.byref(blur.s), _ptr(b), C.byref(o), _ptr(x), C.byref(st),
+                       _stream()))
+        return x, dict(l_end=st.l_end, iota_total=st.iota_total, rc_sb=st.rc_sb,
+                       graph_replays=st.graph_replays)
+
     def kp_apply(self, f: Factors, X, transpose=False, Y=None):
         torch = _torch()
         if Y is None:

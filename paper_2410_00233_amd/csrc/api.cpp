@@ -1261,15 +1261,60 @@ kp_status validate_apply_factors(kp_ctx* c, const kp_factors* f) {
 // The blur operator of a split Bregman solve: the Kronecker sum A_k (factors)
 // or an explicit N x N matrix A in HBM (the paper's method (i) of Table 1).
 // apply(tr, v, P, flags, s) enqueues op(A) v as `ngroups` partial images in P.
+// The blur's FFT products (fft.hip): padded sizes, workspace, the twiddle
+// table and the spectrum of P, enqueued on s.
+kp_status fft_conv_plan(kp_ctx* c, const kp_blur* b, hipStream_t s, FftConv* p) {
+  const int n = b->n;
+  p->n = n;
+  p->pu = b->pu;
+  p->pv = b->pv;
+  p->cu = b->cu;
+  p->cv = b->cv;
+  p->bc = b->bc;
+  p->e1 = n + b->pu - 1;
+  p->e2 = n + b->pv - 1;
+  auto lg = [](int e) {
+    int l = 3;
+    while ((1 << l) < e) ++l;
+    return l;
+  };
+  if (p->e1 > kFftMaxLen || p->e2 > kFftMaxLen)
+    return set_err(c, KP_E_INVAL, "FFT blur products need n + pu - 1 and n + pv - 1 <= 4096");
+  p->l1 = lg(p->e1);
+  p->l2 = lg(p->e2);
+  const int M1 = 1 << p->l1, M2 = 1 << p->l2, h2 = M2 / 2 + 1;
+  p->ls = (h2 + 15) & ~15;
+  p->rp = std::max(1, 2048 / M2);
+  p->cb = std::max(2, std::min(16, kFftMaxLen / M1));
+  double2* tw = nullptr;
+  KP_TRY(wsT(c, "fft_tw", (size_t)kFftMaxLen, &tw));
+  p->tw = tw;
+  KP_TRY(wsT(c, "fft_S", (size_t)p->e1 * p->ls, &p->S));
+  KP_TRY(wsT(c, "fft_H", (size_t)h2 * M1, &p->H));
+  p->G = nullptr;
+  if (p->bc != KP_BC_ZERO) KP_TRY(wsT(c, "fft_G", (size_t)p->e1 * p->e2, &p->G));
+  double* dpsf = nullptr;
+  KP_TRY(upload_psf(c, b, s, &dpsf));
+  fft_set_lds_limits();
+  launch_fft_twiddles(tw, s);
+  launch_fft_psf_spectrum(*p, dpsf, s);
+  return check_launch(c, "fft plan");
+}
+
 struct SbOp {
   int n = 0;
   const kp_factors* f = nullptr;
   const double* A = nullptr;
+  const FftConv* fc = nullptr;
   KpApplyPlan plan;
   double *Z = nullptr, *gv = nullptr, *tv = nullptr, *ty = nullptr;
-  int ngroups() const { return A ? 1 : plan.ngroups; }
+  int ngroups() const { return (A || fc) ? 1 : plan.ngroups; }
   void apply(int tr, const double* v, double* P, const int* flags, int nflags,
              hipStream_t s) const {
+    if (fc) {
+      launch_fft_conv(*fc, tr, v, P, flags, nflags, s);
+      return;
+    }
     if (A) {
       // images are row-major (pixel (r, c) at r n + c); A acts on vec (r + n c)
       launch_transpose_image(v, tv, n, flags, nflags, s);
@@ -1302,7 +1347,9 @@ kp_status sb_solve_impl(kp_ctx* c, SbOp& op, const double* b, const sb_opts* o, 
   KP_TRY(wsT(c, "sb_img", (size_t)14 * NN, &img));
   double *P, *part, *scal;
   int* flags;
-  if (op.A) {
+  if (op.fc) {
+    KP_TRY(wsT(c, "kpP", (size_t)NN, &P));
+  } else if (op.A) {
     KP_TRY(wsT(c, "kpP", (size_t)NN, &P));
     KP_TRY(wsT(c, "sb_gv", (size_t)stored_gemv_ws(NN), &op.gv));
     KP_TRY(wsT(c, "sb_tv", (size_t)2 * NN, &op.tv));
@@ -1472,6 +1519,19 @@ kp_status sb_solve_direct(kp_ctx* c, int n, const double* A, const double* b, co
   SbOp op;
   op.n = n;
   op.A = A;
+  return sb_solve_impl(c, op, b, o, x, st, s, iso);
+}
+
+kp_status sb_solve_fft(kp_ctx* c, const kp_blur* bl, const double* b, const sb_opts* o,
+                       double* x, sb_stats* st, hipStream_t s, int iso) {
+  KP_TRY(validate_blur(c, bl));
+  KP_TRY(sb_check_opts(c, b, o, x));
+  KP_HIP(c, hipSetDevice(c->device));
+  FftConv fc;
+  KP_TRY(fft_conv_plan(c, bl, s, &fc));
+  SbOp op;
+  op.n = bl->n;
+  op.fc = &fc;
   return sb_solve_impl(c, op, b, o, x, st, s, iso);
 }
 
@@ -1981,6 +2041,33 @@ kp_status sb_solve_iso_direct(kp_ctx* c, int32_t n, const double* A, const doubl
                               const sb_opts* o, double* x, sb_stats* st, void* stream) {
   if (!c) return KP_E_INVAL;
   return sb_solve_direct(c, n, A, b, o, x, st, (hipStream_t)stream, 1);
+}
+
+kp_status kp_blur_apply(kp_ctx* c, const kp_blur* b, int transpose, const double* X, double* Y,
+                        void* stream) {
+  if (!c) return KP_E_INVAL;
+  KP_TRY(validate_blur(c, b));
+  if (transpose != 0 && transpose != 1) return set_err(c, KP_E_INVAL, "transpose must be 0 or 1");
+  if (!X || !Y) return set_err(c, KP_E_INVAL, "X or Y is NULL");
+  if (X == Y) return set_err(c, KP_E_INVAL, "X and Y must not alias");
+  KP_HIP(c, hipSetDevice(c->device));
+  hipStream_t s = (hipStream_t)stream;
+  FftConv fc;
+  KP_TRY(fft_conv_plan(c, b, s, &fc));
+  launch_fft_conv(fc, transpose, X, Y, nullptr, 0, s);
+  return check_launch(c, "blur_apply");
+}
+
+kp_status sb_solve_aniso_fft(kp_ctx* c, const kp_blur* blur, const double* b, const sb_opts* o,
+                             double* x, sb_stats* st, void* stream) {
+  if (!c) return KP_E_INVAL;
+  return sb_solve_fft(c, blur, b, o, x, st, (hipStream_t)stream, 0);
+}
+
+kp_status sb_solve_iso_fft(kp_ctx* c, const kp_blur* blur, const double* b, const sb_opts* o,
+                           double* x, sb_stats* st, void* stream) {
+  if (!c) return KP_E_INVAL;
+  return sb_solve_fft(c, blur, b, o, x, st, (hipStream_t)stream, 1);
 }
 
 }  // extern "C"

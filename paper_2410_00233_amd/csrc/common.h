@@ -260,5 +260,31 @@ void launch_form_factors(const T* U, const T* V, long ldu, int n, int k,
                          const double* sigma, O* Ax, O* Ay, int* argmax_scratch,
                          hipStream_t s);
 
+// ---- the blur through two-dimensional FFTs (fft.hip) -----------------------
+// A x and A^T y of a spatially invariant blur with its boundary conditions as
+// a circular convolution of size M1 x M2 (powers of two, 8 .. kFftMaxLen) of
+// the extended image; fields set by fft_conv_plan in api.cpp.
+constexpr int kFftMaxLen = 4096;
+struct FftConv {
+  int n, pu, pv, cu, cv, bc;
+  int e1, e2;        // extended extents n + pu - 1, n + pv - 1
+  int l1, l2;        // log2 M1, log2 M2
+  int ls;            // row stride of S (complex entries), >= M2 / 2 + 1
+  int rp;            // row pairs per workgroup of the row passes
+  int cb;            // columns per workgroup of the column pass
+  const double2* tw; // exp(-2 pi i j / kFftMaxLen), j < kFftMaxLen
+  double2* S;        // e1 x ls: half spectra of the row transforms
+  double2* H;        // (M2 / 2 + 1) x M1: spectrum of P, bit-reversed columns
+  double* G;         // e1 x e2 (adjoint with non-zero boundary conditions)
+};
+void launch_fft_twiddles(double2* tw, hipStream_t s);
+// H from the device PSF (pu x pv row-major); uses S.
+void launch_fft_psf_spectrum(const FftConv& p, const double* psf, hipStream_t s);
+// Y = A X (transpose 0) or A^T X, n x n row-major images; skipped when any of
+// flags[0..nflags) is nonzero. Uses S (and G).
+void launch_fft_conv(const FftConv& p, int transpose, const double* X, double* Y,
+                     const int* flags, int nflags, hipStream_t s);
+// the column pass's dynamic LDS above 64 KB (once per process)
+void fft_set_lds_limits();
 
 }  // namespace kpsb
