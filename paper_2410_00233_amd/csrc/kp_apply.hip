@@ -16,6 +16,7 @@
 // lines, whichever of m, n or k that is.
 #include "common.h"
 #include "sb.h"
+#include "partials.h"
 
 namespace kpsb {
 
@@ -237,9 +238,7 @@ __global__ void sum_terms_kernel(const double* __restrict__ P, int ng, long NN,
       if (flags[i]) return;
   for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < NN;
        e += (long)gridDim.x * blockDim.x) {
-    double v = 0.0;
-    for (int t = 0; t < ng; ++t) v += P[(long)t * NN + e];
-    Y[e] = v;
+    Y[e] = add_partials_in_order(0.0, P + e, 0, ng, NN);
   }
 }
 

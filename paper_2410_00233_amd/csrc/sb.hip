@@ -15,6 +15,7 @@
 // the queued kernels into no-ops, so the host never waits on a scalar.
 #include "common.h"
 #include "sb.h"
+#include "partials.h"
 
 namespace kpsb {
 
@@ -89,9 +90,7 @@ __global__ void __launch_bounds__(256) sb_rhs_kernel(SBDev d) {
 // sum of the ng partial images at P (stride NN), fixed order
 __device__ __forceinline__ double sb_sum_parts(const double* __restrict__ P, int ng, long NN,
                                                long e) {
-  double v = P[e];
-  for (int g = 1; g < ng; ++g) v += P[(long)g * NN + e];
-  return v;
+  return add_partials_in_order(P[e], P + e, 1, ng, NN);
 }
 
 // f = T + lam (L_x^T r2 + L_y^T r3) with T the sum of ng partial images,
