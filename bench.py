@@ -383,6 +383,49 @@ def bench_paper_pipeline(ctx, n=128):
     return out
 
 
+def bench_sb_fft(ctx, sizes=(256, 512), solves=2):
+    """Split Bregman with A itself through FFT products (sb_solve_iso_fft)
+    beside the same solve with rank-20 Kronecker factors (sb_solve_iso), on
+    the same deblurring problem per n (Gaussian PSF on the full offset grid,
+    1 % noise, 50 outer iterations, CGLS tau 1e-4): median wall time of
+    `solves` solves after one untimed solve, CGLS iterations, restoration
+    error."""
+    import numpy as np
+    import torch
+
+    import workloads as wl
+    from paper_2410_00233_amd import api
+    out = {"kind": "isotropic split Bregman, A through 2-D FFTs (zero BC) vs rank-20 A_k "
+                   "(FP32 RSVD factors), 50 outer iterations, CGLS tau 1e-4 (I_max 100), FP64"}
+    for n in sizes:
+        P, cu, cv, x_true, _, b = wl.deblur_problem(n, "gaussian", 0.01, 0)
+        blur = api.Blur(P, cu, cv, n, on_device=True)
+        bd = torch.tensor(b, dtype=torch.float64, device="cuda")
+        f = ctx.kp_svd_rsvd(blur, 20, 10, 2, prec="f32", seed=3, factor_prec="f64")
+        row = {}
+        for name, fn in (("fft", lambda: ctx.sb_solve_iso_fft(blur, bd, 0.115, 0.115 ** 2 / 2,
+                                                              L_max=50, I_max=100, tau_cgls=1e-4)),
+                         ("kp", lambda: ctx.sb_solve_iso(f, bd, 0.115, 0.115 ** 2 / 2, L_max=50,
+                                                         I_max=100, tau_cgls=1e-4))):
+            ts = []
+            for rep in range(1 + solves):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                x, st = fn()
+                torch.cuda.synchronize()
+                if rep > 0:
+                    ts.append(1e3 * (time.perf_counter() - t0))
+            ms = float(np.median(ts))
+            row[f"{name}_ms"] = round(ms, 2)
+            row[f"{name}_iota_total"] = int(st["iota_total"])
+            row[f"{name}_us_per_cgls_iteration"] = round(1e3 * ms / max(st["iota_total"], 1), 2)
+            row[f"{name}_relative_error"] = round(
+                float(np.linalg.norm(x.cpu().numpy() - x_true) / np.linalg.norm(x_true)), 4)
+        row["fft_speedup_vs_kp"] = round(row["kp_ms"] / row["fft_ms"], 3)
+        out[f"n{n}"] = row
+    return out
+
+
 def bench_serving(srv, count, rate, sizes, warmed):
     """Open-loop serving on the server `srv`: Poisson arrivals at `rate`/s, n
     drawn 4:3:2:1 over `sizes`, 16 recurring PSFs, iso/aniso 50/50, split
@@ -573,6 +616,9 @@ def main():
                     help="seconds per timed run of the CPU dense product (3 runs per "
                          "precision and thread count)")
     ap.add_argument("--sb-solves", type=int, default=5)
+    ap.add_argument("--sb-fft-solves", type=int, default=2,
+                    help="timed solves per method and size in the FFT split Bregman section "
+                         "(0 skips it)")
     ap.add_argument("--batched", type=int, default=64,
                     help="problems in the batched KP-SVD run (0 skips it)")
     ap.add_argument("--sb-batched", type=int, default=16,
@@ -814,6 +860,8 @@ def main():
             lat.append(1e3 * (time.perf_counter() - ta))
     x_np = xs.cpu().numpy()
     re_sb = float(np.linalg.norm(x_np - xs_true) / np.linalg.norm(xs_true))
+    log("split Bregman with A through FFTs at n=256, 512")
+    sb_fft = bench_sb_fft(ctx, solves=args.sb_fft_solves) if args.sb_fft_solves > 0 else None
 
     blk = prof["block"]
     avg_blk_ms = blk["ms"] / max(blk["launches"], 1)
@@ -900,6 +948,7 @@ def main():
             "cgls_tflops": round(st["iota_total"] * flops.cgls_iteration_kp(ns, k)
                                  / (float(np.percentile(lat, 50)) * 1e-3) / 1e12, 3),
         },
+        "sb_fft": sb_fft,
         "roofline_bf16": {
             "kernel": f"rmat_block16_kernel<bf16,{BLOCK16_VARIANT_TEMPLATE.get(v16, '?')}> "
                       "(generated-tile R(A) X, BF16 MFMA 16x16x32, FP32 accumulate)",

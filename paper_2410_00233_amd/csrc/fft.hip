@@ -211,7 +211,14 @@ fft_cols_kernel(FftConv p, int mode, int rin0, int rin1, int rout0, int rout1,
   extern __shared__ double2 sbuf[];
   const int M = 1 << p.l1, CB = p.cb;
   const int h2 = ((1 << p.l2) >> 1) + 1;
-  const int k0 = blockIdx.x * CB;
+  // Workgroups go to the 8 XCDs round-robin by id, while the CB columns of a
+  // workgroup fill only part of each 128-byte line of S: give each XCD a
+  // contiguous range of column groups, so the groups that share a line meet
+  // in one L2 (the tail beyond a multiple of 8 keeps its order).
+  const int per = gridDim.x >> 3;
+  const int bid = blockIdx.x;
+  const int grp = bid < (per << 3) ? (bid & 7) * per + (bid >> 3) : bid;
+  const int k0 = grp * CB;
   for (int idx = threadIdx.x; idx < CB * M; idx += blockDim.x) {
     const int b = idx % CB, q = idx / CB;
     double2 v = {0.0, 0.0};
