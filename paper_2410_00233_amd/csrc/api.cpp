@@ -1284,8 +1284,12 @@ kp_status fft_conv_plan(kp_ctx* c, const kp_blur* b, hipStream_t s, FftConv* p) 
   p->l2 = lg(p->e2);
   const int M1 = 1 << p->l1, M2 = 1 << p->l2, h2 = M2 / 2 + 1;
   p->ls = (h2 + 15) & ~15;
-  p->rp = std::max(1, 2048 / M2);
-  p->cb = std::max(2, std::min(16, kFftMaxLen / M1));
+  // one sequence (row pair, column) per workgroup from length 512 up: the
+  // padded sizes leave only a few hundred sequences per pass, and more
+  // workgroups beat longer ones (n = 256, M = 1024: 4 columns and 2 row
+  // pairs per workgroup ran the CGLS iteration in 122 us, one each in 86 us)
+  p->rp = std::max(1, 512 / M2);
+  p->cb = std::max(1, 512 / M1);
   double2* tw = nullptr;
   KP_TRY(wsT(c, "fft_tw", (size_t)kFftMaxLen, &tw));
   p->tw = tw;
