@@ -32,6 +32,7 @@ exact optimum.
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
        python bench.py --profile-products   (the rocprofv3 counter workload)
        python bench.py --profile-qr         (the same for the Householder TSQR)
+       python bench.py --profile-fft        (the same for the FFT blur products)
 """
 from __future__ import annotations
 
@@ -313,7 +314,8 @@ def bench_paper_pipeline(ctx, n=128):
     """The paper's own pipeline on its "Medium" setting (n = 128, reflexive
     boundary conditions, a 15 x 15 speckle-like PSF, k = 8, p = 4): explicit A,
     reorder to R(A), EGKB(SP) and RSVD(SP, q = 1) over the stored R, then
-    isotropic split Bregman with the Kronecker factors and with A itself."""
+    isotropic split Bregman with the Kronecker factors and with A itself
+    (stored, and through FFT products)."""
     import numpy as np
     import torch
 
@@ -368,9 +370,16 @@ def bench_paper_pipeline(ctx, n=128):
     (xk, sk), out["sb_iso_kp_ms"] = timed(lambda: ctx.sb_solve_iso(fk, b_dev, lam, lam ** 2 / 2, **kw))
     (xa, sa), out["sb_iso_direct_ms"] = timed(
         lambda: ctx.sb_solve_iso_direct(n, A64, b_dev, lam, lam ** 2 / 2, **kw))
+    ctx.sb_solve_iso_fft(blur, b_dev, lam, lam ** 2 / 2, L_max=1, I_max=1)
+    (xf, sf), out["sb_iso_fft_ms"] = timed(
+        lambda: ctx.sb_solve_iso_fft(blur, b_dev, lam, lam ** 2 / 2, **kw))
     out["sb_kp_iterations"] = [int(sk["l_end"]), int(sk["iota_total"])]
+    out["sb_fft_iterations"] = [int(sf["l_end"]), int(sf["iota_total"])]
     out["sb_direct_iterations"] = [int(sa["l_end"]), int(sa["iota_total"])]
     out["sb_speedup_kp_vs_direct"] = round(out["sb_iso_direct_ms"] / out["sb_iso_kp_ms"], 2)
+    out["sb_speedup_kp_vs_fft"] = round(out["sb_iso_fft_ms"] / out["sb_iso_kp_ms"], 2)
+    out["sb_fft_relative_error"] = round(float(np.linalg.norm(xf.cpu().numpy() - x_true)
+                                               / np.linalg.norm(x_true)), 4)
     out["sb_kp_relative_error"] = round(float(np.linalg.norm(xk.cpu().numpy() - x_true)
                                               / np.linalg.norm(x_true)), 4)
     out["sb_direct_relative_error"] = round(float(np.linalg.norm(xa.cpu().numpy() - x_true)
@@ -605,6 +614,30 @@ def profile_qr():
     return 0
 
 
+def profile_fft():
+    """Workload of the rocprofv3 passes over the FFT blur products: at n = 512
+    (Gaussian PSF on the full 1023 x 1023 offset grid, zero BC: M1 = M2 =
+    2048) ten A X and ten A^T X, each call planning afresh (twiddles and the
+    PSF spectrum: one row and one column pass over the PSF's rows)."""
+    import torch
+
+    import workloads as wl
+    from paper_2410_00233_amd import api
+    n = 512
+    ctx = api.Context(0)
+    P, cu, cv = wl.gaussian_psf(n)
+    blur = api.Blur(P, cu, cv, n, on_device=True)
+    X = torch.randn(n, n, dtype=torch.float64, device="cuda")
+    Y = torch.empty_like(X)
+    for tr in (False, True):
+        for _ in range(10):
+            ctx.kp_blur_apply(blur, X, transpose=tr, Y=Y)
+    torch.cuda.synchronize()
+    ctx.close()
+    print("done", flush=True)
+    return 0
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -637,6 +670,8 @@ def main():
                          "(a copy of known size for calibration, the n=512 FP32 / BF16 block "
                          "and FP32 matrix-vector products, the n=256 Kronecker apply and a few "
                          "CGLS iterations) and exit")
+    ap.add_argument("--profile-fft", action="store_true",
+                    help="run only the rocprofv3 workload of the FFT blur products and exit")
     ap.add_argument("--profile-qr", action="store_true",
                     help="only run two FP32 RSVDs at n=512 (the workload of the TSQR "
                          "counter pass) and exit")
@@ -650,6 +685,8 @@ def main():
         sys.exit(profile_products())
     if args.profile_qr:
         sys.exit(profile_qr())
+    if args.profile_fft:
+        sys.exit(profile_fft())
     if args.gpus != 1:
         print("bench.py measures one GPU only: the KP-SVD path is built and timed on a single "
               "MI355X (multi-GPU sharding is designed but not built); run with --gpus 1.", file=sys.stderr)
