@@ -507,7 +507,10 @@ kp_status sb_solve_iso_direct(kp_ctx* ctx, int32_t n, const double* A, const dou
  * conditions; blur->compact is ignored). X, Y: DEVICE n x n row-major FP64
  * images (pixel (r, i) at r n + i; r pairs with the PSF's first index),
  * distinct. KP_E_INVAL for a bad blur, NULL or aliased images, or
- * n + pu - 1 or n + pv - 1 above 4096. Uses the context's workspace. */
+ * n + pu - 1 or n + pv - 1 above 4096; KP_E_NUMERIC for a non-finite PSF
+ * entry. Uses the context's workspace. Every call computes the PSF's
+ * spectrum afresh (a row and a column pass over the PSF, about half the cost
+ * of the product at n = 512); the solves below compute it once per solve. */
 kp_status kp_blur_apply(kp_ctx* ctx, const kp_blur* blur, int transpose, const double* X,
                         double* Y, void* stream);
 /* Split Bregman (Algorithms 3 / 4 with CGLS, Algorithm 5) with A itself
