@@ -145,23 +145,39 @@ __global__ void __launch_bounds__(256) cgls_zn_kernel(SBDev d, const double* __r
   if (threadIdx.x == 0) d.part[blockIdx.x * 4 + 1] = acc;
 }
 
-// mu = tau / ||z||^2; x += mu w; r -= mu z; partials ||mu w||^2 (slot 2), ||x||^2 (3)
+// mu = tau / ||z||^2; x += mu w; r -= mu z; partials ||mu w||^2 (slot 2), ||x||^2 (3).
+// The partial of ||z||^2, tau and the first pixel's operands (none depends on
+// mu) are requested together, before the reduction's barriers.
 __global__ void __launch_bounds__(256) cgls_xr_kernel(SBDev d) {
   if (sb_skip(d, 2)) return;
   __shared__ double sh[4];
-  const double zz = sb_partials(d.part, 1, sh);
-  const double tau = d.scal[0];
-  const double mu = tau / zz;
   SB_ROWS
-  double a2 = 0.0, a3 = 0.0;
-  for (long e = lo + threadIdx.x; e < hi; e += 256) {
+  const double pz = d.part[threadIdx.x * 4 + 1];
+  const double tau = d.scal[0];
+  const long e0 = lo + threadIdx.x;
+  double we = 0.0, xe = 0.0, r1e = 0.0, z1e = 0.0, r2e = 0.0, r3e = 0.0, lxw = 0.0, lyw = 0.0;
+  auto fetch = [&](long e) {
     const int r = (int)(e / d.n), c = (int)(e - (long)r * d.n);
-    const double we = d.w[e];
-    const double xn = d.x[e] + mu * we;
+    we = d.w[e];
+    xe = d.x[e];
+    r1e = d.r1[e];
+    z1e = d.z1[e];
+    r2e = d.r2[e];
+    r3e = d.r3[e];
+    lxw = dLx(d.w, d.n, r, c);
+    lyw = dLy(d.w, d.n, r, c);
+  };
+  if (e0 < hi) fetch(e0);
+  const double zz = sb_block_sum(pz, sh);
+  const double mu = tau / zz;
+  double a2 = 0.0, a3 = 0.0;
+  for (long e = e0; e < hi; e += 256) {
+    if (e != e0) fetch(e);
+    const double xn = xe + mu * we;
     d.x[e] = xn;
-    d.r1[e] -= mu * d.z1[e];
-    d.r2[e] -= mu * d.lam * dLx(d.w, d.n, r, c);
-    d.r3[e] -= mu * d.lam * dLy(d.w, d.n, r, c);
+    d.r1[e] = r1e - mu * z1e;
+    d.r2[e] = r2e - mu * d.lam * lxw;
+    d.r3[e] = r3e - mu * d.lam * lyw;
     a2 += (mu * we) * (mu * we);
     a3 += xn * xn;
   }
@@ -177,16 +193,29 @@ __global__ void __launch_bounds__(256) cgls_xr_kernel(SBDev d) {
 // tau' = ||f||^2, delta = tau'/tau, w = f + delta w; RC_CGLS into scal[3];
 // block 0 counts the iteration and applies the stopping test. Blocks that
 // start after the test has fired skip their w update, which the solve no
-// longer reads (the next outer iteration restarts CGLS from w = f).
+// longer reads (the next outer iteration restarts CGLS from w = f). The three
+// partial slots, tau and the first pixel's f and w are requested together,
+// before the reductions' barriers.
 __global__ void __launch_bounds__(256) cgls_w_kernel(SBDev d) {
   if (sb_skip(d, 2)) return;
   __shared__ double sh[4];
-  const double tau_new = sb_partials(d.part, 0, sh);
-  const double delta = tau_new / d.scal[5];
   SB_ROWS
-  for (long e = lo + threadIdx.x; e < hi; e += 256) d.w[e] = d.f[e] + delta * d.w[e];
-  const double s2 = sb_partials(d.part, 2, sh);
-  const double s3 = sb_partials(d.part, 3, sh);
+  const double p0 = d.part[threadIdx.x * 4 + 0];
+  const double p2 = d.part[threadIdx.x * 4 + 2];
+  const double p3 = d.part[threadIdx.x * 4 + 3];
+  const double tau_old = d.scal[5];
+  const long e0 = lo + threadIdx.x;
+  double f0 = 0.0, w0 = 0.0;
+  if (e0 < hi) {
+    f0 = d.f[e0];
+    w0 = d.w[e0];
+  }
+  const double tau_new = sb_block_sum(p0, sh);
+  const double delta = tau_new / tau_old;
+  if (e0 < hi) d.w[e0] = f0 + delta * w0;
+  for (long e = e0 + 256; e < hi; e += 256) d.w[e] = d.f[e] + delta * d.w[e];
+  const double s2 = sb_block_sum(p2, sh);
+  const double s3 = sb_block_sum(p3, sh);
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     const double rc = s3 > 0.0 ? sqrt(s2) / sqrt(s3) : 0.0;
     d.scal[0] = tau_new;
