@@ -102,6 +102,37 @@ def test_blur_apply_full_size_sampled(ctx, bc, n, psf):
     assert abs(lhs - rhs) <= 1e-12 * np.linalg.norm(Y) * np.linalg.norm(Z)
 
 
+@pytest.mark.parametrize("bc,shape,centre", [("zero", (2049, 5), (564, 4)),
+                                              ("periodic", (31, 31), (15, 15)),
+                                              ("reflexive", (5, 2049), (2, 2048))])
+def test_blur_apply_maximum_size_sampled(ctx, bc, shape, centre):
+    """The largest images the FFT products take: n = 2048 (M1 = M2 = 4096),
+    with a 2049-row PSF that makes the extended image exactly 4096 rows (zero
+    BC), and a 2049-column PSF centred on its last column (reflexive BC): 8
+    sampled outputs (the corners and 4 random pixels) of A X and A^T X
+    against the oracle's entry definition, and the adjoint identity over the
+    whole image."""
+    from paper_2410_00233_amd import api
+    n = 2048
+    P, cu, cv = wl.random_psf(shape[0], shape[1], 17, cu=centre[0], cv=centre[1])
+    rng = np.random.default_rng(2048)
+    X = rng.standard_normal((n, n))
+    Z = rng.standard_normal((n, n))
+    blur = api.Blur(P, cu, cv, n, bc=bc)
+    Y = ctx.kp_blur_apply(blur, _dev(X)).cpu().numpy()
+    Yt = ctx.kp_blur_apply(blur, _dev(Z), transpose=True).cpu().numpy()
+    pix = [(0, 0), (n - 1, n - 1), (0, n - 1), (n - 1, 0)] + \
+        [tuple(int(v) for v in rng.integers(0, n, 2)) for _ in range(4)]
+    got = np.array([Y[r, i] for r, i in pix])
+    gott = np.array([Yt[r, i] for r, i in pix])
+    ref = _sampled_rows(P, cu, cv, n, X, pix, bc, False)
+    reft = _sampled_rows(P, cu, cv, n, Z, pix, bc, True)
+    assert np.abs(got - ref).max() <= 1e-13 * np.abs(P).sum() * np.abs(X).max()
+    assert np.abs(gott - reft).max() <= 1e-13 * np.abs(P).sum() * np.abs(Z).max()
+    lhs, rhs = float(np.sum(Y * Z)), float(np.sum(X * Yt))
+    assert abs(lhs - rhs) <= 1e-12 * np.linalg.norm(Y) * np.linalg.norm(Z)
+
+
 @pytest.mark.parametrize("kind", ["aniso", "iso"])
 @pytest.mark.parametrize("bc", ["zero", "reflexive", "periodic"])
 def test_sb_fft_matches_oracle(ctx, kind, bc):
