@@ -30,7 +30,7 @@ vec = lambda M: M.flatten(order="F")
 
 # (n, PSF shape, centre): padded sizes with odd and even log2 M, off-centre and
 # corner centres, PSFs wider than the image, a 1 x 1 PSF, non-square PSFs
-CASES = [(5, (3, 4), (1, 2)), (8, (3, 3), (1, 1)), (7, (9, 5), (2, 4)), (16, (7, 9), (3, 4)),
+CASES = [(2, (3, 3), (1, 1)), (3, (1, 1), (0, 0)), (5, (3, 4), (1, 2)), (8, (3, 3), (1, 1)), (7, (9, 5), (2, 4)), (16, (7, 9), (3, 4)),
          (13, (1, 1), (0, 0)), (12, (23, 23), (11, 11)), (24, (5, 31), (4, 0)),
          (10, (21, 3), (0, 2)), (40, (9, 9), (8, 8))]
 
